@@ -1,0 +1,118 @@
+/*
+ * FP64 CPU oracle for spectral ray tracing of a lit room -- TEST INFRASTRUCTURE.
+ *
+ * This library exists only to judge the HIP path.  Only the test-suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
+ * code, header, table or constant with the GPU library; both read the same
+ * seeded scene arrays (scenegen/), which carry no rendering arithmetic.
+ *
+ * What it computes (plain definitions, in FP64, no decomposition):
+ *  - complex refractive index n + i k (Eq. 1) and the Fresnel reflectance of
+ *    an air / absorbing-dielectric interface for s and p polarisation;
+ *  - the incoherent thick-slab reflectance / transmittance of a pane with
+ *    Beer-Lambert absorption ("direct use of the Fresnel definition", Sec. 6);
+ *  - the global closest hit of a ray (Sec. 4, inverse ray tracing): with the
+ *    spatial decomposition of Sec. 5 the ray is handed from subdomain to
+ *    subdomain unchanged, so the closest hit over all visited subdomains is
+ *    the global closest hit -- the oracle computes it directly, either by
+ *    brute force over all triangles or with its own median-split BVH;
+ *  - a Monte-Carlo spectral path tracer estimating the rendering equation
+ *    (Eq. 2) with one shadow ray per vertex toward the light (Eq. 3 for a
+ *    point light; uniform area sampling for the parallelogram emitter),
+ *    cosine-weighted diffuse bounces, a glass reflect/transmit choice, and a
+ *    fixed bounce cap (Sec. 4).
+ *
+ * Randomness: Philox4x32-10 (Salmon et al., SC'11) keyed by (seed, render_id)
+ * with counter (pixel, sample, depth, block); every 32-bit output x maps to
+ * (x >> 8) * 2^-24.
+ */
+#ifndef ORA_ORACLE_H
+#define ORA_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORA_DIFFUSE = 0, ORA_GLASS = 1, ORA_EMITTER = 2 };
+enum { ORA_LIGHT_NONE = 0, ORA_LIGHT_PARALLELOGRAM = 1, ORA_LIGHT_POINT = 2 };
+
+typedef struct ora_scene {
+    int n_verts;
+    const float *verts;      /* [V][3] metres */
+    int n_tris;
+    const int32_t *tris;     /* [T][3] vertex indices */
+    const int32_t *tri_mat;  /* [T] material index */
+    int n_lambda;
+    const float *lambda_nm;  /* [nl] */
+    const double *lambda_w;  /* [nl] integration weights (nm) */
+    const double *cmf;       /* [nl][3] */
+    int n_mats;
+    const int32_t *mat_type; /* [M] ORA_DIFFUSE / ORA_GLASS / ORA_EMITTER */
+    const float *mat_rho;    /* [M][nl] */
+    const float *mat_n;      /* [M][nl] */
+    const float *mat_k;      /* [M][nl] */
+    const float *mat_thick;  /* [M] metres */
+    const float *mat_le;     /* [M][nl] */
+    int light_type;
+    const float *light_p0, *light_e1, *light_e2; /* [3] each */
+    int light_mat;
+} ora_scene;
+
+typedef struct ora_args {
+    double eye[3], target[3];
+    double fov_deg;
+    int ortho;               /* 1: rays orthogonal to the image plane */
+    double ortho_half_h;
+    int W, H, spp, sample_offset, max_depth;
+    uint32_t seed, render_id;
+    int use_bvh;             /* 1: median-split BVH, 0: brute force */
+    int n_threads;           /* <= 0: OpenMP default */
+    int n_pix;               /* > 0: render only the listed pixels */
+    const int32_t *pix;      /* [n_pix] pixel indices p = py*W + px */
+} ora_args;
+
+typedef struct ora_out {
+    double *spectral;        /* [n_out][nl] mean over spp, or NULL */
+    double *xyz;             /* [n_out][3] or NULL */
+    int32_t *hit_log;        /* [n_out][spp][D]: prim, -1 miss, -2 no ray; or NULL */
+    int32_t *shadow_log;     /* [n_out][spp][D]: 1 visible, 0 blocked, -2 none; or NULL */
+    double *path_L;          /* [n_out][spp][nl] per-sample radiance, or NULL */
+    double *first_hit;       /* [n_out][spp][3] first vertex position (NaN if none), or NULL */
+    int64_t n_ext_rays;      /* closest-hit queries traced */
+    int64_t n_shadow_rays;   /* shadow queries traced */
+} ora_out;
+
+typedef struct ora_accel ora_accel;
+
+ora_accel *ora_build(const ora_scene *sc);
+void ora_free(ora_accel *acc);
+int ora_accel_nodes(const ora_accel *acc);
+
+/* Render; acc == NULL or args->use_bvh == 0 selects brute force. 0 on success. */
+int ora_render(const ora_scene *sc, const ora_accel *acc, const ora_args *args, ora_out *out);
+
+/* Closest hits of n rays (FP64).  exclude[i] = prim to skip (-1 none). */
+int ora_trace_rays(const ora_scene *sc, const ora_accel *acc, int n, const double *o,
+                   const double *d, const int32_t *exclude, double *t_out, int32_t *prim_out);
+
+/* Shadow transmittance of n segments (0 < t < r): out[i][nl]. */
+int ora_shadow_rays(const ora_scene *sc, const ora_accel *acc, int n, const double *o,
+                    const double *d, const double *r, const int32_t *exclude, double *out);
+
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double ora_u01(uint32_t x);
+
+void ora_fresnel_sp(double n, double k, double c, double *Rs, double *Rp);
+void ora_slab_sp(double n, double k, double thick_m, double lambda_nm, double c,
+                 double *Rslab_s, double *Rslab_p, double *T_s, double *T_p);
+void ora_slab(double n, double k, double thick_m, double lambda_nm, double c, double *R, double *T);
+
+void ora_cosine_hemisphere(const double n[3], double u0, double u1, double out[3]);
+void ora_camera_ray(const ora_args *args, double x, double y, double o[3], double d[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
