@@ -123,10 +123,12 @@ void ora_slab(double n, double k, double thick_m, double lambda_nm, double c, do
 /* ------------------------------------------------------------------------ */
 /* sampling and camera                                                       */
 /* ------------------------------------------------------------------------ */
-/* cosine-weighted direction about n; basis of Duff et al., JCGT 2017 */
+/* cosine-weighted direction about n; orthonormal basis of Duff et al.
+ * (JCGT 2017), with the branch sign taken as +1 for both signed zeros of n_z
+ * so the basis never depends on how a zero component was rounded */
 void ora_cosine_hemisphere(const double nn[3], double u0, double u1, double out[3]) {
     double nx = nn[0], ny = nn[1], nz = nn[2];
-    double s = copysign(1.0, nz);
+    double s = nz >= 0.0 ? 1.0 : -1.0;
     double a = -1.0 / (s + nz);
     double b = nx * ny * a;
     v3 b1 = mk(1.0 + s * nx * nx * a, s * b, -s * nx);
