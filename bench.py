@@ -1,0 +1,189 @@
+#!/usr/bin/env python
+"""Throughput of the spectral domain-decomposition path tracer on one MI355X.
+
+A step renders one full frame of the room-scale workload (about 200k
+triangles, three 4 mm panes, 512 x 512 pixels, 16 samples per pixel,
+41 wavelengths, up to 8 surface vertices per path, 4 x 4 x 2 subdomains)
+with sdd_trace_spectral and resolves it with sdd_resolve_image.  Successive
+steps trace new sample ranges of the same progressive render.  The metric is
+(extension rays + shadow rays) * n_lambda / second.
+
+One JSON line is printed (rank 0); progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+REC_BYTES = 40                 # queue record: (o, t_enter) 16 B + (d, path) 16 B + (excl, t_max) 8 B
+HIT_BYTES = 8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+WORKLOADS = {
+    "furnished_room": dict(scene=("furnished_room", dict(seed=1, n_lambda=41)), W=512, H=512, spp=16, D=8,
+                           grid=(4, 4, 2)),
+    "tiny_room": dict(scene=("tiny_room", dict(seed=0, n_lambda=16)), W=64, H=64, spp=1, D=4, grid=(2, 2, 1)),
+}
+
+
+def cpu_baseline(scene, wl, target_s=15.0):
+    """The FP64 oracle on a bounded, strided pixel sample of the same frame (1 spp)."""
+    import numpy as np
+
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    osc = oracle.OracleScene(scene)
+    _ = osc.accel  # build excluded from the timing
+    W, H, D = wl["W"], wl["H"], wl["D"]
+    nl = len(scene["lambda_nm"])
+    n, spp = 512, 1
+    while True:
+        stride = max(1, (W * H) // n)
+        pix = np.arange(0, W * H, stride, dtype=np.int32)[:n]
+        t0 = time.perf_counter()
+        r = oracle.render(scene, W, H, spp, D, pix=pix, oscene=osc, n_threads=threads)
+        dt = time.perf_counter() - t0
+        log(f"[cpu_baseline] {len(pix)} px x {spp} spp: {dt:.2f} s")
+        if dt >= target_s / 3 or (len(pix) >= W * H and spp >= wl["spp"]):
+            break
+        grow = max(2.0, target_s / max(dt, 1e-3))
+        if n < W * H:
+            n = min(W * H, int(n * grow))
+        else:
+            spp = min(wl["spp"], max(spp + 1, int(spp * grow)))
+    rays = r["n_ext_rays"] + r["n_shadow_rays"]
+    return {"value": rays * nl / dt, "unit": "rays*lambda/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(pix)} pixels (every {stride}th of the {W}x{H} frame) x {spp} spp, depth {D}, "
+                      f"{nl} wavelengths, FP64, {rays} rays in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="furnished_room", choices=sorted(WORKLOADS))
+    ap.add_argument("--grid", default=None, help="override subdomain grid, e.g. 1x1x1")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1912_06474_amd as sdd
+    import scenegen
+
+    wl = dict(WORKLOADS[args.workload])
+    if args.grid:
+        wl["grid"] = tuple(int(x) for x in args.grid.lower().split("x"))
+    name, kw = wl["scene"]
+    t0 = time.perf_counter()
+    scene = getattr(scenegen, name)(**kw)
+    log(f"[bench] scene {scene['name']}: {len(scene['tris'])} tris, {len(scene['lambda_nm'])} lambda "
+        f"({time.perf_counter() - t0:.1f} s)")
+    W, H, spp, D = wl["W"], wl["H"], wl["spp"], wl["D"]
+    nl = len(scene["lambda_nm"])
+    cam = scene["camera"]
+
+    tr = sdd.Tracer()
+    tr.load_scene(scene)
+    t0 = time.perf_counter()
+    tr.build_bvh(*wl["grid"])
+    build_s = time.perf_counter() - t0
+    st0 = tr.stats()
+    log(f"[bench] build_bvh {wl['grid']}: {build_s:.2f} s, refs {st0['n_refs']}, nodes {st0['n_nodes']}, "
+        f"depth {st0['max_bvh_depth']}")
+
+    step = 0
+
+    def frame(flags_time=False):
+        nonlocal step
+        tr.trace_spectral(cam, W, H, spp, D, sample_offset=step * spp, render_id=0, time_kernels=flags_time)
+        tr.resolve_image(0, W, H, spectral=True, xyz=True)
+        step += 1
+
+    for i in range(args.warmup):
+        frame()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i + 1}/{args.warmup}")
+
+    # timed region: value
+    tr.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        frame()
+        log(f"[bench] step {i + 1}/{args.steps}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = tr.stats()
+    rays = st["ext_rays"] + st["shadow_rays"]
+    value = rays * nl / dt
+
+    # second pass, same work, every launch bracketed by HIP events on the library's stream
+    tr.reset_stats()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        frame(flags_time=True)
+    torch.cuda.synchronize()
+    dt_ev = time.perf_counter() - t1
+    se = tr.stats()
+    launches_ext = se["launches_trace"] / 2  # half the sweeps are closest-hit, half shadow
+    ms_ext = se["ms_trace_ext"]
+    visits = se["ext_cell_visits"]
+    ext_rays = se["ext_rays"]
+    crossings = max(0, visits - ext_rays)
+    alg_bytes = REC_BYTES * visits + REC_BYTES * crossings + HIT_BYTES * ext_rays
+    achieved = alg_bytes / (ms_ext * 1e-3) / 1e9 if ms_ext > 0 else 0.0
+    kern_ms = {"trace_ext": se["ms_trace_ext"], "trace_shadow": se["ms_trace_shadow"], "shade": se["ms_shade"],
+               "other": se["ms_other"]}
+    log(f"[bench] timed {dt:.3f} s; event pass {dt_ev:.3f} s; kernel ms {kern_ms}")
+
+    res = {
+        "metric": "spectral path samples/s (rays x lambda/s), plain tracer, one MI355X",
+        "value": value,
+        "unit": "rays*lambda/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {len(scene['tris'])} tris, {W}x{H}, {spp} spp, {nl} lambda, "
+                               f"depth {D}, grid {'x'.join(map(str, wl['grid']))}",
+                   "paths_per_step": W * H * spp, "rays_per_step": rays / args.steps,
+                   "path_samples_lambda_per_s": W * H * spp * nl * args.steps / dt},
+        "roofline": {"bound": "hbm", "kernel": "k_trace<closest-hit>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg_bytes / max(1.0, launches_ext),
+                     "avg_launch_ms": ms_ext / max(1.0, launches_ext)},
+        "kernel_ms_per_step": {k: v / args.steps for k, v in kern_ms.items()},
+        "build_bvh_s": build_s,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(scene, wl, args.cpu_seconds)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

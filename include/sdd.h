@@ -1,0 +1,247 @@
+/*
+ * sdd.h -- spectral domain-decomposition ray tracing on MI355X (gfx950).
+ *
+ * C ABI of the HIP library libsdd.so.  The library renders a lit room by
+ * spectral Monte-Carlo path tracing:
+ *   - ray / triangle traversal over per-subdomain BVHs (inverse ray tracing,
+ *     Sec. 4 of the paper: primary ray per pixel, one shadow ray per vertex
+ *     toward the light, secondary reflection / refraction rays, a bounce cap);
+ *   - per-wavelength light / material interaction: Lambert reflection and a
+ *     glass pane whose Fresnel terms come from the complex index
+ *     n(lambda) + i k(lambda) (Eq. 1), with incoherent slab transmittance and
+ *     Beer-Lambert absorption (Sec. 6, "direct use of the Fresnel definition");
+ *   - the paper's spatial domain decomposition (Sec. 5): the scene is split
+ *     into a uniform grid of subdomains, each with its own BVH; a ray is
+ *     traced inside one subdomain over the parameter interval (t_enter, t_exit]
+ *     and, if it finds nothing, is handed across the interface to the
+ *     neighbouring subdomain with its origin, direction and t carried
+ *     unchanged (the interface condition "continuity of the ray properties").
+ *     On one GPU the subdomains become per-subdomain ray queues in HBM.
+ *
+ * Conventions for every entry point:
+ *   - status codes only; nothing throws across the ABI and nothing aborts;
+ *   - on failure, sdd_last_error(ctx) describes the cause (ctx-owned string,
+ *     valid until the next call on that context);
+ *   - a context is not thread-safe; separate contexts are independent;
+ *   - all input pointers are host pointers unless stated otherwise; inputs
+ *     are deep-copied and stay owned by the caller;
+ *   - the context owns all device memory it allocates (scene, BVHs, queues,
+ *     path state, accumulators); sdd_destroy releases it.
+ * Call order: sdd_create -> sdd_load_scene -> sdd_build_bvh ->
+ *   sdd_trace_spectral* -> sdd_resolve_image.  Out of order: SDD_ERR_STATE.
+ */
+#ifndef SDD_H
+#define SDD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SDD_OK = 0,
+    SDD_ERR_INVALID_ARG = -1,
+    SDD_ERR_STATE = -2,
+    SDD_ERR_OOM = -3,
+    SDD_ERR_HIP = -4,
+    SDD_ERR_OVERFLOW = -5,
+    SDD_ERR_UNSUPPORTED = -6
+} sdd_status;
+
+enum { SDD_MAT_DIFFUSE = 0, SDD_MAT_GLASS_SLAB = 1, SDD_MAT_EMITTER = 2 };
+enum { SDD_LIGHT_NONE = 0, SDD_LIGHT_PARALLELOGRAM = 1, SDD_LIGHT_POINT = 2 };
+
+/* Limits (checked; exceeding one returns SDD_ERR_INVALID_ARG). */
+#define SDD_MAX_LAMBDA 128
+#define SDD_MAX_CELLS 1024
+#define SDD_MAX_DEPTH 64
+
+typedef struct sdd_ctx sdd_ctx;
+
+/*
+ * Scene (sdd_load_scene).  Host arrays, row-major:
+ *   verts     float  [n_verts][3]  metres
+ *   tris      int32  [n_tris][3]   vertex indices in [0, n_verts)
+ *   tri_mat   int32  [n_tris]      material index in [0, n_mats)
+ *   lambda_nm float  [n_lambda]    wavelengths (nm), > 0
+ *   lambda_w  double [n_lambda]    integration weights for the XYZ reduction
+ *   cmf       double [n_lambda][3] colour matching functions
+ *   mat_type  int32  [n_mats]      SDD_MAT_*
+ *   mat_rho   float  [n_mats][n_lambda] diffuse reflectance in [0, 1]
+ *   mat_n     float  [n_mats][n_lambda] real index n > 0        (Eq. 1)
+ *   mat_k     float  [n_mats][n_lambda] absorption index k >= 0 (Eq. 1, k = n kappa)
+ *   mat_thick float  [n_mats]      slab thickness (m) of GLASS_SLAB panes, >= 0
+ *   mat_le    float  [n_mats][n_lambda] emitted radiance >= 0 (EMITTER: one-sided,
+ *                                  counted per the NEE rule; DIFFUSE: two-sided,
+ *                                  always counted; GLASS: must be 0)
+ * Light (one at most): PARALLELOGRAM {p0, e1, e2} emits mat_le[light_mat] on
+ *   the side of e1 x e2 (its triangles must also be in tris with an EMITTER
+ *   material); POINT {p0} with intensity mat_le[light_mat] (Eq. 3).
+ */
+typedef struct sdd_scene_desc {
+    int32_t n_verts;
+    const float *verts;
+    int32_t n_tris;
+    const int32_t *tris;
+    const int32_t *tri_mat;
+    int32_t n_lambda;
+    const float *lambda_nm;
+    const double *lambda_w;
+    const double *cmf;
+    int32_t n_mats;
+    const int32_t *mat_type;
+    const float *mat_rho;
+    const float *mat_n;
+    const float *mat_k;
+    const float *mat_thick;
+    const float *mat_le;
+    int32_t light_type;
+    float light_p0[3], light_e1[3], light_e2[3];
+    int32_t light_mat;
+} sdd_scene_desc;
+
+/*
+ * Subdomain grid and BVHs (sdd_build_bvh).  The scene's bounding box (light
+ * included, slightly enlarged) is split into nx * ny * nz equal cells (the
+ * paper's sub-domains, Sec. 5); every triangle is referenced in each cell
+ * its padded bounding box overlaps, and each cell gets its own binned-SAH
+ * BVH over its references.  nx = ny = nz = 1 is the undecomposed special case.
+ *   leaf_max  triangles per leaf (1..8, 0 = default 4)
+ *   sah_bins  SAH bins (2..64, 0 = default 16)
+ */
+typedef struct sdd_bvh_desc {
+    int32_t nx, ny, nz;
+    int32_t leaf_max;
+    int32_t sah_bins;
+} sdd_bvh_desc;
+
+/* sdd_trace_desc.flags */
+#define SDD_TRACE_ORTHO 1u        /* rays orthogonal to the image plane (Sec. 4) */
+#define SDD_TRACE_TIME_KERNELS 2u /* time every launch with HIP events (stats) */
+#define SDD_TRACE_COUNT_WORK 4u   /* count node visits / triangle tests (stats) */
+
+/*
+ * One call traces spp samples of every pixel of render render_id and adds
+ * them to that render's FP32 spectral accumulator (created on first use
+ * with this W, H; later calls must use the same W, H).  Sample s of pixel
+ * p = py * W + px (py = 0 is the top row) draws its random numbers from
+ * Philox4x32-10 with key (seed, render_id) and counter (p, s, depth, block),
+ * s in [sample_offset, sample_offset + spp), so calls split or resumed over
+ * sample ranges give the same result.  The call is stream-ordered and
+ * asynchronous with respect to the host.
+ *   eye, target, fov_deg: pinhole camera (up = +z); with SDD_TRACE_ORTHO the
+ *     image plane is 2 ortho_half_h tall and rays are parallel.
+ *   max_depth: surface vertices per path (1..SDD_MAX_DEPTH).
+ *   hit_log / shadow_log: optional DEVICE int32 buffers [W*H][spp][max_depth]
+ *     (this call's samples).  hit_log gets the hit triangle id of each vertex,
+ *     -1 for a miss, -2 where the path had ended; shadow_log gets 1 (visible),
+ *     0 (blocked) or -2 (no shadow ray) per vertex.  NULL to skip.
+ */
+typedef struct sdd_trace_desc {
+    float eye[3], target[3];
+    float fov_deg;
+    float ortho_half_h;
+    int32_t W, H;
+    int32_t spp;
+    int32_t sample_offset;
+    int32_t max_depth;
+    uint32_t seed;
+    int32_t render_id;
+    uint32_t flags;
+    int32_t *hit_log;
+    int32_t *shadow_log;
+} sdd_trace_desc;
+
+/* Counters (sdd_get_stats); synchronises the context stream. */
+typedef struct sdd_stats {
+    int64_t ext_rays;          /* closest-hit rays generated */
+    int64_t shadow_rays;       /* shadow rays generated */
+    int64_t ext_cell_visits;   /* (ray, subdomain) traversals, closest-hit */
+    int64_t shadow_cell_visits;/* (ray, subdomain) traversals, shadow */
+    int64_t node_visits;       /* BVH inner nodes visited (SDD_TRACE_COUNT_WORK) */
+    int64_t tri_tests;         /* ray / triangle tests (SDD_TRACE_COUNT_WORK) */
+    int64_t batches;           /* path batches launched */
+    int64_t launches_trace;    /* subdomain traversal launches */
+    double ms_trace_ext;       /* summed launch durations (SDD_TRACE_TIME_KERNELS) */
+    double ms_trace_shadow;
+    double ms_shade;
+    double ms_other;
+    int64_t n_refs;            /* triangle references over all cells */
+    int64_t n_nodes;           /* BVH nodes over all cells */
+    int32_t max_bvh_depth;
+    int32_t n_cells;
+    int64_t device_bytes;      /* device memory owned by the context */
+    int64_t paths_per_batch;
+    int32_t overflow;          /* nonzero: a shadow segment crossed more panes than supported */
+    int32_t pad_;
+} sdd_stats;
+
+/* Create a context on HIP device hip_device.  hip_stream is the hipStream_t
+ * every launch and copy of the context goes to (NULL = the device's default
+ * null stream); the caller keeps ownership of a stream it passes.  *out is
+ * set on success. */
+sdd_status sdd_create(int hip_device, void *hip_stream, sdd_ctx **out);
+
+/* Release every device allocation of ctx.  NULL-safe. */
+void sdd_destroy(sdd_ctx *ctx);
+
+/* Description of the last failure on ctx ("" if none; "null context" for NULL). */
+const char *sdd_last_error(const sdd_ctx *ctx);
+
+/* Validate and deep-copy a scene to the device (Eq. 1 tables per material).
+ * Invalidates any previous BVH and renders.  SDD_ERR_INVALID_ARG on: no
+ * triangles, an index out of range, a non-finite vertex, n_lambda out of
+ * [1, SDD_MAX_LAMBDA], rho outside [0, 1], n <= 0, k < 0, thickness < 0,
+ * negative emission, emission on glass, a light without a valid emitter
+ * material, or a degenerate parallelogram light. */
+sdd_status sdd_load_scene(sdd_ctx *ctx, const sdd_scene_desc *scene);
+
+/* Host-only argument check of a scene (no device needed); same rules as
+ * sdd_load_scene.  msg (may be NULL) receives a NUL-terminated reason. */
+sdd_status sdd_validate_scene(const sdd_scene_desc *scene, char *msg, int msg_len);
+
+/* Build the subdomain grid and the per-subdomain BVHs (host), upload them.
+ * SDD_ERR_STATE without a scene; SDD_ERR_INVALID_ARG for grid dims <= 0, more
+ * than SDD_MAX_CELLS cells, or leaf_max / sah_bins out of range. */
+sdd_status sdd_build_bvh(sdd_ctx *ctx, const sdd_bvh_desc *desc);
+
+/* Trace (asynchronously) and accumulate; see sdd_trace_desc.  SDD_ERR_STATE
+ * without a BVH; SDD_ERR_INVALID_ARG for W, H, spp, max_depth out of range,
+ * a render_id < 0, a changed W/H for an existing render, or a degenerate
+ * camera (forward direction parallel to +z or eye == target). */
+sdd_status sdd_trace_spectral(sdd_ctx *ctx, const sdd_trace_desc *desc);
+
+/* Per-pixel mean radiance of render_id over all samples traced so far, in
+ * FP64: spectral_out [H][W][n_lambda] and xyz_out [H][W][3] (XYZ =
+ * sum_l lambda_w[l] cmf[l][:] L[l]).  Either may be NULL.  Pointers are
+ * device pointers if out_is_device, else host pointers.  Synchronises the
+ * stream.  SDD_ERR_STATE for an unknown render or one with no samples;
+ * SDD_ERR_OVERFLOW if a shadow segment crossed more glass panes than the
+ * library tracks (the image is then not trustworthy). */
+sdd_status sdd_resolve_image(sdd_ctx *ctx, int32_t render_id, double *spectral_out, double *xyz_out,
+                             int32_t out_is_device);
+
+/* Forget render_id's accumulator (frees its device memory). */
+sdd_status sdd_reset_render(sdd_ctx *ctx, int32_t render_id);
+
+/* Copy the context counters (synchronises the stream). */
+sdd_status sdd_get_stats(sdd_ctx *ctx, sdd_stats *out);
+
+/* Zero the counters of sdd_get_stats (not the scene / BVH statistics). */
+sdd_status sdd_reset_stats(sdd_ctx *ctx);
+
+/* Diagnostics: evaluate the library's own device Philox4x32-10 on n counters.
+ * ctr: host uint32 [n][4]; key: host uint32 [2]; out: host uint32 [n][4]. */
+sdd_status sdd_debug_philox(sdd_ctx *ctx, int32_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
+
+/* Diagnostics: closest hits of n rays through the subdomain queues (the same
+ * kernels as sdd_trace_spectral's extension phase).  o, d: host float [n][3];
+ * t_out: host float [n] (+inf on a miss); prim_out: host int32 [n] (-1). */
+sdd_status sdd_debug_trace_rays(sdd_ctx *ctx, int32_t n, const float *o, const float *d, float *t_out,
+                                int32_t *prim_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

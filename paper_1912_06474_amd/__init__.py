@@ -1,0 +1,281 @@
+"""Spectral domain-decomposition ray tracing on MI355X (gfx950).
+
+Thin ctypes binding of ``libsdd.so`` (C ABI in ``include/sdd.h``).  It only
+marshals arguments: every step of the rendering runs in the library's HIP
+kernels.  PyTorch supplies device memory (outputs, debug logs) and the HIP
+stream.  There is no CPU fallback: if the library is missing or no GPU is
+present, the calls raise.
+
+    t = Tracer()                        # context on cuda:0, torch's current stream
+    t.load_scene(scene)                 # dict of arrays (see scenegen)
+    t.build_bvh(4, 4, 2)                # subdomain grid + per-subdomain BVHs
+    t.trace_spectral(camera, 512, 512, spp=16, max_depth=8)
+    spec, xyz = t.resolve_image()       # FP64 torch tensors on the device
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsdd.so")
+
+SDD_OK = 0
+STATUS = {0: "SDD_OK", -1: "SDD_ERR_INVALID_ARG", -2: "SDD_ERR_STATE", -3: "SDD_ERR_OOM", -4: "SDD_ERR_HIP",
+          -5: "SDD_ERR_OVERFLOW", -6: "SDD_ERR_UNSUPPORTED"}
+TRACE_ORTHO, TRACE_TIME_KERNELS, TRACE_COUNT_WORK = 1, 2, 4
+
+EXPORTS = ("sdd_create", "sdd_destroy", "sdd_last_error", "sdd_load_scene", "sdd_validate_scene", "sdd_build_bvh",
+           "sdd_trace_spectral", "sdd_resolve_image", "sdd_reset_render", "sdd_get_stats", "sdd_reset_stats",
+           "sdd_debug_philox", "sdd_debug_trace_rays")
+
+
+class SddError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [
+        ("n_verts", C.c_int32), ("verts", C.c_void_p),
+        ("n_tris", C.c_int32), ("tris", C.c_void_p), ("tri_mat", C.c_void_p),
+        ("n_lambda", C.c_int32), ("lambda_nm", C.c_void_p), ("lambda_w", C.c_void_p), ("cmf", C.c_void_p),
+        ("n_mats", C.c_int32), ("mat_type", C.c_void_p), ("mat_rho", C.c_void_p), ("mat_n", C.c_void_p),
+        ("mat_k", C.c_void_p), ("mat_thick", C.c_void_p), ("mat_le", C.c_void_p),
+        ("light_type", C.c_int32), ("light_p0", C.c_float * 3), ("light_e1", C.c_float * 3),
+        ("light_e2", C.c_float * 3), ("light_mat", C.c_int32),
+    ]
+
+
+class BvhDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("leaf_max", C.c_int32),
+                ("sah_bins", C.c_int32)]
+
+
+class TraceDesc(C.Structure):
+    _fields_ = [
+        ("eye", C.c_float * 3), ("target", C.c_float * 3), ("fov_deg", C.c_float), ("ortho_half_h", C.c_float),
+        ("W", C.c_int32), ("H", C.c_int32), ("spp", C.c_int32), ("sample_offset", C.c_int32),
+        ("max_depth", C.c_int32), ("seed", C.c_uint32), ("render_id", C.c_int32), ("flags", C.c_uint32),
+        ("hit_log", C.c_void_p), ("shadow_log", C.c_void_p),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("ext_rays", C.c_int64), ("shadow_rays", C.c_int64), ("ext_cell_visits", C.c_int64),
+        ("shadow_cell_visits", C.c_int64), ("node_visits", C.c_int64), ("tri_tests", C.c_int64),
+        ("batches", C.c_int64), ("launches_trace", C.c_int64),
+        ("ms_trace_ext", C.c_double), ("ms_trace_shadow", C.c_double), ("ms_shade", C.c_double),
+        ("ms_other", C.c_double),
+        ("n_refs", C.c_int64), ("n_nodes", C.c_int64), ("max_bvh_depth", C.c_int32), ("n_cells", C.c_int32),
+        ("device_bytes", C.c_int64), ("paths_per_batch", C.c_int64), ("overflow", C.c_int32), ("pad_", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
+_LIB = None
+
+
+def lib():
+    """Load libsdd.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1912_06474_amd.build` "
+                               "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32 = C.c_void_p, C.c_int32
+        L.sdd_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+        L.sdd_destroy.argtypes = [vp]
+        L.sdd_destroy.restype = None
+        L.sdd_last_error.argtypes = [vp]
+        L.sdd_last_error.restype = C.c_char_p
+        L.sdd_load_scene.argtypes = [vp, C.POINTER(SceneDesc)]
+        L.sdd_validate_scene.argtypes = [C.POINTER(SceneDesc), C.c_char_p, C.c_int]
+        L.sdd_build_bvh.argtypes = [vp, C.POINTER(BvhDesc)]
+        L.sdd_trace_spectral.argtypes = [vp, C.POINTER(TraceDesc)]
+        L.sdd_resolve_image.argtypes = [vp, i32, vp, vp, i32]
+        L.sdd_reset_render.argtypes = [vp, i32]
+        L.sdd_get_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.sdd_reset_stats.argtypes = [vp]
+        L.sdd_debug_philox.argtypes = [vp, i32, vp, vp, vp]
+        L.sdd_debug_trace_rays.argtypes = [vp, i32, vp, vp, vp, vp]
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class _SceneArrays:
+    """Contiguous host copies of a scene dict and the C descriptor over them."""
+
+    def __init__(self, scene):
+        self.keep = {}
+
+        def arr(key, dt):
+            a = np.ascontiguousarray(scene[key], dtype=dt)
+            self.keep[key] = a
+            return a
+
+        verts, tris, tri_mat = arr("verts", np.float32), arr("tris", np.int32), arr("tri_mat", np.int32)
+        lam, w, cmf = arr("lambda_nm", np.float32), arr("lambda_w", np.float64), arr("cmf", np.float64)
+        mt = arr("mat_type", np.int32)
+        rho, mn, mk, le = (arr(k, np.float32) for k in ("mat_rho", "mat_n", "mat_k", "mat_le"))
+        th = arr("mat_thick", np.float32)
+        d = SceneDesc()
+        d.n_verts, d.verts = len(verts), _ptr(verts)
+        d.n_tris, d.tris, d.tri_mat = len(tris), _ptr(tris), _ptr(tri_mat)
+        d.n_lambda, d.lambda_nm, d.lambda_w, d.cmf = len(lam), _ptr(lam), _ptr(w), _ptr(cmf)
+        d.n_mats, d.mat_type = len(mt), _ptr(mt)
+        d.mat_rho, d.mat_n, d.mat_k, d.mat_thick, d.mat_le = _ptr(rho), _ptr(mn), _ptr(mk), _ptr(th), _ptr(le)
+        d.light_type = int(scene["light_type"])
+        d.light_p0[:] = [float(x) for x in np.asarray(scene["light_p0"]).reshape(3)]
+        d.light_e1[:] = [float(x) for x in np.asarray(scene["light_e1"]).reshape(3)]
+        d.light_e2[:] = [float(x) for x in np.asarray(scene["light_e2"]).reshape(3)]
+        d.light_mat = int(scene["light_mat"])
+        self.desc = d
+        self.n_lambda = len(lam)
+
+
+def validate_scene(scene):
+    """Host-only validation (no GPU needed).  Returns (ok, message)."""
+    sa = _SceneArrays(scene)
+    buf = C.create_string_buffer(512)
+    st = lib().sdd_validate_scene(C.byref(sa.desc), buf, 512)
+    return st == SDD_OK, buf.value.decode()
+
+
+class Tracer:
+    """One library context on one HIP device (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the spectral tracer runs only on the GPU")
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = lib().sdd_create(int(device), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != SDD_OK:
+            raise SddError(st, "sdd_create failed")
+        self.h = h
+        self.n_lambda = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sdd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != SDD_OK:
+            raise SddError(st, lib().sdd_last_error(self.h).decode())
+
+    def load_scene(self, scene):
+        sa = _SceneArrays(scene)
+        self._check(lib().sdd_load_scene(self.h, C.byref(sa.desc)))
+        self.n_lambda = sa.n_lambda
+
+    def build_bvh(self, nx=1, ny=1, nz=1, leaf_max=4, sah_bins=16):
+        self._check(lib().sdd_build_bvh(self.h, C.byref(BvhDesc(nx, ny, nz, leaf_max, sah_bins))))
+
+    def trace_spectral(self, camera, W, H, spp, max_depth, *, seed=0, render_id=0, sample_offset=0,
+                       time_kernels=False, count_work=False, hit_log=None, shadow_log=None):
+        d = TraceDesc()
+        d.eye[:] = [float(x) for x in camera["eye"]]
+        d.target[:] = [float(x) for x in camera["target"]]
+        d.fov_deg = float(camera.get("fov_deg", 60.0))
+        d.ortho_half_h = float(camera.get("ortho_half_h", 1.0))
+        d.W, d.H, d.spp, d.sample_offset, d.max_depth = int(W), int(H), int(spp), int(sample_offset), int(max_depth)
+        d.seed, d.render_id = int(seed), int(render_id)
+        fl = 0
+        if camera.get("ortho", False):
+            fl |= TRACE_ORTHO
+        if time_kernels:
+            fl |= TRACE_TIME_KERNELS
+        if count_work:
+            fl |= TRACE_COUNT_WORK
+        d.flags = fl
+        n_slots = int(W) * int(H) * int(spp) * int(max_depth)
+        for name, t in (("hit_log", hit_log), ("shadow_log", shadow_log)):
+            if t is not None:
+                if not (t.is_cuda and t.dtype == self.torch.int32 and t.is_contiguous() and t.numel() == n_slots):
+                    raise ValueError(f"{name} must be a contiguous int32 CUDA tensor of {n_slots} elements")
+                setattr(d, name, t.data_ptr())
+        self._check(lib().sdd_trace_spectral(self.h, C.byref(d)))
+
+    def new_log(self, W, H, spp, max_depth):
+        return self.torch.empty((W * H, spp, max_depth), dtype=self.torch.int32, device=self.device)
+
+    def resolve_image(self, render_id=0, W=None, H=None, spectral=True, xyz=True):
+        """FP64 [H*W, n_lambda] spectral mean and [H*W, 3] XYZ as device tensors."""
+        if W is None or H is None:
+            raise ValueError("resolve_image needs W and H")
+        torch = self.torch
+        s = torch.empty((H * W, self.n_lambda), dtype=torch.float64, device=self.device) if spectral else None
+        x = torch.empty((H * W, 3), dtype=torch.float64, device=self.device) if xyz else None
+        self._check(lib().sdd_resolve_image(self.h, int(render_id), s.data_ptr() if s is not None else None,
+                                            x.data_ptr() if x is not None else None, 1))
+        return s, x
+
+    def reset_render(self, render_id=0):
+        self._check(lib().sdd_reset_render(self.h, int(render_id)))
+
+    def stats(self):
+        s = Stats()
+        self._check(lib().sdd_get_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def reset_stats(self):
+        self._check(lib().sdd_reset_stats(self.h))
+
+    def debug_philox(self, ctr, key):
+        ctr = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+        key = np.ascontiguousarray(key, np.uint32).reshape(2)
+        out = np.zeros_like(ctr)
+        self._check(lib().sdd_debug_philox(self.h, len(ctr), _ptr(ctr), _ptr(key), _ptr(out)))
+        return out
+
+    def debug_trace_rays(self, o, d):
+        o = np.ascontiguousarray(o, np.float32).reshape(-1, 3)
+        d = np.ascontiguousarray(d, np.float32).reshape(-1, 3)
+        t = np.zeros(len(o), np.float32)
+        prim = np.zeros(len(o), np.int32)
+        self._check(lib().sdd_debug_trace_rays(self.h, len(o), _ptr(o), _ptr(d), _ptr(t), _ptr(prim)))
+        return t, prim
+
+
+def render(scene, W, H, spp, max_depth, grid=(1, 1, 1), *, camera=None, seed=0, logs=False, tracer=None):
+    """Convenience: one render; returns numpy spectral [H*W, nl], xyz, and optional logs."""
+    t = tracer or Tracer()
+    t.load_scene(scene)
+    t.build_bvh(*grid)
+    cam = camera or scene["camera"]
+    hl = sl = None
+    if logs:
+        hl = t.new_log(W, H, spp, max_depth)
+        sl = t.new_log(W, H, spp, max_depth)
+    t.trace_spectral(cam, W, H, spp, max_depth, seed=seed, hit_log=hl, shadow_log=sl)
+    s, x = t.resolve_image(0, W, H)
+    out = dict(spectral=s.cpu().numpy(), xyz=x.cpu().numpy())
+    if logs:
+        out["hit_log"] = hl.cpu().numpy()
+        out["shadow_log"] = sl.cpu().numpy()
+    out["stats"] = t.stats()
+    return out

@@ -1,0 +1,978 @@
+// C ABI of libsdd (include/sdd.h): context, validation, device memory, and
+// the host scheduler that drives the per-subdomain queue sweeps.
+//
+// Sweep schedule of one batch of paths (Sec. 4 inverse ray tracing organised
+// as the Sec. 5 domain decomposition):
+//   camgen -> for depth d = 1..D:
+//       S sweeps of k_trace<closest>  over the subdomain queues
+//       k_shade(d)                     (resolves the shadow rays of d-1)
+//       S sweeps of k_trace<shadow>
+//   k_shade(final) -> k_flush
+// S = nx + ny + nz - 2 bounds the number of cells a straight ray can visit,
+// so a fixed number of sweeps drains every queue with no host round trip; a
+// sweep over empty queues exits after reading the per-cell counters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bvh_build.h"
+#include "kernels.h"
+#include "layout.h"
+#include "sdd.h"
+
+using namespace sdd;
+
+namespace {
+
+struct Render {
+    int W = 0, H = 0;
+    float* acc = nullptr;  // [nl][W*H] FP32
+    long long spp_done = 0;
+};
+
+struct TimedLaunch {
+    int cls;  // 0 ext trace, 1 shadow trace, 2 shade, 3 other
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct sdd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int n_cu = 256;
+    int trace_grid = 0;
+
+    // scene (host copies used by the builder)
+    bool has_scene = false, has_bvh = false;
+    int V = 0, T = 0, M = 0, nl = 0, nlp = 0;
+    std::vector<float> verts;
+    std::vector<int32_t> tris, tri_mat, mat_type;
+    int light_type = 0, light_mat = -1;
+    float lp0[3] = {0, 0, 0}, le1[3] = {0, 0, 0}, le2[3] = {0, 0, 0}, nL[3] = {0, 0, 0};
+    float light_area = 0.0f;
+
+    // device scene
+    float4* d_prim_info = nullptr;
+    int* d_mat_type = nullptr;
+    int* d_mat_has_le = nullptr;
+    float* d_mat_thick = nullptr;
+    float* d_rho = nullptr;
+    float* d_mn = nullptr;
+    float* d_mk = nullptr;
+    float* d_le = nullptr;
+    float* d_lambda = nullptr;
+    double* d_w = nullptr;
+    double* d_cmf = nullptr;
+
+    // device accel
+    GridBvh gb;
+    float4* d_nodes = nullptr;
+    float4* d_tris = nullptr;
+    int* d_cell_root = nullptr;
+    float* d_planes = nullptr;
+    GridParams grid{};
+    int G = 0, S = 0;
+
+    // batch buffers
+    long long ncap = 0;
+    int dcap = 0;  // depth capacity of the counter arrays
+    float4* ray_o = nullptr;
+    float4* ray_d = nullptr;
+    float2* hit = nullptr;
+    uint32_t* flags = nullptr;
+    float* beta = nullptr;
+    float* Lp = nullptr;
+    float* nee_g = nullptr;
+    int* sh_state = nullptr;
+    int* sh_cnt = nullptr;
+    float2* sh_glass = nullptr;
+    float4* qa[3] = {nullptr, nullptr, nullptr};
+    float4* qb[3] = {nullptr, nullptr, nullptr};
+    int2* qc[3] = {nullptr, nullptr, nullptr};
+    int* d_counts = nullptr;
+    int* d_sched = nullptr;
+    long long counts_len = 0, sched_len = 0;
+    int* d_overflow = nullptr;
+    unsigned long long* d_stats = nullptr;
+
+    std::map<int, Render> renders;
+    std::map<void*, size_t> allocs;
+    long long device_bytes = 0;
+
+    // host stats
+    long long batches = 0, launches_trace = 0;
+    double ms[4] = {0, 0, 0, 0};
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
+    int leftover = 0;
+};
+
+namespace {
+
+sdd_status fail(sdd_ctx* c, sdd_status st, const std::string& msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+sdd_status hip_fail(sdd_ctx* c, hipError_t e, const char* what) {
+    return fail(c, SDD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, expr)                                          \
+    do {                                                          \
+        hipError_t e_ = (expr);                                   \
+        if (e_ != hipSuccess) return hip_fail((c), e_, #expr);    \
+    } while (0)
+
+template <class T>
+sdd_status dalloc(sdd_ctx* c, T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    const size_t bytes = count * sizeof(T);
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, SDD_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    c->allocs[q] = bytes;
+    c->device_bytes += (long long)bytes;
+    *p = static_cast<T*>(q);
+    return SDD_OK;
+}
+
+template <class T>
+void dfree(sdd_ctx* c, T*& p) {
+    if (!p) return;
+    auto it = c->allocs.find((void*)p);
+    if (it != c->allocs.end()) {
+        c->device_bytes -= (long long)it->second;
+        c->allocs.erase(it);
+    }
+    (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+template <class T>
+sdd_status upload(sdd_ctx* c, T** p, const T* src, size_t count) {
+    sdd_status st = dalloc(c, p, count);
+    if (st != SDD_OK) return st;
+    if (count) HIP_TRY(c, hipMemcpyAsync(*p, src, count * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return SDD_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+void free_scene(sdd_ctx* c) {
+    dfree(c, c->d_prim_info);
+    dfree(c, c->d_mat_type);
+    dfree(c, c->d_mat_has_le);
+    dfree(c, c->d_mat_thick);
+    dfree(c, c->d_rho);
+    dfree(c, c->d_mn);
+    dfree(c, c->d_mk);
+    dfree(c, c->d_le);
+    dfree(c, c->d_lambda);
+    dfree(c, c->d_w);
+    dfree(c, c->d_cmf);
+    c->has_scene = false;
+}
+
+void free_accel(sdd_ctx* c) {
+    dfree(c, c->d_nodes);
+    dfree(c, c->d_tris);
+    dfree(c, c->d_cell_root);
+    dfree(c, c->d_planes);
+    c->has_bvh = false;
+}
+
+void free_batch(sdd_ctx* c) {
+    dfree(c, c->ray_o);
+    dfree(c, c->ray_d);
+    dfree(c, c->hit);
+    dfree(c, c->flags);
+    dfree(c, c->beta);
+    dfree(c, c->Lp);
+    dfree(c, c->nee_g);
+    dfree(c, c->sh_state);
+    dfree(c, c->sh_cnt);
+    dfree(c, c->sh_glass);
+    for (int i = 0; i < 3; ++i) {
+        dfree(c, c->qa[i]);
+        dfree(c, c->qb[i]);
+        dfree(c, c->qc[i]);
+    }
+    dfree(c, c->d_counts);
+    dfree(c, c->d_sched);
+    c->ncap = 0;
+    c->dcap = 0;
+}
+
+void free_renders(sdd_ctx* c) {
+    for (auto& kv : c->renders) dfree(c, kv.second.acc);
+    c->renders.clear();
+}
+
+std::string validate(const sdd_scene_desc* s) {
+    if (!s) return "null scene";
+    if (s->n_tris <= 0) return "scene has no triangles";
+    if (s->n_verts <= 0 || !s->verts) return "scene has no vertices";
+    if (!s->tris || !s->tri_mat) return "null triangle arrays";
+    if (s->n_lambda < 1 || s->n_lambda > SDD_MAX_LAMBDA) return "n_lambda out of range";
+    if (!s->lambda_nm || !s->lambda_w || !s->cmf) return "null wavelength arrays";
+    if (s->n_mats <= 0 || !s->mat_type || !s->mat_rho || !s->mat_n || !s->mat_k || !s->mat_thick || !s->mat_le)
+        return "null material arrays";
+    for (long long i = 0; i < 3LL * s->n_verts; ++i)
+        if (!std::isfinite(s->verts[i])) return "non-finite vertex coordinate at " + std::to_string(i / 3);
+    for (long long i = 0; i < 3LL * s->n_tris; ++i)
+        if (s->tris[i] < 0 || s->tris[i] >= s->n_verts) return "vertex index out of range in triangle " + std::to_string(i / 3);
+    for (int i = 0; i < s->n_tris; ++i)
+        if (s->tri_mat[i] < 0 || s->tri_mat[i] >= s->n_mats) return "material index out of range in triangle " + std::to_string(i);
+    for (int l = 0; l < s->n_lambda; ++l) {
+        if (!(s->lambda_nm[l] > 0.0f) || !std::isfinite(s->lambda_nm[l])) return "wavelength must be positive";
+        if (!std::isfinite(s->lambda_w[l])) return "non-finite wavelength weight";
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(s->cmf[3 * l + k])) return "non-finite colour matching value";
+    }
+    const int nl = s->n_lambda;
+    for (int m = 0; m < s->n_mats; ++m) {
+        const int t = s->mat_type[m];
+        if (t != SDD_MAT_DIFFUSE && t != SDD_MAT_GLASS_SLAB && t != SDD_MAT_EMITTER) return "unknown material type";
+        if (!(s->mat_thick[m] >= 0.0f) || !std::isfinite(s->mat_thick[m])) return "slab thickness must be >= 0";
+        for (int l = 0; l < nl; ++l) {
+            const size_t i = (size_t)m * nl + l;
+            if (!(s->mat_rho[i] >= 0.0f && s->mat_rho[i] <= 1.0f)) return "reflectance outside [0, 1]";
+            if (!(s->mat_n[i] > 0.0f) || !std::isfinite(s->mat_n[i])) return "refractive index n must be > 0";
+            if (!(s->mat_k[i] >= 0.0f) || !std::isfinite(s->mat_k[i])) return "absorption index k must be >= 0";
+            if (!(s->mat_le[i] >= 0.0f) || !std::isfinite(s->mat_le[i])) return "emission must be >= 0";
+            if (t == SDD_MAT_GLASS_SLAB && s->mat_le[i] != 0.0f) return "glass material cannot emit";
+        }
+    }
+    if (s->light_type != SDD_LIGHT_NONE && s->light_type != SDD_LIGHT_PARALLELOGRAM && s->light_type != SDD_LIGHT_POINT)
+        return "unknown light type";
+    if (s->light_type != SDD_LIGHT_NONE) {
+        if (s->light_mat < 0 || s->light_mat >= s->n_mats) return "light material out of range";
+        if (s->mat_type[s->light_mat] != SDD_MAT_EMITTER) return "light material must be an emitter";
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(s->light_p0[k]) || !std::isfinite(s->light_e1[k]) || !std::isfinite(s->light_e2[k]))
+                return "non-finite light geometry";
+        if (s->light_type == SDD_LIGHT_PARALLELOGRAM) {
+            const double e1[3] = {s->light_e1[0], s->light_e1[1], s->light_e1[2]};
+            const double e2[3] = {s->light_e2[0], s->light_e2[1], s->light_e2[2]};
+            const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                         cz = e1[0] * e2[1] - e1[1] * e2[0];
+            if (!(cx * cx + cy * cy + cz * cz > 0.0)) return "degenerate parallelogram light";
+        }
+    }
+    return "";
+}
+
+hipEvent_t take_event(sdd_ctx* c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// collect the durations of finished timed launches (stream must be synchronised)
+void harvest_events(sdd_ctx* c) {
+    for (auto& t : c->timed) {
+        float ms = 0.0f;
+        if (t.a && t.b && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) c->ms[t.cls] += ms;
+        if (t.a) c->event_pool.push_back(t.a);
+        if (t.b) c->event_pool.push_back(t.b);
+    }
+    c->timed.clear();
+}
+
+struct Timer {
+    sdd_ctx* c;
+    bool on;
+    TimedLaunch t{};
+    Timer(sdd_ctx* ctx, bool enabled, int cls) : c(ctx), on(enabled) {
+        if (!on) return;
+        t.cls = cls;
+        t.a = take_event(c);
+        t.b = take_event(c);
+        if (t.a) (void)hipEventRecord(t.a, c->stream);
+    }
+    ~Timer() {
+        if (!on) return;
+        if (t.b) (void)hipEventRecord(t.b, c->stream);
+        c->timed.push_back(t);
+    }
+};
+
+long long mem_budget_bytes() {
+    const char* s = std::getenv("SDD_MEM_BUDGET_GB");
+    double gb = s ? std::atof(s) : 48.0;
+    if (!(gb > 0.0)) gb = 48.0;
+    return (long long)(gb * 1024.0 * 1024.0 * 1024.0);
+}
+
+long long bytes_per_path(const sdd_ctx* c) {
+    return 3LL * c->G * (16 + 16 + 8) + 8LL * c->nlp + 16 + 16 + 8 + 4 + 4 + 4 + 4 + 8 * kMaxGlass;
+}
+
+sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
+    const long long cnt_len = (long long)(2 * max_depth + 1) * (c->S + 1) * c->G;
+    const long long sch_len = (long long)(2 * max_depth + 1) * (c->S + 1) * kXcd;
+    if (n <= c->ncap && max_depth <= c->dcap) return SDD_OK;
+    free_batch(c);
+    sdd_status st;
+    const long long qn = (long long)c->G * n;
+#define ALLOC(ptr, cnt)                            \
+    if ((st = dalloc(c, &(ptr), (size_t)(cnt))) != SDD_OK) { \
+        free_batch(c);                             \
+        return st;                                 \
+    }
+    ALLOC(c->ray_o, n);
+    ALLOC(c->ray_d, n);
+    ALLOC(c->hit, n);
+    ALLOC(c->flags, n);
+    ALLOC(c->beta, n * c->nlp);
+    ALLOC(c->Lp, n * c->nlp);
+    ALLOC(c->nee_g, n);
+    ALLOC(c->sh_state, n);
+    ALLOC(c->sh_cnt, n);
+    ALLOC(c->sh_glass, n * kMaxGlass);
+    for (int i = 0; i < 3; ++i) {
+        ALLOC(c->qa[i], qn);
+        ALLOC(c->qb[i], qn);
+        ALLOC(c->qc[i], qn);
+    }
+    ALLOC(c->d_counts, cnt_len);
+    ALLOC(c->d_sched, sch_len);
+#undef ALLOC
+    c->counts_len = cnt_len;
+    c->sched_len = sch_len;
+    c->ncap = n;
+    c->dcap = max_depth;
+    return SDD_OK;
+}
+
+// counters / scheduler slots of (phase, sweep)
+inline int* counts_at(sdd_ctx* c, int phase, int k) { return c->d_counts + ((long long)phase * (c->S + 1) + k) * c->G; }
+inline int* sched_at(sdd_ctx* c, int phase, int k) { return c->d_sched + ((long long)phase * (c->S + 1) + k) * kXcd; }
+
+TraceParams trace_params(sdd_ctx* c, int in_buf, int out_buf, int phase, int k, long long cap) {
+    TraceParams p{};
+    p.qa_in = c->qa[in_buf];
+    p.qb_in = c->qb[in_buf];
+    p.qc_in = c->qc[in_buf];
+    p.cnt_in = counts_at(c, phase, k);
+    p.qa_out = c->qa[out_buf];
+    p.qb_out = c->qb[out_buf];
+    p.qc_out = c->qc[out_buf];
+    p.cnt_out = counts_at(c, phase, k + 1);
+    p.sched = sched_at(c, phase, k);
+    p.cap = cap;
+    p.n_cells = c->G;
+    p.grid = c->grid;
+    p.nodes = c->d_nodes;
+    p.tris = c->d_tris;
+    p.cell_root = c->d_cell_root;
+    p.prim_info = c->d_prim_info;
+    p.hit = c->hit;
+    p.sh_state = c->sh_state;
+    p.sh_cnt = c->sh_cnt;
+    p.sh_glass = c->sh_glass;
+    p.overflow = c->d_overflow;
+    p.stats = c->d_stats;
+    return p;
+}
+
+// S sweeps of one phase; the phase's initial queue is buffer a, its partner b
+sdd_status run_sweeps(sdd_ctx* c, bool shadow, int phase, int a, int b, long long cap, bool count, bool timing) {
+    for (int k = 0; k < c->S; ++k) {
+        const int in = (k % 2 == 0) ? a : b, out = (k % 2 == 0) ? b : a;
+        TraceParams p = trace_params(c, in, out, phase, k, cap);
+        Timer tm(c, timing, shadow ? 1 : 0);
+        HIP_TRY(c, launch_trace(p, shadow, count, c->trace_grid, c->stream));
+        ++c->launches_trace;
+    }
+    return SDD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+sdd_status sdd_create(int hip_device, void* hip_stream, sdd_ctx** out) {
+    if (!out) return SDD_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SDD_ERR_HIP;
+    if (hip_device < 0 || hip_device >= ndev) return SDD_ERR_INVALID_ARG;
+    sdd_ctx* c = new (std::nothrow) sdd_ctx();
+    if (!c) return SDD_ERR_OOM;
+    c->device = hip_device;
+    DeviceGuard g(hip_device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    c->stream = (hipStream_t)hip_stream;  // NULL: the null stream, ordered with other default-stream work
+    const int per_cu = trace_blocks_per_cu();
+    c->trace_grid = std::max(kXcd, (c->n_cu * per_cu / kXcd) * kXcd);
+    if (dalloc(c, &c->d_overflow, 1) != SDD_OK || dalloc(c, &c->d_stats, kStatCount) != SDD_OK) {
+        sdd_destroy(c);
+        return SDD_ERR_OOM;
+    }
+    if (hipMemsetAsync(c->d_overflow, 0, sizeof(int), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_stats, 0, sizeof(unsigned long long) * kStatCount, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        sdd_destroy(c);
+        return SDD_ERR_HIP;
+    }
+    *out = c;
+    return SDD_OK;
+}
+
+void sdd_destroy(sdd_ctx* c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    harvest_events(c);
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    c->event_pool.clear();
+    free_renders(c);
+    free_batch(c);
+    free_accel(c);
+    free_scene(c);
+    dfree(c, c->d_overflow);
+    dfree(c, c->d_stats);
+    for (auto& kv : c->allocs) (void)hipFree(kv.first);
+    c->allocs.clear();
+    delete c;
+}
+
+const char* sdd_last_error(const sdd_ctx* c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+sdd_status sdd_validate_scene(const sdd_scene_desc* scene, char* msg, int msg_len) {
+    const std::string e = validate(scene);
+    if (msg && msg_len > 0) {
+        std::snprintf(msg, (size_t)msg_len, "%s", e.c_str());
+    }
+    return e.empty() ? SDD_OK : SDD_ERR_INVALID_ARG;
+}
+
+sdd_status sdd_load_scene(sdd_ctx* c, const sdd_scene_desc* s) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    const std::string e = validate(s);
+    if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    free_renders(c);
+    free_batch(c);
+    free_accel(c);
+    free_scene(c);
+    c->V = s->n_verts;
+    c->T = s->n_tris;
+    c->M = s->n_mats;
+    c->nl = s->n_lambda;
+    c->nlp = (c->nl + 3) / 4 * 4;
+    c->verts.assign(s->verts, s->verts + 3 * (size_t)c->V);
+    c->tris.assign(s->tris, s->tris + 3 * (size_t)c->T);
+    c->tri_mat.assign(s->tri_mat, s->tri_mat + c->T);
+    c->mat_type.assign(s->mat_type, s->mat_type + c->M);
+    c->light_type = s->light_type;
+    c->light_mat = s->light_mat;
+    for (int k = 0; k < 3; ++k) {
+        c->lp0[k] = s->light_p0[k];
+        c->le1[k] = s->light_e1[k];
+        c->le2[k] = s->light_e2[k];
+    }
+    if (c->light_type == SDD_LIGHT_PARALLELOGRAM) {
+        const double e1[3] = {s->light_e1[0], s->light_e1[1], s->light_e1[2]};
+        const double e2[3] = {s->light_e2[0], s->light_e2[1], s->light_e2[2]};
+        const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const double a = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int k = 0; k < 3; ++k) c->nL[k] = (float)(n[k] / a);
+        c->light_area = (float)a;
+    } else {
+        c->nL[0] = c->nL[1] = c->nL[2] = 0.0f;
+        c->light_area = 0.0f;
+    }
+    // per-material tables padded to nlp wavelengths
+    const int nl = c->nl, nlp = c->nlp, M = c->M;
+    std::vector<float> rho((size_t)M * nlp, 0.0f), mn((size_t)M * nlp, 1.0f), mk((size_t)M * nlp, 0.0f),
+        le((size_t)M * nlp, 0.0f);
+    std::vector<int> has_le(M, 0);
+    for (int m = 0; m < M; ++m)
+        for (int l = 0; l < nl; ++l) {
+            const size_t i = (size_t)m * nl + l, j = (size_t)m * nlp + l;
+            rho[j] = s->mat_rho[i];
+            mn[j] = s->mat_n[i];
+            mk[j] = s->mat_k[i];
+            le[j] = s->mat_le[i];
+            if (s->mat_le[i] != 0.0f) has_le[m] = 1;
+        }
+    std::vector<float> lam(nlp, 550.0f);
+    for (int l = 0; l < nl; ++l) lam[l] = s->lambda_nm[l];
+    BuildInput bi{c->verts.data(), c->V, c->tris.data(), c->T, c->tri_mat.data(), c->mat_type.data(), 1, 1, 1, 4, 16};
+    std::vector<HostF4> info;
+    triangle_info(bi, info);
+    sdd_status st;
+    if ((st = upload(c, &c->d_prim_info, reinterpret_cast<const float4*>(info.data()), info.size())) != SDD_OK ||
+        (st = upload(c, &c->d_mat_type, c->mat_type.data(), (size_t)M)) != SDD_OK ||
+        (st = upload(c, &c->d_mat_has_le, has_le.data(), (size_t)M)) != SDD_OK ||
+        (st = upload(c, &c->d_mat_thick, s->mat_thick, (size_t)M)) != SDD_OK ||
+        (st = upload(c, &c->d_rho, rho.data(), rho.size())) != SDD_OK ||
+        (st = upload(c, &c->d_mn, mn.data(), mn.size())) != SDD_OK ||
+        (st = upload(c, &c->d_mk, mk.data(), mk.size())) != SDD_OK ||
+        (st = upload(c, &c->d_le, le.data(), le.size())) != SDD_OK ||
+        (st = upload(c, &c->d_lambda, lam.data(), lam.size())) != SDD_OK ||
+        (st = upload(c, &c->d_w, s->lambda_w, (size_t)nl)) != SDD_OK ||
+        (st = upload(c, &c->d_cmf, s->cmf, (size_t)nl * 3)) != SDD_OK) {
+        free_scene(c);
+        return st;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->has_scene = true;
+    return SDD_OK;
+}
+
+sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!d) return fail(c, SDD_ERR_INVALID_ARG, "null bvh desc");
+    if (!c->has_scene) return fail(c, SDD_ERR_STATE, "sdd_build_bvh before sdd_load_scene");
+    if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0) return fail(c, SDD_ERR_INVALID_ARG, "grid dims must be > 0");
+    if ((long long)d->nx * d->ny * d->nz > SDD_MAX_CELLS) return fail(c, SDD_ERR_INVALID_ARG, "too many cells");
+    const int leaf = d->leaf_max == 0 ? 4 : d->leaf_max;
+    const int bins = d->sah_bins == 0 ? 16 : d->sah_bins;
+    if (leaf < 1 || leaf > 8) return fail(c, SDD_ERR_INVALID_ARG, "leaf_max out of range");
+    if (bins < 2 || bins > 64) return fail(c, SDD_ERR_INVALID_ARG, "sah_bins out of range");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    free_renders(c);
+    free_batch(c);
+    free_accel(c);
+    BuildInput bi{c->verts.data(), c->V, c->tris.data(), c->T, c->tri_mat.data(), c->mat_type.data(),
+                  d->nx, d->ny, d->nz, leaf, bins};
+    std::string err;
+    GridBvh gb;
+    if (!build_grid_bvh(bi, gb, err)) return fail(c, SDD_ERR_INVALID_ARG, err);
+    sdd_status st;
+    if ((st = upload(c, &c->d_nodes, reinterpret_cast<const float4*>(gb.nodes.data()), gb.nodes.size())) != SDD_OK ||
+        (st = upload(c, &c->d_tris, reinterpret_cast<const float4*>(gb.tris.data()), gb.tris.size())) != SDD_OK ||
+        (st = upload(c, &c->d_cell_root, gb.cell_root.data(), gb.cell_root.size())) != SDD_OK ||
+        (st = upload(c, &c->d_planes, gb.planes.data(), gb.planes.size())) != SDD_OK) {
+        free_accel(c);
+        return st;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->G = d->nx * d->ny * d->nz;
+    c->S = d->nx + d->ny + d->nz - 2;
+    GridParams& gp = c->grid;
+    gp.planes = c->d_planes;
+    gp.nx = d->nx;
+    gp.ny = d->ny;
+    gp.nz = d->nz;
+    gp.off_y = d->nx + 1;
+    gp.off_z = d->nx + 1 + d->ny + 1;
+    const int n[3] = {d->nx, d->ny, d->nz};
+    const int off[3] = {0, gp.off_y, gp.off_z};
+    for (int a = 0; a < 3; ++a) {
+        gp.lo[a] = gb.planes[off[a]];
+        gp.hi[a] = gb.planes[off[a] + n[a]];
+        gp.inv_h[a] = (float)((double)n[a] / ((double)gp.hi[a] - (double)gp.lo[a]));
+    }
+    c->gb = std::move(gb);
+    c->gb.nodes.clear();
+    c->gb.nodes.shrink_to_fit();
+    c->gb.tris.clear();
+    c->gb.tris.shrink_to_fit();
+    c->has_bvh = true;
+    return SDD_OK;
+}
+
+sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!t) return fail(c, SDD_ERR_INVALID_ARG, "null trace desc");
+    if (!c->has_bvh) return fail(c, SDD_ERR_STATE, "sdd_trace_spectral before sdd_build_bvh");
+    if (t->W <= 0 || t->H <= 0 || t->spp <= 0) return fail(c, SDD_ERR_INVALID_ARG, "W, H and spp must be > 0");
+    if ((long long)t->W * t->H > (1LL << 28)) return fail(c, SDD_ERR_INVALID_ARG, "image too large");
+    if (t->max_depth < 1 || t->max_depth > SDD_MAX_DEPTH) return fail(c, SDD_ERR_INVALID_ARG, "max_depth out of range");
+    if (t->render_id < 0) return fail(c, SDD_ERR_INVALID_ARG, "render_id must be >= 0");
+    if (t->sample_offset < 0) return fail(c, SDD_ERR_INVALID_ARG, "sample_offset must be >= 0");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(t->eye[k]) || !std::isfinite(t->target[k]))
+            return fail(c, SDD_ERR_INVALID_ARG, "non-finite camera");
+    const double f0[3] = {(double)t->target[0] - t->eye[0], (double)t->target[1] - t->eye[1],
+                          (double)t->target[2] - t->eye[2]};
+    const double fl = std::sqrt(f0[0] * f0[0] + f0[1] * f0[1] + f0[2] * f0[2]);
+    if (!(fl > 0.0)) return fail(c, SDD_ERR_INVALID_ARG, "eye == target");
+    const double f[3] = {f0[0] / fl, f0[1] / fl, f0[2] / fl};
+    double r[3] = {f[1], -f[0], 0.0};  // f x z
+    const double rl = std::sqrt(r[0] * r[0] + r[1] * r[1]);
+    if (!(rl > 1e-9)) return fail(c, SDD_ERR_INVALID_ARG, "view direction parallel to +z");
+    for (double& v : r) v /= rl;
+    const double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+    const bool ortho = (t->flags & SDD_TRACE_ORTHO) != 0;
+    if (!ortho && !(t->fov_deg > 0.0f && t->fov_deg < 180.0f)) return fail(c, SDD_ERR_INVALID_ARG, "fov out of range");
+    if (ortho && !(t->ortho_half_h > 0.0f)) return fail(c, SDD_ERR_INVALID_ARG, "ortho_half_h must be > 0");
+    DeviceGuard g(c->device);
+
+    auto it = c->renders.find(t->render_id);
+    if (it != c->renders.end() && (it->second.W != t->W || it->second.H != t->H))
+        return fail(c, SDD_ERR_INVALID_ARG, "render_id reused with a different W, H");
+    const int WH = t->W * t->H;
+    if (it == c->renders.end()) {
+        Render rd;
+        rd.W = t->W;
+        rd.H = t->H;
+        sdd_status st = dalloc(c, &rd.acc, (size_t)c->nl * WH);
+        if (st != SDD_OK) return st;
+        HIP_TRY(c, hipMemsetAsync(rd.acc, 0, sizeof(float) * (size_t)c->nl * WH, c->stream));
+        it = c->renders.emplace(t->render_id, rd).first;
+    }
+    Render& rd = it->second;
+
+    const long long total = (long long)WH * t->spp;
+    long long nb = std::max<long long>(64, mem_budget_bytes() / bytes_per_path(c));
+    nb = std::min<long long>(nb, 1LL << 26);
+    nb = std::min(nb, total);
+    sdd_status st = ensure_batch(c, nb, t->max_depth);
+    if (st != SDD_OK) return st;
+    const bool timing = (t->flags & SDD_TRACE_TIME_KERNELS) != 0;
+    const bool count = (t->flags & SDD_TRACE_COUNT_WORK) != 0;
+    const int D = t->max_depth;
+    const uint2 key = make_uint2(t->seed, (uint32_t)t->render_id);
+    if (t->hit_log) {
+        Timer tm(c, timing, 3);
+        HIP_TRY(c, launch_fill_i32(t->hit_log, total * D, -2, c->stream));
+    }
+    if (t->shadow_log) {
+        Timer tm(c, timing, 3);
+        HIP_TRY(c, launch_fill_i32(t->shadow_log, total * D, -2, c->stream));
+    }
+
+    for (long long g0 = 0; g0 < total; g0 += nb) {
+        const int N = (int)std::min(nb, total - g0);
+        const long long cap = N;
+        {
+            Timer tm(c, timing, 3);
+            HIP_TRY(c, launch_fill_i32(c->d_counts, c->counts_len, 0, c->stream));
+            HIP_TRY(c, launch_fill_i32(c->d_sched, c->sched_len, 0, c->stream));
+        }
+        CamParams cp{};
+        cp.N = N;
+        cp.g0 = g0;
+        cp.W = t->W;
+        cp.H = t->H;
+        cp.WH = WH;
+        cp.s0 = t->sample_offset;
+        cp.key = key;
+        cp.ortho = ortho ? 1 : 0;
+        for (int k = 0; k < 3; ++k) {
+            cp.eye[k] = t->eye[k];
+            cp.fwd[k] = (float)f[k];
+            cp.right[k] = (float)r[k];
+            cp.up[k] = (float)u[k];
+        }
+        cp.tan_half = (float)std::tan(0.5 * (double)t->fov_deg * M_PI / 180.0);
+        cp.aspect = (float)((double)t->W / (double)t->H);
+        cp.ortho_half_h = t->ortho_half_h;
+        cp.nlp = c->nlp;
+        cp.flags = c->flags;
+        cp.ray_o = c->ray_o;
+        cp.ray_d = c->ray_d;
+        cp.hit = c->hit;
+        cp.beta = c->beta;
+        cp.Lp = c->Lp;
+        cp.sh_state = c->sh_state;
+        cp.grid = c->grid;
+        cp.eqa = c->qa[0];
+        cp.eqb = c->qb[0];
+        cp.eqc = c->qc[0];
+        cp.ecnt = counts_at(c, 0, 0);
+        cp.cap = cap;
+        cp.stats = c->d_stats;
+        {
+            Timer tm(c, timing, 3);
+            HIP_TRY(c, launch_camgen(cp, c->stream));
+        }
+        ShadeParams sp{};
+        sp.N = N;
+        sp.g0 = g0;
+        sp.W = t->W;
+        sp.WH = WH;
+        sp.s0 = t->sample_offset;
+        sp.spp_call = t->spp;
+        sp.max_depth = D;
+        sp.key = key;
+        sp.flags = c->flags;
+        sp.ray_o = c->ray_o;
+        sp.ray_d = c->ray_d;
+        sp.hit = c->hit;
+        sp.beta = c->beta;
+        sp.Lp = c->Lp;
+        sp.nee_g = c->nee_g;
+        sp.sh_state = c->sh_state;
+        sp.sh_cnt = c->sh_cnt;
+        sp.sh_glass = c->sh_glass;
+        sp.prim_info = c->d_prim_info;
+        sp.mat_type = c->d_mat_type;
+        sp.mat_has_le = c->d_mat_has_le;
+        sp.mat_thick = c->d_mat_thick;
+        sp.rho = c->d_rho;
+        sp.mn = c->d_mn;
+        sp.mk = c->d_mk;
+        sp.le = c->d_le;
+        sp.lambda_nm = c->d_lambda;
+        sp.nl = c->nl;
+        sp.nlp = c->nlp;
+        sp.light_type = c->light_type;
+        for (int k = 0; k < 3; ++k) {
+            sp.lp0[k] = c->lp0[k];
+            sp.le1[k] = c->le1[k];
+            sp.le2[k] = c->le2[k];
+            sp.nL[k] = c->nL[k];
+        }
+        sp.light_area = c->light_area;
+        sp.light_mat = c->light_mat < 0 ? 0 : c->light_mat;
+        sp.grid = c->grid;
+        sp.eqa = c->qa[0];
+        sp.eqb = c->qb[0];
+        sp.eqc = c->qc[0];
+        sp.sqa = c->qa[1];
+        sp.sqb = c->qb[1];
+        sp.sqc = c->qc[1];
+        sp.cap = cap;
+        sp.hit_log = t->hit_log;
+        sp.shadow_log = t->shadow_log;
+        sp.stats = c->d_stats;
+        for (int d = 1; d <= D; ++d) {
+            const int ph_e = 2 * (d - 1), ph_s = 2 * (d - 1) + 1;
+            st = run_sweeps(c, false, ph_e, 0, 1, cap, count, timing);
+            if (st != SDD_OK) return st;
+            sp.depth = d;
+            sp.final_pass = 0;
+            sp.ecnt = counts_at(c, 2 * d, 0);
+            sp.scnt = counts_at(c, ph_s, 0);
+            {
+                Timer tm(c, timing, 2);
+                HIP_TRY(c, launch_shade(sp, c->stream));
+            }
+            st = run_sweeps(c, true, ph_s, 1, 2, cap, count, timing);
+            if (st != SDD_OK) return st;
+        }
+        sp.depth = D + 1;
+        sp.final_pass = 1;
+        sp.ecnt = counts_at(c, 2 * D, 0);
+        sp.scnt = counts_at(c, 2 * D, 1);
+        {
+            Timer tm(c, timing, 2);
+            HIP_TRY(c, launch_shade(sp, c->stream));
+        }
+        {
+            Timer tm(c, timing, 3);
+            HIP_TRY(c, launch_flush(N, g0, WH, c->nl, c->Lp, rd.acc, c->stream));
+        }
+        ++c->batches;
+    }
+    rd.spp_done += t->spp;
+    return SDD_OK;
+}
+
+sdd_status sdd_resolve_image(sdd_ctx* c, int32_t render_id, double* spectral_out, double* xyz_out,
+                             int32_t out_is_device) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    auto it = c->renders.find(render_id);
+    if (it == c->renders.end()) return fail(c, SDD_ERR_STATE, "unknown render_id");
+    Render& rd = it->second;
+    if (rd.spp_done <= 0) return fail(c, SDD_ERR_STATE, "render has no samples");
+    DeviceGuard g(c->device);
+    const int WH = rd.W * rd.H;
+    double* ds = spectral_out;
+    double* dx = xyz_out;
+    double* tmp_s = nullptr;
+    double* tmp_x = nullptr;
+    if (!out_is_device) {
+        if (spectral_out && dalloc(c, &tmp_s, (size_t)WH * c->nl) != SDD_OK) return SDD_ERR_OOM;
+        if (xyz_out && dalloc(c, &tmp_x, (size_t)WH * 3) != SDD_OK) {
+            dfree(c, tmp_s);
+            return SDD_ERR_OOM;
+        }
+        ds = tmp_s;
+        dx = tmp_x;
+    }
+    hipError_t e = launch_resolve(WH, c->nl, 1.0 / (double)rd.spp_done, rd.acc, c->d_w, c->d_cmf, ds, dx, c->stream);
+    if (e == hipSuccess && !out_is_device) {
+        if (spectral_out)
+            e = hipMemcpyAsync(spectral_out, tmp_s, sizeof(double) * (size_t)WH * c->nl, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && xyz_out)
+            e = hipMemcpyAsync(xyz_out, tmp_x, sizeof(double) * (size_t)WH * 3, hipMemcpyDeviceToHost, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(c, tmp_s);
+    dfree(c, tmp_x);
+    if (e != hipSuccess) return hip_fail(c, e, "resolve");
+    int ovf = 0;
+    HIP_TRY(c, hipMemcpy(&ovf, c->d_overflow, sizeof(int), hipMemcpyDeviceToHost));
+    if (ovf) return fail(c, SDD_ERR_OVERFLOW, "a shadow segment crossed more glass panes than tracked");
+    return SDD_OK;
+}
+
+sdd_status sdd_reset_render(sdd_ctx* c, int32_t render_id) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    auto it = c->renders.find(render_id);
+    if (it == c->renders.end()) return fail(c, SDD_ERR_STATE, "unknown render_id");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c, it->second.acc);
+    c->renders.erase(it);
+    return SDD_OK;
+}
+
+sdd_status sdd_get_stats(sdd_ctx* c, sdd_stats* out) {
+    if (!c || !out) return SDD_ERR_INVALID_ARG;
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    harvest_events(c);
+    unsigned long long s[kStatCount];
+    HIP_TRY(c, hipMemcpy(s, c->d_stats, sizeof(s), hipMemcpyDeviceToHost));
+    int ovf = 0;
+    HIP_TRY(c, hipMemcpy(&ovf, c->d_overflow, sizeof(int), hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    out->ext_rays = (int64_t)s[kStatExtRays];
+    out->shadow_rays = (int64_t)s[kStatShadowRays];
+    out->ext_cell_visits = (int64_t)s[kStatExtVisits];
+    out->shadow_cell_visits = (int64_t)s[kStatShadowVisits];
+    out->node_visits = (int64_t)s[kStatNodes];
+    out->tri_tests = (int64_t)s[kStatTris];
+    out->batches = c->batches;
+    out->launches_trace = c->launches_trace;
+    out->ms_trace_ext = c->ms[0];
+    out->ms_trace_shadow = c->ms[1];
+    out->ms_shade = c->ms[2];
+    out->ms_other = c->ms[3];
+    out->n_refs = c->has_bvh ? c->gb.n_refs : 0;
+    long long nn = 0;
+    for (int v : c->gb.cell_nodes) nn += v;
+    out->n_nodes = c->has_bvh ? nn : 0;
+    out->max_bvh_depth = c->has_bvh ? c->gb.max_depth : 0;
+    out->n_cells = c->has_bvh ? c->G : 0;
+    out->device_bytes = c->device_bytes;
+    out->paths_per_batch = c->ncap;
+    out->overflow = ovf;
+    return SDD_OK;
+}
+
+sdd_status sdd_reset_stats(sdd_ctx* c) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    harvest_events(c);
+    HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, sizeof(unsigned long long) * kStatCount, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->batches = 0;
+    c->launches_trace = 0;
+    for (double& m : c->ms) m = 0.0;
+    return SDD_OK;
+}
+
+sdd_status sdd_debug_philox(sdd_ctx* c, int32_t n, const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!ctr || !key || !out))) return fail(c, SDD_ERR_INVALID_ARG, "bad philox arguments");
+    if (n == 0) return SDD_OK;
+    DeviceGuard g(c->device);
+    uint4* dc = nullptr;
+    uint4* dout = nullptr;
+    if (dalloc(c, &dc, (size_t)n) != SDD_OK || dalloc(c, &dout, (size_t)n) != SDD_OK) {
+        dfree(c, dc);
+        return SDD_ERR_OOM;
+    }
+    hipError_t e = hipMemcpyAsync(dc, ctr, sizeof(uint4) * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_philox(n, dc, make_uint2(key[0], key[1]), dout, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(uint4) * (size_t)n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(c, dc);
+    dfree(c, dout);
+    if (e != hipSuccess) return hip_fail(c, e, "debug philox");
+    return SDD_OK;
+}
+
+sdd_status sdd_debug_trace_rays(sdd_ctx* c, int32_t n, const float* o, const float* d, float* t_out,
+                                int32_t* prim_out) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!c->has_bvh) return fail(c, SDD_ERR_STATE, "sdd_debug_trace_rays before sdd_build_bvh");
+    if (n < 0 || (n > 0 && (!o || !d || !t_out || !prim_out))) return fail(c, SDD_ERR_INVALID_ARG, "bad ray arguments");
+    if (n == 0) return SDD_OK;
+    for (long long i = 0; i < 3LL * n; ++i)
+        if (!std::isfinite(o[i]) || !std::isfinite(d[i])) return fail(c, SDD_ERR_INVALID_ARG, "non-finite ray");
+    DeviceGuard g(c->device);
+    sdd_status st = ensure_batch(c, std::max<long long>(n, c->ncap), std::max(1, c->dcap));
+    if (st != SDD_OK) return st;
+    float* dor = nullptr;
+    float* ddr = nullptr;
+    if (dalloc(c, &dor, 3 * (size_t)n) != SDD_OK || dalloc(c, &ddr, 3 * (size_t)n) != SDD_OK) {
+        dfree(c, dor);
+        return SDD_ERR_OOM;
+    }
+    hipError_t e = hipMemcpyAsync(dor, o, sizeof(float) * 3 * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ddr, d, sizeof(float) * 3 * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_fill_i32(c->d_counts, c->counts_len, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill_i32(c->d_sched, c->sched_len, 0, c->stream);
+    if (e == hipSuccess)
+        e = launch_debug_rays(n, dor, ddr, c->grid, c->hit, c->qa[0], c->qb[0], c->qc[0], counts_at(c, 0, 0), n,
+                              c->stream);
+    if (e != hipSuccess) {
+        dfree(c, dor);
+        dfree(c, ddr);
+        return hip_fail(c, e, "debug rays");
+    }
+    st = run_sweeps(c, false, 0, 0, 1, n, false, false);
+    std::vector<float2> h((size_t)n);
+    if (st == SDD_OK) {
+        e = hipMemcpyAsync(h.data(), c->hit, sizeof(float2) * (size_t)n, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    dfree(c, dor);
+    dfree(c, ddr);
+    if (st != SDD_OK) return st;
+    if (e != hipSuccess) return hip_fail(c, e, "debug rays copy");
+    for (int i = 0; i < n; ++i) {
+        t_out[i] = h[i].x;
+        int p;
+        std::memcpy(&p, &h[i].y, 4);
+        prim_out[i] = p;
+    }
+    return SDD_OK;
+}
+
+}  // extern "C"

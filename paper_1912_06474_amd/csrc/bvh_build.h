@@ -1,0 +1,46 @@
+// Host builder of the subdomain grid and the per-subdomain BVHs.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace sdd {
+
+struct HostF4 {
+    float x, y, z, w;
+};
+
+struct GridBvh {
+    int nx = 1, ny = 1, nz = 1;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    std::vector<float> planes;      // nx+1, ny+1, nz+1 planes (float)
+    std::vector<HostF4> nodes;      // 4 per node (layout.h)
+    std::vector<HostF4> tris;       // 3 per reference
+    std::vector<int32_t> cell_root; // per cell
+    std::vector<int32_t> cell_refs; // references per cell
+    std::vector<int32_t> cell_nodes;// nodes per cell
+    int64_t n_refs = 0;
+    int max_depth = 0;
+};
+
+struct BuildInput {
+    const float* verts;       // [V][3]
+    int n_verts;
+    const int32_t* tris;      // [T][3]
+    int n_tris;
+    const int32_t* tri_mat;   // [T]
+    const int32_t* mat_type;  // [M]
+    int nx, ny, nz;
+    int leaf_max;
+    int sah_bins;
+};
+
+// Returns false and fills err on failure.
+bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err);
+
+// Unit geometric normal (v1 - v0) x (v2 - v0) of every triangle, in double
+// then rounded, with the material index in w (as int bits).
+void triangle_info(const BuildInput& in, std::vector<HostF4>& info);
+
+}  // namespace sdd

@@ -1,0 +1,59 @@
+"""Parity metrics between the HIP path and the FP64 oracle (test helpers).
+
+Hit agreement: fraction of (pixel, sample, depth) slots whose hit ids (and,
+separately, shadow verdicts) are equal; slots after a divergence count as
+mismatches unless both paths have ended.  Radiance: on pixels whose every
+sample has identical hit and shadow logs, per-wavelength relative error of
+the GPU's FP64-resolved mean against the oracle's FP64 mean; 0 == 0 exactly.
+"""
+import numpy as np
+
+HIT_AGREE_MIN = 0.9999       # >= 99.99% identical hit ids
+REL_TOL = 1e-4               # per-pixel spectral radiance, relative to FP64
+EXCLUDED_MAX_FRAC = 1e-4     # pixels whose path sequences differ
+
+
+def hit_agreement(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    assert a.shape == b.shape, (a.shape, b.shape)
+    return float((a == b).mean())
+
+
+def matching_pixels(g, o):
+    """Pixels whose every sample has identical hit and shadow logs."""
+    hl = (g["hit_log"] == o["hit_log"]).reshape(len(g["hit_log"]), -1).all(1)
+    sl = (g["shadow_log"] == o["shadow_log"]).reshape(len(g["shadow_log"]), -1).all(1)
+    return hl & sl
+
+
+def rel_err(gpu, ora):
+    gpu = np.asarray(gpu, np.float64)
+    ora = np.asarray(ora, np.float64)
+    err = np.abs(gpu - ora)
+    den = np.abs(ora)
+    out = np.where(den > 0, err / np.where(den > 0, den, 1.0), np.where(err == 0, 0.0, np.inf))
+    return out
+
+
+def report(g, o):
+    hits = hit_agreement(g["hit_log"], o["hit_log"])
+    sh = hit_agreement(g["shadow_log"], o["shadow_log"])
+    m = matching_pixels(g, o)
+    re = rel_err(g["spectral"][m], o["spectral"][m]) if m.any() else np.zeros(1)
+    rex = rel_err(g["xyz"][m], o["xyz"][m]) if m.any() else np.zeros(1)
+    return dict(hit_agree=hits, shadow_agree=sh, excluded=int((~m).sum()), n_pix=int(len(m)),
+                max_rel=float(re.max()), max_rel_xyz=float(rex.max()),
+                n_over=int((re > REL_TOL).sum()))
+
+
+def assert_parity(g, o, excluded_max=None):
+    r = report(g, o)
+    print("parity:", r, flush=True)
+    assert r["hit_agree"] >= HIT_AGREE_MIN, r
+    assert r["shadow_agree"] >= HIT_AGREE_MIN, r
+    lim = excluded_max if excluded_max is not None else max(1, int(EXCLUDED_MAX_FRAC * r["n_pix"]))
+    assert r["excluded"] <= lim, r
+    assert r["max_rel"] <= REL_TOL, r
+    assert r["max_rel_xyz"] <= REL_TOL, r
+    return r

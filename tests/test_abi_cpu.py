@@ -1,0 +1,103 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/sdd.h, and validates scenes on the host."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sdd():
+    import paper_1912_06474_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_1912_06474_amd import build
+        build.build()
+    m.lib()
+    return m
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sdd.h")).read()
+    return sorted(set(re.findall(r"\b(sdd_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("sdd_create", "sdd_destroy", "sdd_last_error", "sdd_load_scene", "sdd_build_bvh",
+              "sdd_trace_spectral", "sdd_resolve_image", "sdd_get_stats"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(sdd):
+    out = subprocess.run(["nm", "-D", "--defined-only", sdd.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    for n in _declared():
+        assert n in exported, n
+        assert hasattr(sdd.lib(), n)
+    assert set(sdd.EXPORTS) <= exported
+
+
+def test_last_error_null_context(sdd):
+    assert sdd.lib().sdd_last_error(None) == b"null context"
+
+
+def test_validate_accepts_workloads(sdd):
+    for sc in (sg.tiny_room(), sg.floor_plane(), sg.point_light_plane(), sg.area_light_plane(),
+               sg.furnace_room(), sg.lone_pane()):
+        ok, msg = sdd.validate_scene(sc)
+        assert ok, (sc["name"], msg)
+
+
+def _bad(mut):
+    sc = sg.tiny_room()
+    sc = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    mut(sc)
+    return sc
+
+
+@pytest.mark.parametrize("mut,needle", [
+    (lambda s: s.update(tris=s["tris"][:0], tri_mat=s["tri_mat"][:0]), "no triangles"),
+    (lambda s: s["tris"].__setitem__((3, 1), 10 ** 6), "vertex index"),
+    (lambda s: s["tris"].__setitem__((0, 0), -1), "vertex index"),
+    (lambda s: s["verts"].__setitem__((5, 2), np.nan), "non-finite vertex"),
+    (lambda s: s["tri_mat"].__setitem__(7, 999), "material index"),
+    (lambda s: s["mat_rho"].__setitem__((0, 3), 1.5), "reflectance"),
+    (lambda s: s["mat_n"].__setitem__((6, 0), 0.0), "index n"),
+    (lambda s: s["mat_k"].__setitem__((6, 0), -1e-3), "index k"),
+    (lambda s: s["mat_thick"].__setitem__(6, -0.001), "thickness"),
+    (lambda s: s["mat_le"].__setitem__((6, 0), 1.0), "glass material cannot emit"),
+    (lambda s: s.update(light_mat=0), "emitter"),
+    (lambda s: s.update(light_e2=np.zeros(3, np.float32)), "degenerate"),
+    (lambda s: s["lambda_nm"].__setitem__(2, -5.0), "wavelength"),
+])
+def test_validate_rejects(sdd, mut, needle):
+    ok, msg = sdd.validate_scene(_bad(mut))
+    assert not ok
+    assert needle in msg
+
+
+def test_validate_rejects_too_many_wavelengths(sdd):
+    sc = sg.tiny_room()
+    n = 129
+    lam = np.linspace(380, 780, n).astype(np.float32)
+    M = len(sc["mat_type"])
+    sc.update(lambda_nm=lam, lambda_w=np.ones(n), cmf=np.ones((n, 3)), mat_rho=np.zeros((M, n), np.float32),
+              mat_n=np.ones((M, n), np.float32), mat_k=np.zeros((M, n), np.float32),
+              mat_le=np.zeros((M, n), np.float32))
+    ok, msg = sdd.validate_scene(sc)
+    assert not ok and "n_lambda" in msg
+
+
+def test_tracer_refuses_without_gpu(sdd):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(RuntimeError):
+        sdd.Tracer()

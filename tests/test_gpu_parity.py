@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as ora
+import scenegen as sg
+from parity import HIT_AGREE_MIN, REL_TOL, assert_parity, hit_agreement, rel_err
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def sdd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1912_06474_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def tracer(sdd):
+    return sdd.Tracer()
+
+
+def gpu_render(tracer, scene, W, H, spp, D, grid=(1, 1, 1), camera=None, seed=0, sample_offset=0, render_id=0,
+               leaf_max=4):
+    print(f"[gpu_render] {scene['name']} {W}x{H} spp={spp} D={D} grid={grid}", flush=True)
+    tracer.load_scene(scene)
+    tracer.build_bvh(*grid, leaf_max=leaf_max)
+    cam = camera or scene["camera"]
+    hl = tracer.new_log(W, H, spp, D)
+    sl = tracer.new_log(W, H, spp, D)
+    tracer.trace_spectral(cam, W, H, spp, D, seed=seed, sample_offset=sample_offset, render_id=render_id,
+                          hit_log=hl, shadow_log=sl)
+    s, x = tracer.resolve_image(render_id, W, H)
+    return dict(spectral=s.cpu().numpy(), xyz=x.cpu().numpy(), hit_log=hl.cpu().numpy(),
+                shadow_log=sl.cpu().numpy())
+
+
+def test_device_philox_matches_rocrand_vectors(tracer):
+    rows = [list(map(int, l.split())) for l in open(os.path.join(GOLD, "philox_kat.txt")) if not l.startswith("#")]
+    for v in rows:
+        out = tracer.debug_philox(np.array([v[0:4]], np.uint32), np.array(v[4:6], np.uint32))
+        assert list(out[0]) == v[6:10]
+
+
+def test_device_philox_equals_oracle_on_many_counters(tracer):
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2 ** 32, size=(1 << 16, 4), dtype=np.uint64).astype(np.uint32)
+    key = np.array([7, 3], np.uint32)
+    out = tracer.debug_philox(ctr, key)
+    for i in range(0, len(ctr), 997):
+        assert list(out[i]) == list(ora.philox(ctr[i], key))
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (2, 2, 1), (4, 4, 2), (3, 5, 2)])
+def test_closest_hits_vs_brute_force(tracer, grid):
+    sc = sg.tiny_room()
+    tracer.load_scene(sc)
+    tracer.build_bvh(*grid)
+    rng = np.random.default_rng(2)
+    n = 20000
+    o = rng.uniform([0.05, 0.05, 0.05], [3.95, 2.95, 2.45], size=(n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    t, prim = tracer.debug_trace_rays(o, d)
+    to, po = ora.trace_rays(sc, o.astype(np.float64), d.astype(np.float64), use_bvh=False)
+    agree = float((prim == po).mean())
+    print("closest-hit agreement", grid, agree, flush=True)
+    assert agree >= HIT_AGREE_MIN
+    m = (prim == po) & (po >= 0)
+    assert np.all(np.abs(t[m] - to[m]) <= 1e-5 * np.maximum(1.0, to[m]))
+
+
+def test_ray_plane_analytic_hits_gpu(tracer):
+    sc = sg.floor_plane()
+    tracer.load_scene(sc)
+    tracer.build_bvh(2, 2, 1)
+    rng = np.random.default_rng(11)
+    n = 20000
+    o = np.column_stack([rng.uniform(-1, 5, n), rng.uniform(-1, 4, n), rng.uniform(0.2, 3, n)])
+    tgt = np.column_stack([rng.uniform(0.02, 3.98, n), rng.uniform(0.02, 2.98, n), np.zeros(n)])
+    d = tgt - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    t, prim = tracer.debug_trace_rays(o.astype(np.float32), d.astype(np.float32))
+    of, df = o.astype(np.float32).astype(np.float64), d.astype(np.float32).astype(np.float64)
+    t_plane = -of[:, 2] / df[:, 2]
+    assert np.all(prim >= 0)
+    assert np.allclose(t, t_plane, rtol=2e-6)
+    x = of + t_plane[:, None] * df
+    i, j = np.floor(x[:, 0]).astype(int), np.floor(x[:, 1]).astype(int)
+    fx, fy = x[:, 0] - i, x[:, 1] - j
+    away = (np.abs(fx - fy) > 1e-5) & (fx > 1e-5) & (fx < 1 - 1e-5) & (fy > 1e-5) & (fy < 1 - 1e-5)
+    expect = 2 * (j * 4 + i) + (fy > fx).astype(int)
+    assert np.array_equal(prim[away], expect[away])
+
+
+def test_tiny_room_parity(tracer):
+    sc = sg.tiny_room()
+    g = gpu_render(tracer, sc, 64, 64, 1, 4, grid=(2, 2, 1))
+    o = ora.render(sc, 64, 64, 1, 4, logs=True)
+    assert_parity(g, o, excluded_max=2)
+
+
+def test_tiny_room_parity_more_samples(tracer):
+    sc = sg.tiny_room()
+    g = gpu_render(tracer, sc, 48, 40, 4, 6, grid=(2, 2, 1), seed=5)
+    o = ora.render(sc, 48, 40, 4, 6, logs=True, seed=5)
+    assert_parity(g, o, excluded_max=3)
+
+
+def test_decomposition_invariance(tracer):
+    sc = sg.tiny_room()
+    ref = None
+    for grid in [(1, 1, 1), (2, 2, 1), (4, 4, 2), (5, 3, 3)]:
+        g = gpu_render(tracer, sc, 48, 48, 2, 4, grid=grid)
+        if ref is None:
+            ref = g
+            continue
+        same = hit_agreement(g["hit_log"], ref["hit_log"])
+        print("decomposition", grid, same, flush=True)
+        assert same >= 0.9999
+        if same == 1.0:
+            assert np.array_equal(g["spectral"], ref["spectral"])
+
+
+def test_furnace_gpu_closed_form(tracer):
+    sc = sg.furnace_room()
+    D = 5
+    g = gpu_render(tracer, sc, 32, 32, 2, D, grid=(2, 2, 1))
+    rho = sc["mat_rho"][0].astype(np.float64)
+    le = sc["mat_le"][0].astype(np.float64)
+    expect = le * (1 - rho ** D) / (1 - rho)
+    ok = (g["hit_log"] >= 0).reshape(len(g["hit_log"]), -1).all(1)
+    assert ok.mean() >= 0.999
+    err = rel_err(g["spectral"][ok], np.broadcast_to(expect, g["spectral"][ok].shape))
+    assert err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("which", ["point_light_plane", "area_light_plane", "lone_pane"])
+def test_fixture_parity(tracer, which):
+    sc = getattr(sg, which)()
+    W = H = 32
+    spp, D = 4, 2
+    g = gpu_render(tracer, sc, W, H, spp, D, grid=(2, 2, 1))
+    o = ora.render(sc, W, H, spp, D, logs=True)
+    assert_parity(g, o, excluded_max=1)
+
+
+def test_sample_split_and_batching_are_bitwise_identical(tracer):
+    sc = sg.tiny_room()
+    W = H = 32
+    tracer.load_scene(sc)
+    tracer.build_bvh(2, 2, 1)
+    cam = sc["camera"]
+    # render_id keys Philox, so every variant reuses render 1 after a reset
+    tracer.trace_spectral(cam, W, H, 3, 4, render_id=1)
+    a, _ = tracer.resolve_image(1, W, H)
+    tracer.reset_render(1)
+    tracer.trace_spectral(cam, W, H, 1, 4, render_id=1)
+    tracer.trace_spectral(cam, W, H, 2, 4, render_id=1, sample_offset=1)
+    b, _ = tracer.resolve_image(1, W, H)
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    tracer.reset_render(1)
+    old = os.environ.get("SDD_MEM_BUDGET_GB")
+    os.environ["SDD_MEM_BUDGET_GB"] = "0.0005"
+    try:
+        tracer.reset_stats()
+        tracer.trace_spectral(cam, W, H, 3, 4, render_id=1)
+        c, _ = tracer.resolve_image(1, W, H)
+        assert tracer.stats()["batches"] > 3
+    finally:
+        if old is None:
+            del os.environ["SDD_MEM_BUDGET_GB"]
+        else:
+            os.environ["SDD_MEM_BUDGET_GB"] = old
+    assert np.array_equal(a.cpu().numpy(), c.cpu().numpy())
+
+
+def test_run_to_run_bitwise(tracer):
+    sc = sg.tiny_room()
+    a = gpu_render(tracer, sc, 40, 40, 2, 4, grid=(2, 2, 1))
+    b = gpu_render(tracer, sc, 40, 40, 2, 4, grid=(2, 2, 1))
+    for k in ("spectral", "xyz", "hit_log", "shadow_log"):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_xyz_is_weighted_cmf_sum(tracer):
+    sc = sg.tiny_room()
+    g = gpu_render(tracer, sc, 16, 16, 1, 3, grid=(2, 2, 1))
+    w = sc["lambda_w"][:, None] * sc["cmf"]
+    assert np.allclose(g["xyz"], g["spectral"] @ w, rtol=1e-12, atol=1e-15)
+
+
+def test_edge_shapes(tracer):
+    sc = sg.tiny_room()
+    for (W, H, spp, D) in [(1, 1, 1, 1), (3, 1, 2, 1), (1, 7, 1, 3), (65, 33, 1, 2)]:
+        g = gpu_render(tracer, sc, W, H, spp, D, grid=(2, 2, 1))
+        o = ora.render(sc, W, H, spp, D, logs=True)
+        assert_parity(g, o, excluded_max=1)
+
+
+def test_error_paths(sdd):
+    t = sdd.Tracer()
+    cam = dict(eye=(2, 0.5, 1.2), target=(2, 3, 1.2), fov_deg=70.0)
+    with pytest.raises(sdd.SddError) as e:
+        t.trace_spectral(cam, 8, 8, 1, 2)
+    assert e.value.status == -2
+    with pytest.raises(sdd.SddError) as e:
+        t.build_bvh(2, 2, 1)
+    assert e.value.status == -2
+    t.load_scene(sg.tiny_room())
+    with pytest.raises(sdd.SddError) as e:
+        t.build_bvh(0, 1, 1)
+    assert e.value.status == -1
+    t.build_bvh(2, 2, 1)
+    with pytest.raises(sdd.SddError) as e:
+        t.trace_spectral(cam, 0, 8, 1, 2)
+    assert e.value.status == -1
+    with pytest.raises(sdd.SddError) as e:
+        t.trace_spectral(dict(eye=(2, 0.5, 1.2), target=(2, 0.5, 3.0), fov_deg=70.0), 8, 8, 1, 2)
+    assert e.value.status == -1
+    with pytest.raises(sdd.SddError) as e:
+        t.resolve_image(42, 8, 8)
+    assert e.value.status == -2
+    t.close()
