@@ -155,6 +155,7 @@ def main():
     kern_ms = {"trace_ext": se["ms_trace_ext"], "trace_shadow": se["ms_trace_shadow"], "shade": se["ms_shade"],
                "other": se["ms_other"]}
     log(f"[bench] timed {dt:.3f} s; event pass {dt_ev:.3f} s; kernel ms {kern_ms}")
+    log(f"[bench] stats {json.dumps(se)}")
 
     res = {
         "metric": "spectral path samples/s (rays x lambda/s), plain tracer, one MI355X",
