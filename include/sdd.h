@@ -54,7 +54,7 @@ enum { SDD_LIGHT_NONE = 0, SDD_LIGHT_PARALLELOGRAM = 1, SDD_LIGHT_POINT = 2 };
 
 /* Limits (checked; exceeding one returns SDD_ERR_INVALID_ARG). */
 #define SDD_MAX_LAMBDA 128
-#define SDD_MAX_CELLS 1024
+#define SDD_MAX_CELLS 512
 #define SDD_MAX_DEPTH 64
 
 typedef struct sdd_ctx sdd_ctx;

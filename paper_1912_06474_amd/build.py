@@ -14,6 +14,7 @@ SOURCES = ["api.cpp", "bvh_build.cpp", "kernels.hip"]
 # gfx950 only; packed FP32 instructions disabled for all device code
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-fno-hip-fp32-correctly-rounded-divide-sqrt",
             "-Wall", "-Wno-unused-result"]
 
 

@@ -96,13 +96,14 @@ struct sdd_ctx {
     int* sh_state = nullptr;
     int* sh_cnt = nullptr;
     float2* sh_glass = nullptr;
-    float4* qa[3] = {nullptr, nullptr, nullptr};
-    float4* qb[3] = {nullptr, nullptr, nullptr};
-    int2* qc[3] = {nullptr, nullptr, nullptr};
+    // queue buffers: 0/1 closest-hit ping-pong, 2/3 shadow ping-pong
+    float4* qa[4] = {nullptr, nullptr, nullptr, nullptr};
+    float4* qb[4] = {nullptr, nullptr, nullptr, nullptr};
+    int2* qc[4] = {nullptr, nullptr, nullptr, nullptr};
     int* d_counts = nullptr;
-    int* d_sched = nullptr;
-    long long counts_len = 0, sched_len = 0;
+    long long counts_len = 0;
     int* d_overflow = nullptr;
+    int* d_gstack = nullptr;  // traversal stack spill: (kStack - kLdsStack) ints per trace thread
     unsigned long long* d_stats = nullptr;
 
     std::map<int, Render> renders;
@@ -217,13 +218,12 @@ void free_batch(sdd_ctx* c) {
     dfree(c, c->sh_state);
     dfree(c, c->sh_cnt);
     dfree(c, c->sh_glass);
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < 4; ++i) {
         dfree(c, c->qa[i]);
         dfree(c, c->qb[i]);
         dfree(c, c->qc[i]);
     }
     dfree(c, c->d_counts);
-    dfree(c, c->d_sched);
     c->ncap = 0;
     c->dcap = 0;
 }
@@ -335,12 +335,11 @@ long long mem_budget_bytes() {
 }
 
 long long bytes_per_path(const sdd_ctx* c) {
-    return 3LL * c->G * (16 + 16 + 8) + 8LL * c->nlp + 16 + 16 + 8 + 4 + 4 + 4 + 4 + 8 * kMaxGlass;
+    return 4LL * c->G * (16 + 16 + 8) + 8LL * c->nlp + 16 + 16 + 8 + 4 + 4 + 4 + 4 + 8 * kMaxGlass;
 }
 
 sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
     const long long cnt_len = (long long)(2 * max_depth + 1) * (c->S + 1) * c->G;
-    const long long sch_len = (long long)(2 * max_depth + 1) * (c->S + 1) * kXcd;
     if (n <= c->ncap && max_depth <= c->dcap) return SDD_OK;
     free_batch(c);
     sdd_status st;
@@ -360,59 +359,65 @@ sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
     ALLOC(c->sh_state, n);
     ALLOC(c->sh_cnt, n);
     ALLOC(c->sh_glass, n * kMaxGlass);
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < 4; ++i) {
         ALLOC(c->qa[i], qn);
         ALLOC(c->qb[i], qn);
         ALLOC(c->qc[i], qn);
     }
     ALLOC(c->d_counts, cnt_len);
-    ALLOC(c->d_sched, sch_len);
 #undef ALLOC
     c->counts_len = cnt_len;
-    c->sched_len = sch_len;
     c->ncap = n;
     c->dcap = max_depth;
     return SDD_OK;
 }
 
-// counters / scheduler slots of (phase, sweep)
+// counters of (phase, sweep); phase 2(d-1) holds the closest-hit rays of
+// depth d, phase 2(d-1)+1 the shadow rays of depth d
 inline int* counts_at(sdd_ctx* c, int phase, int k) { return c->d_counts + ((long long)phase * (c->S + 1) + k) * c->G; }
-inline int* sched_at(sdd_ctx* c, int phase, int k) { return c->d_sched + ((long long)phase * (c->S + 1) + k) * kXcd; }
+inline int ph_ext(int d) { return 2 * (d - 1); }
+inline int ph_sh(int d) { return 2 * (d - 1) + 1; }
 
-TraceParams trace_params(sdd_ctx* c, int in_buf, int out_buf, int phase, int k, long long cap) {
-    TraceParams p{};
-    p.qa_in = c->qa[in_buf];
-    p.qb_in = c->qb[in_buf];
-    p.qc_in = c->qc[in_buf];
-    p.cnt_in = counts_at(c, phase, k);
-    p.qa_out = c->qa[out_buf];
-    p.qb_out = c->qb[out_buf];
-    p.qc_out = c->qc[out_buf];
-    p.cnt_out = counts_at(c, phase, k + 1);
-    p.sched = sched_at(c, phase, k);
-    p.cap = cap;
-    p.n_cells = c->G;
-    p.grid = c->grid;
-    p.nodes = c->d_nodes;
-    p.tris = c->d_tris;
-    p.cell_root = c->d_cell_root;
-    p.prim_info = c->d_prim_info;
-    p.hit = c->hit;
-    p.sh_state = c->sh_state;
-    p.sh_cnt = c->sh_cnt;
-    p.sh_glass = c->sh_glass;
-    p.overflow = c->d_overflow;
-    p.stats = c->d_stats;
-    return p;
+QueueSet queue_set(sdd_ctx* c, int in_buf, int out_buf, int phase, int k) {
+    QueueSet q{};
+    q.qa_in = c->qa[in_buf];
+    q.qb_in = c->qb[in_buf];
+    q.qc_in = c->qc[in_buf];
+    q.cnt_in = counts_at(c, phase, k);
+    q.qa_out = c->qa[out_buf];
+    q.qb_out = c->qb[out_buf];
+    q.qc_out = c->qc[out_buf];
+    q.cnt_out = counts_at(c, phase, k + 1);
+    return q;
 }
 
-// S sweeps of one phase; the phase's initial queue is buffer a, its partner b
-sdd_status run_sweeps(sdd_ctx* c, bool shadow, int phase, int a, int b, long long cap, bool count, bool timing) {
+// S sweeps over the subdomain queues.  ext_phase / sh_phase < 0: that kind is
+// idle.  Closest-hit rays start in buffer 0 (partner 1), shadow rays in
+// buffer 2 (partner 3).
+sdd_status run_sweeps(sdd_ctx* c, int ext_phase, int sh_phase, long long cap, bool count, bool timing) {
     for (int k = 0; k < c->S; ++k) {
-        const int in = (k % 2 == 0) ? a : b, out = (k % 2 == 0) ? b : a;
-        TraceParams p = trace_params(c, in, out, phase, k, cap);
-        Timer tm(c, timing, shadow ? 1 : 0);
-        HIP_TRY(c, launch_trace(p, shadow, count, c->trace_grid, c->stream));
+        TraceParams p{};
+        const bool even = k % 2 == 0;
+        if (ext_phase >= 0) p.q[0] = queue_set(c, even ? 0 : 1, even ? 1 : 0, ext_phase, k);
+        if (sh_phase >= 0) p.q[1] = queue_set(c, even ? 2 : 3, even ? 3 : 2, sh_phase, k);
+        p.active[0] = ext_phase >= 0;
+        p.active[1] = sh_phase >= 0;
+        p.cap = cap;
+        p.n_cells = c->G;
+        p.grid = c->grid;
+        p.nodes = c->d_nodes;
+        p.tris = c->d_tris;
+        p.cell_root = c->d_cell_root;
+        p.prim_info = c->d_prim_info;
+        p.hit = c->hit;
+        p.sh_state = c->sh_state;
+        p.sh_cnt = c->sh_cnt;
+        p.sh_glass = c->sh_glass;
+        p.overflow = c->d_overflow;
+        p.gstack = c->d_gstack;
+        p.stats = c->d_stats;
+        Timer tm(c, timing, sh_phase >= 0 && ext_phase < 0 ? 1 : 0);
+        HIP_TRY(c, launch_trace(p, count, c->trace_grid, c->stream));
         ++c->launches_trace;
     }
     return SDD_OK;
@@ -440,7 +445,8 @@ sdd_status sdd_create(int hip_device, void* hip_stream, sdd_ctx** out) {
     c->stream = (hipStream_t)hip_stream;  // NULL: the null stream, ordered with other default-stream work
     const int per_cu = trace_blocks_per_cu();
     c->trace_grid = std::max(kXcd, (c->n_cu * per_cu / kXcd) * kXcd);
-    if (dalloc(c, &c->d_overflow, 1) != SDD_OK || dalloc(c, &c->d_stats, kStatCount) != SDD_OK) {
+    if (dalloc(c, &c->d_overflow, 1) != SDD_OK || dalloc(c, &c->d_stats, kStatCount) != SDD_OK ||
+        dalloc(c, &c->d_gstack, (size_t)c->trace_grid * kTraceBlock * (kStack - kLdsStack)) != SDD_OK) {
         sdd_destroy(c);
         return SDD_ERR_OOM;
     }
@@ -466,6 +472,7 @@ void sdd_destroy(sdd_ctx* c) {
     free_accel(c);
     free_scene(c);
     dfree(c, c->d_overflow);
+    dfree(c, c->d_gstack);
     dfree(c, c->d_stats);
     for (auto& kv : c->allocs) (void)hipFree(kv.first);
     c->allocs.clear();
@@ -685,7 +692,6 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         {
             Timer tm(c, timing, 3);
             HIP_TRY(c, launch_fill_i32(c->d_counts, c->counts_len, 0, c->stream));
-            HIP_TRY(c, launch_fill_i32(c->d_sched, c->sched_len, 0, c->stream));
         }
         CamParams cp{};
         cp.N = N;
@@ -714,6 +720,7 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         cp.Lp = c->Lp;
         cp.sh_state = c->sh_state;
         cp.grid = c->grid;
+        cp.n_cells = c->G;
         cp.eqa = c->qa[0];
         cp.eqb = c->qb[0];
         cp.eqc = c->qc[0];
@@ -764,35 +771,36 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         sp.light_area = c->light_area;
         sp.light_mat = c->light_mat < 0 ? 0 : c->light_mat;
         sp.grid = c->grid;
+        sp.n_cells = c->G;
         sp.eqa = c->qa[0];
         sp.eqb = c->qb[0];
         sp.eqc = c->qc[0];
-        sp.sqa = c->qa[1];
-        sp.sqb = c->qb[1];
-        sp.sqc = c->qc[1];
+        sp.sqa = c->qa[2];
+        sp.sqb = c->qb[2];
+        sp.sqc = c->qc[2];
         sp.cap = cap;
         sp.hit_log = t->hit_log;
         sp.shadow_log = t->shadow_log;
         sp.stats = c->d_stats;
         for (int d = 1; d <= D; ++d) {
-            const int ph_e = 2 * (d - 1), ph_s = 2 * (d - 1) + 1;
-            st = run_sweeps(c, false, ph_e, 0, 1, cap, count, timing);
+            // closest-hit rays of depth d share the sweeps with the shadow rays of depth d - 1
+            st = run_sweeps(c, ph_ext(d), d >= 2 ? ph_sh(d - 1) : -1, cap, count, timing);
             if (st != SDD_OK) return st;
             sp.depth = d;
             sp.final_pass = 0;
-            sp.ecnt = counts_at(c, 2 * d, 0);
-            sp.scnt = counts_at(c, ph_s, 0);
+            sp.ecnt = counts_at(c, ph_ext(d + 1), 0);
+            sp.scnt = counts_at(c, ph_sh(d), 0);
             {
                 Timer tm(c, timing, 2);
                 HIP_TRY(c, launch_shade(sp, c->stream));
             }
-            st = run_sweeps(c, true, ph_s, 1, 2, cap, count, timing);
-            if (st != SDD_OK) return st;
         }
+        st = run_sweeps(c, -1, ph_sh(D), cap, count, timing);
+        if (st != SDD_OK) return st;
         sp.depth = D + 1;
         sp.final_pass = 1;
-        sp.ecnt = counts_at(c, 2 * D, 0);
-        sp.scnt = counts_at(c, 2 * D, 1);
+        sp.ecnt = counts_at(c, ph_ext(D + 1), 0);
+        sp.scnt = counts_at(c, ph_ext(D + 1), 1);
         {
             Timer tm(c, timing, 2);
             HIP_TRY(c, launch_shade(sp, c->stream));
@@ -947,7 +955,6 @@ sdd_status sdd_debug_trace_rays(sdd_ctx* c, int32_t n, const float* o, const flo
     hipError_t e = hipMemcpyAsync(dor, o, sizeof(float) * 3 * (size_t)n, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(ddr, d, sizeof(float) * 3 * (size_t)n, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_fill_i32(c->d_counts, c->counts_len, 0, c->stream);
-    if (e == hipSuccess) e = launch_fill_i32(c->d_sched, c->sched_len, 0, c->stream);
     if (e == hipSuccess)
         e = launch_debug_rays(n, dor, ddr, c->grid, c->hit, c->qa[0], c->qb[0], c->qc[0], counts_at(c, 0, 0), n,
                               c->stream);
@@ -956,7 +963,7 @@ sdd_status sdd_debug_trace_rays(sdd_ctx* c, int32_t n, const float* o, const flo
         dfree(c, ddr);
         return hip_fail(c, e, "debug rays");
     }
-    st = run_sweeps(c, false, 0, 0, 1, n, false, false);
+    st = run_sweeps(c, ph_ext(1), -1, n, false, false);
     std::vector<float2> h((size_t)n);
     if (st == SDD_OK) {
         e = hipMemcpyAsync(h.data(), c->hit, sizeof(float2) * (size_t)n, hipMemcpyDeviceToHost, c->stream);

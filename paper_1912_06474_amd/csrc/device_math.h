@@ -167,6 +167,23 @@ __device__ __forceinline__ int wave_append(bool active, int key, int* counts) {
     return slot;
 }
 
+// Workgroup multi-split append: per-segment histogram in LDS (s_cnt, s_base:
+// n_seg ints each), then one global atomic per non-empty segment of the
+// workgroup, issued by different threads in parallel.  Every thread of the
+// block must call it (it synchronises the block).
+__device__ __forceinline__ int block_append(bool active, int key, int* counts, int n_seg, int* s_cnt, int* s_base) {
+    for (int i = threadIdx.x; i < n_seg; i += blockDim.x) s_cnt[i] = 0;
+    __syncthreads();
+    const int local = active ? atomicAdd(&s_cnt[key], 1) : 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_seg; i += blockDim.x) {
+        const int c = s_cnt[i];
+        if (c) s_base[i] = atomicAdd(&counts[i], c);
+    }
+    __syncthreads();
+    return active ? s_base[key] + local : -1;
+}
+
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);

@@ -8,7 +8,7 @@
 namespace sdd {
 
 hipError_t launch_camgen(const CamParams& p, hipStream_t st);
-hipError_t launch_trace(const TraceParams& p, bool shadow, bool count, int grid_blocks, hipStream_t st);
+hipError_t launch_trace(const TraceParams& p, bool count, int grid_blocks, hipStream_t st);
 int trace_blocks_per_cu();
 hipError_t launch_shade(const ShadeParams& p, hipStream_t st);
 hipError_t launch_flush(int N, long long g0, int WH, int nl, const float* Lp, float* acc, hipStream_t st);

@@ -73,6 +73,7 @@ __device__ __forceinline__ int locate_ray(const GridParams& g, f3 o, f3 d, float
 // camera rays
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_camgen(CamParams P) {
+    __shared__ int s_cnt[kMaxCells], s_base[kMaxCells];
     const int pid = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = pid < P.N;
     bool enq = false;
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(256) void k_camgen(CamParams P) {
         cell = locate_ray(P.grid, o, d, t_enter);
         enq = cell >= 0;
     }
-    const int slot = wave_append(enq, cell, P.ecnt);
+    const int slot = block_append(enq, cell, P.ecnt, P.n_cells, s_cnt, s_base);
     if (enq && slot < P.cap) {
         const long long q = (long long)cell * P.cap + slot;
         P.eqa[q] = make_float4(o.x, o.y, o.z, t_enter);
@@ -172,8 +173,8 @@ __device__ __forceinline__ void traverse(const float4* __restrict__ nodes, const
                                          const float4* __restrict__ prim_info, int root, const RayTrav& r,
                                          float tlo, float t_exit, float t_max, int exclude, float& thi, int& best,
                                          bool& blocked, int& n_glass, int pid, int* __restrict__ sh_cnt,
-                                         float2* __restrict__ sh_glass, int* overflow, int* stk, int& n_nodes,
-                                         int& n_tris) {
+                                         float2* __restrict__ sh_glass, int* overflow, int* stk, int* gstk,
+                                         int gstride, int& n_nodes, int& n_tris) {
     int sp = 0;
     int link = root;
     // closest hit: thi = t_exit, best = -1 on entry; shadow: thi = min(t_exit, t_max)
@@ -188,8 +189,11 @@ __device__ __forceinline__ void traverse(const float4* __restrict__ nodes, const
             const bool h0 = t0 != INFINITY, h1 = t1 != INFINITY;
             if (h0 && h1) {
                 const bool first0 = t0 <= t1;
-                // the builder caps BVH depth below kStack, so this never drops an entry
-                if (sp < kStack) stk[sp * kTraceBlock] = first0 ? n3.y : n3.x;
+                // short stack in LDS, deeper entries in HBM; the builder caps the
+                // BVH depth below kStack, so no entry is ever dropped
+                const int far = first0 ? n3.y : n3.x;
+                if (sp < kLdsStack) stk[sp * kTraceBlock] = far;
+                else if (sp < kStack) gstk[(sp - kLdsStack) * gstride] = far;
                 ++sp;
                 link = first0 ? n3.x : n3.y;
                 continue;
@@ -240,27 +244,111 @@ __device__ __forceinline__ void traverse(const float4* __restrict__ nodes, const
         if (sp == 0) break;
         --sp;
         if (sp >= kStack) break;
-        link = stk[sp * kTraceBlock];
+        link = sp < kLdsStack ? stk[sp * kTraceBlock] : gstk[(sp - kLdsStack) * gstride];
     }
 }
 
-// One sweep over all subdomain queues.  Work is split into 64-ray chunks
-// ordered by cell; the chunk range is cut into kXcd contiguous parts, part x
-// served first by the workgroups of XCD x (consecutive cells share an L2),
-// then stolen by the others.
+// One chunk (up to 64 rays of one cell's queue, one wave): traverse the
+// cell's BVH over (t_enter, t_exit] and hand the rays that go on to the
+// neighbouring cell's queue.  Reached by all lanes of the wave together.
 template <bool SHADOW, bool COUNT>
+__device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueSet& Q, int cell, int idx, bool active,
+                                              int* stk, int* gstk, int gstride, int& n_visits, int& n_nodes,
+                                              int& n_tris) {
+    const GridParams& g = P.grid;
+    const int ix = cell % g.nx, iy = (cell / g.nx) % g.ny, iz = cell / (g.nx * g.ny);
+    const float px0 = g.planes[ix], px1 = g.planes[ix + 1];
+    const float py0 = g.planes[g.off_y + iy], py1 = g.planes[g.off_y + iy + 1];
+    const float pz0 = g.planes[g.off_z + iz], pz1 = g.planes[g.off_z + iz + 1];
+    const int root = P.cell_root[cell];
+
+    bool cont = false;
+    int next = 0;
+    float4 qa = make_float4(0, 0, 0, 0), qb = make_float4(0, 0, 0, 0);
+    int2 qc = make_int2(0, 0);
+    if (active) {
+        ++n_visits;
+        const long long q = (long long)cell * P.cap + idx;
+        qa = Q.qa_in[q];
+        qb = Q.qb_in[q];
+        qc = Q.qc_in[q];
+        const f3 o = xyz(qa), d = xyz(qb);
+        const int pid = __float_as_int(qb.w);
+        const float t_enter = qa.w;
+        const float t_max = __int_as_float(qc.y);
+        // exit of this cell: nearest far plane, ties x < y < z
+        const float tx = d.x > 0.0f ? (px1 - o.x) / d.x : (d.x < 0.0f ? (px0 - o.x) / d.x : INFINITY);
+        const float ty = d.y > 0.0f ? (py1 - o.y) / d.y : (d.y < 0.0f ? (py0 - o.y) / d.y : INFINITY);
+        const float tz = d.z > 0.0f ? (pz1 - o.z) / d.z : (d.z < 0.0f ? (pz0 - o.z) / d.z : INFINITY);
+        int axis = 0;
+        float t_exit = tx;
+        if (ty < t_exit) {
+            t_exit = ty;
+            axis = 1;
+        }
+        if (tz < t_exit) {
+            t_exit = tz;
+            axis = 2;
+        }
+        const RayTrav r = make_trav(o, d);
+        float thi = SHADOW ? fminf(t_exit, t_max) : t_exit;
+        int best = -1;
+        bool blocked = false;
+        int n_glass = -1;  // pane crossings so far (-1: not loaded yet)
+        if (!SHADOW || thi > t_enter)
+            traverse<SHADOW, COUNT>(P.nodes, P.tris, P.prim_info, root, r, t_enter, t_exit, t_max, qc.x, thi, best,
+                                    blocked, n_glass, pid, P.sh_cnt, P.sh_glass, P.overflow, stk, gstk, gstride,
+                                    n_nodes, n_tris);
+        bool leave;
+        if (!SHADOW) {
+            if (best >= 0) P.hit[pid] = make_float2(thi, __int_as_float(best));
+            leave = best < 0;
+        } else {
+            if (blocked) P.sh_state[pid] = kShBlocked;
+            else if (n_glass >= 0) P.sh_cnt[pid] = n_glass;
+            leave = !blocked && t_exit < t_max;
+        }
+        if (leave) {
+            int nx = ix, ny = iy, nz = iz;
+            if (axis == 0) nx += d.x > 0.0f ? 1 : -1;
+            else if (axis == 1) ny += d.y > 0.0f ? 1 : -1;
+            else nz += d.z > 0.0f ? 1 : -1;
+            if (nx >= 0 && nx < g.nx && ny >= 0 && ny < g.ny && nz >= 0 && nz < g.nz) {
+                cont = true;
+                next = nx + g.nx * (ny + g.ny * nz);
+                qa.w = t_exit;  // carried bit-exactly into the neighbour
+            }
+        }
+    }
+    const int slot = wave_append(cont, next, Q.cnt_out);
+    if (cont && slot < P.cap) {
+        const long long q = (long long)next * P.cap + slot;
+        Q.qa_out[q] = qa;
+        Q.qb_out[q] = qb;
+        Q.qc_out[q] = qc;
+    }
+}
+
+// One sweep over all subdomain queues of both ray kinds (closest-hit rays of
+// one depth and shadow rays of the previous one are independent, so they
+// share the sweep).  Work is split into 64-ray chunks ordered by (cell, kind);
+// the chunk range is cut into kXcd contiguous parts, part x served by the
+// workgroups of XCD x (consecutive cells share that XCD's L2).
+template <bool COUNT>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
-    __shared__ int s_pref[kMaxCells + 1];
-    __shared__ int s_stack[kStack * kTraceBlock];
+    __shared__ int s_pref[2 * kMaxCells + 1];
+    __shared__ int s_stack[kLdsStack * kTraceBlock];
     const int G = P.n_cells;
+    const int E = 2 * G;  // entry e = 2 * cell + kind
     if (threadIdx.x < 64) {
-        // exclusive prefix of the per-cell chunk counts (wave 0, lane-blocked scan)
+        // exclusive prefix of the per-entry chunk counts (wave 0, lane-blocked scan)
         const int ln = threadIdx.x;
-        const int per = (G + 63) / 64;
-        const int c0 = ln * per, c1 = min(c0 + per, G);
+        const int per = (E + 63) / 64;
+        const int c0 = ln * per, c1 = min(c0 + per, E);
         int local = 0;
-        for (int c = c0; c < c1; ++c) {
-            const int n = P.cnt_in[c];
+        for (int e = c0; e < c1; ++e) {
+            const int kind = e & 1;
+            const int n = P.active[kind] ? P.q[kind].cnt_in[e >> 1] : 0;
             if (n > P.cap) atomicExch(P.overflow, 2);  // never expected: counters are bounded by cap
             local += (n + kChunk - 1) / kChunk;
         }
@@ -271,115 +359,55 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
             if (ln >= o) incl += v;
         }
         int run = incl - local;
-        for (int c = c0; c < c1; ++c) {
-            s_pref[c] = run;
-            run += (P.cnt_in[c] + kChunk - 1) / kChunk;
+        for (int e = c0; e < c1; ++e) {
+            s_pref[e] = run;
+            const int kind = e & 1;
+            const int n = P.active[kind] ? P.q[kind].cnt_in[e >> 1] : 0;
+            run += (n + kChunk - 1) / kChunk;
         }
-        if (ln == 63) s_pref[G] = incl;
+        if (ln == 63) s_pref[E] = incl;
     }
     __syncthreads();
-    const int total = s_pref[G];
+    const int total = s_pref[E];
     if (total == 0) return;
     const int lane = lane_id();
     int* stk = s_stack + threadIdx.x;
+    const int gstride = gridDim.x * kTraceBlock;  // entries of one level are contiguous over the grid
+    int* gstk = P.gstack + blockIdx.x * kTraceBlock + threadIdx.x;
     const int xcd = blockIdx.x % kXcd;
-    int n_nodes = 0, n_tris = 0, n_visits = 0;
-    const GridParams& g = P.grid;
+    int n_nodes = 0, n_tris = 0, n_vis[2] = {0, 0};
 
-    for (int k = 0; k < kXcd; ++k) {
-        const int part = (xcd + k) % kXcd;
-        const int lo = (int)((long long)total * part / kXcd);
-        const int hi = (int)((long long)total * (part + 1) / kXcd);
-        for (;;) {
-            int c = 0;
-            if (lane == 0) c = atomicAdd(&P.sched[part], 1);
-            c = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_readlane(c, 0));
-            if (lo + c >= hi) break;
-            const int chunk = lo + c;
-            int a = 0, b = G;
-            while (b - a > 1) {
-                const int m = (a + b) >> 1;
-                if (s_pref[m] <= chunk) a = m;
-                else b = m;
-            }
-            const int cell = __builtin_amdgcn_readfirstlane(a);
-            const int idx = (chunk - s_pref[cell]) * kChunk + lane;
-            const bool active = idx < min((long long)P.cnt_in[cell], P.cap);
-            const int ix = cell % g.nx, iy = (cell / g.nx) % g.ny, iz = cell / (g.nx * g.ny);
-            const float px0 = g.planes[ix], px1 = g.planes[ix + 1];
-            const float py0 = g.planes[g.off_y + iy], py1 = g.planes[g.off_y + iy + 1];
-            const float pz0 = g.planes[g.off_z + iz], pz1 = g.planes[g.off_z + iz + 1];
-            const int root = P.cell_root[cell];
-
-            bool cont = false;
-            int next = 0;
-            float4 qa = make_float4(0, 0, 0, 0), qb = make_float4(0, 0, 0, 0);
-            int2 qc = make_int2(0, 0);
-            if (active) {
-                ++n_visits;
-                const long long q = (long long)cell * P.cap + idx;
-                qa = P.qa_in[q];
-                qb = P.qb_in[q];
-                qc = P.qc_in[q];
-                const f3 o = xyz(qa), d = xyz(qb);
-                const int pid = __float_as_int(qb.w);
-                const float t_enter = qa.w;
-                const float t_max = __int_as_float(qc.y);
-                // exit of this cell: nearest far plane, ties x < y < z
-                const float tx = d.x > 0.0f ? (px1 - o.x) / d.x : (d.x < 0.0f ? (px0 - o.x) / d.x : INFINITY);
-                const float ty = d.y > 0.0f ? (py1 - o.y) / d.y : (d.y < 0.0f ? (py0 - o.y) / d.y : INFINITY);
-                const float tz = d.z > 0.0f ? (pz1 - o.z) / d.z : (d.z < 0.0f ? (pz0 - o.z) / d.z : INFINITY);
-                int axis = 0;
-                float t_exit = tx;
-                if (ty < t_exit) {
-                    t_exit = ty;
-                    axis = 1;
-                }
-                if (tz < t_exit) {
-                    t_exit = tz;
-                    axis = 2;
-                }
-                const RayTrav r = make_trav(o, d);
-                float thi = SHADOW ? fminf(t_exit, t_max) : t_exit;
-                int best = -1;
-                bool blocked = false;
-                int n_glass = -1;  // pane crossings so far (-1: not loaded yet)
-                if (!SHADOW || thi > t_enter)
-                    traverse<SHADOW, COUNT>(P.nodes, P.tris, P.prim_info, root, r, t_enter, t_exit, t_max, qc.x,
-                                            thi, best, blocked, n_glass, pid, P.sh_cnt, P.sh_glass, P.overflow, stk,
-                                            n_nodes, n_tris);
-                bool leave;
-                if (!SHADOW) {
-                    if (best >= 0) P.hit[pid] = make_float2(thi, __int_as_float(best));
-                    leave = best < 0;
-                } else {
-                    if (blocked) P.sh_state[pid] = kShBlocked;
-                    else if (n_glass >= 0) P.sh_cnt[pid] = n_glass;
-                    leave = !blocked && t_exit < t_max;
-                }
-                if (leave) {
-                    int nx = ix, ny = iy, nz = iz;
-                    if (axis == 0) nx += d.x > 0.0f ? 1 : -1;
-                    else if (axis == 1) ny += d.y > 0.0f ? 1 : -1;
-                    else nz += d.z > 0.0f ? 1 : -1;
-                    if (nx >= 0 && nx < g.nx && ny >= 0 && ny < g.ny && nz >= 0 && nz < g.nz) {
-                        cont = true;
-                        next = nx + g.nx * (ny + g.ny * nz);
-                        qa.w = t_exit;  // carried bit-exactly into the neighbour
-                    }
-                }
-            }
-            const int slot = wave_append(cont, next, P.cnt_out);
-            if (cont && slot < P.cap) {
-                const long long q = (long long)next * P.cap + slot;
-                P.qa_out[q] = qa;
-                P.qb_out[q] = qb;
-                P.qc_out[q] = qc;
-            }
+    // static XCD-aware striding: the waves of XCD x walk part x of the chunk
+    // list round-robin (no atomics, so empty and near-empty sweeps cost only
+    // the prologue)
+    constexpr int kWavesPerBlock = kTraceBlock / 64;
+    const int lw = (blockIdx.x / kXcd) * kWavesPerBlock + (int)(threadIdx.x / 64);
+    const int nwx = (gridDim.x / kXcd) * kWavesPerBlock;
+    const int lo = (int)((long long)total * xcd / kXcd);
+    const int hi = (int)((long long)total * (xcd + 1) / kXcd);
+    for (int chunk = lo + lw; chunk < hi; chunk += nwx) {
+        int a = 0, b = E;
+        while (b - a > 1) {
+            const int m = (a + b) >> 1;
+            if (s_pref[m] <= chunk) a = m;
+            else b = m;
         }
+        const int e = __builtin_amdgcn_readfirstlane(a);
+        const int cell = e >> 1, kind = e & 1;
+        const int idx = (chunk - s_pref[e]) * kChunk + lane;
+        const bool active = idx < min((long long)P.q[kind].cnt_in[cell], P.cap);
+        if (kind == 0)
+            process_chunk<false, COUNT>(P, P.q[0], cell, idx, active, stk, gstk, gstride, n_vis[0], n_nodes,
+                                        n_tris);
+        else
+            process_chunk<true, COUNT>(P, P.q[1], cell, idx, active, stk, gstk, gstride, n_vis[1], n_nodes,
+                                       n_tris);
     }
-    const int v = wave_sum(n_visits);
-    if (lane == 0 && v) atomicAdd(&P.stats[SHADOW ? kStatShadowVisits : kStatExtVisits], (unsigned long long)v);
+    const int v0 = wave_sum(n_vis[0]), v1 = wave_sum(n_vis[1]);
+    if (lane == 0) {
+        if (v0) atomicAdd(&P.stats[kStatExtVisits], (unsigned long long)v0);
+        if (v1) atomicAdd(&P.stats[kStatShadowVisits], (unsigned long long)v1);
+    }
     if (COUNT) {
         const int nn = wave_sum(n_nodes), nt = wave_sum(n_tris);
         if (lane == 0) {
@@ -393,6 +421,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
 // shading: per-wavelength interaction, shadow ray, next ray
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
+    __shared__ int s_cnt[kMaxCells], s_base[kMaxCells];
     const int pid = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = pid < P.N;
     const int N = P.N;
@@ -545,14 +574,14 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
             P.flags[pid] = fl;
         }
     }
-    const int slot_e = wave_append(enq_e, cell_e, P.ecnt);
+    const int slot_e = block_append(enq_e, cell_e, P.ecnt, P.n_cells, s_cnt, s_base);
     if (enq_e && slot_e < P.cap) {
         const long long q = (long long)cell_e * P.cap + slot_e;
         P.eqa[q] = make_float4(xo.x, xo.y, xo.z, te);
         P.eqb[q] = make_float4(dn.x, dn.y, dn.z, __int_as_float(pid));
         P.eqc[q] = make_int2(prim, __float_as_int(INFINITY));
     }
-    const int slot_s = wave_append(enq_s, cell_s, P.scnt);
+    const int slot_s = block_append(enq_s, cell_s, P.scnt, P.n_cells, s_cnt, s_base);
     if (enq_s && slot_s < P.cap) {
         const long long q = (long long)cell_s * P.cap + slot_s;
         P.sqa[q] = make_float4(xo.x, xo.y, xo.z, ts);
@@ -649,20 +678,15 @@ hipError_t launch_camgen(const CamParams& p, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_trace(const TraceParams& p, bool shadow, bool count, int grid_blocks, hipStream_t st) {
-    if (shadow) {
-        if (count) hipLaunchKernelGGL((k_trace<true, true>), dim3(grid_blocks), dim3(kTraceBlock), 0, st, p);
-        else hipLaunchKernelGGL((k_trace<true, false>), dim3(grid_blocks), dim3(kTraceBlock), 0, st, p);
-    } else {
-        if (count) hipLaunchKernelGGL((k_trace<false, true>), dim3(grid_blocks), dim3(kTraceBlock), 0, st, p);
-        else hipLaunchKernelGGL((k_trace<false, false>), dim3(grid_blocks), dim3(kTraceBlock), 0, st, p);
-    }
+hipError_t launch_trace(const TraceParams& p, bool count, int grid_blocks, hipStream_t st) {
+    if (count) hipLaunchKernelGGL((k_trace<true>), dim3(grid_blocks), dim3(kTraceBlock), 0, st, p);
+    else hipLaunchKernelGGL((k_trace<false>), dim3(grid_blocks), dim3(kTraceBlock), 0, st, p);
     return hipGetLastError();
 }
 
 int trace_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false, false>, kTraceBlock, 0) != hipSuccess) return 4;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false>, kTraceBlock, 0) != hipSuccess) return 4;
     return nb > 0 ? nb : 1;
 }
 

@@ -29,12 +29,13 @@
 namespace sdd {
 
 constexpr int kTraceBlock = 128;  // threads per traversal workgroup
-constexpr int kStack = 40;        // LDS traversal stack entries per lane
+constexpr int kStack = 40;        // traversal stack entries per lane (total)
+constexpr int kLdsStack = 16;     // of which the first kLdsStack live in LDS, the rest in HBM
 constexpr int kMaxBvhDepth = kStack;  // the builder never exceeds the stack
 constexpr int kChunk = 64;        // rays per scheduling chunk (one wave)
 constexpr int kXcd = 8;           // XCDs of an MI355X; workgroup i runs on XCD i % 8
 constexpr int kMaxGlass = 4;      // pane crossings recorded per shadow segment
-constexpr int kMaxCells = 1024;
+constexpr int kMaxCells = 512;
 constexpr int kShadeBlock = 256;
 
 enum : int { kDiffuse = 0, kGlass = 1, kEmitter = 2 };
@@ -60,7 +61,8 @@ struct GridParams {
     float inv_h[3];       // cells per metre, for the initial guess of point location
 };
 
-struct TraceParams {
+// one segmented queue pair (input of this sweep, output for the next)
+struct QueueSet {
     const float4* qa_in;
     const float4* qb_in;
     const int2* qc_in;
@@ -69,7 +71,11 @@ struct TraceParams {
     float4* qb_out;
     int2* qc_out;
     int* cnt_out;
-    int* sched;           // [kXcd] chunk counters of this sweep
+};
+
+struct TraceParams {
+    QueueSet q[2];        // [0] closest-hit rays, [1] shadow rays
+    int active[2];        // which of the two sets holds work in this sweep
     long long cap;        // slots per cell
     int n_cells;
     GridParams grid;
@@ -84,6 +90,7 @@ struct TraceParams {
     int* sh_cnt;
     float2* sh_glass;
     int* overflow;
+    int* gstack;          // spill stack: (kStack - kLdsStack) entries per thread of the grid
     unsigned long long* stats;
 };
 
@@ -123,6 +130,7 @@ struct ShadeParams {
     float light_area;
     int light_mat;
     GridParams grid;
+    int n_cells;
     // queues written
     float4* eqa;
     float4* eqb;
@@ -156,6 +164,7 @@ struct CamParams {
     float* Lp;
     int* sh_state;
     GridParams grid;
+    int n_cells;
     float4* eqa;
     float4* eqb;
     int2* eqc;
