@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--grid", default=None, help="override subdomain grid, e.g. 1x1x1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--count-work", action="store_true",
+                    help="trace one extra (untimed) frame counting BVH node visits and triangle tests")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -181,6 +183,16 @@ def main():
         "kernel_ms_per_step": {k: v / args.steps for k, v in kern_ms.items()},
         "build_bvh_s": build_s,
     }
+    if args.count_work:
+        tr.reset_stats()
+        tr.trace_spectral(cam, W, H, spp, D, sample_offset=step * spp, render_id=0, count_work=True)
+        torch.cuda.synchronize()
+        sw = tr.stats()
+        visits = sw["ext_cell_visits"] + sw["shadow_cell_visits"]
+        res["work"] = {"node_visits_per_cell_visit": sw["node_visits"] / max(1, visits),
+                       "tri_tests_per_cell_visit": sw["tri_tests"] / max(1, visits),
+                       "cell_visits_per_ray": visits / max(1, sw["ext_rays"] + sw["shadow_rays"]),
+                       "scene_bytes_per_frame": 64 * sw["node_visits"] + 48 * sw["tri_tests"]}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(scene, wl, args.cpu_seconds)
     print(json.dumps(res))

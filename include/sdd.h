@@ -235,6 +235,12 @@ sdd_status sdd_reset_stats(sdd_ctx *ctx);
  * ctr: host uint32 [n][4]; key: host uint32 [2]; out: host uint32 [n][4]. */
 sdd_status sdd_debug_philox(sdd_ctx *ctx, int32_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
 
+/* Diagnostics: the library's own polarisation-averaged pane reflectance R
+ * and transmittance T (Fresnel terms of n + i k, Eq. 1; incoherent slab with
+ * Beer-Lambert absorption) for n parameter rows params [n][5] =
+ * (n, k, thickness m, wavelength nm, incidence cosine).  Host arrays. */
+sdd_status sdd_debug_pane(sdd_ctx *ctx, int32_t n, const float *params, float *R_out, float *T_out);
+
 /* Diagnostics: closest hits of n rays through the subdomain queues (the same
  * kernels as sdd_trace_spectral's extension phase).  o, d: host float [n][3];
  * t_out: host float [n] (+inf on a miss); prim_out: host int32 [n] (-1). */

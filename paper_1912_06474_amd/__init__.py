@@ -29,7 +29,7 @@ TRACE_ORTHO, TRACE_TIME_KERNELS, TRACE_COUNT_WORK = 1, 2, 4
 
 EXPORTS = ("sdd_create", "sdd_destroy", "sdd_last_error", "sdd_load_scene", "sdd_validate_scene", "sdd_build_bvh",
            "sdd_trace_spectral", "sdd_resolve_image", "sdd_reset_render", "sdd_get_stats", "sdd_reset_stats",
-           "sdd_debug_philox", "sdd_debug_trace_rays")
+           "sdd_debug_philox", "sdd_debug_pane", "sdd_debug_trace_rays")
 
 
 class SddError(RuntimeError):
@@ -105,6 +105,7 @@ def lib():
         L.sdd_get_stats.argtypes = [vp, C.POINTER(Stats)]
         L.sdd_reset_stats.argtypes = [vp]
         L.sdd_debug_philox.argtypes = [vp, i32, vp, vp, vp]
+        L.sdd_debug_pane.argtypes = [vp, i32, vp, vp, vp]
         L.sdd_debug_trace_rays.argtypes = [vp, i32, vp, vp, vp, vp]
         _LIB = L
     return _LIB
@@ -251,6 +252,14 @@ class Tracer:
         out = np.zeros_like(ctr)
         self._check(lib().sdd_debug_philox(self.h, len(ctr), _ptr(ctr), _ptr(key), _ptr(out)))
         return out
+
+    def debug_pane(self, params):
+        """params [n, 5] = (n, k, thickness m, wavelength nm, cos): returns (R, T) float32."""
+        params = np.ascontiguousarray(params, np.float32).reshape(-1, 5)
+        R = np.zeros(len(params), np.float32)
+        T = np.zeros(len(params), np.float32)
+        self._check(lib().sdd_debug_pane(self.h, len(params), _ptr(params), _ptr(R), _ptr(T)))
+        return R, T
 
     def debug_trace_rays(self, o, d):
         o = np.ascontiguousarray(o, np.float32).reshape(-1, 3)

@@ -56,21 +56,17 @@ struct sdd_ctx {
     bool has_scene = false, has_bvh = false;
     int V = 0, T = 0, M = 0, nl = 0, nlp = 0;
     std::vector<float> verts;
-    std::vector<int32_t> tris, tri_mat, mat_type;
+    std::vector<int32_t> tris, tri_mat, mat_type, glass_of, mat_emits;
+    int n_glass = 0;
     int light_type = 0, light_mat = -1;
     float lp0[3] = {0, 0, 0}, le1[3] = {0, 0, 0}, le2[3] = {0, 0, 0}, nL[3] = {0, 0, 0};
     float light_area = 0.0f;
 
     // device scene
     float4* d_prim_info = nullptr;
-    int* d_mat_type = nullptr;
-    int* d_mat_has_le = nullptr;
-    float* d_mat_thick = nullptr;
+    float4* d_pane = nullptr;  // [n_glass][nlp] pane constants
     float* d_rho = nullptr;
-    float* d_mn = nullptr;
-    float* d_mk = nullptr;
     float* d_le = nullptr;
-    float* d_lambda = nullptr;
     double* d_w = nullptr;
     double* d_cmf = nullptr;
 
@@ -90,16 +86,17 @@ struct sdd_ctx {
     float4* ray_d = nullptr;
     float2* hit = nullptr;
     uint32_t* flags = nullptr;
-    float* beta = nullptr;
-    float* Lp = nullptr;
-    float* nee_g = nullptr;
+    // path history [depth][path]
+    int4* vrec = nullptr;
     int* sh_state = nullptr;
-    int* sh_cnt = nullptr;
     float2* sh_glass = nullptr;
     // queue buffers: 0/1 closest-hit ping-pong, 2/3 shadow ping-pong
     float4* qa[4] = {nullptr, nullptr, nullptr, nullptr};
     float4* qb[4] = {nullptr, nullptr, nullptr, nullptr};
     int2* qc[4] = {nullptr, nullptr, nullptr, nullptr};
+    // rays staged in path order before routing: [0] closest-hit, [1] shadow
+    Stage stage[2] = {};
+    int n_blocks = 0;
     int* d_counts = nullptr;
     long long counts_len = 0;
     int* d_overflow = nullptr;
@@ -186,14 +183,9 @@ struct DeviceGuard {
 
 void free_scene(sdd_ctx* c) {
     dfree(c, c->d_prim_info);
-    dfree(c, c->d_mat_type);
-    dfree(c, c->d_mat_has_le);
-    dfree(c, c->d_mat_thick);
+    dfree(c, c->d_pane);
     dfree(c, c->d_rho);
-    dfree(c, c->d_mn);
-    dfree(c, c->d_mk);
     dfree(c, c->d_le);
-    dfree(c, c->d_lambda);
     dfree(c, c->d_w);
     dfree(c, c->d_cmf);
     c->has_scene = false;
@@ -212,16 +204,20 @@ void free_batch(sdd_ctx* c) {
     dfree(c, c->ray_d);
     dfree(c, c->hit);
     dfree(c, c->flags);
-    dfree(c, c->beta);
-    dfree(c, c->Lp);
-    dfree(c, c->nee_g);
+    dfree(c, c->vrec);
     dfree(c, c->sh_state);
-    dfree(c, c->sh_cnt);
     dfree(c, c->sh_glass);
     for (int i = 0; i < 4; ++i) {
         dfree(c, c->qa[i]);
         dfree(c, c->qb[i]);
         dfree(c, c->qc[i]);
+    }
+    for (int k = 0; k < 2; ++k) {
+        dfree(c, c->stage[k].qa);
+        dfree(c, c->stage[k].qb);
+        dfree(c, c->stage[k].qc);
+        dfree(c, c->stage[k].tag);
+        dfree(c, c->stage[k].hist);
     }
     dfree(c, c->d_counts);
     c->ncap = 0;
@@ -334,8 +330,9 @@ long long mem_budget_bytes() {
     return (long long)(gb * 1024.0 * 1024.0 * 1024.0);
 }
 
-long long bytes_per_path(const sdd_ctx* c) {
-    return 4LL * c->G * (16 + 16 + 8) + 8LL * c->nlp + 16 + 16 + 8 + 4 + 4 + 4 + 4 + 8 * kMaxGlass;
+long long bytes_per_path(const sdd_ctx* c, int max_depth) {
+    return 4LL * c->G * (16 + 16 + 8) + 2 * (16 + 16 + 8 + 4) + 16 + 16 + 8 + 4 +
+           (long long)max_depth * (16 + 4 + 8 * kMaxGlass);
 }
 
 sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
@@ -353,19 +350,28 @@ sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
     ALLOC(c->ray_d, n);
     ALLOC(c->hit, n);
     ALLOC(c->flags, n);
-    ALLOC(c->beta, n * c->nlp);
-    ALLOC(c->Lp, n * c->nlp);
-    ALLOC(c->nee_g, n);
-    ALLOC(c->sh_state, n);
-    ALLOC(c->sh_cnt, n);
-    ALLOC(c->sh_glass, n * kMaxGlass);
+    ALLOC(c->vrec, n * max_depth);
+    ALLOC(c->sh_state, n * max_depth);
+    ALLOC(c->sh_glass, n * max_depth * kMaxGlass);
     for (int i = 0; i < 4; ++i) {
         ALLOC(c->qa[i], qn);
         ALLOC(c->qb[i], qn);
         ALLOC(c->qc[i], qn);
     }
+    const long long nblk = (n + kShadeBlock - 1) / kShadeBlock;
+    for (int k = 0; k < 2; ++k) {
+        ALLOC(c->stage[k].qa, n);
+        ALLOC(c->stage[k].qb, n);
+        ALLOC(c->stage[k].qc, n);
+        ALLOC(c->stage[k].tag, n);
+        ALLOC(c->stage[k].hist, nblk * c->G);
+    }
     ALLOC(c->d_counts, cnt_len);
 #undef ALLOC
+    // the path history is replayed up to each path's end; zero it once so
+    // that no record is ever uninitialised memory
+    HIP_TRY(c, hipMemsetAsync(c->vrec, 0, sizeof(int4) * (size_t)(n * max_depth), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->sh_state, 0, sizeof(int) * (size_t)(n * max_depth), c->stream));
     c->counts_len = cnt_len;
     c->ncap = n;
     c->dcap = max_depth;
@@ -393,8 +399,10 @@ QueueSet queue_set(sdd_ctx* c, int in_buf, int out_buf, int phase, int k) {
 
 // S sweeps over the subdomain queues.  ext_phase / sh_phase < 0: that kind is
 // idle.  Closest-hit rays start in buffer 0 (partner 1), shadow rays in
-// buffer 2 (partner 3).
-sdd_status run_sweeps(sdd_ctx* c, int ext_phase, int sh_phase, long long cap, bool count, bool timing) {
+// buffer 2 (partner 3); their results go to the history arrays of depth
+// sh_depth (path stride n_paths).
+sdd_status run_sweeps(sdd_ctx* c, int ext_phase, int sh_phase, long long cap, bool count, bool timing,
+                      int sh_depth = 0, long long n_paths = 0) {
     for (int k = 0; k < c->S; ++k) {
         TraceParams p{};
         const bool even = k % 2 == 0;
@@ -410,9 +418,11 @@ sdd_status run_sweeps(sdd_ctx* c, int ext_phase, int sh_phase, long long cap, bo
         p.cell_root = c->d_cell_root;
         p.prim_info = c->d_prim_info;
         p.hit = c->hit;
-        p.sh_state = c->sh_state;
-        p.sh_cnt = c->sh_cnt;
-        p.sh_glass = c->sh_glass;
+        if (sh_depth > 0) {
+            const long long off = (long long)(sh_depth - 1) * n_paths;
+            p.sh_state = c->sh_state + off;
+            p.sh_glass = c->sh_glass + off * kMaxGlass;
+        }
         p.overflow = c->d_overflow;
         p.gstack = c->d_gstack;
         p.stats = c->d_stats;
@@ -420,6 +430,30 @@ sdd_status run_sweeps(sdd_ctx* c, int ext_phase, int sh_phase, long long cap, bo
         HIP_TRY(c, launch_trace(p, count, c->trace_grid, c->stream));
         ++c->launches_trace;
     }
+    return SDD_OK;
+}
+
+// scatter the staged rays of a batch into the per-cell queues: closest-hit
+// rays to buffer 0 (counters of ext_phase), shadow rays to buffer 2
+sdd_status route(sdd_ctx* c, int N, long long cap, int ext_phase, int sh_phase, bool timing) {
+    RouteParams r{};
+    r.N = N;
+    r.n_blocks = (N + kShadeBlock - 1) / kShadeBlock;
+    r.n_cells = c->G;
+    r.cap = cap;
+    r.active[0] = ext_phase >= 0;
+    r.active[1] = sh_phase >= 0;
+    for (int k = 0; k < 2; ++k) r.st[k] = c->stage[k];
+    r.qa[0] = c->qa[0];
+    r.qb[0] = c->qb[0];
+    r.qc[0] = c->qc[0];
+    r.qa[1] = c->qa[2];
+    r.qb[1] = c->qb[2];
+    r.qc[1] = c->qc[2];
+    r.cnt[0] = ext_phase >= 0 ? counts_at(c, ext_phase, 0) : nullptr;
+    r.cnt[1] = sh_phase >= 0 ? counts_at(c, sh_phase, 0) : nullptr;
+    Timer tm(c, timing, 3);
+    HIP_TRY(c, launch_route(r, c->stream));
     return SDD_OK;
 }
 
@@ -530,35 +564,38 @@ sdd_status sdd_load_scene(sdd_ctx* c, const sdd_scene_desc* s) {
         c->nL[0] = c->nL[1] = c->nL[2] = 0.0f;
         c->light_area = 0.0f;
     }
-    // per-material tables padded to nlp wavelengths
+    // per-material tables padded to nlp wavelengths; glass materials get a
+    // compact index and their pane constants (double, rounded once)
     const int nl = c->nl, nlp = c->nlp, M = c->M;
-    std::vector<float> rho((size_t)M * nlp, 0.0f), mn((size_t)M * nlp, 1.0f), mk((size_t)M * nlp, 0.0f),
-        le((size_t)M * nlp, 0.0f);
-    std::vector<int> has_le(M, 0);
+    std::vector<float> rho((size_t)M * nlp, 0.0f), le((size_t)M * nlp, 0.0f);
+    c->glass_of.assign(M, -1);
+    c->mat_emits.assign(M, 0);
+    c->n_glass = 0;
+    for (int m = 0; m < M; ++m)
+        if (s->mat_type[m] == SDD_MAT_GLASS_SLAB) c->glass_of[m] = c->n_glass++;
+    std::vector<float4> pane((size_t)std::max(1, c->n_glass) * nlp, make_float4(0.0f, 0.0f, 1.0f, 0.0f));
     for (int m = 0; m < M; ++m)
         for (int l = 0; l < nl; ++l) {
             const size_t i = (size_t)m * nl + l, j = (size_t)m * nlp + l;
             rho[j] = s->mat_rho[i];
-            mn[j] = s->mat_n[i];
-            mk[j] = s->mat_k[i];
             le[j] = s->mat_le[i];
-            if (s->mat_le[i] != 0.0f) has_le[m] = 1;
+            if (s->mat_le[i] != 0.0f) c->mat_emits[m] = 1;
+            if (c->glass_of[m] >= 0) {
+                const double n = s->mat_n[i], k = s->mat_k[i];
+                const double at = 4.0 * M_PI * k * (double)s->mat_thick[m] / ((double)s->lambda_nm[l] * 1e-9);
+                pane[(size_t)c->glass_of[m] * nlp + l] =
+                    make_float4((float)(n * n - k * k), (float)(2.0 * n * k), (float)(1.0 / (n * n)), (float)at);
+            }
         }
-    std::vector<float> lam(nlp, 550.0f);
-    for (int l = 0; l < nl; ++l) lam[l] = s->lambda_nm[l];
-    BuildInput bi{c->verts.data(), c->V, c->tris.data(), c->T, c->tri_mat.data(), c->mat_type.data(), 1, 1, 1, 4, 16};
+    BuildInput bi{c->verts.data(), c->V, c->tris.data(), c->T, c->tri_mat.data(), c->mat_type.data(),
+                  c->glass_of.data(), c->mat_emits.data(), 1, 1, 1, 4, 16};
     std::vector<HostF4> info;
     triangle_info(bi, info);
     sdd_status st;
     if ((st = upload(c, &c->d_prim_info, reinterpret_cast<const float4*>(info.data()), info.size())) != SDD_OK ||
-        (st = upload(c, &c->d_mat_type, c->mat_type.data(), (size_t)M)) != SDD_OK ||
-        (st = upload(c, &c->d_mat_has_le, has_le.data(), (size_t)M)) != SDD_OK ||
-        (st = upload(c, &c->d_mat_thick, s->mat_thick, (size_t)M)) != SDD_OK ||
+        (st = upload(c, &c->d_pane, pane.data(), pane.size())) != SDD_OK ||
         (st = upload(c, &c->d_rho, rho.data(), rho.size())) != SDD_OK ||
-        (st = upload(c, &c->d_mn, mn.data(), mn.size())) != SDD_OK ||
-        (st = upload(c, &c->d_mk, mk.data(), mk.size())) != SDD_OK ||
         (st = upload(c, &c->d_le, le.data(), le.size())) != SDD_OK ||
-        (st = upload(c, &c->d_lambda, lam.data(), lam.size())) != SDD_OK ||
         (st = upload(c, &c->d_w, s->lambda_w, (size_t)nl)) != SDD_OK ||
         (st = upload(c, &c->d_cmf, s->cmf, (size_t)nl * 3)) != SDD_OK) {
         free_scene(c);
@@ -586,7 +623,7 @@ sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
     free_batch(c);
     free_accel(c);
     BuildInput bi{c->verts.data(), c->V, c->tris.data(), c->T, c->tri_mat.data(), c->mat_type.data(),
-                  d->nx, d->ny, d->nz, leaf, bins};
+                  c->glass_of.data(), c->mat_emits.data(), d->nx, d->ny, d->nz, leaf, bins};
     std::string err;
     GridBvh gb;
     if (!build_grid_bvh(bi, gb, err)) return fail(c, SDD_ERR_INVALID_ARG, err);
@@ -660,16 +697,16 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         Render rd;
         rd.W = t->W;
         rd.H = t->H;
-        sdd_status st = dalloc(c, &rd.acc, (size_t)c->nl * WH);
+        sdd_status st = dalloc(c, &rd.acc, (size_t)c->nlp * WH);
         if (st != SDD_OK) return st;
-        HIP_TRY(c, hipMemsetAsync(rd.acc, 0, sizeof(float) * (size_t)c->nl * WH, c->stream));
+        HIP_TRY(c, hipMemsetAsync(rd.acc, 0, sizeof(float) * (size_t)c->nlp * WH, c->stream));
         it = c->renders.emplace(t->render_id, rd).first;
     }
     Render& rd = it->second;
 
     const long long total = (long long)WH * t->spp;
-    long long nb = std::max<long long>(64, mem_budget_bytes() / bytes_per_path(c));
-    nb = std::min<long long>(nb, 1LL << 26);
+    long long nb = std::max<long long>(64, mem_budget_bytes() / bytes_per_path(c, t->max_depth));
+    nb = std::min<long long>(nb, kMaxBatch);
     nb = std::min(nb, total);
     sdd_status st = ensure_batch(c, nb, t->max_depth);
     if (st != SDD_OK) return st;
@@ -693,9 +730,13 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
             Timer tm(c, timing, 3);
             HIP_TRY(c, launch_fill_i32(c->d_counts, c->counts_len, 0, c->stream));
         }
+        const FastDiv fwh = make_fastdiv((uint32_t)WH);
+        const int pb = (int)(g0 % WH), sb = (int)(g0 / WH);
         CamParams cp{};
         cp.N = N;
-        cp.g0 = g0;
+        cp.pb = pb;
+        cp.sb = sb;
+        cp.fwh = fwh;
         cp.W = t->W;
         cp.H = t->H;
         cp.WH = WH;
@@ -711,29 +752,26 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         cp.tan_half = (float)std::tan(0.5 * (double)t->fov_deg * M_PI / 180.0);
         cp.aspect = (float)((double)t->W / (double)t->H);
         cp.ortho_half_h = t->ortho_half_h;
-        cp.nlp = c->nlp;
         cp.flags = c->flags;
         cp.ray_o = c->ray_o;
         cp.ray_d = c->ray_d;
         cp.hit = c->hit;
-        cp.beta = c->beta;
-        cp.Lp = c->Lp;
-        cp.sh_state = c->sh_state;
         cp.grid = c->grid;
         cp.n_cells = c->G;
-        cp.eqa = c->qa[0];
-        cp.eqb = c->qb[0];
-        cp.eqc = c->qc[0];
-        cp.ecnt = counts_at(c, 0, 0);
-        cp.cap = cap;
+        cp.se = c->stage[0];
+        cp.n_blocks = (N + kShadeBlock - 1) / kShadeBlock;
         cp.stats = c->d_stats;
         {
             Timer tm(c, timing, 3);
             HIP_TRY(c, launch_camgen(cp, c->stream));
         }
+        st = route(c, N, cap, ph_ext(1), -1, timing);
+        if (st != SDD_OK) return st;
         ShadeParams sp{};
         sp.N = N;
-        sp.g0 = g0;
+        sp.pb = pb;
+        sp.sb = sb;
+        sp.fwh = fwh;
         sp.W = t->W;
         sp.WH = WH;
         sp.s0 = t->sample_offset;
@@ -744,21 +782,9 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         sp.ray_o = c->ray_o;
         sp.ray_d = c->ray_d;
         sp.hit = c->hit;
-        sp.beta = c->beta;
-        sp.Lp = c->Lp;
-        sp.nee_g = c->nee_g;
-        sp.sh_state = c->sh_state;
-        sp.sh_cnt = c->sh_cnt;
-        sp.sh_glass = c->sh_glass;
         sp.prim_info = c->d_prim_info;
-        sp.mat_type = c->d_mat_type;
-        sp.mat_has_le = c->d_mat_has_le;
-        sp.mat_thick = c->d_mat_thick;
-        sp.rho = c->d_rho;
-        sp.mn = c->d_mn;
-        sp.mk = c->d_mk;
-        sp.le = c->d_le;
-        sp.lambda_nm = c->d_lambda;
+        sp.pane = c->d_pane;
+        sp.n_glass = c->n_glass;
         sp.nl = c->nl;
         sp.nlp = c->nlp;
         sp.light_type = c->light_type;
@@ -769,45 +795,56 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
             sp.nL[k] = c->nL[k];
         }
         sp.light_area = c->light_area;
-        sp.light_mat = c->light_mat < 0 ? 0 : c->light_mat;
         sp.grid = c->grid;
         sp.n_cells = c->G;
-        sp.eqa = c->qa[0];
-        sp.eqb = c->qb[0];
-        sp.eqc = c->qc[0];
-        sp.sqa = c->qa[2];
-        sp.sqb = c->qb[2];
-        sp.sqc = c->qc[2];
-        sp.cap = cap;
+        sp.se = c->stage[0];
+        sp.ss = c->stage[1];
+        sp.n_blocks = (N + kShadeBlock - 1) / kShadeBlock;
         sp.hit_log = t->hit_log;
-        sp.shadow_log = t->shadow_log;
         sp.stats = c->d_stats;
         for (int d = 1; d <= D; ++d) {
             // closest-hit rays of depth d share the sweeps with the shadow rays of depth d - 1
-            st = run_sweeps(c, ph_ext(d), d >= 2 ? ph_sh(d - 1) : -1, cap, count, timing);
+            st = run_sweeps(c, ph_ext(d), d >= 2 ? ph_sh(d - 1) : -1, cap, count, timing, d - 1, N);
             if (st != SDD_OK) return st;
             sp.depth = d;
-            sp.final_pass = 0;
-            sp.ecnt = counts_at(c, ph_ext(d + 1), 0);
-            sp.scnt = counts_at(c, ph_sh(d), 0);
+            sp.vrec = c->vrec + (long long)(d - 1) * N;
+            sp.sh_state = c->sh_state + (long long)(d - 1) * N;
             {
                 Timer tm(c, timing, 2);
                 HIP_TRY(c, launch_shade(sp, c->stream));
             }
+            st = route(c, N, cap, d < D ? ph_ext(d + 1) : -1, ph_sh(d), timing);
+            if (st != SDD_OK) return st;
         }
-        st = run_sweeps(c, -1, ph_sh(D), cap, count, timing);
+        st = run_sweeps(c, -1, ph_sh(D), cap, count, timing, D, N);
         if (st != SDD_OK) return st;
-        sp.depth = D + 1;
-        sp.final_pass = 1;
-        sp.ecnt = counts_at(c, ph_ext(D + 1), 0);
-        sp.scnt = counts_at(c, ph_ext(D + 1), 1);
-        {
-            Timer tm(c, timing, 2);
-            HIP_TRY(c, launch_shade(sp, c->stream));
-        }
+        SpectralParams xp{};
+        xp.N = N;
+        xp.pb = pb;
+        xp.sb = sb;
+        xp.fwh = fwh;
+        xp.ngrp = c->nlp / 4;
+        xp.fgrp = make_fastdiv((uint32_t)xp.ngrp);
+        xp.WH = WH;
+        xp.s0 = t->sample_offset;
+        xp.spp_call = t->spp;
+        xp.max_depth = D;
+        xp.vrec = c->vrec;
+        xp.sh_state = c->sh_state;
+        xp.sh_glass = c->sh_glass;
+        xp.pane = c->d_pane;
+        xp.n_glass = std::max(1, c->n_glass);
+        xp.n_mats = c->M;
+        xp.rho = c->d_rho;
+        xp.le = c->d_le;
+        xp.nl = c->nl;
+        xp.nlp = c->nlp;
+        xp.light_mat = c->light_mat < 0 ? 0 : c->light_mat;
+        xp.acc = rd.acc;
+        xp.shadow_log = t->shadow_log;
         {
             Timer tm(c, timing, 3);
-            HIP_TRY(c, launch_flush(N, g0, WH, c->nl, c->Lp, rd.acc, c->stream));
+            HIP_TRY(c, launch_spectral(xp, c->stream));
         }
         ++c->batches;
     }
@@ -838,7 +875,8 @@ sdd_status sdd_resolve_image(sdd_ctx* c, int32_t render_id, double* spectral_out
         ds = tmp_s;
         dx = tmp_x;
     }
-    hipError_t e = launch_resolve(WH, c->nl, 1.0 / (double)rd.spp_done, rd.acc, c->d_w, c->d_cmf, ds, dx, c->stream);
+    hipError_t e =
+        launch_resolve(WH, c->nl, c->nlp, 1.0 / (double)rd.spp_done, rd.acc, c->d_w, c->d_cmf, ds, dx, c->stream);
     if (e == hipSuccess && !out_is_device) {
         if (spectral_out)
             e = hipMemcpyAsync(spectral_out, tmp_s, sizeof(double) * (size_t)WH * c->nl, hipMemcpyDeviceToHost, c->stream);
@@ -931,6 +969,49 @@ sdd_status sdd_debug_philox(sdd_ctx* c, int32_t n, const uint32_t* ctr, const ui
     dfree(c, dc);
     dfree(c, dout);
     if (e != hipSuccess) return hip_fail(c, e, "debug philox");
+    return SDD_OK;
+}
+
+sdd_status sdd_debug_pane(sdd_ctx* c, int32_t n, const float* params, float* R_out, float* T_out) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (n < 0 || (n > 0 && (!params || !R_out || !T_out))) return fail(c, SDD_ERR_INVALID_ARG, "bad pane arguments");
+    if (n == 0) return SDD_OK;
+    std::vector<float4> pc((size_t)n);
+    std::vector<float> cc((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const float* q = params + 5 * (size_t)i;
+        const double nn = q[0], k = q[1], th = q[2], lam = q[3];
+        if (!(nn > 0.0) || !(k >= 0.0) || !(th >= 0.0) || !(lam > 0.0) || !(q[4] >= 0.0f && q[4] <= 1.0f))
+            return fail(c, SDD_ERR_INVALID_ARG, "pane parameters out of range");
+        pc[i] = make_float4((float)(nn * nn - k * k), (float)(2.0 * nn * k), (float)(1.0 / (nn * nn)),
+                            (float)(4.0 * M_PI * k * th / (lam * 1e-9)));
+        cc[i] = q[4];
+    }
+    DeviceGuard g(c->device);
+    float4* dpc = nullptr;
+    float* dc = nullptr;
+    float2* dout = nullptr;
+    if (dalloc(c, &dpc, (size_t)n) != SDD_OK || dalloc(c, &dc, (size_t)n) != SDD_OK ||
+        dalloc(c, &dout, (size_t)n) != SDD_OK) {
+        dfree(c, dpc);
+        dfree(c, dc);
+        return SDD_ERR_OOM;
+    }
+    std::vector<float2> h((size_t)n);
+    hipError_t e = hipMemcpyAsync(dpc, pc.data(), sizeof(float4) * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dc, cc.data(), sizeof(float) * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_pane(n, dpc, dc, dout, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), dout, sizeof(float2) * (size_t)n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(c, dpc);
+    dfree(c, dc);
+    dfree(c, dout);
+    if (e != hipSuccess) return hip_fail(c, e, "debug pane");
+    for (int i = 0; i < n; ++i) {
+        R_out[i] = h[i].x;
+        T_out[i] = h[i].y;
+    }
     return SDD_OK;
 }
 

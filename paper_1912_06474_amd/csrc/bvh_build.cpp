@@ -187,9 +187,12 @@ void triangle_info(const BuildInput& in, std::vector<HostF4>& info) {
                              e1[0] * e2[1] - e1[1] * e2[0]};
         const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
         const double s = len > 0.0 ? 1.0 / len : 0.0;
-        int32_t mat = in.tri_mat[i];
+        const int32_t mat = in.tri_mat[i];
+        const int32_t typ = in.mat_type[mat] & 3;
+        const int32_t id = (typ == kGlass && in.glass_of) ? in.glass_of[mat] : mat;
+        const int32_t word = id | (typ << kMatTypeShift) | ((in.mat_emits && in.mat_emits[mat]) ? kMatEmits : 0);
         float w;
-        std::memcpy(&w, &mat, 4);
+        std::memcpy(&w, &word, 4);
         info[i] = HostF4{(float)(n[0] * s), (float)(n[1] * s), (float)(n[2] * s), w};
     }
 }
@@ -343,11 +346,12 @@ bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err) {
                 const float* v2 = in.verts + 3 * (size_t)t[2];
                 const int mat = in.tri_mat[prim];
                 const int meta = (in.mat_type[mat] & 3) | (i == lf.first + lf.count - 1 ? kLastInLeaf : 0);
+                const int gi = in.glass_of ? in.glass_of[mat] : -1;
                 out.tris.push_back(HostF4{v0[0], v0[1], v0[2], int_bits(prim)});
                 out.tris.push_back(HostF4{(float)((double)v1[0] - v0[0]), (float)((double)v1[1] - v0[1]),
                                           (float)((double)v1[2] - v0[2]), int_bits(meta)});
                 out.tris.push_back(HostF4{(float)((double)v2[0] - v0[0]), (float)((double)v2[1] - v0[1]),
-                                          (float)((double)v2[2] - v0[2]), int_bits(mat)});
+                                          (float)((double)v2[2] - v0[2]), int_bits(gi)});
             }
             return ~start;
         };

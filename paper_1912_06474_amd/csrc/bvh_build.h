@@ -31,6 +31,8 @@ struct BuildInput {
     int n_tris;
     const int32_t* tri_mat;   // [T]
     const int32_t* mat_type;  // [M]
+    const int32_t* glass_of;  // [M] compact glass index or -1 (may be null: no glass)
+    const int32_t* mat_emits; // [M] nonzero if the material emits (may be null)
     int nx, ny, nz;
     int leaf_max;
     int sah_bins;
@@ -40,7 +42,7 @@ struct BuildInput {
 bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err);
 
 // Unit geometric normal (v1 - v0) x (v2 - v0) of every triangle, in double
-// then rounded, with the material index in w (as int bits).
+// then rounded, with the material word (layout.h) in w (as int bits).
 void triangle_info(const BuildInput& in, std::vector<HostF4>& info);
 
 }  // namespace sdd

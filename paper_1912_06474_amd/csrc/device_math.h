@@ -48,69 +48,50 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 // top 24 bits -> [0, 1); exact in FP32
 __device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-8f; }
 
-// ---------------------------------------------------------------------------
-// complex FP32 arithmetic for the Fresnel terms of n + i k (Eq. 1)
-// ---------------------------------------------------------------------------
-struct cf {
-    float re, im;
-};
-__device__ __forceinline__ cf cmul(cf a, cf b) { return cf{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-// Smith's division
-__device__ __forceinline__ cf cdiv(cf a, cf b) {
-    if (fabsf(b.re) >= fabsf(b.im)) {
-        const float r = b.im / b.re, den = b.re + b.im * r;
-        return cf{(a.re + a.im * r) / den, (a.im - a.re * r) / den};
-    }
-    const float r = b.re / b.im, den = b.im + b.re * r;
-    return cf{(a.re * r + a.im) / den, (a.im * r - a.re) / den};
-}
-// principal square root (Re >= 0), stable form
-__device__ __forceinline__ cf csqrt_principal(cf z) {
-    const float m = hypotf(z.re, z.im);
-    if (m == 0.0f) return cf{0.0f, 0.0f};
-    if (z.re >= 0.0f) {
-        const float a = sqrtf(0.5f * (m + z.re));
-        return cf{a, z.im / (2.0f * a)};
-    }
-    float b = copysignf(sqrtf(0.5f * (m - z.re)), z.im);
-    return cf{z.im / (2.0f * b), b};
-}
-
 // Polarisation-averaged reflectance R and transmittance T of a pane: an
-// incoherent slab of thickness thick (m) with index n + i k on both faces,
-// incidence cosine c from air.  Per polarisation: Fresnel R of the face
-// (complex Snell, principal cos theta_t), internal attenuation
-// tau = exp(-4 pi k / lambda * thick / cos theta_r) with theta_r from real
-// Snell, and the sum over internal reflections
-//   T = (1-R)^2 tau / (1 - R^2 tau^2),  Rs = R + (1-R)^2 R tau^2 / (1 - R^2 tau^2).
-__device__ __forceinline__ void pane_RT(float n, float k, float thick, float lambda_nm, float c, float& R_out,
-                                        float& T_out) {
-    const cf nt{n, k};
-    const cf sin2t = cdiv(cf{1.0f - c * c, 0.0f}, cmul(nt, nt));
-    const cf cost = csqrt_principal(cf{1.0f - sin2t.re, -sin2t.im});
-    const cf ntc = cmul(nt, cost);
-    const cf rs = cdiv(cf{c - ntc.re, -ntc.im}, cf{c + ntc.re, ntc.im});
-    const cf nc{nt.re * c, nt.im * c};
-    const cf rp = cdiv(cf{nc.re - cost.re, nc.im - cost.im}, cf{nc.re + cost.re, nc.im + cost.im});
-    const float Rf[2] = {rs.re * rs.re + rs.im * rs.im, rp.re * rp.re + rp.im * rp.im};
-    const float cosr2 = 1.0f - (1.0f - c * c) / (n * n);
-    float tau = 0.0f;
-    if (cosr2 > 0.0f) {
-        const float alpha = 4.0f * kPi * k / (lambda_nm * 1e-9f);
-        tau = expf(-alpha * thick / sqrtf(cosr2));
+// incoherent slab of thickness d with complex index n + i k (Eq. 1) on both
+// faces, incidence cosine c from air.  pc holds per-(material, wavelength)
+// constants (n^2 - k^2, 2 n k, 1 / n^2, 4 pi k d / lambda).
+// Face reflectance: with u + i v = sqrt(n~^2 - sin^2) (principal root, the
+// n~ cos(theta_t) of complex Snell) and n~^2 c = P + i Q,
+//   R_s = ((c - u)^2 + v^2) / ((c + u)^2 + v^2)
+//   R_p = ((P - u)^2 + (Q - v)^2) / ((P + u)^2 + (Q + v)^2).
+// Internal attenuation tau = exp(-4 pi k d / (lambda cos theta_r)) with
+// theta_r from real Snell (Beer-Lambert), and the sum over internal
+// reflections T = (1-R)^2 tau / (1 - R^2 tau^2),
+// R_slab = R + (1-R)^2 R tau^2 / (1 - R^2 tau^2), per polarisation.
+__device__ __forceinline__ void pane_RT(float4 pc, float c, float& R_out, float& T_out) {
+    const float s2 = 1.0f - c * c;
+    const float A = pc.x - s2, B = pc.y;
+    const float m = sqrtf(A * A + B * B);
+    float u, v;
+    if (A >= 0.0f) {
+        u = sqrtf(0.5f * (m + A));
+        v = u > 0.0f ? B / (2.0f * u) : 0.0f;
+    } else {
+        v = sqrtf(0.5f * (m - A));
+        u = B / (2.0f * v);
     }
+    const float P = pc.x * c, Q = pc.y * c;
+    const float rs_den = (c + u) * (c + u) + v * v;
+    const float rp_den = (P + u) * (P + u) + (Q + v) * (Q + v);
+    const float Rf[2] = {rs_den > 0.0f ? ((c - u) * (c - u) + v * v) / rs_den : 1.0f,
+                         rp_den > 0.0f ? ((P - u) * (P - u) + (Q - v) * (Q - v)) / rp_den : 1.0f};
+    const float cosr2 = 1.0f - s2 * pc.z;
+    const float tau = cosr2 > 0.0f ? expf(-pc.w / sqrtf(cosr2)) : 0.0f;
+    const float tau2 = tau * tau;
     float Rsum = 0.0f, Tsum = 0.0f;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const float Ri = Rf[i];
-        const float den = 1.0f - Ri * Ri * tau * tau;
+        const float den = 1.0f - Ri * Ri * tau2;
         if (den <= 0.0f) {
             Rsum += 1.0f;
             continue;
         }
-        const float a = (1.0f - Ri) * (1.0f - Ri);
-        Tsum += a * tau / den;
-        Rsum += Ri + a * Ri * tau * tau / den;
+        const float a = (1.0f - Ri) * (1.0f - Ri) / den;
+        Tsum += a * tau;
+        Rsum += Ri + a * Ri * tau2;
     }
     R_out = 0.5f * Rsum;
     T_out = 0.5f * Tsum;
@@ -167,21 +148,38 @@ __device__ __forceinline__ int wave_append(bool active, int key, int* counts) {
     return slot;
 }
 
-// Workgroup multi-split append: per-segment histogram in LDS (s_cnt, s_base:
-// n_seg ints each), then one global atomic per non-empty segment of the
-// workgroup, issued by different threads in parallel.  Every thread of the
+// Stable workgroup multi-split rank: every thread with `active` gets its
+// rank among the threads of the block with the same key, in thread order
+// (per wave: ballot + mbcnt; across waves: prefix of the per-wave counts held
+// in s_wcnt[wave][n_seg]).  Afterwards s_wcnt[0][k] holds nothing useful; the
+// block's count of key k is returned by block_key_total.  Every thread of the
 // block must call it (it synchronises the block).
-__device__ __forceinline__ int block_append(bool active, int key, int* counts, int n_seg, int* s_cnt, int* s_base) {
-    for (int i = threadIdx.x; i < n_seg; i += blockDim.x) s_cnt[i] = 0;
+__device__ __forceinline__ int block_rank(bool active, int key, int n_seg, int* s_wcnt) {
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();  // earlier readers of s_wcnt are done
+    for (int i = threadIdx.x; i < nw * n_seg; i += blockDim.x) s_wcnt[i] = 0;
     __syncthreads();
-    const int local = active ? atomicAdd(&s_cnt[key], 1) : 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < n_seg; i += blockDim.x) {
-        const int c = s_cnt[i];
-        if (c) s_base[i] = atomicAdd(&counts[i], c);
+    int rank = 0;
+    uint64_t pending = __ballot(active);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int lk = __builtin_amdgcn_readlane(key, leader);
+        const uint64_t m = __ballot(active && key == lk);
+        if (lane_id() == leader) s_wcnt[w * n_seg + lk] = popc64(m);
+        if (active && key == lk) rank = rank_below(m);
+        pending &= ~m;
     }
     __syncthreads();
-    return active ? s_base[key] + local : -1;
+    if (active)
+        for (int v = 0; v < w; ++v) rank += s_wcnt[v * n_seg + key];
+    return rank;
+}
+
+__device__ __forceinline__ int block_key_total(int key, int n_seg, const int* s_wcnt) {
+    const int nw = (blockDim.x + 63) >> 6;
+    int t = 0;
+    for (int v = 0; v < nw; ++v) t += s_wcnt[v * n_seg + key];
+    return t;
 }
 
 __device__ __forceinline__ int wave_sum(int v) {

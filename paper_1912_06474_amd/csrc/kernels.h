@@ -11,10 +11,12 @@ hipError_t launch_camgen(const CamParams& p, hipStream_t st);
 hipError_t launch_trace(const TraceParams& p, bool count, int grid_blocks, hipStream_t st);
 int trace_blocks_per_cu();
 hipError_t launch_shade(const ShadeParams& p, hipStream_t st);
-hipError_t launch_flush(int N, long long g0, int WH, int nl, const float* Lp, float* acc, hipStream_t st);
-hipError_t launch_resolve(int WH, int nl, double inv_spp, const float* acc, const double* w, const double* cmf,
-                          double* spectral, double* xyz, hipStream_t st);
+hipError_t launch_route(const RouteParams& p, hipStream_t st);
+hipError_t launch_spectral(const SpectralParams& p, hipStream_t st);
+hipError_t launch_resolve(int WH, int nl, int nlp, double inv_spp, const float* acc, const double* w,
+                          const double* cmf, double* spectral, double* xyz, hipStream_t st);
 hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
+hipError_t launch_pane(int n, const float4* pc, const float* c, float2* out, hipStream_t st);
 hipError_t launch_philox(int n, const uint4* ctr, uint2 key, uint4* out, hipStream_t st);
 hipError_t launch_debug_rays(int n, const float* o, const float* d, const GridParams& grid, float2* hit, float4* qa,
                              float4* qb, int2* qc, int* cnt, long long cap, hipStream_t st);

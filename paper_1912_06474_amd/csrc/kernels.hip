@@ -8,9 +8,11 @@
 //             is handed to the neighbouring cell's queue with its origin,
 //             direction and t carried unchanged (Sec. 5, interface condition:
 //             continuity of the ray properties)
-//   k_shade   per-wavelength interaction at each hit (Eq. 1-3, Sec. 4, 6),
-//             shadow ray toward the light, next ray of the path
-//   k_flush   per-pixel FP32 accumulation of finished path samples
+//   k_shade   the geometric interaction at each hit (Sec. 4, Eq. 3): shadow
+//             ray toward the light, glass branch choice, next ray; one record
+//             per vertex
+//   k_spectral per-wavelength replay of the vertex records (Eq. 1-3, Sec. 6
+//             pane terms) and per-pixel FP32 accumulation
 //   k_resolve FP64 per-pixel mean and spectral -> XYZ reduction
 #include <hip/hip_runtime.h>
 
@@ -72,8 +74,8 @@ __device__ __forceinline__ int locate_ray(const GridParams& g, f3 o, f3 d, float
 // ---------------------------------------------------------------------------
 // camera rays
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_camgen(CamParams P) {
-    __shared__ int s_cnt[kMaxCells], s_base[kMaxCells];
+__global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
+    __shared__ int s_wcnt[(kShadeBlock / 64) * kMaxCells];
     const int pid = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = pid < P.N;
     bool enq = false;
@@ -81,10 +83,11 @@ __global__ __launch_bounds__(256) void k_camgen(CamParams P) {
     f3 o{0, 0, 0}, d{0, 0, 1};
     float t_enter = 0.0f;
     if (valid) {
-        const long long g = P.g0 + pid;
-        const int s = P.s0 + (int)(g / P.WH);
-        const int p = (int)(g % P.WH);
-        const int px = p % P.W, py = p / P.W;
+        const uint32_t q = (uint32_t)(P.pb + pid);
+        const uint32_t qs = fdiv(q, P.fwh);
+        const int s = P.s0 + P.sb + (int)qs;
+        const int p = (int)(q - qs * (uint32_t)P.WH);
+        const int py = (int)(p / (unsigned)P.W), px = p - py * P.W;
         const uint4 r = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, 0u, 0u), P.key);
         const float x = (float)px + u01(r.x), y = (float)py + u01(r.y);
         const float sx = 2.0f * x / (float)P.W - 1.0f, sy = 1.0f - 2.0f * y / (float)P.H;
@@ -101,21 +104,20 @@ __global__ __launch_bounds__(256) void k_camgen(CamParams P) {
         P.ray_d[pid] = make_float4(d.x, d.y, d.z, 0.0f);
         P.hit[pid] = make_float2(INFINITY, __int_as_float(-1));
         P.flags[pid] = kAlive | kCountE;
-        P.sh_state[pid] = kShNone;
-        for (int l = 0; l < P.nlp; ++l) {
-            P.beta[(size_t)l * P.N + pid] = 1.0f;
-            P.Lp[(size_t)l * P.N + pid] = 0.0f;
-        }
         cell = locate_ray(P.grid, o, d, t_enter);
         enq = cell >= 0;
     }
-    const int slot = block_append(enq, cell, P.ecnt, P.n_cells, s_cnt, s_base);
-    if (enq && slot < P.cap) {
-        const long long q = (long long)cell * P.cap + slot;
-        P.eqa[q] = make_float4(o.x, o.y, o.z, t_enter);
-        P.eqb[q] = make_float4(d.x, d.y, d.z, __int_as_float(pid));
-        P.eqc[q] = make_int2(-1, __float_as_int(INFINITY));
+    const int rank = block_rank(enq, cell, P.n_cells, s_wcnt);
+    if (valid) {
+        P.se.tag[pid] = enq ? (cell | (rank << 16)) : -1;
+        if (enq) {
+            P.se.qa[pid] = make_float4(o.x, o.y, o.z, t_enter);
+            P.se.qb[pid] = make_float4(d.x, d.y, d.z, __int_as_float(pid));
+            P.se.qc[pid] = make_int2(-1, __float_as_int(INFINITY));
+        }
     }
+    for (int c = threadIdx.x; c < P.n_cells; c += blockDim.x)
+        P.se.hist[(long long)c * P.n_blocks + blockIdx.x] = block_key_total(c, P.n_cells, s_wcnt);
     const uint64_t m = __ballot(valid);
     if (lane_id() == 0 && m) atomicAdd(&P.stats[kStatExtRays], (unsigned long long)popc64(m));
 }
@@ -172,7 +174,7 @@ template <bool SHADOW, bool COUNT>
 __device__ __forceinline__ void traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                          const float4* __restrict__ prim_info, int root, const RayTrav& r,
                                          float tlo, float t_exit, float t_max, int exclude, float& thi, int& best,
-                                         bool& blocked, int& n_glass, int pid, int* __restrict__ sh_cnt,
+                                         bool& blocked, int& n_glass, int pid, const int* __restrict__ sh_state,
                                          float2* __restrict__ sh_glass, int* overflow, int* stk, int* gstk,
                                          int gstride, int& n_nodes, int& n_tris) {
     int sp = 0;
@@ -228,7 +230,7 @@ __device__ __forceinline__ void traverse(const float4* __restrict__ nodes, const
                                 return;
                             }
                             const f3 ng = xyz(prim_info[prim]);
-                            if (n_glass < 0) n_glass = sh_cnt[pid];
+                            if (n_glass < 0) n_glass = sh_state[pid] >> 4;
                             if (n_glass < kMaxGlass)
                                 sh_glass[(size_t)pid * kMaxGlass + n_glass] = make_float2(fabsf(dot3(r.d, ng)), c.w);
                             else
@@ -297,7 +299,7 @@ __device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueS
         int n_glass = -1;  // pane crossings so far (-1: not loaded yet)
         if (!SHADOW || thi > t_enter)
             traverse<SHADOW, COUNT>(P.nodes, P.tris, P.prim_info, root, r, t_enter, t_exit, t_max, qc.x, thi, best,
-                                    blocked, n_glass, pid, P.sh_cnt, P.sh_glass, P.overflow, stk, gstk, gstride,
+                                    blocked, n_glass, pid, P.sh_state, P.sh_glass, P.overflow, stk, gstk, gstride,
                                     n_nodes, n_tris);
         bool leave;
         if (!SHADOW) {
@@ -305,7 +307,7 @@ __device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueS
             leave = best < 0;
         } else {
             if (blocked) P.sh_state[pid] = kShBlocked;
-            else if (n_glass >= 0) P.sh_cnt[pid] = n_glass;
+            else if (n_glass >= 0) P.sh_state[pid] = kShVisible | (n_glass << 4);
             leave = !blocked && t_exit < t_max;
         }
         if (leave) {
@@ -418,81 +420,67 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
 }
 
 // ---------------------------------------------------------------------------
-// shading: per-wavelength interaction, shadow ray, next ray
+// shading: the geometric part of the interaction at each hit
 // ---------------------------------------------------------------------------
+// One thread per path.  A single geometric path carries every wavelength
+// (panes do not bend rays, diffuse bounces are wavelength independent), so
+// this kernel decides the path and records each vertex; k_spectral applies the
+// per-wavelength factors afterwards.  Per hit (Sec. 4 inverse ray tracing):
+//  - emitter: counted (one-sided) if no diffuse vertex came since the camera or
+//    since the last glass reflection, then the path ends;
+//  - diffuse: one shadow ray toward the light (Eq. 3 for a point light, a
+//    uniform area sample of the parallelogram), then a cosine-weighted bounce;
+//  - glass pane: reflect with probability P_R = mean R / (mean R + mean T) of
+//    the pane's Fresnel slab terms (Eq. 1, Sec. 6), else transmit straight on.
 __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
-    __shared__ int s_cnt[kMaxCells], s_base[kMaxCells];
+    __shared__ int s_wcnt[(kShadeBlock / 64) * kMaxCells];
+    __shared__ float4 s_pane[kLdsPane];
+    const int n_pane = P.n_glass * P.nlp;
+    const bool pane_lds = n_pane <= kLdsPane;
+    if (pane_lds)
+        for (int i = threadIdx.x; i < n_pane; i += blockDim.x) s_pane[i] = P.pane[i];
+    __syncthreads();
+    const float4* pane = pane_lds ? s_pane : P.pane;
     const int pid = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = pid < P.N;
-    const int N = P.N;
     bool enq_e = false, enq_s = false;
     int cell_e = 0, cell_s = 0;
     f3 xo{0, 0, 0}, dn{0, 0, 1}, ws{0, 0, 1};
     float te = 0.0f, ts = 0.0f, r_sh = 0.0f;
     int prim = -1;
     if (valid) {
-        const long long g = P.g0 + pid;
-        const int s = P.s0 + (int)(g / P.WH);
-        const int p = (int)(g % P.WH);
-        const long long log_base = ((long long)p * P.spp_call + (s - P.s0)) * P.max_depth;
-
-        // 1) resolve the shadow ray of the previous vertex
-        const int sh = P.sh_state[pid];
-        if (sh != kShNone) {
-            const bool vis = sh == kShVisible;
-            if (P.shadow_log) P.shadow_log[log_base + P.depth - 2] = vis ? 1 : 0;
-            if (vis) {
-                const float gfac = P.nee_g[pid];
-                const int ng = min(P.sh_cnt[pid], kMaxGlass);
-                float2 gl[kMaxGlass];
-                for (int j = 0; j < ng; ++j) gl[j] = P.sh_glass[(size_t)pid * kMaxGlass + j];
-                const float* leL = P.le + (size_t)P.light_mat * P.nlp;
-                for (int l = 0; l < P.nl; ++l) {
-                    float tr = 1.0f;
-                    for (int j = 0; j < ng; ++j) {
-                        const int m = __float_as_int(gl[j].y);
-                        float Rg, Tg;
-                        pane_RT(P.mn[(size_t)m * P.nlp + l], P.mk[(size_t)m * P.nlp + l], P.mat_thick[m],
-                                P.lambda_nm[l], gl[j].x, Rg, Tg);
-                        tr *= Tg;
-                    }
-                    P.Lp[(size_t)l * N + pid] += P.beta[(size_t)l * N + pid] * leL[l] * gfac * tr;
-                }
-            }
-            P.sh_state[pid] = kShNone;
-        }
         uint32_t fl = P.flags[pid];
-        if (!P.final_pass && (fl & kAlive)) {
+        if (fl & kAlive) {
+            const uint32_t q = (uint32_t)(P.pb + pid);
+            const uint32_t qs = fdiv(q, P.fwh);
+            const int s = P.s0 + P.sb + (int)qs;
+            const int p = (int)(q - qs * (uint32_t)P.WH);
             const float2 h = P.hit[pid];
             prim = __float_as_int(h.y);
-            if (P.hit_log) P.hit_log[log_base + P.depth - 1] = prim;
+            if (P.hit_log) P.hit_log[((long long)p * P.spp_call + (s - P.s0)) * P.max_depth + P.depth - 1] = prim;
+            const bool last_depth = P.depth == P.max_depth;
+            int4 rec = make_int4(kVNone, 0, 0, 0);
+            int sh = kShNone;
             if (prim < 0) {
-                fl = 0;
+                fl = 0;  // no sky dome: a miss carries nothing
             } else {
                 const f3 o = xyz(P.ray_o[pid]), d = xyz(P.ray_d[pid]);
                 const f3 x = o + d * h.x;
                 const float4 pi = P.prim_info[prim];
                 const f3 ngm = xyz(pi);
-                const int m = __float_as_int(pi.w);
+                const int word = __float_as_int(pi.w);
+                const int m = word & kMatIdMask;  // material, or compact glass index for glass
+                const int typ = (word >> kMatTypeShift) & 3;
+                const int emits = (word & kMatEmits) ? kVEmits : 0;
                 const float cos_o = -dot3(ngm, d);
                 const f3 n = cos_o > 0.0f ? ngm : -ngm;
-                const int typ = P.mat_type[m];
-                const float* le = P.le + (size_t)m * P.nlp;
                 if (typ == kEmitter) {
-                    if ((fl & kCountE) && cos_o > 0.0f)
-                        for (int l = 0; l < P.nl; ++l) P.Lp[(size_t)l * N + pid] += P.beta[(size_t)l * N + pid] * le[l];
+                    rec.x = ((fl & kCountE) && cos_o > 0.0f) ? (kVEmit | kVLast | (m << kVIdShift)) : kVNone;
                     fl = 0;
                 } else if (typ == kDiffuse) {
-                    const float* rho = P.rho + (size_t)m * P.nlp;
-                    const bool emit = P.mat_has_le[m] != 0;
-                    for (int l = 0; l < P.nl; ++l) {
-                        const size_t i = (size_t)l * N + pid;
-                        const float b = P.beta[i];
-                        if (emit) P.Lp[i] += b * le[l];
-                        P.beta[i] = b * rho[l];
-                    }
                     const uint4 ub = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, (uint32_t)P.depth, 0u), P.key);
                     xo = x + n * kOffset;
+                    float gfac = 0.0f;
                     if (P.light_type != 0) {
                         f3 y{P.lp0[0], P.lp0[1], P.lp0[2]};
                         if (P.light_type == 1)
@@ -505,19 +493,18 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                         const float cy = P.light_type == 1 ? -dot3(f3{P.nL[0], P.nL[1], P.nL[2]}, om) : 1.0f;
                         if (cx > 0.0f && cy > 0.0f) {
                             // (rho/pi) Le cos_x cos_y / r^2 * A (area light); (rho/pi) I cos_x / r^2 (Eq. 3)
-                            const float gfac =
-                                (P.light_type == 1 ? cx * cy / r2 * P.light_area : cx / r2) * (1.0f / kPi);
-                            P.nee_g[pid] = gfac;
-                            P.sh_state[pid] = kShVisible;
-                            P.sh_cnt[pid] = 0;
+                            gfac = (P.light_type == 1 ? cx * cy / r2 * P.light_area : cx / r2) * (1.0f / kPi);
+                            sh = kShVisible;
                             ws = om;
                             r_sh = r;
                             cell_s = locate_ray(P.grid, xo, ws, ts);
                             enq_s = cell_s >= 0;
                         }
                     }
+                    rec = make_int4(kVDiffuse | (last_depth ? kVLast : 0) | emits | (m << kVIdShift), 0, 0,
+                                    __float_as_int(gfac));
                     fl &= ~kCountE;
-                    if (P.depth == P.max_depth) {
+                    if (last_depth) {
                         fl = 0;
                     } else {
                         const uint4 uc =
@@ -527,30 +514,24 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                     }
                 } else {  // glass pane
                     const float c = fabsf(dot3(d, ngm));
-                    const float thick = P.mat_thick[m];
                     float sumR = 0.0f, sumT = 0.0f;
+                    const float4* pm = pane + (size_t)m * P.nlp;
                     for (int l = 0; l < P.nl; ++l) {
                         float Rl, Tl;
-                        pane_RT(P.mn[(size_t)m * P.nlp + l], P.mk[(size_t)m * P.nlp + l], thick, P.lambda_nm[l], c, Rl,
-                                Tl);
+                        pane_RT(pm[l], c, Rl, Tl);
                         sumR += Rl;
                         sumT += Tl;
                     }
-                    if (!(sumR + sumT > 0.0f) || P.depth == P.max_depth) {
+                    if (!(sumR + sumT > 0.0f) || last_depth) {
+                        rec.x = kVGlassT | kVLast | (m << kVIdShift);
                         fl = 0;
                     } else {
                         const float PR = sumR / (sumR + sumT);
                         const uint4 ub =
                             philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, (uint32_t)P.depth, 0u), P.key);
                         const bool refl = u01(ub.z) < PR;
-                        const float wgt = refl ? 1.0f / PR : 1.0f / (1.0f - PR);
-                        for (int l = 0; l < P.nl; ++l) {
-                            float Rl, Tl;
-                            pane_RT(P.mn[(size_t)m * P.nlp + l], P.mk[(size_t)m * P.nlp + l], thick, P.lambda_nm[l], c,
-                                    Rl, Tl);
-                            const size_t i = (size_t)l * N + pid;
-                            P.beta[i] = P.beta[i] * ((refl ? Rl : Tl) * wgt);
-                        }
+                        rec = make_int4((refl ? kVGlassR : kVGlassT) | (m << kVIdShift), __float_as_int(c),
+                                        __float_as_int(PR), 0);
                         if (refl) {
                             dn = d - ngm * (2.0f * dot3(d, ngm));
                             fl |= kCountE;
@@ -563,6 +544,8 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                     }
                 }
             }
+            P.vrec[pid] = rec;
+            if ((rec.x & 7) == kVDiffuse) P.sh_state[pid] = sh;
             if (enq_e) {
                 P.ray_o[pid] = make_float4(xo.x, xo.y, xo.z, 0.0f);
                 P.ray_d[pid] = make_float4(dn.x, dn.y, dn.z, 0.0f);
@@ -574,20 +557,29 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
             P.flags[pid] = fl;
         }
     }
-    const int slot_e = block_append(enq_e, cell_e, P.ecnt, P.n_cells, s_cnt, s_base);
-    if (enq_e && slot_e < P.cap) {
-        const long long q = (long long)cell_e * P.cap + slot_e;
-        P.eqa[q] = make_float4(xo.x, xo.y, xo.z, te);
-        P.eqb[q] = make_float4(dn.x, dn.y, dn.z, __int_as_float(pid));
-        P.eqc[q] = make_int2(prim, __float_as_int(INFINITY));
+    // stage both rays in path order; k_route scatters them into the queues
+    const int rank_e = block_rank(enq_e, cell_e, P.n_cells, s_wcnt);
+    if (valid) {
+        P.se.tag[pid] = enq_e ? (cell_e | (rank_e << 16)) : -1;
+        if (enq_e) {
+            P.se.qa[pid] = make_float4(xo.x, xo.y, xo.z, te);
+            P.se.qb[pid] = make_float4(dn.x, dn.y, dn.z, __int_as_float(pid));
+            P.se.qc[pid] = make_int2(prim, __float_as_int(INFINITY));
+        }
     }
-    const int slot_s = block_append(enq_s, cell_s, P.scnt, P.n_cells, s_cnt, s_base);
-    if (enq_s && slot_s < P.cap) {
-        const long long q = (long long)cell_s * P.cap + slot_s;
-        P.sqa[q] = make_float4(xo.x, xo.y, xo.z, ts);
-        P.sqb[q] = make_float4(ws.x, ws.y, ws.z, __int_as_float(pid));
-        P.sqc[q] = make_int2(prim, __float_as_int(r_sh));
+    for (int c = threadIdx.x; c < P.n_cells; c += blockDim.x)
+        P.se.hist[(long long)c * P.n_blocks + blockIdx.x] = block_key_total(c, P.n_cells, s_wcnt);
+    const int rank_s = block_rank(enq_s, cell_s, P.n_cells, s_wcnt);
+    if (valid) {
+        P.ss.tag[pid] = enq_s ? (cell_s | (rank_s << 16)) : -1;
+        if (enq_s) {
+            P.ss.qa[pid] = make_float4(xo.x, xo.y, xo.z, ts);
+            P.ss.qb[pid] = make_float4(ws.x, ws.y, ws.z, __int_as_float(pid));
+            P.ss.qc[pid] = make_int2(prim, __float_as_int(r_sh));
+        }
     }
+    for (int c = threadIdx.x; c < P.n_cells; c += blockDim.x)
+        P.ss.hist[(long long)c * P.n_blocks + blockIdx.x] = block_key_total(c, P.n_cells, s_wcnt);
     const uint64_t me = __ballot(enq_e), ms = __ballot(enq_s);
     if (lane_id() == 0) {
         if (me) atomicAdd(&P.stats[kStatExtRays], (unsigned long long)popc64(me));
@@ -596,31 +588,194 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
 }
 
 // ---------------------------------------------------------------------------
-// accumulation and resolve
+// routing of staged rays into the per-cell queues (count -> scan -> scatter)
 // ---------------------------------------------------------------------------
-// acc[l][p] += path radiance of every sample of pixel p in the batch, in
-// increasing sample order (deterministic).
-__global__ void k_flush(int N, long long g0, int WH, int nl, const float* __restrict__ Lp, float* __restrict__ acc) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int npix = N < WH ? N : WH;
-    if (i >= npix) return;
-    const long long g = g0 + i;
-    const int p = (int)(g % WH);
-    for (int l = 0; l < nl; ++l) {
-        float a = acc[(size_t)l * WH + p];
-        for (long long gg = g; gg < g0 + N; gg += WH) a += Lp[(size_t)l * N + (size_t)(gg - g0)];
-        acc[(size_t)l * WH + p] = a;
+// One workgroup per (kind, cell): exclusive scan, in block order, of the
+// per-block counts; the cell's total becomes its queue length.
+__global__ __launch_bounds__(256) void k_route_scan(RouteParams P) {
+    __shared__ int s_part[256];
+    const int kind = blockIdx.x / P.n_cells, cell = blockIdx.x % P.n_cells;
+    if (!P.active[kind]) return;
+    int* h = P.st[kind].hist + (long long)cell * P.n_blocks;
+    const int nb = P.n_blocks;
+    const int per = (nb + 255) / 256;
+    const int b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
+    int local = 0;
+    for (int b = b0; b < b1; ++b) local += h[b];
+    s_part[threadIdx.x] = local;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int v = threadIdx.x >= o ? s_part[threadIdx.x - o] : 0;
+        __syncthreads();
+        s_part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = s_part[threadIdx.x] - local;
+    for (int b = b0; b < b1; ++b) {
+        const int v = h[b];
+        h[b] = run;
+        run += v;
+    }
+    if (threadIdx.x == 255) P.cnt[kind][cell] = s_part[255];
+}
+
+// One thread per path: copy each staged ray to cell * cap + offset of its
+// block + its rank in the block (stable: block order, then thread order).
+__global__ __launch_bounds__(kShadeBlock) void k_route(RouteParams P) {
+    const int pid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pid >= P.N) return;
+#pragma unroll
+    for (int kind = 0; kind < 2; ++kind) {
+        if (!P.active[kind]) continue;
+        const Stage& S = P.st[kind];
+        const int tag = S.tag[pid];
+        if (tag < 0) continue;
+        const int cell = tag & 0xFFFF, rank = tag >> 16;
+        const long long slot = (long long)S.hist[(long long)cell * P.n_blocks + blockIdx.x] + rank;
+        if (slot < 0 || slot >= P.cap || cell >= P.n_cells) continue;  // never expected: defence only
+        const long long q = (long long)cell * P.cap + slot;
+        P.qa[kind][q] = S.qa[pid];
+        P.qb[kind][q] = S.qb[pid];
+        P.qc[kind][q] = S.qc[pid];
     }
 }
 
+// ---------------------------------------------------------------------------
+// per-wavelength replay of the path histories and per-pixel accumulation
+// ---------------------------------------------------------------------------
+// One thread per (pixel p, group of 4 wavelengths): for every sample of p in
+// the batch (increasing sample order, so the FP32 sums are deterministic)
+// rebuild the path throughput beta(l) from the vertex records and add
+//   emission:  beta Le                       (emitters, diffuse emitters)
+//   shadow ray: beta rho Le_light g T_panes  (after the Lambert factor rho)
+// Glass vertices multiply beta by R/P_R or T/(1-P_R) (Eq. 1, Sec. 6 slab).
+// Vertices are replayed in predicated blocks of 4 so that all their records
+// and table values are loaded before the (sequential) arithmetic.
+constexpr int kVBlock = 4;
+
+__device__ __forceinline__ float4 f4mul(float4 a, float4 b) { return make_float4(a.x * b.x, a.y * b.y, a.z * b.z, a.w * b.w); }
+__device__ __forceinline__ float4 f4fma(float4 a, float4 b, float4 c) {
+    return make_float4(a.x * b.x + c.x, a.y * b.y + c.y, a.z * b.z + c.z, a.w * b.w + c.w);
+}
+__device__ __forceinline__ float4 f4scale(float4 a, float s) { return make_float4(a.x * s, a.y * s, a.z * s, a.w * s); }
+
+__global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
+    __shared__ float4 s_pane[kLdsPane];
+    const int n_pane = P.n_glass * P.nlp;
+    const bool pane_lds = n_pane <= kLdsPane;
+    if (pane_lds)
+        for (int i = threadIdx.x; i < n_pane; i += blockDim.x) s_pane[i] = P.pane[i];
+    __syncthreads();
+    const float4* pane = pane_lds ? s_pane : P.pane;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int npix = P.N < P.WH ? P.N : P.WH;
+    if (t >= (uint32_t)npix * (uint32_t)P.ngrp) return;
+    const int i = (int)fdiv(t, P.fgrp), grp = (int)t - i * P.ngrp;
+    const int l0 = 4 * grp;
+    const uint32_t q = (uint32_t)(P.pb + i);
+    const uint32_t qs = fdiv(q, P.fwh);
+    const int p = (int)(q - qs * (uint32_t)P.WH);
+    int s = P.s0 + P.sb + (int)qs;  // sample of the first path of p in the batch
+    const float4 leL = *reinterpret_cast<const float4*>(P.le + (size_t)P.light_mat * P.nlp + l0);
+    float4* accp = reinterpret_cast<float4*>(P.acc + (size_t)p * P.nlp + l0);
+    float4 a = *accp;
+    for (int pid = i; pid < P.N; pid += P.WH, ++s) {
+        float4 beta = make_float4(1.0f, 1.0f, 1.0f, 1.0f), L = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        bool live = true;
+        for (int d0 = 0; d0 < P.max_depth && live; d0 += kVBlock) {
+            int4 v[kVBlock];
+            int shs[kVBlock];
+#pragma unroll
+            for (int j = 0; j < kVBlock; ++j) {
+                const bool in = d0 + j < P.max_depth;
+                const size_t vi = (size_t)(in ? d0 + j : 0) * P.N + pid;  // always a valid address
+                v[j] = in ? P.vrec[vi] : make_int4(kVNone, 0, 0, 0);
+                shs[j] = in ? P.sh_state[vi] : kShNone;
+            }
+            // which records of the block belong to the path: only those are
+            // dereferenced (records past the path's end are stale or unwritten)
+            bool on[kVBlock];
+            bool run = live;
+#pragma unroll
+            for (int j = 0; j < kVBlock; ++j) {
+                run = run && (v[j].x & 7) != kVNone;
+                on[j] = run;
+                run = run && !(v[j].x & kVLast);
+            }
+            float4 rho[kVBlock], le[kVBlock];
+#pragma unroll
+            for (int j = 0; j < kVBlock; ++j) {
+                const int kind = v[j].x & 7;
+                const int m = min(max(v[j].x >> kVIdShift, 0), P.n_mats - 1);
+                const bool dif = on[j] && kind == kVDiffuse;
+                const bool emit = on[j] && (kind == kVEmit || (kind == kVDiffuse && (v[j].x & kVEmits)));
+                rho[j] = dif ? *reinterpret_cast<const float4*>(P.rho + (size_t)m * P.nlp + l0)
+                             : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+                le[j] = emit ? *reinterpret_cast<const float4*>(P.le + (size_t)m * P.nlp + l0)
+                             : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+#pragma unroll
+            for (int j = 0; j < kVBlock; ++j) {
+                const int x = v[j].x, kind = x & 7;
+                if (!on[j]) continue;
+                L = f4fma(beta, le[j], L);
+                if (kind == kVDiffuse) {
+                    beta = f4mul(beta, rho[j]);
+                    const float gfac = __int_as_float(v[j].w);
+                    if (gfac > 0.0f && (shs[j] & 15) == kShVisible) {
+                        float tr[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+                        const int ng = min(shs[j] >> 4, kMaxGlass);
+                        for (int k = 0; k < ng; ++k) {
+                            const size_t vi = (size_t)(d0 + j) * P.N + pid;
+                            const float2 gl = P.sh_glass[vi * kMaxGlass + k];
+                            const int gi = min(max(__float_as_int(gl.y), 0), P.n_glass - 1);
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                float Rg, Tg;
+                                pane_RT(pane[(size_t)gi * P.nlp + l0 + c], gl.x, Rg, Tg);
+                                tr[c] *= Tg;
+                            }
+                        }
+                        const float4 trv = make_float4(tr[0], tr[1], tr[2], tr[3]);
+                        L = f4fma(f4scale(f4mul(beta, leL), gfac), trv, L);
+                    }
+                } else if ((kind == kVGlassR || kind == kVGlassT) && !(x & kVLast)) {
+                    const int gi = min(max(x >> kVIdShift, 0), P.n_glass - 1);
+                    const float PR = __int_as_float(v[j].z);
+                    const float c = __int_as_float(v[j].y);
+                    float f[4];
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) {
+                        float Rl, Tl;
+                        pane_RT(pane[(size_t)gi * P.nlp + l0 + cc], c, Rl, Tl);
+                        f[cc] = kind == kVGlassR ? Rl * (1.0f / PR) : Tl * (1.0f / (1.0f - PR));
+                    }
+                    beta = f4mul(beta, make_float4(f[0], f[1], f[2], f[3]));
+                }
+            }
+            live = run;
+            if (P.shadow_log && grp == 0) {
+                int* sl = P.shadow_log + ((long long)p * P.spp_call + (s - P.s0)) * P.max_depth;
+#pragma unroll
+                for (int j = 0; j < kVBlock; ++j)
+                    if (on[j] && (v[j].x & 7) == kVDiffuse && __int_as_float(v[j].w) > 0.0f)
+                        sl[d0 + j] = (shs[j] & 15) == kShVisible ? 1 : 0;
+            }
+        }
+        a = make_float4(a.x + L.x, a.y + L.y, a.z + L.z, a.w + L.w);
+    }
+    *accp = a;
+}
+
 // FP64: mean over samples and XYZ = sum_l w_l cmf_l L_l
-__global__ void k_resolve(int WH, int nl, double inv_spp, const float* __restrict__ acc, const double* __restrict__ w,
-                          const double* __restrict__ cmf, double* spectral, double* xyz) {
+__global__ void k_resolve(int WH, int nl, int nlp, double inv_spp, const float* __restrict__ acc,
+                          const double* __restrict__ w, const double* __restrict__ cmf, double* spectral,
+                          double* xyz) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= WH) return;
     double X = 0.0, Y = 0.0, Z = 0.0;
     for (int l = 0; l < nl; ++l) {
-        const double v = (double)acc[(size_t)l * WH + p] * inv_spp;
+        const double v = (double)acc[(size_t)p * nlp + l] * inv_spp;
         if (spectral) spectral[(size_t)p * nl + l] = v;
         X += w[l] * cmf[3 * l] * v;
         Y += w[l] * cmf[3 * l + 1] * v;
@@ -636,6 +791,14 @@ __global__ void k_resolve(int WH, int nl, double inv_spp, const float* __restric
 __global__ void k_fill_i32(int* p, long long n, int v) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+__global__ void k_pane(int n, const float4* pc, const float* c, float2* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float R, T;
+    pane_RT(pc[i], c[i], R, T);
+    out[i] = make_float2(R, T);
 }
 
 __global__ void k_philox(int n, const uint4* ctr, uint2 key, uint4* out) {
@@ -674,7 +837,7 @@ static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + 
 
 hipError_t launch_camgen(const CamParams& p, hipStream_t st) {
     if (p.N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_camgen, dim3(blocks_for(p.N, 256)), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_camgen, dim3(blocks_for(p.N, kShadeBlock)), dim3(kShadeBlock), 0, st, p);
     return hipGetLastError();
 }
 
@@ -696,23 +859,39 @@ hipError_t launch_shade(const ShadeParams& p, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_flush(int N, long long g0, int WH, int nl, const float* Lp, float* acc, hipStream_t st) {
-    const int npix = N < WH ? N : WH;
-    if (npix <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flush, dim3(blocks_for(npix, 256)), dim3(256), 0, st, N, g0, WH, nl, Lp, acc);
+hipError_t launch_route(const RouteParams& p, hipStream_t st) {
+    if (p.N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_route_scan, dim3(2 * p.n_cells), dim3(256), 0, st, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_route, dim3(blocks_for(p.N, kShadeBlock)), dim3(kShadeBlock), 0, st, p);
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(int WH, int nl, double inv_spp, const float* acc, const double* w, const double* cmf,
-                          double* spectral, double* xyz, hipStream_t st) {
-    hipLaunchKernelGGL(k_resolve, dim3(blocks_for(WH, 256)), dim3(256), 0, st, WH, nl, inv_spp, acc, w, cmf, spectral,
-                       xyz);
+hipError_t launch_spectral(const SpectralParams& p, hipStream_t st) {
+    const int npix = p.N < p.WH ? p.N : p.WH;
+    const long long n = (long long)npix * p.ngrp;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spectral, dim3(blocks_for(n, 256)), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve(int WH, int nl, int nlp, double inv_spp, const float* acc, const double* w,
+                          const double* cmf, double* spectral, double* xyz, hipStream_t st) {
+    hipLaunchKernelGGL(k_resolve, dim3(blocks_for(WH, 256)), dim3(256), 0, st, WH, nl, nlp, inv_spp, acc, w, cmf,
+                       spectral, xyz);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_pane(int n, const float4* pc, const float* c, float2* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pane, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, pc, c, out);
     return hipGetLastError();
 }
 

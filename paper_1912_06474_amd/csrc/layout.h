@@ -10,7 +10,13 @@
 //               link < 0 leaf starting at triangle ~link
 //          Nodes of each cell are stored breadth-first (root first).
 //   tris   float4[3 * n_refs]   48 B per triangle reference, in leaf order:
-//          (v0, prim), (e1, meta), (e2, mat) with meta = type | last_in_leaf << 2
+//          (v0, prim), (e1, meta), (e2, glass index) with meta = type | last_in_leaf << 2
+//          and the compact glass-material index (-1 for other materials)
+//   prim_info float4[T]          (unit geometric normal, mat word) with
+//          mat word = id | type << 24 | emits << 26, id = material index, or
+//          the compact glass index for glass
+//   pane   float4[n_glass][nlp]  per glass material and wavelength: the pane
+//          constants (n^2 - k^2, 2 n k, 1 / n^2, 4 pi k d / lambda)
 //   cell_root int[n_cells]      root node of each cell (always an inner node)
 //   planes float[nx+1 + ny+1 + nz+1]  cell boundary planes per axis
 //
@@ -18,9 +24,13 @@
 //   qa float4 (o.x, o.y, o.z, t_enter)   qb float4 (d.x, d.y, d.z, path id)
 //   qc int2   (excluded prim, t_max bits)
 // Path state, indexed by path id within a batch (N paths):
-//   ray_o / ray_d float4, hit float2 (t, prim), flags u32, nee_g float,
-//   sh_state / sh_cnt int, sh_glass float2[4 per path] (cos, mat),
-//   beta / Lp float[n_lambda_pad][N] (wavelength-major, coalesced per lambda).
+//   ray_o / ray_d float4, hit float2 (t, prim), flags u32.
+// Path history, indexed [depth][path]: one geometric path carries every
+// wavelength, so the per-wavelength factors are not stored per bounce; each
+// surface vertex leaves a record that k_spectral replays once per wavelength:
+//   vrec int4     (kind | last << 3 | emits << 4 | id << 5, glass cos, glass P_R, NEE g)
+//   sh_state int  shadow ray of that vertex: none / visible (| panes << 4) / blocked
+//   sh_glass float2[kMaxGlass] (cos, glass index) of the panes the shadow ray crossed
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,10 +48,30 @@ constexpr int kMaxGlass = 4;      // pane crossings recorded per shadow segment
 constexpr int kMaxCells = 512;
 constexpr int kShadeBlock = 256;
 
+constexpr int kMaxBatch = 1 << 24;  // paths per batch (32-bit path arithmetic in the kernels)
+
+// unsigned division by a launch-invariant divisor d (Hacker's Delight,
+// round-up multiplier): n / d = (umulhi(n, m) + n) >> l for n < 2^31
+struct FastDiv {
+    uint32_t d, m, l;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    const uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+    return FastDiv{d, (uint32_t)m, l};
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) { return (__umulhi(n, f.m) + n) >> f.l; }
+
 enum : int { kDiffuse = 0, kGlass = 1, kEmitter = 2 };
 enum : uint32_t { kAlive = 1u, kCountE = 2u };
-enum : int { kShNone = 0, kShVisible = 1, kShBlocked = 2 };
+enum : int { kShNone = 0, kShVisible = 1, kShBlocked = 2 };  // | pane count << 4 when visible
 constexpr int kLastInLeaf = 4;
+// vertex record kinds
+enum : int { kVNone = 0, kVDiffuse = 1, kVGlassR = 2, kVGlassT = 3, kVEmit = 4 };
+constexpr int kVLast = 8, kVEmits = 16, kVIdShift = 5;
+constexpr int kMatTypeShift = 24, kMatEmits = 1 << 26, kMatIdMask = (1 << 24) - 1;
+constexpr int kLdsPane = 512;     // pane constants staged in LDS when n_glass * nlp fits
 
 enum Stat : int {
     kStatExtRays = 0,
@@ -73,6 +103,17 @@ struct QueueSet {
     int* cnt_out;
 };
 
+// rays produced in path order (by camgen / shade), before routing into the
+// per-cell queues: record + tag (cell | rank-in-block << 16, or -1), plus
+// per-block histograms hist[cell][block] (blocks of kShadeBlock paths)
+struct Stage {
+    float4* qa;
+    float4* qb;
+    int2* qc;
+    int* tag;
+    int* hist;
+};
+
 struct TraceParams {
     QueueSet q[2];        // [0] closest-hit rays, [1] shadow rays
     int active[2];        // which of the two sets holds work in this sweep
@@ -85,9 +126,8 @@ struct TraceParams {
     const float4* prim_info;  // (unit geometric normal, mat bits)
     // closest-hit output
     float2* hit;
-    // shadow outputs
+    // shadow outputs (arrays of the shadow rays' depth)
     int* sh_state;
-    int* sh_cnt;
     float2* sh_glass;
     int* overflow;
     int* gstack;          // spill stack: (kStack - kLdsStack) entries per thread of the grid
@@ -96,81 +136,94 @@ struct TraceParams {
 
 struct ShadeParams {
     int N;                 // paths in this batch
-    long long g0;          // first global path index of the batch
+    int pb, sb;            // pixel and sample of the batch's first path
+    FastDiv fwh;           // division by W * H
     int W, WH;
     int s0;                // first sample index of this call
     int spp_call;
     int depth, max_depth;
-    int final_pass;        // 1: only resolve the pending shadow rays
     uint2 key;
     // path state
     uint32_t* flags;
     float4* ray_o;
     float4* ray_d;
     float2* hit;
-    float* beta;
-    float* Lp;
-    float* nee_g;
+    // history of this depth
+    int4* vrec;
     int* sh_state;
-    int* sh_cnt;
-    const float2* sh_glass;
     // scene
     const float4* prim_info;
-    const int* mat_type;
-    const int* mat_has_le;
-    const float* mat_thick;
-    const float* rho;      // [M][nlp]
-    const float* mn;
-    const float* mk;
-    const float* le;
-    const float* lambda_nm;
+    const float4* pane;    // [n_glass][nlp]
+    int n_glass;
     int nl, nlp;
     int light_type;
     float lp0[3], le1[3], le2[3], nL[3];
     float light_area;
-    int light_mat;
     GridParams grid;
     int n_cells;
-    // queues written
-    float4* eqa;
-    float4* eqb;
-    int2* eqc;
-    int* ecnt;
-    float4* sqa;
-    float4* sqb;
-    int2* sqc;
-    int* scnt;
-    long long cap;
+    Stage se, ss;          // next closest-hit rays, shadow rays
+    int n_blocks;          // histogram stride (blocks per batch)
     int* hit_log;
-    int* shadow_log;
     unsigned long long* stats;
 };
 
 struct CamParams {
     int N;
-    long long g0;
+    int pb, sb;
+    FastDiv fwh;
     int W, H, WH;
     int s0;
     uint2 key;
     int ortho;
     float eye[3], fwd[3], right[3], up[3];
     float tan_half, aspect, ortho_half_h;
-    int nlp;
     uint32_t* flags;
     float4* ray_o;
     float4* ray_d;
     float2* hit;
-    float* beta;
-    float* Lp;
-    int* sh_state;
     GridParams grid;
     int n_cells;
-    float4* eqa;
-    float4* eqb;
-    int2* eqc;
-    int* ecnt;
-    long long cap;
+    Stage se;
+    int n_blocks;
     unsigned long long* stats;
+};
+
+// scan of the block histograms and scatter of staged rays into the queues
+struct RouteParams {
+    int N;
+    int n_blocks;
+    int n_cells;
+    long long cap;
+    int active[2];
+    Stage st[2];
+    float4* qa[2];
+    float4* qb[2];
+    int2* qc[2];
+    int* cnt[2];           // per-cell totals of the routed queues
+};
+
+// replay of the path histories, one thread per (pixel, wavelength)
+struct SpectralParams {
+    int N;
+    int pb, sb;
+    FastDiv fwh;
+    int ngrp;              // wavelength groups of 4 (nlp / 4)
+    FastDiv fgrp;
+    int WH;
+    int s0, spp_call;
+    int max_depth;
+    const int4* vrec;      // [D][N]
+    const int* sh_state;   // [D][N]
+    const float2* sh_glass;// [D][N][kMaxGlass]
+    const float4* pane;    // [n_glass][nlp]
+    int n_glass;
+    int n_mats;
+    const float* rho;      // [M][nlp]
+    const float* le;
+    int nl, nlp;
+    int light_mat;
+    float* acc;            // [WH][nlp]
+    int* shadow_log;
 };
 
 }  // namespace sdd

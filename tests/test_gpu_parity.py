@@ -58,6 +58,23 @@ def test_device_philox_equals_oracle_on_many_counters(tracer):
         assert list(out[i]) == list(ora.philox(ctr[i], key))
 
 
+def test_device_pane_terms_vs_oracle(tracer):
+    rng = np.random.default_rng(4)
+    n = 4000
+    params = np.column_stack([rng.uniform(1.2, 2.4, n), 10 ** rng.uniform(-8, -0.3, n), rng.uniform(0.0, 0.01, n),
+                              rng.uniform(380, 780, n), rng.uniform(0.0, 1.0, n)]).astype(np.float32)
+    params[:50, 1] = 0.0                       # lossless
+    params[50:100, 4] = 1.0                    # normal incidence
+    params[100:150, 4] = 0.0                   # grazing
+    params[150:200, 0], params[150:200, 1] = 0.2, 3.0   # conductor-like
+    R, T = tracer.debug_pane(params)
+    for i in range(n):
+        q = [float(x) for x in params[i]]
+        Ro, To = ora.slab(*q)
+        assert abs(R[i] - Ro) <= 2e-6 + 2e-5 * Ro, (i, q, R[i], Ro)
+        assert abs(T[i] - To) <= 2e-6 + 2e-5 * To, (i, q, T[i], To)
+
+
 @pytest.mark.parametrize("grid", [(1, 1, 1), (2, 2, 1), (4, 4, 2), (3, 5, 2)])
 def test_closest_hits_vs_brute_force(tracer, grid):
     sc = sg.tiny_room()
