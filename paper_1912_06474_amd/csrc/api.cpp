@@ -108,7 +108,7 @@ struct sdd_ctx {
     long long device_bytes = 0;
 
     // host stats
-    long long batches = 0, launches_trace = 0;
+    long long batches = 0, launches_trace = 0, cam_rays = 0;
     double ms[4] = {0, 0, 0, 0};
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
@@ -435,7 +435,7 @@ sdd_status run_sweeps(sdd_ctx* c, int ext_phase, int sh_phase, long long cap, bo
 
 // scatter the staged rays of a batch into the per-cell queues: closest-hit
 // rays to buffer 0 (counters of ext_phase), shadow rays to buffer 2
-sdd_status route(sdd_ctx* c, int N, long long cap, int ext_phase, int sh_phase, bool timing) {
+sdd_status route(sdd_ctx* c, int N, long long cap, int ext_phase, int sh_phase, bool count_ext, bool timing) {
     RouteParams r{};
     r.N = N;
     r.n_blocks = (N + kShadeBlock - 1) / kShadeBlock;
@@ -452,6 +452,10 @@ sdd_status route(sdd_ctx* c, int N, long long cap, int ext_phase, int sh_phase, 
     r.qc[1] = c->qc[2];
     r.cnt[0] = ext_phase >= 0 ? counts_at(c, ext_phase, 0) : nullptr;
     r.cnt[1] = sh_phase >= 0 ? counts_at(c, sh_phase, 0) : nullptr;
+    // camera rays are counted on the host (every one is cast, also one that misses the grid)
+    r.count[0] = count_ext ? 1 : 0;
+    r.count[1] = 1;
+    r.stats = c->d_stats;
     Timer tm(c, timing, 3);
     HIP_TRY(c, launch_route(r, c->stream));
     return SDD_OK;
@@ -765,7 +769,8 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
             Timer tm(c, timing, 3);
             HIP_TRY(c, launch_camgen(cp, c->stream));
         }
-        st = route(c, N, cap, ph_ext(1), -1, timing);
+        c->cam_rays += N;
+        st = route(c, N, cap, ph_ext(1), -1, false, timing);
         if (st != SDD_OK) return st;
         ShadeParams sp{};
         sp.N = N;
@@ -813,7 +818,7 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
                 Timer tm(c, timing, 2);
                 HIP_TRY(c, launch_shade(sp, c->stream));
             }
-            st = route(c, N, cap, d < D ? ph_ext(d + 1) : -1, ph_sh(d), timing);
+            st = route(c, N, cap, d < D ? ph_ext(d + 1) : -1, ph_sh(d), true, timing);
             if (st != SDD_OK) return st;
         }
         st = run_sweeps(c, -1, ph_sh(D), cap, count, timing, D, N);
@@ -914,7 +919,7 @@ sdd_status sdd_get_stats(sdd_ctx* c, sdd_stats* out) {
     int ovf = 0;
     HIP_TRY(c, hipMemcpy(&ovf, c->d_overflow, sizeof(int), hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof(*out));
-    out->ext_rays = (int64_t)s[kStatExtRays];
+    out->ext_rays = (int64_t)s[kStatExtRays] + c->cam_rays;
     out->shadow_rays = (int64_t)s[kStatShadowRays];
     out->ext_cell_visits = (int64_t)s[kStatExtVisits];
     out->shadow_cell_visits = (int64_t)s[kStatShadowVisits];
@@ -946,6 +951,7 @@ sdd_status sdd_reset_stats(sdd_ctx* c) {
     HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, sizeof(unsigned long long) * kStatCount, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->batches = 0;
+    c->cam_rays = 0;
     c->launches_trace = 0;
     for (double& m : c->ms) m = 0.0;
     return SDD_OK;

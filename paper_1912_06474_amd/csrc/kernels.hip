@@ -118,8 +118,6 @@ __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
     }
     for (int c = threadIdx.x; c < P.n_cells; c += blockDim.x)
         P.se.hist[(long long)c * P.n_blocks + blockIdx.x] = block_key_total(c, P.n_cells, s_wcnt);
-    const uint64_t m = __ballot(valid);
-    if (lane_id() == 0 && m) atomicAdd(&P.stats[kStatExtRays], (unsigned long long)popc64(m));
 }
 
 // ---------------------------------------------------------------------------
@@ -255,7 +253,7 @@ __device__ __forceinline__ void traverse(const float4* __restrict__ nodes, const
 // neighbouring cell's queue.  Reached by all lanes of the wave together.
 template <bool SHADOW, bool COUNT>
 __device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueSet& Q, int cell, int idx, bool active,
-                                              int* stk, int* gstk, int gstride, int& n_visits, int& n_nodes,
+                                              int* stk, int* gstk, int gstride, int& n_nodes,
                                               int& n_tris) {
     const GridParams& g = P.grid;
     const int ix = cell % g.nx, iy = (cell / g.nx) % g.ny, iz = cell / (g.nx * g.ny);
@@ -269,7 +267,6 @@ __device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueS
     float4 qa = make_float4(0, 0, 0, 0), qb = make_float4(0, 0, 0, 0);
     int2 qc = make_int2(0, 0);
     if (active) {
-        ++n_visits;
         const long long q = (long long)cell * P.cap + idx;
         qa = Q.qa_in[q];
         qb = Q.qb_in[q];
@@ -372,12 +369,18 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
     __syncthreads();
     const int total = s_pref[E];
     if (total == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x < 2 && P.active[threadIdx.x]) {
+        // every queued ray is traversed exactly once in this sweep
+        unsigned long long n = 0;
+        for (int c = 0; c < G; ++c) n += (unsigned long long)min((long long)P.q[threadIdx.x].cnt_in[c], P.cap);
+        if (n) atomicAdd(&P.stats[threadIdx.x == 0 ? kStatExtVisits : kStatShadowVisits], n);
+    }
     const int lane = lane_id();
     int* stk = s_stack + threadIdx.x;
     const int gstride = gridDim.x * kTraceBlock;  // entries of one level are contiguous over the grid
     int* gstk = P.gstack + blockIdx.x * kTraceBlock + threadIdx.x;
     const int xcd = blockIdx.x % kXcd;
-    int n_nodes = 0, n_tris = 0, n_vis[2] = {0, 0};
+    int n_nodes = 0, n_tris = 0;
 
     // static XCD-aware striding: the waves of XCD x walk part x of the chunk
     // list round-robin (no atomics, so empty and near-empty sweeps cost only
@@ -399,16 +402,11 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
         const int idx = (chunk - s_pref[e]) * kChunk + lane;
         const bool active = idx < min((long long)P.q[kind].cnt_in[cell], P.cap);
         if (kind == 0)
-            process_chunk<false, COUNT>(P, P.q[0], cell, idx, active, stk, gstk, gstride, n_vis[0], n_nodes,
+            process_chunk<false, COUNT>(P, P.q[0], cell, idx, active, stk, gstk, gstride, n_nodes,
                                         n_tris);
         else
-            process_chunk<true, COUNT>(P, P.q[1], cell, idx, active, stk, gstk, gstride, n_vis[1], n_nodes,
+            process_chunk<true, COUNT>(P, P.q[1], cell, idx, active, stk, gstk, gstride, n_nodes,
                                        n_tris);
-    }
-    const int v0 = wave_sum(n_vis[0]), v1 = wave_sum(n_vis[1]);
-    if (lane == 0) {
-        if (v0) atomicAdd(&P.stats[kStatExtVisits], (unsigned long long)v0);
-        if (v1) atomicAdd(&P.stats[kStatShadowVisits], (unsigned long long)v1);
     }
     if (COUNT) {
         const int nn = wave_sum(n_nodes), nt = wave_sum(n_tris);
@@ -580,11 +578,6 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
     }
     for (int c = threadIdx.x; c < P.n_cells; c += blockDim.x)
         P.ss.hist[(long long)c * P.n_blocks + blockIdx.x] = block_key_total(c, P.n_cells, s_wcnt);
-    const uint64_t me = __ballot(enq_e), ms = __ballot(enq_s);
-    if (lane_id() == 0) {
-        if (me) atomicAdd(&P.stats[kStatExtRays], (unsigned long long)popc64(me));
-        if (ms) atomicAdd(&P.stats[kStatShadowRays], (unsigned long long)popc64(ms));
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -616,7 +609,11 @@ __global__ __launch_bounds__(256) void k_route_scan(RouteParams P) {
         h[b] = run;
         run += v;
     }
-    if (threadIdx.x == 255) P.cnt[kind][cell] = s_part[255];
+    if (threadIdx.x == 255) {
+        P.cnt[kind][cell] = s_part[255];
+        if (s_part[255] && P.count[kind])
+            atomicAdd(&P.stats[kind == 0 ? kStatExtRays : kStatShadowRays], (unsigned long long)s_part[255]);
+    }
 }
 
 // One thread per path: copy each staged ray to cell * cap + offset of its

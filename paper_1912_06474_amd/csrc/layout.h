@@ -200,6 +200,8 @@ struct RouteParams {
     float4* qb[2];
     int2* qc[2];
     int* cnt[2];           // per-cell totals of the routed queues
+    int count[2];          // add the routed rays of this kind to the ray statistics
+    unsigned long long* stats;
 };
 
 // replay of the path histories, one thread per (pixel, wavelength)
