@@ -50,7 +50,7 @@ struct sdd_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int n_cu = 256;
-    int trace_grid = 0;
+    int trace_grid = 0, trace_grid_max = 0;
 
     // scene (host copies used by the builder)
     bool has_scene = false, has_bvh = false;
@@ -120,6 +120,11 @@ namespace {
 sdd_status fail(sdd_ctx* c, sdd_status st, const std::string& msg) {
     if (c) c->err = msg;
     return st;
+}
+
+// trace workgroups: as many as stay resident on every CU, a multiple of the XCD count
+int trace_grid_for(const sdd_ctx* c, int n_cells) {
+    return std::max(kXcd, (c->n_cu * trace_blocks_per_cu(n_cells) / kXcd) * kXcd);
 }
 
 sdd_status hip_fail(sdd_ctx* c, hipError_t e, const char* what) {
@@ -481,10 +486,12 @@ sdd_status sdd_create(int hip_device, void* hip_stream, sdd_ctx** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
     c->stream = (hipStream_t)hip_stream;  // NULL: the null stream, ordered with other default-stream work
-    const int per_cu = trace_blocks_per_cu();
-    c->trace_grid = std::max(kXcd, (c->n_cu * per_cu / kXcd) * kXcd);
+    // the spill stack is sized for the largest trace grid (one subdomain); build_bvh
+    // sets the grid for its subdomain count, never above this
+    c->trace_grid_max = trace_grid_for(c, 1);
+    c->trace_grid = c->trace_grid_max;
     if (dalloc(c, &c->d_overflow, 1) != SDD_OK || dalloc(c, &c->d_stats, kStatCount) != SDD_OK ||
-        dalloc(c, &c->d_gstack, (size_t)c->trace_grid * kTraceBlock * (kStack - kLdsStack)) != SDD_OK) {
+        dalloc(c, &c->d_gstack, (size_t)c->trace_grid_max * kTraceBlock * (kStack - kLdsStack)) != SDD_OK) {
         sdd_destroy(c);
         return SDD_ERR_OOM;
     }
@@ -642,6 +649,7 @@ sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->G = d->nx * d->ny * d->nz;
     c->S = d->nx + d->ny + d->nz - 2;
+    c->trace_grid = std::min(c->trace_grid_max, trace_grid_for(c, c->G));
     GridParams& gp = c->grid;
     gp.planes = c->d_planes;
     gp.nx = d->nx;

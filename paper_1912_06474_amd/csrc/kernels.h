@@ -9,7 +9,7 @@ namespace sdd {
 
 hipError_t launch_camgen(const CamParams& p, hipStream_t st);
 hipError_t launch_trace(const TraceParams& p, bool count, int grid_blocks, hipStream_t st);
-int trace_blocks_per_cu();
+int trace_blocks_per_cu(int n_cells);  // resident trace workgroups per CU for a grid of n_cells subdomains
 hipError_t launch_shade(const ShadeParams& p, hipStream_t st);
 hipError_t launch_route(const RouteParams& p, hipStream_t st);
 hipError_t launch_spectral(const SpectralParams& p, hipStream_t st);

@@ -335,7 +335,7 @@ __device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueS
 // workgroups of XCD x (consecutive cells share that XCD's L2).
 template <bool COUNT>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
-    __shared__ int s_pref[2 * kMaxCells + 1];
+    extern __shared__ int s_pref[];  // 2 * n_cells + 1 entries (dynamic, so small grids keep occupancy)
     __shared__ int s_stack[kLdsStack * kTraceBlock];
     const int G = P.n_cells;
     const int E = 2 * G;  // entry e = 2 * cell + kind
@@ -838,15 +838,20 @@ hipError_t launch_camgen(const CamParams& p, hipStream_t st) {
     return hipGetLastError();
 }
 
+static size_t trace_lds_bytes(int n_cells) { return sizeof(int) * (size_t)(2 * n_cells + 1); }
+
 hipError_t launch_trace(const TraceParams& p, bool count, int grid_blocks, hipStream_t st) {
-    if (count) hipLaunchKernelGGL((k_trace<true>), dim3(grid_blocks), dim3(kTraceBlock), 0, st, p);
-    else hipLaunchKernelGGL((k_trace<false>), dim3(grid_blocks), dim3(kTraceBlock), 0, st, p);
+    const size_t lds = trace_lds_bytes(p.n_cells);
+    if (count) hipLaunchKernelGGL((k_trace<true>), dim3(grid_blocks), dim3(kTraceBlock), lds, st, p);
+    else hipLaunchKernelGGL((k_trace<false>), dim3(grid_blocks), dim3(kTraceBlock), lds, st, p);
     return hipGetLastError();
 }
 
-int trace_blocks_per_cu() {
+int trace_blocks_per_cu(int n_cells) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false>, kTraceBlock, 0) != hipSuccess) return 4;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<false>, kTraceBlock, trace_lds_bytes(n_cells)) !=
+        hipSuccess)
+        return 4;
     return nb > 0 ? nb : 1;
 }
 
