@@ -24,6 +24,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 REC_BYTES = 40                 # queue record: (o, t_enter) 16 B + (d, path) 16 B + (excl, t_max) 8 B
 HIT_BYTES = 8
+COPY_FLOATS = 1 << 28          # plain device copy of 1 GiB, for scaling FETCH_SIZE / WRITE_SIZE
+
+# HBM bytes of k_trace measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on
+# the room-scale workload, valid only while the kernel sources are unchanged
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_traffic_furnished_room_512x512_16spp.txt")
+TRACE_SOURCES = ["kernels.hip", "layout.h", "device_math.h"]
 
 
 def log(*a):
@@ -35,6 +41,45 @@ WORKLOADS = {
                            grid=(4, 4, 2)),
     "tiny_room": dict(scene=("tiny_room", dict(seed=0, n_lambda=16)), W=64, H=64, spp=1, D=4, grid=(2, 2, 1)),
 }
+
+
+def trace_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRACE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1912_06474_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, grid):
+    """HBM bytes per k_trace launch from the committed counter summary, or None
+    if it was taken on other kernel sources or another workload."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(l.strip().split("=", 1) for l in fh if "=" in l and not l.lstrip().startswith("#"))
+    except OSError:
+        return None
+    if kv.get("source_sha256") != trace_source_hash():
+        return None
+    if kv.get("workload") != workload or kv.get("grid") != "x".join(map(str, grid)):
+        return None
+    fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+    write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
+    return (fetch + write) * 1024.0
+
+
+def copy_calibration():
+    """A plain device copy of known size: what FETCH_SIZE / WRITE_SIZE read for it
+    scales the counters of the trace kernel to bytes."""
+    import torch
+    a = torch.ones(COPY_FLOATS, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": 4 * COPY_FLOATS, "launches": 3}))
 
 
 def cpu_baseline(scene, wl, target_s=15.0):
@@ -80,11 +125,17 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--count-work", action="store_true",
                     help="trace one extra (untimed) frame counting BVH node visits and triangle tests")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
 
@@ -114,9 +165,10 @@ def main():
 
     step = 0
 
-    def frame(flags_time=False):
+    def frame():
         nonlocal step
-        tr.trace_spectral(cam, W, H, spp, D, sample_offset=step * spp, render_id=0, time_kernels=flags_time)
+        # every launch is bracketed by HIP events on the library's stream
+        tr.trace_spectral(cam, W, H, spp, D, sample_offset=step * spp, render_id=0, time_kernels=True)
         tr.resolve_image(0, W, H, spectral=True, xyz=True)
         step += 1
 
@@ -125,7 +177,7 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] warmup {i + 1}/{args.warmup}")
 
-    # timed region: value
+    # timed region
     tr.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -138,26 +190,21 @@ def main():
     rays = st["ext_rays"] + st["shadow_rays"]
     value = rays * nl / dt
 
-    # second pass, same work, every launch bracketed by HIP events on the library's stream
-    tr.reset_stats()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for i in range(args.steps):
-        frame(flags_time=True)
-    torch.cuda.synchronize()
-    dt_ev = time.perf_counter() - t1
-    se = tr.stats()
-    launches_ext = se["launches_trace"] / 2  # half the sweeps are closest-hit, half shadow
-    ms_ext = se["ms_trace_ext"]
-    visits = se["ext_cell_visits"]
-    ext_rays = se["ext_rays"]
-    crossings = max(0, visits - ext_rays)
-    alg_bytes = REC_BYTES * visits + REC_BYTES * crossings + HIT_BYTES * ext_rays
-    achieved = alg_bytes / (ms_ext * 1e-3) / 1e9 if ms_ext > 0 else 0.0
-    kern_ms = {"trace_ext": se["ms_trace_ext"], "trace_shadow": se["ms_trace_shadow"], "shade": se["ms_shade"],
-               "other": se["ms_other"]}
-    log(f"[bench] timed {dt:.3f} s; event pass {dt_ev:.3f} s; kernel ms {kern_ms}")
-    log(f"[bench] stats {json.dumps(se)}")
+    # roofline of k_trace over the timed region: every closest-hit and shadow
+    # sweep; per cell visit a 40 B queue record is read, per crossing a 40 B
+    # record is written to the neighbour's queue, per extension ray an 8 B hit
+    launches = max(1, st["launches_trace"])
+    ms_trace = st["ms_trace_ext"] + st["ms_trace_shadow"]
+    visits = st["ext_cell_visits"] + st["shadow_cell_visits"]
+    crossings = max(0, visits - rays)
+    alg_bytes = REC_BYTES * visits + REC_BYTES * crossings + HIT_BYTES * st["ext_rays"]
+    avg_ms = ms_trace / launches
+    achieved = alg_bytes / launches / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = measured_traffic(args.workload, wl["grid"])
+    kern_ms = {"trace_ext": st["ms_trace_ext"], "trace_shadow": st["ms_trace_shadow"], "shade": st["ms_shade"],
+               "other": st["ms_other"]}
+    log(f"[bench] timed {dt:.3f} s; kernel ms {kern_ms}")
+    log(f"[bench] stats {json.dumps(st)}")
 
     res = {
         "metric": "spectral path samples/s (rays x lambda/s), plain tracer, one MI355X",
@@ -176,10 +223,10 @@ def main():
                                f"depth {D}, grid {'x'.join(map(str, wl['grid']))}",
                    "paths_per_step": W * H * spp, "rays_per_step": rays / args.steps,
                    "path_samples_lambda_per_s": W * H * spp * nl * args.steps / dt},
-        "roofline": {"bound": "hbm", "kernel": "k_trace<closest-hit>", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": alg_bytes / max(1.0, launches_ext),
-                     "avg_launch_ms": ms_ext / max(1.0, launches_ext)},
+        "roofline": {"bound": "hbm", "kernel": "k_trace", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes / launches, "avg_launch_ms": avg_ms,
+                     "launches": launches},
         "kernel_ms_per_step": {k: v / args.steps for k, v in kern_ms.items()},
         "build_bvh_s": build_s,
     }

@@ -59,11 +59,13 @@ struct sdd_ctx {
     std::vector<int32_t> tris, tri_mat, mat_type, glass_of, mat_emits;
     int n_glass = 0;
     int light_type = 0, light_mat = -1;
-    float lp0[3] = {0, 0, 0}, le1[3] = {0, 0, 0}, le2[3] = {0, 0, 0}, nL[3] = {0, 0, 0};
-    float light_area = 0.0f;
+    // light geometry in double (FP32 scene values widened exactly; normal and area in double)
+    double lp0[3] = {0, 0, 0}, le1[3] = {0, 0, 0}, le2[3] = {0, 0, 0}, nL[3] = {0, 0, 0};
+    double light_area = 0.0;
 
     // device scene
     float4* d_prim_info = nullptr;
+    float4* d_prim_v = nullptr;  // [T][3] triangle vertices (w unused), for FP64 shading geometry
     float4* d_pane = nullptr;  // [n_glass][nlp] pane constants
     float* d_rho = nullptr;
     float* d_le = nullptr;
@@ -188,6 +190,7 @@ struct DeviceGuard {
 
 void free_scene(sdd_ctx* c) {
     dfree(c, c->d_prim_info);
+    dfree(c, c->d_prim_v);
     dfree(c, c->d_pane);
     dfree(c, c->d_rho);
     dfree(c, c->d_le);
@@ -569,11 +572,11 @@ sdd_status sdd_load_scene(sdd_ctx* c, const sdd_scene_desc* s) {
         const double e2[3] = {s->light_e2[0], s->light_e2[1], s->light_e2[2]};
         const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
         const double a = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        for (int k = 0; k < 3; ++k) c->nL[k] = (float)(n[k] / a);
-        c->light_area = (float)a;
+        for (int k = 0; k < 3; ++k) c->nL[k] = n[k] / a;
+        c->light_area = a;
     } else {
-        c->nL[0] = c->nL[1] = c->nL[2] = 0.0f;
-        c->light_area = 0.0f;
+        c->nL[0] = c->nL[1] = c->nL[2] = 0.0;
+        c->light_area = 0.0;
     }
     // per-material tables padded to nlp wavelengths; glass materials get a
     // compact index and their pane constants (double, rounded once)
@@ -602,8 +605,15 @@ sdd_status sdd_load_scene(sdd_ctx* c, const sdd_scene_desc* s) {
                   c->glass_of.data(), c->mat_emits.data(), 1, 1, 1, 4, 16};
     std::vector<HostF4> info;
     triangle_info(bi, info);
+    std::vector<float4> prim_v(3 * (size_t)c->T);
+    for (int i = 0; i < c->T; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const float* v = c->verts.data() + 3 * (size_t)c->tris[3 * (size_t)i + j];
+            prim_v[3 * (size_t)i + j] = make_float4(v[0], v[1], v[2], 0.0f);
+        }
     sdd_status st;
     if ((st = upload(c, &c->d_prim_info, reinterpret_cast<const float4*>(info.data()), info.size())) != SDD_OK ||
+        (st = upload(c, &c->d_prim_v, prim_v.data(), prim_v.size())) != SDD_OK ||
         (st = upload(c, &c->d_pane, pane.data(), pane.size())) != SDD_OK ||
         (st = upload(c, &c->d_rho, rho.data(), rho.size())) != SDD_OK ||
         (st = upload(c, &c->d_le, le.data(), le.size())) != SDD_OK ||
@@ -796,6 +806,7 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         sp.ray_d = c->ray_d;
         sp.hit = c->hit;
         sp.prim_info = c->d_prim_info;
+        sp.prim_v = c->d_prim_v;
         sp.pane = c->d_pane;
         sp.n_glass = c->n_glass;
         sp.nl = c->nl;

@@ -463,7 +463,6 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                 fl = 0;  // no sky dome: a miss carries nothing
             } else {
                 const f3 o = xyz(P.ray_o[pid]), d = xyz(P.ray_d[pid]);
-                const f3 x = o + d * h.x;
                 const float4 pi = P.prim_info[prim];
                 const f3 ngm = xyz(pi);
                 const int word = __float_as_int(pi.w);
@@ -472,29 +471,48 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                 const int emits = (word & kMatEmits) ? kVEmits : 0;
                 const float cos_o = -dot3(ngm, d);
                 const f3 n = cos_o > 0.0f ? ngm : -ngm;
+                // hit point and unit normal in FP64 from the triangle's own plane:
+                // x = o + t d with t = N.(v0 - o) / N.d, N = (v1 - v0) x (v2 - v0),
+                // so the point lies on the plane to FP64 rounding whatever the FP32
+                // intersection t was (the FP32 t only chose the triangle)
+                d3 x64 = wide(o) + wide(d) * (double)h.x;
+                d3 nu64 = wide(n);
+                if (typ != kEmitter) {
+                    const d3 v0 = wide(P.prim_v[3 * (size_t)prim]);
+                    const d3 N = cross3(wide(P.prim_v[3 * (size_t)prim + 1]) - v0, wide(P.prim_v[3 * (size_t)prim + 2]) - v0);
+                    const double nd = dot3(N, wide(d)), nn = dot3(N, N);
+                    if (nd != 0.0 && nn > 0.0) {
+                        x64 = wide(o) + wide(d) * (dot3(N, v0 - wide(o)) / nd);
+                        nu64 = N * ((cos_o > 0.0f ? 1.0 : -1.0) / sqrt(nn));
+                    }
+                }
                 if (typ == kEmitter) {
                     rec.x = ((fl & kCountE) && cos_o > 0.0f) ? (kVEmit | kVLast | (m << kVIdShift)) : kVNone;
                     fl = 0;
                 } else if (typ == kDiffuse) {
                     const uint4 ub = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, (uint32_t)P.depth, 0u), P.key);
-                    xo = x + n * kOffset;
+                    const d3 xo64 = x64 + nu64 * (double)kOffset;
+                    xo = narrow(xo64);
                     float gfac = 0.0f;
                     if (P.light_type != 0) {
-                        f3 y{P.lp0[0], P.lp0[1], P.lp0[2]};
+                        // light sample and geometry term in FP64
+                        d3 y{P.lp0[0], P.lp0[1], P.lp0[2]};
                         if (P.light_type == 1)
-                            y = y + f3{P.le1[0], P.le1[1], P.le1[2]} * u01(ub.x) + f3{P.le2[0], P.le2[1], P.le2[2]} * u01(ub.y);
-                        const f3 w = y - xo;
-                        const float r2 = dot3(w, w);
-                        const float r = sqrtf(r2);
-                        const f3 om = w * (1.0f / r);
-                        const float cx = dot3(n, om);
-                        const float cy = P.light_type == 1 ? -dot3(f3{P.nL[0], P.nL[1], P.nL[2]}, om) : 1.0f;
-                        if (cx > 0.0f && cy > 0.0f) {
+                            y = y + d3{P.le1[0], P.le1[1], P.le1[2]} * (double)u01(ub.x) +
+                                d3{P.le2[0], P.le2[1], P.le2[2]} * (double)u01(ub.y);
+                        const d3 w = y - xo64;
+                        const double r2 = dot3(w, w);
+                        const double r = sqrt(r2);
+                        const d3 om = w * (1.0 / r);
+                        const double cx = dot3(nu64, om);
+                        const double cy = P.light_type == 1 ? -dot3(d3{P.nL[0], P.nL[1], P.nL[2]}, om) : 1.0;
+                        if (cx > 0.0 && cy > 0.0) {
                             // (rho/pi) Le cos_x cos_y / r^2 * A (area light); (rho/pi) I cos_x / r^2 (Eq. 3)
-                            gfac = (P.light_type == 1 ? cx * cy / r2 * P.light_area : cx / r2) * (1.0f / kPi);
+                            gfac = (float)((P.light_type == 1 ? cx * cy / r2 * P.light_area : cx / r2) *
+                                           (1.0 / 3.14159265358979323846));
                             sh = kShVisible;
-                            ws = om;
-                            r_sh = r;
+                            ws = narrow(om);
+                            r_sh = (float)r;
                             cell_s = locate_ray(P.grid, xo, ws, ts);
                             enq_s = cell_s >= 0;
                         }
@@ -511,7 +529,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                         enq_e = true;
                     }
                 } else {  // glass pane
-                    const float c = fabsf(dot3(d, ngm));
+                    const float c = (float)fabs(dot3(wide(d), nu64));
                     float sumR = 0.0f, sumT = 0.0f;
                     const float4* pm = pane + (size_t)m * P.nlp;
                     for (int l = 0; l < P.nl; ++l) {
@@ -533,10 +551,10 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                         if (refl) {
                             dn = d - ngm * (2.0f * dot3(d, ngm));
                             fl |= kCountE;
-                            xo = x + n * kOffset;
+                            xo = narrow(x64 + nu64 * (double)kOffset);
                         } else {
                             dn = d;
-                            xo = x - n * kOffset;
+                            xo = narrow(x64 - nu64 * (double)kOffset);
                         }
                         enq_e = true;
                     }

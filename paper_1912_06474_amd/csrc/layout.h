@@ -12,6 +12,7 @@
 //   tris   float4[3 * n_refs]   48 B per triangle reference, in leaf order:
 //          (v0, prim), (e1, meta), (e2, glass index) with meta = type | last_in_leaf << 2
 //          and the compact glass-material index (-1 for other materials)
+//   prim_v float4[T][3]          triangle vertices (FP64 shading geometry)
 //   prim_info float4[T]          (unit geometric normal, mat word) with
 //          mat word = id | type << 24 | emits << 26, id = material index, or
 //          the compact glass index for glass
@@ -153,12 +154,13 @@ struct ShadeParams {
     int* sh_state;
     // scene
     const float4* prim_info;
+    const float4* prim_v;  // [T][3] vertices
     const float4* pane;    // [n_glass][nlp]
     int n_glass;
     int nl, nlp;
     int light_type;
-    float lp0[3], le1[3], le2[3], nL[3];
-    float light_area;
+    double lp0[3], le1[3], le2[3], nL[3];  // light corner, edges, unit front normal
+    double light_area;
     GridParams grid;
     int n_cells;
     Stage se, ss;          // next closest-hit rays, shadow rays
