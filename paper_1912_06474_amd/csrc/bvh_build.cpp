@@ -16,6 +16,13 @@
 // leaf, depth capped at kMaxBvhDepth (a node at the cap becomes a leaf) so the
 // traversal stack never overflows.  Child boxes are padded by 2e-6 of the
 // scene extent so FP32 slab tests cannot reject a box that holds a hit.
+//
+// Node storage: each child box is quantised to 16 bits per coordinate on a
+// per-cell lattice base + q * step spanning the cell's root box, rounded
+// outward so the FP32 lattice value fmaf(q, step, base) never cuts into the
+// padded box.  A node is two 16-byte children (boxes + link): half the bytes
+// of float boxes, with the same traversal result (a looser box only costs
+// visits; every triangle is still tested exactly).
 #include "bvh_build.h"
 
 #include <algorithm>
@@ -52,6 +59,33 @@ float round_up(double v) {
     float f = (float)v;
     if ((double)f < v) f = std::nextafter(f, INFINITY);
     return f;
+}
+
+// per-cell lattice: fmaf(q, step, base) for q in [0, 65535] covers [lo, hi]
+void lattice(float lo, float hi, float& base, float& step) {
+    base = lo;
+    if (!(hi > lo)) {
+        step = 0.0f;
+        return;
+    }
+    step = round_up(((double)hi - (double)lo) / 65535.0);
+    while (std::fmaf(65535.0f, step, base) < hi) step = std::nextafter(step, INFINITY);
+}
+
+// outward-rounded lattice coordinates of [lo, hi] (clamped to the lattice)
+uint32_t quant_lo(float v, float base, float step) {
+    if (!(step > 0.0f)) return 0;
+    double q = std::floor(((double)v - (double)base) / (double)step);
+    int qi = (int)std::min(65535.0, std::max(0.0, q));
+    while (qi > 0 && std::fmaf((float)qi, step, base) > v) --qi;
+    return (uint32_t)qi;
+}
+uint32_t quant_hi(float v, float base, float step) {
+    if (!(step > 0.0f)) return 0;
+    double q = std::ceil(((double)v - (double)base) / (double)step);
+    int qi = (int)std::min(65535.0, std::max(0.0, q));
+    while (qi < 65535 && std::fmaf((float)qi, step, base) < v) ++qi;
+    return (uint32_t)qi;
 }
 
 float half_area(const float lo[3], const float hi[3]) {
@@ -299,6 +333,7 @@ bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err) {
     // flatten: breadth-first inner nodes; leaves become links to triangle runs
     out.nodes.clear();
     out.tris.clear();
+    out.cell_q.assign(2 * (size_t)G, HostF4{0.0f, 0.0f, 0.0f, 0.0f});
     out.cell_root.assign(G, 0);
     out.cell_refs.assign(G, 0);
     out.cell_nodes.assign(G, 0);
@@ -315,7 +350,7 @@ bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err) {
         out.max_depth = std::max(out.max_depth, b.max_depth);
         out.cell_refs[c] = (int)b.refs.size();
         out.n_refs += (int64_t)b.refs.size();
-        const int node_base = (int)(out.nodes.size() / 4);
+        const int node_base = (int)(out.nodes.size() / 8);
         // inner nodes in BFS order; a root leaf (or an empty cell) gets a wrapper
         std::vector<int> bfs;
         std::vector<int> gid(b.nodes.size(), -1);
@@ -335,7 +370,13 @@ bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err) {
         const int n_inner = wrap ? 1 : (int)bfs.size();
         out.cell_root[c] = node_base;
         out.cell_nodes[c] = n_inner;
-        out.nodes.resize(out.nodes.size() + 4 * (size_t)n_inner);
+        out.nodes.resize(out.nodes.size() + 8 * (size_t)n_inner);
+        // lattice over the cell's root box (the union of its references)
+        float qbase[3] = {0.0f, 0.0f, 0.0f}, qstep[3] = {0.0f, 0.0f, 0.0f};
+        if (!b.refs.empty())
+            for (int a = 0; a < 3; ++a) lattice(b.nodes[0].lo[a], b.nodes[0].hi[a], qbase[a], qstep[a]);
+        out.cell_q[2 * (size_t)c] = HostF4{qbase[0], qbase[1], qbase[2], 0.0f};
+        out.cell_q[2 * (size_t)c + 1] = HostF4{qstep[0], qstep[1], qstep[2], 0.0f};
         auto emit_leaf = [&](const BNode& lf) {
             const int start = (int)(out.tris.size() / 3);
             for (int i = lf.first; i < lf.first + lf.count; ++i) {
@@ -358,14 +399,14 @@ bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err) {
         auto child = [&](int ch, float blo[3], float bhi[3]) -> int {
             if (ch < 0) {
                 for (int a = 0; a < 3; ++a) blo[a] = bhi[a] = far;
-                return 0;
+                return kEmptyLink;
             }
             const BNode& nd = b.nodes[ch];
             for (int a = 0; a < 3; ++a) {
                 blo[a] = nd.lo[a];
                 bhi[a] = nd.hi[a];
             }
-            if (nd.left < 0) return nd.count > 0 ? emit_leaf(nd) : 0;
+            if (nd.left < 0) return nd.count > 0 ? emit_leaf(nd) : kEmptyLink;
             return node_base + gid[ch];
         };
         for (int k = 0; k < n_inner; ++k) {
@@ -379,11 +420,21 @@ bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err) {
             float lo0[3], hi0[3], lo1[3], hi1[3];
             const int l0 = child(ch0, lo0, hi0);
             const int l1 = child(ch1, lo1, hi1);
-            HostF4* nd = &out.nodes[4 * (size_t)(node_base + k)];
-            nd[0] = HostF4{lo0[0], hi0[0], lo0[1], hi0[1]};
-            nd[1] = HostF4{lo1[0], hi1[0], lo1[1], hi1[1]};
-            nd[2] = HostF4{lo0[2], hi0[2], lo1[2], hi1[2]};
-            nd[3] = HostF4{int_bits(l0), int_bits(l1), int_bits(0), int_bits(0)};
+            uint32_t* nd = &out.nodes[8 * (size_t)(node_base + k)];
+            const float* clo[2] = {lo0, lo1};
+            const float* chi[2] = {hi0, hi1};
+            const int lk[2] = {l0, l1};
+            for (int i = 0; i < 2; ++i) {
+                for (int a = 0; a < 3; ++a) {
+                    uint32_t ql = 0, qh = 0;
+                    if (lk[i] != kEmptyLink) {
+                        ql = quant_lo(clo[i][a], qbase[a], qstep[a]);
+                        qh = quant_hi(chi[i][a], qbase[a], qstep[a]);
+                    }
+                    nd[4 * i + a] = ql | (qh << 16);
+                }
+                nd[4 * i + 3] = (uint32_t)lk[i];
+            }
         }
     }
     return true;

@@ -15,7 +15,8 @@ struct GridBvh {
     int nx = 1, ny = 1, nz = 1;
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     std::vector<float> planes;      // nx+1, ny+1, nz+1 planes (float)
-    std::vector<HostF4> nodes;      // 4 per node (layout.h)
+    std::vector<uint32_t> nodes;    // 8 words per node: two quantised children (layout.h)
+    std::vector<HostF4> cell_q;     // 2 per cell: quantisation base, step (layout.h)
     std::vector<HostF4> tris;       // 3 per reference
     std::vector<int32_t> cell_root; // per cell
     std::vector<int32_t> cell_refs; // references per cell

@@ -123,28 +123,32 @@ __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
 // ---------------------------------------------------------------------------
 // traversal of one subdomain (cell) BVH
 // ---------------------------------------------------------------------------
+// A ray prepared for one cell: the plane of lattice coordinate q on axis a
+// is met at t = q * sinv.a + boff.a, with sinv = step / d and
+// boff = (base - o) / d of the cell's lattice.
 struct RayTrav {
-    f3 o, d, inv, oinv;
+    f3 o, d, sinv, boff;
 };
 
-__device__ __forceinline__ RayTrav make_trav(f3 o, f3 d) {
+__device__ __forceinline__ RayTrav make_trav(f3 o, f3 d, float4 qbase, float4 qstep) {
     RayTrav r;
     r.o = o;
     r.d = d;
     const float dx = fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x);
     const float dy = fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y);
     const float dz = fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z);
-    r.inv = f3{1.0f / dx, 1.0f / dy, 1.0f / dz};
-    r.oinv = f3{o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z};
+    const f3 inv{1.0f / dx, 1.0f / dy, 1.0f / dz};
+    r.sinv = f3{qstep.x * inv.x, qstep.y * inv.y, qstep.z * inv.z};
+    r.boff = f3{(qbase.x - o.x) * inv.x, (qbase.y - o.y) * inv.y, (qbase.z - o.z) * inv.z};
     return r;
 }
 
-// slab test of one box against [tlo, thi]; returns the entry t (or +inf on a miss)
-__device__ __forceinline__ float box_enter(const RayTrav& r, float lox, float hix, float loy, float hiy, float loz,
-                                           float hiz, float tlo, float thi) {
-    const float ax = fmaf(lox, r.inv.x, -r.oinv.x), bx = fmaf(hix, r.inv.x, -r.oinv.x);
-    const float ay = fmaf(loy, r.inv.y, -r.oinv.y), by = fmaf(hiy, r.inv.y, -r.oinv.y);
-    const float az = fmaf(loz, r.inv.z, -r.oinv.z), bz = fmaf(hiz, r.inv.z, -r.oinv.z);
+// slab test of one quantised child box against [tlo, thi]; returns the entry t
+// (or +inf on a miss)
+__device__ __forceinline__ float box_enter(const RayTrav& r, uint4 c, float tlo, float thi) {
+    const float ax = fmaf((float)(c.x & 0xffffu), r.sinv.x, r.boff.x), bx = fmaf((float)(c.x >> 16), r.sinv.x, r.boff.x);
+    const float ay = fmaf((float)(c.y & 0xffffu), r.sinv.y, r.boff.y), by = fmaf((float)(c.y >> 16), r.sinv.y, r.boff.y);
+    const float az = fmaf((float)(c.z & 0xffffu), r.sinv.z, r.boff.z), bz = fmaf((float)(c.z >> 16), r.sinv.z, r.boff.z);
     const float tmin = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tlo));
     const float tmax = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), thi));
     return tmin <= tmax ? tmin : INFINITY;
@@ -169,7 +173,7 @@ __device__ __forceinline__ bool tri_test(const RayTrav& r, float4 a, float4 b, f
 }
 
 template <bool SHADOW, bool COUNT>
-__device__ __forceinline__ void traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris,
+__device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const float4* __restrict__ tris,
                                          const float4* __restrict__ prim_info, int root, const RayTrav& r,
                                          float tlo, float t_exit, float t_max, int exclude, float& thi, int& best,
                                          bool& blocked, int& n_glass, int pid, const int* __restrict__ sh_state,
@@ -180,30 +184,29 @@ __device__ __forceinline__ void traverse(const float4* __restrict__ nodes, const
     // closest hit: thi = t_exit, best = -1 on entry; shadow: thi = min(t_exit, t_max)
     for (;;) {
         if (link >= 0) {
-            const float4* nd = nodes + 4 * (size_t)link;
-            const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2];
-            const int4 n3 = *reinterpret_cast<const int4*>(nd + 3);
+            const uint4 c0 = nodes[2 * (size_t)link], c1 = nodes[2 * (size_t)link + 1];
+            const int l0 = (int)c0.w, l1 = (int)c1.w;
             if (COUNT) ++n_nodes;
-            const float t0 = box_enter(r, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, tlo, thi);
-            const float t1 = box_enter(r, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, tlo, thi);
-            const bool h0 = t0 != INFINITY, h1 = t1 != INFINITY;
+            const float t0 = box_enter(r, c0, tlo, thi);
+            const float t1 = box_enter(r, c1, tlo, thi);
+            const bool h0 = t0 != INFINITY && l0 != kEmptyLink, h1 = t1 != INFINITY && l1 != kEmptyLink;
             if (h0 && h1) {
                 const bool first0 = t0 <= t1;
                 // short stack in LDS, deeper entries in HBM; the builder caps the
                 // BVH depth below kStack, so no entry is ever dropped
-                const int far = first0 ? n3.y : n3.x;
+                const int far = first0 ? l1 : l0;
                 if (sp < kLdsStack) stk[sp * kTraceBlock] = far;
                 else if (sp < kStack) gstk[(sp - kLdsStack) * gstride] = far;
                 ++sp;
-                link = first0 ? n3.x : n3.y;
+                link = first0 ? l0 : l1;
                 continue;
             }
             if (h0) {
-                link = n3.x;
+                link = l0;
                 continue;
             }
             if (h1) {
-                link = n3.y;
+                link = l1;
                 continue;
             }
         } else {
@@ -289,7 +292,7 @@ __device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueS
             t_exit = tz;
             axis = 2;
         }
-        const RayTrav r = make_trav(o, d);
+        const RayTrav r = make_trav(o, d, P.cell_q[2 * cell], P.cell_q[2 * cell + 1]);
         float thi = SHADOW ? fminf(t_exit, t_max) : t_exit;
         int best = -1;
         bool blocked = false;

@@ -2,13 +2,13 @@
 // and the HIP kernels.
 //
 // Per-subdomain acceleration data (built on the host, one BVH per grid cell):
-//   nodes  float4[4 * n_nodes]  64 B per inner node (both child boxes + links):
-//          n0 = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
-//          n1 = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
-//          n2 = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
-//          n3 = (link0, link1, 0, 0) as int: link >= 0 inner node index,
-//               link < 0 leaf starting at triangle ~link
+//   nodes  uint4[2 * n_nodes]   32 B per inner node, one 16 B record per child:
+//          (lo.x | hi.x << 16, lo.y | hi.y << 16, lo.z | hi.z << 16, link)
+//          with 16-bit lattice coordinates: coordinate = base + q * step of
+//          the node's cell (cell_q), rounded outward; link >= 0 inner node
+//          index, link < 0 leaf starting at triangle ~link, kEmptyLink none.
 //          Nodes of each cell are stored breadth-first (root first).
+//   cell_q float4[2 * n_cells]   lattice of each cell: (base.xyz, 0), (step.xyz, 0)
 //   tris   float4[3 * n_refs]   48 B per triangle reference, in leaf order:
 //          (v0, prim), (e1, meta), (e2, glass index) with meta = type | last_in_leaf << 2
 //          and the compact glass-material index (-1 for other materials)
@@ -68,6 +68,7 @@ enum : int { kDiffuse = 0, kGlass = 1, kEmitter = 2 };
 enum : uint32_t { kAlive = 1u, kCountE = 2u };
 enum : int { kShNone = 0, kShVisible = 1, kShBlocked = 2 };  // | pane count << 4 when visible
 constexpr int kLastInLeaf = 4;
+constexpr int kEmptyLink = 0x7fffffff;  // child slot without a subtree
 // vertex record kinds
 enum : int { kVNone = 0, kVDiffuse = 1, kVGlassR = 2, kVGlassT = 3, kVEmit = 4 };
 constexpr int kVLast = 8, kVEmits = 16, kVIdShift = 5;
@@ -121,7 +122,8 @@ struct TraceParams {
     long long cap;        // slots per cell
     int n_cells;
     GridParams grid;
-    const float4* nodes;
+    const uint4* nodes;
+    const float4* cell_q;
     const float4* tris;
     const int* cell_root;
     const float4* prim_info;  // (unit geometric normal, mat bits)
