@@ -76,6 +76,7 @@ struct sdd_ctx {
     GridBvh gb;
     uint4* d_nodes = nullptr;
     float4* d_cell_q = nullptr;
+    int* d_cell_nodes = nullptr;
     float4* d_tris = nullptr;
     int* d_cell_root = nullptr;
     float* d_planes = nullptr;
@@ -203,6 +204,7 @@ void free_scene(sdd_ctx* c) {
 void free_accel(sdd_ctx* c) {
     dfree(c, c->d_nodes);
     dfree(c, c->d_cell_q);
+    dfree(c, c->d_cell_nodes);
     dfree(c, c->d_tris);
     dfree(c, c->d_cell_root);
     dfree(c, c->d_planes);
@@ -425,6 +427,7 @@ sdd_status run_sweeps(sdd_ctx* c, int ext_phase, int sh_phase, long long cap, bo
         p.grid = c->grid;
         p.nodes = c->d_nodes;
         p.cell_q = c->d_cell_q;
+        p.cell_nodes = c->d_cell_nodes;
         p.tris = c->d_tris;
         p.cell_root = c->d_cell_root;
         p.prim_info = c->d_prim_info;
@@ -654,6 +657,7 @@ sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
     sdd_status st;
     if ((st = upload(c, &c->d_nodes, reinterpret_cast<const uint4*>(gb.nodes.data()), gb.nodes.size() / 4)) != SDD_OK ||
         (st = upload(c, &c->d_cell_q, reinterpret_cast<const float4*>(gb.cell_q.data()), gb.cell_q.size())) != SDD_OK ||
+        (st = upload(c, &c->d_cell_nodes, gb.cell_nodes.data(), gb.cell_nodes.size())) != SDD_OK ||
         (st = upload(c, &c->d_tris, reinterpret_cast<const float4*>(gb.tris.data()), gb.tris.size())) != SDD_OK ||
         (st = upload(c, &c->d_cell_root, gb.cell_root.data(), gb.cell_root.size())) != SDD_OK ||
         (st = upload(c, &c->d_planes, gb.planes.data(), gb.planes.size())) != SDD_OK) {

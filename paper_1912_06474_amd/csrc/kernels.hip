@@ -173,7 +173,8 @@ __device__ __forceinline__ bool tri_test(const RayTrav& r, float4 a, float4 b, f
 }
 
 template <bool SHADOW, bool COUNT>
-__device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const float4* __restrict__ tris,
+__device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const uint4* top,
+                                         const float4* __restrict__ tris,
                                          const float4* __restrict__ prim_info, int root, const RayTrav& r,
                                          float tlo, float t_exit, float t_max, int exclude, float& thi, int& best,
                                          bool& blocked, int& n_glass, int pid, const int* __restrict__ sh_state,
@@ -184,7 +185,16 @@ __device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const 
     // closest hit: thi = t_exit, best = -1 on entry; shadow: thi = min(t_exit, t_max)
     for (;;) {
         if (link >= 0) {
-            const uint4 c0 = nodes[2 * (size_t)link], c1 = nodes[2 * (size_t)link + 1];
+            // the cell's first kTopNodes nodes (breadth-first: its top levels) come from LDS
+            const int rel = link - root;
+            uint4 c0, c1;
+            if (rel < kTopNodes) {
+                c0 = top[2 * rel];
+                c1 = top[2 * rel + 1];
+            } else {
+                c0 = nodes[2 * (size_t)link];
+                c1 = nodes[2 * (size_t)link + 1];
+            }
             const int l0 = (int)c0.w, l1 = (int)c1.w;
             if (COUNT) ++n_nodes;
             const float t0 = box_enter(r, c0, tlo, thi);
@@ -256,7 +266,7 @@ __device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const 
 // neighbouring cell's queue.  Reached by all lanes of the wave together.
 template <bool SHADOW, bool COUNT>
 __device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueSet& Q, int cell, int idx, bool active,
-                                              int* stk, int* gstk, int gstride, int& n_nodes,
+                                              const uint4* top, int* stk, int* gstk, int gstride, int& n_nodes,
                                               int& n_tris) {
     const GridParams& g = P.grid;
     const int ix = cell % g.nx, iy = (cell / g.nx) % g.ny, iz = cell / (g.nx * g.ny);
@@ -298,7 +308,7 @@ __device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueS
         bool blocked = false;
         int n_glass = -1;  // pane crossings so far (-1: not loaded yet)
         if (!SHADOW || thi > t_enter)
-            traverse<SHADOW, COUNT>(P.nodes, P.tris, P.prim_info, root, r, t_enter, t_exit, t_max, qc.x, thi, best,
+            traverse<SHADOW, COUNT>(P.nodes, top, P.tris, P.prim_info, root, r, t_enter, t_exit, t_max, qc.x, thi, best,
                                     blocked, n_glass, pid, P.sh_state, P.sh_glass, P.overflow, stk, gstk, gstride,
                                     n_nodes, n_tris);
         bool leave;
@@ -340,6 +350,7 @@ template <bool COUNT>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
     extern __shared__ int s_pref[];  // 2 * n_cells + 1 entries (dynamic, so small grids keep occupancy)
     __shared__ int s_stack[kLdsStack * kTraceBlock];
+    __shared__ uint4 s_top[(kTraceBlock / 64) * 2 * kTopNodes];
     const int G = P.n_cells;
     const int E = 2 * G;  // entry e = 2 * cell + kind
     if (threadIdx.x < 64) {
@@ -384,6 +395,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
     int* gstk = P.gstack + blockIdx.x * kTraceBlock + threadIdx.x;
     const int xcd = blockIdx.x % kXcd;
     int n_nodes = 0, n_tris = 0;
+    uint4* top = s_top + (threadIdx.x / 64) * 2 * kTopNodes;  // this wave's copy of a cell's top nodes
+    int top_cell = -1;
 
     // static XCD-aware striding: the waves of XCD x walk part x of the chunk
     // list round-robin (no atomics, so empty and near-empty sweeps cost only
@@ -402,13 +415,24 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
         }
         const int e = __builtin_amdgcn_readfirstlane(a);
         const int cell = e >> 1, kind = e & 1;
+        if (cell != top_cell) {
+            // the wave is done with the previous cell's copy (its traversals
+            // have returned), so it can be overwritten; LDS operations of one
+            // wave complete in order
+            top_cell = cell;
+            const int nn = 2 * min(P.cell_nodes[cell], kTopNodes);
+            const uint4* src = P.nodes + 2 * (size_t)P.cell_root[cell];
+            for (int i = lane; i < nn; i += 64) top[i] = src[i];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
         const int idx = (chunk - s_pref[e]) * kChunk + lane;
         const bool active = idx < min((long long)P.q[kind].cnt_in[cell], P.cap);
         if (kind == 0)
-            process_chunk<false, COUNT>(P, P.q[0], cell, idx, active, stk, gstk, gstride, n_nodes,
+            process_chunk<false, COUNT>(P, P.q[0], cell, idx, active, top, stk, gstk, gstride, n_nodes,
                                         n_tris);
         else
-            process_chunk<true, COUNT>(P, P.q[1], cell, idx, active, stk, gstk, gstride, n_nodes,
+            process_chunk<true, COUNT>(P, P.q[1], cell, idx, active, top, stk, gstk, gstride, n_nodes,
                                        n_tris);
     }
     if (COUNT) {

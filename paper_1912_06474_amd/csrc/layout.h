@@ -41,7 +41,8 @@ namespace sdd {
 
 constexpr int kTraceBlock = 128;  // threads per traversal workgroup
 constexpr int kStack = 40;        // traversal stack entries per lane (total)
-constexpr int kLdsStack = 16;     // of which the first kLdsStack live in LDS, the rest in HBM
+constexpr int kLdsStack = 8;      // of which the first kLdsStack live in LDS, the rest in HBM
+constexpr int kTopNodes = 128;    // breadth-first top nodes of the current cell kept in LDS per wave
 constexpr int kMaxBvhDepth = kStack;  // the builder never exceeds the stack
 constexpr int kChunk = 64;        // rays per scheduling chunk (one wave)
 constexpr int kXcd = 8;           // XCDs of an MI355X; workgroup i runs on XCD i % 8
@@ -126,6 +127,7 @@ struct TraceParams {
     const float4* cell_q;
     const float4* tris;
     const int* cell_root;
+    const int* cell_nodes;    // inner nodes per cell
     const float4* prim_info;  // (unit geometric normal, mat bits)
     // closest-hit output
     float2* hit;
