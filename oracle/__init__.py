@@ -35,6 +35,8 @@ class Scene(C.Structure):
         ("mat_k", C.c_void_p), ("mat_thick", C.c_void_p), ("mat_le", C.c_void_p),
         ("light_type", C.c_int), ("light_p0", C.c_void_p), ("light_e1", C.c_void_p),
         ("light_e2", C.c_void_p), ("light_mat", C.c_int),
+        ("max_layers", C.c_int), ("mat_n_layers", C.c_void_p), ("mat_layer_d", C.c_void_p),
+        ("mat_layer_n", C.c_void_p), ("mat_layer_k", C.c_void_p),
     ]
 
 
@@ -73,6 +75,9 @@ def _declare(L):
     L.ora_fresnel_sp.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
     L.ora_slab_sp.argtypes = [C.c_double] * 5 + [dp] * 4
     L.ora_slab.argtypes = [C.c_double] * 5 + [dp] * 2
+    L.ora_tmm_sp.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p] + [C.c_double] * 6 + [dp] * 4
+    L.ora_coated_pane.argtypes = ([C.c_double] * 3 + [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+                                  + [C.c_double] * 2 + [C.c_int] + [dp] * 2)
     L.ora_cosine_hemisphere.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_void_p]
     L.ora_camera_ray.argtypes = [C.POINTER(Args), C.c_double, C.c_double, C.c_void_p, C.c_void_p]
 
@@ -112,6 +117,16 @@ class OracleScene:
                        _ptr(k["mat_thick"]), _ptr(k["mat_le"]),
                        int(scene["light_type"]), _ptr(k["light_p0"]), _ptr(k["light_e1"]),
                        _ptr(k["light_e2"]), int(scene["light_mat"]))
+        if "mat_n_layers" in scene:
+            nlay = arr("mat_n_layers", np.int32)
+            ld = arr("mat_layer_d", np.float32)
+            arr("mat_layer_n", np.float32)
+            arr("mat_layer_k", np.float32)
+            self.c.max_layers = int(ld.shape[1]) if ld.ndim == 2 else 0
+            self.c.mat_n_layers = _ptr(nlay)
+            self.c.mat_layer_d = _ptr(ld)
+            self.c.mat_layer_n = _ptr(k["mat_layer_n"])
+            self.c.mat_layer_k = _ptr(k["mat_layer_k"])
         self._accel = None
 
     @property
@@ -231,6 +246,28 @@ def slab_sp(n, k, thick_m, lam_nm, c):
 def slab(n, k, thick_m, lam_nm, c):
     R, T = C.c_double(), C.c_double()
     lib().ora_slab(n, k, thick_m, lam_nm, c, C.byref(R), C.byref(T))
+    return R.value, T.value
+
+
+def tmm_sp(d_m, n, k, n_in, k_in, n_out, k_out, lam_nm, beta):
+    """Coherent stack between two media: (Rs, Rp, Ts, Tp)."""
+    d = np.ascontiguousarray(d_m, np.float64)
+    nn = np.ascontiguousarray(n, np.float64)
+    kk = np.ascontiguousarray(k, np.float64)
+    v = [C.c_double() for _ in range(4)]
+    lib().ora_tmm_sp(len(d), _ptr(d), _ptr(nn), _ptr(kk), n_in, k_in, n_out, k_out, lam_nm, beta,
+                     *[C.byref(x) for x in v])
+    return tuple(x.value for x in v)
+
+
+def coated_pane(n_s, k_s, thick_m, d_m, n, k, lam_nm, c, coated_side=True):
+    """Coated incoherent pane: (R, T), polarisation-averaged."""
+    d = np.ascontiguousarray(d_m, np.float64)
+    nn = np.ascontiguousarray(n, np.float64)
+    kk = np.ascontiguousarray(k, np.float64)
+    R, T = C.c_double(), C.c_double()
+    lib().ora_coated_pane(n_s, k_s, thick_m, len(d), _ptr(d), _ptr(nn), _ptr(kk), lam_nm, c, int(bool(coated_side)),
+                          C.byref(R), C.byref(T))
     return R.value, T.value
 
 

@@ -121,6 +121,119 @@ void ora_slab(double n, double k, double thick_m, double lambda_nm, double c, do
 }
 
 /* ------------------------------------------------------------------------ */
+/* coherent thin-film stack (electrochromic coating): characteristic matrices */
+/* ------------------------------------------------------------------------ */
+/* Medium of complex index N crossed with Snell invariant beta = N sin(theta)
+ * (the same in every layer): N cos(theta) is the principal root of
+ * N^2 - beta^2, and the tilted optical admittance is N cos(theta) for s and
+ * N / cos(theta) = N^2 / (N cos(theta)) for p polarisation. */
+static double complex admittance(double complex N, double beta, int p_pol) {
+    double complex Nc = csqrt(N * N - beta * beta);
+    return p_pol ? N * N / Nc : Nc;
+}
+
+/* Stack of L layers (thickness d[j] m, index n[j] + i k[j]) between an
+ * incidence medium N_in and an exit medium N_out, layers listed in the order
+ * the light meets them.  With the index written n + i k (fields varying as
+ * exp(i (N k0 z - omega t)), so k > 0 attenuates), each layer's
+ * characteristic matrix is
+ *   [[cos delta, -i sin delta / eta], [-i eta sin delta, cos delta]],
+ * delta = 2 pi N cos(theta) d / lambda; with [B, C] = M_1 ... M_L [1, eta_out],
+ * the amplitude reflectance is r = (eta_in B - C) / (eta_in B + C), the
+ * reflectance R = |r|^2 and the transmittance into the exit medium
+ * T = 4 Re(eta_in) Re(eta_out) / |eta_in B + C|^2. */
+void ora_tmm_sp(int L, const double *d_m, const double *n, const double *k, double n_in, double k_in,
+                double n_out, double k_out, double lambda_nm, double beta,
+                double *Rs, double *Rp, double *Ts, double *Tp) {
+    double lam = lambda_nm * 1e-9;
+    for (int pol = 0; pol < 2; ++pol) {
+        double complex m11 = 1.0, m12 = 0.0, m21 = 0.0, m22 = 1.0;
+        for (int j = 0; j < L; ++j) {
+            double complex N = n[j] + I * k[j];
+            double complex Nc = csqrt(N * N - beta * beta);
+            double complex eta = pol ? N * N / Nc : Nc;
+            double complex delta = 2.0 * ORA_PI * Nc * d_m[j] / lam;
+            double complex a11 = ccos(delta), a12 = -I * csin(delta) / eta;
+            double complex a21 = -I * eta * csin(delta), a22 = ccos(delta);
+            double complex t11 = m11 * a11 + m12 * a21, t12 = m11 * a12 + m12 * a22;
+            double complex t21 = m21 * a11 + m22 * a21, t22 = m21 * a12 + m22 * a22;
+            m11 = t11; m12 = t12; m21 = t21; m22 = t22;
+        }
+        double complex e_in = admittance(n_in + I * k_in, beta, pol);
+        double complex e_out = admittance(n_out + I * k_out, beta, pol);
+        double complex B = m11 + m12 * e_out, Cc = m21 + m22 * e_out;
+        double complex r = (e_in * B - Cc) / (e_in * B + Cc);
+        double complex den = e_in * B + Cc;
+        double R = creal(r) * creal(r) + cimag(r) * cimag(r);
+        double T = 4.0 * creal(e_in) * creal(e_out) / (creal(den) * creal(den) + cimag(den) * cimag(den));
+        if (pol) { *Rp = R; *Tp = T; } else { *Rs = R; *Ts = T; }
+    }
+}
+
+/* Pane with a coherent coating of L layers on one face of the incoherent
+ * substrate (index n_s + i k_s, thickness thick_m).  Per polarisation:
+ *  - coated face: R_c, T_c from air onto the stack into the substrate, R_c'
+ *    from the substrate onto the reversed stack into air;
+ *  - bare face: R_b = Fresnel of the substrate, T_b = 1 - R_b;
+ *  - the substrate attenuates each crossing by tau (Beer-Lambert as for the
+ *    uncoated slab) and the internal reflections sum incoherently:
+ *      from the coated side: T = T_c tau T_b / (1 - R_c' R_b tau^2),
+ *                            R = R_c + T_c T_c' R_b tau^2 / (1 - R_c' R_b tau^2)
+ *      from the bare side:   T = T_b tau T_c' / (1 - R_b R_c' tau^2),
+ *                            R = R_b + T_b^2 R_c' tau^2 / (1 - R_b R_c' tau^2)
+ *  then (s + p) / 2.  c: incidence cosine in air; coated_side: 1 if the light
+ *  arrives on the coated face. */
+void ora_coated_pane(double n_s, double k_s, double thick_m, int L, const double *d_m, const double *n,
+                     const double *k, double lambda_nm, double c, int coated_side, double *R, double *T) {
+    double beta = sqrt(fmax(0.0, 1.0 - c * c));
+    double Rc[2], Tc[2], Rc2[2], Tc2[2], Rb[2];
+    ora_tmm_sp(L, d_m, n, k, 1.0, 0.0, n_s, k_s, lambda_nm, beta, &Rc[0], &Rc[1], &Tc[0], &Tc[1]);
+    double dr[8], nr[8], kr[8];
+    for (int j = 0; j < L; ++j) { dr[j] = d_m[L - 1 - j]; nr[j] = n[L - 1 - j]; kr[j] = k[L - 1 - j]; }
+    ora_tmm_sp(L, dr, nr, kr, n_s, k_s, 1.0, 0.0, lambda_nm, beta, &Rc2[0], &Rc2[1], &Tc2[0], &Tc2[1]);
+    ora_fresnel_sp(n_s, k_s, c, &Rb[0], &Rb[1]);
+    double cosr2 = 1.0 - (1.0 - c * c) / (n_s * n_s);
+    double tau = 0.0;
+    if (cosr2 > 0.0) tau = exp(-4.0 * ORA_PI * k_s / (lambda_nm * 1e-9) * thick_m / sqrt(cosr2));
+    double Rsum = 0.0, Tsum = 0.0;
+    for (int i = 0; i < 2; ++i) {
+        double Tb = 1.0 - Rb[i];
+        double den = 1.0 - Rc2[i] * Rb[i] * tau * tau;
+        if (den <= 0.0) { Rsum += 1.0; continue; }
+        if (coated_side) {
+            Tsum += Tc[i] * tau * Tb / den;
+            Rsum += Rc[i] + Tc[i] * Tc2[i] * Rb[i] * tau * tau / den;
+        } else {
+            Tsum += Tb * tau * Tc2[i] / den;
+            Rsum += Rb[i] + Tb * Tb * Rc2[i] * tau * tau / den;
+        }
+    }
+    *R = 0.5 * Rsum;
+    *T = 0.5 * Tsum;
+}
+
+/* R and T of glass material m at wavelength l for incidence cosine c; the
+ * coating (if any) lies on the face the triangle's geometric normal points
+ * out of, so a ray with dir . n_g < 0 meets it first. */
+static void pane_RT(const ora_scene *sc, int m, int l, double c, int coated_side, double *R, double *T) {
+    const int nl = sc->n_lambda;
+    const int L = sc->mat_n_layers ? sc->mat_n_layers[m] : 0;
+    const double n_s = sc->mat_n[(size_t)m * nl + l], k_s = sc->mat_k[(size_t)m * nl + l];
+    if (L <= 0) {
+        ora_slab(n_s, k_s, sc->mat_thick[m], sc->lambda_nm[l], c, R, T);
+        return;
+    }
+    const int Lm = sc->max_layers;
+    double d[8], n[8], k[8];
+    for (int j = 0; j < L && j < 8; ++j) {
+        d[j] = sc->mat_layer_d[(size_t)m * Lm + j];
+        n[j] = sc->mat_layer_n[((size_t)m * Lm + j) * nl + l];
+        k[j] = sc->mat_layer_k[((size_t)m * Lm + j) * nl + l];
+    }
+    ora_coated_pane(n_s, k_s, sc->mat_thick[m], L < 8 ? L : 8, d, n, k, sc->lambda_nm[l], c, coated_side, R, T);
+}
+
+/* ------------------------------------------------------------------------ */
 /* sampling and camera                                                       */
 /* ------------------------------------------------------------------------ */
 /* cosine-weighted direction about n; orthonormal basis of Duff et al.
@@ -358,11 +471,11 @@ static int shadow_prim(const ora_scene *sc, int prim, v3 o, v3 w, double r, int 
     if (!tri_hit(sc, prim, o, w, &t)) return 1;
     if (!(t > 0.0 && t < r)) return 1;
     if (typ == ORA_DIFFUSE) return 0;
-    double c = fabs(dot(w, tri_normal(sc, prim)));
+    v3 ngs = tri_normal(sc, prim);
+    double c = fabs(dot(w, ngs));
     for (int l = 0; l < nl; ++l) {
         double Rl, Tl;
-        ora_slab(sc->mat_n[(size_t)m * nl + l], sc->mat_k[(size_t)m * nl + l], sc->mat_thick[m],
-                 sc->lambda_nm[l], c, &Rl, &Tl);
+        pane_RT(sc, m, l, c, dot(w, ngs) < 0.0, &Rl, &Tl);
         T[l] *= Tl;
     }
     return 1;
@@ -519,11 +632,11 @@ static void trace_path(const ora_scene *sc, const ora_accel *acc, const ora_args
         /* glass pane: zero-thickness geometry carrying a slab of thickness d */
         {
             double c = fabs(dot(dir, ng));
+            int coated_side = dot(dir, ng) < 0.0;
             double sumR = 0.0, sumT = 0.0;
             for (int l = 0; l < nl; ++l) {
                 double Rl, Tl;
-                ora_slab(sc->mat_n[(size_t)m * nl + l], sc->mat_k[(size_t)m * nl + l], sc->mat_thick[m],
-                         sc->lambda_nm[l], c, &Rl, &Tl);
+                pane_RT(sc, m, l, c, coated_side, &Rl, &Tl);
                 sumR += Rl; sumT += Tl;
                 tmp_T[l] = Rl;          /* keep R; T is recomputed if the ray transmits */
             }
@@ -539,8 +652,7 @@ static void trace_path(const ora_scene *sc, const ora_accel *acc, const ora_args
             } else {
                 for (int l = 0; l < nl; ++l) {
                     double Rl, Tl;
-                    ora_slab(sc->mat_n[(size_t)m * nl + l], sc->mat_k[(size_t)m * nl + l], sc->mat_thick[m],
-                             sc->lambda_nm[l], c, &Rl, &Tl);
+                    pane_RT(sc, m, l, c, coated_side, &Rl, &Tl);
                     beta[l] *= Tl / (1.0 - PR);
                 }
                 o = sub(x, scl(n, ORA_OFFSET));

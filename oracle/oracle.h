@@ -11,6 +11,9 @@
  *    an air / absorbing-dielectric interface for s and p polarisation;
  *  - the incoherent thick-slab reflectance / transmittance of a pane with
  *    Beer-Lambert absorption ("direct use of the Fresnel definition", Sec. 6);
+ *  - for electrochromic windows (the paper's subject, Sec. 1), a coherent
+ *    thin-film coating on one face by characteristic (transfer) matrices,
+ *    combined incoherently with the substrate;
  *  - the global closest hit of a ray (Sec. 4, inverse ray tracing): with the
  *    spatial decomposition of Sec. 5 the ray is handed from subdomain to
  *    subdomain unchanged, so the closest hit over all visited subdomains is
@@ -58,6 +61,12 @@ typedef struct ora_scene {
     int light_type;
     const float *light_p0, *light_e1, *light_e2; /* [3] each */
     int light_mat;
+    /* optional coherent coatings of glass materials (NULL: none) */
+    int max_layers;              /* Lm, at most 8 */
+    const int32_t *mat_n_layers; /* [M] layers on the normal-side face */
+    const float *mat_layer_d;    /* [M][Lm] thickness (m), outermost first */
+    const float *mat_layer_n;    /* [M][Lm][nl] */
+    const float *mat_layer_k;    /* [M][Lm][nl] */
 } ora_scene;
 
 typedef struct ora_args {
@@ -108,6 +117,11 @@ void ora_fresnel_sp(double n, double k, double c, double *Rs, double *Rp);
 void ora_slab_sp(double n, double k, double thick_m, double lambda_nm, double c,
                  double *Rslab_s, double *Rslab_p, double *T_s, double *T_p);
 void ora_slab(double n, double k, double thick_m, double lambda_nm, double c, double *R, double *T);
+void ora_tmm_sp(int L, const double *d_m, const double *n, const double *k, double n_in, double k_in,
+                double n_out, double k_out, double lambda_nm, double beta,
+                double *Rs, double *Rp, double *Ts, double *Tp);
+void ora_coated_pane(double n_s, double k_s, double thick_m, int L, const double *d_m, const double *n,
+                     const double *k, double lambda_nm, double c, int coated_side, double *R, double *T);
 
 void ora_cosine_hemisphere(const double n[3], double u0, double u1, double out[3]);
 void ora_camera_ray(const ora_args *args, double x, double y, double o[3], double d[3]);

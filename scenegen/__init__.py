@@ -284,8 +284,9 @@ class _Materials:
         self.k: list[np.ndarray] = []
         self.thick: list[float] = []
         self.le: list[np.ndarray] = []
+        self.layers: list[list] = []
 
-    def add(self, typ, rho=None, n=None, k=None, thick=0.0, le=None):
+    def add(self, typ, rho=None, n=None, k=None, thick=0.0, le=None, layers=None):
         z = np.zeros(self.nl, dtype=np.float32)
         self.type.append(typ)
         self.rho.append(z if rho is None else np.asarray(rho, dtype=np.float32))
@@ -293,6 +294,7 @@ class _Materials:
         self.k.append(z if k is None else np.asarray(k, dtype=np.float32))
         self.thick.append(float(thick))
         self.le.append(z if le is None else np.asarray(le, dtype=np.float32))
+        self.layers.append(list(layers or []))
         return len(self.type) - 1
 
 
@@ -321,11 +323,44 @@ def _finish(mesh, mats, lam, w, *, light_type, light_mat, name, seed,
         seed=int(seed),
         cmf_provenance="proxy: multi-lobe Gaussian fit (Wyman-Sloan-Shirley 2013), not the CIE table",
     )
+    n_lay = [len(x) for x in mats.layers]
+    if any(n_lay):
+        M, Lm, nl = len(mats.type), max(n_lay), len(lam)
+        d = np.zeros((M, Lm), np.float32)
+        n = np.ones((M, Lm, nl), np.float32)
+        k = np.zeros((M, Lm, nl), np.float32)
+        for m, lay in enumerate(mats.layers):
+            for j, (dj, nj, kj) in enumerate(lay):
+                d[m, j], n[m, j], k[m, j] = dj, nj, kj
+        scene.update(mat_n_layers=np.asarray(n_lay, np.int32), mat_layer_d=d, mat_layer_n=n, mat_layer_k=k)
     return scene
 
 
-def _glass_material(mats, lam, k=1e-7, thick=0.004):
-    return mats.add(GLASS, n=cauchy_n(lam), k=np.full(mats.nl, k, dtype=np.float32), thick=thick)
+def electrochromic_layers(lam_nm, state: float):
+    """Synthetic five-layer electrochromic coating, listed from the air side:
+    transparent conductor / electrochromic / ion conductor / counter electrode /
+    transparent conductor, thicknesses 50-400 nm, n(lambda) in [1.4, 2.4] from
+    Cauchy laws and k(lambda) in [0, 0.5].  ``state`` in [0, 1] is the
+    colouring level: it scales the absorption bands of the electrochromic and
+    counter-electrode layers.  Returns [(thickness_m, n[nl], k[nl]), ...]."""
+    lam = np.asarray(lam_nm, dtype=np.float64)
+    l_um = lam / 1000.0
+    state = float(np.clip(state, 0.0, 1.0))
+
+    def layer(d_nm, a, b, k):
+        n = np.clip(a + b / l_um ** 2, 1.4, 2.4)
+        return (d_nm * 1e-9, n.astype(np.float32), np.clip(k, 0.0, 0.5).astype(np.float32))
+
+    tco = layer(150.0, 1.85, 0.012, np.full_like(lam, 0.004))
+    ec = layer(300.0, 2.05, 0.020, 0.5 * state * np.exp(-0.5 * ((lam - 760.0) / 160.0) ** 2) + 0.002)
+    ion = layer(200.0, 1.45, 0.004, np.zeros_like(lam))
+    ce = layer(100.0, 2.15, 0.015, 0.2 * state * np.exp(-0.5 * ((lam - 450.0) / 90.0) ** 2) + 0.002)
+    return [tco, ec, ion, ce, tco]
+
+
+def _glass_material(mats, lam, k=1e-7, thick=0.004, coating_state=None):
+    layers = None if coating_state is None else electrochromic_layers(lam, coating_state)
+    return mats.add(GLASS, n=cauchy_n(lam), k=np.full(mats.nl, k, dtype=np.float32), thick=thick, layers=layers)
 
 
 # ----------------------------------------------------------------------------
@@ -366,19 +401,21 @@ def tiny_room(seed: int = 0, n_lambda: int = 16, n_boxes: int = 20, window=((1, 
 
 
 def furnished_room(seed: int = 1, n_lambda: int = 41, min_tris: int = 200_000,
-                   panes=((0, 1), (2, 1), (3, 2))):
+                   panes=((0, 1), (2, 1), (3, 2)), coating_state=None, name=None):
     """Room-scale plain-method room: >= ``min_tris`` triangles, three 4 mm panes.
 
     Furniture: boxes (faces s x s, s in 2..6) and capped z-axis cylinders
     (16..64 segments, 1..8 stacks), half-sizes U[0.03, 0.25] m, centres
     uniform in the room volume (1 cm clear of the shell, 0.1 m clear of the
-    camera), generated until the triangle count reaches ``min_tris``.
+    camera), generated until the triangle count reaches ``min_tris``.  With
+    ``coating_state`` the panes carry the electrochromic coating
+    (``electrochromic_layers``) on their room-side face.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     lam, w = lambda_grid(n_lambda)
     mats = _Materials(len(lam))
     rect_mats = [mats.add(DIFFUSE, rho=gaussian_reflectance(rng, lam)) for _ in range(6)]
-    pane = _glass_material(mats, lam)
+    pane = _glass_material(mats, lam, coating_state=coating_state)
     sky = mats.add(EMITTER, le=planck_shape(lam))
     mesh = _Mesh()
     _room_shell(mesh, rect_mats, window_cells=panes, pane_mat=pane)
@@ -403,7 +440,14 @@ def furnished_room(seed: int = 1, n_lambda: int = 41, min_tris: int = 200_000,
         else:
             _cylinder(mesh, c, h[0], h[2], int(rng.integers(16, 65)), int(rng.integers(1, 9)), m)
     return _finish(mesh, mats, lam, w, light_type=LIGHT_PARALLELOGRAM, light_mat=sky,
-                   name=f"furnished_room(seed={seed},nl={n_lambda},T>={min_tris})", seed=seed)
+                   name=name or f"furnished_room(seed={seed},nl={n_lambda},T>={min_tris})", seed=seed)
+
+
+def electrochromic_room(seed: int = 4, n_lambda: int = 81, min_tris: int = 4_000_000, coating_state: float = 0.6):
+    """Large electrochromic workload: the furnished-room recipe grown to
+    >= 4M triangles, 81 wavelengths, panes with the five-layer coating."""
+    return furnished_room(seed=seed, n_lambda=n_lambda, min_tris=min_tris, coating_state=coating_state,
+                          name=f"electrochromic_room(seed={seed},nl={n_lambda},T>={min_tris},state={coating_state})")
 
 
 # ----------------------------------------------------------------------------
@@ -497,12 +541,14 @@ def furnace_room(seed: int = 0, n_lambda: int = 16, n_boxes: int = 20):
     return sc
 
 
-def lone_pane(n_lambda: int = 16, seed: int = 0, k: float = 1e-7, thick: float = 0.004):
+def lone_pane(n_lambda: int = 16, seed: int = 0, k: float = 1e-7, thick: float = 0.004, coating_state=None):
     """A single 1 x 1 m pane at y = 1 with a large emitter behind it (y = 2,
-    facing -y) and an orthographic camera looking along +y at normal incidence."""
+    facing -y) and an orthographic camera looking along +y at normal incidence.
+    With ``coating_state`` the pane carries the electrochromic coating on its
+    camera-side face (the face its geometric normal, -y, points out of)."""
     lam, w = lambda_grid(n_lambda)
     mats = _Materials(len(lam))
-    pane = _glass_material(mats, lam, k=k, thick=thick)
+    pane = _glass_material(mats, lam, k=k, thick=thick, coating_state=coating_state)
     sky = mats.add(EMITTER, le=planck_shape(lam))
     mesh = _Mesh()
     _rect(mesh, (0, 1, 0), (1, 0, 0), (0, 0, 1), 1, 1, pane)
@@ -514,11 +560,6 @@ def lone_pane(n_lambda: int = 16, seed: int = 0, k: float = 1e-7, thick: float =
     cam = dict(eye=(0.5, 0.0, 0.5), target=(0.5, 1.0, 0.5), fov_deg=40.0, ortho=True, ortho_half_h=0.4)
     return _finish(mesh, mats, lam, w, light_type=LIGHT_PARALLELOGRAM, light_mat=sky,
                    name="lone_pane", seed=seed, light_p0=p0, light_e1=e1, light_e2=e2, camera=cam)
-
-
-def with_lambda_count(scene, n_lambda: int):
-    """Not used by the fixtures; kept so callers can assert grid sizes."""
-    return scene["lambda_nm"].shape[0] == n_lambda
 
 
 def save_npz(scene, path):
@@ -551,4 +592,6 @@ WORKLOADS = {
     "tiny_room": dict(build=lambda: tiny_room(0, 16), W=64, H=64, spp=1, max_depth=4, grid=(2, 2, 1), seed=0),
     "furnished_room": dict(build=lambda: furnished_room(1, 41), W=512, H=512, spp=16, max_depth=8,
                            grid=(4, 4, 2), seed=0),
+    "electrochromic_room": dict(build=lambda: electrochromic_room(4, 81), W=3840, H=2160, spp=64, max_depth=8,
+                                grid=(8, 4, 4), seed=0),
 }

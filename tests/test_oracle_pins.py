@@ -391,3 +391,172 @@ def test_logs_are_consistent(tiny_scene):
                 ended = True
     sl = r["shadow_log"]
     assert set(np.unique(sl)) <= {-2, 0, 1}
+
+
+# ---------------------------------------------------------------------------
+# coherent thin-film coating (electrochromic windows): characteristic matrices
+# ---------------------------------------------------------------------------
+def _admittance(N, beta, p_pol):
+    Nc = np.sqrt(complex(N) ** 2 - beta ** 2)
+    if Nc.real < 0 or (Nc.real == 0 and Nc.imag < 0):
+        Nc = -Nc
+    return N * N / Nc if p_pol else Nc, Nc
+
+
+def _rouard_r(layers, N_in, N_out, lam_nm, beta, p_pol):
+    """Amplitude reflectance of a stack by the Rouard recursion of Airy's
+    two-interface formula, from the exit medium up: r_j = (rho_j + r_{j+1} e)
+    / (1 + rho_j r_{j+1} e), e = exp(2 i delta_j) (fields ~ exp(-i omega t),
+    N = n + i k, so Im delta > 0 attenuates)."""
+    media = [N_in] + [complex(n, k) for (_, n, k) in layers] + [N_out]
+    eta = [_admittance(N, beta, p_pol)[0] for N in media]
+    rho = [(eta[i] - eta[i + 1]) / (eta[i] + eta[i + 1]) for i in range(len(media) - 1)]
+    r = rho[-1]
+    for j in range(len(layers), 0, -1):
+        d = layers[j - 1][0]
+        Nc = _admittance(media[j], beta, p_pol)[1]
+        e = np.exp(2j * 2 * np.pi * Nc * d / (lam_nm * 1e-9))
+        r = (rho[j - 1] + r * e) / (1 + rho[j - 1] * r * e)
+    return r
+
+
+def _tmm(layers, n_in, k_in, n_out, k_out, lam, beta):
+    d = [x[0] for x in layers]
+    n = [x[1] for x in layers]
+    k = [x[2] for x in layers]
+    return ora.tmm_sp(d, n, k, n_in, k_in, n_out, k_out, lam, beta)
+
+
+@pytest.mark.parametrize("c", [1.0, 0.6, 0.15])
+def test_tmm_zero_thickness_layers_are_the_bare_interface(c):
+    beta = math.sqrt(1 - c * c)
+    layers = [(0.0, 2.1, 0.3), (0.0, 1.45, 0.0), (0.0, 2.3, 0.05)]
+    Rs, Rp, Ts, Tp = _tmm(layers, 1.0, 0.0, 1.52, 0.0, 550.0, beta)
+    Fs, Fp = ora.fresnel_sp(1.52, 0.0, c)
+    assert Rs == pytest.approx(Fs, rel=1e-12, abs=1e-15)
+    assert Rp == pytest.approx(Fp, rel=1e-12, abs=1e-15)
+    assert Ts == pytest.approx(1 - Fs, rel=1e-12)
+    assert Tp == pytest.approx(1 - Fp, rel=1e-12)
+
+
+@pytest.mark.parametrize("c", [1.0, 0.7, 0.3])
+@pytest.mark.parametrize("layer", [(120e-9, 1.9, 0.0), (80e-9, 2.2, 0.35)])
+def test_tmm_single_layer_is_airy(c, layer):
+    beta = math.sqrt(1 - c * c)
+    lam = 520.0
+    Rs, Rp, _, _ = _tmm([layer], 1.0, 0.0, 1.52, 0.0, lam, beta)
+    # Airy: r = (r01 + r12 exp(2 i delta)) / (1 + r01 r12 exp(2 i delta)) with
+    # Fresnel amplitudes written from Snell's law directly
+    N1, Ns = complex(layer[1], layer[2]), 1.52
+    for p_pol, R in ((False, Rs), (True, Rp)):
+        c1 = np.sqrt(1 - (beta / N1) ** 2)
+        cs = np.sqrt(1 - (beta / Ns) ** 2)
+        if p_pol:
+            r01 = (N1 * c - 1.0 * c1) / (N1 * c + 1.0 * c1)
+            r12 = (Ns * c1 - N1 * cs) / (Ns * c1 + N1 * cs)
+        else:
+            r01 = (c - N1 * c1) / (c + N1 * c1)
+            r12 = (N1 * c1 - Ns * cs) / (N1 * c1 + Ns * cs)
+        e = np.exp(2j * 2 * np.pi * N1 * c1 * layer[0] / (lam * 1e-9))
+        r = (r01 + r12 * e) / (1 + r01 * r12 * e)
+        assert R == pytest.approx(abs(r) ** 2, rel=1e-10, abs=1e-14)
+
+
+@pytest.mark.parametrize("state", [0.0, 0.5, 1.0])
+@pytest.mark.parametrize("c", [1.0, 0.5, 0.1])
+def test_tmm_electrochromic_stack_matches_rouard_recursion(state, c):
+    lam = sg.lambda_grid(16)[0]
+    lay = sg.electrochromic_layers(lam, state)
+    beta = math.sqrt(1 - c * c)
+    for l in (0, 7, 15):
+        layers = [(float(d), float(n[l]), float(k[l])) for (d, n, k) in lay]
+        Rs, Rp, Ts, Tp = _tmm(layers, 1.0, 0.0, 1.52, 0.0, float(lam[l]), beta)
+        for p_pol, R in ((False, Rs), (True, Rp)):
+            r = _rouard_r(layers, 1.0, 1.52, float(lam[l]), beta, p_pol)
+            assert R == pytest.approx(abs(r) ** 2, rel=1e-9, abs=1e-13)
+        # absorbing layers: 0 <= R, T and R + T <= 1
+        for R, T in ((Rs, Ts), (Rp, Tp)):
+            assert 0 <= R <= 1 and 0 <= T <= 1 and R + T <= 1 + 1e-12
+
+
+def test_tmm_quarter_wave_antireflection():
+    ns, lam0 = 1.52, 550.0
+    n1 = math.sqrt(ns)
+    layer = [(lam0 * 1e-9 / (4 * n1), n1, 0.0)]
+    Rs, Rp, Ts, Tp = _tmm(layer, 1.0, 0.0, ns, 0.0, lam0, 0.0)
+    assert Rs < 1e-20 and Rp < 1e-20
+    assert Ts == pytest.approx(1.0, rel=1e-12)
+    bare = ora.fresnel_sp(ns, 0.0, 1.0)[0]
+    for lam in (400.0, 750.0):
+        R = _tmm(layer, 1.0, 0.0, ns, 0.0, lam, 0.0)[0]
+        assert 0 < R < bare
+
+
+@pytest.mark.parametrize("c", [1.0, 0.8, 0.4, 0.05])
+def test_tmm_lossless_stack_conserves_energy(c):
+    beta = math.sqrt(1 - c * c)
+    layers = [(150e-9, 1.85, 0.0), (300e-9, 2.05, 0.0), (200e-9, 1.45, 0.0), (100e-9, 2.15, 0.0), (150e-9, 1.85, 0.0)]
+    Rs, Rp, Ts, Tp = _tmm(layers, 1.0, 0.0, 1.52, 0.0, 480.0, beta)
+    assert Rs + Ts == pytest.approx(1.0, abs=1e-12)
+    assert Rp + Tp == pytest.approx(1.0, abs=1e-12)
+
+
+def test_thick_absorbing_layer_is_semi_infinite():
+    c = math.sqrt(1 - 0.09)
+    Rs, Rp, Ts, Tp = _tmm([(5e-6, 2.0, 0.5)], 1.0, 0.0, 1.5, 0.0, 500.0, 0.3)
+    N = complex(2.0, 0.5)
+    Nc = np.sqrt(N * N - 0.09)
+    assert Rs == pytest.approx(abs((c - Nc) / (c + Nc)) ** 2, rel=1e-9)
+    assert Rp == pytest.approx(abs((N * N / Nc - 1 / c) / (N * N / Nc + 1 / c)) ** 2, rel=1e-9)
+    assert Ts < 1e-20 and Tp < 1e-20
+
+
+@pytest.mark.parametrize("c", [1.0, 0.5])
+def test_coated_pane_without_coating_is_the_slab(c):
+    for side in (True, False):
+        Rc, Tc = ora.coated_pane(1.52, 2e-6, 0.004, [], [], [], 600.0, c, side)
+        Rsl, Tsl = ora.slab(1.52, 2e-6, 0.004, 600.0, c)
+        assert Rc == pytest.approx(Rsl, rel=1e-13)
+        assert Tc == pytest.approx(Tsl, rel=1e-13)
+        Rz, Tz = ora.coated_pane(1.52, 2e-6, 0.004, [0.0, 0.0], [2.0, 1.5], [0.4, 0.0], 600.0, c, side)
+        assert Rz == pytest.approx(Rsl, rel=1e-12)
+        assert Tz == pytest.approx(Tsl, rel=1e-12)
+
+
+@pytest.mark.parametrize("state", [0.2, 1.0])
+def test_coated_pane_reciprocity_and_energy(state):
+    lam = sg.lambda_grid(41)[0]
+    lay = sg.electrochromic_layers(lam, state)
+    for l in (3, 20, 38):
+        d = [float(x[0]) for x in lay]
+        n = [float(x[1][l]) for x in lay]
+        k = [float(x[2][l]) for x in lay]
+        for c in (1.0, 0.6, 0.2):
+            Rf, Tf = ora.coated_pane(1.52, 1e-7, 0.004, d, n, k, float(lam[l]), c, True)
+            Rb, Tb = ora.coated_pane(1.52, 1e-7, 0.004, d, n, k, float(lam[l]), c, False)
+            assert Tf == pytest.approx(Tb, rel=1e-11)       # reciprocity of transmission
+            assert Rf != pytest.approx(Rb, rel=1e-6)        # absorbing coating: R depends on the side
+            for R, T in ((Rf, Tf), (Rb, Tb)):
+                assert 0 < R < 1 and 0 < T < 1 and R + T < 1
+
+
+def test_coated_pane_transmission_branch():
+    sc = sg.lone_pane(coating_state=0.8)
+    W = H = 8
+    r = ora.render(sc, W, H, 64, 2, path_L=True)
+    nl = sc["mat_rho"].shape[1]
+    L = r["path_L"].reshape(-1, nl)
+    Le = sc["mat_le"][1].astype(np.float64)
+    R = np.zeros(nl)
+    T = np.zeros(nl)
+    for l in range(nl):
+        d = sc["mat_layer_d"][0].astype(np.float64)
+        R[l], T[l] = ora.coated_pane(float(sc["mat_n"][0, l]), float(sc["mat_k"][0, l]), float(sc["mat_thick"][0]),
+                                     d, sc["mat_layer_n"][0, :, l].astype(np.float64),
+                                     sc["mat_layer_k"][0, :, l].astype(np.float64), float(sc["lambda_nm"][l]), 1.0,
+                                     True)
+    PR = R.mean() / (R.mean() + T.mean())
+    trans = np.all(L > 0, axis=1)
+    # camera rays meet the coated face (the pane's normal faces the camera)
+    assert np.allclose(L[trans], (Le * T / (1 - PR))[None, :], rtol=1e-12)
+    assert trans.any()
