@@ -40,6 +40,9 @@ WORKLOADS = {
     "furnished_room": dict(scene=("furnished_room", dict(seed=1, n_lambda=41)), W=512, H=512, spp=16, D=8,
                            grid=(4, 4, 2)),
     "tiny_room": dict(scene=("tiny_room", dict(seed=0, n_lambda=16)), W=64, H=64, spp=1, D=4, grid=(2, 2, 1)),
+    # 4M triangles, coated (electrochromic) panes, 81 wavelengths, 128 subdomains
+    "electrochromic_room": dict(scene=("electrochromic_room", dict(seed=4, n_lambda=81)), W=3840, H=2160, spp=64,
+                                D=8, grid=(8, 4, 4)),
 }
 
 

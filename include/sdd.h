@@ -56,6 +56,7 @@ enum { SDD_LIGHT_NONE = 0, SDD_LIGHT_PARALLELOGRAM = 1, SDD_LIGHT_POINT = 2 };
 #define SDD_MAX_LAMBDA 128
 #define SDD_MAX_CELLS 512
 #define SDD_MAX_DEPTH 64
+#define SDD_MAX_LAYERS 8
 
 typedef struct sdd_ctx sdd_ctx;
 
@@ -78,6 +79,17 @@ typedef struct sdd_ctx sdd_ctx;
  * Light (one at most): PARALLELOGRAM {p0, e1, e2} emits mat_le[light_mat] on
  *   the side of e1 x e2 (its triangles must also be in tris with an EMITTER
  *   material); POINT {p0} with intensity mat_le[light_mat] (Eq. 3).
+ * Optional coatings (electrochromic windows; all NULL and max_layers = 0 for
+ * none): a GLASS_SLAB material m may carry mat_n_layers[m] coherent thin
+ * films on the face its triangles' geometric normal (v1 - v0) x (v2 - v0)
+ * points out of, listed from the air side:
+ *   max_layers   Lm in [0, SDD_MAX_LAYERS]
+ *   mat_n_layers int32 [n_mats]          in [0, Lm] (0 for non-glass)
+ *   mat_layer_d  float [n_mats][Lm]      thickness (m), >= 0
+ *   mat_layer_n  float [n_mats][Lm][n_lambda]  n > 0
+ *   mat_layer_k  float [n_mats][Lm][n_lambda]  k >= 0
+ * The pane's R and T then come from the layers' characteristic (transfer)
+ * matrices combined incoherently with the substrate (see sdd_debug_glass).
  */
 typedef struct sdd_scene_desc {
     int32_t n_verts;
@@ -99,6 +111,11 @@ typedef struct sdd_scene_desc {
     int32_t light_type;
     float light_p0[3], light_e1[3], light_e2[3];
     int32_t light_mat;
+    int32_t max_layers;
+    const int32_t *mat_n_layers;
+    const float *mat_layer_d;
+    const float *mat_layer_n;
+    const float *mat_layer_k;
 } sdd_scene_desc;
 
 /*
@@ -139,9 +156,9 @@ typedef struct sdd_bvh_desc {
  *     0 (blocked) or -2 (no shadow ray) per vertex.  NULL to skip.
  */
 typedef struct sdd_trace_desc {
-    float eye[3], target[3];
-    float fov_deg;
-    float ortho_half_h;
+    double eye[3], target[3];
+    double fov_deg;
+    double ortho_half_h;
     int32_t W, H;
     int32_t spp;
     int32_t sample_offset;
@@ -246,6 +263,16 @@ sdd_status sdd_debug_pane(sdd_ctx *ctx, int32_t n, const float *params, float *R
  * t_out: host float [n] (+inf on a miss); prim_out: host int32 [n] (-1). */
 sdd_status sdd_debug_trace_rays(sdd_ctx *ctx, int32_t n, const float *o, const float *d, float *t_out,
                                 int32_t *prim_out);
+
+/* Device evaluation of the loaded scene's glass terms, exactly as the path
+ * uses them (Eq. 1; Sec. 6 slab; coated panes by characteristic matrices
+ * combined incoherently with the substrate, polarisation-averaged).  For
+ * i < n: material mat[i] (must be GLASS_SLAB), wavelength index lam[i],
+ * signed incidence cosine cs[i] (|cs| = cos theta; cs > 0: the light
+ * arrives on the face the geometric normal points out of, the coated face).
+ * Host arrays; R_out, T_out: host float [n]. */
+sdd_status sdd_debug_glass(sdd_ctx *ctx, int32_t n, const int32_t *mat, const int32_t *lam, const float *cs,
+                           float *R_out, float *T_out);
 
 #ifdef __cplusplus
 }

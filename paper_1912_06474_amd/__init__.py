@@ -29,7 +29,7 @@ TRACE_ORTHO, TRACE_TIME_KERNELS, TRACE_COUNT_WORK = 1, 2, 4
 
 EXPORTS = ("sdd_create", "sdd_destroy", "sdd_last_error", "sdd_load_scene", "sdd_validate_scene", "sdd_build_bvh",
            "sdd_trace_spectral", "sdd_resolve_image", "sdd_reset_render", "sdd_get_stats", "sdd_reset_stats",
-           "sdd_debug_philox", "sdd_debug_pane", "sdd_debug_trace_rays")
+           "sdd_debug_philox", "sdd_debug_pane", "sdd_debug_trace_rays", "sdd_debug_glass")
 
 
 class SddError(RuntimeError):
@@ -47,6 +47,8 @@ class SceneDesc(C.Structure):
         ("mat_k", C.c_void_p), ("mat_thick", C.c_void_p), ("mat_le", C.c_void_p),
         ("light_type", C.c_int32), ("light_p0", C.c_float * 3), ("light_e1", C.c_float * 3),
         ("light_e2", C.c_float * 3), ("light_mat", C.c_int32),
+        ("max_layers", C.c_int32), ("mat_n_layers", C.c_void_p), ("mat_layer_d", C.c_void_p),
+        ("mat_layer_n", C.c_void_p), ("mat_layer_k", C.c_void_p),
     ]
 
 
@@ -57,7 +59,7 @@ class BvhDesc(C.Structure):
 
 class TraceDesc(C.Structure):
     _fields_ = [
-        ("eye", C.c_float * 3), ("target", C.c_float * 3), ("fov_deg", C.c_float), ("ortho_half_h", C.c_float),
+        ("eye", C.c_double * 3), ("target", C.c_double * 3), ("fov_deg", C.c_double), ("ortho_half_h", C.c_double),
         ("W", C.c_int32), ("H", C.c_int32), ("spp", C.c_int32), ("sample_offset", C.c_int32),
         ("max_depth", C.c_int32), ("seed", C.c_uint32), ("render_id", C.c_int32), ("flags", C.c_uint32),
         ("hit_log", C.c_void_p), ("shadow_log", C.c_void_p),
@@ -107,6 +109,7 @@ def lib():
         L.sdd_debug_philox.argtypes = [vp, i32, vp, vp, vp]
         L.sdd_debug_pane.argtypes = [vp, i32, vp, vp, vp]
         L.sdd_debug_trace_rays.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.sdd_debug_glass.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         _LIB = L
     return _LIB
 
@@ -142,6 +145,12 @@ class _SceneArrays:
         d.light_e1[:] = [float(x) for x in np.asarray(scene["light_e1"]).reshape(3)]
         d.light_e2[:] = [float(x) for x in np.asarray(scene["light_e2"]).reshape(3)]
         d.light_mat = int(scene["light_mat"])
+        if "mat_n_layers" in scene:
+            nlay = arr("mat_n_layers", np.int32)
+            ld = arr("mat_layer_d", np.float32)
+            ln, lk = arr("mat_layer_n", np.float32), arr("mat_layer_k", np.float32)
+            d.max_layers = int(ld.shape[1]) if ld.ndim == 2 else 0
+            d.mat_n_layers, d.mat_layer_d, d.mat_layer_n, d.mat_layer_k = _ptr(nlay), _ptr(ld), _ptr(ln), _ptr(lk)
         self.desc = d
         self.n_lambda = len(lam)
 
@@ -259,6 +268,19 @@ class Tracer:
         R = np.zeros(len(params), np.float32)
         T = np.zeros(len(params), np.float32)
         self._check(lib().sdd_debug_pane(self.h, len(params), _ptr(params), _ptr(R), _ptr(T)))
+        return R, T
+
+    def debug_glass(self, mat, lam_idx, cs):
+        """Glass R, T of the loaded scene: material indices, wavelength indices and
+        signed incidence cosines (> 0: the coated, normal-side face).  float32 arrays."""
+        mat = np.ascontiguousarray(mat, np.int32).reshape(-1)
+        lam_idx = np.ascontiguousarray(lam_idx, np.int32).reshape(-1)
+        cs = np.ascontiguousarray(cs, np.float32).reshape(-1)
+        if not (len(mat) == len(lam_idx) == len(cs)):
+            raise ValueError("mat, lam_idx and cs must have the same length")
+        R = np.zeros(len(cs), np.float32)
+        T = np.zeros(len(cs), np.float32)
+        self._check(lib().sdd_debug_glass(self.h, len(cs), _ptr(mat), _ptr(lam_idx), _ptr(cs), _ptr(R), _ptr(T)))
         return R, T
 
     def debug_trace_rays(self, o, d):

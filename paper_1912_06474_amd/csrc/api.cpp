@@ -67,6 +67,9 @@ struct sdd_ctx {
     float4* d_prim_info = nullptr;
     float4* d_prim_v = nullptr;  // [T][3] triangle vertices (w unused), for FP64 shading geometry
     float4* d_pane = nullptr;  // [n_glass][nlp] pane constants
+    float4* d_coat = nullptr;  // [n_glass][coat_layers][nlp] coating layer constants (if any)
+    int* d_coat_n = nullptr;   // [n_glass] coating layers (if any)
+    int max_layers = 0, coat_layers = 0;
     float* d_rho = nullptr;
     float* d_le = nullptr;
     double* d_w = nullptr;
@@ -86,8 +89,8 @@ struct sdd_ctx {
     // batch buffers
     long long ncap = 0;
     int dcap = 0;  // depth capacity of the counter arrays
-    float4* ray_o = nullptr;
-    float4* ray_d = nullptr;
+    D4* ray_o = nullptr;  // FP64 path state
+    D4* ray_d = nullptr;
     float2* hit = nullptr;
     uint32_t* flags = nullptr;
     // path history [depth][path]
@@ -194,6 +197,9 @@ void free_scene(sdd_ctx* c) {
     dfree(c, c->d_prim_info);
     dfree(c, c->d_prim_v);
     dfree(c, c->d_pane);
+    dfree(c, c->d_coat);
+    dfree(c, c->d_coat_n);
+    c->coat_layers = 0;
     dfree(c, c->d_rho);
     dfree(c, c->d_le);
     dfree(c, c->d_w);
@@ -276,6 +282,25 @@ std::string validate(const sdd_scene_desc* s) {
             if (t == SDD_MAT_GLASS_SLAB && s->mat_le[i] != 0.0f) return "glass material cannot emit";
         }
     }
+    if (s->max_layers < 0 || s->max_layers > SDD_MAX_LAYERS) return "max_layers out of range";
+    if (s->max_layers > 0) {
+        if (!s->mat_n_layers || !s->mat_layer_d || !s->mat_layer_n || !s->mat_layer_k) return "null coating arrays";
+        const int Lm = s->max_layers;
+        for (int m = 0; m < s->n_mats; ++m) {
+            const int L = s->mat_n_layers[m];
+            if (L < 0 || L > Lm) return "coating layer count out of range";
+            if (L > 0 && s->mat_type[m] != SDD_MAT_GLASS_SLAB) return "only glass materials carry coatings";
+            for (int j = 0; j < L; ++j) {
+                const float d = s->mat_layer_d[(size_t)m * Lm + j];
+                if (!(d >= 0.0f) || !std::isfinite(d)) return "coating layer thickness must be >= 0";
+                for (int l = 0; l < nl; ++l) {
+                    const size_t i = ((size_t)m * Lm + j) * nl + l;
+                    if (!(s->mat_layer_n[i] > 0.0f) || !std::isfinite(s->mat_layer_n[i])) return "coating n must be > 0";
+                    if (!(s->mat_layer_k[i] >= 0.0f) || !std::isfinite(s->mat_layer_k[i])) return "coating k must be >= 0";
+                }
+            }
+        }
+    }
     if (s->light_type != SDD_LIGHT_NONE && s->light_type != SDD_LIGHT_PARALLELOGRAM && s->light_type != SDD_LIGHT_POINT)
         return "unknown light type";
     if (s->light_type != SDD_LIGHT_NONE) {
@@ -343,7 +368,7 @@ long long mem_budget_bytes() {
 }
 
 long long bytes_per_path(const sdd_ctx* c, int max_depth) {
-    return 4LL * c->G * (16 + 16 + 8) + 2 * (16 + 16 + 8 + 4) + 16 + 16 + 8 + 4 +
+    return 4LL * c->G * (16 + 16 + 8) + 2 * (16 + 16 + 8 + 4) + 32 + 32 + 8 + 4 +
            (long long)max_depth * (16 + 4 + 8 * kMaxGlass);
 }
 
@@ -607,6 +632,34 @@ sdd_status sdd_load_scene(sdd_ctx* c, const sdd_scene_desc* s) {
                     make_float4((float)(n * n - k * k), (float)(2.0 * n * k), (float)(1.0 / (n * n)), (float)at);
             }
         }
+    // coherent coatings: per (glass, layer, wavelength) (Re N^2, Im N^2, 2 pi d / lambda)
+    c->max_layers = s->max_layers > 0 ? s->max_layers : 0;
+    std::vector<int> coat_n((size_t)std::max(1, c->n_glass), 0);
+    bool any_coat = false;
+    if (c->max_layers > 0)
+        for (int m = 0; m < M; ++m)
+            if (c->glass_of[m] >= 0) {
+                coat_n[c->glass_of[m]] = s->mat_n_layers[m];
+                any_coat = any_coat || s->mat_n_layers[m] > 0;
+            }
+    const int Lm = std::max(1, c->max_layers);
+    std::vector<float4> coat((size_t)std::max(1, c->n_glass) * Lm * nlp, make_float4(1.0f, 0.0f, 0.0f, 0.0f));
+    if (any_coat)
+        for (int m = 0; m < M; ++m) {
+            const int g = c->glass_of[m];
+            if (g < 0) continue;
+            for (int j = 0; j < s->mat_n_layers[m]; ++j) {
+                const double d = s->mat_layer_d[(size_t)m * c->max_layers + j];
+                for (int l = 0; l < nl; ++l) {
+                    const size_t i = ((size_t)m * c->max_layers + j) * nl + l;
+                    const double n = s->mat_layer_n[i], k = s->mat_layer_k[i];
+                    coat[((size_t)g * Lm + j) * nlp + l] = make_float4(
+                        (float)(n * n - k * k), (float)(2.0 * n * k),
+                        (float)(2.0 * M_PI * d / ((double)s->lambda_nm[l] * 1e-9)), 0.0f);
+                }
+            }
+        }
+    c->coat_layers = any_coat ? Lm : 0;
     BuildInput bi{c->verts.data(), c->V, c->tris.data(), c->T, c->tri_mat.data(), c->mat_type.data(),
                   c->glass_of.data(), c->mat_emits.data(), 1, 1, 1, 4, 16};
     std::vector<HostF4> info;
@@ -621,6 +674,8 @@ sdd_status sdd_load_scene(sdd_ctx* c, const sdd_scene_desc* s) {
     if ((st = upload(c, &c->d_prim_info, reinterpret_cast<const float4*>(info.data()), info.size())) != SDD_OK ||
         (st = upload(c, &c->d_prim_v, prim_v.data(), prim_v.size())) != SDD_OK ||
         (st = upload(c, &c->d_pane, pane.data(), pane.size())) != SDD_OK ||
+        (any_coat && (st = upload(c, &c->d_coat, coat.data(), coat.size())) != SDD_OK) ||
+        (any_coat && (st = upload(c, &c->d_coat_n, coat_n.data(), coat_n.size())) != SDD_OK) ||
         (st = upload(c, &c->d_rho, rho.data(), rho.size())) != SDD_OK ||
         (st = upload(c, &c->d_le, le.data(), le.size())) != SDD_OK ||
         (st = upload(c, &c->d_w, s->lambda_w, (size_t)nl)) != SDD_OK ||
@@ -775,12 +830,12 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         cp.ortho = ortho ? 1 : 0;
         for (int k = 0; k < 3; ++k) {
             cp.eye[k] = t->eye[k];
-            cp.fwd[k] = (float)f[k];
-            cp.right[k] = (float)r[k];
-            cp.up[k] = (float)u[k];
+            cp.fwd[k] = f[k];
+            cp.right[k] = r[k];
+            cp.up[k] = u[k];
         }
-        cp.tan_half = (float)std::tan(0.5 * (double)t->fov_deg * M_PI / 180.0);
-        cp.aspect = (float)((double)t->W / (double)t->H);
+        cp.tan_half = std::tan(0.5 * t->fov_deg * M_PI / 180.0);
+        cp.aspect = (double)t->W / (double)t->H;
         cp.ortho_half_h = t->ortho_half_h;
         cp.flags = c->flags;
         cp.ray_o = c->ray_o;
@@ -816,6 +871,9 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         sp.prim_info = c->d_prim_info;
         sp.prim_v = c->d_prim_v;
         sp.pane = c->d_pane;
+        sp.coat = c->d_coat;
+        sp.coat_n = c->coat_layers ? c->d_coat_n : nullptr;
+        sp.coat_layers = c->coat_layers;
         sp.n_glass = c->n_glass;
         sp.nl = c->nl;
         sp.nlp = c->nlp;
@@ -866,6 +924,9 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         xp.sh_glass = c->sh_glass;
         xp.pane = c->d_pane;
         xp.n_glass = std::max(1, c->n_glass);
+        xp.coat = c->d_coat;
+        xp.coat_n = c->coat_layers ? c->d_coat_n : nullptr;
+        xp.coat_layers = c->coat_layers;
         xp.n_mats = c->M;
         xp.rho = c->d_rho;
         xp.le = c->d_le;
@@ -1041,6 +1102,48 @@ sdd_status sdd_debug_pane(sdd_ctx* c, int32_t n, const float* params, float* R_o
     dfree(c, dc);
     dfree(c, dout);
     if (e != hipSuccess) return hip_fail(c, e, "debug pane");
+    for (int i = 0; i < n; ++i) {
+        R_out[i] = h[i].x;
+        T_out[i] = h[i].y;
+    }
+    return SDD_OK;
+}
+
+sdd_status sdd_debug_glass(sdd_ctx* c, int32_t n, const int32_t* mat, const int32_t* lam, const float* cs,
+                           float* R_out, float* T_out) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!c->has_scene) return fail(c, SDD_ERR_STATE, "sdd_debug_glass before sdd_load_scene");
+    if (n < 0 || (n > 0 && (!mat || !lam || !cs || !R_out || !T_out)))
+        return fail(c, SDD_ERR_INVALID_ARG, "bad glass arguments");
+    if (n == 0) return SDD_OK;
+    std::vector<int4> q((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        if (mat[i] < 0 || mat[i] >= c->M || c->glass_of[mat[i]] < 0)
+            return fail(c, SDD_ERR_INVALID_ARG, "material is not a glass material");
+        if (lam[i] < 0 || lam[i] >= c->nl) return fail(c, SDD_ERR_INVALID_ARG, "wavelength index out of range");
+        if (!(std::fabs(cs[i]) <= 1.0f)) return fail(c, SDD_ERR_INVALID_ARG, "cosine outside [-1, 1]");
+        float f = cs[i];
+        int bits;
+        std::memcpy(&bits, &f, 4);
+        q[i] = make_int4(c->glass_of[mat[i]], lam[i], bits, 0);
+    }
+    DeviceGuard g(c->device);
+    int4* dq = nullptr;
+    float2* dout = nullptr;
+    if (dalloc(c, &dq, (size_t)n) != SDD_OK || dalloc(c, &dout, (size_t)n) != SDD_OK) {
+        dfree(c, dq);
+        return SDD_ERR_OOM;
+    }
+    std::vector<float2> h((size_t)n);
+    GlassTable tab{c->d_pane, c->d_coat, c->coat_layers ? c->d_coat_n : nullptr, c->coat_layers, c->nlp};
+    hipError_t e = hipMemcpyAsync(dq, q.data(), sizeof(int4) * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_glass(n, tab, dq, dout, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), dout, sizeof(float2) * (size_t)n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(c, dq);
+    dfree(c, dout);
+    if (e != hipSuccess) return hip_fail(c, e, "debug glass");
     for (int i = 0; i < n; ++i) {
         R_out[i] = h[i].x;
         T_out[i] = h[i].y;

@@ -112,6 +112,131 @@ __device__ __forceinline__ void pane_RT(float4 pc, float c, float& R_out, float&
     T_out = 0.5f * Tsum;
 }
 
+// ---------------------------------------------------------------------------
+// complex arithmetic (FP32) for coherent coatings
+// ---------------------------------------------------------------------------
+struct cpx {
+    float re, im;
+};
+__device__ __forceinline__ cpx cadd(cpx a, cpx b) { return cpx{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cpx csub(cpx a, cpx b) { return cpx{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cpx cmul(cpx a, cpx b) { return cpx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cpx cscale(cpx a, float s) { return cpx{a.re * s, a.im * s}; }
+__device__ __forceinline__ float cabs2(cpx a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ cpx cdiv(cpx a, cpx b) {
+    const float inv = 1.0f / cabs2(b);
+    return cpx{(a.re * b.re + a.im * b.im) * inv, (a.im * b.re - a.re * b.im) * inv};
+}
+// principal square root (re >= 0)
+__device__ __forceinline__ cpx csqrt_p(cpx z) {
+    const float m = sqrtf(z.re * z.re + z.im * z.im);
+    if (z.re >= 0.0f) {
+        const float u = sqrtf(0.5f * (m + z.re));
+        return cpx{u, u > 0.0f ? z.im / (2.0f * u) : 0.0f};
+    }
+    const float v = copysignf(sqrtf(0.5f * (m - z.re)), z.im);
+    return cpx{z.im / (2.0f * v), v};
+}
+// cos and sin of a complex argument a + i b
+__device__ __forceinline__ void csincos(cpx z, cpx& sn, cpx& cs) {
+    float s, c;
+    sincosf(z.re, &s, &c);
+    const float ep = expf(z.im), em = 1.0f / ep;
+    const float ch = 0.5f * (ep + em), sh = 0.5f * (ep - em);
+    sn = cpx{s * ch, c * sh};
+    cs = cpx{c * ch, -s * sh};
+}
+
+// 2 x 2 complex matrix, right-multiplied by a layer's characteristic matrix
+// [[cos D, -i sin D / eta], [-i eta sin D, cos D]]
+struct CMat {
+    cpx m11{1.0f, 0.0f}, m12{0.0f, 0.0f}, m21{0.0f, 0.0f}, m22{1.0f, 0.0f};
+    __device__ __forceinline__ void times_layer(cpx cs, cpx sn, cpx eta) {
+        const cpx t12 = cdiv(sn, eta), t21 = cmul(eta, sn);
+        const cpx a12{t12.im, -t12.re}, a21{t21.im, -t21.re};  // times -i
+        const cpx n11 = cadd(cmul(m11, cs), cmul(m12, a21)), n12 = cadd(cmul(m11, a12), cmul(m12, cs));
+        const cpx n21 = cadd(cmul(m21, cs), cmul(m22, a21)), n22 = cadd(cmul(m21, a12), cmul(m22, cs));
+        m11 = n11;
+        m12 = n12;
+        m21 = n21;
+        m22 = n22;
+    }
+};
+
+// Pane with a coherent coating of L layers on its coated face (thin-film
+// optics by characteristic matrices; the index is n + i k with fields
+// ~ exp(-i omega t)).  pc: substrate pane constants as for pane_RT; lay[j *
+// stride]: per layer (Re N^2, Im N^2, 2 pi d / lambda); c: incidence cosine
+// in air; coated_side: the light arrives on the coated face.  With beta^2 =
+// 1 - c^2, every medium has w = sqrt(N^2 - beta^2) (= N cos theta, principal
+// root) and admittance w (s) or N^2 / w (p); a layer's matrix is
+// [[cos D, -i sin D / eta], [-i eta sin D, cos D]], D = (2 pi d / lambda) w.
+// With M = M_1 ... M_L, the stack seen from air gives B = m11 + m12 eta_s,
+// C = m21 + m22 eta_s, r = (eta_0 B - C) / (eta_0 B + C),
+// T = 4 eta_0 Re(eta_s) / |eta_0 B + C|^2; seen from the substrate the
+// product runs backwards, which for these matrices swaps m11 and m22.  The
+// two faces then combine incoherently through the substrate (Beer-Lambert
+// tau as for the uncoated pane), per polarisation, and (s + p) / 2 is taken.
+__device__ __forceinline__ void coated_RT(float4 pc, const float4* lay, int L, int stride, float c, bool coated_side,
+                                          float& R_out, float& T_out) {
+    if (!(c > 1e-6f)) {
+        R_out = 1.0f;
+        T_out = 0.0f;
+        return;
+    }
+    const float b2 = 1.0f - c * c;
+    const cpx Ns2{pc.x, pc.y};
+    const cpx ws = csqrt_p(cpx{pc.x - b2, pc.y});
+    // product matrices for s and p
+    CMat ms, mp;
+    for (int j = 0; j < L; ++j) {
+        const float4 q = lay[(size_t)j * stride];
+        const cpx N2{q.x, q.y};
+        const cpx w = csqrt_p(cpx{q.x - b2, q.y});
+        cpx sn, cs;
+        csincos(cscale(w, q.z), sn, cs);
+        ms.times_layer(cs, sn, w);
+        mp.times_layer(cs, sn, cdiv(N2, w));
+    }
+    const float cosr2 = 1.0f - b2 * pc.z;
+    const float tau = cosr2 > 0.0f ? expf(-pc.w / sqrtf(cosr2)) : 0.0f;
+    const float tau2 = tau * tau;
+    float Rsum = 0.0f, Tsum = 0.0f;
+#pragma unroll
+    for (int pol = 0; pol < 2; ++pol) {
+        const CMat& M = pol ? mp : ms;
+        const float e0 = pol ? 1.0f / c : c;
+        const cpx em = pol ? cdiv(Ns2, ws) : ws;
+        // coated face from air
+        const cpx B = cadd(M.m11, cmul(M.m12, em)), C = cadd(M.m21, cmul(M.m22, em));
+        const cpx den = cadd(cscale(B, e0), C);
+        const float inv_den = 1.0f / cabs2(den);
+        const float Rc = cabs2(csub(cscale(B, e0), C)) * inv_den;
+        const float Tc = 4.0f * e0 * em.re * inv_den;
+        // coated face from the substrate (reversed product: m11 <-> m22)
+        const cpx B2 = cadd(M.m22, cscale(M.m12, e0)), C2 = cadd(M.m21, cscale(M.m11, e0));
+        const cpx den2 = cadd(cmul(em, B2), C2);
+        const float Rc2 = cabs2(csub(cmul(em, B2), C2)) / cabs2(den2);
+        // bare face
+        const float Rb = cabs2(csub(cpx{e0, 0.0f}, em)) / cabs2(cadd(cpx{e0, 0.0f}, em));
+        const float Tb = 1.0f - Rb;
+        const float dn = 1.0f - Rc2 * Rb * tau2;
+        if (!(dn > 0.0f)) {
+            Rsum += 1.0f;
+            continue;
+        }
+        if (coated_side) {
+            Tsum += Tc * tau * Tb / dn;
+            Rsum += Rc + Tc * Tc * Rb * tau2 / dn;
+        } else {
+            Tsum += Tb * tau * Tc / dn;
+            Rsum += Rb + Tb * Tb * Rc2 * tau2 / dn;
+        }
+    }
+    R_out = 0.5f * Rsum;
+    T_out = 0.5f * Tsum;
+}
+
 // Cosine-weighted direction about the unit normal n (pdf cos/pi), with the
 // orthonormal basis of Duff et al. (JCGT 2017); the branch sign is +1 for
 // both signed zeros of n.z.
@@ -125,6 +250,20 @@ __device__ __forceinline__ f3 cosine_dir(f3 n, float u0, float u1) {
     float sp, cp;
     sincosf(2.0f * kPi * u1, &sp, &cp);
     const float lz = sqrtf(1.0f - u0);
+    return b1 * (r * cp) + b2 * (r * sp) + n * lz;
+}
+
+// The same in FP64 (the path's shading geometry).
+__device__ __forceinline__ d3 cosine_dir64(d3 n, double u0, double u1) {
+    const double s = n.z >= 0.0 ? 1.0 : -1.0;
+    const double a = -1.0 / (s + n.z);
+    const double b = n.x * n.y * a;
+    const d3 b1{1.0 + s * n.x * n.x * a, s * b, -s * n.x};
+    const d3 b2{b, s + n.y * n.y * a, -n.y};
+    const double r = sqrt(u0);
+    double sp, cp;
+    sincos(2.0 * 3.14159265358979323846 * u1, &sp, &cp);
+    const double lz = sqrt(1.0 - u0);
     return b1 * (r * cp) + b2 * (r * sp) + n * lz;
 }
 

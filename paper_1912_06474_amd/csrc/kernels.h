@@ -17,6 +17,8 @@ hipError_t launch_resolve(int WH, int nl, int nlp, double inv_spp, const float* 
                           const double* cmf, double* spectral, double* xyz, hipStream_t st);
 hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
 hipError_t launch_pane(int n, const float4* pc, const float* c, float2* out, hipStream_t st);
+// q[i] = (glass index, wavelength index, signed cosine bits, 0)
+hipError_t launch_glass(int n, const GlassTable& tab, const int4* q, float2* out, hipStream_t st);
 hipError_t launch_philox(int n, const uint4* ctr, uint2 key, uint4* out, hipStream_t st);
 hipError_t launch_debug_rays(int n, const float* o, const float* d, const GridParams& grid, float2* hit, float4* qa,
                              float4* qb, int2* qc, int* cnt, long long cap, hipStream_t st);

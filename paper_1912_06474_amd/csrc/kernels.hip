@@ -23,6 +23,33 @@
 namespace sdd {
 
 // ---------------------------------------------------------------------------
+// glass terms: uncoated slab or coated pane, by the sign convention of the
+// stored cosine cs (> 0: the light arrives on the face the geometric normal
+// points out of, where a coating lies)
+// ---------------------------------------------------------------------------
+// COATED: the scene has coated glass (kernels are instantiated both ways, so
+// scenes without coatings keep the small uncoated code)
+template <bool COATED>
+__device__ __forceinline__ void glass_RT(const float4* pane, const float4* coat, const int* coat_n, int coat_layers,
+                                         int nlp, int g, int l, float cs, float& R, float& T) {
+    const float4 pc = pane[(size_t)g * nlp + l];
+    const int L = COATED ? coat_n[g] : 0;
+    if (!COATED || L <= 0) pane_RT(pc, fabsf(cs), R, T);
+    else coated_RT(pc, coat + (size_t)g * coat_layers * nlp + l, min(L, coat_layers), nlp, fabsf(cs), cs > 0.0f, R, T);
+}
+
+// four consecutive wavelengths l0 .. l0 + 3 (no indexed arrays, so nothing
+// leaves registers)
+template <bool COATED>
+__device__ __forceinline__ void glass_RT4(const float4* pane, const float4* coat, const int* coat_n, int coat_layers,
+                                          int nlp, int g, int l0, float cs, float4& R, float4& T) {
+    glass_RT<COATED>(pane, coat, coat_n, coat_layers, nlp, g, l0 + 0, cs, R.x, T.x);
+    glass_RT<COATED>(pane, coat, coat_n, coat_layers, nlp, g, l0 + 1, cs, R.y, T.y);
+    glass_RT<COATED>(pane, coat, coat_n, coat_layers, nlp, g, l0 + 2, cs, R.z, T.z);
+    glass_RT<COATED>(pane, coat, coat_n, coat_layers, nlp, g, l0 + 3, cs, R.w, T.w);
+}
+
+// ---------------------------------------------------------------------------
 // subdomain grid: point location, entry, exit
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int locate_axis(const float* pl, int n, float lo, float inv_h, float x) {
@@ -89,19 +116,22 @@ __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
         const int p = (int)(q - qs * (uint32_t)P.WH);
         const int py = (int)(p / (unsigned)P.W), px = p - py * P.W;
         const uint4 r = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, 0u, 0u), P.key);
-        const float x = (float)px + u01(r.x), y = (float)py + u01(r.y);
-        const float sx = 2.0f * x / (float)P.W - 1.0f, sy = 1.0f - 2.0f * y / (float)P.H;
-        const f3 eye{P.eye[0], P.eye[1], P.eye[2]}, fw{P.fwd[0], P.fwd[1], P.fwd[2]};
-        const f3 rt{P.right[0], P.right[1], P.right[2]}, up{P.up[0], P.up[1], P.up[2]};
+        // the ray in FP64 (path state); traversal gets its FP32 rounding
+        const double x = (double)px + (double)u01(r.x), y = (double)py + (double)u01(r.y);
+        const double sx = 2.0 * x / (double)P.W - 1.0, sy = 1.0 - 2.0 * y / (double)P.H;
+        const d3 eye{P.eye[0], P.eye[1], P.eye[2]}, fw{P.fwd[0], P.fwd[1], P.fwd[2]};
+        const d3 rt{P.right[0], P.right[1], P.right[2]}, up{P.up[0], P.up[1], P.up[2]};
+        d3 o64 = eye, d64 = fw;
         if (P.ortho) {
-            o = eye + rt * (sx * P.ortho_half_h * P.aspect) + up * (sy * P.ortho_half_h);
-            d = fw;
+            o64 = eye + rt * (sx * P.ortho_half_h * P.aspect) + up * (sy * P.ortho_half_h);
         } else {
-            o = eye;
-            d = unit3(fw + rt * (sx * P.tan_half * P.aspect) + up * (sy * P.tan_half));
+            const d3 v = fw + rt * (sx * P.tan_half * P.aspect) + up * (sy * P.tan_half);
+            d64 = v * (1.0 / sqrt(dot3(v, v)));
         }
-        P.ray_o[pid] = make_float4(o.x, o.y, o.z, 0.0f);
-        P.ray_d[pid] = make_float4(d.x, d.y, d.z, 0.0f);
+        o = narrow(o64);
+        d = narrow(d64);
+        P.ray_o[pid] = D4{o64.x, o64.y, o64.z, 0.0};
+        P.ray_d[pid] = D4{d64.x, d64.y, d64.z, 0.0};
         P.hit[pid] = make_float2(INFINITY, __int_as_float(-1));
         P.flags[pid] = kAlive | kCountE;
         cell = locate_ray(P.grid, o, d, t_enter);
@@ -243,7 +273,7 @@ __device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const 
                             const f3 ng = xyz(prim_info[prim]);
                             if (n_glass < 0) n_glass = sh_state[pid] >> 4;
                             if (n_glass < kMaxGlass)
-                                sh_glass[(size_t)pid * kMaxGlass + n_glass] = make_float2(fabsf(dot3(r.d, ng)), c.w);
+                                sh_glass[(size_t)pid * kMaxGlass + n_glass] = make_float2(-dot3(r.d, ng), c.w);
                             else
                                 atomicExch(overflow, 1);
                             ++n_glass;
@@ -347,7 +377,8 @@ __device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueS
 // the chunk range is cut into kXcd contiguous parts, part x served by the
 // workgroups of XCD x (consecutive cells share that XCD's L2).
 template <bool COUNT>
-__global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
+__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(kTraceWaves, kTraceWaves)))
+void k_trace(TraceParams P) {
     extern __shared__ int s_pref[];  // 2 * n_cells + 1 entries (dynamic, so small grids keep occupancy)
     __shared__ int s_stack[kLdsStack * kTraceBlock];
     __shared__ uint4 s_top[(kTraceBlock / 64) * 2 * kTopNodes];
@@ -457,6 +488,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(TraceParams P) {
 //    uniform area sample of the parallelogram), then a cosine-weighted bounce;
 //  - glass pane: reflect with probability P_R = mean R / (mean R + mean T) of
 //    the pane's Fresnel slab terms (Eq. 1, Sec. 6), else transmit straight on.
+template <bool COATED>
 __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
     __shared__ int s_wcnt[(kShadeBlock / 64) * kMaxCells];
     __shared__ float4 s_pane[kLdsPane];
@@ -489,40 +521,34 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
             if (prim < 0) {
                 fl = 0;  // no sky dome: a miss carries nothing
             } else {
-                const f3 o = xyz(P.ray_o[pid]), d = xyz(P.ray_d[pid]);
+                const D4 ro = P.ray_o[pid], rd = P.ray_d[pid];
+                const d3 o{ro.x, ro.y, ro.z}, d{rd.x, rd.y, rd.z};
                 const float4 pi = P.prim_info[prim];
-                const f3 ngm = xyz(pi);
                 const int word = __float_as_int(pi.w);
                 const int m = word & kMatIdMask;  // material, or compact glass index for glass
                 const int typ = (word >> kMatTypeShift) & 3;
                 const int emits = (word & kMatEmits) ? kVEmits : 0;
-                const float cos_o = -dot3(ngm, d);
-                const f3 n = cos_o > 0.0f ? ngm : -ngm;
-                // hit point and unit normal in FP64 from the triangle's own plane:
-                // x = o + t d with t = N.(v0 - o) / N.d, N = (v1 - v0) x (v2 - v0),
-                // so the point lies on the plane to FP64 rounding whatever the FP32
-                // intersection t was (the FP32 t only chose the triangle)
-                d3 x64 = wide(o) + wide(d) * (double)h.x;
-                d3 nu64 = wide(n);
-                if (typ != kEmitter) {
-                    const d3 v0 = wide(P.prim_v[3 * (size_t)prim]);
-                    const d3 N = cross3(wide(P.prim_v[3 * (size_t)prim + 1]) - v0, wide(P.prim_v[3 * (size_t)prim + 2]) - v0);
-                    const double nd = dot3(N, wide(d)), nn = dot3(N, N);
-                    if (nd != 0.0 && nn > 0.0) {
-                        x64 = wide(o) + wide(d) * (dot3(N, v0 - wide(o)) / nd);
-                        nu64 = N * ((cos_o > 0.0f ? 1.0 : -1.0) / sqrt(nn));
-                    }
-                }
+                // geometry in FP64 from the triangle's vertices: N = (v1 - v0) x (v2 - v0),
+                // the hit point on its plane x = o + t d with t = N.(v0 - o) / N.d (the
+                // FP32 traversal t only chose the triangle), the side the ray came from
+                const d3 v0 = wide(P.prim_v[3 * (size_t)prim]);
+                const d3 N = cross3(wide(P.prim_v[3 * (size_t)prim + 1]) - v0, wide(P.prim_v[3 * (size_t)prim + 2]) - v0);
+                const double nn = dot3(N, N), nd = dot3(N, d);
+                const d3 ng = nn > 0.0 ? N * (1.0 / sqrt(nn)) : wide(xyz(pi));
+                const double cos_o = -dot3(ng, d);
+                const d3 n = cos_o > 0.0 ? ng : ng * -1.0;
+                const d3 x = nd != 0.0 ? o + d * (dot3(N, v0 - o) / nd) : o + d * (double)h.x;
+                d3 xo64 = x, dn64 = d;
                 if (typ == kEmitter) {
-                    rec.x = ((fl & kCountE) && cos_o > 0.0f) ? (kVEmit | kVLast | (m << kVIdShift)) : kVNone;
+                    rec.x = ((fl & kCountE) && cos_o > 0.0) ? (kVEmit | kVLast | (m << kVIdShift)) : kVNone;
                     fl = 0;
                 } else if (typ == kDiffuse) {
                     const uint4 ub = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, (uint32_t)P.depth, 0u), P.key);
-                    const d3 xo64 = x64 + nu64 * (double)kOffset;
+                    xo64 = x + n * (double)kOffset;
                     xo = narrow(xo64);
                     float gfac = 0.0f;
                     if (P.light_type != 0) {
-                        // light sample and geometry term in FP64
+                        // light sample and geometry term
                         d3 y{P.lp0[0], P.lp0[1], P.lp0[2]};
                         if (P.light_type == 1)
                             y = y + d3{P.le1[0], P.le1[1], P.le1[2]} * (double)u01(ub.x) +
@@ -531,7 +557,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                         const double r2 = dot3(w, w);
                         const double r = sqrt(r2);
                         const d3 om = w * (1.0 / r);
-                        const double cx = dot3(nu64, om);
+                        const double cx = dot3(n, om);
                         const double cy = P.light_type == 1 ? -dot3(d3{P.nL[0], P.nL[1], P.nL[2]}, om) : 1.0;
                         if (cx > 0.0 && cy > 0.0) {
                             // (rho/pi) Le cos_x cos_y / r^2 * A (area light); (rho/pi) I cos_x / r^2 (Eq. 3)
@@ -552,16 +578,17 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                     } else {
                         const uint4 uc =
                             philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, (uint32_t)P.depth, 1u), P.key);
-                        dn = cosine_dir(n, u01(uc.x), u01(uc.y));
+                        dn64 = cosine_dir64(n, (double)u01(uc.x), (double)u01(uc.y));
                         enq_e = true;
                     }
                 } else {  // glass pane
-                    const float c = (float)fabs(dot3(wide(d), nu64));
+                    // signed cosine: > 0 when the ray meets the normal-side (coated) face
+                    const float cabs = (float)fabs(dot3(d, ng));
+                    const float c = cos_o > 0.0 ? cabs : -cabs;
                     float sumR = 0.0f, sumT = 0.0f;
-                    const float4* pm = pane + (size_t)m * P.nlp;
                     for (int l = 0; l < P.nl; ++l) {
                         float Rl, Tl;
-                        pane_RT(pm[l], c, Rl, Tl);
+                        glass_RT<COATED>(pane, P.coat, P.coat_n, P.coat_layers, P.nlp, m, l, c, Rl, Tl);
                         sumR += Rl;
                         sumT += Tl;
                     }
@@ -576,22 +603,25 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                         rec = make_int4((refl ? kVGlassR : kVGlassT) | (m << kVIdShift), __float_as_int(c),
                                         __float_as_int(PR), 0);
                         if (refl) {
-                            dn = d - ngm * (2.0f * dot3(d, ngm));
+                            dn64 = d - ng * (2.0 * dot3(d, ng));
                             fl |= kCountE;
-                            xo = narrow(x64 + nu64 * (double)kOffset);
+                            xo64 = x + n * (double)kOffset;
                         } else {
-                            dn = d;
-                            xo = narrow(x64 - nu64 * (double)kOffset);
+                            xo64 = x - n * (double)kOffset;
                         }
                         enq_e = true;
                     }
+                }
+                if (enq_e) {
+                    P.ray_o[pid] = D4{xo64.x, xo64.y, xo64.z, 0.0};
+                    P.ray_d[pid] = D4{dn64.x, dn64.y, dn64.z, 0.0};
+                    xo = narrow(xo64);
+                    dn = narrow(dn64);
                 }
             }
             P.vrec[pid] = rec;
             if ((rec.x & 7) == kVDiffuse) P.sh_state[pid] = sh;
             if (enq_e) {
-                P.ray_o[pid] = make_float4(xo.x, xo.y, xo.z, 0.0f);
-                P.ray_d[pid] = make_float4(dn.x, dn.y, dn.z, 0.0f);
                 P.hit[pid] = make_float2(INFINITY, __int_as_float(-1));
                 cell_e = locate_ray(P.grid, xo, dn, te);
                 // a ray that never enters the grid keeps its miss record
@@ -692,8 +722,8 @@ __global__ __launch_bounds__(kShadeBlock) void k_route(RouteParams P) {
 //   shadow ray: beta rho Le_light g T_panes  (after the Lambert factor rho)
 // Glass vertices multiply beta by R/P_R or T/(1-P_R) (Eq. 1, Sec. 6 slab).
 // Vertices are replayed in predicated blocks of 4 so that all their records
-// and table values are loaded before the (sequential) arithmetic.
-constexpr int kVBlock = 4;
+// and table values are loaded before the (sequential) arithmetic (one at a
+// time in scenes with coated panes, whose glass code is too large to unroll).
 
 __device__ __forceinline__ float4 f4mul(float4 a, float4 b) { return make_float4(a.x * b.x, a.y * b.y, a.z * b.z, a.w * b.w); }
 __device__ __forceinline__ float4 f4fma(float4 a, float4 b, float4 c) {
@@ -701,7 +731,11 @@ __device__ __forceinline__ float4 f4fma(float4 a, float4 b, float4 c) {
 }
 __device__ __forceinline__ float4 f4scale(float4 a, float s) { return make_float4(a.x * s, a.y * s, a.z * s, a.w * s); }
 
+template <bool COATED>
 __global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
+    // records replayed per block: the coated pane code is too large to
+    // unroll four times, so coated scenes go one vertex at a time
+    constexpr int kVBlock = COATED ? 1 : 4;
     __shared__ float4 s_pane[kLdsPane];
     const int n_pane = P.n_glass * P.nlp;
     const bool pane_lds = n_pane <= kLdsPane;
@@ -765,34 +799,25 @@ __global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
                     beta = f4mul(beta, rho[j]);
                     const float gfac = __int_as_float(v[j].w);
                     if (gfac > 0.0f && (shs[j] & 15) == kShVisible) {
-                        float tr[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+                        float4 trv = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
                         const int ng = min(shs[j] >> 4, kMaxGlass);
                         for (int k = 0; k < ng; ++k) {
                             const size_t vi = (size_t)(d0 + j) * P.N + pid;
                             const float2 gl = P.sh_glass[vi * kMaxGlass + k];
                             const int gi = min(max(__float_as_int(gl.y), 0), P.n_glass - 1);
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) {
-                                float Rg, Tg;
-                                pane_RT(pane[(size_t)gi * P.nlp + l0 + c], gl.x, Rg, Tg);
-                                tr[c] *= Tg;
-                            }
+                            float4 Rg, Tg;
+                            glass_RT4<COATED>(pane, P.coat, P.coat_n, P.coat_layers, P.nlp, gi, l0, gl.x, Rg, Tg);
+                            trv = f4mul(trv, Tg);
                         }
-                        const float4 trv = make_float4(tr[0], tr[1], tr[2], tr[3]);
                         L = f4fma(f4scale(f4mul(beta, leL), gfac), trv, L);
                     }
                 } else if ((kind == kVGlassR || kind == kVGlassT) && !(x & kVLast)) {
                     const int gi = min(max(x >> kVIdShift, 0), P.n_glass - 1);
                     const float PR = __int_as_float(v[j].z);
                     const float c = __int_as_float(v[j].y);
-                    float f[4];
-#pragma unroll
-                    for (int cc = 0; cc < 4; ++cc) {
-                        float Rl, Tl;
-                        pane_RT(pane[(size_t)gi * P.nlp + l0 + cc], c, Rl, Tl);
-                        f[cc] = kind == kVGlassR ? Rl * (1.0f / PR) : Tl * (1.0f / (1.0f - PR));
-                    }
-                    beta = f4mul(beta, make_float4(f[0], f[1], f[2], f[3]));
+                    float4 Rl, Tl;
+                    glass_RT4<COATED>(pane, P.coat, P.coat_n, P.coat_layers, P.nlp, gi, l0, c, Rl, Tl);
+                    beta = f4mul(beta, kind == kVGlassR ? f4scale(Rl, 1.0f / PR) : f4scale(Tl, 1.0f / (1.0f - PR)));
                 }
             }
             live = run;
@@ -840,6 +865,16 @@ __global__ void k_pane(int n, const float4* pc, const float* c, float2* out) {
     if (i >= n) return;
     float R, T;
     pane_RT(pc[i], c[i], R, T);
+    out[i] = make_float2(R, T);
+}
+
+__global__ void k_glass(int n, GlassTable tab, const int4* q, float2* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int4 v = q[i];
+    float R, T;
+    if (tab.coat_n) glass_RT<true>(tab.pane, tab.coat, tab.coat_n, tab.coat_layers, tab.nlp, v.x, v.y, __int_as_float(v.z), R, T);
+    else glass_RT<false>(tab.pane, tab.coat, tab.coat_n, tab.coat_layers, tab.nlp, v.x, v.y, __int_as_float(v.z), R, T);
     out[i] = make_float2(R, T);
 }
 
@@ -902,7 +937,8 @@ int trace_blocks_per_cu(int n_cells) {
 
 hipError_t launch_shade(const ShadeParams& p, hipStream_t st) {
     if (p.N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_shade, dim3(blocks_for(p.N, kShadeBlock)), dim3(kShadeBlock), 0, st, p);
+    if (p.coat_n) hipLaunchKernelGGL(k_shade<true>, dim3(blocks_for(p.N, kShadeBlock)), dim3(kShadeBlock), 0, st, p);
+    else hipLaunchKernelGGL(k_shade<false>, dim3(blocks_for(p.N, kShadeBlock)), dim3(kShadeBlock), 0, st, p);
     return hipGetLastError();
 }
 
@@ -919,7 +955,8 @@ hipError_t launch_spectral(const SpectralParams& p, hipStream_t st) {
     const int npix = p.N < p.WH ? p.N : p.WH;
     const long long n = (long long)npix * p.ngrp;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spectral, dim3(blocks_for(n, 256)), dim3(256), 0, st, p);
+    if (p.coat_n) hipLaunchKernelGGL(k_spectral<true>, dim3(blocks_for(n, 256)), dim3(256), 0, st, p);
+    else hipLaunchKernelGGL(k_spectral<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 
@@ -939,6 +976,12 @@ hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st) {
 hipError_t launch_pane(int n, const float4* pc, const float* c, float2* out, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pane, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, pc, c, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_glass(int n, const GlassTable& tab, const int4* q, float2* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_glass, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, tab, q, out);
     return hipGetLastError();
 }
 

@@ -18,6 +18,9 @@
 //          the compact glass index for glass
 //   pane   float4[n_glass][nlp]  per glass material and wavelength: the pane
 //          constants (n^2 - k^2, 2 n k, 1 / n^2, 4 pi k d / lambda)
+//   coat   float4[n_glass][Lc][nlp] coating layers of each glass (from the air
+//          side of the coated face): (Re N^2, Im N^2, 2 pi d / lambda, 0);
+//          coat_n int[n_glass] layers in use (absent when no glass is coated)
 //   cell_root int[n_cells]      root node of each cell (always an inner node)
 //   planes float[nx+1 + ny+1 + nz+1]  cell boundary planes per axis
 //
@@ -25,7 +28,9 @@
 //   qa float4 (o.x, o.y, o.z, t_enter)   qb float4 (d.x, d.y, d.z, path id)
 //   qc int2   (excluded prim, t_max bits)
 // Path state, indexed by path id within a batch (N paths):
-//   ray_o / ray_d float4, hit float2 (t, prim), flags u32.
+//   ray_o / ray_d D4 (FP64 origin and direction: shading geometry), hit
+//   float2 (FP32 t, prim: traversal result), flags u32.  The queue records
+//   carry the FP32-rounded ray that traversal tests.
 // Path history, indexed [depth][path]: one geometric path carries every
 // wavelength, so the per-wavelength factors are not stored per bounce; each
 // surface vertex leaves a record that k_spectral replays once per wavelength:
@@ -42,7 +47,8 @@ namespace sdd {
 constexpr int kTraceBlock = 128;  // threads per traversal workgroup
 constexpr int kStack = 40;        // traversal stack entries per lane (total)
 constexpr int kLdsStack = 8;      // of which the first kLdsStack live in LDS, the rest in HBM
-constexpr int kTopNodes = 128;    // breadth-first top nodes of the current cell kept in LDS per wave
+constexpr int kTopNodes = 64;     // breadth-first top nodes of the current cell kept in LDS per wave
+constexpr int kTraceWaves = 8;    // waves per SIMD the trace kernel is compiled for (registers <= 64)
 constexpr int kMaxBvhDepth = kStack;  // the builder never exceeds the stack
 constexpr int kChunk = 64;        // rays per scheduling chunk (one wave)
 constexpr int kXcd = 8;           // XCDs of an MI355X; workgroup i runs on XCD i % 8
@@ -64,6 +70,11 @@ inline FastDiv make_fastdiv(uint32_t d) {
     return FastDiv{d, (uint32_t)m, l};
 }
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) { return (__umulhi(n, f.m) + n) >> f.l; }
+
+// FP64 vector of the per-path ray state (32 B, w unused)
+struct alignas(32) D4 {
+    double x, y, z, w;
+};
 
 enum : int { kDiffuse = 0, kGlass = 1, kEmitter = 2 };
 enum : uint32_t { kAlive = 1u, kCountE = 2u };
@@ -150,8 +161,8 @@ struct ShadeParams {
     uint2 key;
     // path state
     uint32_t* flags;
-    float4* ray_o;
-    float4* ray_d;
+    D4* ray_o;
+    D4* ray_d;
     float2* hit;
     // history of this depth
     int4* vrec;
@@ -160,6 +171,9 @@ struct ShadeParams {
     const float4* prim_info;
     const float4* prim_v;  // [T][3] vertices
     const float4* pane;    // [n_glass][nlp]
+    const float4* coat;    // [n_glass][coat_layers][nlp] coating layers, or null
+    const int* coat_n;     // [n_glass] layers per glass, or null (no coatings)
+    int coat_layers;
     int n_glass;
     int nl, nlp;
     int light_type;
@@ -181,11 +195,11 @@ struct CamParams {
     int s0;
     uint2 key;
     int ortho;
-    float eye[3], fwd[3], right[3], up[3];
-    float tan_half, aspect, ortho_half_h;
+    double eye[3], fwd[3], right[3], up[3];
+    double tan_half, aspect, ortho_half_h;
     uint32_t* flags;
-    float4* ray_o;
-    float4* ray_d;
+    D4* ray_o;
+    D4* ray_d;
     float2* hit;
     GridParams grid;
     int n_cells;
@@ -210,6 +224,15 @@ struct RouteParams {
     unsigned long long* stats;
 };
 
+// the glass tables of a scene, as the debug entry point sees them
+struct GlassTable {
+    const float4* pane;
+    const float4* coat;
+    const int* coat_n;
+    int coat_layers;
+    int nlp;
+};
+
 // replay of the path histories, one thread per (pixel, wavelength)
 struct SpectralParams {
     int N;
@@ -224,6 +247,9 @@ struct SpectralParams {
     const int* sh_state;   // [D][N]
     const float2* sh_glass;// [D][N][kMaxGlass]
     const float4* pane;    // [n_glass][nlp]
+    const float4* coat;    // [n_glass][coat_layers][nlp] coating layers, or null
+    const int* coat_n;     // [n_glass] layers per glass, or null (no coatings)
+    int coat_layers;
     int n_glass;
     int n_mats;
     const float* rho;      // [M][nlp]

@@ -367,7 +367,7 @@ def _glass_material(mats, lam, k=1e-7, thick=0.004, coating_state=None):
 # the workloads
 # ----------------------------------------------------------------------------
 
-def tiny_room(seed: int = 0, n_lambda: int = 16, n_boxes: int = 20, window=((1, 1), (2, 1))):
+def tiny_room(seed: int = 0, n_lambda: int = 16, n_boxes: int = 20, window=((1, 1), (2, 1)), coating_state=None):
     """Tiny plain-method room: 1,092 triangles, one 4 mm pane, sky light.
 
     132 shell triangles, minus the 4 of the two window quads, plus the
@@ -378,7 +378,7 @@ def tiny_room(seed: int = 0, n_lambda: int = 16, n_boxes: int = 20, window=((1, 
     lam, w = lambda_grid(n_lambda)
     mats = _Materials(len(lam))
     rect_mats = [mats.add(DIFFUSE, rho=gaussian_reflectance(rng, lam)) for _ in range(6)]
-    pane = _glass_material(mats, lam)
+    pane = _glass_material(mats, lam, coating_state=coating_state)
     sky = mats.add(EMITTER, le=planck_shape(lam))
     mesh = _Mesh()
     _room_shell(mesh, rect_mats, window_cells=window, pane_mat=pane)

@@ -83,6 +83,35 @@ def test_validate_rejects(sdd, mut, needle):
     assert needle in msg
 
 
+def _bad_coated(mut):
+    sc = sg.tiny_room(coating_state=0.5)
+    sc = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    mut(sc)
+    return sc
+
+
+def test_validate_accepts_coated_scenes(sdd):
+    for sc in (sg.tiny_room(coating_state=0.5), sg.lone_pane(coating_state=1.0)):
+        ok, msg = sdd.validate_scene(sc)
+        assert ok, (sc["name"], msg)
+
+
+@pytest.mark.parametrize("mut,needle", [
+    (lambda s: s["mat_n_layers"].__setitem__(6, 9), "layer count"),
+    (lambda s: s["mat_n_layers"].__setitem__(0, 2), "only glass"),
+    (lambda s: s["mat_layer_d"].__setitem__((6, 1), -1e-9), "thickness"),
+    (lambda s: s["mat_layer_n"].__setitem__((6, 2, 3), 0.0), "coating n"),
+    (lambda s: s["mat_layer_k"].__setitem__((6, 0, 0), -0.1), "coating k"),
+    (lambda s: s["mat_layer_d"].__setitem__((6, 0), np.inf), "thickness"),
+])
+def test_validate_rejects_bad_coatings(sdd, mut, needle):
+    sc = _bad_coated(mut)
+    assert sc["mat_type"][6] == sg.GLASS
+    ok, msg = sdd.validate_scene(sc)
+    assert not ok
+    assert needle in msg
+
+
 def test_validate_rejects_too_many_wavelengths(sdd):
     sc = sg.tiny_room()
     n = 129
