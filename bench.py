@@ -40,6 +40,10 @@ WORKLOADS = {
     "furnished_room": dict(scene=("furnished_room", dict(seed=1, n_lambda=41)), W=512, H=512, spp=16, D=8,
                            grid=(4, 4, 2)),
     "tiny_room": dict(scene=("tiny_room", dict(seed=0, n_lambda=16)), W=64, H=64, spp=1, D=4, grid=(2, 2, 1)),
+    # 64 renders of uneven resolution (128^2 .. 1024^2, 8 spp) with 8 photochromic
+    # states, traced together in one sdd_trace_batch call per step
+    "photochromic_batch": dict(scene=("furnished_room", dict(seed=1, n_lambda=41)), W=1024, H=1024, spp=8, D=8,
+                               grid=(4, 4, 2), batch=dict(n=64, seed=2, n_states=8, spp=8)),
     # 4M triangles, coated (electrochromic) panes, 81 wavelengths, 128 subdomains
     "electrochromic_room": dict(scene=("electrochromic_room", dict(seed=4, n_lambda=81)), W=3840, H=2160, spp=64,
                                 D=8, grid=(8, 4, 4)),
@@ -151,6 +155,13 @@ def main():
     name, kw = wl["scene"]
     t0 = time.perf_counter()
     scene = getattr(scenegen, name)(**kw)
+    renders = None
+    if "batch" in wl:
+        bw = wl["batch"]
+        scene, base, states = scenegen.photochromic_states(scene, bw["n_states"])
+        renders = scenegen.batch_renders(bw["n"], bw["seed"], bw["n_states"], spp=bw["spp"])
+        for r in renders:
+            r["glass_swap"] = (base, states[r["state"]])
     log(f"[bench] scene {scene['name']}: {len(scene['tris'])} tris, {len(scene['lambda_nm'])} lambda "
         f"({time.perf_counter() - t0:.1f} s)")
     W, H, spp, D = wl["W"], wl["H"], wl["spp"], wl["D"]
@@ -171,8 +182,15 @@ def main():
     def frame():
         nonlocal step
         # every launch is bracketed by HIP events on the library's stream
-        tr.trace_spectral(cam, W, H, spp, D, sample_offset=step * spp, render_id=0, time_kernels=True)
-        tr.resolve_image(0, W, H, spectral=True, xyz=True)
+        if renders is None:
+            tr.trace_spectral(cam, W, H, spp, D, sample_offset=step * spp, render_id=0, time_kernels=True)
+            tr.resolve_image(0, W, H, spectral=True, xyz=True)
+        else:
+            for r in renders:
+                r["sample_offset"] = step * r["spp"]
+            tr.trace_batch(renders, D, time_kernels=True)
+            for r in renders:
+                tr.resolve_image(r["render_id"], r["W"], r["H"], spectral=True, xyz=True)
         step += 1
 
     for i in range(args.warmup):
@@ -209,6 +227,16 @@ def main():
     log(f"[bench] timed {dt:.3f} s; kernel ms {kern_ms}")
     log(f"[bench] stats {json.dumps(st)}")
 
+    if renders is None:
+        paths_per_step = W * H * spp
+        frame_desc = f"{W}x{H}, {spp} spp"
+    else:
+        paths_per_step = sum(r["W"] * r["H"] * r["spp"] for r in renders)
+        frame_desc = (f"{len(renders)} renders {min(r['W'] for r in renders)}^2..{max(r['W'] for r in renders)}^2 "
+                      f"({sum(r['W'] * r['H'] for r in renders)} px), {renders[0]['spp']} spp, "
+                      f"{wl['batch']['n_states']} photochromic states")
+    workload_desc = (f"{args.workload}: {len(scene['tris'])} tris, {frame_desc}, {nl} lambda, depth {D}, "
+                     f"grid {'x'.join(map(str, wl['grid']))}")
     res = {
         "metric": "spectral path samples/s (rays x lambda/s), plain tracer, one MI355X",
         "value": value,
@@ -222,10 +250,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {len(scene['tris'])} tris, {W}x{H}, {spp} spp, {nl} lambda, "
-                               f"depth {D}, grid {'x'.join(map(str, wl['grid']))}",
-                   "paths_per_step": W * H * spp, "rays_per_step": rays / args.steps,
-                   "path_samples_lambda_per_s": W * H * spp * nl * args.steps / dt},
+        "config": {"workload": workload_desc, "paths_per_step": paths_per_step, "rays_per_step": rays / args.steps,
+                   "path_samples_lambda_per_s": paths_per_step * nl * args.steps / dt},
         "roofline": {"bound": "hbm", "kernel": "k_trace", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes / launches, "avg_launch_ms": avg_ms,
@@ -235,7 +261,7 @@ def main():
     }
     if args.count_work:
         tr.reset_stats()
-        tr.trace_spectral(cam, W, H, spp, D, sample_offset=step * spp, render_id=0, count_work=True)
+        tr.trace_spectral(cam, W, H, spp, D, sample_offset=step * spp, render_id=1 << 30, count_work=True)
         torch.cuda.synchronize()
         sw = tr.stats()
         visits = sw["ext_cell_visits"] + sw["shadow_cell_visits"]

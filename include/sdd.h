@@ -57,6 +57,7 @@ enum { SDD_LIGHT_NONE = 0, SDD_LIGHT_PARALLELOGRAM = 1, SDD_LIGHT_POINT = 2 };
 #define SDD_MAX_CELLS 512
 #define SDD_MAX_DEPTH 64
 #define SDD_MAX_LAYERS 8
+#define SDD_MAX_RENDERS 256
 
 typedef struct sdd_ctx sdd_ctx;
 
@@ -154,6 +155,10 @@ typedef struct sdd_bvh_desc {
  *     (this call's samples).  hit_log gets the hit triangle id of each vertex,
  *     -1 for a miss, -2 where the path had ended; shadow_log gets 1 (visible),
  *     0 (blocked) or -2 (no shadow ray) per vertex.  NULL to skip.
+ *   glass_from, glass_to: material substitution for this render (photochromic
+ *     states): pane triangles of GLASS_SLAB material glass_from are traced as
+ *     GLASS_SLAB material glass_to.  Inactive when equal (e.g. both 0).
+ * W * H * spp must be below 2^31.
  */
 typedef struct sdd_trace_desc {
     double eye[3], target[3];
@@ -168,6 +173,7 @@ typedef struct sdd_trace_desc {
     uint32_t flags;
     int32_t *hit_log;
     int32_t *shadow_log;
+    int32_t glass_from, glass_to;
 } sdd_trace_desc;
 
 /* Counters (sdd_get_stats); synchronises the context stream. */
@@ -228,6 +234,14 @@ sdd_status sdd_build_bvh(sdd_ctx *ctx, const sdd_bvh_desc *desc);
  * a render_id < 0, a changed W/H for an existing render, or a degenerate
  * camera (forward direction parallel to +z or eye == target). */
 sdd_status sdd_trace_spectral(sdd_ctx *ctx, const sdd_trace_desc *desc);
+
+/* Several renders in one pass of the pipeline (n in 1..SDD_MAX_RENDERS, all
+ * with the same max_depth and distinct render_ids): their paths share the
+ * per-subdomain queues and every traversal sweep, so many small or uneven
+ * renders fill the GPU together.  Each render is traced exactly as
+ * sdd_trace_spectral would trace it alone (same random numbers, same
+ * result); TIME_KERNELS / COUNT_WORK apply if any desc sets them. */
+sdd_status sdd_trace_batch(sdd_ctx *ctx, int32_t n, const sdd_trace_desc *descs);
 
 /* Per-pixel mean radiance of render_id over all samples traced so far, in
  * FP64: spectral_out [H][W][n_lambda] and xyz_out [H][W][3] (XYZ =

@@ -29,7 +29,7 @@ TRACE_ORTHO, TRACE_TIME_KERNELS, TRACE_COUNT_WORK = 1, 2, 4
 
 EXPORTS = ("sdd_create", "sdd_destroy", "sdd_last_error", "sdd_load_scene", "sdd_validate_scene", "sdd_build_bvh",
            "sdd_trace_spectral", "sdd_resolve_image", "sdd_reset_render", "sdd_get_stats", "sdd_reset_stats",
-           "sdd_debug_philox", "sdd_debug_pane", "sdd_debug_trace_rays", "sdd_debug_glass")
+           "sdd_debug_philox", "sdd_debug_pane", "sdd_debug_trace_rays", "sdd_debug_glass", "sdd_trace_batch")
 
 
 class SddError(RuntimeError):
@@ -62,7 +62,7 @@ class TraceDesc(C.Structure):
         ("eye", C.c_double * 3), ("target", C.c_double * 3), ("fov_deg", C.c_double), ("ortho_half_h", C.c_double),
         ("W", C.c_int32), ("H", C.c_int32), ("spp", C.c_int32), ("sample_offset", C.c_int32),
         ("max_depth", C.c_int32), ("seed", C.c_uint32), ("render_id", C.c_int32), ("flags", C.c_uint32),
-        ("hit_log", C.c_void_p), ("shadow_log", C.c_void_p),
+        ("hit_log", C.c_void_p), ("shadow_log", C.c_void_p), ("glass_from", C.c_int32), ("glass_to", C.c_int32),
     ]
 
 
@@ -110,6 +110,7 @@ def lib():
         L.sdd_debug_pane.argtypes = [vp, i32, vp, vp, vp]
         L.sdd_debug_trace_rays.argtypes = [vp, i32, vp, vp, vp, vp]
         L.sdd_debug_glass.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.sdd_trace_batch.argtypes = [vp, i32, C.POINTER(TraceDesc)]
         _LIB = L
     return _LIB
 
@@ -205,8 +206,8 @@ class Tracer:
     def build_bvh(self, nx=1, ny=1, nz=1, leaf_max=4, sah_bins=16):
         self._check(lib().sdd_build_bvh(self.h, C.byref(BvhDesc(nx, ny, nz, leaf_max, sah_bins))))
 
-    def trace_spectral(self, camera, W, H, spp, max_depth, *, seed=0, render_id=0, sample_offset=0,
-                       time_kernels=False, count_work=False, hit_log=None, shadow_log=None):
+    def _desc(self, camera, W, H, spp, max_depth, seed=0, render_id=0, sample_offset=0, time_kernels=False,
+              count_work=False, hit_log=None, shadow_log=None, glass_swap=None):
         d = TraceDesc()
         d.eye[:] = [float(x) for x in camera["eye"]]
         d.target[:] = [float(x) for x in camera["target"]]
@@ -228,7 +229,26 @@ class Tracer:
                 if not (t.is_cuda and t.dtype == self.torch.int32 and t.is_contiguous() and t.numel() == n_slots):
                     raise ValueError(f"{name} must be a contiguous int32 CUDA tensor of {n_slots} elements")
                 setattr(d, name, t.data_ptr())
+        d.glass_from, d.glass_to = (-1, -1) if glass_swap is None else (int(glass_swap[0]), int(glass_swap[1]))
+        return d
+
+    def trace_spectral(self, camera, W, H, spp, max_depth, *, seed=0, render_id=0, sample_offset=0,
+                       time_kernels=False, count_work=False, hit_log=None, shadow_log=None, glass_swap=None):
+        """Trace spp samples of every pixel; glass_swap = (from_material, to_material) substitutes a
+        glass material for this render (photochromic state)."""
+        d = self._desc(camera, W, H, spp, max_depth, seed, render_id, sample_offset, time_kernels, count_work,
+                       hit_log, shadow_log, glass_swap)
         self._check(lib().sdd_trace_spectral(self.h, C.byref(d)))
+
+    def trace_batch(self, renders, max_depth, *, seed=0, time_kernels=False, count_work=False):
+        """Several renders in one pipeline pass.  renders: list of dicts with keys camera, W, H, spp,
+        render_id and optionally sample_offset, hit_log, shadow_log, glass_swap."""
+        arr = (TraceDesc * len(renders))()
+        for i, r in enumerate(renders):
+            arr[i] = self._desc(r["camera"], r["W"], r["H"], r["spp"], max_depth, seed, r["render_id"],
+                                r.get("sample_offset", 0), time_kernels, count_work, r.get("hit_log"),
+                                r.get("shadow_log"), r.get("glass_swap"))
+        self._check(lib().sdd_trace_batch(self.h, len(renders), arr))
 
     def new_log(self, W, H, spp, max_depth):
         return self.torch.empty((W * H, spp, max_depth), dtype=self.torch.int32, device=self.device)

@@ -746,124 +746,155 @@ sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
     return SDD_OK;
 }
 
-sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
-    if (!c) return SDD_ERR_INVALID_ARG;
-    c->err.clear();
+}  // extern "C"
+
+namespace {
+
+// one render of a trace call
+struct Job {
+    const sdd_trace_desc* t = nullptr;
+    Render* rd = nullptr;
+    int WH = 0;
+    long long total = 0;  // W * H * spp paths
+    long long start = 0;  // first index in the call's path space (multiple of kShadeBlock)
+    double f[3], r[3], u[3];
+    bool ortho = false;
+    int glass_from = -1, glass_to = -1;  // compact glass indices of the substitution
+};
+
+// argument checks and camera basis of one render (no device work)
+sdd_status check_desc(sdd_ctx* c, const sdd_trace_desc* t, Job& j) {
     if (!t) return fail(c, SDD_ERR_INVALID_ARG, "null trace desc");
-    if (!c->has_bvh) return fail(c, SDD_ERR_STATE, "sdd_trace_spectral before sdd_build_bvh");
     if (t->W <= 0 || t->H <= 0 || t->spp <= 0) return fail(c, SDD_ERR_INVALID_ARG, "W, H and spp must be > 0");
     if ((long long)t->W * t->H > (1LL << 28)) return fail(c, SDD_ERR_INVALID_ARG, "image too large");
+    if ((long long)t->W * t->H * t->spp >= (1LL << 31))
+        return fail(c, SDD_ERR_INVALID_ARG, "W * H * spp must be < 2^31 per call");
     if (t->max_depth < 1 || t->max_depth > SDD_MAX_DEPTH) return fail(c, SDD_ERR_INVALID_ARG, "max_depth out of range");
     if (t->render_id < 0) return fail(c, SDD_ERR_INVALID_ARG, "render_id must be >= 0");
     if (t->sample_offset < 0) return fail(c, SDD_ERR_INVALID_ARG, "sample_offset must be >= 0");
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(t->eye[k]) || !std::isfinite(t->target[k]))
             return fail(c, SDD_ERR_INVALID_ARG, "non-finite camera");
-    const double f0[3] = {(double)t->target[0] - t->eye[0], (double)t->target[1] - t->eye[1],
-                          (double)t->target[2] - t->eye[2]};
+    const double f0[3] = {t->target[0] - t->eye[0], t->target[1] - t->eye[1], t->target[2] - t->eye[2]};
     const double fl = std::sqrt(f0[0] * f0[0] + f0[1] * f0[1] + f0[2] * f0[2]);
     if (!(fl > 0.0)) return fail(c, SDD_ERR_INVALID_ARG, "eye == target");
-    const double f[3] = {f0[0] / fl, f0[1] / fl, f0[2] / fl};
-    double r[3] = {f[1], -f[0], 0.0};  // f x z
+    for (int k = 0; k < 3; ++k) j.f[k] = f0[k] / fl;
+    double r[3] = {j.f[1], -j.f[0], 0.0};  // f x z
     const double rl = std::sqrt(r[0] * r[0] + r[1] * r[1]);
     if (!(rl > 1e-9)) return fail(c, SDD_ERR_INVALID_ARG, "view direction parallel to +z");
-    for (double& v : r) v /= rl;
-    const double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
-    const bool ortho = (t->flags & SDD_TRACE_ORTHO) != 0;
-    if (!ortho && !(t->fov_deg > 0.0f && t->fov_deg < 180.0f)) return fail(c, SDD_ERR_INVALID_ARG, "fov out of range");
-    if (ortho && !(t->ortho_half_h > 0.0f)) return fail(c, SDD_ERR_INVALID_ARG, "ortho_half_h must be > 0");
-    DeviceGuard g(c->device);
-
-    auto it = c->renders.find(t->render_id);
-    if (it != c->renders.end() && (it->second.W != t->W || it->second.H != t->H))
-        return fail(c, SDD_ERR_INVALID_ARG, "render_id reused with a different W, H");
-    const int WH = t->W * t->H;
-    if (it == c->renders.end()) {
-        Render rd;
-        rd.W = t->W;
-        rd.H = t->H;
-        sdd_status st = dalloc(c, &rd.acc, (size_t)c->nlp * WH);
-        if (st != SDD_OK) return st;
-        HIP_TRY(c, hipMemsetAsync(rd.acc, 0, sizeof(float) * (size_t)c->nlp * WH, c->stream));
-        it = c->renders.emplace(t->render_id, rd).first;
+    for (int k = 0; k < 3; ++k) j.r[k] = r[k] / rl;
+    j.u[0] = j.r[1] * j.f[2] - j.r[2] * j.f[1];
+    j.u[1] = j.r[2] * j.f[0] - j.r[0] * j.f[2];
+    j.u[2] = j.r[0] * j.f[1] - j.r[1] * j.f[0];
+    j.ortho = (t->flags & SDD_TRACE_ORTHO) != 0;
+    if (!j.ortho && !(t->fov_deg > 0.0 && t->fov_deg < 180.0)) return fail(c, SDD_ERR_INVALID_ARG, "fov out of range");
+    if (j.ortho && !(t->ortho_half_h > 0.0)) return fail(c, SDD_ERR_INVALID_ARG, "ortho_half_h must be > 0");
+    if (t->glass_from != t->glass_to) {
+        const int a = t->glass_from, b = t->glass_to;
+        if (a < 0 || a >= c->M || b < 0 || b >= c->M || c->glass_of[a] < 0 || c->glass_of[b] < 0)
+            return fail(c, SDD_ERR_INVALID_ARG, "glass substitution needs two glass materials");
+        j.glass_from = c->glass_of[a];
+        j.glass_to = c->glass_of[b];
     }
-    Render& rd = it->second;
+    j.t = t;
+    j.WH = t->W * t->H;
+    j.total = (long long)j.WH * t->spp;
+    return SDD_OK;
+}
 
-    const long long total = (long long)WH * t->spp;
-    long long nb = std::max<long long>(64, mem_budget_bytes() / bytes_per_path(c, t->max_depth));
+// The renders of one call share one path space: render j occupies
+// [start_j, start_j + total_j), each start a multiple of kShadeBlock (the
+// gaps hold no path).  The space is traced in batches; every batch runs the
+// whole pipeline once, with the per-render kernels (camera rays, shading,
+// spectral replay) launched per render segment and the routing and
+// traversal sweeps over the whole batch.
+sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
+    const int D = jobs[0].t->max_depth;
+    uint32_t any_flags = 0;
+    for (const Job& j : jobs) any_flags |= j.t->flags;
+    const bool timing = (any_flags & SDD_TRACE_TIME_KERNELS) != 0;
+    const bool count = (any_flags & SDD_TRACE_COUNT_WORK) != 0;
+    long long total_pad = 0;
+    for (Job& j : jobs) {
+        j.start = total_pad;
+        total_pad += (j.total + kShadeBlock - 1) / kShadeBlock * kShadeBlock;
+    }
+    long long nb = mem_budget_bytes() / bytes_per_path(c, D);
     nb = std::min<long long>(nb, kMaxBatch);
-    nb = std::min(nb, total);
-    sdd_status st = ensure_batch(c, nb, t->max_depth);
+    nb = std::max<long long>(kShadeBlock, nb / kShadeBlock * kShadeBlock);
+    nb = std::min(nb, total_pad);
+    sdd_status st = ensure_batch(c, nb, D);
     if (st != SDD_OK) return st;
-    const bool timing = (t->flags & SDD_TRACE_TIME_KERNELS) != 0;
-    const bool count = (t->flags & SDD_TRACE_COUNT_WORK) != 0;
-    const int D = t->max_depth;
-    const uint2 key = make_uint2(t->seed, (uint32_t)t->render_id);
-    if (t->hit_log) {
-        Timer tm(c, timing, 3);
-        HIP_TRY(c, launch_fill_i32(t->hit_log, total * D, -2, c->stream));
+    for (const Job& j : jobs) {
+        if (j.t->hit_log) {
+            Timer tm(c, timing, 3);
+            HIP_TRY(c, launch_fill_i32(j.t->hit_log, j.total * D, -2, c->stream));
+        }
+        if (j.t->shadow_log) {
+            Timer tm(c, timing, 3);
+            HIP_TRY(c, launch_fill_i32(j.t->shadow_log, j.total * D, -2, c->stream));
+        }
     }
-    if (t->shadow_log) {
-        Timer tm(c, timing, 3);
-        HIP_TRY(c, launch_fill_i32(t->shadow_log, total * D, -2, c->stream));
-    }
-
-    for (long long g0 = 0; g0 < total; g0 += nb) {
-        const int N = (int)std::min(nb, total - g0);
+    struct Seg {
+        const Job* j;
+        long long q0;  // first path of the render in this segment
+        int n;         // paths
+        int pid_off;   // position in the batch (multiple of kShadeBlock)
+    };
+    std::vector<Seg> segs;
+    for (long long g0 = 0; g0 < total_pad; g0 += nb) {
+        const int N = (int)std::min(nb, total_pad - g0);
         const long long cap = N;
+        segs.clear();
+        for (const Job& j : jobs) {
+            const long long a = std::max(g0, j.start), b = std::min(g0 + N, j.start + j.total);
+            if (a < b) segs.push_back(Seg{&j, a - j.start, (int)(b - a), (int)(a - g0)});
+        }
         {
             Timer tm(c, timing, 3);
             HIP_TRY(c, launch_fill_i32(c->d_counts, c->counts_len, 0, c->stream));
         }
-        const FastDiv fwh = make_fastdiv((uint32_t)WH);
-        const int pb = (int)(g0 % WH), sb = (int)(g0 / WH);
-        CamParams cp{};
-        cp.N = N;
-        cp.pb = pb;
-        cp.sb = sb;
-        cp.fwh = fwh;
-        cp.W = t->W;
-        cp.H = t->H;
-        cp.WH = WH;
-        cp.s0 = t->sample_offset;
-        cp.key = key;
-        cp.ortho = ortho ? 1 : 0;
-        for (int k = 0; k < 3; ++k) {
-            cp.eye[k] = t->eye[k];
-            cp.fwd[k] = f[k];
-            cp.right[k] = r[k];
-            cp.up[k] = u[k];
-        }
-        cp.tan_half = std::tan(0.5 * t->fov_deg * M_PI / 180.0);
-        cp.aspect = (double)t->W / (double)t->H;
-        cp.ortho_half_h = t->ortho_half_h;
-        cp.flags = c->flags;
-        cp.ray_o = c->ray_o;
-        cp.ray_d = c->ray_d;
-        cp.hit = c->hit;
-        cp.grid = c->grid;
-        cp.n_cells = c->G;
-        cp.se = c->stage[0];
-        cp.n_blocks = (N + kShadeBlock - 1) / kShadeBlock;
-        cp.stats = c->d_stats;
-        {
+        const int n_blocks = N / kShadeBlock;
+        for (const Seg& sg : segs) {
+            const sdd_trace_desc* t = sg.j->t;
+            CamParams cp{};
+            cp.N = sg.n;
+            cp.pid_off = sg.pid_off;
+            cp.pb = (int)(sg.q0 % sg.j->WH);
+            cp.sb = (int)(sg.q0 / sg.j->WH);
+            cp.fwh = make_fastdiv((uint32_t)sg.j->WH);
+            cp.W = t->W;
+            cp.H = t->H;
+            cp.WH = sg.j->WH;
+            cp.s0 = t->sample_offset;
+            cp.key = make_uint2(t->seed, (uint32_t)t->render_id);
+            cp.ortho = sg.j->ortho ? 1 : 0;
+            for (int k = 0; k < 3; ++k) {
+                cp.eye[k] = t->eye[k];
+                cp.fwd[k] = sg.j->f[k];
+                cp.right[k] = sg.j->r[k];
+                cp.up[k] = sg.j->u[k];
+            }
+            cp.tan_half = std::tan(0.5 * t->fov_deg * M_PI / 180.0);
+            cp.aspect = (double)t->W / (double)t->H;
+            cp.ortho_half_h = t->ortho_half_h;
+            cp.flags = c->flags;
+            cp.ray_o = c->ray_o;
+            cp.ray_d = c->ray_d;
+            cp.hit = c->hit;
+            cp.grid = c->grid;
+            cp.n_cells = c->G;
+            cp.se = c->stage[0];
+            cp.n_blocks = n_blocks;
+            cp.stats = c->d_stats;
             Timer tm(c, timing, 3);
             HIP_TRY(c, launch_camgen(cp, c->stream));
+            c->cam_rays += sg.n;
         }
-        c->cam_rays += N;
         st = route(c, N, cap, ph_ext(1), -1, false, timing);
         if (st != SDD_OK) return st;
         ShadeParams sp{};
-        sp.N = N;
-        sp.pb = pb;
-        sp.sb = sb;
-        sp.fwh = fwh;
-        sp.W = t->W;
-        sp.WH = WH;
-        sp.s0 = t->sample_offset;
-        sp.spp_call = t->spp;
         sp.max_depth = D;
-        sp.key = key;
         sp.flags = c->flags;
         sp.ray_o = c->ray_o;
         sp.ray_d = c->ray_d;
@@ -889,8 +920,7 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         sp.n_cells = c->G;
         sp.se = c->stage[0];
         sp.ss = c->stage[1];
-        sp.n_blocks = (N + kShadeBlock - 1) / kShadeBlock;
-        sp.hit_log = t->hit_log;
+        sp.n_blocks = n_blocks;
         sp.stats = c->d_stats;
         for (int d = 1; d <= D; ++d) {
             // closest-hit rays of depth d share the sweeps with the shadow rays of depth d - 1
@@ -899,7 +929,21 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
             sp.depth = d;
             sp.vrec = c->vrec + (long long)(d - 1) * N;
             sp.sh_state = c->sh_state + (long long)(d - 1) * N;
-            {
+            for (const Seg& sg : segs) {
+                const sdd_trace_desc* t = sg.j->t;
+                sp.N = sg.n;
+                sp.pid_off = sg.pid_off;
+                sp.pb = (int)(sg.q0 % sg.j->WH);
+                sp.sb = (int)(sg.q0 / sg.j->WH);
+                sp.fwh = make_fastdiv((uint32_t)sg.j->WH);
+                sp.W = t->W;
+                sp.WH = sg.j->WH;
+                sp.s0 = t->sample_offset;
+                sp.spp_call = t->spp;
+                sp.key = make_uint2(t->seed, (uint32_t)t->render_id);
+                sp.hit_log = t->hit_log;
+                sp.glass_from = sg.j->glass_from;
+                sp.glass_to = sg.j->glass_to;
                 Timer tm(c, timing, 2);
                 HIP_TRY(c, launch_shade(sp, c->stream));
             }
@@ -908,42 +952,103 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
         }
         st = run_sweeps(c, -1, ph_sh(D), cap, count, timing, D, N);
         if (st != SDD_OK) return st;
-        SpectralParams xp{};
-        xp.N = N;
-        xp.pb = pb;
-        xp.sb = sb;
-        xp.fwh = fwh;
-        xp.ngrp = c->nlp / 4;
-        xp.fgrp = make_fastdiv((uint32_t)xp.ngrp);
-        xp.WH = WH;
-        xp.s0 = t->sample_offset;
-        xp.spp_call = t->spp;
-        xp.max_depth = D;
-        xp.vrec = c->vrec;
-        xp.sh_state = c->sh_state;
-        xp.sh_glass = c->sh_glass;
-        xp.pane = c->d_pane;
-        xp.n_glass = std::max(1, c->n_glass);
-        xp.coat = c->d_coat;
-        xp.coat_n = c->coat_layers ? c->d_coat_n : nullptr;
-        xp.coat_layers = c->coat_layers;
-        xp.n_mats = c->M;
-        xp.rho = c->d_rho;
-        xp.le = c->d_le;
-        xp.nl = c->nl;
-        xp.nlp = c->nlp;
-        xp.light_mat = c->light_mat < 0 ? 0 : c->light_mat;
-        xp.acc = rd.acc;
-        xp.shadow_log = t->shadow_log;
-        {
+        for (const Seg& sg : segs) {
+            const sdd_trace_desc* t = sg.j->t;
+            SpectralParams xp{};
+            xp.N = sg.n;
+            xp.pid_off = sg.pid_off;
+            xp.N_all = N;
+            xp.pb = (int)(sg.q0 % sg.j->WH);
+            xp.sb = (int)(sg.q0 / sg.j->WH);
+            xp.fwh = make_fastdiv((uint32_t)sg.j->WH);
+            xp.ngrp = c->nlp / 4;
+            xp.fgrp = make_fastdiv((uint32_t)xp.ngrp);
+            xp.WH = sg.j->WH;
+            xp.s0 = t->sample_offset;
+            xp.spp_call = t->spp;
+            xp.max_depth = D;
+            xp.vrec = c->vrec;
+            xp.sh_state = c->sh_state;
+            xp.sh_glass = c->sh_glass;
+            xp.pane = c->d_pane;
+            xp.n_glass = std::max(1, c->n_glass);
+            xp.coat = c->d_coat;
+            xp.coat_n = c->coat_layers ? c->d_coat_n : nullptr;
+            xp.coat_layers = c->coat_layers;
+            xp.glass_from = sg.j->glass_from;
+            xp.glass_to = sg.j->glass_to;
+            xp.n_mats = c->M;
+            xp.rho = c->d_rho;
+            xp.le = c->d_le;
+            xp.nl = c->nl;
+            xp.nlp = c->nlp;
+            xp.light_mat = c->light_mat < 0 ? 0 : c->light_mat;
+            xp.acc = sg.j->rd->acc;
+            xp.shadow_log = t->shadow_log;
             Timer tm(c, timing, 3);
             HIP_TRY(c, launch_spectral(xp, c->stream));
         }
         ++c->batches;
     }
-    rd.spp_done += t->spp;
+    for (Job& j : jobs) j.rd->spp_done += j.t->spp;
     return SDD_OK;
 }
+
+// the accumulator of render_id (created on first use)
+sdd_status render_for(sdd_ctx* c, const sdd_trace_desc* t, Render*& out) {
+    auto it = c->renders.find(t->render_id);
+    if (it != c->renders.end() && (it->second.W != t->W || it->second.H != t->H))
+        return fail(c, SDD_ERR_INVALID_ARG, "render_id reused with a different W, H");
+    if (it == c->renders.end()) {
+        Render rd;
+        rd.W = t->W;
+        rd.H = t->H;
+        const size_t n = (size_t)c->nlp * t->W * t->H;
+        sdd_status st = dalloc(c, &rd.acc, n);
+        if (st != SDD_OK) return st;
+        HIP_TRY(c, hipMemsetAsync(rd.acc, 0, sizeof(float) * n, c->stream));
+        it = c->renders.emplace(t->render_id, rd).first;
+    }
+    out = &it->second;
+    return SDD_OK;
+}
+
+sdd_status trace_call(sdd_ctx* c, int n, const sdd_trace_desc* descs) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!c->has_bvh) return fail(c, SDD_ERR_STATE, "trace before sdd_build_bvh");
+    if (n < 1 || n > SDD_MAX_RENDERS || !descs) return fail(c, SDD_ERR_INVALID_ARG, "bad render count");
+    std::vector<Job> jobs((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        sdd_status st = check_desc(c, &descs[i], jobs[i]);
+        if (st != SDD_OK) return st;
+        if (descs[i].max_depth != descs[0].max_depth)
+            return fail(c, SDD_ERR_INVALID_ARG, "renders of one call must share max_depth");
+        for (int k = 0; k < i; ++k)
+            if (descs[k].render_id == descs[i].render_id)
+                return fail(c, SDD_ERR_INVALID_ARG, "render_id repeated within one call");
+    }
+    DeviceGuard g(c->device);
+    for (int i = 0; i < n; ++i) {
+        sdd_status st = render_for(c, &descs[i], jobs[i].rd);
+        if (st != SDD_OK) return st;
+    }
+    return trace_jobs(c, jobs);
+}
+
+}  // namespace
+
+extern "C" {
+
+sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
+    if (c && !t) {
+        c->err = "null trace desc";
+        return SDD_ERR_INVALID_ARG;
+    }
+    return trace_call(c, 1, t);
+}
+
+sdd_status sdd_trace_batch(sdd_ctx* c, int32_t n, const sdd_trace_desc* descs) { return trace_call(c, n, descs); }
 
 sdd_status sdd_resolve_image(sdd_ctx* c, int32_t render_id, double* spectral_out, double* xyz_out,
                              int32_t out_is_device) {

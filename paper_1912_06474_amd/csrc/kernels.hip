@@ -103,14 +103,16 @@ __device__ __forceinline__ int locate_ray(const GridParams& g, f3 o, f3 d, float
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
     __shared__ int s_wcnt[(kShadeBlock / 64) * kMaxCells];
-    const int pid = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = pid < P.N;
+    const int lpid = blockIdx.x * blockDim.x + threadIdx.x;  // path of the segment
+    const int pid = P.pid_off + lpid;                        // path of the batch
+    const int blk = P.pid_off / kShadeBlock + blockIdx.x;    // histogram column
+    const bool valid = lpid < P.N;
     bool enq = false;
     int cell = 0;
     f3 o{0, 0, 0}, d{0, 0, 1};
     float t_enter = 0.0f;
     if (valid) {
-        const uint32_t q = (uint32_t)(P.pb + pid);
+        const uint32_t q = (uint32_t)(P.pb + lpid);
         const uint32_t qs = fdiv(q, P.fwh);
         const int s = P.s0 + P.sb + (int)qs;
         const int p = (int)(q - qs * (uint32_t)P.WH);
@@ -138,16 +140,16 @@ __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
         enq = cell >= 0;
     }
     const int rank = block_rank(enq, cell, P.n_cells, s_wcnt);
-    if (valid) {
-        P.se.tag[pid] = enq ? (cell | (rank << 16)) : -1;
-        if (enq) {
-            P.se.qa[pid] = make_float4(o.x, o.y, o.z, t_enter);
-            P.se.qb[pid] = make_float4(d.x, d.y, d.z, __int_as_float(pid));
-            P.se.qc[pid] = make_int2(-1, __float_as_int(INFINITY));
-        }
+    // every slot of the segment's blocks gets a tag (-1 past its last path)
+    P.se.tag[pid] = enq ? (cell | (rank << 16)) : -1;
+    if (enq) {
+        P.se.qa[pid] = make_float4(o.x, o.y, o.z, t_enter);
+        P.se.qb[pid] = make_float4(d.x, d.y, d.z, __int_as_float(pid));
+        P.se.qc[pid] = make_int2(-1, __float_as_int(INFINITY));
     }
+    if (!valid) P.flags[pid] = 0;
     for (int c = threadIdx.x; c < P.n_cells; c += blockDim.x)
-        P.se.hist[(long long)c * P.n_blocks + blockIdx.x] = block_key_total(c, P.n_cells, s_wcnt);
+        P.se.hist[(long long)c * P.n_blocks + blk] = block_key_total(c, P.n_cells, s_wcnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -498,8 +500,10 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
         for (int i = threadIdx.x; i < n_pane; i += blockDim.x) s_pane[i] = P.pane[i];
     __syncthreads();
     const float4* pane = pane_lds ? s_pane : P.pane;
-    const int pid = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = pid < P.N;
+    const int lpid = blockIdx.x * blockDim.x + threadIdx.x;  // path of the segment
+    const int pid = P.pid_off + lpid;                        // path of the batch
+    const int blk = P.pid_off / kShadeBlock + blockIdx.x;    // histogram column
+    const bool valid = lpid < P.N;
     bool enq_e = false, enq_s = false;
     int cell_e = 0, cell_s = 0;
     f3 xo{0, 0, 0}, dn{0, 0, 1}, ws{0, 0, 1};
@@ -508,7 +512,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
     if (valid) {
         uint32_t fl = P.flags[pid];
         if (fl & kAlive) {
-            const uint32_t q = (uint32_t)(P.pb + pid);
+            const uint32_t q = (uint32_t)(P.pb + lpid);
             const uint32_t qs = fdiv(q, P.fwh);
             const int s = P.s0 + P.sb + (int)qs;
             const int p = (int)(q - qs * (uint32_t)P.WH);
@@ -525,8 +529,10 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                 const d3 o{ro.x, ro.y, ro.z}, d{rd.x, rd.y, rd.z};
                 const float4 pi = P.prim_info[prim];
                 const int word = __float_as_int(pi.w);
-                const int m = word & kMatIdMask;  // material, or compact glass index for glass
                 const int typ = (word >> kMatTypeShift) & 3;
+                // material, or compact glass index for glass (with this render's substitution)
+                int m = word & kMatIdMask;
+                if (typ == kGlass && m == P.glass_from) m = P.glass_to;
                 const int emits = (word & kMatEmits) ? kVEmits : 0;
                 // geometry in FP64 from the triangle's vertices: N = (v1 - v0) x (v2 - v0),
                 // the hit point on its plane x = o + t d with t = N.(v0 - o) / N.d (the
@@ -631,28 +637,25 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
         }
     }
     // stage both rays in path order; k_route scatters them into the queues
+    // every slot of the segment's blocks gets a tag (-1 past its last path)
     const int rank_e = block_rank(enq_e, cell_e, P.n_cells, s_wcnt);
-    if (valid) {
-        P.se.tag[pid] = enq_e ? (cell_e | (rank_e << 16)) : -1;
-        if (enq_e) {
-            P.se.qa[pid] = make_float4(xo.x, xo.y, xo.z, te);
-            P.se.qb[pid] = make_float4(dn.x, dn.y, dn.z, __int_as_float(pid));
-            P.se.qc[pid] = make_int2(prim, __float_as_int(INFINITY));
-        }
+    P.se.tag[pid] = enq_e ? (cell_e | (rank_e << 16)) : -1;
+    if (enq_e) {
+        P.se.qa[pid] = make_float4(xo.x, xo.y, xo.z, te);
+        P.se.qb[pid] = make_float4(dn.x, dn.y, dn.z, __int_as_float(pid));
+        P.se.qc[pid] = make_int2(prim, __float_as_int(INFINITY));
     }
     for (int c = threadIdx.x; c < P.n_cells; c += blockDim.x)
-        P.se.hist[(long long)c * P.n_blocks + blockIdx.x] = block_key_total(c, P.n_cells, s_wcnt);
+        P.se.hist[(long long)c * P.n_blocks + blk] = block_key_total(c, P.n_cells, s_wcnt);
     const int rank_s = block_rank(enq_s, cell_s, P.n_cells, s_wcnt);
-    if (valid) {
-        P.ss.tag[pid] = enq_s ? (cell_s | (rank_s << 16)) : -1;
-        if (enq_s) {
-            P.ss.qa[pid] = make_float4(xo.x, xo.y, xo.z, ts);
-            P.ss.qb[pid] = make_float4(ws.x, ws.y, ws.z, __int_as_float(pid));
-            P.ss.qc[pid] = make_int2(prim, __float_as_int(r_sh));
-        }
+    P.ss.tag[pid] = enq_s ? (cell_s | (rank_s << 16)) : -1;
+    if (enq_s) {
+        P.ss.qa[pid] = make_float4(xo.x, xo.y, xo.z, ts);
+        P.ss.qb[pid] = make_float4(ws.x, ws.y, ws.z, __int_as_float(pid));
+        P.ss.qc[pid] = make_int2(prim, __float_as_int(r_sh));
     }
     for (int c = threadIdx.x; c < P.n_cells; c += blockDim.x)
-        P.ss.hist[(long long)c * P.n_blocks + blockIdx.x] = block_key_total(c, P.n_cells, s_wcnt);
+        P.ss.hist[(long long)c * P.n_blocks + blk] = block_key_total(c, P.n_cells, s_wcnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -755,7 +758,7 @@ __global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
     const float4 leL = *reinterpret_cast<const float4*>(P.le + (size_t)P.light_mat * P.nlp + l0);
     float4* accp = reinterpret_cast<float4*>(P.acc + (size_t)p * P.nlp + l0);
     float4 a = *accp;
-    for (int pid = i; pid < P.N; pid += P.WH, ++s) {
+    for (int pid = P.pid_off + i; pid < P.pid_off + P.N; pid += P.WH, ++s) {
         float4 beta = make_float4(1.0f, 1.0f, 1.0f, 1.0f), L = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         bool live = true;
         for (int d0 = 0; d0 < P.max_depth && live; d0 += kVBlock) {
@@ -764,7 +767,7 @@ __global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
 #pragma unroll
             for (int j = 0; j < kVBlock; ++j) {
                 const bool in = d0 + j < P.max_depth;
-                const size_t vi = (size_t)(in ? d0 + j : 0) * P.N + pid;  // always a valid address
+                const size_t vi = (size_t)(in ? d0 + j : 0) * P.N_all + pid;  // always a valid address
                 v[j] = in ? P.vrec[vi] : make_int4(kVNone, 0, 0, 0);
                 shs[j] = in ? P.sh_state[vi] : kShNone;
             }
@@ -802,9 +805,10 @@ __global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
                         float4 trv = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
                         const int ng = min(shs[j] >> 4, kMaxGlass);
                         for (int k = 0; k < ng; ++k) {
-                            const size_t vi = (size_t)(d0 + j) * P.N + pid;
+                            const size_t vi = (size_t)(d0 + j) * P.N_all + pid;
                             const float2 gl = P.sh_glass[vi * kMaxGlass + k];
-                            const int gi = min(max(__float_as_int(gl.y), 0), P.n_glass - 1);
+                            int gi = min(max(__float_as_int(gl.y), 0), P.n_glass - 1);
+                            if (gi == P.glass_from) gi = P.glass_to;
                             float4 Rg, Tg;
                             glass_RT4<COATED>(pane, P.coat, P.coat_n, P.coat_layers, P.nlp, gi, l0, gl.x, Rg, Tg);
                             trv = f4mul(trv, Tg);

@@ -151,7 +151,9 @@ struct TraceParams {
 };
 
 struct ShadeParams {
-    int N;                 // paths in this batch
+    int N;                 // paths of this render segment
+    int pid_off;           // its first path in the batch (a multiple of kShadeBlock)
+    int glass_from, glass_to;  // compact glass index substituted for this render (-1: none)
     int pb, sb;            // pixel and sample of the batch's first path
     FastDiv fwh;           // division by W * H
     int W, WH;
@@ -188,7 +190,8 @@ struct ShadeParams {
 };
 
 struct CamParams {
-    int N;
+    int N;                 // paths of this render segment
+    int pid_off;           // its first path in the batch (a multiple of kShadeBlock)
     int pb, sb;
     FastDiv fwh;
     int W, H, WH;
@@ -235,7 +238,10 @@ struct GlassTable {
 
 // replay of the path histories, one thread per (pixel, wavelength)
 struct SpectralParams {
-    int N;
+    int N;                 // paths of this render segment
+    int pid_off;           // its first path in the batch
+    int N_all;             // paths in the batch (stride of the history arrays)
+    int glass_from, glass_to;  // compact glass index substituted for this render (-1: none)
     int pb, sb;
     FastDiv fwh;
     int ngrp;              // wavelength groups of 4 (nlp / 4)

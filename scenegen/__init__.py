@@ -443,6 +443,56 @@ def furnished_room(seed: int = 1, n_lambda: int = 41, min_tris: int = 200_000,
                    name=name or f"furnished_room(seed={seed},nl={n_lambda},T>={min_tris})", seed=seed)
 
 
+def photochromic_k(lam_nm, k_peak: float, k0: float = 1e-7, sigma_nm: float = 50.0):
+    """Darkened pane absorption k(lambda) = k0 + (k_peak - k0) exp(-(lambda - 550)^2 / (2 sigma^2))."""
+    lam = np.asarray(lam_nm, dtype=np.float64)
+    return (k0 + (k_peak - k0) * np.exp(-0.5 * ((lam - 550.0) / sigma_nm) ** 2)).astype(np.float32)
+
+
+def photochromic_states(scene, n_states: int = 8, k_lo: float = 1e-7, k_hi: float = 5e-6):
+    """Append ``n_states`` darkening states of the scene's (first) glass material
+    as extra glass materials (k_peak log-spaced over [k_lo, k_hi]); returns
+    (scene, base glass material, [state material indices]).  A render selects
+    a state by substituting its material for the base one."""
+    sc = dict(scene)
+    base = int(np.flatnonzero(sc["mat_type"] == GLASS)[0])
+    lam = sc["lambda_nm"]
+    ks = [photochromic_k(lam, kp) for kp in np.geomspace(k_lo, k_hi, n_states)]
+    M = len(sc["mat_type"])
+    rep = lambda a: np.concatenate([a, np.repeat(a[base:base + 1], n_states, axis=0)])
+    sc["mat_type"] = rep(sc["mat_type"])
+    sc["mat_rho"] = rep(sc["mat_rho"])
+    sc["mat_n"] = rep(sc["mat_n"])
+    sc["mat_thick"] = rep(sc["mat_thick"])
+    sc["mat_le"] = rep(sc["mat_le"])
+    sc["mat_k"] = np.concatenate([sc["mat_k"], np.stack(ks).astype(np.float32)])
+    for key in ("mat_n_layers", "mat_layer_d", "mat_layer_n", "mat_layer_k"):
+        if key in sc:
+            sc[key] = rep(sc[key])
+    sc["name"] = f"{scene['name']}+{n_states} photochromic states"
+    return sc, base, list(range(M, M + n_states))
+
+
+def batch_renders(n: int = 64, seed: int = 2, n_states: int = 8, sizes=(128, 256, 512, 1024), spp: int = 8):
+    """Seeded render list for the batched workload: square resolutions drawn
+    uniformly from ``sizes``, camera poses inside the room (eye 0.3 m clear of
+    the walls, heading uniform, pitch within +-15 degrees, vertical fov 60
+    degrees) and a photochromic state per render."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    room = np.asarray(ROOM)
+    out = []
+    for i in range(n):
+        res = int(rng.choice(sizes))
+        eye = rng.uniform(0.3, room - 0.3)
+        yaw = rng.uniform(0.0, 2.0 * math.pi)
+        pitch = math.radians(rng.uniform(-15.0, 15.0))
+        look = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
+        cam = dict(eye=tuple(float(x) for x in eye), target=tuple(float(x) for x in eye + look), fov_deg=60.0,
+                   ortho=False, ortho_half_h=1.0)
+        out.append(dict(camera=cam, W=res, H=res, spp=spp, render_id=i, state=int(rng.integers(0, n_states))))
+    return out
+
+
 def electrochromic_room(seed: int = 4, n_lambda: int = 81, min_tris: int = 4_000_000, coating_state: float = 0.6):
     """Large electrochromic workload: the furnished-room recipe grown to
     >= 4M triangles, 81 wavelengths, panes with the five-layer coating."""
