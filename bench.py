@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--count-work", action="store_true",
                     help="trace one extra (untimed) frame counting BVH node visits and triangle tests")
+    ap.add_argument("--device-bvh", action="store_true",
+                    help="build the subdomain BVHs on the GPU (linear BVH per cell) instead of the host SAH build")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -171,7 +173,7 @@ def main():
     tr = sdd.Tracer()
     tr.load_scene(scene)
     t0 = time.perf_counter()
-    tr.build_bvh(*wl["grid"])
+    tr.build_bvh(*wl["grid"], device=args.device_bvh)
     build_s = time.perf_counter() - t0
     st0 = tr.stats()
     log(f"[bench] build_bvh {wl['grid']}: {build_s:.2f} s, refs {st0['n_refs']}, nodes {st0['n_nodes']}, "
@@ -258,6 +260,7 @@ def main():
                      "launches": launches},
         "kernel_ms_per_step": {k: v / args.steps for k, v in kern_ms.items()},
         "build_bvh_s": build_s,
+        "bvh": "device LBVH" if args.device_bvh else "host binned SAH",
     }
     if args.count_work:
         tr.reset_stats()

@@ -132,6 +132,9 @@ typedef struct sdd_bvh_desc {
     int32_t nx, ny, nz;
     int32_t leaf_max;
     int32_t sah_bins;
+    int32_t device_build;  /* nonzero: build the references and BVHs on the GPU
+                              (linear BVH per cell from Morton-sorted reference
+                              centroids, Karras 2012; sah_bins unused) */
 } sdd_bvh_desc;
 
 /* sdd_trace_desc.flags */

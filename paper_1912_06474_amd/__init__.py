@@ -54,7 +54,7 @@ class SceneDesc(C.Structure):
 
 class BvhDesc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("leaf_max", C.c_int32),
-                ("sah_bins", C.c_int32)]
+                ("sah_bins", C.c_int32), ("device_build", C.c_int32)]
 
 
 class TraceDesc(C.Structure):
@@ -203,8 +203,10 @@ class Tracer:
         self._check(lib().sdd_load_scene(self.h, C.byref(sa.desc)))
         self.n_lambda = sa.n_lambda
 
-    def build_bvh(self, nx=1, ny=1, nz=1, leaf_max=4, sah_bins=16):
-        self._check(lib().sdd_build_bvh(self.h, C.byref(BvhDesc(nx, ny, nz, leaf_max, sah_bins))))
+    def build_bvh(self, nx=1, ny=1, nz=1, leaf_max=4, sah_bins=16, device=False):
+        """Subdomain grid and per-cell BVHs: host binned SAH, or with device=True a
+        linear BVH per cell built on the GPU."""
+        self._check(lib().sdd_build_bvh(self.h, C.byref(BvhDesc(nx, ny, nz, leaf_max, sah_bins, int(bool(device))))))
 
     def _desc(self, camera, W, H, spp, max_depth, seed=0, render_id=0, sample_offset=0, time_kernels=False,
               count_work=False, hit_log=None, shadow_log=None, glass_swap=None):

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "bvh_build.h"
+#include "bvh_device.h"
 #include "kernels.h"
 #include "layout.h"
 #include "sdd.h"
@@ -688,6 +689,123 @@ sdd_status sdd_load_scene(sdd_ctx* c, const sdd_scene_desc* s) {
     return SDD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Grid planes on the host, references and BVHs on the device (bvh_device.hip);
+// fills the context's device arrays and gb's host-side counts.
+sdd_status device_bvh(sdd_ctx* c, const BuildInput& bi, GridBvh& gb) {
+    std::string err;
+    double ext = 0.0;
+    if (!grid_planes(bi, gb, ext, err)) return fail(c, SDD_ERR_INVALID_ARG, err);
+    sdd_status st = upload(c, &c->d_planes, gb.planes.data(), gb.planes.size());
+    if (st != SDD_OK) return st;
+    const int G = bi.nx * bi.ny * bi.nz;
+    DevBuildArgs a{};
+    a.T = bi.n_tris;
+    a.prim_v = c->d_prim_v;
+    a.prim_info = c->d_prim_info;
+    a.planes = c->d_planes;
+    a.n[0] = bi.nx;
+    a.n[1] = bi.ny;
+    a.n[2] = bi.nz;
+    a.G = G;
+    a.cpad = 1e-4 * ext;
+    a.npad = 2e-6 * ext;
+    a.leaf_max = bi.leaf_max;
+    DevBuildBufs b{};
+    std::vector<void*> temps;
+    auto tmp_alloc = [&](auto** p, size_t n) -> sdd_status {
+        sdd_status s2 = dalloc(c, p, n);
+        if (s2 == SDD_OK) temps.push_back((void*)*p);
+        return s2;
+    };
+    auto release = [&]() {
+        for (void* p : temps) dfree(c, p);
+        temps.clear();
+    };
+    // references per triangle and their prefix
+    size_t scan_bytes = 0;
+    if ((st = tmp_alloc(&b.count, (size_t)a.T)) != SDD_OK || (st = tmp_alloc(&b.offset, (size_t)a.T)) != SDD_OK) {
+        release();
+        return st;
+    }
+    hipError_t e = dev_count_refs(a, b.count, b.offset, nullptr, scan_bytes, c->stream);
+    char* scan_tmp = nullptr;
+    if (e == hipSuccess && (st = tmp_alloc(&scan_tmp, std::max<size_t>(1, scan_bytes))) != SDD_OK) {
+        release();
+        return st;
+    }
+    if (e == hipSuccess) e = dev_count_refs(a, b.count, b.offset, scan_tmp, scan_bytes, c->stream);
+    int last[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(&last[0], b.offset + a.T - 1, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&last[1], b.count + a.T - 1, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        release();
+        return hip_fail(c, e, "device BVH: reference count");
+    }
+    const long long total = (long long)last[0] + last[1];
+    if (total <= 0 || total >= (1LL << 31) / 3) {
+        release();
+        return fail(c, SDD_ERR_UNSUPPORTED, "device BVH: reference count out of range");
+    }
+    b.total = total;
+    size_t sort_bytes = 0;
+    e = dev_sort_bytes(total, sort_bytes);
+    if (e != hipSuccess) {
+        release();
+        return hip_fail(c, e, "device BVH: sort scratch");
+    }
+    b.tmp_bytes = std::max<size_t>(1, sort_bytes);
+    char* sort_tmp = nullptr;
+    const size_t T3 = (size_t)total;
+    if ((st = tmp_alloc(&sort_tmp, b.tmp_bytes)) != SDD_OK || (st = tmp_alloc(&b.ref_lo, T3)) != SDD_OK ||
+        (st = tmp_alloc(&b.ref_hi, T3)) != SDD_OK || (st = tmp_alloc(&b.key_in, T3)) != SDD_OK ||
+        (st = tmp_alloc(&b.key, T3)) != SDD_OK || (st = tmp_alloc(&b.val_in, T3)) != SDD_OK ||
+        (st = tmp_alloc(&b.val, T3)) != SDD_OK || (st = tmp_alloc(&b.cell_start, (size_t)G + 1)) != SDD_OK ||
+        (st = tmp_alloc(&b.child, T3)) != SDD_OK || (st = tmp_alloc(&b.range, T3)) != SDD_OK ||
+        (st = tmp_alloc(&b.parent, 2 * T3)) != SDD_OK || (st = tmp_alloc(&b.arrive, T3)) != SDD_OK ||
+        (st = tmp_alloc(&b.box_lo, T3)) != SDD_OK || (st = tmp_alloc(&b.box_hi, T3)) != SDD_OK ||
+        (st = tmp_alloc(&b.level_a, T3)) != SDD_OK || (st = tmp_alloc(&b.level_b, T3)) != SDD_OK ||
+        (st = tmp_alloc(&b.last_flag, T3)) != SDD_OK || (st = tmp_alloc(&b.max_depth, 2)) != SDD_OK ||
+        (st = dalloc(c, &c->d_nodes, 2 * (T3 + (size_t)G))) != SDD_OK ||
+        (st = dalloc(c, &c->d_tris, 3 * T3)) != SDD_OK || (st = dalloc(c, &c->d_cell_q, 2 * (size_t)G)) != SDD_OK ||
+        (st = dalloc(c, &c->d_cell_root, (size_t)G)) != SDD_OK ||
+        (st = dalloc(c, &c->d_cell_nodes, (size_t)G)) != SDD_OK) {
+        release();
+        return st;
+    }
+    b.tmp = sort_tmp;
+    b.error = b.max_depth + 1;
+    b.nodes = c->d_nodes;
+    b.tris = c->d_tris;
+    b.cell_q = c->d_cell_q;
+    b.cell_root = c->d_cell_root;
+    b.cell_nodes = c->d_cell_nodes;
+    int flags[2] = {0, 0};
+    gb.cell_nodes.assign(G, 0);
+    e = hipMemsetAsync(b.max_depth, 0, 2 * sizeof(int), c->stream);
+    if (e == hipSuccess) e = dev_build(a, b, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags, b.max_depth, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(gb.cell_nodes.data(), c->d_cell_nodes, sizeof(int) * G, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    release();
+    if (e != hipSuccess) return hip_fail(c, e, "device BVH build");
+    if (flags[1] != 0) return fail(c, SDD_ERR_HIP, "device BVH build produced an inconsistent hierarchy");
+    gb.n_refs = total;
+    gb.max_depth = flags[0];
+    gb.cell_root.assign(G, 0);
+    gb.cell_refs.assign(G, 0);
+    return SDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
     if (!c) return SDD_ERR_INVALID_ARG;
     c->err.clear();
@@ -708,9 +826,16 @@ sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
                   c->glass_of.data(), c->mat_emits.data(), d->nx, d->ny, d->nz, leaf, bins};
     std::string err;
     GridBvh gb;
-    if (!build_grid_bvh(bi, gb, err)) return fail(c, SDD_ERR_INVALID_ARG, err);
     sdd_status st;
-    if ((st = upload(c, &c->d_nodes, reinterpret_cast<const uint4*>(gb.nodes.data()), gb.nodes.size() / 4)) != SDD_OK ||
+    if (d->device_build) {
+        st = device_bvh(c, bi, gb);
+        if (st != SDD_OK) {
+            free_accel(c);
+            return st;
+        }
+    } else if (!build_grid_bvh(bi, gb, err)) {
+        return fail(c, SDD_ERR_INVALID_ARG, err);
+    } else if ((st = upload(c, &c->d_nodes, reinterpret_cast<const uint4*>(gb.nodes.data()), gb.nodes.size() / 4)) != SDD_OK ||
         (st = upload(c, &c->d_cell_q, reinterpret_cast<const float4*>(gb.cell_q.data()), gb.cell_q.size())) != SDD_OK ||
         (st = upload(c, &c->d_cell_nodes, gb.cell_nodes.data(), gb.cell_nodes.size())) != SDD_OK ||
         (st = upload(c, &c->d_tris, reinterpret_cast<const float4*>(gb.tris.data()), gb.tris.size())) != SDD_OK ||

@@ -231,7 +231,7 @@ void triangle_info(const BuildInput& in, std::vector<HostF4>& info) {
     }
 }
 
-bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err) {
+bool grid_planes(const BuildInput& in, GridBvh& out, double& ext, std::string& err) {
     const int T = in.n_tris;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int i = 0; i < T; ++i)
@@ -242,34 +242,44 @@ bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err) {
                 hi[a] = std::max(hi[a], (double)p[a]);
             }
         }
-    double ext = 0.0;
+    ext = 0.0;
     for (int a = 0; a < 3; ++a) ext = std::max(ext, hi[a] - lo[a]);
     if (!(ext > 0.0) || !std::isfinite(ext)) {
         err = "scene has no spatial extent";
         return false;
     }
-    const double gpad = 1e-3 * ext, cpad = 1e-4 * ext, npad = 2e-6 * ext;
+    const double gpad = 1e-3 * ext;
     const int n[3] = {in.nx, in.ny, in.nz};
     out.nx = in.nx;
     out.ny = in.ny;
     out.nz = in.nz;
     out.planes.clear();
-    std::vector<float> pl[3];
     for (int a = 0; a < 3; ++a) {
         const double g0 = lo[a] - gpad, g1 = hi[a] + gpad;
         out.lo[a] = g0;
         out.hi[a] = g1;
-        pl[a].resize(n[a] + 1);
-        for (int i = 0; i <= n[a]; ++i) pl[a][i] = (float)(g0 + (g1 - g0) * (double)i / (double)n[a]);
-        pl[a][0] = round_down(g0);
-        pl[a][n[a]] = round_up(g1);
+        std::vector<float> pl(n[a] + 1);
+        for (int i = 0; i <= n[a]; ++i) pl[i] = (float)(g0 + (g1 - g0) * (double)i / (double)n[a]);
+        pl[0] = round_down(g0);
+        pl[n[a]] = round_up(g1);
         for (int i = 0; i < n[a]; ++i)
-            if (!(pl[a][i + 1] > pl[a][i])) {
+            if (!(pl[i + 1] > pl[i])) {
                 err = "subdomain grid too fine for FP32 planes";
                 return false;
             }
-        out.planes.insert(out.planes.end(), pl[a].begin(), pl[a].end());
+        out.planes.insert(out.planes.end(), pl.begin(), pl.end());
     }
+    return true;
+}
+
+bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err) {
+    const int T = in.n_tris;
+    double ext = 0.0;
+    if (!grid_planes(in, out, ext, err)) return false;
+    const double cpad = 1e-4 * ext, npad = 2e-6 * ext;
+    const int n[3] = {in.nx, in.ny, in.nz};
+    std::vector<float> pl[3];
+    for (int a = 0, o = 0; a < 3; o += n[a] + 1, ++a) pl[a].assign(out.planes.begin() + o, out.planes.begin() + o + n[a] + 1);
     const int G = n[0] * n[1] * n[2];
 
     // references per cell

@@ -42,6 +42,10 @@ struct BuildInput {
 // Returns false and fills err on failure.
 bool build_grid_bvh(const BuildInput& in, GridBvh& out, std::string& err);
 
+// Only the subdomain grid (planes, lo, hi) and the scene extent, whose
+// fractions pad references (1e-4) and child boxes (2e-6).
+bool grid_planes(const BuildInput& in, GridBvh& out, double& ext, std::string& err);
+
 // Unit geometric normal (v1 - v0) x (v2 - v0) of every triangle, in double
 // then rounded, with the material word (layout.h) in w (as int bits).
 void triangle_info(const BuildInput& in, std::vector<HostF4>& info);
