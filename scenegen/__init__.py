@@ -493,6 +493,37 @@ def batch_renders(n: int = 64, seed: int = 2, n_states: int = 8, sizes=(128, 256
     return out
 
 
+def nrc_params(seed: int = 0, table_size: int = 1 << 19, levels: int = 16, features: int = 2, n_in: int = 64,
+               n_hid: int = 64, n_layers: int = 5):
+    """Seeded initial parameters of the radiance-cache network (inputs of both
+    the oracle and the GPU path): He-uniform weights U(-sqrt(6/fan_in),
+    sqrt(6/fan_in)), zero biases, hash-table entries U(-1e-4, 1e-4).  float32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W, b = [], []
+    fan = n_in
+    for _ in range(n_layers):
+        lim = math.sqrt(6.0 / fan)
+        W.append(rng.uniform(-lim, lim, size=(n_hid, fan)).astype(np.float32))
+        b.append(np.zeros(n_hid, np.float32))
+        fan = n_hid
+    lim = math.sqrt(6.0 / n_hid)
+    wo = rng.uniform(-lim, lim, size=n_hid).astype(np.float32)
+    tables = rng.uniform(-1e-4, 1e-4, size=(levels, table_size, features)).astype(np.float32)
+    return dict(W=W, b=b, wo=wo, bo=np.float32(0.0)), tables
+
+
+def nrc_rows(n: int, seed: int, aabb_lo=(0.0, 0.0, 0.0), aabb_hi=(4.0, 3.0, 2.5), lam=(380.0, 780.0)):
+    """Seeded query rows (position in the box, unit direction, wavelength) and
+    positive targets, for network tests."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.uniform(aabb_lo, aabb_hi, size=(n, 3))
+    w = rng.normal(size=(n, 3))
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    lam_nm = rng.uniform(lam[0], lam[1], size=n)
+    t = rng.gamma(2.0, 0.5, size=n)
+    return x.astype(np.float32), w.astype(np.float32), lam_nm.astype(np.float32), t.astype(np.float32)
+
+
 def electrochromic_room(seed: int = 4, n_lambda: int = 81, min_tris: int = 4_000_000, coating_state: float = 0.6):
     """Large electrochromic workload: the furnished-room recipe grown to
     >= 4M triangles, 81 wavelengths, panes with the five-layer coating."""

@@ -1,0 +1,163 @@
+"""Pins of the FP64 radiance-cache reference (oracle/nrc.py): closed forms,
+orthonormality, exact reproduction of affine fields, finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import nrc
+
+
+def test_sh_orthonormal():
+    # Gauss-Legendre in cos(theta) x uniform phi integrates degree <= 6 products exactly
+    xg, wg = np.polynomial.legendre.leggauss(24)
+    phi = (np.arange(48) + 0.5) * 2 * np.pi / 48
+    ct, ph = np.meshgrid(xg, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    w = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=-1).reshape(-1, 3)
+    wt = (wg[:, None] * np.full(len(phi), 2 * np.pi / 48)[None, :]).reshape(-1)
+    Y = nrc.sh_encode(w)
+    G = (Y * wt[:, None]).T @ Y
+    assert np.abs(G - np.eye(16)).max() < 1e-12
+
+
+def test_sh_low_bands_closed_form():
+    w = np.array([[0.6, 0.0, 0.8], [0.0, -1.0, 0.0], [0.36, 0.48, 0.8]])
+    Y = nrc.sh_encode(w)
+    c0, c1 = 0.5 / math.sqrt(math.pi), math.sqrt(3 / (4 * math.pi))
+    assert np.allclose(Y[:, 0], c0, rtol=1e-14)
+    assert np.allclose(Y[:, 1], c1 * w[:, 1], rtol=1e-13, atol=1e-15)  # (1,-1) ~ y
+    assert np.allclose(Y[:, 2], c1 * w[:, 2], rtol=1e-13, atol=1e-15)  # (1, 0) ~ z
+    assert np.allclose(Y[:, 3], c1 * w[:, 0], rtol=1e-13, atol=1e-15)  # (1, 1) ~ x
+    # (2, 0) = sqrt(5 / 16 pi) (3 z^2 - 1)
+    assert np.allclose(Y[:, 6], math.sqrt(5 / (16 * math.pi)) * (3 * w[:, 2] ** 2 - 1), rtol=1e-13, atol=1e-15)
+
+
+def test_level_resolutions():
+    r = [nrc.level_resolution(l) for l in range(16)]
+    assert r[0] == 16 and r[-1] in (2047, 2048)
+    assert all(b > a for a, b in zip(r, r[1:]))
+
+
+def test_corner_index_dense_and_hashed():
+    T = 1 << 19
+    # a dense level is a bijection of its (N + 1)^3 lattice onto [0, (N+1)^3)
+    N = 16
+    g = np.stack(np.meshgrid(*[np.arange(N + 1)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    idx = nrc.corner_index(g, N, T)
+    assert len(np.unique(idx)) == (N + 1) ** 3 and idx.max() == (N + 1) ** 3 - 1
+    # a hashed level: uint32 products of the three primes, xor, modulo T
+    N = 1000
+    c = np.array([[1, 2, 3], [7, 0, 999]])
+    expect = [(1 ^ ((2 * 2654435761) % 2 ** 32) ^ ((3 * 805459861) % 2 ** 32)) % T,
+              (7 ^ 0 ^ ((999 * 805459861) % 2 ** 32)) % T]
+    assert list(nrc.corner_index(c, N, T)) == expect
+
+
+def test_hash_encode_reproduces_affine_fields_on_dense_levels():
+    # tables holding an affine function of the lattice corner are interpolated exactly
+    T, F = 1 << 16, 2
+    tables = np.zeros((16, T, F))
+    a = np.array([0.3, -1.2, 0.7])
+    dense = [l for l in range(16) if (nrc.level_resolution(l) + 1) ** 3 <= T]
+    assert dense == [0, 1, 2]
+    for l in dense:
+        N = nrc.level_resolution(l)
+        g = np.stack(np.meshgrid(*[np.arange(N + 1)] * 3, indexing="ij"), -1).reshape(-1, 3)
+        idx = nrc.corner_index(g, N, T)
+        tables[l, idx, 0] = g @ a / N + 0.25
+        tables[l, idx, 1] = g[:, 2] / N
+    rng = np.random.default_rng(0)
+    xn = rng.uniform(0, 1, size=(200, 3))
+    f = nrc.hash_encode(xn, tables)
+    for l in dense:
+        assert np.allclose(f[:, 2 * l], xn @ a + 0.25, atol=1e-12)
+        assert np.allclose(f[:, 2 * l + 1], xn[:, 2], atol=1e-12)
+
+
+def test_one_blob():
+    lam = np.array([381.0, 590.0, 701.0])
+    B = nrc.blob_encode(lam)
+    u = (lam - 380) / 400 * 16
+    assert np.array_equal(np.argmax(B, axis=1), np.clip(np.floor(u), 0, 15).astype(int))
+    # an interior blob sums to ~sqrt(2 pi) (sampled unit Gaussian)
+    assert abs(B[1].sum() - math.sqrt(2 * math.pi)) < 1e-6
+
+
+def _small_net(seed=1):
+    params, tables = sg.nrc_params(seed, table_size=1 << 12)
+    p = {"W": [w.astype(np.float64) for w in params["W"]], "b": [np.asarray(b, np.float64) + 0.01 for b in params["b"]],
+         "wo": params["wo"].astype(np.float64), "bo": 0.1}
+    return p, tables.astype(np.float64) * 1e3
+
+
+def test_mlp_backward_matches_finite_differences():
+    p, tables = _small_net()
+    x, w, lam, t = sg.nrc_rows(16, 3)
+    X = nrc.encode(x, w, lam, (0, 0, 0), (4, 3, 2.5), tables)
+
+    def loss_of(pp, XX):
+        y, _ = nrc.mlp_forward(pp, XX)
+        return np.mean((y - t) ** 2)
+
+    y, acts = nrc.mlp_forward(p, X)
+    dy = 2 * (y - t) / len(y)
+    g, dX = nrc.mlp_backward(p, acts, dy)
+    h = 1e-6
+    for k, (i, j) in ((0, (3, 5)), (2, (10, 60)), (4, (63, 0))):
+        q = {"W": [w.copy() for w in p["W"]], "b": list(p["b"]), "wo": p["wo"], "bo": p["bo"]}
+        q["W"][k][i, j] += h
+        up = loss_of(q, X)
+        q["W"][k][i, j] -= 2 * h
+        dn = loss_of(q, X)
+        assert g["W"][k][i, j] == pytest.approx((up - dn) / (2 * h), rel=1e-5, abs=1e-9)
+    Xp = X.copy()
+    Xp[2, 7] += h
+    up = loss_of(p, Xp)
+    Xp[2, 7] -= 2 * h
+    dn = loss_of(p, Xp)
+    assert dX[2, 7] == pytest.approx((up - dn) / (2 * h), rel=1e-5, abs=1e-9)
+
+
+def test_hash_backward_matches_finite_differences():
+    _, tables = _small_net()
+    rng = np.random.default_rng(4)
+    xn = rng.uniform(0, 1, size=(8, 3))
+    dfeat = rng.normal(size=(8, 32))
+    gt = nrc.hash_backward(xn, dfeat, tables.shape)
+    f0 = nrc.hash_encode(xn, tables)
+    # the loss sum(dfeat * features) is linear in the tables: its gradient is exact
+    for (l, i, c) in ((0, 5, 0), (7, 100, 1), (15, 4000, 0)):
+        t2 = tables.copy()
+        t2[l, i, c] += 1.0
+        f1 = nrc.hash_encode(xn, t2)
+        assert np.sum(dfeat * (f1 - f0)) == pytest.approx(gt[l, i, c], rel=1e-12, abs=1e-14)
+
+
+def test_rel_l2_gradient_holds_the_denominator():
+    y = np.array([0.5, 2.0, -0.1])
+    t = np.array([1.0, 1.5, 0.0])
+    _, dy = nrc.rel_l2_loss(y, t)
+    assert np.allclose(dy, 2 * (y - t) / (y * y + 0.01) / 3)
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    opt = nrc.Adam(lr=1e-2)
+    opt.t = 1
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    q = opt.step("p", p, g)
+    assert np.allclose(q, p - 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_train_step_reduces_the_loss():
+    p, tables = _small_net(2)
+    tables = tables * 1e-3
+    x, w, lam, t = sg.nrc_rows(256, 5)
+    opt = nrc.Adam(lr=1e-3)
+    losses = []
+    for _ in range(30):
+        loss, p, tables = nrc.train_step(p, tables, opt, x, w, lam, t, (0, 0, 0), (4, 3, 2.5))
+        losses.append(loss)
+    assert losses[-1] < 0.5 * losses[0]
