@@ -291,6 +291,62 @@ sdd_status sdd_debug_trace_rays(sdd_ctx *ctx, int32_t n, const float *o, const f
 sdd_status sdd_debug_glass(sdd_ctx *ctx, int32_t n, const int32_t *mat, const int32_t *lam, const float *cs,
                            float *R_out, float *T_out);
 
+/*
+ * Learned radiance cache: a small network L(x, w, lambda) trained online on
+ * radiance estimates the tracer produces (neural radiance caching, Mueller,
+ * Rousselle, Novak, Keller 2021; multiresolution hash encoding, Mueller,
+ * Evans, Schied, Keller 2022).  One cache per context.
+ *   input   hash encoding of the position normalised to the box
+ *           [aabb_lo, aabb_hi] (16 levels, resolutions floor(16 b^l) with
+ *           b = exp(ln(2048 / 16) / 15), 2^table_log2 entries of 2 features
+ *           per level, direct indexing where (N + 1)^3 fits the table, else
+ *           the spatial hash with primes 1, 2654435761, 805459861), real
+ *           spherical harmonics of the unit direction (bands 0..3, 16 values)
+ *           and a one-blob encoding of the wavelength over
+ *           [lambda_lo, lambda_hi] (16 Gaussian bins);
+ *   network 5 hidden ReLU layers of 64, one linear output;
+ *   loss    relative L2, mean of (y - t)^2 / (y^2 + 0.01), y^2 held constant;
+ *   update  Adam (lr, beta1, beta2, eps).
+ * Parameters: one flat FP32 array of sdd_nrc_param_count(table_log2) values,
+ *   tables [16][T][2] | W [5][64][64] (out, in) | b [5][64] | wo [64] | bo [1].
+ */
+typedef struct sdd_nrc_desc {
+    int32_t table_log2;            /* T = 2^table_log2, 10..24 */
+    float aabb_lo[3], aabb_hi[3];  /* position box, hi > lo per axis */
+    float lambda_lo, lambda_hi;    /* nm, hi > lo */
+    float lr, beta1, beta2, eps;   /* lr > 0, 0 <= beta < 1, eps > 0 */
+    const float *params;           /* host; initial parameters (copied) */
+} sdd_nrc_desc;
+
+/* Parameter count for a table size; -1 if table_log2 is out of range. */
+int64_t sdd_nrc_param_count(int32_t table_log2);
+
+/* (Re)create the cache with the given parameters; Adam moments start at
+ * zero.  SDD_ERR_INVALID_ARG for a bad desc or non-finite parameters. */
+sdd_status sdd_nrc_init(sdd_ctx *ctx, const sdd_nrc_desc *desc);
+
+/* Network output of n rows, stream-ordered.  x, w: DEVICE float [n][3]
+ * (positions, unit directions); lambda_nm: DEVICE float [n]; y: DEVICE
+ * float [n].  precision 0: FP32 throughout; 1: BF16 matrix-core products
+ * with FP32 accumulation (inputs and hidden activations rounded to BF16
+ * where they enter a product; output layer in FP32).  SDD_ERR_STATE
+ * without sdd_nrc_init. */
+sdd_status sdd_nrc_infer(sdd_ctx *ctx, int32_t n, const float *x, const float *w, const float *lambda_nm, float *y,
+                         int32_t precision);
+
+/* One optimisation step on n rows (1 <= n <= 2^22) with targets t: the
+ * loss's gradient over all parameters (FP32), then, if apply, one Adam step.
+ * x, w, lambda_nm, t: DEVICE arrays as in sdd_nrc_infer.  loss: host float
+ * (the batch loss before the update; the call then synchronises) or NULL
+ * (asynchronous).  The gradient stays readable (sdd_nrc_get_params) until
+ * the next step. */
+sdd_status sdd_nrc_train_step(sdd_ctx *ctx, int32_t n, const float *x, const float *w, const float *lambda_nm,
+                              const float *t, int32_t apply, float *loss);
+
+/* Copy a parameter-sized array to the host: which 0 parameters, 1 last
+ * gradient, 2 Adam first moments, 3 second moments.  Synchronises. */
+sdd_status sdd_nrc_get_params(sdd_ctx *ctx, int32_t which, float *out);
+
 #ifdef __cplusplus
 }
 #endif

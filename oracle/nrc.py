@@ -17,7 +17,9 @@ written from the definitions:
   associated Legendre functions without the Condon-Shortley phase;
 * one-blob encoding of the wavelength: u = (lambda - lam_lo) / (lam_hi -
   lam_lo), 16 Gaussian bins exp(-(16 u - (i + 0.5))^2 / 2);
-* a multilayer perceptron 64 -> 64 (ReLU) x 5 hidden layers -> 1 (linear),
+* a multilayer perceptron 64 -> 64 (ReLU) x 5 hidden layers -> 1 (linear)
+  (also as BF16 matrix units evaluate it: hidden-layer operands rounded to
+  bfloat16, round to nearest even),
   its backward pass, the relative L2 loss (y - t)^2 / (sg(y)^2 + 0.01) with
   the prediction's magnitude held constant (Mueller, Rousselle, Novak,
   Keller, SIGGRAPH 2021), and Adam (Kingma and Ba, ICLR 2015).
@@ -143,6 +145,25 @@ def mlp_forward(params, X):
         acts.append(h)
     y = h @ params["wo"] + params["bo"]
     return y, acts
+
+
+def bf16_round(a):
+    """Nearest bfloat16 (ties to even) of each value taken as float32: the
+    float32 bit pattern rounded at bit 16 (IEEE round-to-nearest-even)."""
+    f = np.ascontiguousarray(np.asarray(a, np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))) & np.uint64(0xFFFF0000)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mlp_forward_bf16(params, X):
+    """The forward pass as BF16 matrix units evaluate it: each hidden layer's
+    operands (inputs and weights) rounded to bfloat16, products summed exactly
+    (here in float64) onto the bias, ReLU; the output layer unrounded."""
+    h = np.asarray(X, np.float64)
+    for k in range(N_LAYERS):
+        h = np.maximum(0.0, bf16_round(h) @ bf16_round(params["W"][k]).T + params["b"][k])
+    return h @ params["wo"] + params["bo"]
 
 
 def rel_l2_loss(y, t, eps=0.01):

@@ -29,7 +29,9 @@ TRACE_ORTHO, TRACE_TIME_KERNELS, TRACE_COUNT_WORK = 1, 2, 4
 
 EXPORTS = ("sdd_create", "sdd_destroy", "sdd_last_error", "sdd_load_scene", "sdd_validate_scene", "sdd_build_bvh",
            "sdd_trace_spectral", "sdd_resolve_image", "sdd_reset_render", "sdd_get_stats", "sdd_reset_stats",
-           "sdd_debug_philox", "sdd_debug_pane", "sdd_debug_trace_rays", "sdd_debug_glass", "sdd_trace_batch")
+           "sdd_debug_philox", "sdd_debug_pane", "sdd_debug_trace_rays", "sdd_debug_glass", "sdd_trace_batch",
+           "sdd_nrc_param_count", "sdd_nrc_init", "sdd_nrc_infer", "sdd_nrc_train_step", "sdd_nrc_get_params")
+NRC_LEVELS, NRC_FEAT, NRC_HID, NRC_LAYERS = 16, 2, 64, 5
 
 
 class SddError(RuntimeError):
@@ -64,6 +66,12 @@ class TraceDesc(C.Structure):
         ("max_depth", C.c_int32), ("seed", C.c_uint32), ("render_id", C.c_int32), ("flags", C.c_uint32),
         ("hit_log", C.c_void_p), ("shadow_log", C.c_void_p), ("glass_from", C.c_int32), ("glass_to", C.c_int32),
     ]
+
+
+class NrcDesc(C.Structure):
+    _fields_ = [("table_log2", C.c_int32), ("aabb_lo", C.c_float * 3), ("aabb_hi", C.c_float * 3),
+                ("lambda_lo", C.c_float), ("lambda_hi", C.c_float), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("params", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -111,6 +119,12 @@ def lib():
         L.sdd_debug_trace_rays.argtypes = [vp, i32, vp, vp, vp, vp]
         L.sdd_debug_glass.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.sdd_trace_batch.argtypes = [vp, i32, C.POINTER(TraceDesc)]
+        L.sdd_nrc_param_count.argtypes = [i32]
+        L.sdd_nrc_param_count.restype = C.c_int64
+        L.sdd_nrc_init.argtypes = [vp, C.POINTER(NrcDesc)]
+        L.sdd_nrc_infer.argtypes = [vp, i32, vp, vp, vp, vp, i32]
+        L.sdd_nrc_train_step.argtypes = [vp, i32, vp, vp, vp, vp, i32, C.POINTER(C.c_float)]
+        L.sdd_nrc_get_params.argtypes = [vp, i32, vp]
         _LIB = L
     return _LIB
 
@@ -312,6 +326,86 @@ class Tracer:
         prim = np.zeros(len(o), np.int32)
         self._check(lib().sdd_debug_trace_rays(self.h, len(o), _ptr(o), _ptr(d), _ptr(t), _ptr(prim)))
         return t, prim
+
+
+    # ---- learned radiance cache -------------------------------------------------
+    def nrc_init(self, params, tables, aabb_lo, aabb_hi, lambda_range=(380.0, 780.0), lr=1e-2, betas=(0.9, 0.99),
+                 eps=1e-8):
+        """Create the cache from a parameter dict (W [5][64][64], b [5][64], wo [64], bo) and hash
+        tables [16][T][2] (T a power of two)."""
+        T = int(np.asarray(tables).shape[1])
+        log2 = T.bit_length() - 1
+        if T != 1 << log2:
+            raise ValueError("table size must be a power of two")
+        flat = nrc_flatten(params, tables)
+        self._nrc_T = T
+        d = NrcDesc()
+        d.table_log2 = log2
+        d.aabb_lo[:] = [float(v) for v in aabb_lo]
+        d.aabb_hi[:] = [float(v) for v in aabb_hi]
+        d.lambda_lo, d.lambda_hi = float(lambda_range[0]), float(lambda_range[1])
+        d.lr, d.beta1, d.beta2, d.eps = float(lr), float(betas[0]), float(betas[1]), float(eps)
+        d.params = flat.ctypes.data
+        self._check(lib().sdd_nrc_init(self.h, C.byref(d)))
+
+    def _rows(self, *arrays):
+        out = []
+        for a in arrays:
+            t = self.torch.as_tensor(a, dtype=self.torch.float32, device=self.device).contiguous()
+            out.append(t)
+        return out
+
+    def nrc_infer(self, x, w, lam, precision="fp32"):
+        """Network outputs for rows (x [n,3], w [n,3], lambda [n]); a float32 device tensor."""
+        x, w, lam = self._rows(x, w, lam)
+        n = lam.numel()
+        y = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        prec = {"fp32": 0, "bf16": 1}[precision]
+        self._check(lib().sdd_nrc_infer(self.h, n, x.data_ptr(), w.data_ptr(), lam.data_ptr(), y.data_ptr(), prec))
+        return y
+
+    def nrc_train_step(self, x, w, lam, target, apply=True):
+        """One gradient (and, if apply, Adam) step; returns the batch loss before the update."""
+        x, w, lam, target = self._rows(x, w, lam, target)
+        loss = C.c_float()
+        self._check(lib().sdd_nrc_train_step(self.h, lam.numel(), x.data_ptr(), w.data_ptr(), lam.data_ptr(),
+                                             target.data_ptr(), int(bool(apply)), C.byref(loss)))
+        return float(loss.value)
+
+    def nrc_get(self, which="params"):
+        """(dict, tables) of the parameters, last gradient, or Adam moments ('m', 'v')."""
+        n = lib().sdd_nrc_param_count(self._nrc_T.bit_length() - 1)
+        out = np.empty(n, np.float32)
+        self._check(lib().sdd_nrc_get_params(self.h, {"params": 0, "grad": 1, "m": 2, "v": 3}[which], _ptr(out)))
+        return nrc_unflatten(out, self._nrc_T)
+
+
+def nrc_flatten(params, tables):
+    """Parameter dict + tables -> the library's flat float32 layout."""
+    tables = np.ascontiguousarray(tables, np.float32)
+    if tables.ndim != 3 or tables.shape[0] != NRC_LEVELS or tables.shape[2] != NRC_FEAT:
+        raise ValueError("tables must be [16][T][2]")
+    parts = [tables.reshape(-1),
+             np.ascontiguousarray(params["W"], np.float32).reshape(-1),
+             np.ascontiguousarray(params["b"], np.float32).reshape(-1),
+             np.ascontiguousarray(params["wo"], np.float32).reshape(-1),
+             np.asarray([params["bo"]], np.float32)]
+    flat = np.ascontiguousarray(np.concatenate(parts))
+    if flat.size != NRC_LEVELS * tables.shape[1] * NRC_FEAT + NRC_LAYERS * NRC_HID * (NRC_HID + 1) + NRC_HID + 1:
+        raise ValueError("parameter shapes do not match the network")
+    return flat
+
+
+def nrc_unflatten(flat, T):
+    nt = NRC_LEVELS * T * NRC_FEAT
+    o = nt
+    W = flat[o:o + NRC_LAYERS * NRC_HID * NRC_HID].reshape(NRC_LAYERS, NRC_HID, NRC_HID)
+    o += NRC_LAYERS * NRC_HID * NRC_HID
+    b = flat[o:o + NRC_LAYERS * NRC_HID].reshape(NRC_LAYERS, NRC_HID)
+    o += NRC_LAYERS * NRC_HID
+    wo = flat[o:o + NRC_HID]
+    bo = float(flat[o + NRC_HID])
+    return dict(W=list(W), b=list(b), wo=wo, bo=bo), flat[:nt].reshape(NRC_LEVELS, T, NRC_FEAT)
 
 
 def render(scene, W, H, spp, max_depth, grid=(1, 1, 1), *, camera=None, seed=0, logs=False, tracer=None):

@@ -27,6 +27,7 @@
 #include "bvh_device.h"
 #include "kernels.h"
 #include "layout.h"
+#include "nrc.h"
 #include "sdd.h"
 
 using namespace sdd;
@@ -114,6 +115,18 @@ struct sdd_ctx {
     std::map<int, Render> renders;
     std::map<void*, size_t> allocs;
     long long device_bytes = 0;
+
+    // learned radiance cache
+    bool has_nrc = false;
+    NrcNet nrc{};
+    float nrc_lr = 0.0f, nrc_b1 = 0.0f, nrc_b2 = 0.0f, nrc_eps = 0.0f;
+    int nrc_t = 0;  // Adam steps taken
+    long long nrc_cap = 0;
+    float* nrc_acts = nullptr;
+    float* nrc_dz = nullptr;
+    float* nrc_y = nullptr;
+    float* nrc_dy = nullptr;
+    float* nrc_loss = nullptr;
 
     // host stats
     long long batches = 0, launches_trace = 0, cam_rays = 0;
@@ -241,6 +254,25 @@ void free_batch(sdd_ctx* c) {
     dfree(c, c->d_counts);
     c->ncap = 0;
     c->dcap = 0;
+}
+
+void free_nrc_batch(sdd_ctx* c) {
+    dfree(c, c->nrc_acts);
+    dfree(c, c->nrc_dz);
+    dfree(c, c->nrc_y);
+    dfree(c, c->nrc_dy);
+    c->nrc_cap = 0;
+}
+
+void free_nrc(sdd_ctx* c) {
+    free_nrc_batch(c);
+    dfree(c, c->nrc_loss);
+    dfree(c, c->nrc.p);
+    dfree(c, c->nrc.g);
+    dfree(c, c->nrc.m);
+    dfree(c, c->nrc.v);
+    dfree(c, c->nrc.wq);
+    c->has_nrc = false;
 }
 
 void free_renders(sdd_ctx* c) {
@@ -551,6 +583,7 @@ void sdd_destroy(sdd_ctx* c) {
     free_batch(c);
     free_accel(c);
     free_scene(c);
+    free_nrc(c);
     dfree(c, c->d_overflow);
     dfree(c, c->d_gstack);
     dfree(c, c->d_stats);
@@ -1426,6 +1459,177 @@ sdd_status sdd_debug_trace_rays(sdd_ctx* c, int32_t n, const float* o, const flo
         std::memcpy(&p, &h[i].y, 4);
         prim_out[i] = p;
     }
+    return SDD_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Learned radiance cache
+// ===========================================================================
+namespace {
+
+constexpr int kNrcMinLog2 = 10, kNrcMaxLog2 = 24;
+constexpr int kNrcMaxRows = 1 << 22;
+
+long long nrc_count(int log2) {
+    const long long T = 1LL << log2;
+    return (long long)kNrcLevels * T * kNrcFeat + kNrcW + kNrcLayers * kNrcHid + kNrcHid + 1;
+}
+
+// K_l^|m| = sqrt((2l + 1) / (4 pi) (l - |m|)! / (l + |m|)!) in (l, m) order
+void sh_constants(float* K) {
+    auto fact = [](int k) {
+        double f = 1.0;
+        for (int i = 2; i <= k; ++i) f *= i;
+        return f;
+    };
+    int k = 0;
+    for (int l = 0; l < 4; ++l)
+        for (int m = -l; m <= l; ++m, ++k) {
+            const int am = m < 0 ? -m : m;
+            K[k] = (float)std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * fact(l - am) / fact(l + am));
+        }
+}
+
+sdd_status nrc_reserve(sdd_ctx* c, long long n) {
+    if (n <= c->nrc_cap) return SDD_OK;
+    free_nrc_batch(c);
+    sdd_status st;
+    if ((st = dalloc(c, &c->nrc_acts, (size_t)(kNrcLayers + 1) * kNrcHid * n)) != SDD_OK ||
+        (st = dalloc(c, &c->nrc_dz, (size_t)kNrcLayers * kNrcHid * n)) != SDD_OK ||
+        (st = dalloc(c, &c->nrc_y, (size_t)n)) != SDD_OK || (st = dalloc(c, &c->nrc_dy, (size_t)n)) != SDD_OK) {
+        free_nrc_batch(c);
+        return st;
+    }
+    c->nrc_cap = n;
+    return SDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t sdd_nrc_param_count(int32_t table_log2) {
+    if (table_log2 < kNrcMinLog2 || table_log2 > kNrcMaxLog2) return -1;
+    return nrc_count(table_log2);
+}
+
+sdd_status sdd_nrc_init(sdd_ctx* c, const sdd_nrc_desc* d) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!d) return fail(c, SDD_ERR_INVALID_ARG, "null nrc desc");
+    if (d->table_log2 < kNrcMinLog2 || d->table_log2 > kNrcMaxLog2)
+        return fail(c, SDD_ERR_INVALID_ARG, "table_log2 out of range");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(d->aabb_lo[a]) || !std::isfinite(d->aabb_hi[a]) || !(d->aabb_hi[a] > d->aabb_lo[a]))
+            return fail(c, SDD_ERR_INVALID_ARG, "bad position box");
+    if (!std::isfinite(d->lambda_lo) || !std::isfinite(d->lambda_hi) || !(d->lambda_hi > d->lambda_lo))
+        return fail(c, SDD_ERR_INVALID_ARG, "bad wavelength range");
+    if (!(d->lr > 0.0f) || !std::isfinite(d->lr) || !(d->beta1 >= 0.0f && d->beta1 < 1.0f) ||
+        !(d->beta2 >= 0.0f && d->beta2 < 1.0f) || !(d->eps > 0.0f) || !std::isfinite(d->eps))
+        return fail(c, SDD_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+    if (!d->params) return fail(c, SDD_ERR_INVALID_ARG, "null parameters");
+    const long long n_all = nrc_count(d->table_log2);
+    for (long long i = 0; i < n_all; ++i)
+        if (!std::isfinite(d->params[i])) return fail(c, SDD_ERR_INVALID_ARG, "non-finite parameter");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    free_nrc(c);
+    NrcNet& net = c->nrc;
+    net = NrcNet{};
+    net.T = 1 << d->table_log2;
+    net.n_tab = (long long)kNrcLevels * net.T * kNrcFeat;
+    net.n_all = n_all;
+    const double b = std::exp((std::log(2048.0) - std::log(16.0)) / (kNrcLevels - 1));
+    for (int l = 0; l < kNrcLevels; ++l) {
+        const int N = (int)std::floor(16.0 * std::pow(b, (double)l));
+        net.res[l] = N;
+        net.dense[l] = (long long)(N + 1) * (N + 1) * (N + 1) <= (long long)net.T ? 1 : 0;
+    }
+    for (int a = 0; a < 3; ++a) {
+        net.lo[a] = d->aabb_lo[a];
+        net.inv_ext[a] = (float)(1.0 / ((double)d->aabb_hi[a] - (double)d->aabb_lo[a]));
+    }
+    net.lam_lo = d->lambda_lo;
+    net.lam_inv = (float)(1.0 / ((double)d->lambda_hi - (double)d->lambda_lo));
+    sh_constants(net.shK);
+    sdd_status st;
+    if ((st = upload(c, &net.p, d->params, (size_t)n_all)) != SDD_OK || (st = dalloc(c, &net.g, (size_t)n_all)) != SDD_OK ||
+        (st = dalloc(c, &net.m, (size_t)n_all)) != SDD_OK || (st = dalloc(c, &net.v, (size_t)n_all)) != SDD_OK ||
+        (st = dalloc(c, &net.wq, (size_t)kNrcFrags * 8)) != SDD_OK || (st = dalloc(c, &c->nrc_loss, 1)) != SDD_OK) {
+        free_nrc(c);
+        return st;
+    }
+    hipError_t e = nrc_launch_zero(net.g, n_all, c->stream);
+    if (e == hipSuccess) e = nrc_launch_zero(net.m, n_all, c->stream);
+    if (e == hipSuccess) e = nrc_launch_zero(net.v, n_all, c->stream);
+    if (e == hipSuccess) e = nrc_launch_pack(net, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        free_nrc(c);
+        return hip_fail(c, e, "nrc init");
+    }
+    c->nrc_lr = d->lr;
+    c->nrc_b1 = d->beta1;
+    c->nrc_b2 = d->beta2;
+    c->nrc_eps = d->eps;
+    c->nrc_t = 0;
+    c->has_nrc = true;
+    return SDD_OK;
+}
+
+sdd_status sdd_nrc_infer(sdd_ctx* c, int32_t n, const float* x, const float* w, const float* lam, float* y,
+                         int32_t precision) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_infer before sdd_nrc_init");
+    if (n < 0 || (n > 0 && (!x || !w || !lam || !y))) return fail(c, SDD_ERR_INVALID_ARG, "bad rows");
+    if (precision != 0 && precision != 1) return fail(c, SDD_ERR_INVALID_ARG, "precision must be 0 or 1");
+    if (n == 0) return SDD_OK;
+    DeviceGuard g(c->device);
+    const hipError_t e = precision == 0 ? nrc_launch_infer(c->nrc, n, x, w, lam, y, c->stream)
+                                        : nrc_launch_infer_mfma(c->nrc, n, x, w, lam, y, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "nrc infer");
+    return SDD_OK;
+}
+
+sdd_status sdd_nrc_train_step(sdd_ctx* c, int32_t n, const float* x, const float* w, const float* lam, const float* t,
+                              int32_t apply, float* loss) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_train_step before sdd_nrc_init");
+    if (n < 1 || n > kNrcMaxRows) return fail(c, SDD_ERR_INVALID_ARG, "n out of range");
+    if (!x || !w || !lam || !t) return fail(c, SDD_ERR_INVALID_ARG, "null rows");
+    DeviceGuard g(c->device);
+    sdd_status st = nrc_reserve(c, n);
+    if (st != SDD_OK) return st;
+    NrcBatch b{n, x, w, lam, t, c->nrc_acts, c->nrc_dz, c->nrc_y, c->nrc_dy, c->nrc_loss};
+    hipError_t e = nrc_launch_zero(c->nrc.g, c->nrc.n_all, c->stream);
+    if (e == hipSuccess) e = nrc_launch_zero(c->nrc_loss, 1, c->stream);
+    if (e == hipSuccess) e = nrc_launch_grad(c->nrc, b, c->stream);
+    if (e == hipSuccess && apply) {
+        e = nrc_launch_adam(c->nrc, c->nrc_t + 1, c->nrc_lr, c->nrc_b1, c->nrc_b2, c->nrc_eps, c->stream);
+        if (e == hipSuccess) e = nrc_launch_pack(c->nrc, c->stream);
+        if (e == hipSuccess) ++c->nrc_t;
+    }
+    if (e == hipSuccess && loss) {
+        e = hipMemcpyAsync(loss, c->nrc_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "nrc train step");
+    return SDD_OK;
+}
+
+sdd_status sdd_nrc_get_params(sdd_ctx* c, int32_t which, float* out) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_get_params before sdd_nrc_init");
+    if (which < 0 || which > 3 || !out) return fail(c, SDD_ERR_INVALID_ARG, "bad arguments");
+    DeviceGuard g(c->device);
+    const float* src = which == 0 ? c->nrc.p : which == 1 ? c->nrc.g : which == 2 ? c->nrc.m : c->nrc.v;
+    HIP_TRY(c, hipMemcpyAsync(out, src, sizeof(float) * (size_t)c->nrc.n_all, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return SDD_OK;
 }
 

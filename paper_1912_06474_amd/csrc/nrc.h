@@ -1,0 +1,75 @@
+// Learned radiance cache: device state and kernel launchers (nrc.hip).
+//
+// Network: input 64 = multiresolution hash encoding of the position (16
+// levels x 2 features) + real spherical harmonics of the direction (bands
+// 0..3, 16) + one-blob encoding of the wavelength (16 bins); 5 hidden ReLU
+// layers of 64; one linear output (radiance at that wavelength).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sdd {
+
+constexpr int kNrcLevels = 16;
+constexpr int kNrcFeat = 2;
+constexpr int kNrcHash = kNrcLevels * kNrcFeat;  // 32
+constexpr int kNrcSh = 16;
+constexpr int kNrcBlob = 16;
+constexpr int kNrcIn = 64;
+constexpr int kNrcHid = 64;
+constexpr int kNrcLayers = 5;
+constexpr int kNrcW = kNrcLayers * kNrcHid * kNrcHid;  // hidden weights (out, in)
+// BF16 weights in matrix-core operand order: [layer][out tile 4][k step 2][lane 64] x 8 values
+constexpr int kNrcFrags = kNrcLayers * 4 * 2 * 64;
+
+// flat parameter space: tables [L][T][F] | W [5][64][64] | b [5][64] | wo [64] | bo
+struct NrcNet {
+    float* p;          // parameters (FP32 master copy)
+    float* g;          // gradients (same layout)
+    float* m;          // Adam first moments
+    float* v;          // Adam second moments
+    uint16_t* wq;      // [kNrcFrags][8] BF16 hidden weights, operand order (refreshed by nrc_launch_pack)
+    long long n_tab;   // L * T * F
+    long long n_all;   // all parameters
+    int T;             // table entries per level (power of two)
+    int res[kNrcLevels];
+    int dense[kNrcLevels];    // (res + 1)^3 <= T: direct indexing
+    float lo[3], inv_ext[3];  // position normalisation to [0, 1]^3
+    float lam_lo, lam_inv;    // wavelength normalisation to [0, 1]
+    float shK[kNrcSh];        // spherical-harmonic normalisation K_l^|m|, (l, m) order
+    __host__ __device__ long long off_W() const { return n_tab; }
+    __host__ __device__ long long off_b() const { return n_tab + kNrcW; }
+    __host__ __device__ long long off_wo() const { return n_tab + kNrcW + kNrcLayers * kNrcHid; }
+    __host__ __device__ long long off_bo() const { return off_wo() + kNrcHid; }
+};
+
+// one training batch on the device
+struct NrcBatch {
+    int n;              // rows
+    const float* x;     // [n][3] positions (m)
+    const float* w;     // [n][3] unit directions
+    const float* lam;   // [n] wavelengths (nm)
+    const float* t;     // [n] targets
+    float* acts;        // [6][64][n] input features and hidden activations (feature-major)
+    float* dz;          // [5][64][n] pre-activation gradients (feature-major)
+    float* y;           // [n] outputs
+    float* dy;          // [n] dloss / dy
+    float* loss;        // [1] accumulated loss (mean over the rows)
+};
+
+// FP32 forward of n rows (device arrays)
+hipError_t nrc_launch_infer(const NrcNet& net, int n, const float* x, const float* w, const float* lam, float* y,
+                            hipStream_t st);
+// BF16 matrix-core forward (FP32 accumulation); needs net.wq packed from the current weights
+hipError_t nrc_launch_infer_mfma(const NrcNet& net, int n, const float* x, const float* w, const float* lam,
+                                 float* y, hipStream_t st);
+// BF16 operand-order copy of the hidden weights into net.wq
+hipError_t nrc_launch_pack(const NrcNet& net, hipStream_t st);
+// forward, loss, backward, gradient reduction (gradients are accumulated in net.g)
+hipError_t nrc_launch_grad(const NrcNet& net, const NrcBatch& b, hipStream_t st);
+// Adam step t (>= 1) over all parameters
+hipError_t nrc_launch_adam(const NrcNet& net, int t, float lr, float b1, float b2, float eps, hipStream_t st);
+hipError_t nrc_launch_zero(float* p, long long n, hipStream_t st);
+
+}  // namespace sdd

@@ -1,0 +1,525 @@
+// Learned radiance cache on the device: FP32 training and inference, and a
+// BF16 matrix-core (MFMA) inference path with FP32 accumulation.
+//
+// Encodings, each from its definition:
+//  - multiresolution hash encoding (Mueller et al. 2022): level l has
+//    resolution N_l; the 8 lattice corners around the position are looked
+//    up, directly (c.x + c.y (N+1) + c.z (N+1)^2) when the level's lattice
+//    fits the table, else by the spatial hash (c.x * 1) ^ (c.y * 2654435761)
+//    ^ (c.z * 805459861) mod T, and blended trilinearly;
+//  - real spherical harmonics, bands 0..3: K_l^m P_l^|m|(cos theta) times
+//    sqrt2 cos(m phi) (m > 0), 1 (m = 0) or sqrt2 sin(|m| phi) (m < 0); the
+//    associated Legendre functions come from their recurrences (no
+//    Condon-Shortley phase), K_l^m from the host in double;
+//  - one-blob wavelength encoding: 16 Gaussian bins exp(-(16 u - (i + 1/2))^2 / 2).
+// Loss: relative L2, (y - t)^2 / (y^2 + 0.01) with y^2 held constant
+// (Mueller et al. 2021).  Optimiser: Adam (Kingma and Ba 2015).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "nrc.h"
+
+namespace sdd {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// encodings
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void sh_features(const float* K, float x, float y, float z, float* out) {
+    const float ct = z, st = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+    // cos(m phi), sin(m phi) of the azimuth phi = atan2(y, x) by the angle-sum
+    // recurrence from cos phi = x / rho, sin phi = y / rho (phi = 0 on the pole)
+    const float rho = sqrtf(x * x + y * y);
+    const float c1 = rho > 0.0f ? x / rho : 1.0f, s1 = rho > 0.0f ? y / rho : 0.0f;
+    float cm[4], sm[4];
+    cm[0] = 1.0f;
+    sm[0] = 0.0f;
+#pragma unroll
+    for (int m = 1; m < 4; ++m) {
+        cm[m] = cm[m - 1] * c1 - sm[m - 1] * s1;
+        sm[m] = sm[m - 1] * c1 + cm[m - 1] * s1;
+    }
+    float P[4][4];  // P[l][m], m <= l
+    float pmm = 1.0f;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (m > 0) pmm *= (float)(2 * m - 1) * st;
+        P[m][m] = pmm;
+        if (m + 1 < 4) P[m + 1][m] = ct * (float)(2 * m + 1) * pmm;
+#pragma unroll
+        for (int l = m + 2; l < 4; ++l)
+            P[l][m] = ((float)(2 * l - 1) * ct * P[l - 1][m] - (float)(l + m - 1) * P[l - 2][m]) / (float)(l - m);
+    }
+    int k = 0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int m = -l; m <= l; ++m, ++k) {
+            const int am = m < 0 ? -m : m;
+            const float base = K[k] * P[l][am];
+            out[k] = m > 0 ? 1.41421356237309515f * base * cm[am]
+                           : (m < 0 ? 1.41421356237309515f * base * sm[am] : base);
+        }
+}
+
+__device__ __forceinline__ float blob_bin(const NrcNet& net, float lam, int i) {
+    const float u = (lam - net.lam_lo) * net.lam_inv * (float)kNrcBlob;
+    const float d = u - ((float)i + 0.5f);
+    return expf(-0.5f * d * d);
+}
+
+__device__ __forceinline__ uint32_t corner_slot(int N, int dense, int T, int cx, int cy, int cz) {
+    if (dense) return (uint32_t)(cx + (N + 1) * (cy + (N + 1) * cz));
+    const uint32_t h = (uint32_t)cx ^ ((uint32_t)cy * 2654435761u) ^ ((uint32_t)cz * 805459861u);
+    return h & (uint32_t)(T - 1);
+}
+
+__device__ __forceinline__ void level_setup(int N, const float xn[3], int i0[3], float f[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float p = xn[a] * (float)N;
+        int i = (int)floorf(p);
+        i = i < 0 ? 0 : (i > N - 1 ? N - 1 : i);
+        i0[a] = i;
+        f[a] = p - (float)i;
+    }
+}
+
+__device__ __forceinline__ float corner_weight(const float f[3], int c) {
+    return ((c & 1) ? f[0] : 1.0f - f[0]) * ((c & 2) ? f[1] : 1.0f - f[1]) * ((c & 4) ? f[2] : 1.0f - f[2]);
+}
+
+__device__ __forceinline__ void normalise(const NrcNet& net, const float* x, float xn[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xn[a] = fminf(1.0f, fmaxf(0.0f, (x[a] - net.lo[a]) * net.inv_ext[a]));
+}
+
+// both features of level l (resolution N) at the normalised position xn
+__device__ __forceinline__ float2 hash_level(const NrcNet& net, int l, int N, int dense, const float xn[3]) {
+    int i0[3];
+    float f[3];
+    level_setup(N, xn, i0, f);
+    const float2* tab = reinterpret_cast<const float2*>(net.p) + (size_t)l * net.T;
+    float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float w = corner_weight(f, c);
+        const uint32_t s = corner_slot(N, dense, net.T, i0[0] + (c & 1), i0[1] + ((c >> 1) & 1), i0[2] + (c >> 2));
+        const float2 e = tab[s];
+        a0 += w * e.x;
+        a1 += w * e.y;
+    }
+    return make_float2(a0, a1);
+}
+
+__device__ __forceinline__ void features(const NrcNet& net, const float* x, const float* w, float lam, float* f) {
+    float xn[3];
+    normalise(net, x, xn);
+#pragma unroll
+    for (int l = 0; l < kNrcLevels; ++l) {
+        const float2 e = hash_level(net, l, net.res[l], net.dense[l], xn);
+        f[2 * l] = e.x;
+        f[2 * l + 1] = e.y;
+    }
+    sh_features(net.shK, w[0], w[1], w[2], f + kNrcHash);
+#pragma unroll
+    for (int i = 0; i < kNrcBlob; ++i) f[kNrcHash + kNrcSh + i] = blob_bin(net, lam, i);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 network, one row per thread; weights are read at wave-uniform
+// addresses (scalar loads shared by the wave)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void layer(const float* __restrict__ W, const float* __restrict__ b, const float* in,
+                                      float* out) {
+#pragma unroll
+    for (int i = 0; i < kNrcHid; ++i) {
+        float s = b[i];
+#pragma unroll
+        for (int j = 0; j < kNrcHid; ++j) s = fmaf(W[i * kNrcHid + j], in[j], s);
+        out[i] = fmaxf(s, 0.0f);
+    }
+}
+
+__device__ __forceinline__ float output(const NrcNet& net, const float* h) {
+    const float* wo = net.p + net.off_wo();
+    float s = net.p[net.off_bo()];
+#pragma unroll
+    for (int j = 0; j < kNrcHid; ++j) s = fmaf(wo[j], h[j], s);
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_infer(NrcNet net, int n, const float* x, const float* w, const float* lam,
+                                               float* y) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    float h[kNrcHid], g[kNrcHid];
+    features(net, x + 3 * (size_t)r, w + 3 * (size_t)r, lam[r], h);
+    const float* W = net.p + net.off_W();
+    const float* b = net.p + net.off_b();
+    for (int k = 0; k < kNrcLayers; ++k) {
+        layer(W + k * kNrcHid * kNrcHid, b + k * kNrcHid, h, g);
+#pragma unroll
+        for (int j = 0; j < kNrcHid; ++j) h[j] = g[j];
+    }
+    y[r] = output(net, h);
+}
+
+// training forward: activations stored feature-major acts[k][j][r]; loss and dy
+__global__ __launch_bounds__(256) void k_train_fwd(NrcNet net, NrcBatch b) {
+    __shared__ float s_loss[256];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    float contrib = 0.0f;
+    if (r < b.n) {
+        float h[kNrcHid], g[kNrcHid];
+        features(net, b.x + 3 * (size_t)r, b.w + 3 * (size_t)r, b.lam[r], h);
+        const size_t n = (size_t)b.n;
+#pragma unroll
+        for (int j = 0; j < kNrcIn; ++j) b.acts[(size_t)j * n + r] = h[j];
+        const float* W = net.p + net.off_W();
+        const float* bb = net.p + net.off_b();
+        for (int k = 0; k < kNrcLayers; ++k) {
+            layer(W + k * kNrcHid * kNrcHid, bb + k * kNrcHid, h, g);
+            float* a = b.acts + (size_t)(k + 1) * kNrcHid * n;
+#pragma unroll
+            for (int j = 0; j < kNrcHid; ++j) {
+                a[(size_t)j * n + r] = g[j];
+                h[j] = g[j];
+            }
+        }
+        const float s = output(net, h);
+        const float t = b.t[r];
+        const float den = s * s + 0.01f;
+        b.y[r] = s;
+        b.dy[r] = 2.0f * (s - t) / den / (float)b.n;
+        contrib = (s - t) * (s - t) / den / (float)b.n;
+    }
+    s_loss[threadIdx.x] = contrib;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s_loss[threadIdx.x] += s_loss[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(b.loss, s_loss[0]);
+}
+
+// training backward per row: dz of every layer, then the hash-table gradient
+__global__ __launch_bounds__(256) void k_train_bwd(NrcNet net, NrcBatch b) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= b.n) return;
+    const size_t n = (size_t)b.n;
+    const float* wo = net.p + net.off_wo();
+    const float* W = net.p + net.off_W();
+    float dh[kNrcHid], dz[kNrcHid];
+    const float dy = b.dy[r];
+#pragma unroll
+    for (int j = 0; j < kNrcHid; ++j) dh[j] = dy * wo[j];
+    for (int k = kNrcLayers - 1; k >= 0; --k) {
+        const float* a = b.acts + (size_t)(k + 1) * kNrcHid * n;
+        float* z = b.dz + (size_t)k * kNrcHid * n;
+#pragma unroll
+        for (int i = 0; i < kNrcHid; ++i) {
+            dz[i] = a[(size_t)i * n + r] > 0.0f ? dh[i] : 0.0f;
+            z[(size_t)i * n + r] = dz[i];
+        }
+        const float* Wk = W + k * kNrcHid * kNrcHid;
+#pragma unroll
+        for (int j = 0; j < kNrcHid; ++j) {
+            float s = 0.0f;
+#pragma unroll
+            for (int i = 0; i < kNrcHid; ++i) s = fmaf(Wk[i * kNrcHid + j], dz[i], s);
+            dh[j] = s;
+        }
+    }
+    // dh is now dloss / d(input features); scatter its hash part
+    float xn[3];
+    normalise(net, b.x + 3 * (size_t)r, xn);
+#pragma unroll
+    for (int l = 0; l < kNrcLevels; ++l) {
+        const int N = net.res[l];
+        int i0[3];
+        float f[3];
+        level_setup(N, xn, i0, f);
+        float2* gt = reinterpret_cast<float2*>(net.g) + (size_t)l * net.T;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float wc = corner_weight(f, c);
+            const uint32_t s =
+                corner_slot(N, net.dense[l], net.T, i0[0] + (c & 1), i0[1] + ((c >> 1) & 1), i0[2] + (c >> 2));
+            float* gp = reinterpret_cast<float*>(gt + s);
+            atomicAdd(gp, wc * dh[2 * l]);
+            atomicAdd(gp + 1, wc * dh[2 * l + 1]);
+        }
+    }
+}
+
+// weight gradients of layer k (k < 5: hidden layer, k == 5: output layer):
+// sums over a chunk of rows of dz_k[i][r] acts_k[j][r], accumulated in net.g
+constexpr int kRowTile = 64;
+__global__ __launch_bounds__(256) void k_train_wgrad(NrcNet net, NrcBatch b, int rows_per_block) {
+    __shared__ float s_dz[kNrcHid][kRowTile + 1];
+    __shared__ float s_a[kNrcHid][kRowTile + 1];
+    const int k = blockIdx.y;
+    const int r0 = blockIdx.x * rows_per_block, r1 = min(b.n, r0 + rows_per_block);
+    const size_t n = (size_t)b.n;
+    const int i = threadIdx.x >> 2, j0 = (threadIdx.x & 3) * 16;
+    const bool out_layer = k == kNrcLayers;
+    const int n_i = out_layer ? 1 : kNrcHid;
+    float acc[16];
+    float accb = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+    const float* A = b.acts + (size_t)k * kNrcHid * n;  // inputs of layer k (acts[5] for the output layer)
+    const float* Z = out_layer ? b.dy : b.dz + (size_t)k * kNrcHid * n;
+    for (int rt = r0; rt < r1; rt += kRowTile) {
+        const int nr = min(kRowTile, r1 - rt);
+        for (int e = threadIdx.x; e < kNrcHid * kRowTile; e += blockDim.x) {
+            const int f = e / kRowTile, rr = e % kRowTile;
+            const bool in = rr < nr;
+            s_a[f][rr] = in ? A[(size_t)f * n + rt + rr] : 0.0f;
+            s_dz[f][rr] = (in && f < n_i) ? Z[(size_t)f * n + rt + rr] : 0.0f;
+        }
+        __syncthreads();
+        if (i < n_i) {
+            for (int rr = 0; rr < nr; ++rr) {
+                const float zz = s_dz[i][rr];
+                accb += zz;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[q] = fmaf(zz, s_a[j0 + q][rr], acc[q]);
+            }
+        }
+        __syncthreads();
+    }
+    if (i < n_i) {
+        float* gW = out_layer ? net.g + net.off_wo()
+                              : net.g + net.off_W() + (size_t)k * kNrcHid * kNrcHid + (size_t)i * kNrcHid;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) atomicAdd(gW + j0 + q, acc[q]);
+        if (j0 == 0) atomicAdd(out_layer ? net.g + net.off_bo() : net.g + net.off_b() + k * kNrcHid + i, accb);
+    }
+}
+
+__global__ void k_adam(NrcNet net, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= net.n_all) return;
+    const float g = net.g[i];
+    const float m = b1 * net.m[i] + (1.0f - b1) * g;
+    const float v = b2 * net.v[i] + (1.0f - b2) * g * g;
+    net.m[i] = m;
+    net.v[i] = v;
+    net.p[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+__global__ void k_zero(float* p, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// BF16 matrix-core forward.
+//
+// Each layer is computed transposed, Z^T = W H^T, with v_mfma_f32_16x16x32_bf16:
+// A = a 16 x 32 tile of W (16 output features x 32 inputs), B = a 32 x 16
+// tile of H^T (32 inputs x 16 rows), D = 16 output features x 16 rows.  Lane
+// l of a wave holds operand rows / columns l % 16 and 8 k slots of group
+// g = l / 16, and D values (rows 4 g + i, column l % 16).  A layer's D tiles
+// therefore already hold, per lane, the 16 features {16 mt + 4 g + i} of one
+// data row; they become the next layer's B operand without leaving
+// registers if the contraction index is permuted: k step s, slot j of group
+// g stands for input feature 16 (2 s + j / 4) + 4 g + j % 4 (A and B use the
+// same slot-to-k map, so the product is the plain one).  The weights are
+// stored in that order (k_pack) and staged in LDS.  A wave evaluates 64 rows
+// (4 column tiles), so each weight fragment read from LDS feeds 4 MFMAs.
+// Input features follow the same permutation: in step 0 group g holds hash
+// levels 2g, 2g+1, 8+2g, 9+2g; in step 1 the harmonics 4g..4g+3 and the
+// wavelength bins 4g..4g+3.
+// ---------------------------------------------------------------------------
+
+// a[4 g + j] by selects on register values (an indexed read would place a in scratch)
+__device__ __forceinline__ float pick4(const float* a, int g, int j) {
+    float v0 = a[j], v1 = a[4 + j], v2 = a[8 + j], v3 = a[12 + j];
+    asm volatile("" : "+v"(v0), "+v"(v1), "+v"(v2), "+v"(v3));
+    const float lo = (g & 1) ? v1 : v0, hi = (g & 1) ? v3 : v2;
+    return (g & 2) ? hi : lo;
+}
+
+__device__ __forceinline__ bf16x8 relu_pack8(f32x4 a, f32x4 b) {
+    bf16x8 r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        r[i] = (__bf16)fmaxf(a[i], 0.0f);
+        r[4 + i] = (__bf16)fmaxf(b[i], 0.0f);
+    }
+    return r;
+}
+
+constexpr int kMfmaBlock = 256;
+constexpr int kMfmaRowsPerWave = 64;
+
+__global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, const float* x, const float* w,
+                                                          const float* lam, float* y) {
+    __shared__ bf16x8 s_w[kNrcFrags];
+    __shared__ __align__(16) float s_b[kNrcLayers * kNrcHid];
+    __shared__ float s_wo[kNrcHid];
+    __shared__ int s_res[kNrcLevels], s_dense[kNrcLevels];
+    __shared__ bf16x8 s_in[kMfmaBlock / 64][4][2][64];
+    const bf16x8* wq = reinterpret_cast<const bf16x8*>(net.wq);
+    for (int e = threadIdx.x; e < kNrcFrags; e += kMfmaBlock) s_w[e] = wq[e];
+    for (int e = threadIdx.x; e < kNrcLayers * kNrcHid; e += kMfmaBlock) s_b[e] = net.p[net.off_b() + e];
+    if (threadIdx.x < kNrcHid) s_wo[threadIdx.x] = net.p[net.off_wo() + threadIdx.x];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int l = 0; l < kNrcLevels; ++l) {  // static indexes: kernel arguments stay out of scratch
+            s_res[l] = net.res[l];
+            s_dense[l] = net.dense[l];
+        }
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
+    const long long base = ((long long)blockIdx.x * (kMfmaBlock / 64) + (threadIdx.x >> 6)) * kMfmaRowsPerWave;
+    if (base >= n) return;  // whole wave idle (no barrier follows)
+
+    // features, one column tile at a time (a rolled loop bounds the live
+    // gathers); each lane parks its operands in its own LDS slots
+#pragma unroll 1
+    for (int nt = 0; nt < 4; ++nt) {
+        const long long row = min(base + nt * 16 + c, (long long)n - 1);
+        float xn[3];
+        normalise(net, x + 3 * row, xn);
+        bf16x8 v0, v1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int l = (q < 2 ? 0 : 8) + 2 * g + (q & 1);
+            const float2 e = hash_level(net, l, s_res[l], s_dense[l], xn);
+            v0[2 * q] = (__bf16)e.x;
+            v0[2 * q + 1] = (__bf16)e.y;
+        }
+        float sh[kNrcSh];
+        sh_features(net.shK, w[3 * row], w[3 * row + 1], w[3 * row + 2], sh);
+        const float lm = lam[row];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v1[j] = (__bf16)pick4(sh, g, j);
+            v1[4 + j] = (__bf16)blob_bin(net, lm, 4 * g + j);
+        }
+        s_in[wv][nt][0][lane] = v0;
+        s_in[wv][nt][1][lane] = v1;
+    }
+    bf16x8 b0[4], b1[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        b0[nt] = s_in[wv][nt][0][lane];
+        b1[nt] = s_in[wv][nt][1][lane];
+    }
+
+    f32x4 acc[4][4];
+    for (int k = 0; k < kNrcLayers; ++k) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const f32x4 bias = *reinterpret_cast<const f32x4*>(&s_b[k * kNrcHid + 16 * mt + 4 * g]);
+            const bf16x8 a0 = s_w[((k * 4 + mt) * 2 + 0) * 64 + lane];
+            const bf16x8 a1 = s_w[((k * 4 + mt) * 2 + 1) * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0[nt], bias, 0, 0, 0);
+                acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1[nt], acc[nt][mt], 0, 0, 0);
+            }
+        }
+        if (k + 1 < kNrcLayers) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                b0[nt] = relu_pack8(acc[nt][0], acc[nt][1]);
+                b1[nt] = relu_pack8(acc[nt][2], acc[nt][3]);
+            }
+        }
+    }
+    const float bo = net.p[net.off_bo()];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        float s = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s = fmaf(s_wo[16 * mt + 4 * g + i], fmaxf(acc[nt][mt][i], 0.0f), s);
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        const long long row = base + nt * 16 + c;
+        if (g == 0 && row < n) y[row] = s + bo;
+    }
+}
+
+// hidden weights -> BF16 operand order: fragment e = ((k * 4 + mt) * 2 + s) * 64 + lane
+__global__ void k_pack(NrcNet net) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kNrcFrags) return;
+    const int lane = e & 63, s = (e >> 6) & 1, mt = (e >> 7) & 3, k = e >> 9;
+    const int m = 16 * mt + (lane & 15), g = lane >> 4;
+    const float* W = net.p + net.off_W() + (size_t)k * kNrcHid * kNrcHid + (size_t)m * kNrcHid;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int in = 16 * (2 * s + j / 4) + 4 * g + (j & 3);
+        net.wq[(size_t)e * 8 + j] = __builtin_bit_cast(uint16_t, (__bf16)W[in]);
+    }
+}
+
+inline unsigned nblocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t nrc_launch_infer(const NrcNet& net, int n, const float* x, const float* w, const float* lam, float* y,
+                            hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_infer, dim3(nblocks(n, 256)), dim3(256), 0, st, net, n, x, w, lam, y);
+    return hipGetLastError();
+}
+
+hipError_t nrc_launch_infer_mfma(const NrcNet& net, int n, const float* x, const float* w, const float* lam,
+                                 float* y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int rows_per_block = (kMfmaBlock / 64) * kMfmaRowsPerWave;
+    hipLaunchKernelGGL(k_infer_mfma, dim3(nblocks(n, rows_per_block)), dim3(kMfmaBlock), 0, st, net, n, x, w, lam,
+                       y);
+    return hipGetLastError();
+}
+
+hipError_t nrc_launch_pack(const NrcNet& net, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(kNrcFrags, 256)), dim3(256), 0, st, net);
+    return hipGetLastError();
+}
+
+hipError_t nrc_launch_grad(const NrcNet& net, const NrcBatch& b, hipStream_t st) {
+    if (b.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_train_fwd, dim3(nblocks(b.n, 256)), dim3(256), 0, st, net, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_train_bwd, dim3(nblocks(b.n, 256)), dim3(256), 0, st, net, b);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int rows_per_block = 1024;
+    hipLaunchKernelGGL(k_train_wgrad, dim3(nblocks(b.n, rows_per_block), kNrcLayers + 1), dim3(256), 0, st, net, b,
+                       rows_per_block);
+    return hipGetLastError();
+}
+
+hipError_t nrc_launch_adam(const NrcNet& net, int t, float lr, float b1, float b2, float eps, hipStream_t st) {
+    const float c1 = (float)(1.0 - std::pow((double)b1, (double)t));
+    const float c2 = (float)(1.0 - std::pow((double)b2, (double)t));
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(net.n_all, 256)), dim3(256), 0, st, net, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t nrc_launch_zero(float* p, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(nblocks(n, 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace sdd

@@ -1,0 +1,316 @@
+"""Radiance-cache kernels against the FP64 reference (oracle/nrc.py), through
+the C ABI (sdd_nrc_*): encodings + forward (FP32 and BF16 matrix cores),
+gradients of the relative L2 loss (network and hash tables), the Adam step,
+and a short training run.
+
+Tolerances: the FP32 path within 3e-4 of |y| + rms y.  Its largest error is
+the lattice coordinate x N of the finest levels (N up to 2048): the FP32
+normalised position carries a relative error up to 2^-23, so the trilinear
+weights move by up to 2048 * 2^-23 = 2.4e-4 of a cell, times the table's
+slope (O(1) per cell for the U(-0.5, 0.5) test tables); the ~10^3 accumulated
+products add ~1e-6.  On dyadic positions in a power-of-two box (lattice
+coordinates exact in FP32) the FP32 path must agree within 1e-5.  Gradients
+(dyadic positions) within 1e-4 of each block's largest entry, over the rows
+whose ReLU decisions are clear: a row with a hidden pre-activation within
+1e-5 of the magnitude of its summed terms could take the other branch in FP32
+(a different but equally valid derivative), so such rows (a few per mille)
+are left out of the batch on both sides.  The BF16 path is compared with the reference that rounds the same
+operands to BF16: a row agrees to FP32 accumulation error unless one of its
+~400 rounding decisions falls the other way because the kernel's operand is
+an FP32 value and the reference's an FP64 one (odds ~1e-7 / 2^-8 per
+decision); such a row moves by about one BF16 ulp (2^-8) of one operand's
+contribution.  The odds are largest for the fine hash levels: the lattice
+coordinate x N (N up to 2048) carries the FP32 rounding of the normalised
+position amplified N times (~1e-4), so on general positions a good fraction
+of rows carries a flip: half the rows agree within 1e-4 and every row within
+2e-2.  On a power-of-two box with dyadic positions the lattice coordinates are
+exact in FP32 and flips become rare: on a network whose hidden layers are
+permutations (their sums are exact, so only the 64 input features are
+decisions in doubt) at least 98% of rows agree within 1e-5, which pins the
+operand layout exactly."""
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import nrc as ora
+
+pytestmark = pytest.mark.gpu
+
+LO, HI = (0.0, 0.0, 0.0), (4.0, 3.0, 2.5)
+
+
+@pytest.fixture(scope="module")
+def tracer():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1912_06474_amd as m
+    return m.Tracer()
+
+
+def _net(seed, log2, table_scale=0.5):
+    """Initial network of the cache recipe with O(1) table entries and non-zero
+    biases, so every input and parameter block influences the output."""
+    params, tables = sg.nrc_params(seed, table_size=1 << log2)
+    rng = np.random.default_rng(seed + 1000)
+    tables = rng.uniform(-table_scale, table_scale, tables.shape).astype(np.float32)
+    params["b"] = [rng.uniform(-0.1, 0.1, 64).astype(np.float32) for _ in range(5)]
+    params["bo"] = np.float32(0.05)
+    return params, tables
+
+
+def _f64(params, tables):
+    return ({"W": [np.asarray(w, np.float64) for w in params["W"]],
+             "b": [np.asarray(b, np.float64) for b in params["b"]],
+             "wo": np.asarray(params["wo"], np.float64), "bo": float(params["bo"])},
+            np.asarray(tables, np.float64))
+
+
+def _edge_rows():
+    """Box corners and faces, positions outside the box (clamped), the poles of
+    the direction sphere, and the ends of the wavelength range."""
+    x = np.array([LO, HI, (4.0, 0.0, 2.5), (-1.0, 1.5, 1.0), (2.0, 5.0, 3.0), (2.0, 1.5, 1.25),
+                  (1.0, 1.0, 1.0), (3.999, 2.999, 2.499)], np.float32)
+    w = np.array([(0, 0, 1), (0, 0, -1), (1, 0, 0), (0, -1, 0), (-1, 0, 0), (0.6, 0.8, 0.0),
+                  (0.0, 0.6, -0.8), (-0.48, -0.6, 0.64)], np.float32)
+    lam = np.array([380.0, 780.0, 380.0, 779.9, 500.0, 555.5, 700.0, 400.0], np.float32)
+    return x, w, lam
+
+
+def _rows(n, seed):
+    x, w, lam, _ = sg.nrc_rows(n, seed, LO, HI)
+    ex, ew, el = _edge_rows()
+    k = min(n, len(el))
+    x[:k], w[:k], lam[:k] = ex[:k], ew[:k], el[:k]
+    return x, w, lam
+
+
+BOX2 = ((0.0, 0.0, 0.0), (4.0, 4.0, 4.0))
+
+
+def _dyadic_rows(n, seed):
+    """Positions on a 2^-10 m grid in a 4 m cube and wavelengths on a 1/8 nm
+    grid: every lattice coordinate x N is exact in FP32."""
+    rng = np.random.default_rng(seed)
+    x = (rng.integers(0, 4096, (n, 3)) / 1024.0).astype(np.float32)
+    w = rng.normal(size=(n, 3))
+    w = (w / np.linalg.norm(w, axis=1, keepdims=True)).astype(np.float32)
+    lam = (380.0 + rng.integers(0, 3200, n) / 8.0).astype(np.float32)
+    return x, w, lam
+
+
+def _oracle_y(params, tables, x, w, lam, bf16=False):
+    p, t = _f64(params, tables)
+    X = ora.encode(x, w, lam, LO, HI, t)
+    if bf16:
+        return ora.mlp_forward_bf16(p, X)
+    return ora.mlp_forward(p, X)[0]
+
+
+def _rel(y, yo):
+    scale = max(float(np.sqrt(np.mean(yo ** 2))), 1e-30)
+    return np.abs(y - yo) / (np.abs(yo) + scale)
+
+
+def _close(y, yo, tol=None):
+    return float(_rel(y, yo).max())
+
+
+def _bf16_ok(y, yb):
+    e = _rel(y, yb)
+    return float(np.mean(e <= 1e-4)), float(e.max())
+
+
+@pytest.mark.parametrize("n", [1, 8, 257, 3001])
+def test_fp32_forward_matches_oracle(tracer, n):
+    params, tables = _net(1, 14)  # levels 0-1 indexed directly, 2-15 hashed
+    tracer.nrc_init(params, tables, LO, HI)
+    x, w, lam = _rows(n, 11)
+    y = tracer.nrc_infer(x, w, lam, "fp32").cpu().numpy()
+    yo = _oracle_y(params, tables, x, w, lam)
+    err = _close(y, yo)
+    print(f"[nrc] fp32 forward n={n}: max rel err {err:.3e}", flush=True)
+    assert err <= 3e-4
+
+
+@pytest.mark.parametrize("n", [7, 3001])
+def test_fp32_forward_exact_lattice(tracer, n):
+    params, tables = _net(9, 14)
+    tracer.nrc_init(params, tables, *BOX2)
+    x, w, lam = _dyadic_rows(n, 23)
+    y = tracer.nrc_infer(x, w, lam, "fp32").cpu().numpy()
+    p, tb = _f64(params, tables)
+    yo = ora.mlp_forward(p, ora.encode(x, w, lam, BOX2[0], BOX2[1], tb))[0]
+    err = _close(y, yo)
+    print(f"[nrc] fp32 forward, dyadic positions n={n}: max rel err {err:.3e}", flush=True)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("n", [5, 64, 1000, 4097])
+def test_bf16_forward_matches_bf16_oracle(tracer, n):
+    params, tables = _net(2, 14)
+    tracer.nrc_init(params, tables, LO, HI)
+    x, w, lam = _rows(n, 12)
+    y = tracer.nrc_infer(x, w, lam, "bf16").cpu().numpy()
+    frac, err_b = _bf16_ok(y, _oracle_y(params, tables, x, w, lam, bf16=True))
+    err_f = _close(y, _oracle_y(params, tables, x, w, lam))
+    print(f"[nrc] bf16 forward n={n}: vs BF16-operand reference: {frac:.4f} of rows within 1e-4, max {err_b:.3e}; "
+          f"vs FP64 max {err_f:.3e}", flush=True)
+    assert frac >= 0.5 and err_b <= 2e-2
+    assert err_f <= 5e-2
+
+
+@pytest.mark.parametrize("n", [64, 3001])
+def test_bf16_layout_exact_on_permutation_layers(tracer, n):
+    rng = np.random.default_rng(21)
+    params, tables = _net(8, 14)
+    params["W"] = [(rng.integers(-8, 9, (64, 64)) / 16.0).astype(np.float32)] + \
+        [np.eye(64, dtype=np.float32)[rng.permutation(64)] for _ in range(4)]
+    params["b"] = [(rng.integers(-4, 5, 64) / 8.0).astype(np.float32)] + [np.zeros(64, np.float32)] * 4
+    tracer.nrc_init(params, tables, *BOX2)
+    x, w, lam = _dyadic_rows(n, 22)
+    y = tracer.nrc_infer(x, w, lam, "bf16").cpu().numpy()
+    p, tb = _f64(params, tables)
+    yb = ora.mlp_forward_bf16(p, ora.encode(x, w, lam, BOX2[0], BOX2[1], tb))
+    e = _rel(y, yb)
+    frac = float(np.mean(e <= 1e-5))
+    print(f"[nrc] bf16 permutation layers n={n}: {frac:.4f} of rows within 1e-5, max {e.max():.3e}", flush=True)
+    assert frac >= 0.98 and e.max() <= 2e-2
+
+
+def test_forward_full_table_sampled(tracer):
+    """Full-size cache (2^19 entries per level, levels 0-4 direct), 2^20 rows in
+    one launch of each path; 2000 sampled rows against the reference."""
+    params, tables = _net(3, 19)
+    tracer.nrc_init(params, tables, LO, HI)
+    x, w, lam = _rows(1 << 20, 13)
+    y32 = tracer.nrc_infer(x, w, lam, "fp32").cpu().numpy()
+    y16 = tracer.nrc_infer(x, w, lam, "bf16").cpu().numpy()
+    idx = np.random.default_rng(14).choice(len(lam), 2000, replace=False)
+    idx[:8] = np.arange(8)
+    yo = _oracle_y(params, tables, x[idx], w[idx], lam[idx])
+    yb = _oracle_y(params, tables, x[idx], w[idx], lam[idx], bf16=True)
+    e32 = _close(y32[idx], yo)
+    frac, e16 = _bf16_ok(y16[idx], yb)
+    print(f"[nrc] 2^20 rows, T=2^19: fp32 max {e32:.3e}; bf16 {frac:.4f} within 1e-4, max {e16:.3e}", flush=True)
+    assert e32 <= 3e-4
+    assert frac >= 0.5 and e16 <= 2e-2
+    assert np.all(np.isfinite(y32)) and np.all(np.isfinite(y16))
+
+
+def _oracle_grads(params, tables, x, w, lam, t, lo=LO, hi=HI):
+    p, tb = _f64(params, tables)
+    X = ora.encode(x, w, lam, lo, hi, tb)
+    y, acts = ora.mlp_forward(p, X)
+    loss, dy = ora.rel_l2_loss(y, np.asarray(t, np.float64))
+    g, dX = ora.mlp_backward(p, acts, dy)
+    xn = np.clip((np.asarray(x, np.float64) - lo) / (np.asarray(hi) - np.asarray(lo)), 0.0, 1.0)
+    gt = ora.hash_backward(xn, dX[:, :32], tb.shape)
+    return loss, g, gt
+
+
+def _block_err(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30))
+
+
+def _clear_relu_rows(params, tables, x, w, lam, lo, hi, margin=1e-5):
+    p, tb = _f64(params, tables)
+    h = ora.encode(x, w, lam, lo, hi, tb)
+    ok = np.ones(len(h), bool)
+    for k in range(5):
+        z = h @ p["W"][k].T + p["b"][k]
+        S = np.abs(h) @ np.abs(p["W"][k]).T + np.abs(p["b"][k])
+        ok &= np.all(np.abs(z) > margin * S, axis=1)
+        h = np.maximum(z, 0.0)
+    return ok
+
+
+@pytest.mark.parametrize("n", [1, 300, 2000])
+def test_gradients_match_oracle(tracer, n):
+    params, tables = _net(4, 12)
+    tracer.nrc_init(params, tables, *BOX2)
+    x, w, lam = _dyadic_rows(n + 64, 15)
+    keep = _clear_relu_rows(params, tables, x, w, lam, *BOX2)
+    x, w, lam = x[keep][:n], w[keep][:n], lam[keep][:n]
+    t = sg.nrc_rows(n, 16)[3]
+    loss = tracer.nrc_train_step(x, w, lam, t, apply=False)
+    g, gt = tracer.nrc_get("grad")
+    lo, go, gto = _oracle_grads(params, tables, x, w, lam, t, *BOX2)
+    errs = {"loss": abs(loss - lo) / lo, "tables": _block_err(gt, gto), "wo": _block_err(g["wo"], go["wo"]),
+            "bo": abs(g["bo"] - go["bo"]) / max(abs(go["bo"]), 1e-30)}
+    for k in range(5):
+        errs[f"W{k}"] = _block_err(g["W"][k], go["W"][k])
+        errs[f"b{k}"] = _block_err(g["b"][k], go["b"][k])
+    print(f"[nrc] gradients n={n}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    assert max(errs.values()) <= 1e-4, errs
+    # parameters untouched without apply
+    p_after, t_after = tracer.nrc_get("params")
+    assert np.array_equal(t_after, tables)
+    assert np.array_equal(p_after["W"][0], params["W"][0])
+
+
+def test_adam_step_matches_oracle(tracer):
+    params, tables = _net(5, 12)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.99, 1e-8
+    tracer.nrc_init(params, tables, LO, HI, lr=lr, betas=(b1, b2), eps=eps)
+    x, w, lam = _rows(1500, 17)
+    t = sg.nrc_rows(1500, 18)[3]
+    for step in range(2):
+        p0, t0 = tracer.nrc_get("params")
+        m0, mt0 = tracer.nrc_get("m")
+        v0, vt0 = tracer.nrc_get("v")
+        tracer.nrc_train_step(x, w, lam, t, apply=True)
+        g, gt = tracer.nrc_get("grad")  # the gradient this step applied
+        p1, t1 = tracer.nrc_get("params")
+        opt = ora.Adam(lr, b1, b2, eps)
+        opt.t = step + 1
+        opt.m = {"tables": mt0.astype(np.float64)}
+        opt.v = {"tables": vt0.astype(np.float64)}
+        t1o = opt.step("tables", t0.astype(np.float64), gt.astype(np.float64))
+        opt.m["W0"], opt.v["W0"] = m0["W"][0].astype(np.float64), v0["W"][0].astype(np.float64)
+        w1o = opt.step("W0", p0["W"][0].astype(np.float64), g["W"][0].astype(np.float64))
+        e_t = float(np.max(np.abs(t1 - t1o) / (np.abs(t1o) + lr)))
+        e_w = float(np.max(np.abs(p1["W"][0] - w1o) / (np.abs(w1o) + lr)))
+        print(f"[nrc] Adam step {step + 1}: tables {e_t:.2e}, W0 {e_w:.2e}", flush=True)
+        assert e_t <= 1e-5 and e_w <= 1e-5
+
+
+def test_training_tracks_the_oracle(tracer):
+    """The cache recipe (tables U(+-1e-4), lr 1e-2) on the same batches: the
+    GPU's loss curve follows the FP64 one and the loss falls."""
+    params, tables = sg.nrc_params(6, table_size=1 << 12)
+    tracer.nrc_init(params, tables, LO, HI)
+    p, tb = _f64(params, tables)
+    opt = ora.Adam()
+    gl, ol = [], []
+    for step in range(20):
+        x, w, lam, t = sg.nrc_rows(512, 200 + step, LO, HI)
+        gl.append(tracer.nrc_train_step(x, w, lam, t, apply=True))
+        loss, p, tb = ora.train_step(p, tb, opt, x, w, lam, t, LO, HI)
+        ol.append(loss)
+    gl, ol = np.array(gl), np.array(ol)
+    print("[nrc] loss gpu   " + " ".join(f"{v:.4f}" for v in gl), flush=True)
+    print("[nrc] loss oracle" + " ".join(f"{v:.4f}" for v in ol), flush=True)
+    assert abs(gl[0] - ol[0]) <= 1e-4 * ol[0]
+    assert np.all(np.abs(gl - ol) <= 0.05 * ol)
+    assert gl[-1] < 0.5 * gl[0]
+
+
+def test_errors(tracer):
+    import paper_1912_06474_amd as m
+    params, tables = _net(7, 10)
+    with pytest.raises(m.SddError, match="INVALID_ARG"):
+        tracer.nrc_init(params, tables[:, :512], LO, HI)  # 2^9 entries: below the minimum
+    bad = tables.copy()
+    bad[3, 5, 1] = np.nan
+    with pytest.raises(m.SddError, match="non-finite"):
+        tracer.nrc_init(params, bad, LO, HI)
+    with pytest.raises(m.SddError, match="box"):
+        tracer.nrc_init(params, tables, HI, LO)
+    tracer.nrc_init(params, tables, LO, HI)
+    x, w, lam = _rows(4, 1)
+    with pytest.raises(KeyError):
+        tracer.nrc_infer(x, w, lam, "fp8")
+    y = tracer.nrc_infer(x[:0], w[:0], lam[:0])
+    assert y.numel() == 0

@@ -161,3 +161,33 @@ def test_train_step_reduces_the_loss():
         loss, p, tables = nrc.train_step(p, tables, opt, x, w, lam, t, (0, 0, 0), (4, 3, 2.5))
         losses.append(loss)
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_bf16_round_ties_to_even_and_matches_torch():
+    u = 2.0 ** -8  # half an ulp of bfloat16 at 1
+    got = nrc.bf16_round(np.array([1.0, 1.0 + u, 1.0 + 3 * u, 1.0 + u + 2.0 ** -20, -(1.0 + 3 * u), 0.0]))
+    assert got.tolist() == [1.0, 1.0, 1.0 + 4 * u, 1.0 + 2 * u, -(1.0 + 4 * u), 0.0]
+    import torch
+    x = np.random.default_rng(3).normal(size=4096) * np.exp(np.random.default_rng(4).uniform(-20, 20, 4096))
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(nrc.bf16_round(x), ref)
+
+
+def test_bf16_forward_is_exact_on_bf16_operands():
+    rng = np.random.default_rng(5)
+    # operands with at most 8 significant bits are bfloat16 values: nothing rounds
+    params = {"W": [rng.integers(-8, 9, (64, 64)) / 16.0] + [np.zeros((64, 64)) for _ in range(4)],
+              "b": [rng.integers(-4, 5, 64) / 8.0 for _ in range(5)],
+              "wo": rng.normal(size=64), "bo": 0.25}
+    X = rng.integers(-64, 65, (50, 64)) / 32.0
+    y, _ = nrc.mlp_forward(params, X)
+    assert np.array_equal(nrc.mlp_forward_bf16(params, X), y)
+    # with W_1 = I the second layer consumes the first layer's outputs, which need
+    # more than 8 bits: the result is relu(bf16(h1) + b1) passed on exactly
+    params["W"][1] = np.eye(64)
+    _, acts = nrc.mlp_forward(params, X)
+    assert not np.array_equal(nrc.bf16_round(acts[1]), acts[1])
+    h = np.maximum(0.0, nrc.bf16_round(acts[1]) + params["b"][1])
+    for k in range(2, 5):
+        h = np.maximum(0.0, 0.0 * h + params["b"][k])
+    assert np.allclose(nrc.mlp_forward_bf16(params, X), h @ params["wo"] + params["bo"], rtol=0, atol=1e-12)
