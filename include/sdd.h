@@ -141,6 +141,7 @@ typedef struct sdd_bvh_desc {
 #define SDD_TRACE_ORTHO 1u        /* rays orthogonal to the image plane (Sec. 4) */
 #define SDD_TRACE_TIME_KERNELS 2u /* time every launch with HIP events (stats) */
 #define SDD_TRACE_COUNT_WORK 4u   /* count node visits / triangle tests (stats) */
+#define SDD_TRACE_NRC 8u          /* radiance-cache estimator (see sdd_nrc_desc); one render per call */
 
 /*
  * One call traces spp samples of every pixel of render render_id and adds
@@ -316,6 +317,11 @@ typedef struct sdd_nrc_desc {
     float lambda_lo, lambda_hi;    /* nm, hi > lo */
     float lr, beta1, beta2, eps;   /* lr > 0, 0 <= beta < 1, eps > 0 */
     const float *params;           /* host; initial parameters (copied) */
+    /* renders with SDD_TRACE_NRC */
+    int32_t train_paths;           /* training paths per call (>= 1) */
+    int32_t train_steps;           /* Adam steps after each call (>= 0) */
+    int32_t train_batch;           /* rows per step, 1..2^22 */
+    int32_t precision;             /* cache queries: 0 FP32, 1 BF16 matrix cores */
 } sdd_nrc_desc;
 
 /* Parameter count for a table size; -1 if table_log2 is out of range. */
@@ -342,6 +348,39 @@ sdd_status sdd_nrc_infer(sdd_ctx *ctx, int32_t n, const float *x, const float *w
  * the next step. */
 sdd_status sdd_nrc_train_step(sdd_ctx *ctx, int32_t n, const float *x, const float *w, const float *lambda_nm,
                               const float *t, int32_t apply, float *loss);
+
+/*
+ * Rendering with the cache (sdd_trace_desc.flags |= SDD_TRACE_NRC).  Path
+ * (p, s) is a training path when (s * W * H + p) % stride == 0, stride =
+ * ceil(W * H * spp / train_paths); training paths are traced exactly as
+ * without the cache.  Every other path ends at its first diffuse vertex x of
+ * depth >= 2: emission and the light sample there are added as usual, then
+ * beta(lambda) * L(x, n, lambda), beta the path throughput after the vertex's
+ * Lambert factor, L the cache at the hit point with the geometric normal n
+ * on the side the ray arrived from as its direction input.  Each diffuse
+ * vertex of depth >= 2 of a training path that continues gives one training
+ * row at one wavelength l drawn from Philox counter (p, s, depth, 3) (l =
+ * word 0 mod n_lambda): target the radiance the path carries back into the
+ * vertex along its continuation, at l, the same terms the estimator adds.
+ * After the call, train_steps Adam steps run on the call's rows (step k of S
+ * on rows k, k + S, ...).  Gradient sums use atomics, so trained caches
+ * differ between runs by rounding.
+ */
+
+/* Cache values of n surface points at every wavelength of the loaded scene,
+ * as a cache render queries them: x4, n4 DEVICE float [n][4] (position;
+ * normal as the direction input; w ignored); out DEVICE float [n][nlp], nlp
+ * = n_lambda rounded up to a multiple of 4 (entries past n_lambda are not
+ * written).  precision as in sdd_nrc_infer.  SDD_ERR_STATE without a scene
+ * or cache. */
+sdd_status sdd_nrc_query(sdd_ctx *ctx, int32_t n, const float *x4, const float *n4, float *out, int32_t precision);
+
+/* The last cache render's training rows (compacted, in path order): rows
+ * host float [max_rows][8] = (x, y, z, lambda_nm, n_x, n_y, n_z, target);
+ * n_rows gets the row count, n_steps the Adam steps taken, loss the last
+ * step's loss.  Any output pointer may be NULL.  Synchronises. */
+sdd_status sdd_nrc_last_rows(sdd_ctx *ctx, int32_t max_rows, float *rows, int32_t *n_rows, int32_t *n_steps,
+                             float *loss);
 
 /* Copy a parameter-sized array to the host: which 0 parameters, 1 last
  * gradient, 2 Adam first moments, 3 second moments.  Synchronises. */

@@ -47,13 +47,15 @@ class Args(C.Structure):
         ("W", C.c_int), ("H", C.c_int), ("spp", C.c_int), ("sample_offset", C.c_int), ("max_depth", C.c_int),
         ("seed", C.c_uint32), ("render_id", C.c_uint32), ("use_bvh", C.c_int), ("n_threads", C.c_int),
         ("n_pix", C.c_int), ("pix", C.c_void_p),
+        ("nrc", C.c_int), ("nrc_stride", C.c_uint32), ("nrc_c", C.c_double * 7), ("nrc_lo", C.c_double * 3),
+        ("nrc_hi", C.c_double * 3),
     ]
 
 
 class Out(C.Structure):
     _fields_ = [
         ("spectral", C.c_void_p), ("xyz", C.c_void_p), ("hit_log", C.c_void_p),
-        ("shadow_log", C.c_void_p), ("path_L", C.c_void_p), ("first_hit", C.c_void_p),
+        ("shadow_log", C.c_void_p), ("path_L", C.c_void_p), ("first_hit", C.c_void_p), ("nrc_rows", C.c_void_p),
         ("n_ext_rays", C.c_int64), ("n_shadow_rays", C.c_int64),
     ]
 
@@ -160,10 +162,13 @@ def make_args(camera, W, H, spp, max_depth, seed=0, render_id=0, sample_offset=0
 
 def render(scene, W, H, spp, max_depth, *, camera=None, seed=0, render_id=0, sample_offset=0,
            use_bvh=True, n_threads=0, pix=None, logs=False, path_L=False, first_hit=False,
-           oscene=None):
+           oscene=None, nrc=None):
     """Render with the oracle.  Returns a dict of numpy arrays.
 
     ``pix``: optional list of pixel indices p = py*W + px (outputs follow it).
+    ``nrc``: optional dict(stride, c (7 coefficients), lo, hi) selecting the
+    radiance-cache estimator with the closed-form cache c0 + c[1:4].xn + c[4:7].n;
+    the result then also holds ``nrc_rows`` [n_out][spp][D-1][9].
     """
     osc = oscene or OracleScene(scene)
     cam = camera or scene["camera"]
@@ -182,8 +187,14 @@ def render(scene, W, H, spp, max_depth, *, camera=None, seed=0, render_id=0, sam
         res["path_L"] = np.zeros((n_out, spp, nl))
     if first_hit:
         res["first_hit"] = np.zeros((n_out, spp, 3))
+    if nrc is not None:
+        a.nrc, a.nrc_stride = 1, int(nrc["stride"])
+        a.nrc_c[:] = [float(v) for v in nrc["c"]]
+        a.nrc_lo[:] = [float(v) for v in nrc["lo"]]
+        a.nrc_hi[:] = [float(v) for v in nrc["hi"]]
+        res["nrc_rows"] = np.zeros((n_out, spp, max(1, max_depth - 1), 9))
     o = Out(_ptr(res["spectral"]), _ptr(res["xyz"]), _ptr(res.get("hit_log")), _ptr(res.get("shadow_log")),
-            _ptr(res.get("path_L")), _ptr(res.get("first_hit")), 0, 0)
+            _ptr(res.get("path_L")), _ptr(res.get("first_hit")), _ptr(res.get("nrc_rows")), 0, 0)
     acc = osc.accel if use_bvh else None
     rc = lib().ora_render(C.byref(osc.c), acc, C.byref(a), C.byref(o))
     if rc != 0:

@@ -543,11 +543,22 @@ static int any_nonzero(const float *v, int n) {
  * parallelogram emitter) and a secondary ray continues the path; a glass
  * vertex reflects or transmits with probability from the pane's R and T; the
  * path stops after max_depth surface vertices. */
+/* Radiance-cache reading of the estimator (used when ar->nrc): a training
+ * row at a diffuse vertex of depth d >= 2 that continues the path records
+ * the wavelength index l = (Philox word 0 of counter (p, s, d, 3)) mod nl and
+ * the radiance the path then carries back into the vertex along its
+ * continuation, (L_end[l] - L_d[l]) / beta_d[l], with L_d and beta_d the
+ * estimate and throughput right after the vertex's light sample. */
 static void trace_path(const ora_scene *sc, const ora_accel *acc, const ora_args *ar, int px, int py,
                        uint32_t s, double *L, int32_t *hlog, int32_t *slog, double *fhit,
-                       double *beta, double *tmp_T, int64_t *n_ext, int64_t *n_sh) {
+                       double *beta, double *tmp_T, int64_t *n_ext, int64_t *n_sh, double *rows) {
     const int nl = sc->n_lambda, D = ar->max_depth;
     const uint32_t p = (uint32_t)(py * ar->W + px);
+    const int train = ar->nrc && ((uint64_t)s * (uint64_t)ar->W * (uint64_t)ar->H + p) % ar->nrc_stride == 0;
+    /* per training row: estimate and throughput at its wavelength when recorded */
+    double row_L[64], row_b[64];
+    int row_l[64];
+    if (rows) for (int k = 0; k < (D - 1) * 9; ++k) rows[k] = 0.0;
     double u[4], ub[4], uc[4];
     rng_u(ar->seed, ar->render_id, p, s, 0, 0, u);
     double oa[3], da[3];
@@ -621,7 +632,27 @@ static void trace_path(const ora_scene *sc, const ora_accel *acc, const ora_args
                 }
             }
             countE = 0;
+            if (ar->nrc && d >= 2 && !train) {     /* the cache takes the rest of the path */
+                double c = ar->nrc_c[0];
+                const double xv[3] = {x.x, x.y, x.z}, nv[3] = {n.x, n.y, n.z};
+                for (int k = 0; k < 3; ++k) {
+                    double u = (xv[k] - ar->nrc_lo[k]) / (ar->nrc_hi[k] - ar->nrc_lo[k]);
+                    u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+                    c += ar->nrc_c[1 + k] * u + ar->nrc_c[4 + k] * nv[k];
+                }
+                for (int l = 0; l < nl; ++l) L[l] += beta[l] * c;
+                break;
+            }
             if (d == D) break;
+            if (ar->nrc && train && d >= 2 && rows && d - 2 < 64) {
+                uint32_t ctr[4] = {p, s, (uint32_t)d, 3u}, key[2] = {ar->seed, ar->render_id}, o[4];
+                ora_philox4x32_10(ctr, key, o);
+                const int l = (int)(o[0] % (uint32_t)nl);
+                double *r = rows + (size_t)(d - 2) * 9;
+                r[0] = 1.0; r[1] = x.x; r[2] = x.y; r[3] = x.z; r[4] = (double)sc->lambda_nm[l];
+                r[5] = n.x; r[6] = n.y; r[7] = n.z;
+                row_l[d - 2] = l; row_L[d - 2] = L[l]; row_b[d - 2] = beta[l];
+            }
             double nn[3] = {n.x, n.y, n.z}, wd[3];
             ora_cosine_hemisphere(nn, uc[0], uc[1], wd);
             dir = mk(wd[0], wd[1], wd[2]);
@@ -660,6 +691,10 @@ static void trace_path(const ora_scene *sc, const ora_accel *acc, const ora_args
             exclude = prim;
         }
     }
+    if (rows)
+        for (int k = 0; k < D - 1 && k < 64; ++k)
+            if (rows[(size_t)k * 9] != 0.0)
+                rows[(size_t)k * 9 + 8] = row_b[k] != 0.0 ? (L[row_l[k]] - row_L[k]) / row_b[k] : NAN;
 }
 
 int ora_render(const ora_scene *sc, const ora_accel *acc, const ora_args *ar, ora_out *out) {
@@ -692,8 +727,9 @@ int ora_render(const ora_scene *sc, const ora_accel *acc, const ora_args *ar, or
                 if (hl) for (int d = 0; d < D; ++d) hl[d] = -2;
                 if (sl) for (int d = 0; d < D; ++d) sl[d] = -2;
                 double *fh = out->first_hit ? out->first_hit + slot * 3 : NULL;
+                double *rw = out->nrc_rows ? out->nrc_rows + slot * (size_t)(D - 1) * 9 : NULL;
                 trace_path(sc, a, ar, px, py, (uint32_t)(ar->sample_offset + j), L, hl, sl, fh, beta, tmpT,
-                           &n_ext, &n_sh);
+                           &n_ext, &n_sh, rw);
                 if (out->path_L) memcpy(out->path_L + slot * nl, L, sizeof(double) * (size_t)nl);
                 for (int l = 0; l < nl; ++l) acc_l[l] += L[l];
             }

@@ -80,6 +80,15 @@ typedef struct ora_args {
     int n_threads;           /* <= 0: OpenMP default */
     int n_pix;               /* > 0: render only the listed pixels */
     const int32_t *pix;      /* [n_pix] pixel indices p = py*W + px */
+    /* radiance-cache estimator (nrc != 0) with a closed-form cache
+     * L(x, n) = c[0] + c[1..3] . xn + c[4..6] . n, xn = clip((x - lo) / (hi - lo), 0, 1):
+     * training paths ((s W H + p) % nrc_stride == 0) are traced as without
+     * it; any other path ends at its first diffuse vertex of depth >= 2 after
+     * that vertex's light sample, adding beta * L(x, n). */
+    int nrc;
+    uint32_t nrc_stride;
+    double nrc_c[7];
+    double nrc_lo[3], nrc_hi[3];
 } ora_args;
 
 typedef struct ora_out {
@@ -89,6 +98,9 @@ typedef struct ora_out {
     int32_t *shadow_log;     /* [n_out][spp][D]: 1 visible, 0 blocked, -2 none; or NULL */
     double *path_L;          /* [n_out][spp][nl] per-sample radiance, or NULL */
     double *first_hit;       /* [n_out][spp][3] first vertex position (NaN if none), or NULL */
+    double *nrc_rows;        /* [n_out][spp][D-1][9] training rows of training paths, or NULL:
+                                (valid, x, y, z, lambda_nm, n_x, n_y, n_z, target) for the
+                                diffuse vertex of depth 2 + index that continued the path */
     int64_t n_ext_rays;      /* closest-hit queries traced */
     int64_t n_shadow_rays;   /* shadow queries traced */
 } ora_out;

@@ -25,12 +25,13 @@ LIB_PATH = os.path.join(HERE, "libsdd.so")
 SDD_OK = 0
 STATUS = {0: "SDD_OK", -1: "SDD_ERR_INVALID_ARG", -2: "SDD_ERR_STATE", -3: "SDD_ERR_OOM", -4: "SDD_ERR_HIP",
           -5: "SDD_ERR_OVERFLOW", -6: "SDD_ERR_UNSUPPORTED"}
-TRACE_ORTHO, TRACE_TIME_KERNELS, TRACE_COUNT_WORK = 1, 2, 4
+TRACE_ORTHO, TRACE_TIME_KERNELS, TRACE_COUNT_WORK, TRACE_NRC = 1, 2, 4, 8
 
 EXPORTS = ("sdd_create", "sdd_destroy", "sdd_last_error", "sdd_load_scene", "sdd_validate_scene", "sdd_build_bvh",
            "sdd_trace_spectral", "sdd_resolve_image", "sdd_reset_render", "sdd_get_stats", "sdd_reset_stats",
            "sdd_debug_philox", "sdd_debug_pane", "sdd_debug_trace_rays", "sdd_debug_glass", "sdd_trace_batch",
-           "sdd_nrc_param_count", "sdd_nrc_init", "sdd_nrc_infer", "sdd_nrc_train_step", "sdd_nrc_get_params")
+           "sdd_nrc_param_count", "sdd_nrc_init", "sdd_nrc_infer", "sdd_nrc_train_step", "sdd_nrc_get_params",
+           "sdd_nrc_last_rows", "sdd_nrc_query")
 NRC_LEVELS, NRC_FEAT, NRC_HID, NRC_LAYERS = 16, 2, 64, 5
 
 
@@ -71,7 +72,9 @@ class TraceDesc(C.Structure):
 class NrcDesc(C.Structure):
     _fields_ = [("table_log2", C.c_int32), ("aabb_lo", C.c_float * 3), ("aabb_hi", C.c_float * 3),
                 ("lambda_lo", C.c_float), ("lambda_hi", C.c_float), ("lr", C.c_float), ("beta1", C.c_float),
-                ("beta2", C.c_float), ("eps", C.c_float), ("params", C.c_void_p)]
+                ("beta2", C.c_float), ("eps", C.c_float), ("params", C.c_void_p),
+                ("train_paths", C.c_int32), ("train_steps", C.c_int32), ("train_batch", C.c_int32),
+                ("precision", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -125,6 +128,9 @@ def lib():
         L.sdd_nrc_infer.argtypes = [vp, i32, vp, vp, vp, vp, i32]
         L.sdd_nrc_train_step.argtypes = [vp, i32, vp, vp, vp, vp, i32, C.POINTER(C.c_float)]
         L.sdd_nrc_get_params.argtypes = [vp, i32, vp]
+        L.sdd_nrc_query.argtypes = [vp, i32, vp, vp, vp, i32]
+        L.sdd_nrc_last_rows.argtypes = [vp, i32, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_float)]
         _LIB = L
     return _LIB
 
@@ -223,7 +229,7 @@ class Tracer:
         self._check(lib().sdd_build_bvh(self.h, C.byref(BvhDesc(nx, ny, nz, leaf_max, sah_bins, int(bool(device))))))
 
     def _desc(self, camera, W, H, spp, max_depth, seed=0, render_id=0, sample_offset=0, time_kernels=False,
-              count_work=False, hit_log=None, shadow_log=None, glass_swap=None):
+              count_work=False, hit_log=None, shadow_log=None, glass_swap=None, nrc=False):
         d = TraceDesc()
         d.eye[:] = [float(x) for x in camera["eye"]]
         d.target[:] = [float(x) for x in camera["target"]]
@@ -238,6 +244,8 @@ class Tracer:
             fl |= TRACE_TIME_KERNELS
         if count_work:
             fl |= TRACE_COUNT_WORK
+        if nrc:
+            fl |= TRACE_NRC
         d.flags = fl
         n_slots = int(W) * int(H) * int(spp) * int(max_depth)
         for name, t in (("hit_log", hit_log), ("shadow_log", shadow_log)):
@@ -249,11 +257,13 @@ class Tracer:
         return d
 
     def trace_spectral(self, camera, W, H, spp, max_depth, *, seed=0, render_id=0, sample_offset=0,
-                       time_kernels=False, count_work=False, hit_log=None, shadow_log=None, glass_swap=None):
+                       time_kernels=False, count_work=False, hit_log=None, shadow_log=None, glass_swap=None,
+                       nrc=False):
         """Trace spp samples of every pixel; glass_swap = (from_material, to_material) substitutes a
-        glass material for this render (photochromic state)."""
+        glass material for this render (photochromic state); nrc=True uses the radiance cache
+        (paths end in the cache, training paths train it after the call)."""
         d = self._desc(camera, W, H, spp, max_depth, seed, render_id, sample_offset, time_kernels, count_work,
-                       hit_log, shadow_log, glass_swap)
+                       hit_log, shadow_log, glass_swap, nrc)
         self._check(lib().sdd_trace_spectral(self.h, C.byref(d)))
 
     def trace_batch(self, renders, max_depth, *, seed=0, time_kernels=False, count_work=False):
@@ -330,9 +340,9 @@ class Tracer:
 
     # ---- learned radiance cache -------------------------------------------------
     def nrc_init(self, params, tables, aabb_lo, aabb_hi, lambda_range=(380.0, 780.0), lr=1e-2, betas=(0.9, 0.99),
-                 eps=1e-8):
+                 eps=1e-8, train_paths=1 << 16, train_steps=4, train_batch=1 << 16, precision="bf16"):
         """Create the cache from a parameter dict (W [5][64][64], b [5][64], wo [64], bo) and hash
-        tables [16][T][2] (T a power of two)."""
+        tables [16][T][2] (T a power of two); the last four settings apply to renders with nrc=True."""
         T = int(np.asarray(tables).shape[1])
         log2 = T.bit_length() - 1
         if T != 1 << log2:
@@ -346,6 +356,8 @@ class Tracer:
         d.lambda_lo, d.lambda_hi = float(lambda_range[0]), float(lambda_range[1])
         d.lr, d.beta1, d.beta2, d.eps = float(lr), float(betas[0]), float(betas[1]), float(eps)
         d.params = flat.ctypes.data
+        d.train_paths, d.train_steps, d.train_batch = int(train_paths), int(train_steps), int(train_batch)
+        d.precision = {"fp32": 0, "bf16": 1}[precision]
         self._check(lib().sdd_nrc_init(self.h, C.byref(d)))
 
     def _rows(self, *arrays):
@@ -371,6 +383,32 @@ class Tracer:
         self._check(lib().sdd_nrc_train_step(self.h, lam.numel(), x.data_ptr(), w.data_ptr(), lam.data_ptr(),
                                              target.data_ptr(), int(bool(apply)), C.byref(loss)))
         return float(loss.value)
+
+    def nrc_query(self, x, nrm, precision="fp32"):
+        """Cache values of points (x [n,3], normal [n,3]) at every scene wavelength: [n, nlp] device tensor."""
+        torch = self.torch
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device).reshape(-1, 3)
+        nrm = torch.as_tensor(nrm, dtype=torch.float32, device=self.device).reshape(-1, 3)
+        n = x.shape[0]
+        x4 = torch.zeros((n, 4), dtype=torch.float32, device=self.device)
+        n4 = torch.zeros((n, 4), dtype=torch.float32, device=self.device)
+        x4[:, :3] = x
+        n4[:, :3] = nrm
+        nlp = (self.n_lambda + 3) // 4 * 4
+        out = torch.zeros((n, nlp), dtype=torch.float32, device=self.device)
+        self._check(lib().sdd_nrc_query(self.h, n, x4.data_ptr(), n4.data_ptr(), out.data_ptr(),
+                                        {"fp32": 0, "bf16": 1}[precision]))
+        return out
+
+    def nrc_last_rows(self, max_rows=None):
+        """(rows [n][8] = x, y, z, lambda, n_x, n_y, n_z, target; Adam steps; last loss) of the last cache render."""
+        n, steps, loss = C.c_int32(), C.c_int32(), C.c_float()
+        self._check(lib().sdd_nrc_last_rows(self.h, 0, None, C.byref(n), C.byref(steps), C.byref(loss)))
+        m = n.value if max_rows is None else min(n.value, int(max_rows))
+        rows = np.zeros((m, 8), np.float32)
+        if m:
+            self._check(lib().sdd_nrc_last_rows(self.h, m, _ptr(rows), None, None, None))
+        return rows, steps.value, loss.value
 
     def nrc_get(self, which="params"):
         """(dict, tables) of the parameters, last gradient, or Adam moments ('m', 'v')."""

@@ -127,6 +127,31 @@ struct sdd_ctx {
     float* nrc_y = nullptr;
     float* nrc_dy = nullptr;
     float* nrc_loss = nullptr;
+    // cache settings for renders
+    int nrc_train_paths = 0, nrc_train_steps = 0, nrc_train_batch = 0, nrc_precision = 1;
+    // render buffers of the cache: per batch path, per training slot, training rows
+    long long nrc_pcap = 0, nrc_scap = 0;
+    int nrc_dcap = 0;
+    float4* nrc_cx = nullptr;
+    float4* nrc_cn = nullptr;
+    float* nrc_lhat = nullptr;
+    float4* nrc_tx = nullptr;
+    float4* nrc_tn = nullptr;
+    float4* nrc_rows = nullptr;
+    int* nrc_ok = nullptr;
+    float4* nrc_crows = nullptr;
+    int* nrc_count = nullptr;
+    void* nrc_tmp = nullptr;
+    size_t nrc_tmp_bytes = 0;
+    float* nrc_bx = nullptr;  // training batch, SoA
+    float* nrc_bw = nullptr;
+    float* nrc_blam = nullptr;
+    float* nrc_bt = nullptr;
+    long long nrc_bcap = 0;
+    long long nrc_last_rows = 0;
+    int nrc_last_steps = 0;
+    float nrc_last_loss = 0.0f;
+    float* d_lam = nullptr;  // scene wavelengths (nm), FP32
 
     // host stats
     long long batches = 0, launches_trace = 0, cam_rays = 0;
@@ -218,6 +243,7 @@ void free_scene(sdd_ctx* c) {
     dfree(c, c->d_le);
     dfree(c, c->d_w);
     dfree(c, c->d_cmf);
+    dfree(c, c->d_lam);
     c->has_scene = false;
 }
 
@@ -264,7 +290,28 @@ void free_nrc_batch(sdd_ctx* c) {
     c->nrc_cap = 0;
 }
 
+void free_nrc_render(sdd_ctx* c) {
+    dfree(c, c->nrc_cx);
+    dfree(c, c->nrc_cn);
+    dfree(c, c->nrc_lhat);
+    dfree(c, c->nrc_tx);
+    dfree(c, c->nrc_tn);
+    dfree(c, c->nrc_rows);
+    dfree(c, c->nrc_ok);
+    dfree(c, c->nrc_crows);
+    dfree(c, c->nrc_count);
+    dfree(c, c->nrc_tmp);
+    dfree(c, c->nrc_bx);
+    dfree(c, c->nrc_bw);
+    dfree(c, c->nrc_blam);
+    dfree(c, c->nrc_bt);
+    c->nrc_pcap = c->nrc_scap = c->nrc_bcap = 0;
+    c->nrc_dcap = 0;
+    c->nrc_tmp_bytes = 0;
+}
+
 void free_nrc(sdd_ctx* c) {
+    free_nrc_render(c);
     free_nrc_batch(c);
     dfree(c, c->nrc_loss);
     dfree(c, c->nrc.p);
@@ -713,7 +760,8 @@ sdd_status sdd_load_scene(sdd_ctx* c, const sdd_scene_desc* s) {
         (st = upload(c, &c->d_rho, rho.data(), rho.size())) != SDD_OK ||
         (st = upload(c, &c->d_le, le.data(), le.size())) != SDD_OK ||
         (st = upload(c, &c->d_w, s->lambda_w, (size_t)nl)) != SDD_OK ||
-        (st = upload(c, &c->d_cmf, s->cmf, (size_t)nl * 3)) != SDD_OK) {
+        (st = upload(c, &c->d_cmf, s->cmf, (size_t)nl * 3)) != SDD_OK ||
+        (st = upload(c, &c->d_lam, s->lambda_nm, (size_t)nl)) != SDD_OK) {
         free_scene(c);
         return st;
     }
@@ -908,6 +956,109 @@ sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
 
 namespace {
 
+sdd_status nrc_reserve(sdd_ctx* c, long long n);
+
+// render buffers of the radiance cache: n batch paths, slots training paths of depth D
+sdd_status nrc_ensure_render(sdd_ctx* c, long long n, long long slots, int D) {
+    sdd_status st;
+    if (n > c->nrc_pcap) {
+        dfree(c, c->nrc_cx);
+        dfree(c, c->nrc_cn);
+        dfree(c, c->nrc_lhat);
+        c->nrc_pcap = 0;
+        if ((st = dalloc(c, &c->nrc_cx, (size_t)n)) != SDD_OK || (st = dalloc(c, &c->nrc_cn, (size_t)n)) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_lhat, (size_t)n * c->nlp)) != SDD_OK)
+            return st;
+        c->nrc_pcap = n;
+    }
+    if (slots > c->nrc_scap || D > c->nrc_dcap) {
+        dfree(c, c->nrc_tx);
+        dfree(c, c->nrc_tn);
+        dfree(c, c->nrc_rows);
+        dfree(c, c->nrc_ok);
+        dfree(c, c->nrc_crows);
+        dfree(c, c->nrc_tmp);
+        c->nrc_scap = 0;
+        c->nrc_dcap = 0;
+        const long long rows = slots * std::max(1, D - 1);
+        if ((st = dalloc(c, &c->nrc_tx, (size_t)(slots * D))) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_tn, (size_t)(slots * D))) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_rows, (size_t)(2 * rows))) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_ok, (size_t)rows)) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_crows, (size_t)(2 * rows))) != SDD_OK)
+            return st;
+        size_t tb = 0;
+        HIP_TRY(c, nrc_select_rows(c->nrc_rows, c->nrc_ok, (int)rows, c->nrc_crows, c->nrc_count, nullptr, &tb,
+                                   c->stream));
+        c->nrc_tmp_bytes = std::max<size_t>(tb, 16);
+        if ((st = dalloc(c, reinterpret_cast<char**>(&c->nrc_tmp), c->nrc_tmp_bytes)) != SDD_OK) return st;
+        c->nrc_scap = slots;
+        c->nrc_dcap = D;
+    }
+    if (!c->nrc_count && (st = dalloc(c, &c->nrc_count, 1)) != SDD_OK) return st;
+    const long long bn = c->nrc_train_batch;
+    if (bn > c->nrc_bcap) {
+        dfree(c, c->nrc_bx);
+        dfree(c, c->nrc_bw);
+        dfree(c, c->nrc_blam);
+        dfree(c, c->nrc_bt);
+        c->nrc_bcap = 0;
+        if ((st = dalloc(c, &c->nrc_bx, (size_t)(3 * bn))) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_bw, (size_t)(3 * bn))) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_blam, (size_t)bn)) != SDD_OK || (st = dalloc(c, &c->nrc_bt, (size_t)bn)) != SDD_OK)
+            return st;
+        c->nrc_bcap = bn;
+    }
+    return SDD_OK;
+}
+
+// After a cache render: compact the training rows the call produced and take
+// up to train_steps Adam steps, step k on rows k, k + S, k + 2S, ... (S steps;
+// at most train_batch rows each), spread over the image.
+sdd_status nrc_train_after_call(sdd_ctx* c, long long n_rows, bool timing) {
+    c->nrc_last_rows = 0;
+    c->nrc_last_steps = 0;
+    c->nrc_last_loss = 0.0f;
+    if (n_rows <= 0) return SDD_OK;
+    {
+        Timer tm(c, timing, 3);
+        size_t tb = c->nrc_tmp_bytes;
+        HIP_TRY(c, nrc_select_rows(c->nrc_rows, c->nrc_ok, (int)n_rows, c->nrc_crows, c->nrc_count, c->nrc_tmp, &tb,
+                                   c->stream));
+    }
+    int count = 0;
+    HIP_TRY(c, hipMemcpyAsync(&count, c->nrc_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->nrc_last_rows = count;
+    if (count <= 0) return SDD_OK;
+    const int S = std::min(c->nrc_train_steps, count);
+    sdd_status st = nrc_reserve(c, c->nrc_train_batch);
+    if (st != SDD_OK) return st;
+    double loss_sum = 0.0;
+    for (int k = 0; k < S; ++k) {
+        const int nk = (int)std::min<long long>(c->nrc_train_batch, (count - k + S - 1) / S);
+        Timer tm(c, timing, 3);
+        HIP_TRY(c, nrc_launch_unpack(c->nrc_crows, k, S, nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt, c->stream));
+        NrcBatch b{nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt, c->nrc_acts, c->nrc_dz, c->nrc_y, c->nrc_dy,
+                   c->nrc_loss};
+        HIP_TRY(c, nrc_launch_zero(c->nrc.g, c->nrc.n_all, c->stream));
+        HIP_TRY(c, nrc_launch_zero(c->nrc_loss, 1, c->stream));
+        HIP_TRY(c, nrc_launch_grad(c->nrc, b, c->stream));
+        HIP_TRY(c, nrc_launch_adam(c->nrc, c->nrc_t + 1, c->nrc_lr, c->nrc_b1, c->nrc_b2, c->nrc_eps, c->stream));
+        HIP_TRY(c, nrc_launch_pack(c->nrc, c->stream));
+        ++c->nrc_t;
+        if (k == S - 1) {  // the last step's loss (one read-back per call)
+            float l = 0.0f;
+            HIP_TRY(c, hipMemcpyAsync(&l, c->nrc_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            loss_sum = l;
+        }
+    }
+    c->nrc_last_steps = S;
+    c->nrc_last_loss = (float)loss_sum;
+    return SDD_OK;
+}
+
 // one render of a trace call
 struct Job {
     const sdd_trace_desc* t = nullptr;
@@ -977,12 +1128,28 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
         j.start = total_pad;
         total_pad += (j.total + kShadeBlock - 1) / kShadeBlock * kShadeBlock;
     }
-    long long nb = mem_budget_bytes() / bytes_per_path(c, D);
+    const bool nrc = (any_flags & SDD_TRACE_NRC) != 0;
+    long long nb = mem_budget_bytes() / (bytes_per_path(c, D) + (nrc ? 32 + 4LL * c->nlp : 0));
     nb = std::min<long long>(nb, kMaxBatch);
     nb = std::max<long long>(kShadeBlock, nb / kShadeBlock * kShadeBlock);
     nb = std::min(nb, total_pad);
     sdd_status st = ensure_batch(c, nb, D);
     if (st != SDD_OK) return st;
+    // radiance cache (one render per call): training paths are those with
+    // (s * WH + p) % stride == 0; in the call's path numbering qc = (s - s0) WH + p
+    // they are qc = r + j * stride, j the training slot
+    NrcPaths np{};
+    uint32_t stride = 1;
+    long long r_nrc = 0, n_slots = 0;
+    if (nrc) {
+        const Job& j = jobs[0];
+        stride = (uint32_t)std::max<long long>(1, (j.total + c->nrc_train_paths - 1) / c->nrc_train_paths);
+        const unsigned long long sw = (unsigned long long)(uint32_t)j.t->sample_offset * (unsigned long long)j.WH;
+        r_nrc = (long long)((stride - sw % stride) % stride);
+        n_slots = j.total > r_nrc ? (j.total - 1 - r_nrc) / stride + 1 : 0;
+        if ((st = nrc_ensure_render(c, nb, std::max<long long>(1, n_slots), D)) != SDD_OK) return st;
+        np = NrcPaths{1, stride, c->nrc_cx, c->nrc_cn, c->nrc_tx, c->nrc_tn};
+    }
     for (const Job& j : jobs) {
         if (j.t->hit_log) {
             Timer tm(c, timing, 3);
@@ -1045,6 +1212,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
             cp.se = c->stage[0];
             cp.n_blocks = n_blocks;
             cp.stats = c->d_stats;
+            cp.nrc = np;
             Timer tm(c, timing, 3);
             HIP_TRY(c, launch_camgen(cp, c->stream));
             c->cam_rays += sg.n;
@@ -1080,6 +1248,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
         sp.ss = c->stage[1];
         sp.n_blocks = n_blocks;
         sp.stats = c->d_stats;
+        sp.nrc = np;
         for (int d = 1; d <= D; ++d) {
             // closest-hit rays of depth d share the sweeps with the shadow rays of depth d - 1
             st = run_sweeps(c, ph_ext(d), d >= 2 ? ph_sh(d - 1) : -1, cap, count, timing, d - 1, N);
@@ -1110,6 +1279,11 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
         }
         st = run_sweeps(c, -1, ph_sh(D), cap, count, timing, D, N);
         if (st != SDD_OK) return st;
+        if (nrc) {  // cache values at the batch's cache vertices, every wavelength
+            Timer tm(c, timing, 3);
+            HIP_TRY(c, nrc_launch_query(c->nrc, N, c->nrc_cx, c->nrc_cn, c->d_lam, c->nl, c->nlp, c->nrc_lhat,
+                                        c->nrc_precision, c->stream));
+        }
         for (const Seg& sg : segs) {
             const sdd_trace_desc* t = sg.j->t;
             SpectralParams xp{};
@@ -1143,12 +1317,55 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
             xp.light_mat = c->light_mat < 0 ? 0 : c->light_mat;
             xp.acc = sg.j->rd->acc;
             xp.shadow_log = t->shadow_log;
+            xp.lhat = nrc ? c->nrc_lhat : nullptr;
             Timer tm(c, timing, 3);
             HIP_TRY(c, launch_spectral(xp, c->stream));
+            if (nrc) {  // training rows of the segment's training paths
+                const long long a = sg.q0, b = sg.q0 + sg.n;  // call path indices of the segment
+                const long long jlo = a <= r_nrc ? 0 : (a - r_nrc + stride - 1) / stride;
+                const long long jhi = b - 1 < r_nrc ? -1 : (b - 1 - r_nrc) / stride;
+                if (jhi >= jlo) {
+                    NrcRowParams rp{};
+                    rp.n = (int)(jhi - jlo + 1);
+                    rp.j0 = jlo;
+                    rp.r = r_nrc;
+                    rp.stride = stride;
+                    rp.q0 = sg.q0;
+                    rp.pid_off = sg.pid_off;
+                    rp.N_all = N;
+                    rp.WH = sg.j->WH;
+                    rp.s0 = t->sample_offset;
+                    rp.key = make_uint2(t->seed, (uint32_t)t->render_id);
+                    rp.max_depth = D;
+                    rp.nl = c->nl;
+                    rp.nlp = c->nlp;
+                    rp.n_glass = c->n_glass;
+                    rp.n_mats = c->M;
+                    rp.glass_from = sg.j->glass_from;
+                    rp.glass_to = sg.j->glass_to;
+                    rp.vrec = c->vrec;
+                    rp.sh_state = c->sh_state;
+                    rp.sh_glass = c->sh_glass;
+                    rp.pane = c->d_pane;
+                    rp.coat = c->d_coat;
+                    rp.coat_n = c->coat_layers ? c->d_coat_n : nullptr;
+                    rp.coat_layers = c->coat_layers;
+                    rp.rho = c->d_rho;
+                    rp.le = c->d_le;
+                    rp.light_mat = c->light_mat < 0 ? 0 : c->light_mat;
+                    rp.lam_nm = c->d_lam;
+                    rp.tx = c->nrc_tx;
+                    rp.tn = c->nrc_tn;
+                    rp.rows = c->nrc_rows;
+                    rp.row_ok = c->nrc_ok;
+                    HIP_TRY(c, launch_nrc_rows(rp, c->stream));
+                }
+            }
         }
         ++c->batches;
     }
     for (Job& j : jobs) j.rd->spp_done += j.t->spp;
+    if (nrc) return nrc_train_after_call(c, n_slots * (D - 1), timing);
     return SDD_OK;
 }
 
@@ -1186,6 +1403,11 @@ sdd_status trace_call(sdd_ctx* c, int n, const sdd_trace_desc* descs) {
             if (descs[k].render_id == descs[i].render_id)
                 return fail(c, SDD_ERR_INVALID_ARG, "render_id repeated within one call");
     }
+    for (int i = 0; i < n; ++i)
+        if (descs[i].flags & SDD_TRACE_NRC) {
+            if (n != 1) return fail(c, SDD_ERR_UNSUPPORTED, "radiance-cache rendering takes one render per call");
+            if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "SDD_TRACE_NRC before sdd_nrc_init");
+        }
     DeviceGuard g(c->device);
     for (int i = 0; i < n; ++i) {
         sdd_status st = render_for(c, &descs[i], jobs[i].rd);
@@ -1530,6 +1752,9 @@ sdd_status sdd_nrc_init(sdd_ctx* c, const sdd_nrc_desc* d) {
         !(d->beta2 >= 0.0f && d->beta2 < 1.0f) || !(d->eps > 0.0f) || !std::isfinite(d->eps))
         return fail(c, SDD_ERR_INVALID_ARG, "bad Adam hyper-parameters");
     if (!d->params) return fail(c, SDD_ERR_INVALID_ARG, "null parameters");
+    if (d->train_paths < 1 || d->train_steps < 0 || d->train_batch < 1 || d->train_batch > kNrcMaxRows ||
+        (d->precision != 0 && d->precision != 1))
+        return fail(c, SDD_ERR_INVALID_ARG, "bad render settings (train_paths, train_steps, train_batch, precision)");
     const long long n_all = nrc_count(d->table_log2);
     for (long long i = 0; i < n_all; ++i)
         if (!std::isfinite(d->params[i])) return fail(c, SDD_ERR_INVALID_ARG, "non-finite parameter");
@@ -1570,6 +1795,10 @@ sdd_status sdd_nrc_init(sdd_ctx* c, const sdd_nrc_desc* d) {
         free_nrc(c);
         return hip_fail(c, e, "nrc init");
     }
+    c->nrc_train_paths = d->train_paths;
+    c->nrc_train_steps = d->train_steps;
+    c->nrc_train_batch = d->train_batch;
+    c->nrc_precision = d->precision;
     c->nrc_lr = d->lr;
     c->nrc_b1 = d->beta1;
     c->nrc_b2 = d->beta2;
@@ -1618,6 +1847,42 @@ sdd_status sdd_nrc_train_step(sdd_ctx* c, int32_t n, const float* x, const float
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "nrc train step");
+    return SDD_OK;
+}
+
+sdd_status sdd_nrc_query(sdd_ctx* c, int32_t n, const float* x4, const float* n4, float* out, int32_t precision) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_query before sdd_nrc_init");
+    if (!c->has_scene) return fail(c, SDD_ERR_STATE, "sdd_nrc_query before sdd_load_scene (wavelengths)");
+    if (n < 0 || (n > 0 && (!x4 || !n4 || !out))) return fail(c, SDD_ERR_INVALID_ARG, "bad arguments");
+    if (precision != 0 && precision != 1) return fail(c, SDD_ERR_INVALID_ARG, "precision must be 0 or 1");
+    if (n == 0) return SDD_OK;
+    DeviceGuard g(c->device);
+    const hipError_t e = nrc_launch_query(c->nrc, n, reinterpret_cast<const float4*>(x4),
+                                          reinterpret_cast<const float4*>(n4), c->d_lam, c->nl, c->nlp, out, precision,
+                                          c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "nrc query");
+    return SDD_OK;
+}
+
+sdd_status sdd_nrc_last_rows(sdd_ctx* c, int32_t max_rows, float* rows, int32_t* n_rows, int32_t* n_steps,
+                             float* loss) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_last_rows before sdd_nrc_init");
+    if (max_rows < 0 || (max_rows > 0 && !rows)) return fail(c, SDD_ERR_INVALID_ARG, "bad arguments");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (n_rows) *n_rows = (int32_t)c->nrc_last_rows;
+    if (n_steps) *n_steps = c->nrc_last_steps;
+    if (loss) *loss = c->nrc_last_loss;
+    const long long m = std::min<long long>(max_rows, c->nrc_last_rows);
+    if (m > 0) {
+        HIP_TRY(c, hipMemcpyAsync(rows, c->nrc_crows, sizeof(float4) * 2 * (size_t)m, hipMemcpyDeviceToHost,
+                                  c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
     return SDD_OK;
 }
 

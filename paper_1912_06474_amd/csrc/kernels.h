@@ -13,6 +13,8 @@ int trace_blocks_per_cu(int n_cells);  // resident trace workgroups per CU for a
 hipError_t launch_shade(const ShadeParams& p, hipStream_t st);
 hipError_t launch_route(const RouteParams& p, hipStream_t st);
 hipError_t launch_spectral(const SpectralParams& p, hipStream_t st);
+// radiance-cache training rows of the training paths of one batch segment
+hipError_t launch_nrc_rows(const NrcRowParams& p, hipStream_t st);
 hipError_t launch_resolve(int WH, int nl, int nlp, double inv_spp, const float* acc, const double* w,
                           const double* cmf, double* spectral, double* xyz, hipStream_t st);
 hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);

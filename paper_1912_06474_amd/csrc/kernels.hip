@@ -135,7 +135,9 @@ __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
         P.ray_o[pid] = D4{o64.x, o64.y, o64.z, 0.0};
         P.ray_d[pid] = D4{d64.x, d64.y, d64.z, 0.0};
         P.hit[pid] = make_float2(INFINITY, __int_as_float(-1));
-        P.flags[pid] = kAlive | kCountE;
+        uint32_t fl = kAlive | kCountE;
+        if (P.nrc.on && ((uint64_t)(uint32_t)s * (uint64_t)P.WH + (uint64_t)p) % P.nrc.stride == 0) fl |= kTrain;
+        P.flags[pid] = fl;
         cell = locate_ray(P.grid, o, d, t_enter);
         enq = cell >= 0;
     }
@@ -148,6 +150,10 @@ __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
         P.se.qc[pid] = make_int2(-1, __float_as_int(INFINITY));
     }
     if (!valid) P.flags[pid] = 0;
+    if (P.nrc.on) {  // no cache vertex yet (the cache query reads every slot)
+        P.nrc.cx[pid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        P.nrc.cn[pid] = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+    }
     for (int c = threadIdx.x; c < P.n_cells; c += blockDim.x)
         P.se.hist[(long long)c * P.n_blocks + blk] = block_key_total(c, P.n_cells, s_wcnt);
 }
@@ -576,10 +582,26 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                             enq_s = cell_s >= 0;
                         }
                     }
-                    rec = make_int4(kVDiffuse | (last_depth ? kVLast : 0) | emits | (m << kVIdShift), 0, 0,
-                                    __float_as_int(gfac));
+                    // radiance cache: a path other than a training path ends here from depth 2 on
+                    const bool to_cache = P.nrc.on && P.depth >= 2 && !(fl & kTrain);
+                    const bool stop = last_depth || to_cache;
+                    rec = make_int4(kVDiffuse | (stop ? kVLast : 0) | emits | (m << kVIdShift), to_cache ? 1 : 0,
+                                    0, __float_as_int(gfac));
+                    if (P.nrc.on && P.depth >= 2 && (to_cache || !last_depth)) {
+                        const float4 xf = make_float4((float)x.x, (float)x.y, (float)x.z, 1.0f);
+                        const float4 nf = make_float4((float)n.x, (float)n.y, (float)n.z, 0.0f);
+                        if (to_cache) {
+                            P.nrc.cx[pid] = xf;
+                            P.nrc.cn[pid] = nf;
+                        } else {  // a vertex of a training path that continues
+                            const uint64_t qc = (uint64_t)(uint32_t)(s - P.s0) * (uint64_t)P.WH + (uint64_t)p;
+                            const size_t slot = (size_t)(qc / P.nrc.stride) * P.max_depth + (P.depth - 1);
+                            P.nrc.tx[slot] = xf;
+                            P.nrc.tn[slot] = nf;
+                        }
+                    }
                     fl &= ~kCountE;
-                    if (last_depth) {
+                    if (stop) {
                         fl = 0;
                     } else {
                         const uint4 uc =
@@ -815,6 +837,8 @@ __global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
                         }
                         L = f4fma(f4scale(f4mul(beta, leL), gfac), trv, L);
                     }
+                    if (P.lhat && v[j].y == 1)  // the path's cache vertex: beta (after rho) times the cache
+                        L = f4fma(beta, *reinterpret_cast<const float4*>(P.lhat + (size_t)pid * P.nlp + l0), L);
                 } else if ((kind == kVGlassR || kind == kVGlassT) && !(x & kVLast)) {
                     const int gi = min(max(x >> kVIdShift, 0), P.n_glass - 1);
                     const float PR = __int_as_float(v[j].z);
@@ -836,6 +860,80 @@ __global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
         a = make_float4(a.x + L.x, a.y + L.y, a.z + L.z, a.w + L.w);
     }
     *accp = a;
+}
+
+// ---------------------------------------------------------------------------
+// radiance-cache training rows
+// ---------------------------------------------------------------------------
+// One thread per training path.  For each diffuse vertex v of depth >= 2 that
+// continued the path, at one wavelength l drawn for (p, s, depth, 3): the
+// target is the radiance the path carries back into v along its continuation,
+// R(v + 1), where R(k) = Le_k + f_k (N_k + R(k + 1)) over the later records k
+// (f the record's throughput factor -- rho, R / P_R or T / (1 - P_R) -- and N
+// the light sample of a diffuse record), exactly the terms the spectral
+// replay adds for those records.
+template <bool COATED>
+__global__ __launch_bounds__(256) void k_nrc_rows(NrcRowParams P) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const long long j = P.j0 + i;
+    const long long qc = P.r + j * (long long)P.stride;
+    const int pid = P.pid_off + (int)(qc - P.q0);
+    const int s = P.s0 + (int)(qc / P.WH), p = (int)(qc % P.WH);
+    const int D = P.max_depth;
+    bool live = true;
+    for (int v = 0; v < D; ++v) {
+        const int4 rv = live ? P.vrec[(size_t)v * P.N_all + pid] : make_int4(kVNone, 0, 0, 0);
+        const bool on = live && (rv.x & 7) != kVNone;
+        if (v >= 1) {
+            const size_t row = (size_t)j * (D - 1) + (v - 1);
+            const bool ok = on && (rv.x & 7) == kVDiffuse && !(rv.x & kVLast);
+            P.row_ok[row] = ok ? 1 : 0;
+            if (ok) {
+                const uint4 u = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, (uint32_t)(v + 1), 3u), P.key);
+                const int l = (int)(u.x % (uint32_t)P.nl);
+                float R = 0.0f, f = 1.0f;
+                for (int k = v + 1; k < D; ++k) {
+                    const int4 rk = P.vrec[(size_t)k * P.N_all + pid];
+                    const int kind = rk.x & 7;
+                    if (kind == kVNone) break;
+                    const int m = min(max(rk.x >> kVIdShift, 0), P.n_mats - 1);
+                    if (kind == kVEmit) {
+                        R += f * P.le[(size_t)m * P.nlp + l];
+                    } else if (kind == kVDiffuse) {
+                        if (rk.x & kVEmits) R += f * P.le[(size_t)m * P.nlp + l];
+                        f *= P.rho[(size_t)m * P.nlp + l];
+                        const float gfac = __int_as_float(rk.w);
+                        const int shs = P.sh_state[(size_t)k * P.N_all + pid];
+                        if (gfac > 0.0f && (shs & 15) == kShVisible) {
+                            float trv = 1.0f;
+                            const int ng = min(shs >> 4, kMaxGlass);
+                            for (int q = 0; q < ng; ++q) {
+                                const float2 gl = P.sh_glass[((size_t)k * P.N_all + pid) * kMaxGlass + q];
+                                int gi = min(max(__float_as_int(gl.y), 0), P.n_glass - 1);
+                                if (gi == P.glass_from) gi = P.glass_to;
+                                float Rg, Tg;
+                                glass_RT<COATED>(P.pane, P.coat, P.coat_n, P.coat_layers, P.nlp, gi, l, gl.x, Rg, Tg);
+                                trv *= Tg;
+                            }
+                            R += f * P.le[(size_t)P.light_mat * P.nlp + l] * gfac * trv;
+                        }
+                    } else if (!(rk.x & kVLast)) {  // glass, reflected or transmitted
+                        const int gi = min(max(rk.x >> kVIdShift, 0), P.n_glass - 1);
+                        const float PR = __int_as_float(rk.z), c = __int_as_float(rk.y);
+                        float Rl, Tl;
+                        glass_RT<COATED>(P.pane, P.coat, P.coat_n, P.coat_layers, P.nlp, gi, l, c, Rl, Tl);
+                        f *= kind == kVGlassR ? Rl / PR : Tl / (1.0f - PR);
+                    }
+                    if (rk.x & kVLast) break;
+                }
+                const float4 x = P.tx[(size_t)j * D + v], n = P.tn[(size_t)j * D + v];
+                P.rows[2 * row] = make_float4(x.x, x.y, x.z, P.lam_nm[l]);
+                P.rows[2 * row + 1] = make_float4(n.x, n.y, n.z, R);
+            }
+        }
+        live = on && !(rv.x & kVLast);
+    }
 }
 
 // FP64: mean over samples and XYZ = sum_l w_l cmf_l L_l
@@ -961,6 +1059,13 @@ hipError_t launch_spectral(const SpectralParams& p, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (p.coat_n) hipLaunchKernelGGL(k_spectral<true>, dim3(blocks_for(n, 256)), dim3(256), 0, st, p);
     else hipLaunchKernelGGL(k_spectral<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_nrc_rows(const NrcRowParams& p, hipStream_t st) {
+    if (p.n <= 0) return hipSuccess;
+    if (p.coat_n) hipLaunchKernelGGL(k_nrc_rows<true>, dim3(blocks_for(p.n, 256)), dim3(256), 0, st, p);
+    else hipLaunchKernelGGL(k_nrc_rows<false>, dim3(blocks_for(p.n, 256)), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 

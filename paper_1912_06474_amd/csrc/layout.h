@@ -77,7 +77,7 @@ struct alignas(32) D4 {
 };
 
 enum : int { kDiffuse = 0, kGlass = 1, kEmitter = 2 };
-enum : uint32_t { kAlive = 1u, kCountE = 2u };
+enum : uint32_t { kAlive = 1u, kCountE = 2u, kTrain = 4u };
 enum : int { kShNone = 0, kShVisible = 1, kShBlocked = 2 };  // | pane count << 4 when visible
 constexpr int kLastInLeaf = 4;
 constexpr int kEmptyLink = 0x7fffffff;  // child slot without a subtree
@@ -150,6 +150,18 @@ struct TraceParams {
     unsigned long long* stats;
 };
 
+// Radiance-cache rendering.  Training paths ((s * WH + p) % stride == 0,
+// s the absolute sample index) are traced in full; every other path ends at
+// its first diffuse vertex of depth >= 2, where the cache value is added.
+struct NrcPaths {
+    int on;
+    uint32_t stride;
+    float4* cx;  // [N_all] cache vertex position (w = 1 once set)
+    float4* cn;  // [N_all] its geometric normal, on the side the ray arrived from
+    float4* tx;  // [slots][D] vertices of training paths (position)
+    float4* tn;  // [slots][D] (normal)
+};
+
 struct ShadeParams {
     int N;                 // paths of this render segment
     int pid_off;           // its first path in the batch (a multiple of kShadeBlock)
@@ -187,6 +199,7 @@ struct ShadeParams {
     int n_blocks;          // histogram stride (blocks per batch)
     int* hit_log;
     unsigned long long* stats;
+    NrcPaths nrc;
 };
 
 struct CamParams {
@@ -209,6 +222,7 @@ struct CamParams {
     Stage se;
     int n_blocks;
     unsigned long long* stats;
+    NrcPaths nrc;
 };
 
 // scan of the block histograms and scatter of staged rays into the queues
@@ -264,6 +278,38 @@ struct SpectralParams {
     int light_mat;
     float* acc;            // [WH][nlp]
     int* shadow_log;
+    const float* lhat;     // [N_all][nlp] cache values at the paths' cache vertices, or null
+};
+
+// training rows of the radiance cache from the training paths of one batch
+// segment: one row per diffuse vertex of depth >= 2 that continued the path
+struct NrcRowParams {
+    int n;                 // training paths in the segment
+    long long j0;          // first training slot (call-wide numbering)
+    long long r;           // call path index of slot j: r + j * stride
+    uint32_t stride;
+    long long q0;          // call path index of the segment's first path
+    int pid_off;           // batch position of that path
+    int N_all;
+    int WH, s0;
+    uint2 key;
+    int max_depth, nl, nlp, n_glass, n_mats;
+    int glass_from, glass_to;
+    const int4* vrec;
+    const int* sh_state;
+    const float2* sh_glass;
+    const float4* pane;
+    const float4* coat;
+    const int* coat_n;
+    int coat_layers;
+    const float* rho;
+    const float* le;
+    int light_mat;
+    const float* lam_nm;   // [nl]
+    const float4* tx;      // [slots][D]
+    const float4* tn;
+    float4* rows;          // [slots][D - 1][2]: (x, lambda nm), (n, target)
+    int* row_ok;           // [slots][D - 1]
 };
 
 }  // namespace sdd

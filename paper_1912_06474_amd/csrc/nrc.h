@@ -64,6 +64,17 @@ hipError_t nrc_launch_infer(const NrcNet& net, int n, const float* x, const floa
 // BF16 matrix-core forward (FP32 accumulation); needs net.wq packed from the current weights
 hipError_t nrc_launch_infer_mfma(const NrcNet& net, int n, const float* x, const float* w, const float* lam,
                                  float* y, hipStream_t st);
+// cache values of n paths at nl wavelengths: lhat[path * nlp + l] for the
+// cache vertex (cx, cn) of each path (precision 0: FP32, 1: BF16 matrix cores)
+hipError_t nrc_launch_query(const NrcNet& net, int n, const float4* cx, const float4* cn, const float* lam, int nl,
+                            int nlp, float* lhat, int precision, hipStream_t st);
+// stable compaction of the training rows (pairs of float4) whose flag is set;
+// with temp == nullptr only sets *temp_bytes
+hipError_t nrc_select_rows(const float4* rows, const int* ok, int n, float4* out, int* d_count, void* temp,
+                           size_t* temp_bytes, hipStream_t st);
+// training batch k of S (rows k, k + S, ...) of the compacted rows into SoA arrays
+hipError_t nrc_launch_unpack(const float4* rows, int k, int S, int n, float* x, float* w, float* lam, float* t,
+                             hipStream_t st);
 // BF16 operand-order copy of the hidden weights into net.wq
 hipError_t nrc_launch_pack(const NrcNet& net, hipStream_t st);
 // forward, loss, backward, gradient reduction (gradients are accumulated in net.g)

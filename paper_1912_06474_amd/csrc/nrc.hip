@@ -16,6 +16,8 @@
 // (Mueller et al. 2021).  Optimiser: Adam (Kingma and Ba 2015).
 #include <hip/hip_runtime.h>
 
+#include <hipcub/hipcub.hpp>
+
 #include <cmath>
 
 #include "nrc.h"
@@ -363,70 +365,54 @@ __device__ __forceinline__ bf16x8 relu_pack8(f32x4 a, f32x4 b) {
 constexpr int kMfmaBlock = 256;
 constexpr int kMfmaRowsPerWave = 64;
 
-__global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, const float* x, const float* w,
-                                                          const float* lam, float* y) {
-    __shared__ bf16x8 s_w[kNrcFrags];
-    __shared__ __align__(16) float s_b[kNrcLayers * kNrcHid];
-    __shared__ float s_wo[kNrcHid];
-    __shared__ int s_res[kNrcLevels], s_dense[kNrcLevels];
-    __shared__ bf16x8 s_in[kMfmaBlock / 64][4][2][64];
+// LDS of a matrix-core block: the BF16 weight fragments, biases, output
+// weights, level table, and per-lane parking slots for the input operands
+struct MfmaLds {
+    bf16x8 w[kNrcFrags];
+    __align__(16) float b[kNrcLayers * kNrcHid];
+    float wo[kNrcHid];
+    int res[kNrcLevels], dense[kNrcLevels];
+    bf16x8 in[kMfmaBlock / 64][4][2][64];
+};
+
+__device__ __forceinline__ void mfma_stage(const NrcNet& net, MfmaLds& L) {
     const bf16x8* wq = reinterpret_cast<const bf16x8*>(net.wq);
-    for (int e = threadIdx.x; e < kNrcFrags; e += kMfmaBlock) s_w[e] = wq[e];
-    for (int e = threadIdx.x; e < kNrcLayers * kNrcHid; e += kMfmaBlock) s_b[e] = net.p[net.off_b() + e];
-    if (threadIdx.x < kNrcHid) s_wo[threadIdx.x] = net.p[net.off_wo() + threadIdx.x];
+    for (int e = threadIdx.x; e < kNrcFrags; e += kMfmaBlock) L.w[e] = wq[e];
+    for (int e = threadIdx.x; e < kNrcLayers * kNrcHid; e += kMfmaBlock) L.b[e] = net.p[net.off_b() + e];
+    if (threadIdx.x < kNrcHid) L.wo[threadIdx.x] = net.p[net.off_wo() + threadIdx.x];
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int l = 0; l < kNrcLevels; ++l) {  // static indexes: kernel arguments stay out of scratch
-            s_res[l] = net.res[l];
-            s_dense[l] = net.dense[l];
+            L.res[l] = net.res[l];
+            L.dense[l] = net.dense[l];
         }
     }
     __syncthreads();
+}
 
-    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
-    const long long base = ((long long)blockIdx.x * (kMfmaBlock / 64) + (threadIdx.x >> 6)) * kMfmaRowsPerWave;
-    if (base >= n) return;  // whole wave idle (no barrier follows)
-
-    // features, one column tile at a time (a rolled loop bounds the live
-    // gathers); each lane parks its operands in its own LDS slots
-#pragma unroll 1
-    for (int nt = 0; nt < 4; ++nt) {
-        const long long row = min(base + nt * 16 + c, (long long)n - 1);
-        float xn[3];
-        normalise(net, x + 3 * row, xn);
-        bf16x8 v0, v1;
+// step-0 operand of one row: hash levels 2g, 2g+1, 8+2g, 9+2g
+__device__ __forceinline__ bf16x8 mfma_hash_operand(const NrcNet& net, const MfmaLds& L, int g, const float xn[3]) {
+    bf16x8 v;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int l = (q < 2 ? 0 : 8) + 2 * g + (q & 1);
-            const float2 e = hash_level(net, l, s_res[l], s_dense[l], xn);
-            v0[2 * q] = (__bf16)e.x;
-            v0[2 * q + 1] = (__bf16)e.y;
-        }
-        float sh[kNrcSh];
-        sh_features(net.shK, w[3 * row], w[3 * row + 1], w[3 * row + 2], sh);
-        const float lm = lam[row];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            v1[j] = (__bf16)pick4(sh, g, j);
-            v1[4 + j] = (__bf16)blob_bin(net, lm, 4 * g + j);
-        }
-        s_in[wv][nt][0][lane] = v0;
-        s_in[wv][nt][1][lane] = v1;
+    for (int q = 0; q < 4; ++q) {
+        const int l = (q < 2 ? 0 : 8) + 2 * g + (q & 1);
+        const float2 e = hash_level(net, l, L.res[l], L.dense[l], xn);
+        v[2 * q] = (__bf16)e.x;
+        v[2 * q + 1] = (__bf16)e.y;
     }
-    bf16x8 b0[4], b1[4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        b0[nt] = s_in[wv][nt][0][lane];
-        b1[nt] = s_in[wv][nt][1][lane];
-    }
+    return v;
+}
 
-    f32x4 acc[4][4];
-    for (int k = 0; k < kNrcLayers; ++k) {
+// hidden layers k_begin..4; b0, b1 hold the inputs of layer k_begin, acc gets
+// the pre-activations of the last layer
+__device__ __forceinline__ void mfma_layers(const MfmaLds& L, int lane, int g, bf16x8 (&b0)[4], bf16x8 (&b1)[4],
+                                            f32x4 (&acc)[4][4], int k_begin) {
+    for (int k = k_begin; k < kNrcLayers; ++k) {
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
-            const f32x4 bias = *reinterpret_cast<const f32x4*>(&s_b[k * kNrcHid + 16 * mt + 4 * g]);
-            const bf16x8 a0 = s_w[((k * 4 + mt) * 2 + 0) * 64 + lane];
-            const bf16x8 a1 = s_w[((k * 4 + mt) * 2 + 1) * 64 + lane];
+            const f32x4 bias = *reinterpret_cast<const f32x4*>(&L.b[k * kNrcHid + 16 * mt + 4 * g]);
+            const bf16x8 a0 = L.w[((k * 4 + mt) * 2 + 0) * 64 + lane];
+            const bf16x8 a1 = L.w[((k * 4 + mt) * 2 + 1) * 64 + lane];
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
                 acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0[nt], bias, 0, 0, 0);
@@ -441,20 +427,158 @@ __global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, co
             }
         }
     }
+}
+
+// output of column tile nt (FP32 dot product over the 64 ReLU outputs, reduced over the 4 lane groups)
+__device__ __forceinline__ float mfma_output(const MfmaLds& L, int g, const f32x4 (&acc)[4][4], int nt) {
+    float s = 0.0f;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s = fmaf(L.wo[16 * mt + 4 * g + i], fmaxf(acc[nt][mt][i], 0.0f), s);
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return s;
+}
+
+__global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, const float* x, const float* w,
+                                                          const float* lam, float* y) {
+    __shared__ MfmaLds L;
+    mfma_stage(net, L);
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
+    const long long base = ((long long)blockIdx.x * (kMfmaBlock / 64) + wv) * kMfmaRowsPerWave;
+    if (base >= n) return;  // whole wave idle (no barrier follows)
+    // features, one column tile at a time (a rolled loop bounds the live
+    // gathers); each lane parks its operands in its own LDS slots
+#pragma unroll 1
+    for (int nt = 0; nt < 4; ++nt) {
+        const long long row = min(base + nt * 16 + c, (long long)n - 1);
+        float xn[3];
+        normalise(net, x + 3 * row, xn);
+        const bf16x8 v0 = mfma_hash_operand(net, L, g, xn);
+        float sh[kNrcSh];
+        sh_features(net.shK, w[3 * row], w[3 * row + 1], w[3 * row + 2], sh);
+        const float lm = lam[row];
+        bf16x8 v1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v1[j] = (__bf16)pick4(sh, g, j);
+            v1[4 + j] = (__bf16)blob_bin(net, lm, 4 * g + j);
+        }
+        L.in[wv][nt][0][lane] = v0;
+        L.in[wv][nt][1][lane] = v1;
+    }
+    bf16x8 b0[4], b1[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        b0[nt] = L.in[wv][nt][0][lane];
+        b1[nt] = L.in[wv][nt][1][lane];
+    }
+    f32x4 acc[4][4];
+    mfma_layers(L, lane, g, b0, b1, acc, 0);
     const float bo = net.p[net.off_bo()];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        float s = 0.0f;
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) s = fmaf(s_wo[16 * mt + 4 * g + i], fmaxf(acc[nt][mt][i], 0.0f), s);
-        s += __shfl_xor(s, 16);
-        s += __shfl_xor(s, 32);
+        const float s = mfma_output(L, g, acc, nt);
         const long long row = base + nt * 16 + c;
         if (g == 0 && row < n) y[row] = s + bo;
     }
 }
+
+// Cache values of n paths at every wavelength: lhat[path][l].  The hash and
+// harmonic operands of a path are formed once (the 128 table gathers) and
+// parked in LDS; per wavelength only the one-blob slots change.  Same
+// products and summation order as k_infer_mfma.
+__global__ __launch_bounds__(kMfmaBlock) void k_query_mfma(NrcNet net, int n, const float4* cx, const float4* cn,
+                                                          const float* lam, int nl, int nlp, float* lhat) {
+    __shared__ MfmaLds L;
+    mfma_stage(net, L);
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
+    const long long base = ((long long)blockIdx.x * (kMfmaBlock / 64) + wv) * kMfmaRowsPerWave;
+    if (base >= n) return;  // whole wave idle (no barrier follows)
+#pragma unroll 1
+    for (int nt = 0; nt < 4; ++nt) {
+        const long long row = min(base + nt * 16 + c, (long long)n - 1);
+        const float4 x4 = cx[row], n4 = cn[row];
+        const float xp[3] = {x4.x, x4.y, x4.z};
+        float xn[3];
+        normalise(net, xp, xn);
+        const bf16x8 v0 = mfma_hash_operand(net, L, g, xn);
+        float sh[kNrcSh];
+        sh_features(net.shK, n4.x, n4.y, n4.z, sh);
+        bf16x8 v1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v1[j] = (__bf16)pick4(sh, g, j);
+            v1[4 + j] = (__bf16)0.0f;
+        }
+        L.in[wv][nt][0][lane] = v0;
+        L.in[wv][nt][1][lane] = v1;
+    }
+    const float bo = net.p[net.off_bo()];
+    for (int l = 0; l < nl; ++l) {
+        // keeps the weight fragments' LDS reads inside the loop (hoisted out of
+        // it they would hold 160 registers)
+        asm volatile("" ::: "memory");
+        const float lm = lam[l];
+        bf16x8 b0[4], b1[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            b0[nt] = L.in[wv][nt][0][lane];
+            b1[nt] = L.in[wv][nt][1][lane];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b1[nt][4 + j] = (__bf16)blob_bin(net, lm, 4 * g + j);
+        }
+        f32x4 acc[4][4];
+        mfma_layers(L, lane, g, b0, b1, acc, 0);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const float s = mfma_output(L, g, acc, nt);
+            const long long row = base + nt * 16 + c;
+            if (g == 0 && row < n) lhat[row * nlp + l] = s + bo;
+        }
+    }
+}
+
+// FP32 cache values, one thread per (path, wavelength), as k_infer
+__global__ __launch_bounds__(256) void k_query(NrcNet net, int n, const float4* cx, const float4* cn, const float* lam,
+                                               int nl, int nlp, float* lhat) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)n * nl) return;
+    const int path = (int)(t / nl), l = (int)(t - (long long)path * nl);
+    const float4 x4 = cx[path], n4 = cn[path];
+    const float xp[3] = {x4.x, x4.y, x4.z}, wp[3] = {n4.x, n4.y, n4.z};
+    float h[kNrcHid], g[kNrcHid];
+    features(net, xp, wp, lam[l], h);
+    const float* W = net.p + net.off_W();
+    const float* b = net.p + net.off_b();
+    for (int k = 0; k < kNrcLayers; ++k) {
+        layer(W + k * kNrcHid * kNrcHid, b + k * kNrcHid, h, g);
+#pragma unroll
+        for (int j = 0; j < kNrcHid; ++j) h[j] = g[j];
+    }
+    lhat[(size_t)path * nlp + l] = output(net, h);
+}
+
+// training batch k of S: rows k, k + S, k + 2S, ... of the compacted rows, into SoA
+__global__ void k_unpack(const float4* rows, int k, int S, int n, float* x, float* w, float* lam, float* t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t src = (size_t)k + (size_t)i * S;
+    const float4 a = rows[2 * src], b = rows[2 * src + 1];
+    x[3 * (size_t)i] = a.x;
+    x[3 * (size_t)i + 1] = a.y;
+    x[3 * (size_t)i + 2] = a.z;
+    lam[i] = a.w;
+    w[3 * (size_t)i] = b.x;
+    w[3 * (size_t)i + 1] = b.y;
+    w[3 * (size_t)i + 2] = b.z;
+    t[i] = b.w;
+}
+
+struct NrcRow {
+    float4 a, b;
+};
 
 // hidden weights -> BF16 operand order: fragment e = ((k * 4 + mt) * 2 + s) * 64 + lane
 __global__ void k_pack(NrcNet net) {
@@ -487,6 +611,33 @@ hipError_t nrc_launch_infer_mfma(const NrcNet& net, int n, const float* x, const
     const int rows_per_block = (kMfmaBlock / 64) * kMfmaRowsPerWave;
     hipLaunchKernelGGL(k_infer_mfma, dim3(nblocks(n, rows_per_block)), dim3(kMfmaBlock), 0, st, net, n, x, w, lam,
                        y);
+    return hipGetLastError();
+}
+
+hipError_t nrc_launch_query(const NrcNet& net, int n, const float4* cx, const float4* cn, const float* lam, int nl,
+                            int nlp, float* lhat, int precision, hipStream_t st) {
+    if (n <= 0 || nl <= 0) return hipSuccess;
+    if (precision == 0) {
+        hipLaunchKernelGGL(k_query, dim3(nblocks((long long)n * nl, 256)), dim3(256), 0, st, net, n, cx, cn, lam, nl,
+                           nlp, lhat);
+    } else {
+        const int rows_per_block = (kMfmaBlock / 64) * kMfmaRowsPerWave;
+        hipLaunchKernelGGL(k_query_mfma, dim3(nblocks(n, rows_per_block)), dim3(kMfmaBlock), 0, st, net, n, cx, cn,
+                           lam, nl, nlp, lhat);
+    }
+    return hipGetLastError();
+}
+
+hipError_t nrc_select_rows(const float4* rows, const int* ok, int n, float4* out, int* d_count, void* temp,
+                           size_t* temp_bytes, hipStream_t st) {
+    return hipcub::DeviceSelect::Flagged(temp, *temp_bytes, reinterpret_cast<const NrcRow*>(rows), ok,
+                                         reinterpret_cast<NrcRow*>(out), d_count, n, st);
+}
+
+hipError_t nrc_launch_unpack(const float4* rows, int k, int S, int n, float* x, float* w, float* lam, float* t,
+                             hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpack, dim3(nblocks(n, 256)), dim3(256), 0, st, rows, k, S, n, x, w, lam, t);
     return hipGetLastError();
 }
 

@@ -1,0 +1,176 @@
+"""Rendering with the radiance cache (SDD_TRACE_NRC) against the FP64
+oracle's cache estimator.
+
+The cache under test is a network built to evaluate a closed form,
+L(x, n) = c0 + c[1:4] . xn + c[4:7] . n: hash level 0 (direct indexing,
+resolution 16) holds the affine field c[1:4] . (i, j, k) / 16, which
+trilinear interpolation reproduces exactly; the harmonics Y_1^-1, Y_1^0,
+Y_1^1 of the normal are K (n_y, n_z, n_x) with K = sqrt(3 / 4 pi); hidden
+unit 0 carries their sum plus an offset through the five ReLU layers.  Its
+FP32 evaluation then differs from the closed form by FP32 rounding only, so
+the render with FP32 cache queries meets the plain tracer's parity bar
+against the oracle (which evaluates the closed form in FP64): identical hit
+and shadow logs, per-pixel radiance within 1e-4, and training rows (position,
+normal, wavelength, target) equal in order, targets within 1e-4.  The
+cache-query kernels are pinned to the already pinned forward kernels: FP32
+and BF16 queries equal sdd_nrc_infer on the same rows bit for bit."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as ora
+import scenegen as sg
+from parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+LO, HI = (0.0, 0.0, 0.0), (4.0, 3.0, 2.5)
+COEF = (0.12, 0.05, -0.03, 0.04, 0.02, -0.01, 0.03)
+
+
+@pytest.fixture(scope="module")
+def tracer():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1912_06474_amd as m
+    return m.Tracer()
+
+
+def affine_net(c, log2=13, offset=4.0):  # 2^13 >= 17^3: level 0 indexed directly
+    params, tables = sg.nrc_params(0, table_size=1 << log2)
+    tables = np.zeros_like(tables)
+    N = 16
+    i, j, k = np.meshgrid(np.arange(N + 1), np.arange(N + 1), np.arange(N + 1), indexing="ij")
+    idx = (i + (N + 1) * j + (N + 1) ** 2 * k).ravel()
+    tables[0, idx, 0] = ((c[1] * i + c[2] * j + c[3] * k) / N).ravel()
+    K = math.sqrt(3.0 / (4.0 * math.pi))
+    W = [np.zeros((64, 64), np.float32) for _ in range(5)]
+    b = [np.zeros(64, np.float32) for _ in range(5)]
+    W[0][0, 0] = 1.0
+    W[0][0, 32 + 1] = c[5] / K  # Y_1^-1 = K n_y
+    W[0][0, 32 + 2] = c[6] / K  # Y_1^0 = K n_z
+    W[0][0, 32 + 3] = c[4] / K  # Y_1^1 = K n_x
+    b[0][0] = offset
+    for q in range(1, 5):
+        W[q][0, 0] = 1.0
+    wo = np.zeros(64, np.float32)
+    wo[0] = 1.0
+    return dict(W=W, b=b, wo=wo, bo=np.float32(c[0] - offset)), tables
+
+
+def closed_form(c, x, n):
+    xn = np.clip((np.asarray(x, np.float64) - LO) / (np.asarray(HI) - np.asarray(LO)), 0.0, 1.0)
+    return c[0] + xn @ np.asarray(c[1:4]) + np.asarray(n, np.float64) @ np.asarray(c[4:7])
+
+
+def test_affine_network_is_the_closed_form(tracer):
+    params, tables = affine_net(COEF)
+    tracer.nrc_init(params, tables, LO, HI)
+    x, w, lam, _ = sg.nrc_rows(5000, 3, LO, HI)
+    y = tracer.nrc_infer(x, w, lam, "fp32").cpu().numpy()
+    ref = closed_form(COEF, x, w)
+    err = np.abs(y - ref).max()
+    print(f"[nrc_render] affine cache: max abs err {err:.2e}", flush=True)
+    assert err <= 2e-6
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_query_equals_infer(tracer, precision):
+    """The render's per-path, all-wavelength query equals the row forward bit for bit."""
+    sc = sg.tiny_room(0, 16)
+    tracer.load_scene(sc)
+    params, tables = sg.nrc_params(3, table_size=1 << 14)
+    tables = np.random.default_rng(4).uniform(-0.5, 0.5, tables.shape).astype(np.float32)
+    tracer.nrc_init(params, tables, LO, HI)
+    n = 1000
+    x, w, _, _ = sg.nrc_rows(n, 5, LO, HI)
+    q = tracer.nrc_query(x, w, precision).cpu().numpy()
+    lam = np.asarray(sc["lambda_nm"], np.float32)
+    nl = len(lam)
+    X = np.repeat(x, nl, axis=0)
+    Wd = np.repeat(w, nl, axis=0)
+    L = np.tile(lam, n)
+    y = tracer.nrc_infer(X, Wd, L, precision).cpu().numpy().reshape(n, nl)
+    assert np.array_equal(q[:, :nl], y)
+
+
+def _gpu_nrc_render(tracer, sc, W, H, spp, D, grid, train_paths, precision="fp32", seed=0, steps=0,
+                    sample_offset=0):
+    tracer.load_scene(sc)
+    tracer.build_bvh(*grid)
+    params, tables = affine_net(COEF)
+    tracer.nrc_init(params, tables, LO, HI, train_paths=train_paths, train_steps=steps, precision=precision)
+    hl = tracer.new_log(W, H, spp, D)
+    sl = tracer.new_log(W, H, spp, D)
+    tracer.trace_spectral(sc["camera"], W, H, spp, D, seed=seed, render_id=0, sample_offset=sample_offset,
+                          hit_log=hl, shadow_log=sl, nrc=True)
+    s, x = tracer.resolve_image(0, W, H)
+    tracer.reset_render(0)
+    rows, nsteps, loss = tracer.nrc_last_rows()
+    return dict(spectral=s.cpu().numpy(), xyz=x.cpu().numpy(), hit_log=hl.cpu().numpy(),
+                shadow_log=sl.cpu().numpy()), rows, nsteps, loss
+
+
+def _oracle_rows(o, W, H, spp):
+    """Valid oracle rows in the library's order: path index (s - s0) W H + p, then depth."""
+    r = o["nrc_rows"]  # [WH][spp][D-1][9]
+    r = np.transpose(r, (1, 0, 2, 3)).reshape(-1, 9)
+    return r[r[:, 0] == 1.0]
+
+
+@pytest.mark.parametrize("case", [
+    dict(name="tiny_room", W=64, H=64, spp=2, D=5, grid=(2, 2, 1), train_paths=1000, sample_offset=0),
+    dict(name="tiny_room", W=48, H=40, spp=3, D=6, grid=(1, 1, 1), train_paths=500, sample_offset=7),
+])
+def test_cache_render_matches_oracle(tracer, case):
+    sc = sg.tiny_room(0, 16)
+    W, H, spp, D = case["W"], case["H"], case["spp"], case["D"]
+    print(f"[nrc_render] {case}", flush=True)
+    g, rows, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, case["grid"], case["train_paths"],
+                                    sample_offset=case["sample_offset"])
+    stride = -(-(W * H * spp) // case["train_paths"])
+    o = ora.render(sc, W, H, spp, D, logs=True, seed=0, sample_offset=case["sample_offset"],
+                   nrc=dict(stride=stride, c=COEF, lo=LO, hi=HI))
+    assert_parity(g, o)
+    orows = _oracle_rows(o, W, H, spp)
+    print(f"[nrc_render] stride {stride}: {len(rows)} training rows (oracle {len(orows)})", flush=True)
+    assert len(rows) == len(orows) and len(rows) > 0
+    assert np.array_equal(rows[:, 3], orows[:, 4].astype(np.float32))          # wavelength
+    assert np.abs(rows[:, 0:3] - orows[:, 1:4]).max() <= 1e-5                   # position
+    assert np.abs(rows[:, 4:7] - orows[:, 5:8]).max() <= 1e-6                   # normal
+    t, to = rows[:, 7].astype(np.float64), orows[:, 8]
+    err = np.abs(t - to) / (np.abs(to) + 1e-6)
+    print(f"[nrc_render] targets: {np.mean(to > 0):.3f} nonzero, max rel err {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-4
+
+
+def test_every_path_training_is_the_plain_render(tracer):
+    """train_paths >= W H spp makes every path a training path: the plain estimator."""
+    sc = sg.tiny_room(0, 16)
+    W, H, spp, D = 32, 32, 2, 5
+    g, rows, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), W * H * spp)
+    tracer.trace_spectral(sc["camera"], W, H, spp, D, seed=0, render_id=0)
+    s, _ = tracer.resolve_image(0, W, H)
+    tracer.reset_render(0)
+    assert np.array_equal(g["spectral"], s.cpu().numpy())
+
+
+def test_bf16_queries_and_training_in_the_render(tracer):
+    """BF16 cache queries inside the render, and the Adam steps after it."""
+    sc = sg.tiny_room(0, 16)
+    W, H, spp, D = 64, 64, 2, 5
+    g16, rows, steps, loss = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), 2000, precision="bf16", steps=3)
+    p1, t1 = tracer.nrc_get("params")
+    params, tables = affine_net(COEF)
+    g32, _, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), 2000, precision="fp32")
+    assert np.array_equal(g16["hit_log"], g32["hit_log"])
+    # the BF16 cache moves each cache term by at most a few BF16 ulps of the
+    # hidden unit (offset 4: ulp 2^-5) -- bounded by 0.1 of the throughput
+    diff = np.abs(g16["spectral"] - g32["spectral"]).max()
+    print(f"[nrc_render] bf16 vs fp32 queries: max |dL| {diff:.3e}; {len(rows)} rows, {steps} steps, "
+          f"loss {loss:.4f}", flush=True)
+    assert diff <= 0.1
+    assert steps == 3 and np.isfinite(loss) and len(rows) > 0
+    assert not np.array_equal(t1, tables)  # the tables moved
