@@ -362,8 +362,8 @@ sdd_status sdd_nrc_train_step(sdd_ctx *ctx, int32_t n, const float *x, const flo
  * row at one wavelength l drawn from Philox counter (p, s, depth, 3) (l =
  * word 0 mod n_lambda): target the radiance the path carries back into the
  * vertex along its continuation, at l, the same terms the estimator adds.
- * After the call, train_steps Adam steps run on the call's rows (step k of S
- * on rows k, k + S, ...).  Gradient sums use atomics, so trained caches
+ * After the call, S = train_steps Adam steps run on the call's rows: step k
+ * on rows (k + i S) m, i < train_batch, m = max(1, rows / (S train_batch)).  Gradient sums use atomics, so trained caches
  * differ between runs by rounding.
  */
 

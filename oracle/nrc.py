@@ -18,7 +18,7 @@ written from the definitions:
 * one-blob encoding of the wavelength: u = (lambda - lam_lo) / (lam_hi -
   lam_lo), 16 Gaussian bins exp(-(16 u - (i + 0.5))^2 / 2);
 * a multilayer perceptron 64 -> 64 (ReLU) x 5 hidden layers -> 1 (linear)
-  (also as BF16 matrix units evaluate it: hidden-layer operands rounded to
+  (also as BF16 matrix units evaluate it: every layer's operands rounded to
   bfloat16, round to nearest even),
   its backward pass, the relative L2 loss (y - t)^2 / (sg(y)^2 + 0.01) with
   the prediction's magnitude held constant (Mueller, Rousselle, Novak,
@@ -157,13 +157,14 @@ def bf16_round(a):
 
 
 def mlp_forward_bf16(params, X):
-    """The forward pass as BF16 matrix units evaluate it: each hidden layer's
-    operands (inputs and weights) rounded to bfloat16, products summed exactly
-    (here in float64) onto the bias, ReLU; the output layer unrounded."""
+    """The forward pass as BF16 matrix units evaluate it: every layer's
+    operands (inputs and weights, the output layer's included) rounded to
+    bfloat16, products summed exactly (here in float64) onto the bias, ReLU
+    between layers."""
     h = np.asarray(X, np.float64)
     for k in range(N_LAYERS):
         h = np.maximum(0.0, bf16_round(h) @ bf16_round(params["W"][k]).T + params["b"][k])
-    return h @ params["wo"] + params["bo"]
+    return bf16_round(h) @ bf16_round(params["wo"]) + params["bo"]
 
 
 def rel_l2_loss(y, t, eps=0.01):

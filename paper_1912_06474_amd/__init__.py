@@ -340,7 +340,7 @@ class Tracer:
 
     # ---- learned radiance cache -------------------------------------------------
     def nrc_init(self, params, tables, aabb_lo, aabb_hi, lambda_range=(380.0, 780.0), lr=1e-2, betas=(0.9, 0.99),
-                 eps=1e-8, train_paths=1 << 16, train_steps=4, train_batch=1 << 16, precision="bf16"):
+                 eps=1e-8, train_paths=1 << 16, train_steps=4, train_batch=1 << 14, precision="bf16"):
         """Create the cache from a parameter dict (W [5][64][64], b [5][64], wo [64], bo) and hash
         tables [16][T][2] (T a power of two); the last four settings apply to renders with nrc=True."""
         T = int(np.asarray(tables).shape[1])

@@ -15,6 +15,8 @@ SOURCES = ["api.cpp", "bvh_build.cpp", "kernels.hip", "bvh_device.hip", "nrc.hip
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+            # matrix-core results in ordinary VGPRs (no copies out of accumulation registers)
+            "-mllvm", "-amdgpu-mfma-vgpr-form=1",
             "-Wall", "-Wno-unused-result"]
 
 

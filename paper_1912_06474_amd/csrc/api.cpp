@@ -1013,8 +1013,8 @@ sdd_status nrc_ensure_render(sdd_ctx* c, long long n, long long slots, int D) {
 }
 
 // After a cache render: compact the training rows the call produced and take
-// up to train_steps Adam steps, step k on rows k, k + S, k + 2S, ... (S steps;
-// at most train_batch rows each), spread over the image.
+// up to train_steps Adam steps (S), step k on rows (k + i S) m, i < train_batch,
+// with m = max(1, rows / (S train_batch)): spread over the whole image.
 sdd_status nrc_train_after_call(sdd_ctx* c, long long n_rows, bool timing) {
     c->nrc_last_rows = 0;
     c->nrc_last_steps = 0;
@@ -1032,13 +1032,18 @@ sdd_status nrc_train_after_call(sdd_ctx* c, long long n_rows, bool timing) {
     c->nrc_last_rows = count;
     if (count <= 0) return SDD_OK;
     const int S = std::min(c->nrc_train_steps, count);
+    if (S <= 0) return SDD_OK;
     sdd_status st = nrc_reserve(c, c->nrc_train_batch);
     if (st != SDD_OK) return st;
+    // more rows than S steps take: every m-th row (spread over the whole image)
+    const long long used = (long long)S * c->nrc_train_batch;
+    const int m = count > used ? (int)(count / used) : 1;
     double loss_sum = 0.0;
     for (int k = 0; k < S; ++k) {
-        const int nk = (int)std::min<long long>(c->nrc_train_batch, (count - k + S - 1) / S);
+        const int nk = (int)std::min<long long>(c->nrc_train_batch, ((long long)count / m - k + S - 1) / S);
         Timer tm(c, timing, 3);
-        HIP_TRY(c, nrc_launch_unpack(c->nrc_crows, k, S, nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt, c->stream));
+        HIP_TRY(c, nrc_launch_unpack(c->nrc_crows, k, S, m, nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt,
+                                     c->stream));
         NrcBatch b{nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt, c->nrc_acts, c->nrc_dz, c->nrc_y, c->nrc_dy,
                    c->nrc_loss};
         HIP_TRY(c, nrc_launch_zero(c->nrc.g, c->nrc.n_all, c->stream));
@@ -1782,7 +1787,7 @@ sdd_status sdd_nrc_init(sdd_ctx* c, const sdd_nrc_desc* d) {
     sdd_status st;
     if ((st = upload(c, &net.p, d->params, (size_t)n_all)) != SDD_OK || (st = dalloc(c, &net.g, (size_t)n_all)) != SDD_OK ||
         (st = dalloc(c, &net.m, (size_t)n_all)) != SDD_OK || (st = dalloc(c, &net.v, (size_t)n_all)) != SDD_OK ||
-        (st = dalloc(c, &net.wq, (size_t)kNrcFrags * 8)) != SDD_OK || (st = dalloc(c, &c->nrc_loss, 1)) != SDD_OK) {
+        (st = dalloc(c, &net.wq, (size_t)kNrcFragsAll * 8)) != SDD_OK || (st = dalloc(c, &c->nrc_loss, 1)) != SDD_OK) {
         free_nrc(c);
         return st;
     }

@@ -20,8 +20,10 @@ constexpr int kNrcIn = 64;
 constexpr int kNrcHid = 64;
 constexpr int kNrcLayers = 5;
 constexpr int kNrcW = kNrcLayers * kNrcHid * kNrcHid;  // hidden weights (out, in)
-// BF16 weights in matrix-core operand order: [layer][out tile 4][k step 2][lane 64] x 8 values
+// BF16 weights in matrix-core operand order: [layer][out tile 4][k step 2][lane 64] x 8 values,
+// then the output layer as one 16-row tile (row 0 = wo, rows 1..15 zero): [k step 2][lane 64] x 8
 constexpr int kNrcFrags = kNrcLayers * 4 * 2 * 64;
+constexpr int kNrcFragsAll = kNrcFrags + 2 * 64;
 
 // flat parameter space: tables [L][T][F] | W [5][64][64] | b [5][64] | wo [64] | bo
 struct NrcNet {
@@ -29,7 +31,7 @@ struct NrcNet {
     float* g;          // gradients (same layout)
     float* m;          // Adam first moments
     float* v;          // Adam second moments
-    uint16_t* wq;      // [kNrcFrags][8] BF16 hidden weights, operand order (refreshed by nrc_launch_pack)
+    uint16_t* wq;      // [kNrcFragsAll][8] BF16 weights, operand order (refreshed by nrc_launch_pack)
     long long n_tab;   // L * T * F
     long long n_all;   // all parameters
     int T;             // table entries per level (power of two)
@@ -72,8 +74,8 @@ hipError_t nrc_launch_query(const NrcNet& net, int n, const float4* cx, const fl
 // with temp == nullptr only sets *temp_bytes
 hipError_t nrc_select_rows(const float4* rows, const int* ok, int n, float4* out, int* d_count, void* temp,
                            size_t* temp_bytes, hipStream_t st);
-// training batch k of S (rows k, k + S, ...) of the compacted rows into SoA arrays
-hipError_t nrc_launch_unpack(const float4* rows, int k, int S, int n, float* x, float* w, float* lam, float* t,
+// training batch k of S (rows (k + i S) m, i < n) of the compacted rows into SoA arrays
+hipError_t nrc_launch_unpack(const float4* rows, int k, int S, int m, int n, float* x, float* w, float* lam, float* t,
                              hipStream_t st);
 // BF16 operand-order copy of the hidden weights into net.wq
 hipError_t nrc_launch_pack(const NrcNet& net, hipStream_t st);

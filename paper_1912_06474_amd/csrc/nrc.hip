@@ -341,7 +341,9 @@ __global__ void k_zero(float* p, long long n) {
 // (4 column tiles), so each weight fragment read from LDS feeds 4 MFMAs.
 // Input features follow the same permutation: in step 0 group g holds hash
 // levels 2g, 2g+1, 8+2g, 9+2g; in step 1 the harmonics 4g..4g+3 and the
-// wavelength bins 4g..4g+3.
+// wavelength bins 4g..4g+3.  The output layer runs on the matrix cores too,
+// as a 16-row tile whose row 0 is wo (the others zero): the output of a
+// column is D row 0, held by the lanes of group 0.
 // ---------------------------------------------------------------------------
 
 // a[4 g + j] by selects on register values (an indexed read would place a in scratch)
@@ -352,14 +354,27 @@ __device__ __forceinline__ float pick4(const float* a, int g, int j) {
     return (g & 2) ? hi : lo;
 }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// relu(a), relu(b) rounded to BF16: rounding keeps the sign, so the ReLU is a
+// signed 16-bit max with 0 on the rounded bit patterns (negative values and
+// -0 become +0), one packed integer op per pair
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s16x2 relu_bf16x2(float a, float b) {
+    const bf16x2 p = __builtin_convertvector((f32x2){a, b}, bf16x2);
+    return __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), (s16x2){0, 0});
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ bf16x8 relu_pack8(f32x4 a, f32x4 b) {
-    bf16x8 r;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        r[i] = (__bf16)fmaxf(a[i], 0.0f);
-        r[4 + i] = (__bf16)fmaxf(b[i], 0.0f);
-    }
-    return r;
+    const u32x4 q = {__builtin_bit_cast(uint32_t, relu_bf16x2(a[0], a[1])),
+                     __builtin_bit_cast(uint32_t, relu_bf16x2(a[2], a[3])),
+                     __builtin_bit_cast(uint32_t, relu_bf16x2(b[0], b[1])),
+                     __builtin_bit_cast(uint32_t, relu_bf16x2(b[2], b[3]))};
+    return __builtin_bit_cast(bf16x8, q);
 }
 
 constexpr int kMfmaBlock = 256;
@@ -368,18 +383,16 @@ constexpr int kMfmaRowsPerWave = 64;
 // LDS of a matrix-core block: the BF16 weight fragments, biases, output
 // weights, level table, and per-lane parking slots for the input operands
 struct MfmaLds {
-    bf16x8 w[kNrcFrags];
+    bf16x8 w[kNrcFragsAll];
     __align__(16) float b[kNrcLayers * kNrcHid];
-    float wo[kNrcHid];
     int res[kNrcLevels], dense[kNrcLevels];
     bf16x8 in[kMfmaBlock / 64][4][2][64];
 };
 
 __device__ __forceinline__ void mfma_stage(const NrcNet& net, MfmaLds& L) {
     const bf16x8* wq = reinterpret_cast<const bf16x8*>(net.wq);
-    for (int e = threadIdx.x; e < kNrcFrags; e += kMfmaBlock) L.w[e] = wq[e];
+    for (int e = threadIdx.x; e < kNrcFragsAll; e += kMfmaBlock) L.w[e] = wq[e];
     for (int e = threadIdx.x; e < kNrcLayers * kNrcHid; e += kMfmaBlock) L.b[e] = net.p[net.off_b() + e];
-    if (threadIdx.x < kNrcHid) L.wo[threadIdx.x] = net.p[net.off_wo() + threadIdx.x];
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int l = 0; l < kNrcLevels; ++l) {  // static indexes: kernel arguments stay out of scratch
@@ -403,11 +416,13 @@ __device__ __forceinline__ bf16x8 mfma_hash_operand(const NrcNet& net, const Mfm
     return v;
 }
 
-// hidden layers k_begin..4; b0, b1 hold the inputs of layer k_begin, acc gets
-// the pre-activations of the last layer
-__device__ __forceinline__ void mfma_layers(const MfmaLds& L, int lane, int g, bf16x8 (&b0)[4], bf16x8 (&b1)[4],
-                                            f32x4 (&acc)[4][4], int k_begin) {
-    for (int k = k_begin; k < kNrcLayers; ++k) {
+// the network from its input operands b0, b1 (4 column tiles): hidden layers
+// 0..4, then the output layer; y[nt] is the output of column c of tile nt in
+// the lanes of group 0
+__device__ __forceinline__ void mfma_forward(const MfmaLds& L, int lane, int g, bf16x8 (&b0)[4], bf16x8 (&b1)[4],
+                                             float bo, float (&y)[4]) {
+    f32x4 acc[4][4];
+    for (int k = 0; k < kNrcLayers; ++k) {
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             const f32x4 bias = *reinterpret_cast<const f32x4*>(&L.b[k * kNrcHid + 16 * mt + 4 * g]);
@@ -419,26 +434,20 @@ __device__ __forceinline__ void mfma_layers(const MfmaLds& L, int lane, int g, b
                 acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1[nt], acc[nt][mt], 0, 0, 0);
             }
         }
-        if (k + 1 < kNrcLayers) {
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                b0[nt] = relu_pack8(acc[nt][0], acc[nt][1]);
-                b1[nt] = relu_pack8(acc[nt][2], acc[nt][3]);
-            }
+        for (int nt = 0; nt < 4; ++nt) {
+            b0[nt] = relu_pack8(acc[nt][0], acc[nt][1]);
+            b1[nt] = relu_pack8(acc[nt][2], acc[nt][3]);
         }
     }
-}
-
-// output of column tile nt (FP32 dot product over the 64 ReLU outputs, reduced over the 4 lane groups)
-__device__ __forceinline__ float mfma_output(const MfmaLds& L, int g, const f32x4 (&acc)[4][4], int nt) {
-    float s = 0.0f;
+    const bf16x8 o0 = L.w[kNrcFrags + lane], o1 = L.w[kNrcFrags + 64 + lane];
+    const f32x4 c0 = {g == 0 ? bo : 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) s = fmaf(L.wo[16 * mt + 4 * g + i], fmaxf(acc[nt][mt][i], 0.0f), s);
-    s += __shfl_xor(s, 16);
-    s += __shfl_xor(s, 32);
-    return s;
+    for (int nt = 0; nt < 4; ++nt) {
+        f32x4 o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o0, b0[nt], c0, 0, 0, 0);
+        o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o1, b1[nt], o, 0, 0, 0);
+        y[nt] = o[0];
+    }
 }
 
 __global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, const float* x, const float* w,
@@ -474,14 +483,12 @@ __global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, co
         b0[nt] = L.in[wv][nt][0][lane];
         b1[nt] = L.in[wv][nt][1][lane];
     }
-    f32x4 acc[4][4];
-    mfma_layers(L, lane, g, b0, b1, acc, 0);
-    const float bo = net.p[net.off_bo()];
+    float out[4];
+    mfma_forward(L, lane, g, b0, b1, net.p[net.off_bo()], out);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        const float s = mfma_output(L, g, acc, nt);
         const long long row = base + nt * 16 + c;
-        if (g == 0 && row < n) y[row] = s + bo;
+        if (g == 0 && row < n) y[row] = out[nt];
     }
 }
 
@@ -521,21 +528,23 @@ __global__ __launch_bounds__(kMfmaBlock) void k_query_mfma(NrcNet net, int n, co
         // it they would hold 160 registers)
         asm volatile("" ::: "memory");
         const float lm = lam[l];
+        __bf16 blob[4];  // the wavelength's bins 4g..4g+3, the same for every path
+#pragma unroll
+        for (int j = 0; j < 4; ++j) blob[j] = (__bf16)blob_bin(net, lm, 4 * g + j);
         bf16x8 b0[4], b1[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             b0[nt] = L.in[wv][nt][0][lane];
             b1[nt] = L.in[wv][nt][1][lane];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b1[nt][4 + j] = (__bf16)blob_bin(net, lm, 4 * g + j);
+            for (int j = 0; j < 4; ++j) b1[nt][4 + j] = blob[j];
         }
-        f32x4 acc[4][4];
-        mfma_layers(L, lane, g, b0, b1, acc, 0);
+        float out[4];
+        mfma_forward(L, lane, g, b0, b1, bo, out);
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            const float s = mfma_output(L, g, acc, nt);
             const long long row = base + nt * 16 + c;
-            if (g == 0 && row < n) lhat[row * nlp + l] = s + bo;
+            if (g == 0 && row < n) lhat[row * nlp + l] = out[nt];
         }
     }
 }
@@ -560,11 +569,11 @@ __global__ __launch_bounds__(256) void k_query(NrcNet net, int n, const float4* 
     lhat[(size_t)path * nlp + l] = output(net, h);
 }
 
-// training batch k of S: rows k, k + S, k + 2S, ... of the compacted rows, into SoA
-__global__ void k_unpack(const float4* rows, int k, int S, int n, float* x, float* w, float* lam, float* t) {
+// training batch k of S: rows (k + i S) m, i < n, of the compacted rows, into SoA
+__global__ void k_unpack(const float4* rows, int k, int S, int m, int n, float* x, float* w, float* lam, float* t) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const size_t src = (size_t)k + (size_t)i * S;
+    const size_t src = ((size_t)k + (size_t)i * S) * m;
     const float4 a = rows[2 * src], b = rows[2 * src + 1];
     x[3 * (size_t)i] = a.x;
     x[3 * (size_t)i + 1] = a.y;
@@ -580,17 +589,23 @@ struct NrcRow {
     float4 a, b;
 };
 
-// hidden weights -> BF16 operand order: fragment e = ((k * 4 + mt) * 2 + s) * 64 + lane
+// weights -> BF16 operand order: hidden fragment e = ((k * 4 + mt) * 2 + s) * 64 + lane,
+// output fragment kNrcFrags + s * 64 + lane (row 0 = wo, rows 1..15 zero)
 __global__ void k_pack(NrcNet net) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= kNrcFrags) return;
-    const int lane = e & 63, s = (e >> 6) & 1, mt = (e >> 7) & 3, k = e >> 9;
-    const int m = 16 * mt + (lane & 15), g = lane >> 4;
-    const float* W = net.p + net.off_W() + (size_t)k * kNrcHid * kNrcHid + (size_t)m * kNrcHid;
+    if (e >= kNrcFragsAll) return;
+    const bool out = e >= kNrcFrags;
+    const int f = out ? e - kNrcFrags : e;
+    const int lane = f & 63, s = (f >> 6) & 1, mt = (f >> 7) & 3, k = f >> 9;
+    const int g = lane >> 4;
+    const int m = out ? (lane & 15) : 16 * mt + (lane & 15);
+    const float* W = out ? net.p + net.off_wo()
+                         : net.p + net.off_W() + (size_t)k * kNrcHid * kNrcHid + (size_t)m * kNrcHid;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int in = 16 * (2 * s + j / 4) + 4 * g + (j & 3);
-        net.wq[(size_t)e * 8 + j] = __builtin_bit_cast(uint16_t, (__bf16)W[in]);
+        const float v = out && m != 0 ? 0.0f : W[in];
+        net.wq[(size_t)e * 8 + j] = __builtin_bit_cast(uint16_t, (__bf16)v);
     }
 }
 
@@ -634,15 +649,15 @@ hipError_t nrc_select_rows(const float4* rows, const int* ok, int n, float4* out
                                          reinterpret_cast<NrcRow*>(out), d_count, n, st);
 }
 
-hipError_t nrc_launch_unpack(const float4* rows, int k, int S, int n, float* x, float* w, float* lam, float* t,
+hipError_t nrc_launch_unpack(const float4* rows, int k, int S, int m, int n, float* x, float* w, float* lam, float* t,
                              hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_unpack, dim3(nblocks(n, 256)), dim3(256), 0, st, rows, k, S, n, x, w, lam, t);
+    hipLaunchKernelGGL(k_unpack, dim3(nblocks(n, 256)), dim3(256), 0, st, rows, k, S, m, n, x, w, lam, t);
     return hipGetLastError();
 }
 
 hipError_t nrc_launch_pack(const NrcNet& net, hipStream_t st) {
-    hipLaunchKernelGGL(k_pack, dim3(nblocks(kNrcFrags, 256)), dim3(256), 0, st, net);
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(kNrcFragsAll, 256)), dim3(256), 0, st, net);
     return hipGetLastError();
 }
 

@@ -401,7 +401,7 @@ def tiny_room(seed: int = 0, n_lambda: int = 16, n_boxes: int = 20, window=((1, 
 
 
 def furnished_room(seed: int = 1, n_lambda: int = 41, min_tris: int = 200_000,
-                   panes=((0, 1), (2, 1), (3, 2)), coating_state=None, name=None):
+                   panes=((0, 1), (2, 1), (3, 2)), coating_state=None, name=None, detail: int = 1):
     """Room-scale plain-method room: >= ``min_tris`` triangles, three 4 mm panes.
 
     Furniture: boxes (faces s x s, s in 2..6) and capped z-axis cylinders
@@ -409,7 +409,9 @@ def furnished_room(seed: int = 1, n_lambda: int = 41, min_tris: int = 200_000,
     uniform in the room volume (1 cm clear of the shell, 0.1 m clear of the
     camera), generated until the triangle count reaches ``min_tris``.  With
     ``coating_state`` the panes carry the electrochromic coating
-    (``electrochromic_layers``) on their room-side face.
+    (``electrochromic_layers``) on their room-side face.  ``detail`` multiplies
+    the tessellation (face splits, segments and stacks), so a larger triangle
+    budget buys finer furniture instead of more of it.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     lam, w = lambda_grid(n_lambda)
@@ -436,9 +438,9 @@ def furnished_room(seed: int = 1, n_lambda: int = 41, min_tris: int = 200_000,
             continue
         m = mats.add(DIFFUSE, rho=gaussian_reflectance(rng, lam))
         if is_box:
-            _box(mesh, lo, hi, int(rng.integers(2, 7)), m)
+            _box(mesh, lo, hi, int(rng.integers(2, 7)) * detail, m)
         else:
-            _cylinder(mesh, c, h[0], h[2], int(rng.integers(16, 65)), int(rng.integers(1, 9)), m)
+            _cylinder(mesh, c, h[0], h[2], int(rng.integers(16, 65)) * detail, int(rng.integers(1, 9)) * detail, m)
     return _finish(mesh, mats, lam, w, light_type=LIGHT_PARALLELOGRAM, light_mat=sky,
                    name=name or f"furnished_room(seed={seed},nl={n_lambda},T>={min_tris})", seed=seed)
 
@@ -522,6 +524,14 @@ def nrc_rows(n: int, seed: int, aabb_lo=(0.0, 0.0, 0.0), aabb_hi=(4.0, 3.0, 2.5)
     lam_nm = rng.uniform(lam[0], lam[1], size=n)
     t = rng.gamma(2.0, 0.5, size=n)
     return x.astype(np.float32), w.astype(np.float32), lam_nm.astype(np.float32), t.astype(np.float32)
+
+
+def nrc_room(seed: int = 3, n_lambda: int = 41, min_tris: int = 1_000_000, detail: int = 3):
+    """Radiance-cache workload: the furnished-room recipe at >= 1M triangles,
+    the furniture tessellated ``detail`` times finer (so the room holds about
+    half as many pieces as the 200k room rather than five times as many)."""
+    return furnished_room(seed=seed, n_lambda=n_lambda, min_tris=min_tris, detail=detail,
+                          name=f"nrc_room(seed={seed},nl={n_lambda},T>={min_tris},detail={detail})")
 
 
 def electrochromic_room(seed: int = 4, n_lambda: int = 81, min_tris: int = 4_000_000, coating_state: float = 0.6):
@@ -675,4 +685,5 @@ WORKLOADS = {
                            grid=(4, 4, 2), seed=0),
     "electrochromic_room": dict(build=lambda: electrochromic_room(4, 81), W=3840, H=2160, spp=64, max_depth=8,
                                 grid=(8, 4, 4), seed=0),
+    "nrc_room": dict(build=lambda: nrc_room(3, 41), W=1920, H=1080, spp=4, max_depth=8, grid=(4, 4, 2), seed=0),
 }

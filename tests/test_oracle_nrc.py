@@ -178,7 +178,7 @@ def test_bf16_forward_is_exact_on_bf16_operands():
     # operands with at most 8 significant bits are bfloat16 values: nothing rounds
     params = {"W": [rng.integers(-8, 9, (64, 64)) / 16.0] + [np.zeros((64, 64)) for _ in range(4)],
               "b": [rng.integers(-4, 5, 64) / 8.0 for _ in range(5)],
-              "wo": rng.normal(size=64), "bo": 0.25}
+              "wo": rng.integers(-16, 17, 64) / 32.0, "bo": 0.25}
     X = rng.integers(-64, 65, (50, 64)) / 32.0
     y, _ = nrc.mlp_forward(params, X)
     assert np.array_equal(nrc.mlp_forward_bf16(params, X), y)
