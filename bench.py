@@ -47,7 +47,17 @@ WORKLOADS = {
     # 4M triangles, coated (electrochromic) panes, 81 wavelengths, 128 subdomains
     "electrochromic_room": dict(scene=("electrochromic_room", dict(seed=4, n_lambda=81)), W=3840, H=2160, spp=64,
                                 D=8, grid=(8, 4, 4)),
+    # radiance cache vs plain at equal image quality: 1M triangles, 1920 x 1080,
+    # 4 spp per frame, 41 wavelengths, paths end in the cache after vertex 2
+    "nrc_room": dict(scene=("nrc_room", dict(seed=3, n_lambda=41)), W=1920, H=1080, spp=4, D=8, grid=(4, 4, 2),
+                     nrc=dict(ref_frames=48, train_paths=1 << 16, train_steps=4, train_batch=1 << 14)),
 }
+
+# per cache query (one path, one wavelength): multiply-adds of the five 64 x 64
+# hidden layers and the 64-wide output layer, two flops each
+NRC_FLOPS_PER_ROW = 2 * (5 * 64 * 64 + 64)
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16
+ROOM_LO, ROOM_HI = (0.0, 0.0, 0.0), (4.0, 3.0, 2.5)
 
 
 def trace_source_hash():
@@ -121,6 +131,136 @@ def cpu_baseline(scene, wl, target_s=15.0):
                       f"{nl} wavelengths, FP64, {rays} rays in {dt:.2f} s"}
 
 
+def nrc_comparison(args, tr, scene, wl):
+    """Plain tracer and radiance-cache tracer on the same frame sequence until
+    equal image quality.  Quality: rel-MSE = mean over pixels and wavelengths
+    of ((I - R)^2 - var R) / (R^2 + 0.01 mean(R)^2) against a plain reference
+    R = (A + B) / 2 of two independent halves, var R = (A - B)^2 / 4 (removes
+    the reference's own noise from the estimate).  The plain run traces
+    ``steps`` frames; its final rel-MSE q is the target; the cache run (after
+    ``warmup`` training frames, timed) traces frames until it reaches q.  Both
+    times are whole-frame wall times (trace + resolve), synchronised."""
+    import numpy as np
+    import torch
+
+    import scenegen
+
+    W, H, spp, D = wl["W"], wl["H"], wl["spp"], wl["D"]
+    cfg = wl["nrc"]
+    nl = len(scene["lambda_nm"])
+    cam = scene["camera"]
+
+    def trace(rid, off, nrc):
+        tr.trace_spectral(cam, W, H, spp, D, seed=0, render_id=rid, sample_offset=off, nrc=nrc, time_kernels=True)
+        s, _ = tr.resolve_image(rid, W, H, spectral=True, xyz=True)
+        return s
+
+    t0 = time.perf_counter()
+    for f in range(cfg["ref_frames"]):
+        trace(10, 1_000_000 + f * spp, False)
+        trace(11, 2_000_000 + f * spp, False)
+    A, _ = tr.resolve_image(10, W, H, spectral=True, xyz=False)
+    B, _ = tr.resolve_image(11, W, H, spectral=True, xyz=False)
+    tr.reset_render(10)
+    tr.reset_render(11)
+    R = 0.5 * (A + B)
+    varR = 0.25 * (A - B) ** 2
+    den = R * R + 0.01 * R.mean() ** 2
+    ref_self = float((varR / den).mean())
+    log(f"[bench] reference: {2 * cfg['ref_frames'] * spp} spp in {time.perf_counter() - t0:.1f} s, "
+        f"its own rel-MSE {ref_self:.3e}")
+
+    def relmse(img):
+        return float((((img - R) ** 2 - varR) / den).mean())
+
+    def run(rid, nrc, n_frames, target=None, warm=0):
+        tt, hist = 0.0, []
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for f in range(warm):  # cache training frames, not accumulated
+            trace(3, 3_000_000 + f * spp, True)
+        torch.cuda.synchronize()
+        if warm:
+            tr.reset_render(3)
+        tt = time.perf_counter() - t1
+        warm_s = tt
+        for f in range(n_frames):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            img = trace(rid, f * spp, nrc)
+            torch.cuda.synchronize()
+            tt += time.perf_counter() - t1
+            hist.append((f + 1, tt, relmse(img)))
+            if f % 10 == 9:
+                log(f"[bench] {'cache' if nrc else 'plain'} frame {f + 1}: {tt:.2f} s, rel-MSE {hist[-1][2]:.4f}")
+            if target is not None and hist[-1][2] <= target:
+                break
+        tr.reset_render(rid)
+        return hist, warm_s
+
+    def fit(hist):
+        """rel-MSE(n) ~ a + b / n over the second half of the run; frames to 1%."""
+        h = np.array(hist[len(hist) // 2:])
+        X = np.stack([np.ones(len(h)), 1.0 / h[:, 0]], 1)
+        a, b = np.linalg.lstsq(X, h[:, 2], rcond=None)[0]
+        n1 = b / (0.01 - a) if 0.01 - a > 0 and b > 0 else None
+        return float(a), float(b), (float(n1) if n1 is not None else None)
+
+    tr.reset_stats()
+    hp, _ = run(1, False, args.steps)
+    stp = tr.stats()
+    q = hp[-1][2]
+    t_plain = hp[-1][1]
+    log(f"[bench] plain: {args.steps} frames, {t_plain:.2f} s, rel-MSE {q:.4f}")
+
+    params, tables = scenegen.nrc_params(0)
+    tr.nrc_init(params, tables, ROOM_LO, ROOM_HI, train_paths=cfg["train_paths"], train_steps=cfg["train_steps"],
+                train_batch=cfg["train_batch"], precision="bf16")
+    tr.reset_stats()
+    hn, warm_s = run(2, True, 4 * args.steps, target=q, warm=args.warmup)
+    stn = tr.stats()
+    reached = hn[-1][2] <= q
+    t_nrc = hn[-1][1]
+    log(f"[bench] cache: warm-up {args.warmup} frames {warm_s:.2f} s, then {len(hn)} frames, {t_nrc:.2f} s, "
+        f"rel-MSE {hn[-1][2]:.4f} ({'reached' if reached else 'did not reach'} {q:.4f})")
+    fp, fn = fit(hp), fit(hn)
+    nrc_frames = args.warmup + len(hn)
+    fr_plain = t_plain / len(hp)
+    fr_nrc = (t_nrc - warm_s) / len(hn)
+    samples_plain = len(hp) * W * H * spp
+    # roofline of the cache query (BF16 matrix cores) over the cache run
+    launches = max(1, stn["nrc_query_launches"])
+    avg_ms = stn["ms_nrc_query"] / launches
+    flops = stn["nrc_query_rows"] / launches * NRC_FLOPS_PER_ROW
+    achieved = flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    value = samples_plain * nl / t_nrc if reached else None
+    return {
+        "metric": "spectral path samples/s (rays x lambda/s) at equal rel-MSE, radiance cache vs plain, one MI355X",
+        "value": value,
+        "unit": "plain-equivalent path samples*lambda/s",
+        "ms_per_step": fr_nrc * 1e3,
+        "dtype": "bf16 cache (f32 transport)",
+        "comparison": {
+            "target_rel_mse": q, "reference_own_rel_mse": ref_self,
+            "plain": {"frames": len(hp), "seconds": t_plain, "ms_per_frame": fr_plain * 1e3,
+                      "path_samples_lambda_per_s": W * H * spp * nl / fr_plain,
+                      "rays_lambda_per_s": (stp["ext_rays"] + stp["shadow_rays"]) * nl / t_plain,
+                      "fit_a_b": fp[:2], "frames_to_1pct_extrapolated": fp[2]},
+            "cache": {"warmup_frames": args.warmup, "frames": len(hn), "seconds_incl_warmup": t_nrc,
+                      "ms_per_frame": fr_nrc * 1e3, "path_samples_lambda_per_s": W * H * spp * nl / fr_nrc,
+                      "rays_lambda_per_s": (stn["ext_rays"] + stn["shadow_rays"]) * nl / t_nrc,
+                      "rel_mse": hn[-1][2], "reached_target": reached,
+                      "fit_a_b": fn[:2], "frames_to_1pct_extrapolated": fn[2],
+                      "ms_query_per_frame": stn["ms_nrc_query"] / nrc_frames,
+                      "ms_train_per_frame": stn["ms_nrc_train"] / nrc_frames},
+            "speedup_at_equal_quality": (t_plain / t_nrc) if reached else None,
+        },
+        "roofline": {"bound": "mfma", "kernel": "k_query_mfma", "achieved": achieved,
+                     "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
+                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": avg_ms, "launches": launches},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +318,19 @@ def main():
     st0 = tr.stats()
     log(f"[bench] build_bvh {wl['grid']}: {build_s:.2f} s, refs {st0['n_refs']}, nodes {st0['n_nodes']}, "
         f"depth {st0['max_bvh_depth']}")
+
+    if "nrc" in wl:
+        res = nrc_comparison(args, tr, scene, wl)
+        res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+                    "scaling": "weak", "vs_baseline": None, "data": "synthetic"})
+        res["config"] = {"workload": f"{args.workload}: {len(scene['tris'])} tris, {W}x{H}, {spp} spp per frame, "
+                                     f"{nl} lambda, depth {D}, cache after vertex 2, grid "
+                                     f"{'x'.join(map(str, wl['grid']))}"}
+        res["build_bvh_s"] = build_s
+        if not args.no_cpu_baseline:
+            res["cpu_baseline"] = cpu_baseline(scene, wl, args.cpu_seconds)
+        print(json.dumps(res))
+        return
 
     step = 0
 

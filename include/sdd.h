@@ -202,6 +202,11 @@ typedef struct sdd_stats {
     int64_t paths_per_batch;
     int32_t overflow;          /* nonzero: a shadow segment crossed more panes than supported */
     int32_t pad_;
+    double ms_nrc_query;       /* cache queries of SDD_TRACE_NRC renders (SDD_TRACE_TIME_KERNELS) */
+    double ms_nrc_train;       /* cache training after those renders (SDD_TRACE_TIME_KERNELS) */
+    int64_t nrc_query_rows;    /* (path, wavelength) cache queries */
+    int64_t nrc_query_launches;
+    int64_t nrc_train_rows;    /* rows of the Adam steps */
 } sdd_stats;
 
 /* Create a context on HIP device hip_device.  hip_stream is the hipStream_t

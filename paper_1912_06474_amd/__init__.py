@@ -86,6 +86,8 @@ class Stats(C.Structure):
         ("ms_other", C.c_double),
         ("n_refs", C.c_int64), ("n_nodes", C.c_int64), ("max_bvh_depth", C.c_int32), ("n_cells", C.c_int32),
         ("device_bytes", C.c_int64), ("paths_per_batch", C.c_int64), ("overflow", C.c_int32), ("pad_", C.c_int32),
+        ("ms_nrc_query", C.c_double), ("ms_nrc_train", C.c_double), ("nrc_query_rows", C.c_int64),
+        ("nrc_query_launches", C.c_int64), ("nrc_train_rows", C.c_int64),
     ]
 
     def as_dict(self):

@@ -41,7 +41,7 @@ struct Render {
 };
 
 struct TimedLaunch {
-    int cls;  // 0 ext trace, 1 shadow trace, 2 shade, 3 other
+    int cls;  // 0 ext trace, 1 shadow trace, 2 shade, 3 other, 4 cache query, 5 cache training
     hipEvent_t a, b;
 };
 
@@ -155,7 +155,8 @@ struct sdd_ctx {
 
     // host stats
     long long batches = 0, launches_trace = 0, cam_rays = 0;
-    double ms[4] = {0, 0, 0, 0};
+    double ms[6] = {0, 0, 0, 0, 0, 0};
+    long long nrc_query_rows = 0, nrc_query_launches = 0, nrc_train_rows = 0;
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
     int leftover = 0;
@@ -1021,7 +1022,7 @@ sdd_status nrc_train_after_call(sdd_ctx* c, long long n_rows, bool timing) {
     c->nrc_last_loss = 0.0f;
     if (n_rows <= 0) return SDD_OK;
     {
-        Timer tm(c, timing, 3);
+        Timer tm(c, timing, 5);
         size_t tb = c->nrc_tmp_bytes;
         HIP_TRY(c, nrc_select_rows(c->nrc_rows, c->nrc_ok, (int)n_rows, c->nrc_crows, c->nrc_count, c->nrc_tmp, &tb,
                                    c->stream));
@@ -1041,7 +1042,8 @@ sdd_status nrc_train_after_call(sdd_ctx* c, long long n_rows, bool timing) {
     double loss_sum = 0.0;
     for (int k = 0; k < S; ++k) {
         const int nk = (int)std::min<long long>(c->nrc_train_batch, ((long long)count / m - k + S - 1) / S);
-        Timer tm(c, timing, 3);
+        c->nrc_train_rows += nk;
+        Timer tm(c, timing, 5);
         HIP_TRY(c, nrc_launch_unpack(c->nrc_crows, k, S, m, nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt,
                                      c->stream));
         NrcBatch b{nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt, c->nrc_acts, c->nrc_dz, c->nrc_y, c->nrc_dy,
@@ -1285,7 +1287,9 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
         st = run_sweeps(c, -1, ph_sh(D), cap, count, timing, D, N);
         if (st != SDD_OK) return st;
         if (nrc) {  // cache values at the batch's cache vertices, every wavelength
-            Timer tm(c, timing, 3);
+            Timer tm(c, timing, 4);
+            c->nrc_query_rows += (long long)N * c->nl;
+            ++c->nrc_query_launches;
             HIP_TRY(c, nrc_launch_query(c->nrc, N, c->nrc_cx, c->nrc_cn, c->d_lam, c->nl, c->nlp, c->nrc_lhat,
                                         c->nrc_precision, c->stream));
         }
@@ -1509,6 +1513,11 @@ sdd_status sdd_get_stats(sdd_ctx* c, sdd_stats* out) {
     out->ms_trace_shadow = c->ms[1];
     out->ms_shade = c->ms[2];
     out->ms_other = c->ms[3];
+    out->ms_nrc_query = c->ms[4];
+    out->ms_nrc_train = c->ms[5];
+    out->nrc_query_rows = c->nrc_query_rows;
+    out->nrc_query_launches = c->nrc_query_launches;
+    out->nrc_train_rows = c->nrc_train_rows;
     out->n_refs = c->has_bvh ? c->gb.n_refs : 0;
     long long nn = 0;
     for (int v : c->gb.cell_nodes) nn += v;
@@ -1532,6 +1541,7 @@ sdd_status sdd_reset_stats(sdd_ctx* c) {
     c->cam_rays = 0;
     c->launches_trace = 0;
     for (double& m : c->ms) m = 0.0;
+    c->nrc_query_rows = c->nrc_query_launches = c->nrc_train_rows = 0;
     return SDD_OK;
 }
 
