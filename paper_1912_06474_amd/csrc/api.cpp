@@ -152,6 +152,9 @@ struct sdd_ctx {
     int nrc_last_steps = 0;
     float nrc_last_loss = 0.0f;
     float* d_lam = nullptr;  // scene wavelengths (nm), FP32
+    uint4* nrc_hop = nullptr;  // staged matrix operands of cache queries
+    uint2* nrc_sop = nullptr;
+    long long nrc_ocap = 0;
 
     // host stats
     long long batches = 0, launches_trace = 0, cam_rays = 0;
@@ -313,6 +316,9 @@ void free_nrc_render(sdd_ctx* c) {
 
 void free_nrc(sdd_ctx* c) {
     free_nrc_render(c);
+    dfree(c, c->nrc_hop);
+    dfree(c, c->nrc_sop);
+    c->nrc_ocap = 0;
     free_nrc_batch(c);
     dfree(c, c->nrc_loss);
     dfree(c, c->nrc.p);
@@ -959,6 +965,21 @@ namespace {
 
 sdd_status nrc_reserve(sdd_ctx* c, long long n);
 
+// operand staging of BF16 cache queries for n paths
+sdd_status nrc_ensure_ops(sdd_ctx* c, int n) {
+    const long long need = nrc_query_ops_paths(n);
+    if (need <= c->nrc_ocap) return SDD_OK;
+    dfree(c, c->nrc_hop);
+    dfree(c, c->nrc_sop);
+    c->nrc_ocap = 0;
+    sdd_status st;
+    if ((st = dalloc(c, &c->nrc_hop, (size_t)(4 * need))) != SDD_OK ||
+        (st = dalloc(c, &c->nrc_sop, (size_t)(4 * need))) != SDD_OK)
+        return st;
+    c->nrc_ocap = need;
+    return SDD_OK;
+}
+
 // render buffers of the radiance cache: n batch paths, slots training paths of depth D
 sdd_status nrc_ensure_render(sdd_ctx* c, long long n, long long slots, int D) {
     sdd_status st;
@@ -997,6 +1018,7 @@ sdd_status nrc_ensure_render(sdd_ctx* c, long long n, long long slots, int D) {
         c->nrc_dcap = D;
     }
     if (!c->nrc_count && (st = dalloc(c, &c->nrc_count, 1)) != SDD_OK) return st;
+    if ((st = nrc_ensure_ops(c, (int)n)) != SDD_OK) return st;
     const long long bn = c->nrc_train_batch;
     if (bn > c->nrc_bcap) {
         dfree(c, c->nrc_bx);
@@ -1291,7 +1313,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
             c->nrc_query_rows += (long long)N * c->nl;
             ++c->nrc_query_launches;
             HIP_TRY(c, nrc_launch_query(c->nrc, N, c->nrc_cx, c->nrc_cn, c->d_lam, c->nl, c->nlp, c->nrc_lhat,
-                                        c->nrc_precision, c->stream));
+                                        c->nrc_precision, c->nrc_hop, c->nrc_sop, c->stream));
         }
         for (const Seg& sg : segs) {
             const sdd_trace_desc* t = sg.j->t;
@@ -1874,9 +1896,13 @@ sdd_status sdd_nrc_query(sdd_ctx* c, int32_t n, const float* x4, const float* n4
     if (precision != 0 && precision != 1) return fail(c, SDD_ERR_INVALID_ARG, "precision must be 0 or 1");
     if (n == 0) return SDD_OK;
     DeviceGuard g(c->device);
+    if (precision == 1) {
+        sdd_status st = nrc_ensure_ops(c, n);
+        if (st != SDD_OK) return st;
+    }
     const hipError_t e = nrc_launch_query(c->nrc, n, reinterpret_cast<const float4*>(x4),
                                           reinterpret_cast<const float4*>(n4), c->d_lam, c->nl, c->nlp, out, precision,
-                                          c->stream);
+                                          c->nrc_hop, c->nrc_sop, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "nrc query");
     return SDD_OK;
 }

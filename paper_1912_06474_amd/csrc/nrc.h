@@ -67,9 +67,12 @@ hipError_t nrc_launch_infer(const NrcNet& net, int n, const float* x, const floa
 hipError_t nrc_launch_infer_mfma(const NrcNet& net, int n, const float* x, const float* w, const float* lam,
                                  float* y, hipStream_t st);
 // cache values of n paths at nl wavelengths: lhat[path * nlp + l] for the
-// cache vertex (cx, cn) of each path (precision 0: FP32, 1: BF16 matrix cores)
+// cache vertex (cx, cn) of each path (precision 0: FP32, 1: BF16 matrix cores,
+// which stage the paths' operands in hop, sop: nrc_query_ops_paths(n) entries
+// each -- 4 lane groups of 16 B and 8 B per path; unused for precision 0)
+long long nrc_query_ops_paths(int n);
 hipError_t nrc_launch_query(const NrcNet& net, int n, const float4* cx, const float4* cn, const float* lam, int nl,
-                            int nlp, float* lhat, int precision, hipStream_t st);
+                            int nlp, float* lhat, int precision, uint4* hop, uint2* sop, hipStream_t st);
 // stable compaction of the training rows (pairs of float4) whose flag is set;
 // with temp == nullptr only sets *temp_bytes
 hipError_t nrc_select_rows(const float4* rows, const int* ok, int n, float4* out, int* d_count, void* temp,

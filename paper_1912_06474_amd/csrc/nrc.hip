@@ -380,13 +380,11 @@ __device__ __forceinline__ bf16x8 relu_pack8(f32x4 a, f32x4 b) {
 constexpr int kMfmaBlock = 256;
 constexpr int kMfmaRowsPerWave = 64;
 
-// LDS of a matrix-core block: the BF16 weight fragments, biases, output
-// weights, level table, and per-lane parking slots for the input operands
+// LDS of a matrix-core block: the BF16 weight fragments, biases and level table
 struct MfmaLds {
     bf16x8 w[kNrcFragsAll];
     __align__(16) float b[kNrcLayers * kNrcHid];
     int res[kNrcLevels], dense[kNrcLevels];
-    bf16x8 in[kMfmaBlock / 64][4][2][64];
 };
 
 __device__ __forceinline__ void mfma_stage(const NrcNet& net, MfmaLds& L) {
@@ -453,6 +451,7 @@ __device__ __forceinline__ void mfma_forward(const MfmaLds& L, int lane, int g, 
 __global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, const float* x, const float* w,
                                                           const float* lam, float* y) {
     __shared__ MfmaLds L;
+    __shared__ bf16x8 s_in[kMfmaBlock / 64][4][2][64];  // per-lane parking of the input operands
     mfma_stage(net, L);
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
     const long long base = ((long long)blockIdx.x * (kMfmaBlock / 64) + wv) * kMfmaRowsPerWave;
@@ -474,14 +473,14 @@ __global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, co
             v1[j] = (__bf16)pick4(sh, g, j);
             v1[4 + j] = (__bf16)blob_bin(net, lm, 4 * g + j);
         }
-        L.in[wv][nt][0][lane] = v0;
-        L.in[wv][nt][1][lane] = v1;
+        s_in[wv][nt][0][lane] = v0;
+        s_in[wv][nt][1][lane] = v1;
     }
     bf16x8 b0[4], b1[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        b0[nt] = L.in[wv][nt][0][lane];
-        b1[nt] = L.in[wv][nt][1][lane];
+        b0[nt] = s_in[wv][nt][0][lane];
+        b1[nt] = s_in[wv][nt][1][lane];
     }
     float out[4];
     mfma_forward(L, lane, g, b0, b1, net.p[net.off_bo()], out);
@@ -492,35 +491,58 @@ __global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, co
     }
 }
 
-// Cache values of n paths at every wavelength: lhat[path][l].  The hash and
-// harmonic operands of a path are formed once (the 128 table gathers) and
-// parked in LDS; per wavelength only the one-blob slots change.  Same
-// products and summation order as k_infer_mfma.
-__global__ __launch_bounds__(kMfmaBlock) void k_query_mfma(NrcNet net, int n, const float4* cx, const float4* cn,
+// Operands of the cache query, one thread per path: for each lane group g of
+// the matrix layout, the step-0 operand (hash levels 2g, 2g+1, 8+2g, 9+2g,
+// 8 BF16) and the harmonics 4g..4g+3 (4 BF16), stored where lane (g, c) of
+// the path's 16-column tile reads them: hop[(tile * 4 + g) * 16 + c],
+// sop[(tile * 4 + g) * 16 + c].  A plain gather kernel at full occupancy; the
+// matrix kernel then needs no parking space and no gathers.
+__global__ __launch_bounds__(256) void k_query_operands(NrcNet net, int n, const float4* cx, const float4* cn,
+                                                        uint4* hop, uint2* sop) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float4 x4 = cx[p], n4 = cn[p];
+    const float xp[3] = {x4.x, x4.y, x4.z};
+    float xn[3];
+    normalise(net, xp, xn);
+    float sh[kNrcSh];
+    sh_features(net.shK, n4.x, n4.y, n4.z, sh);
+    const size_t slot = (size_t)(p >> 4) * 64 + (p & 15);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int l = (q < 2 ? 0 : 8) + 2 * g + (q & 1);
+            const float2 e = hash_level(net, l, net.res[l], net.dense[l], xn);
+            w[q] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){e.x, e.y}, bf16x2));
+        }
+        hop[slot + 16 * g] = make_uint4(w[0], w[1], w[2], w[3]);
+        sop[slot + 16 * g] = make_uint2(
+            __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){sh[4 * g], sh[4 * g + 1]}, bf16x2)),
+            __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){sh[4 * g + 2], sh[4 * g + 3]}, bf16x2)));
+    }
+}
+
+// Cache values of n paths at every wavelength: lhat[path][l], from the
+// operands of k_query_operands (n rounded up to whole 64-path waves there).
+// Per wavelength only the one-blob slots change.  LDS holds only the
+// weights, so three blocks fit a CU.  Same products and summation order as
+// k_infer_mfma.
+__global__ __launch_bounds__(kMfmaBlock) void k_query_mfma(NrcNet net, int n, const uint4* hop, const uint2* sop,
                                                           const float* lam, int nl, int nlp, float* lhat) {
     __shared__ MfmaLds L;
     mfma_stage(net, L);
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
     const long long base = ((long long)blockIdx.x * (kMfmaBlock / 64) + wv) * kMfmaRowsPerWave;
     if (base >= n) return;  // whole wave idle (no barrier follows)
-#pragma unroll 1
-    for (int nt = 0; nt < 4; ++nt) {
-        const long long row = min(base + nt * 16 + c, (long long)n - 1);
-        const float4 x4 = cx[row], n4 = cn[row];
-        const float xp[3] = {x4.x, x4.y, x4.z};
-        float xn[3];
-        normalise(net, xp, xn);
-        const bf16x8 v0 = mfma_hash_operand(net, L, g, xn);
-        float sh[kNrcSh];
-        sh_features(net.shK, n4.x, n4.y, n4.z, sh);
-        bf16x8 v1;
+    bf16x8 hq[4];           // step-0 operand per tile
+    uint2 shq[4];           // harmonics per tile
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            v1[j] = (__bf16)pick4(sh, g, j);
-            v1[4 + j] = (__bf16)0.0f;
-        }
-        L.in[wv][nt][0][lane] = v0;
-        L.in[wv][nt][1][lane] = v1;
+    for (int nt = 0; nt < 4; ++nt) {
+        const size_t slot = (size_t)((base >> 4) + nt) * 64 + 16 * g + c;
+        hq[nt] = __builtin_bit_cast(bf16x8, hop[slot]);
+        shq[nt] = sop[slot];
     }
     const float bo = net.p[net.off_bo()];
     for (int l = 0; l < nl; ++l) {
@@ -528,16 +550,17 @@ __global__ __launch_bounds__(kMfmaBlock) void k_query_mfma(NrcNet net, int n, co
         // it they would hold 160 registers)
         asm volatile("" ::: "memory");
         const float lm = lam[l];
-        __bf16 blob[4];  // the wavelength's bins 4g..4g+3, the same for every path
-#pragma unroll
-        for (int j = 0; j < 4; ++j) blob[j] = (__bf16)blob_bin(net, lm, 4 * g + j);
+        // the wavelength's bins 4g..4g+3, the same for every path
+        const uint32_t bl0 = __builtin_bit_cast(
+            uint32_t, __builtin_convertvector((f32x2){blob_bin(net, lm, 4 * g), blob_bin(net, lm, 4 * g + 1)}, bf16x2));
+        const uint32_t bl1 = __builtin_bit_cast(
+            uint32_t,
+            __builtin_convertvector((f32x2){blob_bin(net, lm, 4 * g + 2), blob_bin(net, lm, 4 * g + 3)}, bf16x2));
         bf16x8 b0[4], b1[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            b0[nt] = L.in[wv][nt][0][lane];
-            b1[nt] = L.in[wv][nt][1][lane];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b1[nt][4 + j] = blob[j];
+            b0[nt] = hq[nt];
+            b1[nt] = __builtin_bit_cast(bf16x8, (u32x4){shq[nt].x, shq[nt].y, bl0, bl1});
         }
         float out[4];
         mfma_forward(L, lane, g, b0, b1, bo, out);
@@ -629,17 +652,22 @@ hipError_t nrc_launch_infer_mfma(const NrcNet& net, int n, const float* x, const
     return hipGetLastError();
 }
 
+long long nrc_query_ops_paths(int n) { return ((long long)n + kMfmaRowsPerWave - 1) / kMfmaRowsPerWave * kMfmaRowsPerWave; }
+
 hipError_t nrc_launch_query(const NrcNet& net, int n, const float4* cx, const float4* cn, const float* lam, int nl,
-                            int nlp, float* lhat, int precision, hipStream_t st) {
+                            int nlp, float* lhat, int precision, uint4* hop, uint2* sop, hipStream_t st) {
     if (n <= 0 || nl <= 0) return hipSuccess;
     if (precision == 0) {
         hipLaunchKernelGGL(k_query, dim3(nblocks((long long)n * nl, 256)), dim3(256), 0, st, net, n, cx, cn, lam, nl,
                            nlp, lhat);
-    } else {
-        const int rows_per_block = (kMfmaBlock / 64) * kMfmaRowsPerWave;
-        hipLaunchKernelGGL(k_query_mfma, dim3(nblocks(n, rows_per_block)), dim3(kMfmaBlock), 0, st, net, n, cx, cn,
-                           lam, nl, nlp, lhat);
+        return hipGetLastError();
     }
+    hipLaunchKernelGGL(k_query_operands, dim3(nblocks(n, 256)), dim3(256), 0, st, net, n, cx, cn, hop, sop);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int rows_per_block = (kMfmaBlock / 64) * kMfmaRowsPerWave;
+    hipLaunchKernelGGL(k_query_mfma, dim3(nblocks(n, rows_per_block)), dim3(kMfmaBlock), 0, st, net, n, hop, sop,
+                       lam, nl, nlp, lhat);
     return hipGetLastError();
 }
 
