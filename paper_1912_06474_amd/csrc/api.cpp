@@ -326,6 +326,7 @@ void free_nrc(sdd_ctx* c) {
     dfree(c, c->nrc.m);
     dfree(c, c->nrc.v);
     dfree(c, c->nrc.wq);
+    dfree(c, c->nrc.wf);
     c->has_nrc = false;
 }
 
@@ -1819,7 +1820,8 @@ sdd_status sdd_nrc_init(sdd_ctx* c, const sdd_nrc_desc* d) {
     sdd_status st;
     if ((st = upload(c, &net.p, d->params, (size_t)n_all)) != SDD_OK || (st = dalloc(c, &net.g, (size_t)n_all)) != SDD_OK ||
         (st = dalloc(c, &net.m, (size_t)n_all)) != SDD_OK || (st = dalloc(c, &net.v, (size_t)n_all)) != SDD_OK ||
-        (st = dalloc(c, &net.wq, (size_t)kNrcFragsAll * 8)) != SDD_OK || (st = dalloc(c, &c->nrc_loss, 1)) != SDD_OK) {
+        (st = dalloc(c, &net.wq, (size_t)kNrcFragsAll * 8)) != SDD_OK ||
+        (st = dalloc(c, &net.wf, (size_t)kNrcFrags32)) != SDD_OK || (st = dalloc(c, &c->nrc_loss, 1)) != SDD_OK) {
         free_nrc(c);
         return st;
     }

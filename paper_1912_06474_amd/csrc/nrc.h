@@ -24,6 +24,7 @@ constexpr int kNrcW = kNrcLayers * kNrcHid * kNrcHid;  // hidden weights (out, i
 // then the output layer as one 16-row tile (row 0 = wo, rows 1..15 zero): [k step 2][lane 64] x 8
 constexpr int kNrcFrags = kNrcLayers * 4 * 2 * 64;
 constexpr int kNrcFragsAll = kNrcFrags + 2 * 64;
+constexpr int kNrcFrags32 = 2 * kNrcLayers * 4 * 16 * 64;  // FP32 training fragments (one float per lane)
 
 // flat parameter space: tables [L][T][F] | W [5][64][64] | b [5][64] | wo [64] | bo
 struct NrcNet {
@@ -32,6 +33,7 @@ struct NrcNet {
     float* m;          // Adam first moments
     float* v;          // Adam second moments
     uint16_t* wq;      // [kNrcFragsAll][8] BF16 weights, operand order (refreshed by nrc_launch_pack)
+    float* wf;         // [2][5][4][16][64] FP32 hidden weights in training operand order: W, then W^T
     long long n_tab;   // L * T * F
     long long n_all;   // all parameters
     int T;             // table entries per level (power of two)

@@ -134,6 +134,14 @@ __device__ __forceinline__ void features(const NrcNet& net, const float* x, cons
     for (int i = 0; i < kNrcBlob; ++i) f[kNrcHash + kNrcSh + i] = blob_bin(net, lam, i);
 }
 
+// a[4 g + j] by selects on register values (an indexed read would place a in scratch)
+__device__ __forceinline__ float pick4(const float* a, int g, int j) {
+    float v0 = a[j], v1 = a[4 + j], v2 = a[8 + j], v3 = a[12 + j];
+    asm volatile("" : "+v"(v0), "+v"(v1), "+v"(v2), "+v"(v3));
+    const float lo = (g & 1) ? v1 : v0, hi = (g & 1) ? v3 : v2;
+    return (g & 2) ? hi : lo;
+}
+
 // ---------------------------------------------------------------------------
 // FP32 network, one row per thread; weights are read at wave-uniform
 // addresses (scalar loads shared by the wave)
@@ -174,90 +182,196 @@ __global__ __launch_bounds__(256) void k_infer(NrcNet net, int n, const float* x
     y[r] = output(net, h);
 }
 
-// training forward: activations stored feature-major acts[k][j][r]; loss and dy
-__global__ __launch_bounds__(256) void k_train_fwd(NrcNet net, NrcBatch b) {
-    __shared__ float s_loss[256];
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// ---------------------------------------------------------------------------
+// Training on the FP32 matrix cores (v_mfma_f32_16x16x4_f32).
+//
+// As in the BF16 path each layer is computed transposed, Z^T = W H^T, on 16 x
+// 16 tiles (16 features x 16 rows); a step of 4 contraction slots takes one
+// value per lane group, and step t, group g stands for input feature
+// F(t, g) = 16 (t / 4) + 4 g + t % 4.  Lane (g, c) then holds, for row c of
+// each column tile, exactly the features {16 mt + 4 g + i} a D tile gives it,
+// so activations chain from layer to layer in registers.  The backward pass
+// is the same product with W^T.  Activations and pre-activation gradients are
+// also stored feature-major for the weight-gradient reduction.  A wave covers
+// 64 rows (4 column tiles).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int frag_feature(int q, int g) { return 16 * (q >> 2) + 4 * g + (q & 3); }
+
+constexpr int kTrainBlock = 256;
+
+__global__ __launch_bounds__(kTrainBlock) void k_train_fwd_mfma(NrcNet net, NrcBatch b) {
+    __shared__ float s_loss[kTrainBlock / 64];
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
+    const int n = b.n;
+    const size_t nn = (size_t)n;
+    const long long base = ((long long)blockIdx.x * (kTrainBlock / 64) + wv) * 64;
     float contrib = 0.0f;
-    if (r < b.n) {
-        float h[kNrcHid], g[kNrcHid];
-        features(net, b.x + 3 * (size_t)r, b.w + 3 * (size_t)r, b.lam[r], h);
-        const size_t n = (size_t)b.n;
+    if (base < n) {
+        float h[4][16];
 #pragma unroll
-        for (int j = 0; j < kNrcIn; ++j) b.acts[(size_t)j * n + r] = h[j];
-        const float* W = net.p + net.off_W();
-        const float* bb = net.p + net.off_b();
+        for (int nt = 0; nt < 4; ++nt) {
+            const long long row = base + nt * 16 + c;
+            const long long rr = min(row, (long long)n - 1);
+            float xn[3];
+            normalise(net, b.x + 3 * rr, xn);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int l = (q < 2 ? 0 : 8) + 2 * g + (q & 1);
+                const float2 e = hash_level(net, l, net.res[l], net.dense[l], xn);
+                h[nt][2 * q] = e.x;
+                h[nt][2 * q + 1] = e.y;
+            }
+            float sh[kNrcSh];
+            sh_features(net.shK, b.w[3 * rr], b.w[3 * rr + 1], b.w[3 * rr + 2], sh);
+            const float lm = b.lam[rr];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                h[nt][8 + i] = pick4(sh, g, i);
+                h[nt][12 + i] = blob_bin(net, lm, 4 * g + i);
+            }
+            if (row < n)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) b.acts[(size_t)frag_feature(q, g) * nn + row] = h[nt][q];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll 1
         for (int k = 0; k < kNrcLayers; ++k) {
-            layer(W + k * kNrcHid * kNrcHid, bb + k * kNrcHid, h, g);
-            float* a = b.acts + (size_t)(k + 1) * kNrcHid * n;
+            const float* wf = net.wf + (size_t)k * 4 * 16 * 64 + lane;
+            const float* bk = net.p + net.off_b() + k * kNrcHid;
+            f32x4 acc[4][4];
 #pragma unroll
-            for (int j = 0; j < kNrcHid; ++j) {
-                a[(size_t)j * n + r] = g[j];
-                h[j] = g[j];
+            for (int mt = 0; mt < 4; ++mt) {
+                const f32x4 bias = {bk[16 * mt + 4 * g], bk[16 * mt + 4 * g + 1], bk[16 * mt + 4 * g + 2],
+                                    bk[16 * mt + 4 * g + 3]};
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) acc[nt][mt] = bias;
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const float a = wf[(mt * 16 + t) * 64];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+                        acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, h[nt][t], acc[nt][mt], 0, 0, 0);
+                }
+            }
+            float* a_out = b.acts + (size_t)(k + 1) * kNrcHid * nn;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const long long row = base + nt * 16 + c;
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) h[nt][4 * mt + i] = fmaxf(acc[nt][mt][i], 0.0f);
+                if (row < n)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) a_out[(size_t)frag_feature(q, g) * nn + row] = h[nt][q];
             }
         }
-        const float s = output(net, h);
-        const float t = b.t[r];
-        const float den = s * s + 0.01f;
-        b.y[r] = s;
-        b.dy[r] = 2.0f * (s - t) / den / (float)b.n;
-        contrib = (s - t) * (s - t) / den / (float)b.n;
-    }
-    s_loss[threadIdx.x] = contrib;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) s_loss[threadIdx.x] += s_loss[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(b.loss, s_loss[0]);
-}
-
-// training backward per row: dz of every layer, then the hash-table gradient
-__global__ __launch_bounds__(256) void k_train_bwd(NrcNet net, NrcBatch b) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= b.n) return;
-    const size_t n = (size_t)b.n;
-    const float* wo = net.p + net.off_wo();
-    const float* W = net.p + net.off_W();
-    float dh[kNrcHid], dz[kNrcHid];
-    const float dy = b.dy[r];
+        const float* wo = net.p + net.off_wo();
+        const float bo = net.p[net.off_bo()];
 #pragma unroll
-    for (int j = 0; j < kNrcHid; ++j) dh[j] = dy * wo[j];
-    for (int k = kNrcLayers - 1; k >= 0; --k) {
-        const float* a = b.acts + (size_t)(k + 1) * kNrcHid * n;
-        float* z = b.dz + (size_t)k * kNrcHid * n;
-#pragma unroll
-        for (int i = 0; i < kNrcHid; ++i) {
-            dz[i] = a[(size_t)i * n + r] > 0.0f ? dh[i] : 0.0f;
-            z[(size_t)i * n + r] = dz[i];
-        }
-        const float* Wk = W + k * kNrcHid * kNrcHid;
-#pragma unroll
-        for (int j = 0; j < kNrcHid; ++j) {
+        for (int nt = 0; nt < 4; ++nt) {
             float s = 0.0f;
 #pragma unroll
-            for (int i = 0; i < kNrcHid; ++i) s = fmaf(Wk[i * kNrcHid + j], dz[i], s);
-            dh[j] = s;
+            for (int q = 0; q < 16; ++q) s = fmaf(wo[frag_feature(q, g)], h[nt][q], s);
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            const long long row = base + nt * 16 + c;
+            if (g == 0 && row < n) {
+                const float y = s + bo, t = b.t[row];
+                const float den = y * y + 0.01f;
+                b.y[row] = y;
+                b.dy[row] = 2.0f * (y - t) / den / (float)n;
+                contrib += (y - t) * (y - t) / den / (float)n;
+            }
         }
     }
-    // dh is now dloss / d(input features); scatter its hash part
-    float xn[3];
-    normalise(net, b.x + 3 * (size_t)r, xn);
 #pragma unroll
-    for (int l = 0; l < kNrcLevels; ++l) {
-        const int N = net.res[l];
-        int i0[3];
-        float f[3];
-        level_setup(N, xn, i0, f);
-        float2* gt = reinterpret_cast<float2*>(net.g) + (size_t)l * net.T;
+    for (int o = 32; o > 0; o >>= 1) contrib += __shfl_xor(contrib, o);
+    if (lane == 0) s_loss[wv] = contrib;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w2 = 0; w2 < kTrainBlock / 64; ++w2) t += s_loss[w2];
+        atomicAdd(b.loss, t);
+    }
+}
+
+__global__ __launch_bounds__(kTrainBlock) void k_train_bwd_mfma(NrcNet net, NrcBatch b) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
+    const int n = b.n;
+    const size_t nn = (size_t)n;
+    const long long base = ((long long)blockIdx.x * (kTrainBlock / 64) + wv) * 64;
+    if (base >= n) return;
+    const float* wo = net.p + net.off_wo();
+    float d[4][16];  // gradient w.r.t. the current layer's output, fragment layout
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const float wc = corner_weight(f, c);
-            const uint32_t s =
-                corner_slot(N, net.dense[l], net.T, i0[0] + (c & 1), i0[1] + ((c >> 1) & 1), i0[2] + (c >> 2));
-            float* gp = reinterpret_cast<float*>(gt + s);
-            atomicAdd(gp, wc * dh[2 * l]);
-            atomicAdd(gp + 1, wc * dh[2 * l + 1]);
+    for (int nt = 0; nt < 4; ++nt) {
+        const long long row = base + nt * 16 + c;
+        const float dy = row < n ? b.dy[row] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) d[nt][q] = dy * wo[frag_feature(q, g)];
+    }
+#pragma unroll 1
+    for (int k = kNrcLayers - 1; k >= 0; --k) {
+        const float* a_k = b.acts + (size_t)(k + 1) * kNrcHid * nn;
+        float* z_k = b.dz + (size_t)k * kNrcHid * nn;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const long long row = base + nt * 16 + c;
+            const long long rr = min(row, (long long)n - 1);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const size_t at = (size_t)frag_feature(q, g) * nn;
+                d[nt][q] = a_k[at + rr] > 0.0f ? d[nt][q] : 0.0f;
+                if (row < n) z_k[at + row] = d[nt][q];
+            }
+        }
+        const float* wf = net.wf + (size_t)(kNrcLayers + k) * 4 * 16 * 64 + lane;  // W_k^T fragments
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[nt][mt] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const float a = wf[(mt * 16 + t) * 64];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, d[nt][t], acc[nt][mt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) d[nt][4 * mt + i] = acc[nt][mt][i];
+    }
+    // d is now dloss / d(input features); its slots 0..7 are hash levels 2g, 2g+1, 8+2g, 9+2g
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const long long row = base + nt * 16 + c;
+        if (row >= n) continue;
+        float xn[3];
+        normalise(net, b.x + 3 * row, xn);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int l = (q < 2 ? 0 : 8) + 2 * g + (q & 1);
+            const int N = net.res[l];
+            int i0[3];
+            float f[3];
+            level_setup(N, xn, i0, f);
+            float2* gt = reinterpret_cast<float2*>(net.g) + (size_t)l * net.T;
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc) {
+                const float wc = corner_weight(f, cc);
+                const uint32_t sl = corner_slot(N, net.dense[l], net.T, i0[0] + (cc & 1), i0[1] + ((cc >> 1) & 1),
+                                                i0[2] + (cc >> 2));
+                float* gp = reinterpret_cast<float*>(gt + sl);
+                atomicAdd(gp, wc * d[nt][2 * q]);
+                atomicAdd(gp + 1, wc * d[nt][2 * q + 1]);
+            }
         }
     }
 }
@@ -345,14 +459,6 @@ __global__ void k_zero(float* p, long long n) {
 // as a 16-row tile whose row 0 is wo (the others zero): the output of a
 // column is D row 0, held by the lanes of group 0.
 // ---------------------------------------------------------------------------
-
-// a[4 g + j] by selects on register values (an indexed read would place a in scratch)
-__device__ __forceinline__ float pick4(const float* a, int g, int j) {
-    float v0 = a[j], v1 = a[4 + j], v2 = a[8 + j], v3 = a[12 + j];
-    asm volatile("" : "+v"(v0), "+v"(v1), "+v"(v2), "+v"(v3));
-    const float lo = (g & 1) ? v1 : v0, hi = (g & 1) ? v3 : v2;
-    return (g & 2) ? hi : lo;
-}
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
@@ -632,6 +738,18 @@ __global__ void k_pack(NrcNet net) {
     }
 }
 
+// hidden weights -> FP32 training fragments: [dir][k][mt][t][lane], dir 0 = W
+// (A[16 mt + c][F(t, g)]), dir 1 = W^T (A[16 mt + c][F(t, g)] = W[F(t, g)][16 mt + c])
+__global__ void k_pack32(NrcNet net) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kNrcFrags32) return;
+    const int lane = e & 63, t = (e >> 6) & 15, mt = (e >> 10) & 3, kk = e >> 12;  // kk = dir * 5 + k
+    const int dir = kk / kNrcLayers, k = kk % kNrcLayers;
+    const int m = 16 * mt + (lane & 15), fin = frag_feature(t, lane >> 4);
+    const float* W = net.p + net.off_W() + (size_t)k * kNrcHid * kNrcHid;
+    net.wf[e] = dir == 0 ? W[m * kNrcHid + fin] : W[fin * kNrcHid + m];
+}
+
 inline unsigned nblocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -686,15 +804,18 @@ hipError_t nrc_launch_unpack(const float4* rows, int k, int S, int m, int n, flo
 
 hipError_t nrc_launch_pack(const NrcNet& net, hipStream_t st) {
     hipLaunchKernelGGL(k_pack, dim3(nblocks(kNrcFragsAll, 256)), dim3(256), 0, st, net);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pack32, dim3(nblocks(kNrcFrags32, 256)), dim3(256), 0, st, net);
     return hipGetLastError();
 }
 
 hipError_t nrc_launch_grad(const NrcNet& net, const NrcBatch& b, hipStream_t st) {
     if (b.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_train_fwd, dim3(nblocks(b.n, 256)), dim3(256), 0, st, net, b);
+    hipLaunchKernelGGL(k_train_fwd_mfma, dim3(nblocks(b.n, kTrainBlock)), dim3(kTrainBlock), 0, st, net, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_train_bwd, dim3(nblocks(b.n, 256)), dim3(256), 0, st, net, b);
+    hipLaunchKernelGGL(k_train_bwd_mfma, dim3(nblocks(b.n, kTrainBlock)), dim3(kTrainBlock), 0, st, net, b);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int rows_per_block = 1024;
