@@ -26,10 +26,14 @@ REC_BYTES = 40                 # queue record: (o, t_enter) 16 B + (d, path) 16 
 HIT_BYTES = 8
 COPY_FLOATS = 1 << 28          # plain device copy of 1 GiB, for scaling FETCH_SIZE / WRITE_SIZE
 
-# HBM bytes of k_trace measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on
-# the room-scale workload, valid only while the kernel sources are unchanged
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_traffic_furnished_room_512x512_16spp.txt")
-TRACE_SOURCES = ["kernels.hip", "layout.h", "device_math.h"]
+# HBM bytes of the dominant kernel measured with rocprofv3 --pmc FETCH_SIZE /
+# WRITE_SIZE, valid only while that kernel's sources are unchanged
+TRAFFIC = {
+    "furnished_room": (os.path.join(ROOT, "profiles", "k_trace_traffic_furnished_room_512x512_16spp.txt"),
+                       ["kernels.hip", "layout.h", "device_math.h"]),
+    "nrc_room": (os.path.join(ROOT, "profiles", "k_query_mfma_traffic_nrc_room_1920x1080_4spp.txt"),
+                 ["nrc.hip", "nrc.h"]),
+}
 
 
 def log(*a):
@@ -60,24 +64,28 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16
 ROOM_LO, ROOM_HI = (0.0, 0.0, 0.0), (4.0, 3.0, 2.5)
 
 
-def trace_source_hash():
+def source_hash(sources):
     import hashlib
     h = hashlib.sha256()
-    for f in TRACE_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_1912_06474_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
 def measured_traffic(workload, grid):
-    """HBM bytes per k_trace launch from the committed counter summary, or None
-    if it was taken on other kernel sources or another workload."""
+    """HBM bytes per launch of the workload's dominant kernel from the committed
+    counter summary, or None if it was taken on other kernel sources or another
+    workload."""
+    if workload not in TRAFFIC:
+        return None
+    path, sources = TRAFFIC[workload]
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             kv = dict(l.strip().split("=", 1) for l in fh if "=" in l and not l.lstrip().startswith("#"))
     except OSError:
         return None
-    if kv.get("source_sha256") != trace_source_hash():
+    if kv.get("source_sha256") != source_hash(sources):
         return None
     if kv.get("workload") != workload or kv.get("grid") != "x".join(map(str, grid)):
         return None
@@ -146,7 +154,9 @@ def nrc_comparison(args, tr, scene, wl):
     import scenegen
 
     W, H, spp, D = wl["W"], wl["H"], wl["spp"], wl["D"]
-    cfg = wl["nrc"]
+    cfg = dict(wl["nrc"])
+    if args.ref_frames:
+        cfg["ref_frames"] = args.ref_frames
     nl = len(scene["lambda_nm"])
     cam = scene["camera"]
 
@@ -251,13 +261,14 @@ def nrc_comparison(args, tr, scene, wl):
                       "rays_lambda_per_s": (stn["ext_rays"] + stn["shadow_rays"]) * nl / t_nrc,
                       "rel_mse": hn[-1][2], "reached_target": reached,
                       "fit_a_b": fn[:2], "frames_to_1pct_extrapolated": fn[2],
-                      "ms_query_per_frame": stn["ms_nrc_query"] / nrc_frames,
+                      "ms_query_mfma_per_frame": stn["ms_nrc_query"] / nrc_frames,
                       "ms_train_per_frame": stn["ms_nrc_train"] / nrc_frames},
             "speedup_at_equal_quality": (t_plain / t_nrc) if reached else None,
         },
         "roofline": {"bound": "mfma", "kernel": "k_query_mfma", "achieved": achieved,
                      "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
-                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": avg_ms, "launches": launches},
+                     "traffic": measured_traffic(args.workload, wl["grid"]), "flops_per_launch": flops,
+                     "avg_launch_ms": avg_ms, "launches": launches},
     }
 
 
@@ -274,6 +285,8 @@ def main():
                     help="trace one extra (untimed) frame counting BVH node visits and triangle tests")
     ap.add_argument("--device-bvh", action="store_true",
                     help="build the subdomain BVHs on the GPU (linear BVH per cell) instead of the host SAH build")
+    ap.add_argument("--ref-frames", type=int, default=None,
+                    help="nrc_room: frames in each half of the plain reference (default 48)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()

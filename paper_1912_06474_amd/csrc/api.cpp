@@ -1310,11 +1310,22 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
         st = run_sweeps(c, -1, ph_sh(D), cap, count, timing, D, N);
         if (st != SDD_OK) return st;
         if (nrc) {  // cache values at the batch's cache vertices, every wavelength
-            Timer tm(c, timing, 4);
             c->nrc_query_rows += (long long)N * c->nl;
             ++c->nrc_query_launches;
-            HIP_TRY(c, nrc_launch_query(c->nrc, N, c->nrc_cx, c->nrc_cn, c->d_lam, c->nl, c->nlp, c->nrc_lhat,
-                                        c->nrc_precision, c->nrc_hop, c->nrc_sop, c->stream));
+            if (c->nrc_precision == 0) {
+                Timer tm(c, timing, 4);
+                HIP_TRY(c, nrc_launch_query(c->nrc, N, c->nrc_cx, c->nrc_cn, c->d_lam, c->nl, c->nlp, c->nrc_lhat, 1,
+                                            0, c->nrc_hop, c->nrc_sop, c->stream));
+            } else {
+                {
+                    Timer tm(c, timing, 3);
+                    HIP_TRY(c, nrc_launch_query_operands(c->nrc, N, c->nrc_cx, c->nrc_cn, c->nrc_hop, c->nrc_sop,
+                                                         c->stream));
+                }
+                Timer tm(c, timing, 4);  // the matrix-core kernel alone
+                HIP_TRY(c, nrc_launch_query_mfma(c->nrc, N, c->nrc_hop, c->nrc_sop, c->d_lam, c->nl, c->nlp,
+                                                 c->nrc_lhat, 1, c->stream));
+            }
         }
         for (const Seg& sg : segs) {
             const sdd_trace_desc* t = sg.j->t;
@@ -1903,8 +1914,8 @@ sdd_status sdd_nrc_query(sdd_ctx* c, int32_t n, const float* x4, const float* n4
         if (st != SDD_OK) return st;
     }
     const hipError_t e = nrc_launch_query(c->nrc, n, reinterpret_cast<const float4*>(x4),
-                                          reinterpret_cast<const float4*>(n4), c->d_lam, c->nl, c->nlp, out, precision,
-                                          c->nrc_hop, c->nrc_sop, c->stream);
+                                          reinterpret_cast<const float4*>(n4), c->d_lam, c->nl, c->nlp, out, 0,
+                                          precision, c->nrc_hop, c->nrc_sop, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "nrc query");
     return SDD_OK;
 }

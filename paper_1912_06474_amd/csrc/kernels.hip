@@ -837,8 +837,11 @@ __global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
                         }
                         L = f4fma(f4scale(f4mul(beta, leL), gfac), trv, L);
                     }
-                    if (P.lhat && v[j].y == 1)  // the path's cache vertex: beta (after rho) times the cache
-                        L = f4fma(beta, *reinterpret_cast<const float4*>(P.lhat + (size_t)pid * P.nlp + l0), L);
+                    if (P.lhat && v[j].y == 1) {  // the path's cache vertex: beta (after rho) times the cache
+                        // cache values tiled by 16 paths: [pid / 16][l][pid % 16]
+                        const float* lh = P.lhat + (size_t)(pid >> 4) * P.nlp * 16 + (size_t)l0 * 16 + (pid & 15);
+                        L = f4fma(beta, make_float4(lh[0], lh[16], lh[32], lh[48]), L);
+                    }
                 } else if ((kind == kVGlassR || kind == kVGlassT) && !(x & kVLast)) {
                     const int gi = min(max(x >> kVIdShift, 0), P.n_glass - 1);
                     const float PR = __int_as_float(v[j].z);

@@ -278,7 +278,7 @@ struct SpectralParams {
     int light_mat;
     float* acc;            // [WH][nlp]
     int* shadow_log;
-    const float* lhat;     // [N_all][nlp] cache values at the paths' cache vertices, or null
+    const float* lhat;     // [N_all / 16][nlp][16] cache values at the paths' cache vertices, or null
 };
 
 // training rows of the radiance cache from the training paths of one batch

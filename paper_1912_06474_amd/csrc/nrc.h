@@ -68,13 +68,27 @@ hipError_t nrc_launch_infer(const NrcNet& net, int n, const float* x, const floa
 // BF16 matrix-core forward (FP32 accumulation); needs net.wq packed from the current weights
 hipError_t nrc_launch_infer_mfma(const NrcNet& net, int n, const float* x, const float* w, const float* lam,
                                  float* y, hipStream_t st);
-// cache values of n paths at nl wavelengths: lhat[path * nlp + l] for the
+// Position of the cache value of (path, wavelength l) in an [n][nlp] array:
+// row-major, or tiled by 16 paths, [path / 16][l][path % 16], which the query
+// writes in whole 64-byte runs (16 paths of one wavelength) -- the render's
+// layout.  n must be a multiple of 16 for the tiled form.
+__host__ __device__ inline size_t nrc_lhat_index(long long path, int l, int nlp, int tiled) {
+    return tiled ? (size_t)(path >> 4) * (size_t)nlp * 16 + (size_t)l * 16 + (size_t)(path & 15)
+                 : (size_t)path * nlp + l;
+}
+
+// cache values of n paths at nl wavelengths, lhat[nrc_lhat_index(path, l)], for the
 // cache vertex (cx, cn) of each path (precision 0: FP32, 1: BF16 matrix cores,
 // which stage the paths' operands in hop, sop: nrc_query_ops_paths(n) entries
 // each -- 4 lane groups of 16 B and 8 B per path; unused for precision 0)
 long long nrc_query_ops_paths(int n);
 hipError_t nrc_launch_query(const NrcNet& net, int n, const float4* cx, const float4* cn, const float* lam, int nl,
-                            int nlp, float* lhat, int precision, uint4* hop, uint2* sop, hipStream_t st);
+                            int nlp, float* lhat, int tiled, int precision, uint4* hop, uint2* sop, hipStream_t st);
+// the two stages of the BF16 query: operand gathers, then the matrix-core network
+hipError_t nrc_launch_query_operands(const NrcNet& net, int n, const float4* cx, const float4* cn, uint4* hop,
+                                     uint2* sop, hipStream_t st);
+hipError_t nrc_launch_query_mfma(const NrcNet& net, int n, const uint4* hop, const uint2* sop, const float* lam,
+                                 int nl, int nlp, float* lhat, int tiled, hipStream_t st);
 // stable compaction of the training rows (pairs of float4) whose flag is set;
 // with temp == nullptr only sets *temp_bytes
 hipError_t nrc_select_rows(const float4* rows, const int* ok, int n, float4* out, int* d_count, void* temp,

@@ -636,7 +636,7 @@ __global__ __launch_bounds__(256) void k_query_operands(NrcNet net, int n, const
 // weights, so three blocks fit a CU.  Same products and summation order as
 // k_infer_mfma.
 __global__ __launch_bounds__(kMfmaBlock) void k_query_mfma(NrcNet net, int n, const uint4* hop, const uint2* sop,
-                                                          const float* lam, int nl, int nlp, float* lhat) {
+                                                          const float* lam, int nl, int nlp, float* lhat, int tiled) {
     __shared__ MfmaLds L;
     mfma_stage(net, L);
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
@@ -673,14 +673,14 @@ __global__ __launch_bounds__(kMfmaBlock) void k_query_mfma(NrcNet net, int n, co
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const long long row = base + nt * 16 + c;
-            if (g == 0 && row < n) lhat[row * nlp + l] = out[nt];
+            if (g == 0 && row < n) lhat[nrc_lhat_index(row, l, nlp, tiled)] = out[nt];
         }
     }
 }
 
 // FP32 cache values, one thread per (path, wavelength), as k_infer
 __global__ __launch_bounds__(256) void k_query(NrcNet net, int n, const float4* cx, const float4* cn, const float* lam,
-                                               int nl, int nlp, float* lhat) {
+                                               int nl, int nlp, float* lhat, int tiled) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)n * nl) return;
     const int path = (int)(t / nl), l = (int)(t - (long long)path * nl);
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(256) void k_query(NrcNet net, int n, const float4* 
 #pragma unroll
         for (int j = 0; j < kNrcHid; ++j) h[j] = g[j];
     }
-    lhat[(size_t)path * nlp + l] = output(net, h);
+    lhat[nrc_lhat_index(path, l, nlp, tiled)] = output(net, h);
 }
 
 // training batch k of S: rows (k + i S) m, i < n, of the compacted rows, into SoA
@@ -773,19 +773,31 @@ hipError_t nrc_launch_infer_mfma(const NrcNet& net, int n, const float* x, const
 long long nrc_query_ops_paths(int n) { return ((long long)n + kMfmaRowsPerWave - 1) / kMfmaRowsPerWave * kMfmaRowsPerWave; }
 
 hipError_t nrc_launch_query(const NrcNet& net, int n, const float4* cx, const float4* cn, const float* lam, int nl,
-                            int nlp, float* lhat, int precision, uint4* hop, uint2* sop, hipStream_t st) {
+                            int nlp, float* lhat, int tiled, int precision, uint4* hop, uint2* sop, hipStream_t st) {
     if (n <= 0 || nl <= 0) return hipSuccess;
     if (precision == 0) {
         hipLaunchKernelGGL(k_query, dim3(nblocks((long long)n * nl, 256)), dim3(256), 0, st, net, n, cx, cn, lam, nl,
-                           nlp, lhat);
+                           nlp, lhat, tiled);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_query_operands, dim3(nblocks(n, 256)), dim3(256), 0, st, net, n, cx, cn, hop, sop);
-    hipError_t e = hipGetLastError();
+    hipError_t e = nrc_launch_query_operands(net, n, cx, cn, hop, sop, st);
     if (e != hipSuccess) return e;
+    return nrc_launch_query_mfma(net, n, hop, sop, lam, nl, nlp, lhat, tiled, st);
+}
+
+hipError_t nrc_launch_query_operands(const NrcNet& net, int n, const float4* cx, const float4* cn, uint4* hop,
+                                     uint2* sop, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_query_operands, dim3(nblocks(n, 256)), dim3(256), 0, st, net, n, cx, cn, hop, sop);
+    return hipGetLastError();
+}
+
+hipError_t nrc_launch_query_mfma(const NrcNet& net, int n, const uint4* hop, const uint2* sop, const float* lam,
+                                 int nl, int nlp, float* lhat, int tiled, hipStream_t st) {
+    if (n <= 0 || nl <= 0) return hipSuccess;
     const int rows_per_block = (kMfmaBlock / 64) * kMfmaRowsPerWave;
     hipLaunchKernelGGL(k_query_mfma, dim3(nblocks(n, rows_per_block)), dim3(kMfmaBlock), 0, st, net, n, hop, sop,
-                       lam, nl, nlp, lhat);
+                       lam, nl, nlp, lhat, tiled);
     return hipGetLastError();
 }
 
