@@ -202,7 +202,9 @@ typedef struct sdd_stats {
     int64_t paths_per_batch;
     int32_t overflow;          /* nonzero: a shadow segment crossed more panes than supported */
     int32_t pad_;
-    double ms_nrc_query;       /* cache queries of SDD_TRACE_NRC renders (SDD_TRACE_TIME_KERNELS) */
+    double ms_nrc_query;       /* cache-network launches of SDD_TRACE_NRC renders (SDD_TRACE_TIME_KERNELS;
+                                  with BF16 queries the matrix-core kernel alone, its operand gathers
+                                  count in ms_other) */
     double ms_nrc_train;       /* cache training after those renders (SDD_TRACE_TIME_KERNELS) */
     int64_t nrc_query_rows;    /* (path, wavelength) cache queries */
     int64_t nrc_query_launches;

@@ -940,23 +940,39 @@ __global__ __launch_bounds__(256) void k_nrc_rows(NrcRowParams P) {
 }
 
 // FP64: mean over samples and XYZ = sum_l w_l cmf_l L_l
-__global__ void k_resolve(int WH, int nl, int nlp, double inv_spp, const float* __restrict__ acc,
-                          const double* __restrict__ w, const double* __restrict__ cmf, double* spectral,
-                          double* xyz) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= WH) return;
-    double X = 0.0, Y = 0.0, Z = 0.0;
-    for (int l = 0; l < nl; ++l) {
-        const double v = (double)acc[(size_t)p * nlp + l] * inv_spp;
-        if (spectral) spectral[(size_t)p * nl + l] = v;
-        X += w[l] * cmf[3 * l] * v;
-        Y += w[l] * cmf[3 * l + 1] * v;
-        Z += w[l] * cmf[3 * l + 2] * v;
+// 64 pixels per block: their accumulator rows (contiguous) are staged in LDS
+// with coalesced loads, the spectral means are written as one contiguous run,
+// and one thread per pixel forms XYZ
+constexpr int kResolvePix = 64;
+__global__ __launch_bounds__(256) void k_resolve(int WH, int nl, int nlp, double inv_spp, const float* __restrict__ acc,
+                                                 const double* __restrict__ w, const double* __restrict__ cmf,
+                                                 double* spectral, double* xyz) {
+    __shared__ float s_acc[kResolvePix * 128];
+    const int p0 = blockIdx.x * kResolvePix;
+    const int np = min(kResolvePix, WH - p0);
+    const float* src = acc + (size_t)p0 * nlp;
+    for (int e = threadIdx.x; e < np * nlp; e += blockDim.x) s_acc[e] = src[e];
+    __syncthreads();
+    if (spectral) {
+        double* dst = spectral + (size_t)p0 * nl;
+        for (int e = threadIdx.x; e < np * nl; e += blockDim.x) {
+            const int pp = e / nl, l = e - pp * nl;
+            dst[e] = (double)s_acc[pp * nlp + l] * inv_spp;
+        }
     }
-    if (xyz) {
-        xyz[3 * (size_t)p] = X;
-        xyz[3 * (size_t)p + 1] = Y;
-        xyz[3 * (size_t)p + 2] = Z;
+    if (xyz && (int)threadIdx.x < np) {
+        const int pp = threadIdx.x;
+        double X = 0.0, Y = 0.0, Z = 0.0;
+        for (int l = 0; l < nl; ++l) {
+            const double v = (double)s_acc[pp * nlp + l] * inv_spp;
+            X += w[l] * cmf[3 * l] * v;
+            Y += w[l] * cmf[3 * l + 1] * v;
+            Z += w[l] * cmf[3 * l + 2] * v;
+        }
+        const size_t p = (size_t)(p0 + pp);
+        xyz[3 * p] = X;
+        xyz[3 * p + 1] = Y;
+        xyz[3 * p + 2] = Z;
     }
 }
 
@@ -1074,8 +1090,9 @@ hipError_t launch_nrc_rows(const NrcRowParams& p, hipStream_t st) {
 
 hipError_t launch_resolve(int WH, int nl, int nlp, double inv_spp, const float* acc, const double* w,
                           const double* cmf, double* spectral, double* xyz, hipStream_t st) {
-    hipLaunchKernelGGL(k_resolve, dim3(blocks_for(WH, 256)), dim3(256), 0, st, WH, nl, nlp, inv_spp, acc, w, cmf,
-                       spectral, xyz);
+    if (nlp > 128) return hipErrorInvalidValue;  // the LDS staging holds 128 wavelengths per pixel
+    hipLaunchKernelGGL(k_resolve, dim3(blocks_for(WH, kResolvePix)), dim3(256), 0, st, WH, nl, nlp, inv_spp, acc, w,
+                       cmf, spectral, xyz);
     return hipGetLastError();
 }
 
