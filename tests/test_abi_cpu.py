@@ -130,3 +130,23 @@ def test_tracer_refuses_without_gpu(sdd):
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         sdd.Tracer()
+
+
+def test_nrc_param_count(sdd):
+    L = sdd.lib()
+    for log2 in (10, 14, 19, 24):
+        assert L.sdd_nrc_param_count(log2) == 16 * (1 << log2) * 2 + 5 * 64 * 64 + 5 * 64 + 64 + 1
+    assert L.sdd_nrc_param_count(9) == -1
+    assert L.sdd_nrc_param_count(25) == -1
+
+
+def test_nrc_flatten_roundtrip(sdd):
+    import scenegen as sg
+    params, tables = sg.nrc_params(1, table_size=1 << 10)
+    flat = sdd.nrc_flatten(params, tables)
+    assert flat.size == sdd.lib().sdd_nrc_param_count(10)
+    p2, t2 = sdd.nrc_unflatten(flat, 1 << 10)
+    assert np.array_equal(t2, tables)
+    for k in range(5):
+        assert np.array_equal(p2["W"][k], params["W"][k]) and np.array_equal(p2["b"][k], params["b"][k])
+    assert np.array_equal(p2["wo"], params["wo"]) and p2["bo"] == float(params["bo"])

@@ -174,3 +174,65 @@ def test_bf16_queries_and_training_in_the_render(tracer):
     assert diff <= 0.1
     assert steps == 3 and np.isfinite(loss) and len(rows) > 0
     assert not np.array_equal(t1, tables)  # the tables moved
+
+
+def test_cache_render_across_batches(tracer):
+    """Small memory budgets split the call into many batches: the training
+    slots of each batch segment are found from the call's path numbering, so
+    image and rows equal the one-batch render bit for bit."""
+    import os
+    sc = sg.tiny_room(0, 16)
+    W, H, spp, D = 64, 48, 3, 5
+    one, rows1, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), 700, sample_offset=5)
+    old = os.environ.get("SDD_MEM_BUDGET_GB")
+    os.environ["SDD_MEM_BUDGET_GB"] = "0.002"
+    try:
+        tracer.reset_stats()
+        many, rows2, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), 700, sample_offset=5)
+        batches = tracer.stats()["batches"]
+    finally:
+        if old is None:
+            del os.environ["SDD_MEM_BUDGET_GB"]
+        else:
+            os.environ["SDD_MEM_BUDGET_GB"] = old
+    print(f"[nrc_render] {batches} batches, {len(rows2)} rows", flush=True)
+    assert batches > 3
+    assert np.array_equal(one["spectral"], many["spectral"])
+    assert np.array_equal(one["hit_log"], many["hit_log"])
+    assert np.array_equal(rows1, rows2)
+
+
+def test_cache_render_coated_panes_match_oracle(tracer):
+    """Training-row targets through coated (electrochromic) panes."""
+    sc = sg.tiny_room(0, 16, coating_state=0.5)
+    W, H, spp, D = 48, 48, 2, 6
+    g, rows, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), 600)
+    stride = -(-(W * H * spp) // 600)
+    o = ora.render(sc, W, H, spp, D, logs=True, seed=0, nrc=dict(stride=stride, c=COEF, lo=LO, hi=HI))
+    assert_parity(g, o)
+    orows = _oracle_rows(o, W, H, spp)
+    assert len(rows) == len(orows) and len(rows) > 0
+    t, to = rows[:, 7].astype(np.float64), orows[:, 8]
+    err = np.abs(t - to) / (np.abs(to) + 1e-6)
+    print(f"[nrc_render] coated: {len(rows)} rows, max rel err {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-4
+
+
+@pytest.mark.parametrize("D", [1, 2])
+def test_cache_render_shallow_depths(tracer, D):
+    """D = 1: no vertex reaches depth 2, the cache render is the plain render.
+    D = 2: the cache vertex is the last vertex; no training path continues, so
+    no rows."""
+    sc = sg.tiny_room(0, 16)
+    W, H, spp = 32, 32, 2
+    g, rows, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), 300)
+    assert len(rows) == 0
+    if D == 1:
+        tracer.trace_spectral(sc["camera"], W, H, spp, D, seed=0, render_id=0)
+        s, _ = tracer.resolve_image(0, W, H)
+        tracer.reset_render(0)
+        assert np.array_equal(g["spectral"], s.cpu().numpy())
+    else:
+        stride = -(-(W * H * spp) // 300)
+        o = ora.render(sc, W, H, spp, D, logs=True, seed=0, nrc=dict(stride=stride, c=COEF, lo=LO, hi=HI))
+        assert_parity(g, o)
