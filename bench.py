@@ -157,6 +157,11 @@ def nrc_comparison(args, tr, scene, wl):
     cfg = dict(wl["nrc"])
     if args.ref_frames:
         cfg["ref_frames"] = args.ref_frames
+    if args.nrc_train_steps is not None:
+        cfg["train_steps"] = args.nrc_train_steps
+    if args.nrc_train_batch is not None:
+        cfg["train_batch"] = args.nrc_train_batch
+    cfg["lr"] = args.nrc_lr if args.nrc_lr is not None else 1e-2
     nl = len(scene["lambda_nm"])
     cam = scene["camera"]
 
@@ -224,8 +229,8 @@ def nrc_comparison(args, tr, scene, wl):
     log(f"[bench] plain: {args.steps} frames, {t_plain:.2f} s, rel-MSE {q:.4f}")
 
     params, tables = scenegen.nrc_params(0)
-    tr.nrc_init(params, tables, ROOM_LO, ROOM_HI, train_paths=cfg["train_paths"], train_steps=cfg["train_steps"],
-                train_batch=cfg["train_batch"], precision="bf16")
+    tr.nrc_init(params, tables, ROOM_LO, ROOM_HI, lr=cfg["lr"], train_paths=cfg["train_paths"],
+                train_steps=cfg["train_steps"], train_batch=cfg["train_batch"], precision="bf16")
     tr.reset_stats()
     hn, warm_s = run(2, True, 4 * args.steps, target=q, warm=args.warmup)
     stn = tr.stats()
@@ -264,6 +269,7 @@ def nrc_comparison(args, tr, scene, wl):
                       "ms_query_mfma_per_frame": stn["ms_nrc_query"] / nrc_frames,
                       "ms_train_per_frame": stn["ms_nrc_train"] / nrc_frames},
             "speedup_at_equal_quality": (t_plain / t_nrc) if reached else None,
+            "cache_settings": {k: cfg[k] for k in ("train_paths", "train_steps", "train_batch", "lr")},
         },
         "roofline": {"bound": "mfma", "kernel": "k_query_mfma", "achieved": achieved,
                      "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
@@ -287,6 +293,9 @@ def main():
                     help="build the subdomain BVHs on the GPU (linear BVH per cell) instead of the host SAH build")
     ap.add_argument("--ref-frames", type=int, default=None,
                     help="nrc_room: frames in each half of the plain reference (default 48)")
+    ap.add_argument("--nrc-train-steps", type=int, default=None, help="nrc_room: Adam steps per frame (default 4)")
+    ap.add_argument("--nrc-train-batch", type=int, default=None, help="nrc_room: rows per Adam step (default 2^14)")
+    ap.add_argument("--nrc-lr", type=float, default=None, help="nrc_room: Adam learning rate (default 1e-2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
