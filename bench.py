@@ -291,6 +291,8 @@ def main():
                     help="trace one extra (untimed) frame counting BVH node visits and triangle tests")
     ap.add_argument("--device-bvh", action="store_true",
                     help="build the subdomain BVHs on the GPU (linear BVH per cell) instead of the host SAH build")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the same steps replayed from a captured HIP graph (no per-launch events)")
     ap.add_argument("--ref-frames", type=int, default=None,
                     help="nrc_room: frames in each half of the plain reference (default 48)")
     ap.add_argument("--nrc-train-steps", type=int, default=None, help="nrc_room: Adam steps per frame (default 4)")
@@ -356,16 +358,17 @@ def main():
 
     step = 0
 
-    def frame():
+    def frame(graph=False):
         nonlocal step
-        # every launch is bracketed by HIP events on the library's stream
+        # every launch is bracketed by HIP events on the library's stream (not in graph replays)
         if renders is None:
-            tr.trace_spectral(cam, W, H, spp, D, sample_offset=step * spp, render_id=0, time_kernels=True)
+            tr.trace_spectral(cam, W, H, spp, D, sample_offset=step * spp, render_id=0, time_kernels=not graph,
+                              graph=graph)
             tr.resolve_image(0, W, H, spectral=True, xyz=True)
         else:
             for r in renders:
                 r["sample_offset"] = step * r["spp"]
-            tr.trace_batch(renders, D, time_kernels=True)
+            tr.trace_batch(renders, D, time_kernels=not graph, graph=graph)
             for r in renders:
                 tr.resolve_image(r["render_id"], r["W"], r["H"], spectral=True, xyz=True)
         step += 1
@@ -447,6 +450,23 @@ def main():
                        "tri_tests_per_cell_visit": sw["tri_tests"] / max(1, visits),
                        "cell_visits_per_ray": visits / max(1, sw["ext_rays"] + sw["shadow_rays"]),
                        "scene_bytes_per_frame": 64 * sw["node_visits"] + 48 * sw["tri_tests"]}
+    if args.graph:
+        gt = sdd.Tracer(stream=torch.cuda.Stream())  # graph capture needs a stream other than the null stream
+        gt.load_scene(scene)
+        gt.build_bvh(*wl["grid"], device=args.device_bvh)
+        tr_main, tr = tr, gt
+        frame(graph=True)  # capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            frame(graph=True)
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - t0
+        res["graph_replay"] = {"ms_per_step": dtg / args.steps * 1e3, "value": rays * nl / dtg,
+                               "note": "same steps replayed from one captured HIP graph, without per-launch events"}
+        log(f"[bench] graph replay: {dtg / args.steps * 1e3:.2f} ms per step")
+        tr = tr_main
+        gt.close()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(scene, wl, args.cpu_seconds)
     print(json.dumps(res))

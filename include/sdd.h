@@ -142,6 +142,11 @@ typedef struct sdd_bvh_desc {
 #define SDD_TRACE_TIME_KERNELS 2u /* time every launch with HIP events (stats) */
 #define SDD_TRACE_COUNT_WORK 4u   /* count node visits / triangle tests (stats) */
 #define SDD_TRACE_NRC 8u          /* radiance-cache estimator (see sdd_nrc_desc); one render per call */
+#define SDD_TRACE_GRAPH 16u       /* capture the call's launches in a HIP graph; later calls with the
+                                     same descs except sample_offset replay it (any reallocation, new
+                                     render, reset or new scene/BVH recaptures).  Needs a context
+                                     stream other than NULL; excludes NRC and TIME_KERNELS
+                                     (SDD_ERR_UNSUPPORTED).  Same result as without it. */
 
 /*
  * One call traces spp samples of every pixel of render render_id and adds

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(HERE, "libsdd.so")
 SDD_OK = 0
 STATUS = {0: "SDD_OK", -1: "SDD_ERR_INVALID_ARG", -2: "SDD_ERR_STATE", -3: "SDD_ERR_OOM", -4: "SDD_ERR_HIP",
           -5: "SDD_ERR_OVERFLOW", -6: "SDD_ERR_UNSUPPORTED"}
-TRACE_ORTHO, TRACE_TIME_KERNELS, TRACE_COUNT_WORK, TRACE_NRC = 1, 2, 4, 8
+TRACE_ORTHO, TRACE_TIME_KERNELS, TRACE_COUNT_WORK, TRACE_NRC, TRACE_GRAPH = 1, 2, 4, 8, 16
 
 EXPORTS = ("sdd_create", "sdd_destroy", "sdd_last_error", "sdd_load_scene", "sdd_validate_scene", "sdd_build_bvh",
            "sdd_trace_spectral", "sdd_resolve_image", "sdd_reset_render", "sdd_get_stats", "sdd_reset_stats",
@@ -231,7 +231,7 @@ class Tracer:
         self._check(lib().sdd_build_bvh(self.h, C.byref(BvhDesc(nx, ny, nz, leaf_max, sah_bins, int(bool(device))))))
 
     def _desc(self, camera, W, H, spp, max_depth, seed=0, render_id=0, sample_offset=0, time_kernels=False,
-              count_work=False, hit_log=None, shadow_log=None, glass_swap=None, nrc=False):
+              count_work=False, hit_log=None, shadow_log=None, glass_swap=None, nrc=False, graph=False):
         d = TraceDesc()
         d.eye[:] = [float(x) for x in camera["eye"]]
         d.target[:] = [float(x) for x in camera["target"]]
@@ -248,6 +248,8 @@ class Tracer:
             fl |= TRACE_COUNT_WORK
         if nrc:
             fl |= TRACE_NRC
+        if graph:
+            fl |= TRACE_GRAPH
         d.flags = fl
         n_slots = int(W) * int(H) * int(spp) * int(max_depth)
         for name, t in (("hit_log", hit_log), ("shadow_log", shadow_log)):
@@ -260,22 +262,23 @@ class Tracer:
 
     def trace_spectral(self, camera, W, H, spp, max_depth, *, seed=0, render_id=0, sample_offset=0,
                        time_kernels=False, count_work=False, hit_log=None, shadow_log=None, glass_swap=None,
-                       nrc=False):
+                       nrc=False, graph=False):
         """Trace spp samples of every pixel; glass_swap = (from_material, to_material) substitutes a
         glass material for this render (photochromic state); nrc=True uses the radiance cache
-        (paths end in the cache, training paths train it after the call)."""
+        (paths end in the cache, training paths train it after the call); graph=True captures the
+        call's launches in a HIP graph replayed by later calls that differ only in sample_offset."""
         d = self._desc(camera, W, H, spp, max_depth, seed, render_id, sample_offset, time_kernels, count_work,
-                       hit_log, shadow_log, glass_swap, nrc)
+                       hit_log, shadow_log, glass_swap, nrc, graph)
         self._check(lib().sdd_trace_spectral(self.h, C.byref(d)))
 
-    def trace_batch(self, renders, max_depth, *, seed=0, time_kernels=False, count_work=False):
+    def trace_batch(self, renders, max_depth, *, seed=0, time_kernels=False, count_work=False, graph=False):
         """Several renders in one pipeline pass.  renders: list of dicts with keys camera, W, H, spp,
         render_id and optionally sample_offset, hit_log, shadow_log, glass_swap."""
         arr = (TraceDesc * len(renders))()
         for i, r in enumerate(renders):
             arr[i] = self._desc(r["camera"], r["W"], r["H"], r["spp"], max_depth, seed, r["render_id"],
                                 r.get("sample_offset", 0), time_kernels, count_work, r.get("hit_log"),
-                                r.get("shadow_log"), r.get("glass_swap"))
+                                r.get("shadow_log"), r.get("glass_swap"), graph=graph)
         self._check(lib().sdd_trace_batch(self.h, len(renders), arr))
 
     def new_log(self, W, H, spp, max_depth):

@@ -156,6 +156,15 @@ struct sdd_ctx {
     uint2* nrc_sop = nullptr;
     long long nrc_ocap = 0;
 
+    // graph replay of repeated trace calls (SDD_TRACE_GRAPH)
+    long long gen = 0;            // bumped whenever a buffer a captured graph may use is (re)allocated or freed
+    int* d_s0 = nullptr;          // per-render first sample index, read by the kernels of a graph
+    int s0_cap = 0;
+    std::vector<int> h_s0;
+    std::string graph_key;
+    hipGraphExec_t graph_exec = nullptr;
+    long long graph_cam_rays = 0, graph_launches = 0, graph_batches = 0;
+
     // host stats
     long long batches = 0, launches_trace = 0, cam_rays = 0;
     double ms[6] = {0, 0, 0, 0, 0, 0};
@@ -237,6 +246,7 @@ struct DeviceGuard {
 };
 
 void free_scene(sdd_ctx* c) {
+    ++c->gen;
     dfree(c, c->d_prim_info);
     dfree(c, c->d_prim_v);
     dfree(c, c->d_pane);
@@ -252,6 +262,7 @@ void free_scene(sdd_ctx* c) {
 }
 
 void free_accel(sdd_ctx* c) {
+    ++c->gen;
     dfree(c, c->d_nodes);
     dfree(c, c->d_cell_q);
     dfree(c, c->d_cell_nodes);
@@ -262,6 +273,7 @@ void free_accel(sdd_ctx* c) {
 }
 
 void free_batch(sdd_ctx* c) {
+    ++c->gen;
     dfree(c, c->ray_o);
     dfree(c, c->ray_d);
     dfree(c, c->hit);
@@ -331,6 +343,7 @@ void free_nrc(sdd_ctx* c) {
 }
 
 void free_renders(sdd_ctx* c) {
+    ++c->gen;
     for (auto& kv : c->renders) dfree(c, kv.second.acc);
     c->renders.clear();
 }
@@ -631,6 +644,9 @@ void sdd_destroy(sdd_ctx* c) {
     if (!c) return;
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+    dfree(c, c->d_s0);
     harvest_events(c);
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
     c->event_pool.clear();
@@ -1147,13 +1163,12 @@ sdd_status check_desc(sdd_ctx* c, const sdd_trace_desc* t, Job& j) {
 // whole pipeline once, with the per-render kernels (camera rays, shading,
 // spectral replay) launched per render segment and the routing and
 // traversal sweeps over the whole batch.
-sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
+// Path-space layout of a call's renders and the batch size (paths per pass).
+long long plan_batches(sdd_ctx* c, std::vector<Job>& jobs, long long& total_pad) {
     const int D = jobs[0].t->max_depth;
     uint32_t any_flags = 0;
     for (const Job& j : jobs) any_flags |= j.t->flags;
-    const bool timing = (any_flags & SDD_TRACE_TIME_KERNELS) != 0;
-    const bool count = (any_flags & SDD_TRACE_COUNT_WORK) != 0;
-    long long total_pad = 0;
+    total_pad = 0;
     for (Job& j : jobs) {
         j.start = total_pad;
         total_pad += (j.total + kShadeBlock - 1) / kShadeBlock * kShadeBlock;
@@ -1162,7 +1177,20 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
     long long nb = mem_budget_bytes() / (bytes_per_path(c, D) + (nrc ? 32 + 4LL * c->nlp : 0));
     nb = std::min<long long>(nb, kMaxBatch);
     nb = std::max<long long>(kShadeBlock, nb / kShadeBlock * kShadeBlock);
-    nb = std::min(nb, total_pad);
+    return std::min(nb, total_pad);
+}
+
+// s0_dev: if set, the kernels read each render's first sample index from
+// s0_dev[job] (a captured graph replays with new sample ranges)
+sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nullptr) {
+    const int D = jobs[0].t->max_depth;
+    uint32_t any_flags = 0;
+    for (const Job& j : jobs) any_flags |= j.t->flags;
+    const bool timing = (any_flags & SDD_TRACE_TIME_KERNELS) != 0;
+    const bool count = (any_flags & SDD_TRACE_COUNT_WORK) != 0;
+    const bool nrc = (any_flags & SDD_TRACE_NRC) != 0;
+    long long total_pad = 0;
+    const long long nb = plan_batches(c, jobs, total_pad);
     sdd_status st = ensure_batch(c, nb, D);
     if (st != SDD_OK) return st;
     // radiance cache (one render per call): training paths are those with
@@ -1222,6 +1250,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
             cp.H = t->H;
             cp.WH = sg.j->WH;
             cp.s0 = t->sample_offset;
+            cp.s0p = s0_dev ? s0_dev + (sg.j - jobs.data()) : nullptr;
             cp.key = make_uint2(t->seed, (uint32_t)t->render_id);
             cp.ortho = sg.j->ortho ? 1 : 0;
             for (int k = 0; k < 3; ++k) {
@@ -1296,6 +1325,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
                 sp.W = t->W;
                 sp.WH = sg.j->WH;
                 sp.s0 = t->sample_offset;
+                sp.s0p = s0_dev ? s0_dev + (sg.j - jobs.data()) : nullptr;
                 sp.spp_call = t->spp;
                 sp.key = make_uint2(t->seed, (uint32_t)t->render_id);
                 sp.hit_log = t->hit_log;
@@ -1340,6 +1370,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs) {
             xp.fgrp = make_fastdiv((uint32_t)xp.ngrp);
             xp.WH = sg.j->WH;
             xp.s0 = t->sample_offset;
+            xp.s0p = s0_dev ? s0_dev + (sg.j - jobs.data()) : nullptr;
             xp.spp_call = t->spp;
             xp.max_depth = D;
             xp.vrec = c->vrec;
@@ -1422,12 +1453,74 @@ sdd_status render_for(sdd_ctx* c, const sdd_trace_desc* t, Render*& out) {
         rd.W = t->W;
         rd.H = t->H;
         const size_t n = (size_t)c->nlp * t->W * t->H;
+        ++c->gen;
         sdd_status st = dalloc(c, &rd.acc, n);
         if (st != SDD_OK) return st;
         HIP_TRY(c, hipMemsetAsync(rd.acc, 0, sizeof(float) * n, c->stream));
         it = c->renders.emplace(t->render_id, rd).first;
     }
     out = &it->second;
+    return SDD_OK;
+}
+
+// SDD_TRACE_GRAPH: the call's whole launch sequence is captured once into a
+// HIP graph and replayed by later calls that differ only in sample_offset
+// (the kernels read each render's first sample index from d_s0).  A graph is
+// keyed by the descs without their sample offsets and by the buffer
+// generation, so any reallocation or reset recaptures.
+sdd_status trace_graph(sdd_ctx* c, int n, const sdd_trace_desc* descs, std::vector<Job>& jobs) {
+    long long total_pad = 0;
+    const long long nb = plan_batches(c, jobs, total_pad);
+    sdd_status st = ensure_batch(c, nb, descs[0].max_depth);  // allocate before any capture
+    if (st != SDD_OK) return st;
+    if (n > c->s0_cap) {
+        dfree(c, c->d_s0);
+        c->s0_cap = 0;
+        if ((st = dalloc(c, &c->d_s0, (size_t)SDD_MAX_RENDERS)) != SDD_OK) return st;
+        c->s0_cap = SDD_MAX_RENDERS;
+        ++c->gen;
+    }
+    std::string key(reinterpret_cast<const char*>(&c->gen), sizeof(c->gen));
+    key.append(reinterpret_cast<const char*>(&nb), sizeof(nb));
+    c->h_s0.assign((size_t)n, 0);
+    for (int i = 0; i < n; ++i) {
+        sdd_trace_desc d = descs[i];
+        c->h_s0[(size_t)i] = d.sample_offset;
+        d.sample_offset = 0;
+        key.append(reinterpret_cast<const char*>(&d), sizeof(d));
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_s0, c->h_s0.data(), sizeof(int) * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    if (c->graph_exec && key == c->graph_key) {
+        HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+        c->cam_rays += c->graph_cam_rays;
+        c->launches_trace += c->graph_launches;
+        c->batches += c->graph_batches;
+        for (Job& j : jobs) j.rd->spp_done += j.t->spp;
+        return SDD_OK;
+    }
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+    c->graph_key.clear();
+    const long long cr0 = c->cam_rays, lt0 = c->launches_trace, b0 = c->batches;
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    st = trace_jobs(c, jobs, c->d_s0);
+    hipGraph_t gr = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->stream, &gr);
+    if (st != SDD_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return st;
+    }
+    if (ee != hipSuccess) return hip_fail(c, ee, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (ei != hipSuccess) return hip_fail(c, ei, "hipGraphInstantiate");
+    c->graph_exec = ex;
+    c->graph_key = key;
+    c->graph_cam_rays = c->cam_rays - cr0;
+    c->graph_launches = c->launches_trace - lt0;
+    c->graph_batches = c->batches - b0;
+    HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));  // the captured work has not run yet
     return SDD_OK;
 }
 
@@ -1451,12 +1544,21 @@ sdd_status trace_call(sdd_ctx* c, int n, const sdd_trace_desc* descs) {
             if (n != 1) return fail(c, SDD_ERR_UNSUPPORTED, "radiance-cache rendering takes one render per call");
             if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "SDD_TRACE_NRC before sdd_nrc_init");
         }
+    bool graph = false;
+    for (int i = 0; i < n; ++i) graph = graph || (descs[i].flags & SDD_TRACE_GRAPH);
+    if (graph) {
+        for (int i = 0; i < n; ++i)
+            if (descs[i].flags & (SDD_TRACE_NRC | SDD_TRACE_TIME_KERNELS))
+                return fail(c, SDD_ERR_UNSUPPORTED, "SDD_TRACE_GRAPH excludes SDD_TRACE_NRC and SDD_TRACE_TIME_KERNELS");
+        if (!c->stream) return fail(c, SDD_ERR_UNSUPPORTED, "SDD_TRACE_GRAPH needs a context stream other than NULL");
+    }
     DeviceGuard g(c->device);
     for (int i = 0; i < n; ++i) {
         sdd_status st = render_for(c, &descs[i], jobs[i].rd);
         if (st != SDD_OK) return st;
     }
-    return trace_jobs(c, jobs);
+    if (!graph) return trace_jobs(c, jobs);
+    return trace_graph(c, n, descs, jobs);
 }
 
 }  // namespace
@@ -1515,6 +1617,7 @@ sdd_status sdd_resolve_image(sdd_ctx* c, int32_t render_id, double* spectral_out
 }
 
 sdd_status sdd_reset_render(sdd_ctx* c, int32_t render_id) {
+    if (c) ++c->gen;
     if (!c) return SDD_ERR_INVALID_ARG;
     auto it = c->renders.find(render_id);
     if (it == c->renders.end()) return fail(c, SDD_ERR_STATE, "unknown render_id");

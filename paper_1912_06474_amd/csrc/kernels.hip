@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
     if (valid) {
         const uint32_t q = (uint32_t)(P.pb + lpid);
         const uint32_t qs = fdiv(q, P.fwh);
-        const int s = P.s0 + P.sb + (int)qs;
+        const int s = (P.s0p ? *P.s0p : P.s0) + P.sb + (int)qs;
         const int p = (int)(q - qs * (uint32_t)P.WH);
         const int py = (int)(p / (unsigned)P.W), px = p - py * P.W;
         const uint4 r = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, 0u, 0u), P.key);
@@ -520,11 +520,12 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
         if (fl & kAlive) {
             const uint32_t q = (uint32_t)(P.pb + lpid);
             const uint32_t qs = fdiv(q, P.fwh);
-            const int s = P.s0 + P.sb + (int)qs;
+            const int s0 = P.s0p ? *P.s0p : P.s0;
+            const int s = s0 + P.sb + (int)qs;
             const int p = (int)(q - qs * (uint32_t)P.WH);
             const float2 h = P.hit[pid];
             prim = __float_as_int(h.y);
-            if (P.hit_log) P.hit_log[((long long)p * P.spp_call + (s - P.s0)) * P.max_depth + P.depth - 1] = prim;
+            if (P.hit_log) P.hit_log[((long long)p * P.spp_call + (s - s0)) * P.max_depth + P.depth - 1] = prim;
             const bool last_depth = P.depth == P.max_depth;
             int4 rec = make_int4(kVNone, 0, 0, 0);
             int sh = kShNone;
@@ -594,7 +595,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                             P.nrc.cx[pid] = xf;
                             P.nrc.cn[pid] = nf;
                         } else {  // a vertex of a training path that continues
-                            const uint64_t qc = (uint64_t)(uint32_t)(s - P.s0) * (uint64_t)P.WH + (uint64_t)p;
+                            const uint64_t qc = (uint64_t)(uint32_t)(s - s0) * (uint64_t)P.WH + (uint64_t)p;
                             const size_t slot = (size_t)(qc / P.nrc.stride) * P.max_depth + (P.depth - 1);
                             P.nrc.tx[slot] = xf;
                             P.nrc.tn[slot] = nf;
@@ -776,7 +777,8 @@ __global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
     const uint32_t q = (uint32_t)(P.pb + i);
     const uint32_t qs = fdiv(q, P.fwh);
     const int p = (int)(q - qs * (uint32_t)P.WH);
-    int s = P.s0 + P.sb + (int)qs;  // sample of the first path of p in the batch
+    const int s0 = P.s0p ? *P.s0p : P.s0;
+    int s = s0 + P.sb + (int)qs;  // sample of the first path of p in the batch
     const float4 leL = *reinterpret_cast<const float4*>(P.le + (size_t)P.light_mat * P.nlp + l0);
     float4* accp = reinterpret_cast<float4*>(P.acc + (size_t)p * P.nlp + l0);
     float4 a = *accp;
@@ -853,7 +855,7 @@ __global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
             }
             live = run;
             if (P.shadow_log && grp == 0) {
-                int* sl = P.shadow_log + ((long long)p * P.spp_call + (s - P.s0)) * P.max_depth;
+                int* sl = P.shadow_log + ((long long)p * P.spp_call + (s - s0)) * P.max_depth;
 #pragma unroll
                 for (int j = 0; j < kVBlock; ++j)
                     if (on[j] && (v[j].x & 7) == kVDiffuse && __int_as_float(v[j].w) > 0.0f)

@@ -170,6 +170,7 @@ struct ShadeParams {
     FastDiv fwh;           // division by W * H
     int W, WH;
     int s0;                // first sample index of this call
+    const int* s0p;        // if set, read the first sample index here (graph replays)
     int spp_call;
     int depth, max_depth;
     uint2 key;
@@ -209,6 +210,7 @@ struct CamParams {
     FastDiv fwh;
     int W, H, WH;
     int s0;
+    const int* s0p;        // if set, read the first sample index here (graph replays)
     uint2 key;
     int ortho;
     double eye[3], fwd[3], right[3], up[3];
@@ -262,6 +264,7 @@ struct SpectralParams {
     FastDiv fgrp;
     int WH;
     int s0, spp_call;
+    const int* s0p;        // if set, read the first sample index here (graph replays)
     int max_depth;
     const int4* vrec;      // [D][N]
     const int* sh_state;   // [D][N]
