@@ -53,6 +53,7 @@ struct sdd_ctx {
     std::string err;
     int n_cu = 256;
     int trace_grid = 0, trace_grid_max = 0;
+    int ext_bins = 1;  // direction bins per cell of the closest-hit routing
 
     // scene (host copies used by the builder)
     bool has_scene = false, has_bvh = false;
@@ -109,6 +110,7 @@ struct sdd_ctx {
     int* d_counts = nullptr;
     long long counts_len = 0;
     int* d_overflow = nullptr;
+    int* d_ktot = nullptr;  // routing key totals [2][kMaxCells * kExtBins]
     int* d_gstack = nullptr;  // traversal stack spill: (kStack - kLdsStack) ints per trace thread
     unsigned long long* d_stats = nullptr;
 
@@ -502,7 +504,7 @@ sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
         ALLOC(c->stage[k].qb, n);
         ALLOC(c->stage[k].qc, n);
         ALLOC(c->stage[k].tag, n);
-        ALLOC(c->stage[k].hist, nblk * c->G);
+        ALLOC(c->stage[k].hist, nblk * c->G * kExtBins);
     }
     ALLOC(c->d_counts, cnt_len);
 #undef ALLOC
@@ -583,6 +585,10 @@ sdd_status route(sdd_ctx* c, int N, long long cap, int ext_phase, int sh_phase, 
     r.cap = cap;
     r.active[0] = ext_phase >= 0;
     r.active[1] = sh_phase >= 0;
+    r.nbin[0] = c->ext_bins;
+    r.nbin[1] = 1;
+    r.ktot[0] = c->d_ktot;
+    r.ktot[1] = c->d_ktot + kMaxCells * kExtBins;
     for (int k = 0; k < 2; ++k) r.st[k] = c->stage[k];
     r.qa[0] = c->qa[0];
     r.qb[0] = c->qb[0];
@@ -626,6 +632,7 @@ sdd_status sdd_create(int hip_device, void* hip_stream, sdd_ctx** out) {
     c->trace_grid_max = trace_grid_for(c, 1);
     c->trace_grid = c->trace_grid_max;
     if (dalloc(c, &c->d_overflow, 1) != SDD_OK || dalloc(c, &c->d_stats, kStatCount) != SDD_OK ||
+        dalloc(c, &c->d_ktot, 2 * (size_t)kMaxCells * kExtBins) != SDD_OK ||
         dalloc(c, &c->d_gstack, (size_t)c->trace_grid_max * kTraceBlock * (kStack - kLdsStack)) != SDD_OK) {
         sdd_destroy(c);
         return SDD_ERR_OOM;
@@ -656,6 +663,7 @@ void sdd_destroy(sdd_ctx* c) {
     free_scene(c);
     free_nrc(c);
     dfree(c, c->d_overflow);
+    dfree(c, c->d_ktot);
     dfree(c, c->d_gstack);
     dfree(c, c->d_stats);
     for (auto& kv : c->allocs) (void)hipFree(kv.first);
@@ -952,6 +960,7 @@ sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->G = d->nx * d->ny * d->nz;
     c->S = d->nx + d->ny + d->nz - 2;
+    c->ext_bins = c->G * kExtBins <= kMaxCells ? kExtBins : 1;
     c->trace_grid = std::min(c->trace_grid_max, trace_grid_for(c, c->G));
     GridParams& gp = c->grid;
     gp.planes = c->d_planes;
@@ -1269,6 +1278,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
             cp.grid = c->grid;
             cp.n_cells = c->G;
             cp.se = c->stage[0];
+            cp.ext_bins = c->ext_bins;
             cp.n_blocks = n_blocks;
             cp.stats = c->d_stats;
             cp.nrc = np;
@@ -1305,6 +1315,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
         sp.n_cells = c->G;
         sp.se = c->stage[0];
         sp.ss = c->stage[1];
+        sp.ext_bins = c->ext_bins;
         sp.n_blocks = n_blocks;
         sp.stats = c->d_stats;
         sp.nrc = np;

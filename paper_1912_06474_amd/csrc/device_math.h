@@ -308,6 +308,9 @@ __device__ __forceinline__ int wave_append(bool active, int key, int* counts) {
 // in s_wcnt[wave][n_seg]).  Afterwards s_wcnt[0][k] holds nothing useful; the
 // block's count of key k is returned by block_key_total.  Every thread of the
 // block must call it (it synchronises the block).
+// direction bin of the closest-hit routing: sign bits of x and y
+__device__ __forceinline__ int dir_bin(f3 d) { return (d.x < 0.0f ? 1 : 0) | (d.y < 0.0f ? 2 : 0); }
+
 __device__ __forceinline__ int block_rank(bool active, int key, int n_seg, int* s_wcnt) {
     const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     __syncthreads();  // earlier readers of s_wcnt are done

@@ -141,9 +141,11 @@ __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
         cell = locate_ray(P.grid, o, d, t_enter);
         enq = cell >= 0;
     }
-    const int rank = block_rank(enq, cell, P.n_cells, s_wcnt);
+    const int nb = P.ext_bins;
+    const int key = cell * nb + (nb > 1 ? dir_bin(d) : 0);
+    const int rank = block_rank(enq, key, P.n_cells * nb, s_wcnt);
     // every slot of the segment's blocks gets a tag (-1 past its last path)
-    P.se.tag[pid] = enq ? (cell | (rank << 16)) : -1;
+    P.se.tag[pid] = enq ? (key | (rank << 16)) : -1;
     if (enq) {
         P.se.qa[pid] = make_float4(o.x, o.y, o.z, t_enter);
         P.se.qb[pid] = make_float4(d.x, d.y, d.z, __int_as_float(pid));
@@ -154,8 +156,8 @@ __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
         P.nrc.cx[pid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         P.nrc.cn[pid] = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
     }
-    for (int c = threadIdx.x; c < P.n_cells; c += blockDim.x)
-        P.se.hist[(long long)c * P.n_blocks + blk] = block_key_total(c, P.n_cells, s_wcnt);
+    for (int c = threadIdx.x; c < P.n_cells * nb; c += blockDim.x)
+        P.se.hist[(long long)c * P.n_blocks + blk] = block_key_total(c, P.n_cells * nb, s_wcnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -661,15 +663,17 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
     }
     // stage both rays in path order; k_route scatters them into the queues
     // every slot of the segment's blocks gets a tag (-1 past its last path)
-    const int rank_e = block_rank(enq_e, cell_e, P.n_cells, s_wcnt);
-    P.se.tag[pid] = enq_e ? (cell_e | (rank_e << 16)) : -1;
+    const int nb = P.ext_bins;
+    const int key_e = cell_e * nb + (nb > 1 ? dir_bin(dn) : 0);
+    const int rank_e = block_rank(enq_e, key_e, P.n_cells * nb, s_wcnt);
+    P.se.tag[pid] = enq_e ? (key_e | (rank_e << 16)) : -1;
     if (enq_e) {
         P.se.qa[pid] = make_float4(xo.x, xo.y, xo.z, te);
         P.se.qb[pid] = make_float4(dn.x, dn.y, dn.z, __int_as_float(pid));
         P.se.qc[pid] = make_int2(prim, __float_as_int(INFINITY));
     }
-    for (int c = threadIdx.x; c < P.n_cells; c += blockDim.x)
-        P.se.hist[(long long)c * P.n_blocks + blk] = block_key_total(c, P.n_cells, s_wcnt);
+    for (int c = threadIdx.x; c < P.n_cells * nb; c += blockDim.x)
+        P.se.hist[(long long)c * P.n_blocks + blk] = block_key_total(c, P.n_cells * nb, s_wcnt);
     const int rank_s = block_rank(enq_s, cell_s, P.n_cells, s_wcnt);
     P.ss.tag[pid] = enq_s ? (cell_s | (rank_s << 16)) : -1;
     if (enq_s) {
@@ -686,11 +690,16 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
 // ---------------------------------------------------------------------------
 // One workgroup per (kind, cell): exclusive scan, in block order, of the
 // per-block counts; the cell's total becomes its queue length.
+// One workgroup per (kind, routing key): exclusive scan, in block order, of
+// the key's per-block counts; the key's total goes to ktot and is added to its
+// cell's queue length.  A cell's keys (direction bins) follow each other in
+// its queue: k_route adds the totals of the cell's lower bins.
 __global__ __launch_bounds__(256) void k_route_scan(RouteParams P) {
     __shared__ int s_part[256];
-    const int kind = blockIdx.x / P.n_cells, cell = blockIdx.x % P.n_cells;
-    if (!P.active[kind]) return;
-    int* h = P.st[kind].hist + (long long)cell * P.n_blocks;
+    const int per_kind = P.n_cells * kExtBins;
+    const int kind = blockIdx.x / per_kind, key = blockIdx.x % per_kind;
+    if (!P.active[kind] || key >= P.n_cells * P.nbin[kind]) return;
+    int* h = P.st[kind].hist + (long long)key * P.n_blocks;
     const int nb = P.n_blocks;
     const int per = (nb + 255) / 256;
     const int b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
@@ -711,14 +720,16 @@ __global__ __launch_bounds__(256) void k_route_scan(RouteParams P) {
         run += v;
     }
     if (threadIdx.x == 255) {
-        P.cnt[kind][cell] = s_part[255];
-        if (s_part[255] && P.count[kind])
-            atomicAdd(&P.stats[kind == 0 ? kStatExtRays : kStatShadowRays], (unsigned long long)s_part[255]);
+        const int total = s_part[255];
+        P.ktot[kind][key] = total;
+        if (total) {
+            atomicAdd(&P.cnt[kind][key / P.nbin[kind]], total);  // queue lengths start at zero per batch
+            if (P.count[kind])
+                atomicAdd(&P.stats[kind == 0 ? kStatExtRays : kStatShadowRays], (unsigned long long)total);
+        }
     }
 }
 
-// One thread per path: copy each staged ray to cell * cap + offset of its
-// block + its rank in the block (stable: block order, then thread order).
 __global__ __launch_bounds__(kShadeBlock) void k_route(RouteParams P) {
     const int pid = blockIdx.x * blockDim.x + threadIdx.x;
     if (pid >= P.N) return;
@@ -728,8 +739,10 @@ __global__ __launch_bounds__(kShadeBlock) void k_route(RouteParams P) {
         const Stage& S = P.st[kind];
         const int tag = S.tag[pid];
         if (tag < 0) continue;
-        const int cell = tag & 0xFFFF, rank = tag >> 16;
-        const long long slot = (long long)S.hist[(long long)cell * P.n_blocks + blockIdx.x] + rank;
+        const int key = tag & 0xFFFF, rank = tag >> 16, nbin = P.nbin[kind];
+        const int cell = key / nbin;
+        long long slot = (long long)S.hist[(long long)key * P.n_blocks + blockIdx.x] + rank;
+        for (int k2 = cell * nbin; k2 < key; ++k2) slot += P.ktot[kind][k2];  // the cell's lower bins
         if (slot < 0 || slot >= P.cap || cell >= P.n_cells) continue;  // never expected: defence only
         const long long q = (long long)cell * P.cap + slot;
         P.qa[kind][q] = S.qa[pid];
@@ -1067,7 +1080,7 @@ hipError_t launch_shade(const ShadeParams& p, hipStream_t st) {
 
 hipError_t launch_route(const RouteParams& p, hipStream_t st) {
     if (p.N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_route_scan, dim3(2 * p.n_cells), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_route_scan, dim3(2 * p.n_cells * kExtBins), dim3(256), 0, st, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_route, dim3(blocks_for(p.N, kShadeBlock)), dim3(kShadeBlock), 0, st, p);
