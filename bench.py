@@ -298,6 +298,9 @@ def main():
     ap.add_argument("--nrc-train-steps", type=int, default=None, help="nrc_room: Adam steps per frame (default 4)")
     ap.add_argument("--nrc-train-batch", type=int, default=None, help="nrc_room: rows per Adam step (default 2^14)")
     ap.add_argument("--nrc-lr", type=float, default=None, help="nrc_room: Adam learning rate (default 1e-2)")
+    ap.add_argument("--autotune", nargs="?", const="", default=None, metavar="FILE",
+                    help="search the launch settings on the step's own call before the warmup (results file "
+                         "FILE is read first and written after a search)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -373,6 +376,13 @@ def main():
                 tr.resolve_image(r["render_id"], r["W"], r["H"], spectral=True, xyz=True)
         step += 1
 
+    tuned = None
+    if args.autotune is not None:
+        t0 = time.perf_counter()
+        call = renders if renders is not None else [dict(camera=cam, W=W, H=H, spp=spp, render_id=0)]
+        tuned = tr.autotune(call, D, reps=2, cache=args.autotune or None)
+        log(f"[bench] autotune {tuned} ({time.perf_counter() - t0:.1f} s)")
+
     for i in range(args.warmup):
         frame()
         torch.cuda.synchronize()
@@ -439,6 +449,9 @@ def main():
         "kernel_ms_per_step": {k: v / args.steps for k, v in kern_ms.items()},
         "build_bvh_s": build_s,
         "bvh": "device LBVH" if args.device_bvh else "host binned SAH",
+        "tuning": dict(tr.get_tuning(), paths_per_pass=st["paths_per_batch"],
+                       autotuned=None if tuned is None else {"from_cache": tuned["from_cache"],
+                                                             "search_ms_per_call": tuned["ms"]}),
     }
     if args.count_work:
         tr.reset_stats()

@@ -204,7 +204,7 @@ typedef struct sdd_stats {
     int32_t max_bvh_depth;
     int32_t n_cells;
     int64_t device_bytes;      /* device memory owned by the context */
-    int64_t paths_per_batch;
+    int64_t paths_per_batch;   /* paths per pipeline pass of the last trace call */
     int32_t overflow;          /* nonzero: a shadow segment crossed more panes than supported */
     int32_t pad_;
     double ms_nrc_query;       /* cache-network launches of SDD_TRACE_NRC renders (SDD_TRACE_TIME_KERNELS;
@@ -258,6 +258,75 @@ sdd_status sdd_trace_spectral(sdd_ctx *ctx, const sdd_trace_desc *desc);
  * sdd_trace_spectral would trace it alone (same random numbers, same
  * result); TIME_KERNELS / COUNT_WORK apply if any desc sets them. */
 sdd_status sdd_trace_batch(sdd_ctx *ctx, int32_t n, const sdd_trace_desc *descs);
+
+/* Launch settings of the pipeline.  They change speed only: every setting
+ * traces the same paths with the same random numbers, so images are
+ * bit-identical under any of them.  0 in a field selects the library's
+ * own choice.
+ *   batch_paths  paths per pipeline pass, which is also the capacity of each
+ *                subdomain queue; 0 = as many as a 48 GiB budget
+ *                (SDD_MEM_BUDGET_GB) holds, else a multiple of 256 in
+ *                [256, 2^24]; a call with more paths runs several passes
+ *   trace_grid   traversal workgroups per sweep launch; 0 = all that stay
+ *                resident on the device, else a multiple of 8 (one share per
+ *                XCD) up to that resident maximum
+ *   dir_bins     direction bins per subdomain when closest-hit rays are
+ *                queued: 0 = 4 (signs of the direction's x and y) whenever
+ *                4 x cells <= SDD_MAX_CELLS, 1 = cell only, 4 = as 0 */
+typedef struct sdd_tuning {
+    int64_t batch_paths;
+    int32_t trace_grid;
+    int32_t dir_bins;
+} sdd_tuning;
+
+/* Host-only check of the field ranges above (no device needed); msg (may be
+ * NULL) receives a NUL-terminated reason.  SDD_ERR_INVALID_ARG if malformed. */
+sdd_status sdd_validate_tuning(const sdd_tuning *t, char *msg, int msg_len);
+
+/* Apply t to later calls (waits for the context's stream first).
+ * SDD_ERR_INVALID_ARG for a malformed t or a trace_grid above the resident
+ * maximum.  A captured SDD_TRACE_GRAPH sequence is recaptured. */
+sdd_status sdd_set_tuning(sdd_ctx *ctx, const sdd_tuning *t);
+
+/* Settings in force: batch_paths as requested (0 = from the budget; the
+ * paths per pass of the last call are in sdd_stats.paths_per_batch), trace_grid and
+ * dir_bins as launched (0 before sdd_build_bvh). */
+sdd_status sdd_get_tuning(sdd_ctx *ctx, sdd_tuning *out);
+
+/* Search launch settings for a call shaped like descs (as sdd_trace_batch
+ * takes them) by timing that call on the device: direction bins, then the
+ * traversal grid (all, 3/4, 1/2 of the resident workgroups), then the paths
+ * per pass (the budget's, 1/2, 1/4), each candidate as one untimed and reps
+ * (1..100) timed calls, keeping a candidate only if it is more than 1% faster.
+ * The winner is applied as by sdd_set_tuning; *out receives it, *ms_out (may
+ * be NULL) the time of one call under it.
+ * With SDD_TUNE_VERBOSE set in the environment each candidate's time is
+ * printed to stderr.
+ * cache_path (may be NULL or ""): a text file of earlier results, one line per
+ * key of sdd_tune_key; a result found there is applied without any timing
+ * (*from_cache = 1), and a new result is stored there.
+ * The search's calls are discarded: the render ids of descs must not hold
+ * samples (SDD_ERR_STATE otherwise) and hold none afterwards.
+ * SDD_ERR_UNSUPPORTED for SDD_TRACE_NRC (the calls would train the cache);
+ * SDD_ERR_INVALID_ARG for hit or shadow logs; SDD_ERR_STATE if the file
+ * cannot be written (the result is still applied). */
+sdd_status sdd_autotune(sdd_ctx *ctx, int32_t n, const sdd_trace_desc *descs, int32_t reps, const char *cache_path,
+                        sdd_tuning *out, double *ms_out, int32_t *from_cache);
+
+/* The results-file key of a call shaped like descs: device name and compute
+ * units, library build, scene size, subdomain grid, render count, total paths,
+ * max_depth and the COUNT_WORK / GRAPH flags.  out: host buffer of out_len
+ * bytes (SDD_ERR_INVALID_ARG if too small).  SDD_ERR_STATE before a BVH. */
+sdd_status sdd_tune_key(sdd_ctx *ctx, int32_t n, const sdd_trace_desc *descs, char *out, int32_t out_len);
+
+/* Host-only access to a results file.  lookup: *found = 1 and *out (and *ms,
+ * may be NULL) from the last well-formed line of key, else *found = 0 (also
+ * for a missing file).  store: replaces the key's lines by one new line,
+ * through a temporary file renamed over path; SDD_ERR_INVALID_ARG for a key
+ * with a tab or newline, a malformed t or ms < 0, SDD_ERR_STATE if the file
+ * cannot be written. */
+sdd_status sdd_tune_cache_lookup(const char *path, const char *key, sdd_tuning *out, double *ms, int32_t *found);
+sdd_status sdd_tune_cache_store(const char *path, const char *key, const sdd_tuning *t, double ms);
 
 /* Per-pixel mean radiance of render_id over all samples traced so far, in
  * FP64: spectral_out [H][W][n_lambda] and xyz_out [H][W][3] (XYZ =

@@ -77,6 +77,14 @@ class NrcDesc(C.Structure):
                 ("precision", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("batch_paths", C.c_int64), ("trace_grid", C.c_int32), ("dir_bins", C.c_int32)]
+
+    def as_dict(self):
+        return {"batch_paths": int(self.batch_paths), "trace_grid": int(self.trace_grid),
+                "dir_bins": int(self.dir_bins)}
+
+
 class Stats(C.Structure):
     _fields_ = [
         ("ext_rays", C.c_int64), ("shadow_rays", C.c_int64), ("ext_cell_visits", C.c_int64),
@@ -133,6 +141,15 @@ def lib():
         L.sdd_nrc_query.argtypes = [vp, i32, vp, vp, vp, i32]
         L.sdd_nrc_last_rows.argtypes = [vp, i32, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_float)]
+        tp = C.POINTER(Tuning)
+        L.sdd_validate_tuning.argtypes = [tp, C.c_char_p, C.c_int]
+        L.sdd_set_tuning.argtypes = [vp, tp]
+        L.sdd_get_tuning.argtypes = [vp, tp]
+        L.sdd_autotune.argtypes = [vp, i32, C.POINTER(TraceDesc), i32, C.c_char_p, tp, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_int32)]
+        L.sdd_tune_key.argtypes = [vp, i32, C.POINTER(TraceDesc), C.c_char_p, i32]
+        L.sdd_tune_cache_lookup.argtypes = [C.c_char_p, C.c_char_p, tp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.sdd_tune_cache_store.argtypes = [C.c_char_p, C.c_char_p, tp, C.c_double]
         _LIB = L
     return _LIB
 
@@ -184,6 +201,32 @@ def validate_scene(scene):
     buf = C.create_string_buffer(512)
     st = lib().sdd_validate_scene(C.byref(sa.desc), buf, 512)
     return st == SDD_OK, buf.value.decode()
+
+
+def validate_tuning(batch_paths=0, trace_grid=0, dir_bins=0):
+    """Host-only check of launch settings.  Returns (ok, message)."""
+    buf = C.create_string_buffer(256)
+    st = lib().sdd_validate_tuning(C.byref(Tuning(batch_paths, trace_grid, dir_bins)), buf, 256)
+    return st == SDD_OK, buf.value.decode()
+
+
+def tune_cache_lookup(path, key):
+    """(settings dict with "ms", or None) for key in a results file (host only)."""
+    t, ms, found = Tuning(), C.c_double(0.0), C.c_int32(0)
+    st = lib().sdd_tune_cache_lookup(str(path).encode(), key.encode(), C.byref(t), C.byref(ms), C.byref(found))
+    if st != SDD_OK:
+        raise SddError(st, "sdd_tune_cache_lookup failed")
+    if not found.value:
+        return None
+    return dict(t.as_dict(), ms=ms.value)
+
+
+def tune_cache_store(path, key, batch_paths=0, trace_grid=0, dir_bins=0, ms=0.0):
+    """Replace key's entry of a results file (host only)."""
+    st = lib().sdd_tune_cache_store(str(path).encode(), key.encode(),
+                                    C.byref(Tuning(batch_paths, trace_grid, dir_bins)), float(ms))
+    if st != SDD_OK:
+        raise SddError(st, "sdd_tune_cache_store failed")
 
 
 class Tracer:
@@ -280,6 +323,41 @@ class Tracer:
                                 r.get("sample_offset", 0), time_kernels, count_work, r.get("hit_log"),
                                 r.get("shadow_log"), r.get("glass_swap"), graph=graph)
         self._check(lib().sdd_trace_batch(self.h, len(renders), arr))
+
+    def _batch_descs(self, renders, max_depth, seed=0, count_work=False, graph=False):
+        arr = (TraceDesc * len(renders))()
+        for i, r in enumerate(renders):
+            arr[i] = self._desc(r["camera"], r["W"], r["H"], r["spp"], max_depth, seed, r["render_id"],
+                                r.get("sample_offset", 0), False, count_work, None, None, r.get("glass_swap"),
+                                graph=graph)
+        return arr
+
+    def set_tuning(self, batch_paths=0, trace_grid=0, dir_bins=0):
+        """Launch settings for later calls (0 = the library's choice); images do not change."""
+        self._check(lib().sdd_set_tuning(self.h, C.byref(Tuning(batch_paths, trace_grid, dir_bins))))
+
+    def get_tuning(self):
+        t = Tuning()
+        self._check(lib().sdd_get_tuning(self.h, C.byref(t)))
+        return t.as_dict()
+
+    def tune_key(self, renders, max_depth, *, count_work=False, graph=False):
+        arr = self._batch_descs(renders, max_depth, count_work=count_work, graph=graph)
+        buf = C.create_string_buffer(1024)
+        self._check(lib().sdd_tune_key(self.h, len(renders), arr, buf, 1024))
+        return buf.value.decode()
+
+    def autotune(self, renders, max_depth, *, seed=0, reps=2, cache=None, count_work=False, graph=False):
+        """Time a call shaped like trace_batch(renders, max_depth) under candidate launch settings,
+        apply the fastest and return it (with "ms" and "from_cache").  cache: path of a results file
+        read first and written after a search.  The search's samples are discarded: the render ids
+        must be unused."""
+        arr = self._batch_descs(renders, max_depth, seed, count_work, graph)
+        t, ms, fc = Tuning(), C.c_double(0.0), C.c_int32(0)
+        self._check(lib().sdd_autotune(self.h, len(renders), arr, int(reps),
+                                       None if cache is None else str(cache).encode(), C.byref(t), C.byref(ms),
+                                       C.byref(fc)))
+        return dict(t.as_dict(), ms=ms.value, from_cache=bool(fc.value))
 
     def new_log(self, W, H, spp, max_depth):
         return self.torch.empty((W * H, spp, max_depth), dtype=self.torch.int32, device=self.device)

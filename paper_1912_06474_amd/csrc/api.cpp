@@ -18,7 +18,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <limits>
 #include <map>
+#include <sstream>
+#include <unistd.h>
 #include <new>
 #include <string>
 #include <vector>
@@ -54,6 +58,10 @@ struct sdd_ctx {
     int n_cu = 256;
     int trace_grid = 0, trace_grid_max = 0;
     int ext_bins = 1;  // direction bins per cell of the closest-hit routing
+    // launch settings requested through sdd_set_tuning (0: the library's choice)
+    long long tune_batch = 0;
+    int tune_grid = 0, tune_bins = 0;
+    long long last_nb = 0;  // paths per pass of the last trace call
 
     // scene (host copies used by the builder)
     bool has_scene = false, has_bvh = false;
@@ -186,6 +194,24 @@ sdd_status fail(sdd_ctx* c, sdd_status st, const std::string& msg) {
 // trace workgroups: as many as stay resident on every CU, a multiple of the XCD count
 int trace_grid_for(const sdd_ctx* c, int n_cells) {
     return std::max(kXcd, (c->n_cu * trace_blocks_per_cu(n_cells) / kXcd) * kXcd);
+}
+
+// traversal grid and direction bins from the requested settings and the grid of cells
+void apply_tuning(sdd_ctx* c) {
+    const int g_auto = std::min(c->trace_grid_max, trace_grid_for(c, c->G));
+    c->trace_grid = c->tune_grid > 0 ? std::min(c->tune_grid, c->trace_grid_max) : g_auto;
+    c->ext_bins = (c->tune_bins == 1 || c->G * kExtBins > kMaxCells) ? 1 : kExtBins;
+}
+
+// reason a tuning is malformed, or nullptr (host-only checks)
+const char* tuning_problem(const sdd_tuning* t) {
+    if (!t) return "null tuning";
+    if (t->batch_paths != 0 &&
+        (t->batch_paths < kShadeBlock || t->batch_paths > kMaxBatch || t->batch_paths % kShadeBlock != 0))
+        return "batch_paths must be 0 or a multiple of 256 in [256, 2^24]";
+    if (t->trace_grid < 0 || t->trace_grid % kXcd != 0) return "trace_grid must be 0 or a positive multiple of 8";
+    if (t->dir_bins != 0 && t->dir_bins != 1 && t->dir_bins != kExtBins) return "dir_bins must be 0, 1 or 4";
+    return nullptr;
 }
 
 sdd_status hip_fail(sdd_ctx* c, hipError_t e, const char* what) {
@@ -960,8 +986,7 @@ sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->G = d->nx * d->ny * d->nz;
     c->S = d->nx + d->ny + d->nz - 2;
-    c->ext_bins = c->G * kExtBins <= kMaxCells ? kExtBins : 1;
-    c->trace_grid = std::min(c->trace_grid_max, trace_grid_for(c, c->G));
+    apply_tuning(c);
     GridParams& gp = c->grid;
     gp.planes = c->d_planes;
     gp.nx = d->nx;
@@ -1183,7 +1208,8 @@ long long plan_batches(sdd_ctx* c, std::vector<Job>& jobs, long long& total_pad)
         total_pad += (j.total + kShadeBlock - 1) / kShadeBlock * kShadeBlock;
     }
     const bool nrc = (any_flags & SDD_TRACE_NRC) != 0;
-    long long nb = mem_budget_bytes() / (bytes_per_path(c, D) + (nrc ? 32 + 4LL * c->nlp : 0));
+    long long nb = c->tune_batch > 0 ? c->tune_batch
+                                     : mem_budget_bytes() / (bytes_per_path(c, D) + (nrc ? 32 + 4LL * c->nlp : 0));
     nb = std::min<long long>(nb, kMaxBatch);
     nb = std::max<long long>(kShadeBlock, nb / kShadeBlock * kShadeBlock);
     return std::min(nb, total_pad);
@@ -1202,6 +1228,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
     const long long nb = plan_batches(c, jobs, total_pad);
     sdd_status st = ensure_batch(c, nb, D);
     if (st != SDD_OK) return st;
+    c->last_nb = nb;
     // radiance cache (one render per call): training paths are those with
     // (s * WH + p) % stride == 0; in the call's path numbering qc = (s - s0) WH + p
     // they are qc = r + j * stride, j the training slot
@@ -1484,6 +1511,7 @@ sdd_status trace_graph(sdd_ctx* c, int n, const sdd_trace_desc* descs, std::vect
     const long long nb = plan_batches(c, jobs, total_pad);
     sdd_status st = ensure_batch(c, nb, descs[0].max_depth);  // allocate before any capture
     if (st != SDD_OK) return st;
+    c->last_nb = nb;
     if (n > c->s0_cap) {
         dfree(c, c->d_s0);
         c->s0_cap = 0;
@@ -1572,6 +1600,194 @@ sdd_status trace_call(sdd_ctx* c, int n, const sdd_trace_desc* descs) {
     return trace_graph(c, n, descs, jobs);
 }
 
+// ---------------------------------------------------------------------------
+// launch-setting search (sdd_autotune) and its results file
+// ---------------------------------------------------------------------------
+// One line per configuration: "<key>\t<batch_paths> <trace_grid> <dir_bins> <ms>".
+bool tune_cache_read(const char* path, const std::string& key, sdd_tuning* t, double* ms) {
+    std::ifstream f(path);
+    if (!f) return false;
+    bool found = false;
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t tab = line.rfind('\t');
+        if (tab == std::string::npos || line.compare(0, tab, key) != 0 || tab != key.size()) continue;
+        long long b = 0;
+        int g = 0, d = 0;
+        double m = 0.0;
+        if (std::sscanf(line.c_str() + tab + 1, "%lld %d %d %lf", &b, &g, &d, &m) != 4) continue;
+        sdd_tuning u{};
+        u.batch_paths = b;
+        u.trace_grid = g;
+        u.dir_bins = d;
+        if (tuning_problem(&u)) continue;  // a damaged line is skipped
+        *t = u;
+        if (ms) *ms = m;
+        found = true;  // the last valid line of the key wins
+    }
+    return found;
+}
+
+// rewrites the file without the key's old lines, then appends the new one
+// (written to a temporary file and renamed, so readers never see half a file)
+bool tune_cache_write(const char* path, const std::string& key, const sdd_tuning& t, double ms) {
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (f && std::getline(f, line)) {
+            const size_t tab = line.rfind('\t');
+            if (tab != std::string::npos && tab == key.size() && line.compare(0, tab, key) == 0) continue;
+            if (!line.empty()) keep.push_back(line);
+        }
+    }
+    const std::string tmp = std::string(path) + ".tmp." + std::to_string((long long)getpid());
+    {
+        std::ofstream o(tmp, std::ios::trunc);
+        if (!o) return false;
+        for (const std::string& l : keep) o << l << '\n';
+        char buf[128];
+        std::snprintf(buf, sizeof(buf), "\t%lld %d %d %.6f\n", (long long)t.batch_paths, t.trace_grid, t.dir_bins, ms);
+        o << key << buf;
+        if (!o.good()) {
+            std::remove(tmp.c_str());
+            return false;
+        }
+    }
+    if (std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return false;
+    }
+    return true;
+}
+
+// what the best settings depend on: the device, the library build, the scene
+// and its grid of cells, and the shape of the call (not its sample offsets or
+// camera poses)
+std::string tune_key(const sdd_ctx* c, int n, const sdd_trace_desc* d) {
+    hipDeviceProp_t pr{};
+    if (hipGetDeviceProperties(&pr, c->device) != hipSuccess) std::snprintf(pr.gcnArchName, sizeof(pr.gcnArchName), "?");
+    long long paths = 0;
+    uint32_t fl = 0;
+    for (int i = 0; i < n; ++i) {
+        paths += (long long)d[i].W * d[i].H * d[i].spp;
+        fl |= d[i].flags & (SDD_TRACE_COUNT_WORK | SDD_TRACE_GRAPH);
+    }
+    std::ostringstream k;
+    k << "sdd-tune-1 dev=" << pr.gcnArchName << "/" << pr.multiProcessorCount << "cu build=" << __DATE__ << " "
+      << __TIME__ << " tris=" << c->T << " lambda=" << c->nl << " glass=" << c->n_glass << " coats=" << c->coat_layers
+      << " cells=" << c->grid.nx << "x" << c->grid.ny << "x" << c->grid.nz << " renders=" << n << " paths=" << paths
+      << " depth=" << d[0].max_depth << " flags=" << fl;
+    std::string s = k.str();
+    for (char& ch : s)
+        if (ch == '\t' || ch == '\n' || ch == '\r') ch = ' ';
+    return s;
+}
+
+void set_tuning_fields(sdd_ctx* c, const sdd_tuning& t) {
+    c->tune_batch = t.batch_paths;
+    c->tune_grid = t.trace_grid;
+    c->tune_bins = t.dir_bins;
+    if (c->has_bvh) apply_tuning(c);
+    ++c->gen;  // a captured graph holds the old launch shapes
+}
+
+// drops the accumulators of the call's renders (the search's samples)
+void drop_renders(sdd_ctx* c, int n, const sdd_trace_desc* d) {
+    (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < n; ++i) {
+        auto it = c->renders.find(d[i].render_id);
+        if (it == c->renders.end()) continue;
+        dfree(c, it->second.acc);
+        c->renders.erase(it);
+    }
+    ++c->gen;
+}
+
+// time of one call under tuning t: one untimed call (allocation, graph
+// capture), then the fastest of reps timed calls
+sdd_status time_call(sdd_ctx* c, int n, const sdd_trace_desc* descs, int reps, const sdd_tuning& t, hipEvent_t a,
+                     hipEvent_t b, double& ms) {
+    set_tuning_fields(c, t);
+    sdd_status st = trace_call(c, n, descs);
+    if (st != SDD_OK) return st;
+    ms = std::numeric_limits<double>::infinity();
+    for (int r = 0; r < reps; ++r) {
+        HIP_TRY(c, hipEventRecord(a, c->stream));
+        if ((st = trace_call(c, n, descs)) != SDD_OK) return st;
+        HIP_TRY(c, hipEventRecord(b, c->stream));
+        HIP_TRY(c, hipEventSynchronize(b));
+        float e = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&e, a, b));
+        ms = std::min(ms, (double)e);
+    }
+    return SDD_OK;
+}
+
+// coordinate search from the library's own choices: direction bins, then the
+// traversal grid, then the paths per pass; a candidate must win by more than
+// 1% to replace the incumbent, so timing noise keeps the defaults
+sdd_status search_tuning(sdd_ctx* c, int n, const sdd_trace_desc* descs, int reps, sdd_tuning& best, double& best_ms) {
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(c, hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(c, SDD_ERR_HIP, "hipEventCreate");
+    }
+    const bool verbose = std::getenv("SDD_TUNE_VERBOSE") != nullptr;  // one stderr line per candidate
+    auto report = [&](const sdd_tuning& t, double ms) {
+        if (verbose)
+            std::fprintf(stderr, "[sdd tune] batch_paths %lld trace_grid %d dir_bins %d: %.3f ms (launched grid %d, bins %d)\n",
+                         (long long)t.batch_paths, t.trace_grid, t.dir_bins, ms, c->trace_grid, c->ext_bins);
+    };
+    best = sdd_tuning{};
+    sdd_status st = time_call(c, n, descs, reps, best, a, b, best_ms);
+    if (st == SDD_OK) report(best, best_ms);
+    auto consider = [&](const sdd_tuning& t) {
+        if (st != SDD_OK) return;
+        double ms = 0.0;
+        st = time_call(c, n, descs, reps, t, a, b, ms);
+        if (st == SDD_OK) report(t, ms);
+        if (st == SDD_OK && ms < 0.99 * best_ms) {
+            best = t;
+            best_ms = ms;
+        }
+    };
+    if (c->G * kExtBins <= kMaxCells) {
+        sdd_tuning t = best;
+        t.dir_bins = 1;
+        consider(t);
+    }
+    const int g_auto = std::min(c->trace_grid_max, trace_grid_for(c, c->G));
+    for (int num : {3, 2}) {
+        const int g = std::max(kXcd, g_auto * num / 4 / kXcd * kXcd);
+        if (g >= g_auto) continue;
+        sdd_tuning t = best;
+        t.trace_grid = g;
+        consider(t);
+    }
+    long long total_pad = 0;
+    {
+        std::vector<Job> jobs((size_t)n);
+        for (int i = 0; i < n; ++i) jobs[i].t = &descs[i];
+        for (int i = 0; i < n; ++i) jobs[i].total = (long long)descs[i].W * descs[i].H * descs[i].spp;
+        const long long keep = c->tune_batch;
+        c->tune_batch = 0;
+        const long long nb_auto = plan_batches(c, jobs, total_pad);
+        c->tune_batch = keep;
+        for (int div : {2, 4}) {
+            const long long nb = (nb_auto / div + kShadeBlock - 1) / kShadeBlock * kShadeBlock;
+            if (nb < (1LL << 16)) continue;  // small passes only add sweep overhead
+            sdd_tuning t = best;
+            t.batch_paths = nb;
+            consider(t);
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1585,6 +1801,102 @@ sdd_status sdd_trace_spectral(sdd_ctx* c, const sdd_trace_desc* t) {
 }
 
 sdd_status sdd_trace_batch(sdd_ctx* c, int32_t n, const sdd_trace_desc* descs) { return trace_call(c, n, descs); }
+
+sdd_status sdd_validate_tuning(const sdd_tuning* t, char* msg, int msg_len) {
+    const char* e = tuning_problem(t);
+    if (msg && msg_len > 0) std::snprintf(msg, (size_t)msg_len, "%s", e ? e : "");
+    return e ? SDD_ERR_INVALID_ARG : SDD_OK;
+}
+
+sdd_status sdd_set_tuning(sdd_ctx* c, const sdd_tuning* t) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (const char* e = tuning_problem(t)) return fail(c, SDD_ERR_INVALID_ARG, e);
+    if (t->trace_grid > c->trace_grid_max)
+        return fail(c, SDD_ERR_INVALID_ARG, "trace_grid above the device's resident maximum of " +
+                                                std::to_string(c->trace_grid_max));
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    set_tuning_fields(c, *t);
+    return SDD_OK;
+}
+
+sdd_status sdd_get_tuning(sdd_ctx* c, sdd_tuning* out) {
+    if (!c || !out) return SDD_ERR_INVALID_ARG;
+    out->batch_paths = c->tune_batch;
+    out->trace_grid = c->has_bvh ? c->trace_grid : 0;
+    out->dir_bins = c->has_bvh ? c->ext_bins : 0;
+    return SDD_OK;
+}
+
+sdd_status sdd_tune_cache_lookup(const char* path, const char* key, sdd_tuning* out, double* ms, int32_t* found) {
+    if (!path || !key || !out || !found) return SDD_ERR_INVALID_ARG;
+    *found = tune_cache_read(path, key, out, ms) ? 1 : 0;
+    return SDD_OK;
+}
+
+sdd_status sdd_tune_cache_store(const char* path, const char* key, const sdd_tuning* t, double ms) {
+    if (!path || !*path || !key || !*key || tuning_problem(t) || !(ms >= 0.0)) return SDD_ERR_INVALID_ARG;
+    for (const char* p = key; *p; ++p)
+        if (*p == '\t' || *p == '\n' || *p == '\r') return SDD_ERR_INVALID_ARG;
+    return tune_cache_write(path, key, *t, ms) ? SDD_OK : SDD_ERR_STATE;
+}
+
+sdd_status sdd_tune_key(sdd_ctx* c, int32_t n, const sdd_trace_desc* descs, char* out, int32_t out_len) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!descs || n < 1 || n > SDD_MAX_RENDERS || !out || out_len < 1)
+        return fail(c, SDD_ERR_INVALID_ARG, "bad arguments to sdd_tune_key");
+    if (!c->has_bvh) return fail(c, SDD_ERR_STATE, "sdd_tune_key before sdd_build_bvh");
+    const std::string k = tune_key(c, n, descs);
+    if ((int)k.size() >= out_len) return fail(c, SDD_ERR_INVALID_ARG, "key buffer too small");
+    std::snprintf(out, (size_t)out_len, "%s", k.c_str());
+    return SDD_OK;
+}
+
+sdd_status sdd_autotune(sdd_ctx* c, int32_t n, const sdd_trace_desc* descs, int32_t reps, const char* cache_path,
+                        sdd_tuning* out, double* ms_out, int32_t* from_cache) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!descs || !out || n < 1 || n > SDD_MAX_RENDERS) return fail(c, SDD_ERR_INVALID_ARG, "bad arguments to sdd_autotune");
+    if (reps < 1 || reps > 100) return fail(c, SDD_ERR_INVALID_ARG, "reps must be in 1..100");
+    if (!c->has_bvh) return fail(c, SDD_ERR_STATE, "sdd_autotune before sdd_build_bvh");
+    for (int i = 0; i < n; ++i) {
+        if (descs[i].flags & SDD_TRACE_NRC)
+            return fail(c, SDD_ERR_UNSUPPORTED, "autotune of radiance-cache renders (the calls would train the cache)");
+        if (descs[i].hit_log || descs[i].shadow_log) return fail(c, SDD_ERR_INVALID_ARG, "autotune takes no logs");
+        if (c->renders.count(descs[i].render_id))
+            return fail(c, SDD_ERR_STATE, "autotune needs render ids that hold no samples (its calls are discarded)");
+    }
+    DeviceGuard g(c->device);
+    if (from_cache) *from_cache = 0;
+    const std::string key = tune_key(c, n, descs);
+    sdd_tuning t{};
+    double ms = 0.0;
+    if (cache_path && *cache_path && tune_cache_read(cache_path, key, &t, &ms) && t.trace_grid <= c->trace_grid_max) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        set_tuning_fields(c, t);
+        *out = t;
+        if (ms_out) *ms_out = ms;
+        if (from_cache) *from_cache = 1;
+        return SDD_OK;
+    }
+    const sdd_tuning before{c->tune_batch, c->tune_grid, c->tune_bins};
+    sdd_status st = search_tuning(c, n, descs, reps, t, ms);
+    drop_renders(c, n, descs);
+    if (st != SDD_OK) {
+        const std::string e = c->err;
+        set_tuning_fields(c, before);
+        c->err = e;
+        return st;
+    }
+    set_tuning_fields(c, t);
+    *out = t;
+    if (ms_out) *ms_out = ms;
+    if (cache_path && *cache_path && !tune_cache_write(cache_path, key, t, ms))
+        return fail(c, SDD_ERR_STATE, std::string("cannot write the tuning file ") + cache_path);
+    return SDD_OK;
+}
 
 sdd_status sdd_resolve_image(sdd_ctx* c, int32_t render_id, double* spectral_out, double* xyz_out,
                              int32_t out_is_device) {
@@ -1673,7 +1985,7 @@ sdd_status sdd_get_stats(sdd_ctx* c, sdd_stats* out) {
     out->max_bvh_depth = c->has_bvh ? c->gb.max_depth : 0;
     out->n_cells = c->has_bvh ? c->G : 0;
     out->device_bytes = c->device_bytes;
-    out->paths_per_batch = c->ncap;
+    out->paths_per_batch = c->last_nb;
     out->overflow = ovf;
     return SDD_OK;
 }

@@ -261,7 +261,6 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit_cell(DevBuildArgs A, const 
                                                           int* max_depth, int* error) {
     __shared__ int s_scan[kEmitBlock];
     __shared__ float s_q[6];
-    __shared__ int s_count;
     const int c = blockIdx.x;
     const int s = cell_start[c], n = cell_start[c + 1] - s;
     const int base = s + c;  // n + 1 node slots per cell

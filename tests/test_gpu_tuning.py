@@ -1,0 +1,129 @@
+"""Launch settings (sdd_set_tuning) and the autotuner (sdd_autotune) on the
+device.  Settings change speed only, so every image, spectral and XYZ, and
+every per-vertex hit record must be bit-identical under any of them: several
+passes per call, fewer traversal workgroups, cell-only queues, and graph
+replays recaptured after a change."""
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tracer():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1912_06474_amd as m
+    return m.Tracer(stream=torch.cuda.Stream())
+
+
+def _render(tracer, sc, W, H, spp, D, graph=False, frames=1):
+    hl = tracer.new_log(W, H, spp, D)
+    for f in range(frames):
+        tracer.trace_spectral(sc["camera"], W, H, spp, D, seed=11, render_id=0, sample_offset=f * spp, hit_log=hl,
+                              graph=graph)
+    s, x = tracer.resolve_image(0, W, H)
+    out = (s.cpu().numpy(), x.cpu().numpy(), hl.cpu().numpy())
+    tracer.reset_render(0)
+    return out
+
+
+SETTINGS = [dict(batch_paths=4096), dict(batch_paths=1280), dict(trace_grid=8), dict(trace_grid=24),
+            dict(dir_bins=1), dict(batch_paths=2048, trace_grid=16, dir_bins=1), dict(dir_bins=4)]
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (2, 2, 1), (4, 2, 2)])
+def test_settings_leave_images_bit_identical(tracer, grid):
+    sc = sg.tiny_room(0, 16)
+    tracer.load_scene(sc)
+    tracer.build_bvh(*grid)
+    W, H, spp, D = 80, 56, 3, 6
+    tracer.set_tuning()
+    base = _render(tracer, sc, W, H, spp, D)
+    assert base[0].max() > 0
+    for t in SETTINGS:
+        tracer.set_tuning(**t)
+        got = tracer.get_tuning()
+        assert got["batch_paths"] == t.get("batch_paths", 0)
+        if "trace_grid" in t:
+            assert got["trace_grid"] == t["trace_grid"]
+        assert got["dir_bins"] == (1 if t.get("dir_bins") == 1 else 4)
+        tracer.reset_stats()
+        img = _render(tracer, sc, W, H, spp, D)
+        st = tracer.stats()
+        if "batch_paths" in t:
+            padded = -(-W * H * spp // 256) * 256
+            assert st["batches"] == -(-padded // t["batch_paths"])
+            assert st["paths_per_batch"] == t["batch_paths"]
+        for u, v in zip(base, img):
+            assert np.array_equal(u, v), f"settings {t}"
+    tracer.set_tuning()
+
+
+def test_graph_recaptures_after_a_change(tracer):
+    sc = sg.tiny_room(0, 16)
+    tracer.load_scene(sc)
+    tracer.build_bvh(2, 2, 1)
+    W, H, spp, D = 64, 48, 2, 5
+    tracer.set_tuning()
+    eager = _render(tracer, sc, W, H, spp, D, frames=3)
+    for t in (dict(batch_paths=2048), dict(trace_grid=16, dir_bins=1), dict()):
+        tracer.set_tuning(**t)
+        g = _render(tracer, sc, W, H, spp, D, graph=True, frames=3)
+        for u, v in zip(eager, g):
+            assert np.array_equal(u, v), f"graph under {t}"
+
+
+def test_set_tuning_rejects(tracer):
+    import paper_1912_06474_amd as m
+    sc = sg.tiny_room(0, 16)
+    tracer.load_scene(sc)
+    tracer.build_bvh(1, 1, 1)
+    for t in (dict(batch_paths=100), dict(trace_grid=12), dict(dir_bins=2), dict(trace_grid=1 << 20)):
+        with pytest.raises(m.SddError):
+            tracer.set_tuning(**t)
+    tracer.set_tuning()
+    assert tracer.get_tuning()["batch_paths"] == 0
+
+
+def test_autotune_search_cache_and_result(tracer, tmp_path):
+    import paper_1912_06474_amd as m
+    sc = sg.tiny_room(0, 16)
+    tracer.load_scene(sc)
+    tracer.build_bvh(2, 2, 1)
+    W, H, spp, D = 96, 64, 4, 6
+    tracer.set_tuning()
+    base = _render(tracer, sc, W, H, spp, D)
+    renders = [dict(camera=sc["camera"], W=W, H=H, spp=spp, render_id=5),
+               dict(camera=dict(sc["camera"], eye=(1.0, 0.6, 1.4)), W=W // 2, H=H // 2, spp=spp, render_id=6)]
+    f = tmp_path / "tune.txt"
+    r1 = tracer.autotune(renders, D, reps=1, cache=f)
+    print(f"[tune] searched: {r1}")
+    assert not r1["from_cache"] and r1["ms"] > 0
+    assert m.validate_tuning(r1["batch_paths"], r1["trace_grid"], r1["dir_bins"])[0]
+    assert tracer.get_tuning()["batch_paths"] == r1["batch_paths"]
+    key = tracer.tune_key(renders, D)
+    assert "renders=2" in key and f"paths={W * H * spp + (W // 2) * (H // 2) * spp}" in key
+    assert m.tune_cache_lookup(f, key)["trace_grid"] == r1["trace_grid"]
+    # the search's samples were discarded
+    for rid, w, h in ((5, W, H), (6, W // 2, H // 2)):
+        with pytest.raises(m.SddError):
+            tracer.resolve_image(rid, w, h)
+    # a second search of the same shape comes from the file, with no timing
+    tracer.set_tuning()
+    r2 = tracer.autotune(renders, D, reps=1, cache=f)
+    assert r2["from_cache"] and {k: r2[k] for k in ("batch_paths", "trace_grid", "dir_bins")} == \
+        {k: r1[k] for k in ("batch_paths", "trace_grid", "dir_bins")}
+    # images under the chosen settings equal the default ones
+    img = _render(tracer, sc, W, H, spp, D)
+    for u, v in zip(base, img):
+        assert np.array_equal(u, v)
+    # render ids that hold samples are refused
+    tracer.trace_spectral(sc["camera"], W, H, 1, D, render_id=5)
+    with pytest.raises(m.SddError):
+        tracer.autotune(renders, D, reps=1)
+    tracer.reset_render(5)
+    tracer.set_tuning()
