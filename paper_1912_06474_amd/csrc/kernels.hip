@@ -212,18 +212,25 @@ __device__ __forceinline__ bool tri_test(const RayTrav& r, float4 a, float4 b, f
     return true;
 }
 
-// Closest-hit traversal with the node steps and the triangle tests in
+// Traversal of one cell's BVH with the node steps and the triangle tests in
 // separate loops.  A lane that reaches a leaf parks it and goes on down the
-// tree until every lane of the wave still taking node steps has a parked leaf;
-// then the parked leaves are tested together.  The wave thus runs node steps
-// and triangle tests each with most of its lanes busy, instead of both with
-// part of them.  The hit does not depend on the visiting order (equal t goes
-// to the lower primitive index).
-template <bool COUNT>
-__device__ __forceinline__ void traverse_closest(const uint4* __restrict__ nodes, const uint4* top,
-                                                 const float4* __restrict__ tris, int root, const RayTrav& r,
-                                                 float tlo, int exclude, float& thi, int& best, int* stk, int* gstk,
-                                                 int gstride, int& n_nodes, int& n_tris) {
+// tree until most lanes of the wave still taking node steps have a parked
+// leaf; then the parked leaves are tested together.  The wave thus runs node
+// steps and triangle tests each with most of its lanes busy, instead of both
+// with part of them.
+//  - closest hit: thi = t_exit, best = -1 on entry; the hit does not depend on
+//    the visiting order (equal t goes to the lower primitive index);
+//  - shadow: thi = min(t_exit, t_max); a diffuse triangle in (tlo, thi] blocks
+//    the segment, a pane crossing is recorded in sh_glass (the order of the
+//    records changes only the rounding of the product of the pane factors).
+template <bool SHADOW, bool COUNT>
+__device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const uint4* top,
+                                         const float4* __restrict__ tris,
+                                         const float4* __restrict__ prim_info, int root, const RayTrav& r,
+                                         float tlo, float t_exit, float t_max, int exclude, float& thi, int& best,
+                                         bool& blocked, int& n_glass, int pid, const int* __restrict__ sh_state,
+                                         float2* __restrict__ sh_glass, int* overflow, int* stk, int* gstk,
+                                         int gstride, int& n_nodes, int& n_tris) {
     constexpr int kDone = -2147483647 - 1;  // INT_MIN: no leaf encodes as it (~INT_MAX triangles)
     int sp = 0;
     auto pop = [&]() -> int {
@@ -268,7 +275,10 @@ __device__ __forceinline__ void traverse_closest(const uint4* __restrict__ nodes
                 leaf = link;
                 link = pop();
             }
-            if (__ballot(leaf == 0) == 0) break;
+            // leave for the leaf loop once at most a third of the lanes here
+            // have no parked leaf (measured faster than waiting for all)
+            const unsigned long long here = __ballot(true), bare = __ballot(leaf == 0);
+            if (3 * __popcll(bare) <= __popcll(here)) break;
         }
         if (leaf == 0 && link < 0 && link != kDone) {
             leaf = link;
@@ -276,79 +286,6 @@ __device__ __forceinline__ void traverse_closest(const uint4* __restrict__ nodes
         }
         while (leaf < 0) {
             int ti = ~leaf;
-            for (;;) {
-                const float4 a = tris[3 * (size_t)ti], b = tris[3 * (size_t)ti + 1], c = tris[3 * (size_t)ti + 2];
-                const int prim = __float_as_int(a.w);
-                const int meta = __float_as_int(b.w);
-                if (prim != exclude) {
-                    if (COUNT) ++n_tris;
-                    float t;
-                    if (tri_test(r, a, b, c, t) && t > tlo && (t < thi || (t == thi && (best < 0 || prim < best)))) {
-                        thi = t;
-                        best = prim;
-                    }
-                }
-                if (meta & kLastInLeaf) break;
-                ++ti;
-            }
-            leaf = 0;
-            if (link < 0 && link != kDone) {
-                leaf = link;
-                link = pop();
-            }
-        }
-    }
-}
-
-template <bool SHADOW, bool COUNT>
-__device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const uint4* top,
-                                         const float4* __restrict__ tris,
-                                         const float4* __restrict__ prim_info, int root, const RayTrav& r,
-                                         float tlo, float t_exit, float t_max, int exclude, float& thi, int& best,
-                                         bool& blocked, int& n_glass, int pid, const int* __restrict__ sh_state,
-                                         float2* __restrict__ sh_glass, int* overflow, int* stk, int* gstk,
-                                         int gstride, int& n_nodes, int& n_tris) {
-    int sp = 0;
-    int link = root;
-    // closest hit: thi = t_exit, best = -1 on entry; shadow: thi = min(t_exit, t_max)
-    for (;;) {
-        if (link >= 0) {
-            // the cell's first kTopNodes nodes (breadth-first: its top levels) come from LDS
-            const int rel = link - root;
-            uint4 c0, c1;
-            if (rel < kTopNodes) {
-                c0 = top[2 * rel];
-                c1 = top[2 * rel + 1];
-            } else {
-                c0 = nodes[2 * (size_t)link];
-                c1 = nodes[2 * (size_t)link + 1];
-            }
-            const int l0 = (int)c0.w, l1 = (int)c1.w;
-            if (COUNT) ++n_nodes;
-            const float t0 = box_enter(r, c0, tlo, thi);
-            const float t1 = box_enter(r, c1, tlo, thi);
-            const bool h0 = t0 != INFINITY && l0 != kEmptyLink, h1 = t1 != INFINITY && l1 != kEmptyLink;
-            if (h0 && h1) {
-                const bool first0 = t0 <= t1;
-                // short stack in LDS, deeper entries in HBM; the builder caps the
-                // BVH depth below kStack, so no entry is ever dropped
-                const int far = first0 ? l1 : l0;
-                if (sp < kLdsStack) stk[sp * kTraceBlock] = far;
-                else if (sp < kStack) gstk[(sp - kLdsStack) * gstride] = far;
-                ++sp;
-                link = first0 ? l0 : l1;
-                continue;
-            }
-            if (h0) {
-                link = l0;
-                continue;
-            }
-            if (h1) {
-                link = l1;
-                continue;
-            }
-        } else {
-            int ti = ~link;
             for (;;) {
                 const float4 a = tris[3 * (size_t)ti], b = tris[3 * (size_t)ti + 1], c = tris[3 * (size_t)ti + 2];
                 const int prim = __float_as_int(a.w);
@@ -381,11 +318,12 @@ __device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const 
                 if (meta & kLastInLeaf) break;
                 ++ti;
             }
+            leaf = 0;
+            if (link < 0 && link != kDone) {
+                leaf = link;
+                link = pop();
+            }
         }
-        if (sp == 0) break;
-        --sp;
-        if (sp >= kStack) break;
-        link = sp < kLdsStack ? stk[sp * kTraceBlock] : gstk[(sp - kLdsStack) * gstride];
     }
 }
 
@@ -435,10 +373,7 @@ __device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueS
         int best = -1;
         bool blocked = false;
         int n_glass = -1;  // pane crossings so far (-1: not loaded yet)
-        if (!SHADOW)
-            traverse_closest<COUNT>(P.nodes, top, P.tris, root, r, t_enter, qc.x, thi, best, stk, gstk, gstride,
-                                    n_nodes, n_tris);
-        else if (thi > t_enter)
+        if (!SHADOW || thi > t_enter)
             traverse<SHADOW, COUNT>(P.nodes, top, P.tris, P.prim_info, root, r, t_enter, t_exit, t_max, qc.x, thi, best,
                                     blocked, n_glass, pid, P.sh_state, P.sh_glass, P.overflow, stk, gstk, gstride,
                                     n_nodes, n_tris);
