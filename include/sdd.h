@@ -200,8 +200,8 @@ typedef struct sdd_stats {
     double ms_shade;
     double ms_other;
     int64_t n_refs;            /* triangle references over all cells */
-    int64_t n_nodes;           /* BVH nodes over all cells */
-    int32_t max_bvh_depth;
+    int64_t n_nodes;           /* 4-wide BVH nodes over all cells */
+    int32_t max_bvh_depth;     /* depth of the binary hierarchy the builder made (before widening) */
     int32_t n_cells;
     int64_t device_bytes;      /* device memory owned by the context */
     int64_t paths_per_batch;   /* paths per pipeline pass of the last trace call */

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsdd.so")
-SOURCES = ["api.cpp", "bvh_build.cpp", "kernels.hip", "bvh_device.hip", "nrc.hip"]
+SOURCES = ["api.cpp", "bvh_build.cpp", "kernels.hip", "bvh_device.hip", "bvh_wide.hip", "nrc.hip"]
 
 # gfx950 only; packed FP32 instructions disabled for all device code
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -29,6 +29,7 @@
 
 #include "bvh_build.h"
 #include "bvh_device.h"
+#include "bvh_wide.h"
 #include "kernels.h"
 #include "layout.h"
 #include "nrc.h"
@@ -941,6 +942,88 @@ sdd_status device_bvh(sdd_ctx* c, const BuildInput& bi, GridBvh& gb) {
     return SDD_OK;
 }
 
+// Replaces the binary nodes on the device (n2 slots; cell roots and node
+// counts in c->d_cell_root / c->d_cell_nodes and gb.cell_nodes) by the 4-wide
+// nodes the traversal reads, and updates gb.cell_root / gb.cell_nodes.
+sdd_status widen_bvh(sdd_ctx* c, long long n2, GridBvh& gb) {
+    const int G = (int)gb.cell_nodes.size();
+    if (n2 <= 0 || n2 >= (1LL << 31) - 1) return fail(c, SDD_ERR_UNSUPPORTED, "BVH node count out of range");
+    WidenBufs b{};
+    b.n2 = (int)n2;
+    b.nodes2 = c->d_nodes;
+    b.cell_root = c->d_cell_root;
+    b.cell_nodes = c->d_cell_nodes;
+    b.G = G;
+    b.max_cell_nodes = 0;
+    for (int v : gb.cell_nodes) b.max_cell_nodes = std::max(b.max_cell_nodes, v);
+    std::vector<void*> temps;
+    auto tmp_alloc = [&](auto** p, size_t n) -> sdd_status {
+        sdd_status s2 = dalloc(c, p, n);
+        if (s2 == SDD_OK) temps.push_back((void*)*p);
+        return s2;
+    };
+    auto release = [&]() {
+        for (void* p : temps) dfree(c, p);
+        temps.clear();
+    };
+    const size_t n1 = (size_t)n2 + 1;
+    sdd_status st;
+    hipError_t e = widen_mark(b, c->stream);  // scratch size only
+    if (e != hipSuccess) return hip_fail(c, e, "widen: scan scratch");
+    char* tmp = nullptr;
+    if ((st = tmp_alloc(&b.anc[0], n1)) != SDD_OK || (st = tmp_alloc(&b.anc[1], n1)) != SDD_OK ||
+        (st = tmp_alloc(&b.dist[0], n1)) != SDD_OK || (st = tmp_alloc(&b.dist[1], n1)) != SDD_OK ||
+        (st = tmp_alloc(&b.flag, n1)) != SDD_OK || (st = tmp_alloc(&b.idx, n1)) != SDD_OK ||
+        (st = tmp_alloc(&tmp, std::max<size_t>(1, b.tmp_bytes))) != SDD_OK) {
+        release();
+        return st;
+    }
+    b.tmp = tmp;
+    int total = 0;
+    e = widen_mark(b, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&total, b.idx + n2, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        release();
+        return hip_fail(c, e, "widen: node depths");
+    }
+    uint4* nodes4 = nullptr;
+    int *root4 = nullptr, *cnt4 = nullptr;
+    if (total <= 0) {
+        release();
+        return fail(c, SDD_ERR_HIP, "widen: no nodes");
+    }
+    if ((st = dalloc(c, &nodes4, 4 * (size_t)total)) != SDD_OK || (st = dalloc(c, &root4, (size_t)G)) != SDD_OK ||
+        (st = dalloc(c, &cnt4, (size_t)G)) != SDD_OK) {
+        dfree(c, nodes4);
+        dfree(c, root4);
+        dfree(c, cnt4);
+        release();
+        return st;
+    }
+    e = widen_emit(b, nodes4, root4, cnt4, c->stream);
+    gb.cell_root.assign(G, 0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(gb.cell_root.data(), root4, sizeof(int) * G, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(gb.cell_nodes.data(), cnt4, sizeof(int) * G, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    release();
+    if (e != hipSuccess) {
+        dfree(c, nodes4);
+        dfree(c, root4);
+        dfree(c, cnt4);
+        return hip_fail(c, e, "widen: 4-wide nodes");
+    }
+    dfree(c, c->d_nodes);
+    dfree(c, c->d_cell_root);
+    dfree(c, c->d_cell_nodes);
+    c->d_nodes = nodes4;
+    c->d_cell_root = root4;
+    c->d_cell_nodes = cnt4;
+    return SDD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -980,6 +1063,11 @@ sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
         (st = upload(c, &c->d_tris, reinterpret_cast<const float4*>(gb.tris.data()), gb.tris.size())) != SDD_OK ||
         (st = upload(c, &c->d_cell_root, gb.cell_root.data(), gb.cell_root.size())) != SDD_OK ||
         (st = upload(c, &c->d_planes, gb.planes.data(), gb.planes.size())) != SDD_OK) {
+        free_accel(c);
+        return st;
+    }
+    const long long n2 = d->device_build ? gb.n_refs + (long long)d->nx * d->ny * d->nz : (long long)gb.nodes.size() / 8;
+    if ((st = widen_bvh(c, n2, gb)) != SDD_OK) {
         free_accel(c);
         return st;
     }

@@ -212,6 +212,22 @@ __device__ __forceinline__ bool tri_test(const RayTrav& r, float4 a, float4 b, f
     return true;
 }
 
+// A value the compiler cannot look through: a load of LDS on one side of a
+// branch and of HBM on the other then stay two loads (ds_read and
+// global_load) instead of one load through a selected generic pointer, a
+// flat access that waits on both memory paths.  The asm is empty: it
+// neither reads nor writes memory.
+typedef __attribute__((address_space(3))) int lds_int;
+typedef __attribute__((address_space(1))) int global_int;
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ uint4 opaque(uint4 v) {
+    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+    return v;
+}
+
 // Traversal of one cell's BVH with the node steps and the triangle tests in
 // separate loops.  A lane that reaches a leaf parks it and goes on down the
 // tree until most lanes of the wave still taking node steps have a parked
@@ -234,43 +250,65 @@ __device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const 
     constexpr int kDone = -2147483647 - 1;  // INT_MIN: no leaf encodes as it (~INT_MAX triangles)
     int sp = 0;
     auto pop = [&]() -> int {
-        // entries beyond kStack were never stored (the builder keeps the depth below it)
+        // entries beyond kStack were never stored (the builders' depth cap keeps
+        // the stack below it)
         if (sp == 0 || sp > kStack) return kDone;
         --sp;
-        return sp < kLdsStack ? stk[sp * kTraceBlock] : gstk[(sp - kLdsStack) * gstride];
+        int v;
+        if (sp < kLdsStack) v = opaque(stk[sp * kTraceBlock]);
+        else v = gstk[(sp - kLdsStack) * gstride];
+        return v;
     };
     int link = root;  // next node (>= 0) or leaf (< 0), kDone when the stack is empty
     int leaf = 0;     // parked leaf (< 0), 0 for none
     while (link != kDone) {
         while (link >= 0) {
+            // the cell's first kTopNodes nodes (breadth-first: its top levels) come from LDS
             const int rel = link - root;
-            uint4 c0, c1;
+            uint4 ch[kBvhWidth];
             if (rel < kTopNodes) {
-                c0 = top[2 * rel];
-                c1 = top[2 * rel + 1];
+#pragma unroll
+                for (int i = 0; i < kBvhWidth; ++i) ch[i] = opaque(top[kBvhWidth * rel + i]);
             } else {
-                c0 = nodes[2 * (size_t)link];
-                c1 = nodes[2 * (size_t)link + 1];
+#pragma unroll
+                for (int i = 0; i < kBvhWidth; ++i) ch[i] = nodes[kBvhWidth * (size_t)link + i];
             }
-            const int l0 = (int)c0.w, l1 = (int)c1.w;
             if (COUNT) ++n_nodes;
-            const float t0 = box_enter(r, c0, tlo, thi);
-            const float t1 = box_enter(r, c1, tlo, thi);
-            const bool h0 = t0 != INFINITY && l0 != kEmptyLink, h1 = t1 != INFINITY && l1 != kEmptyLink;
-            if (h0 && h1) {
-                const bool first0 = t0 <= t1;
-                const int far = first0 ? l1 : l0;
-                if (sp < kLdsStack) stk[sp * kTraceBlock] = far;
-                else if (sp < kStack) gstk[(sp - kLdsStack) * gstride] = far;
-                ++sp;
-                link = first0 ? l0 : l1;
-            } else if (h0) {
-                link = l0;
-            } else if (h1) {
-                link = l1;
-            } else {
-                link = pop();
+            float t[kBvhWidth];
+            int l[kBvhWidth];
+#pragma unroll
+            for (int i = 0; i < kBvhWidth; ++i) {
+                l[i] = (int)ch[i].w;
+                const float te = box_enter(r, ch[i], tlo, thi);  // tested unconditionally: no branch per child
+                t[i] = l[i] == kEmptyLink ? INFINITY : te;
             }
+            // nearest first: sorting network on (t, link), as min / max and selects
+            static_assert(kBvhWidth == 4, "the sorting network is written for 4 children");
+            auto order = [&](int i, int j) {
+                const bool sw = t[j] < t[i];
+                const float lo = sw ? t[j] : t[i], hi = sw ? t[i] : t[j];
+                const int li = sw ? l[j] : l[i], lj = sw ? l[i] : l[j];
+                t[i] = lo;
+                t[j] = hi;
+                l[i] = li;
+                l[j] = lj;
+            };
+            order(0, 1);
+            order(2, 3);
+            order(0, 2);
+            order(1, 3);
+            order(1, 2);
+            // the farther hit children wait on the stack, farthest deepest; the
+            // nearest is next (short stack in LDS, deeper entries in HBM)
+#pragma unroll
+            for (int i = kBvhWidth - 1; i >= 1; --i)
+                if (t[i] != INFINITY) {
+                    // typed address spaces keep these two stores apart (no flat store)
+                    if (sp < kLdsStack) ((lds_int*)stk)[sp * kTraceBlock] = l[i];
+                    else if (sp < kStack) ((global_int*)gstk)[(sp - kLdsStack) * gstride] = l[i];
+                    ++sp;
+                }
+            link = t[0] != INFINITY ? l[0] : pop();
             if (link < 0 && link != kDone && leaf == 0) {
                 leaf = link;
                 link = pop();
@@ -417,7 +455,7 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(kTr
 void k_trace(TraceParams P) {
     extern __shared__ int s_pref[];  // 2 * n_cells + 1 entries (dynamic, so small grids keep occupancy)
     __shared__ int s_stack[kLdsStack * kTraceBlock];
-    __shared__ uint4 s_top[(kTraceBlock / 64) * 2 * kTopNodes];
+    __shared__ uint4 s_top[(kTraceBlock / 64) * kBvhWidth * kTopNodes];
     const int G = P.n_cells;
     const int E = 2 * G;  // entry e = 2 * cell + kind
     if (threadIdx.x < 64) {
@@ -462,7 +500,7 @@ void k_trace(TraceParams P) {
     int* gstk = P.gstack + blockIdx.x * kTraceBlock + threadIdx.x;
     const int xcd = blockIdx.x % kXcd;
     int n_nodes = 0, n_tris = 0;
-    uint4* top = s_top + (threadIdx.x / 64) * 2 * kTopNodes;  // this wave's copy of a cell's top nodes
+    uint4* top = s_top + (threadIdx.x / 64) * kBvhWidth * kTopNodes;  // this wave's copy of a cell's top nodes
     int top_cell = -1;
 
     // static XCD-aware striding: the waves of XCD x walk part x of the chunk
@@ -487,8 +525,8 @@ void k_trace(TraceParams P) {
             // have returned), so it can be overwritten; LDS operations of one
             // wave complete in order
             top_cell = cell;
-            const int nn = 2 * min(P.cell_nodes[cell], kTopNodes);
-            const uint4* src = P.nodes + 2 * (size_t)P.cell_root[cell];
+            const int nn = kBvhWidth * min(P.cell_nodes[cell], kTopNodes);
+            const uint4* src = P.nodes + kBvhWidth * (size_t)P.cell_root[cell];
             for (int i = lane; i < nn; i += 64) top[i] = src[i];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();

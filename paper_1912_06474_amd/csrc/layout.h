@@ -2,12 +2,14 @@
 // and the HIP kernels.
 //
 // Per-subdomain acceleration data (built on the host, one BVH per grid cell):
-//   nodes  uint4[2 * n_nodes]   32 B per inner node, one 16 B record per child:
+//   nodes  uint4[4 * n_nodes]   64 B per 4-wide inner node, one 16 B record per child:
 //          (lo.x | hi.x << 16, lo.y | hi.y << 16, lo.z | hi.z << 16, link)
 //          with 16-bit lattice coordinates: coordinate = base + q * step of
 //          the node's cell (cell_q), rounded outward; link >= 0 inner node
-//          index, link < 0 leaf starting at triangle ~link, kEmptyLink none.
-//          Nodes of each cell are stored breadth-first (root first).
+//          index, link < 0 leaf starting at triangle ~link, kEmptyLink none
+//          (a node's empty records come last).  Nodes of each cell are stored
+//          breadth-first (root first).  The builders emit binary nodes (two
+//          records, same format), which bvh_wide.hip widens.
 //   cell_q float4[2 * n_cells]   lattice of each cell: (base.xyz, 0), (step.xyz, 0)
 //   tris   float4[3 * n_refs]   48 B per triangle reference, in leaf order:
 //          (v0, prim), (e1, meta), (e2, glass index) with meta = type | last_in_leaf << 2
@@ -45,11 +47,15 @@
 namespace sdd {
 
 constexpr int kTraceBlock = 128;  // threads per traversal workgroup
-constexpr int kStack = 40;        // traversal stack entries per lane (total)
+constexpr int kBvhWidth = 4;      // child records per node the traversal reads
+constexpr int kMaxBvhDepth = 40;  // depth cap of the binary builders (a node at the cap becomes a leaf)
+// traversal stack entries per lane (total): a 4-wide node pushes at most 3
+// siblings, and the widened tree has at most kMaxBvhDepth / 2 + 1 inner levels
+constexpr int kStack = 64;
+static_assert(3 * (kMaxBvhDepth / 2 + 1) <= kStack, "the traversal stack must hold every pushed sibling");
 constexpr int kLdsStack = 8;      // of which the first kLdsStack live in LDS, the rest in HBM
-constexpr int kTopNodes = 64;     // breadth-first top nodes of the current cell kept in LDS per wave
+constexpr int kTopNodes = 32;     // breadth-first top nodes (128 records) of the current cell kept in LDS per wave
 constexpr int kTraceWaves = 8;    // waves per SIMD the trace kernel is compiled for (registers <= 64)
-constexpr int kMaxBvhDepth = kStack;  // the builder never exceeds the stack
 constexpr int kChunk = 64;        // rays per scheduling chunk (one wave)
 constexpr int kXcd = 8;           // XCDs of an MI355X; workgroup i runs on XCD i % 8
 constexpr int kMaxGlass = 4;      // pane crossings recorded per shadow segment
