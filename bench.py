@@ -57,9 +57,12 @@ WORKLOADS = {
                      nrc=dict(ref_frames=48, train_paths=1 << 16, train_steps=4, train_batch=1 << 14)),
 }
 
-# per cache query (one path, one wavelength): multiply-adds of the five 64 x 64
-# hidden layers and the 64-wide output layer, two flops each
-NRC_FLOPS_PER_ROW = 2 * (5 * 64 * 64 + 64)
+# Multiply-adds of one cache query launch, two flops each, as the network is
+# evaluated: per (path, wavelength) hidden layers 1..4 (64 x 64) and the output
+# (64); per path layer 0's 48 position and direction inputs (x 64); per
+# wavelength layer 0's 16 one-blob inputs (x 64).
+def nrc_query_flops(rows, nl):
+    return 2 * (rows * (4 * 64 * 64 + 64) + rows // nl * 48 * 64 + nl * 16 * 64)
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16
 ROOM_LO, ROOM_HI = (0.0, 0.0, 0.0), (4.0, 3.0, 2.5)
 
@@ -246,7 +249,7 @@ def nrc_comparison(args, tr, scene, wl):
     # roofline of the cache query (BF16 matrix cores) over the cache run
     launches = max(1, stn["nrc_query_launches"])
     avg_ms = stn["ms_nrc_query"] / launches
-    flops = stn["nrc_query_rows"] / launches * NRC_FLOPS_PER_ROW
+    flops = nrc_query_flops(stn["nrc_query_rows"] // launches, nl)
     achieved = flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     value = samples_plain * nl / t_nrc if reached else None
     return {

@@ -520,28 +520,71 @@ __device__ __forceinline__ bf16x8 mfma_hash_operand(const NrcNet& net, const Mfm
     return v;
 }
 
-// the network from its input operands b0, b1 (4 column tiles): hidden layers
-// 0..4, then the output layer; y[nt] is the output of column c of tile nt in
+// Layer 0 is split by input: its path part (hash levels and harmonics, step
+// 0 and the harmonic slots of step 1, started from the bias) and its
+// wavelength part (the one-blob slots of step 1, started from 0), added in
+// FP32.  A BF16 product is exact in FP32, so only the summation order
+// differs from one chain, and it is the same for every kernel that uses these
+// functions.  The cache query then computes the path part once per path and
+// the wavelength part once per wavelength for all paths.
+__device__ __forceinline__ void mfma_layer0_path(const MfmaLds& L, int lane, int g, const bf16x8 (&h)[4],
+                                                 const bf16x8 (&sh)[4], f32x4 (&P)[4][4]) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const f32x4 bias = *reinterpret_cast<const f32x4*>(&L.b[16 * mt + 4 * g]);
+        const bf16x8 a0 = L.w[(mt * 2 + 0) * 64 + lane];
+        const bf16x8 a1 = L.w[(mt * 2 + 1) * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            P[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, h[nt], bias, 0, 0, 0);
+            P[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, sh[nt], P[nt][mt], 0, 0, 0);
+        }
+    }
+}
+
+// wavelength part of layer 0 for one B operand (one-blob slots, harmonic slots zero)
+__device__ __forceinline__ f32x4 mfma_layer0_lambda(const MfmaLds& L, int lane, int mt, bf16x8 bl) {
+    const bf16x8 a1 = L.w[(mt * 2 + 1) * 64 + lane];
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bl, (f32x4){0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+}
+
+// hidden layers 1..4 and the output layer from layer 0's pre-activations
+// z0[nt][mt] (4 column tiles); y[nt] is the output of column c of tile nt in
 // the lanes of group 0
-__device__ __forceinline__ void mfma_forward(const MfmaLds& L, int lane, int g, bf16x8 (&b0)[4], bf16x8 (&b1)[4],
-                                             float bo, float (&y)[4]) {
-    f32x4 acc[4][4];
-    for (int k = 0; k < kNrcLayers; ++k) {
+__device__ __forceinline__ void mfma_rest(const MfmaLds& L, int lane, int g, const f32x4 (&z0)[4][4], float bo,
+                                          float (&y)[4]) {
+    bf16x8 b0[4], b1[4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const f32x4 bias = *reinterpret_cast<const f32x4*>(&L.b[k * kNrcHid + 16 * mt + 4 * g]);
-            const bf16x8 a0 = L.w[((k * 4 + mt) * 2 + 0) * 64 + lane];
-            const bf16x8 a1 = L.w[((k * 4 + mt) * 2 + 1) * 64 + lane];
+    for (int nt = 0; nt < 4; ++nt) {
+        b0[nt] = relu_pack8(z0[nt][0], z0[nt][1]);
+        b1[nt] = relu_pack8(z0[nt][2], z0[nt][3]);
+    }
+    for (int k = 1; k < kNrcLayers; ++k) {
+        // output tiles in pairs, each pair packed to the next operand before
+        // the next pair (fewer live accumulators; same products and order)
+        bf16x8 nb[2][4];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0[nt], bias, 0, 0, 0);
-                acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1[nt], acc[nt][mt], 0, 0, 0);
+        for (int half = 0; half < 2; ++half) {
+            f32x4 acc[4][2];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int mt = 2 * half + m;
+                const f32x4 bias = *reinterpret_cast<const f32x4*>(&L.b[k * kNrcHid + 16 * mt + 4 * g]);
+                const bf16x8 a0 = L.w[((k * 4 + mt) * 2 + 0) * 64 + lane];
+                const bf16x8 a1 = L.w[((k * 4 + mt) * 2 + 1) * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    acc[nt][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0[nt], bias, 0, 0, 0);
+                    acc[nt][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1[nt], acc[nt][m], 0, 0, 0);
+                }
             }
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) nb[half][nt] = relu_pack8(acc[nt][0], acc[nt][1]);
         }
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            b0[nt] = relu_pack8(acc[nt][0], acc[nt][1]);
-            b1[nt] = relu_pack8(acc[nt][2], acc[nt][3]);
+            b0[nt] = nb[0][nt];
+            b1[nt] = nb[1][nt];
         }
     }
     const bf16x8 o0 = L.w[kNrcFrags + lane], o1 = L.w[kNrcFrags + 64 + lane];
@@ -552,6 +595,26 @@ __device__ __forceinline__ void mfma_forward(const MfmaLds& L, int lane, int g, 
         o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o1, b1[nt], o, 0, 0, 0);
         y[nt] = o[0];
     }
+}
+
+// the network from its input operands b0 (step 0), b1 (step 1: harmonics in
+// slots 0..3, one-blob in slots 4..7), 4 column tiles
+__device__ __forceinline__ void mfma_forward(const MfmaLds& L, int lane, int g, const bf16x8 (&b0)[4],
+                                             const bf16x8 (&b1)[4], float bo, float (&y)[4]) {
+    bf16x8 shq[4], blq[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const u32x4 v = __builtin_bit_cast(u32x4, b1[nt]);
+        shq[nt] = __builtin_bit_cast(bf16x8, (u32x4){v[0], v[1], 0u, 0u});
+        blq[nt] = __builtin_bit_cast(bf16x8, (u32x4){0u, 0u, v[2], v[3]});
+    }
+    f32x4 z0[4][4];
+    mfma_layer0_path(L, lane, g, b0, shq, z0);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) z0[nt][mt] = z0[nt][mt] + mfma_layer0_lambda(L, lane, mt, blq[nt]);
+    mfma_rest(L, lane, g, z0, bo, y);
 }
 
 __global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, const float* x, const float* w,
@@ -632,10 +695,12 @@ __global__ __launch_bounds__(256) void k_query_operands(NrcNet net, int n, const
 
 // Cache values of n paths at every wavelength: lhat[path][l], from the
 // operands of k_query_operands (n rounded up to whole 64-path waves there).
-// Per wavelength only the one-blob slots change.  LDS holds only the
-// weights, so three blocks fit a CU.  Same products and summation order as
-// k_infer_mfma.
-__global__ __launch_bounds__(kMfmaBlock) void k_query_mfma(NrcNet net, int n, const uint4* hop, const uint2* sop,
+// Per wavelength only the one-blob slots change, so layer 0's path part is
+// computed once and its wavelength part once per wavelength.  LDS holds only
+// the weights, so three blocks fit a CU.  Same products and summation order
+// as k_infer_mfma.
+__global__ __launch_bounds__(kMfmaBlock) __attribute__((amdgpu_waves_per_eu(3)))
+void k_query_mfma(NrcNet net, int n, const uint4* hop, const uint2* sop,
                                                           const float* lam, int nl, int nlp, float* lhat, int tiled) {
     __shared__ MfmaLds L;
     mfma_stage(net, L);
@@ -651,6 +716,14 @@ __global__ __launch_bounds__(kMfmaBlock) void k_query_mfma(NrcNet net, int n, co
         shq[nt] = sop[slot];
     }
     const float bo = net.p[net.off_bo()];
+    // layer 0's path part, once for all wavelengths
+    f32x4 P[4][4];
+    {
+        bf16x8 shop[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) shop[nt] = __builtin_bit_cast(bf16x8, (u32x4){shq[nt].x, shq[nt].y, 0u, 0u});
+        mfma_layer0_path(L, lane, g, hq, shop, P);
+    }
     for (int l = 0; l < nl; ++l) {
         // keeps the weight fragments' LDS reads inside the loop (hoisted out of
         // it they would hold 160 registers)
@@ -662,14 +735,17 @@ __global__ __launch_bounds__(kMfmaBlock) void k_query_mfma(NrcNet net, int n, co
         const uint32_t bl1 = __builtin_bit_cast(
             uint32_t,
             __builtin_convertvector((f32x2){blob_bin(net, lm, 4 * g + 2), blob_bin(net, lm, 4 * g + 3)}, bf16x2));
-        bf16x8 b0[4], b1[4];
+        const bf16x8 blq = __builtin_bit_cast(bf16x8, (u32x4){0u, 0u, bl0, bl1});
+        // layer 0's wavelength part: every column of the tile holds the same bins
+        f32x4 z0[4][4];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            b0[nt] = hq[nt];
-            b1[nt] = __builtin_bit_cast(bf16x8, (u32x4){shq[nt].x, shq[nt].y, bl0, bl1});
+        for (int mt = 0; mt < 4; ++mt) {
+            const f32x4 q = mfma_layer0_lambda(L, lane, mt, blq);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) z0[nt][mt] = P[nt][mt] + q;
         }
         float out[4];
-        mfma_forward(L, lane, g, b0, b1, bo, out);
+        mfma_rest(L, lane, g, z0, bo, out);
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const long long row = base + nt * 16 + c;
