@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_infer(NrcNet net, int n, const float* x
 
 __device__ __forceinline__ int frag_feature(int q, int g) { return 16 * (q >> 2) + 4 * g + (q & 3); }
 
-constexpr int kTrainBlock = 256;
+constexpr int kTrainBlock = 64;
 
 __global__ __launch_bounds__(kTrainBlock) void k_train_fwd_mfma(NrcNet net, NrcBatch b) {
     __shared__ float s_loss[kTrainBlock / 64];
@@ -906,7 +906,7 @@ hipError_t nrc_launch_grad(const NrcNet& net, const NrcBatch& b, hipStream_t st)
     hipLaunchKernelGGL(k_train_bwd_mfma, dim3(nblocks(b.n, kTrainBlock)), dim3(kTrainBlock), 0, st, net, b);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int rows_per_block = 1024;
+    const int rows_per_block = 256;  // 2^14 rows: 64 x 6 blocks, enough to fill the device
     hipLaunchKernelGGL(k_train_wgrad, dim3(nblocks(b.n, rows_per_block), kNrcLayers + 1), dim3(256), 0, st, net, b,
                        rows_per_block);
     return hipGetLastError();
