@@ -165,6 +165,10 @@ struct sdd_ctx {
     float* d_lam = nullptr;  // scene wavelengths (nm), FP32
     uint4* nrc_hop = nullptr;  // staged matrix operands of cache queries
     uint2* nrc_sop = nullptr;
+    uint32_t* nrc_okeys = nullptr;  // gather order of the cache queries: sort keys [2][paths],
+    int* nrc_ovals = nullptr;       // path indices [2][paths], and the sort's scratch
+    char* nrc_otemp = nullptr;
+    size_t nrc_otemp_bytes = 0;
     long long nrc_ocap = 0;
 
     // graph replay of repeated trace calls (SDD_TRACE_GRAPH)
@@ -359,7 +363,11 @@ void free_nrc(sdd_ctx* c) {
     free_nrc_render(c);
     dfree(c, c->nrc_hop);
     dfree(c, c->nrc_sop);
+    dfree(c, c->nrc_okeys);
+    dfree(c, c->nrc_ovals);
+    dfree(c, c->nrc_otemp);
     c->nrc_ocap = 0;
+    c->nrc_otemp_bytes = 0;
     free_nrc_batch(c);
     dfree(c, c->nrc_loss);
     dfree(c, c->nrc.p);
@@ -1110,14 +1118,26 @@ sdd_status nrc_ensure_ops(sdd_ctx* c, int n) {
     if (need <= c->nrc_ocap) return SDD_OK;
     dfree(c, c->nrc_hop);
     dfree(c, c->nrc_sop);
+    dfree(c, c->nrc_okeys);
+    dfree(c, c->nrc_ovals);
+    dfree(c, c->nrc_otemp);
     c->nrc_ocap = 0;
+    c->nrc_otemp_bytes = 0;
     sdd_status st;
+    const size_t tb = std::max<size_t>(1, nrc_order_temp_bytes((int)need));
     if ((st = dalloc(c, &c->nrc_hop, (size_t)(4 * need))) != SDD_OK ||
-        (st = dalloc(c, &c->nrc_sop, (size_t)(4 * need))) != SDD_OK)
+        (st = dalloc(c, &c->nrc_sop, (size_t)(4 * need))) != SDD_OK ||
+        (st = dalloc(c, &c->nrc_okeys, (size_t)(2 * need))) != SDD_OK ||
+        (st = dalloc(c, &c->nrc_ovals, (size_t)(2 * need))) != SDD_OK ||
+        (st = dalloc(c, &c->nrc_otemp, tb)) != SDD_OK)
         return st;
+    c->nrc_otemp_bytes = tb;
     c->nrc_ocap = need;
     return SDD_OK;
 }
+
+// the gather order scratch of the cache queries (valid after nrc_ensure_ops)
+NrcOrder nrc_order(sdd_ctx* c) { return NrcOrder{c->nrc_okeys, c->nrc_ovals, c->nrc_otemp, c->nrc_otemp_bytes}; }
 
 // render buffers of the radiance cache: n batch paths, slots training paths of depth D
 sdd_status nrc_ensure_render(sdd_ctx* c, long long n, long long slots, int D) {
@@ -1471,12 +1491,13 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
             if (c->nrc_precision == 0) {
                 Timer tm(c, timing, 4);
                 HIP_TRY(c, nrc_launch_query(c->nrc, N, c->nrc_cx, c->nrc_cn, c->d_lam, c->nl, c->nlp, c->nrc_lhat, 1,
-                                            0, c->nrc_hop, c->nrc_sop, c->stream));
+                                            0, c->nrc_hop, c->nrc_sop, nullptr, c->stream));
             } else {
                 {
                     Timer tm(c, timing, 3);
+                    const NrcOrder ord = nrc_order(c);
                     HIP_TRY(c, nrc_launch_query_operands(c->nrc, N, c->nrc_cx, c->nrc_cn, c->nrc_hop, c->nrc_sop,
-                                                         c->stream));
+                                                         &ord, c->stream));
                 }
                 Timer tm(c, timing, 4);  // the matrix-core kernel alone
                 HIP_TRY(c, nrc_launch_query_mfma(c->nrc, N, c->nrc_hop, c->nrc_sop, c->d_lam, c->nl, c->nlp,
@@ -2427,9 +2448,11 @@ sdd_status sdd_nrc_query(sdd_ctx* c, int32_t n, const float* x4, const float* n4
         sdd_status st = nrc_ensure_ops(c, n);
         if (st != SDD_OK) return st;
     }
+    const NrcOrder ord = nrc_order(c);
     const hipError_t e = nrc_launch_query(c->nrc, n, reinterpret_cast<const float4*>(x4),
                                           reinterpret_cast<const float4*>(n4), c->d_lam, c->nl, c->nlp, out, 0,
-                                          precision, c->nrc_hop, c->nrc_sop, c->stream);
+                                          precision, c->nrc_hop, c->nrc_sop, precision == 1 ? &ord : nullptr,
+                                          c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "nrc query");
     return SDD_OK;
 }

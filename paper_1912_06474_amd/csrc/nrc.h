@@ -62,6 +62,20 @@ struct NrcBatch {
     float* loss;        // [1] accumulated loss (mean over the rows)
 };
 
+// Order of the operand gathers: the paths sorted by the Morton code of
+// their (normalised) cache vertex, so that neighbouring gathers share table
+// lines in the caches.  keys and vals hold 2 x n entries each (the sort's two
+// buffers); temp is the sort's scratch, nrc_order_temp_bytes(n) bytes.  The
+// operands of every path still go to that path's own slots, so the order
+// changes no result.
+struct NrcOrder {
+    uint32_t* keys;
+    int* vals;
+    void* temp;
+    size_t temp_bytes;
+};
+size_t nrc_order_temp_bytes(int n);
+
 // FP32 forward of n rows (device arrays)
 hipError_t nrc_launch_infer(const NrcNet& net, int n, const float* x, const float* w, const float* lam, float* y,
                             hipStream_t st);
@@ -83,10 +97,12 @@ __host__ __device__ inline size_t nrc_lhat_index(long long path, int l, int nlp,
 // each -- 4 lane groups of 16 B and 8 B per path; unused for precision 0)
 long long nrc_query_ops_paths(int n);
 hipError_t nrc_launch_query(const NrcNet& net, int n, const float4* cx, const float4* cn, const float* lam, int nl,
-                            int nlp, float* lhat, int tiled, int precision, uint4* hop, uint2* sop, hipStream_t st);
-// the two stages of the BF16 query: operand gathers, then the matrix-core network
+                            int nlp, float* lhat, int tiled, int precision, uint4* hop, uint2* sop,
+                            const NrcOrder* ord, hipStream_t st);
+// the two stages of the BF16 query: operand gathers (in the order of ord, or
+// path order if ord is null), then the matrix-core network
 hipError_t nrc_launch_query_operands(const NrcNet& net, int n, const float4* cx, const float4* cn, uint4* hop,
-                                     uint2* sop, hipStream_t st);
+                                     uint2* sop, const NrcOrder* ord, hipStream_t st);
 hipError_t nrc_launch_query_mfma(const NrcNet& net, int n, const uint4* hop, const uint2* sop, const float* lam,
                                  int nl, int nlp, float* lhat, int tiled, hipStream_t st);
 // stable compaction of the training rows (pairs of float4) whose flag is set;

@@ -667,9 +667,10 @@ __global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, co
 // sop[(tile * 4 + g) * 16 + c].  A plain gather kernel at full occupancy; the
 // matrix kernel then needs no parking space and no gathers.
 __global__ __launch_bounds__(256) void k_query_operands(NrcNet net, int n, const float4* cx, const float4* cn,
-                                                        uint4* hop, uint2* sop) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+                                                        uint4* hop, uint2* sop, const int* order) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int p = order ? order[i] : i;  // a permutation of 0 .. n-1
     const float4 x4 = cx[p], n4 = cn[p];
     const float xp[3] = {x4.x, x4.y, x4.z};
     float xn[3];
@@ -691,6 +692,33 @@ __global__ __launch_bounds__(256) void k_query_operands(NrcNet net, int n, const
             __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){sh[4 * g], sh[4 * g + 1]}, bf16x2)),
             __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){sh[4 * g + 2], sh[4 * g + 3]}, bf16x2)));
     }
+}
+
+// 30-bit Morton code of the normalised cache vertex (10 bits per axis)
+__device__ __forceinline__ uint32_t spread3(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_query_keys(NrcNet net, int n, const float4* cx, uint32_t* keys, int* vals) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float4 x4 = cx[p];
+    const float xp[3] = {x4.x, x4.y, x4.z};
+    float xn[3];
+    normalise(net, xp, xn);
+    uint32_t m = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float q = fminf(fmaxf(xn[a] * 1024.0f, 0.0f), 1023.0f);  // NaN -> 0
+        m |= spread3((uint32_t)q) << a;
+    }
+    keys[p] = m;
+    vals[p] = p;
 }
 
 // Cache values of n paths at every wavelength: lhat[path][l], from the
@@ -849,22 +877,44 @@ hipError_t nrc_launch_infer_mfma(const NrcNet& net, int n, const float* x, const
 long long nrc_query_ops_paths(int n) { return ((long long)n + kMfmaRowsPerWave - 1) / kMfmaRowsPerWave * kMfmaRowsPerWave; }
 
 hipError_t nrc_launch_query(const NrcNet& net, int n, const float4* cx, const float4* cn, const float* lam, int nl,
-                            int nlp, float* lhat, int tiled, int precision, uint4* hop, uint2* sop, hipStream_t st) {
+                            int nlp, float* lhat, int tiled, int precision, uint4* hop, uint2* sop,
+                            const NrcOrder* ord, hipStream_t st) {
     if (n <= 0 || nl <= 0) return hipSuccess;
     if (precision == 0) {
         hipLaunchKernelGGL(k_query, dim3(nblocks((long long)n * nl, 256)), dim3(256), 0, st, net, n, cx, cn, lam, nl,
                            nlp, lhat, tiled);
         return hipGetLastError();
     }
-    hipError_t e = nrc_launch_query_operands(net, n, cx, cn, hop, sop, st);
+    hipError_t e = nrc_launch_query_operands(net, n, cx, cn, hop, sop, ord, st);
     if (e != hipSuccess) return e;
     return nrc_launch_query_mfma(net, n, hop, sop, lam, nl, nlp, lhat, tiled, st);
 }
 
+size_t nrc_order_temp_bytes(int n) {
+    size_t bytes = 0;
+    hipcub::DoubleBuffer<uint32_t> kb(nullptr, nullptr);
+    hipcub::DoubleBuffer<int> vb(nullptr, nullptr);
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kb, vb, n, 0, 30) != hipSuccess) return 0;
+    return bytes;
+}
+
 hipError_t nrc_launch_query_operands(const NrcNet& net, int n, const float4* cx, const float4* cn, uint4* hop,
-                                     uint2* sop, hipStream_t st) {
+                                     uint2* sop, const NrcOrder* ord, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_query_operands, dim3(nblocks(n, 256)), dim3(256), 0, st, net, n, cx, cn, hop, sop);
+    const int* order = nullptr;
+    if (ord) {
+        if (nrc_order_temp_bytes(n) > ord->temp_bytes) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_query_keys, dim3(nblocks(n, 256)), dim3(256), 0, st, net, n, cx, ord->keys, ord->vals);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipcub::DoubleBuffer<uint32_t> kb(ord->keys, ord->keys + n);
+        hipcub::DoubleBuffer<int> vb(ord->vals, ord->vals + n);
+        size_t bytes = ord->temp_bytes;
+        e = hipcub::DeviceRadixSort::SortPairs(ord->temp, bytes, kb, vb, n, 0, 30, st);
+        if (e != hipSuccess) return e;
+        order = vb.Current();  // the buffer the last pass wrote (chosen on the host)
+    }
+    hipLaunchKernelGGL(k_query_operands, dim3(nblocks(n, 256)), dim3(256), 0, st, net, n, cx, cn, hop, sop, order);
     return hipGetLastError();
 }
 
