@@ -794,8 +794,16 @@ __global__ __launch_bounds__(256) void k_route_scan(RouteParams P) {
     }
 }
 
+// Workgroup i runs on XCD i % 8; path block pb = x * per + j goes to the j-th
+// workgroup of XCD x, so each XCD routes a contiguous range of path blocks.
+// A key's runs from consecutive path blocks are adjacent in its queue, and
+// when one XCD writes them its L2 merges them into whole lines instead of
+// several XCDs writing back parts of the same lines.
 __global__ __launch_bounds__(kShadeBlock) void k_route(RouteParams P) {
-    const int pid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = gridDim.x / kXcd;  // the grid is a multiple of kXcd
+    const int pb = (int)(blockIdx.x % kXcd) * per + (int)(blockIdx.x / kXcd);
+    if (pb >= P.n_blocks) return;
+    const int pid = pb * kShadeBlock + threadIdx.x;
     if (pid >= P.N) return;
 #pragma unroll
     for (int kind = 0; kind < 2; ++kind) {
@@ -805,7 +813,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_route(RouteParams P) {
         if (tag < 0) continue;
         const int key = tag & 0xFFFF, rank = tag >> 16, nbin = P.nbin[kind];
         const int cell = key / nbin;
-        long long slot = (long long)S.hist[(long long)key * P.n_blocks + blockIdx.x] + rank;
+        long long slot = (long long)S.hist[(long long)key * P.n_blocks + pb] + rank;
         for (int k2 = cell * nbin; k2 < key; ++k2) slot += P.ktot[kind][k2];  // the cell's lower bins
         if (slot < 0 || slot >= P.cap || cell >= P.n_cells) continue;  // never expected: defence only
         const long long q = (long long)cell * P.cap + slot;
@@ -1147,7 +1155,8 @@ hipError_t launch_route(const RouteParams& p, hipStream_t st) {
     hipLaunchKernelGGL(k_route_scan, dim3(2 * p.n_cells * kExtBins), dim3(256), 0, st, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_route, dim3(blocks_for(p.N, kShadeBlock)), dim3(kShadeBlock), 0, st, p);
+    const int per = (p.n_blocks + kXcd - 1) / kXcd;
+    hipLaunchKernelGGL(k_route, dim3(per * kXcd), dim3(kShadeBlock), 0, st, p);
     return hipGetLastError();
 }
 
