@@ -963,7 +963,11 @@ sdd_status widen_bvh(sdd_ctx* c, long long n2, GridBvh& gb) {
     b.cell_nodes = c->d_cell_nodes;
     b.G = G;
     b.max_cell_nodes = 0;
-    for (int v : gb.cell_nodes) b.max_cell_nodes = std::max(b.max_cell_nodes, v);
+    for (int v : gb.cell_nodes) {
+        // every builder gives each cell a root (a wrapper node for an empty cell)
+        if (v <= 0) return fail(c, SDD_ERR_HIP, "widen: a cell without BVH nodes");
+        b.max_cell_nodes = std::max(b.max_cell_nodes, v);
+    }
     std::vector<void*> temps;
     auto tmp_alloc = [&](auto** p, size_t n) -> sdd_status {
         sdd_status s2 = dalloc(c, p, n);
@@ -1017,11 +1021,14 @@ sdd_status widen_bvh(sdd_ctx* c, long long n2, GridBvh& gb) {
         e = hipMemcpyAsync(gb.cell_nodes.data(), cnt4, sizeof(int) * G, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     release();
-    if (e != hipSuccess) {
+    bool rooted = e == hipSuccess;
+    for (int c2 = 0; rooted && c2 < G; ++c2) rooted = gb.cell_nodes[c2] >= 1 && gb.cell_root[c2] < total;
+    if (!rooted) {
         dfree(c, nodes4);
         dfree(c, root4);
         dfree(c, cnt4);
-        return hip_fail(c, e, "widen: 4-wide nodes");
+        return e != hipSuccess ? hip_fail(c, e, "widen: 4-wide nodes")
+                               : fail(c, SDD_ERR_HIP, "widen: a cell without a 4-wide root");
     }
     dfree(c, c->d_nodes);
     dfree(c, c->d_cell_root);

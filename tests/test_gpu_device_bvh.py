@@ -88,3 +88,28 @@ def test_device_bvh_room_scale_hits_and_build_time(tracer, which):
     assert st_d["n_refs"] == st_h["n_refs"]
     assert np.array_equal(pd, ph)
     assert np.array_equal(td, th)
+
+
+@pytest.mark.parametrize("grid,leaf,boxes", [((8, 8, 8), 1, 0), ((8, 8, 8), 4, 3), ((6, 5, 4), 2, 1)])
+def test_widened_trees_of_sparse_cells(tracer, grid, leaf, boxes):
+    """Both builders' binary trees are widened to 4-wide nodes on the device.
+    A fine grid over a sparse room gives the degenerate cases of the widening:
+    empty cells, cells whose root is one leaf (a wrapper node), one-triangle
+    leaves and trees of odd depth.  Hits must equal brute force either way."""
+    sc = sg.tiny_room(0, 16, n_boxes=boxes)
+    tracer.load_scene(sc)
+    o, d = _rays(20000, 7)
+    to, po = ora.trace_rays(sc, o.astype(np.float64), d.astype(np.float64), use_bvh=False)
+    results = []
+    for device in (False, True):
+        tracer.build_bvh(*grid, leaf_max=leaf, device=device)
+        st = tracer.stats()
+        print(f"[widen] grid {grid} leaf {leaf} boxes {boxes} device {device}: refs {st['n_refs']}, "
+              f"4-wide nodes {st['n_nodes']}, binary depth {st['max_bvh_depth']}", flush=True)
+        assert st["n_nodes"] >= st["n_cells"]  # at least a root per cell, empty cells included
+        t, prim = tracer.debug_trace_rays(o, d)
+        assert hit_agreement(prim, po) >= 0.9999
+        m = (prim == po) & (po >= 0)
+        assert np.all(np.abs(t[m] - to[m]) <= 1e-5 * np.maximum(1.0, to[m]))
+        results.append((t, prim))
+    assert np.array_equal(results[0][1], results[1][1])
