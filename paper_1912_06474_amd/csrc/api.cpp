@@ -511,7 +511,7 @@ long long bytes_per_path(const sdd_ctx* c, int max_depth) {
 }
 
 sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
-    const long long cnt_len = (long long)(2 * max_depth + 1) * (c->S + 1) * c->G;
+    const long long cnt_len = (long long)(2 * max_depth + 1) * (c->S + 1) * c->G * kCntStride;
     if (n <= c->ncap && max_depth <= c->dcap) return SDD_OK;
     free_batch(c);
     sdd_status st;
@@ -555,7 +555,9 @@ sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
 
 // counters of (phase, sweep); phase 2(d-1) holds the closest-hit rays of
 // depth d, phase 2(d-1)+1 the shadow rays of depth d
-inline int* counts_at(sdd_ctx* c, int phase, int k) { return c->d_counts + ((long long)phase * (c->S + 1) + k) * c->G; }
+inline int* counts_at(sdd_ctx* c, int phase, int k) {
+    return c->d_counts + ((long long)phase * (c->S + 1) + k) * c->G * kCntStride;
+}
 inline int ph_ext(int d) { return 2 * (d - 1); }
 inline int ph_sh(int d) { return 2 * (d - 1) + 1; }
 

@@ -281,9 +281,9 @@ __device__ __forceinline__ int rank_below(uint64_t m) {
 
 // Multi-split append: every lane with `active` gets a unique slot in the
 // segment `key` of a segmented queue whose per-segment fill counters are
-// `counts`.  One atomic per distinct key in the wave (ballot + mbcnt).  Must
-// be reached by all lanes of the wave together.
-__device__ __forceinline__ int wave_append(bool active, int key, int* counts) {
+// counts[key * stride].  One atomic per distinct key in the wave (ballot +
+// mbcnt).  Must be reached by all lanes of the wave together.
+__device__ __forceinline__ int wave_append(bool active, int key, int* counts, int stride) {
     int slot = -1;
     uint64_t pending = __ballot(active);
     while (pending) {
@@ -291,7 +291,7 @@ __device__ __forceinline__ int wave_append(bool active, int key, int* counts) {
         const int lk = __builtin_amdgcn_readlane(key, leader);
         const uint64_t m = __ballot(active && key == lk);
         int base = 0;
-        if (lane_id() == leader) base = atomicAdd(&counts[lk], popc64(m));
+        if (lane_id() == leader) base = atomicAdd(&counts[(size_t)lk * stride], popc64(m));
         base = __builtin_amdgcn_readlane(base, leader);
         if (active && key == lk) {
             slot = base + rank_below(m);

@@ -436,7 +436,7 @@ __device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueS
             }
         }
     }
-    const int slot = wave_append(cont, next, Q.cnt_out);
+    const int slot = wave_append(cont, next, Q.cnt_out, kCntStride);
     if (cont && slot < P.cap) {
         const long long q = (long long)next * P.cap + slot;
         Q.qa_out[q] = qa;
@@ -466,7 +466,7 @@ void k_trace(TraceParams P) {
         int local = 0;
         for (int e = c0; e < c1; ++e) {
             const int kind = e & 1;
-            const int n = P.active[kind] ? P.q[kind].cnt_in[e >> 1] : 0;
+            const int n = P.active[kind] ? P.q[kind].cnt_in[(e >> 1) * kCntStride] : 0;
             if (n > P.cap) atomicExch(P.overflow, 2);  // never expected: counters are bounded by cap
             local += (n + kChunk - 1) / kChunk;
         }
@@ -480,7 +480,7 @@ void k_trace(TraceParams P) {
         for (int e = c0; e < c1; ++e) {
             s_pref[e] = run;
             const int kind = e & 1;
-            const int n = P.active[kind] ? P.q[kind].cnt_in[e >> 1] : 0;
+            const int n = P.active[kind] ? P.q[kind].cnt_in[(e >> 1) * kCntStride] : 0;
             run += (n + kChunk - 1) / kChunk;
         }
         if (ln == 63) s_pref[E] = incl;
@@ -491,7 +491,8 @@ void k_trace(TraceParams P) {
     if (blockIdx.x == 0 && threadIdx.x < 2 && P.active[threadIdx.x]) {
         // every queued ray is traversed exactly once in this sweep
         unsigned long long n = 0;
-        for (int c = 0; c < G; ++c) n += (unsigned long long)min((long long)P.q[threadIdx.x].cnt_in[c], P.cap);
+        for (int c = 0; c < G; ++c)
+            n += (unsigned long long)min((long long)P.q[threadIdx.x].cnt_in[c * kCntStride], P.cap);
         if (n) atomicAdd(&P.stats[threadIdx.x == 0 ? kStatExtVisits : kStatShadowVisits], n);
     }
     const int lane = lane_id();
@@ -532,7 +533,7 @@ void k_trace(TraceParams P) {
             __builtin_amdgcn_wave_barrier();
         }
         const int idx = (chunk - s_pref[e]) * kChunk + lane;
-        const bool active = idx < min((long long)P.q[kind].cnt_in[cell], P.cap);
+        const bool active = idx < min((long long)P.q[kind].cnt_in[cell * kCntStride], P.cap);
         if (kind == 0)
             process_chunk<false, COUNT>(P, P.q[0], cell, idx, active, top, stk, gstk, gstride, n_nodes,
                                         n_tris);
@@ -787,7 +788,7 @@ __global__ __launch_bounds__(256) void k_route_scan(RouteParams P) {
         const int total = s_part[255];
         P.ktot[kind][key] = total;
         if (total) {
-            atomicAdd(&P.cnt[kind][key / P.nbin[kind]], total);  // queue lengths start at zero per batch
+            atomicAdd(&P.cnt[kind][(key / P.nbin[kind]) * kCntStride], total);  // queue lengths start at zero per batch
             if (P.count[kind])
                 atomicAdd(&P.stats[kind == 0 ? kStatExtRays : kStatShadowRays], (unsigned long long)total);
         }
@@ -1106,7 +1107,7 @@ __global__ void k_debug_rays(int n, const float* o, const float* d, GridParams g
         cell = locate_ray(grid, oo, dd, te);
     }
     const bool enq = valid && cell >= 0;
-    const int slot = wave_append(enq, cell, cnt);
+    const int slot = wave_append(enq, cell, cnt, kCntStride);
     if (enq && slot < cap) {
         const long long q = (long long)cell * cap + slot;
         qa[q] = make_float4(oo.x, oo.y, oo.z, te);

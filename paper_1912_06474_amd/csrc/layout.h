@@ -54,6 +54,10 @@ constexpr int kMaxBvhDepth = 40;  // depth cap of the binary builders (a node at
 constexpr int kStack = 64;
 static_assert(3 * (kMaxBvhDepth / 2 + 1) <= kStack, "the traversal stack must hold every pushed sibling");
 constexpr int kLdsStack = 8;      // of which the first kLdsStack live in LDS, the rest in HBM
+// queue fill counters are kCntStride ints apart (one 128-B line each): the
+// appends of every wave in the device are atomics on them, and counters
+// sharing a line would serialise all of them on that line
+constexpr int kCntStride = 32;
 constexpr int kTopNodes = 32;     // breadth-first top nodes (128 records) of the current cell kept in LDS per wave
 constexpr int kTraceWaves = 8;    // waves per SIMD the trace kernel is compiled for (registers <= 64)
 constexpr int kChunk = 64;        // rays per scheduling chunk (one wave)
