@@ -118,6 +118,8 @@ struct sdd_ctx {
     int n_blocks = 0;
     int* d_counts = nullptr;
     long long counts_len = 0;
+    long long batch_bytes = 0;  // device bytes of the path batch (ensure_batch)
+    long long call_budget = 0;  // memory budget of the current call (set before any capture)
     int* d_overflow = nullptr;
     int* d_ktot = nullptr;  // routing key totals [2][kMaxCells * kExtBins]
     int* d_gstack = nullptr;  // traversal stack spill: (kStack - kLdsStack) ints per trace thread
@@ -329,6 +331,7 @@ void free_batch(sdd_ctx* c) {
     dfree(c, c->d_counts);
     c->ncap = 0;
     c->dcap = 0;
+    c->batch_bytes = 0;
 }
 
 void free_nrc_batch(sdd_ctx* c) {
@@ -498,11 +501,23 @@ struct Timer {
     }
 };
 
-long long mem_budget_bytes() {
-    const char* s = std::getenv("SDD_MEM_BUDGET_GB");
-    double gb = s ? std::atof(s) : 48.0;
-    if (!(gb > 0.0)) gb = 48.0;
-    return (long long)(gb * 1024.0 * 1024.0 * 1024.0);
+// Device memory the path batch (queues, path state, history) may take:
+// SDD_MEM_BUDGET_GB if set, else half the device's memory, at most three
+// quarters of what is free plus what this context's batch already holds (it
+// is freed before a larger one is allocated), and at least 4 GiB.  Queues
+// take O(cells x batch) memory, so many-cell grids run larger batches, and
+// fewer of them, when the budget is larger.
+long long mem_budget_bytes(const sdd_ctx* c) {
+    constexpr double kGiB = 1024.0 * 1024.0 * 1024.0;
+    if (const char* s = std::getenv("SDD_MEM_BUDGET_GB")) {
+        const double gb = std::atof(s);
+        if (gb > 0.0) return (long long)(gb * kGiB);
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || total_b == 0) return (long long)(48.0 * kGiB);
+    const double avail = (double)free_b + (double)c->batch_bytes;
+    const double budget = std::min(0.5 * (double)total_b, 0.75 * avail);
+    return (long long)std::max(budget, 4.0 * kGiB);
 }
 
 long long bytes_per_path(const sdd_ctx* c, int max_depth) {
@@ -514,6 +529,7 @@ sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
     const long long cnt_len = (long long)(2 * max_depth + 1) * (c->S + 1) * c->G * kCntStride;
     if (n <= c->ncap && max_depth <= c->dcap) return SDD_OK;
     free_batch(c);
+    const long long bytes0 = c->device_bytes;
     sdd_status st;
     const long long qn = (long long)c->G * n;
 #define ALLOC(ptr, cnt)                            \
@@ -550,6 +566,7 @@ sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
     c->counts_len = cnt_len;
     c->ncap = n;
     c->dcap = max_depth;
+    c->batch_bytes = c->device_bytes - bytes0;
     return SDD_OK;
 }
 
@@ -1325,8 +1342,9 @@ long long plan_batches(sdd_ctx* c, std::vector<Job>& jobs, long long& total_pad)
         total_pad += (j.total + kShadeBlock - 1) / kShadeBlock * kShadeBlock;
     }
     const bool nrc = (any_flags & SDD_TRACE_NRC) != 0;
+    if (c->call_budget <= 0) c->call_budget = mem_budget_bytes(c);
     long long nb = c->tune_batch > 0 ? c->tune_batch
-                                     : mem_budget_bytes() / (bytes_per_path(c, D) + (nrc ? 32 + 4LL * c->nlp : 0));
+                                     : c->call_budget / (bytes_per_path(c, D) + (nrc ? 32 + 4LL * c->nlp : 0));
     nb = std::min<long long>(nb, kMaxBatch);
     nb = std::max<long long>(kShadeBlock, nb / kShadeBlock * kShadeBlock);
     return std::min(nb, total_pad);
@@ -1714,6 +1732,7 @@ sdd_status trace_call(sdd_ctx* c, int n, const sdd_trace_desc* descs) {
         sdd_status st = render_for(c, &descs[i], jobs[i].rd);
         if (st != SDD_OK) return st;
     }
+    c->call_budget = mem_budget_bytes(c);  // once per call: plan_batches also runs under graph capture
     if (!graph) return trace_jobs(c, jobs);
     return trace_graph(c, n, descs, jobs);
 }
@@ -1891,6 +1910,7 @@ sdd_status search_tuning(sdd_ctx* c, int n, const sdd_trace_desc* descs, int rep
         for (int i = 0; i < n; ++i) jobs[i].total = (long long)descs[i].W * descs[i].H * descs[i].spp;
         const long long keep = c->tune_batch;
         c->tune_batch = 0;
+        c->call_budget = mem_budget_bytes(c);
         const long long nb_auto = plan_batches(c, jobs, total_pad);
         c->tune_batch = keep;
         for (int div : {2, 4}) {
