@@ -125,7 +125,7 @@ typedef struct sdd_scene_desc {
  * paper's sub-domains, Sec. 5); every triangle is referenced in each cell
  * its padded bounding box overlaps, and each cell gets its own binned-SAH
  * BVH over its references.  nx = ny = nz = 1 is the undecomposed special case.
- *   leaf_max  triangles per leaf (1..8, 0 = default 4)
+ *   leaf_max  triangles per leaf (1..8, 0 = default 3)
  *   sah_bins  SAH bins (2..64, 0 = default 16)
  */
 typedef struct sdd_bvh_desc {

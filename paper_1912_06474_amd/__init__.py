@@ -268,7 +268,7 @@ class Tracer:
         self._check(lib().sdd_load_scene(self.h, C.byref(sa.desc)))
         self.n_lambda = sa.n_lambda
 
-    def build_bvh(self, nx=1, ny=1, nz=1, leaf_max=4, sah_bins=16, device=False):
+    def build_bvh(self, nx=1, ny=1, nz=1, leaf_max=3, sah_bins=16, device=False):
         """Subdomain grid and per-cell BVHs: host binned SAH, or with device=True a
         linear BVH per cell built on the GPU."""
         self._check(lib().sdd_build_bvh(self.h, C.byref(BvhDesc(nx, ny, nz, leaf_max, sah_bins, int(bool(device))))))

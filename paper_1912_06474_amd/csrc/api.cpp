@@ -1069,7 +1069,7 @@ sdd_status sdd_build_bvh(sdd_ctx* c, const sdd_bvh_desc* d) {
     if (!c->has_scene) return fail(c, SDD_ERR_STATE, "sdd_build_bvh before sdd_load_scene");
     if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0) return fail(c, SDD_ERR_INVALID_ARG, "grid dims must be > 0");
     if ((long long)d->nx * d->ny * d->nz > SDD_MAX_CELLS) return fail(c, SDD_ERR_INVALID_ARG, "too many cells");
-    const int leaf = d->leaf_max == 0 ? 4 : d->leaf_max;
+    const int leaf = d->leaf_max == 0 ? 3 : d->leaf_max;  // 3 measured fastest on the 4-wide tree
     const int bins = d->sah_bins == 0 ? 16 : d->sah_bins;
     if (leaf < 1 || leaf > 8) return fail(c, SDD_ERR_INVALID_ARG, "leaf_max out of range");
     if (bins < 2 || bins > 64) return fail(c, SDD_ERR_INVALID_ARG, "sah_bins out of range");
