@@ -127,3 +127,32 @@ def test_autotune_search_cache_and_result(tracer, tmp_path):
         tracer.autotune(renders, D, reps=1)
     tracer.reset_render(5)
     tracer.set_tuning()
+
+
+def test_autotune_refusals(tracer):
+    """Cache renders (the search's calls would train the cache), hit logs and a
+    repetition count of 0 are refused before any work."""
+    import ctypes as C
+    import paper_1912_06474_amd as m
+    sc = sg.tiny_room(0, 16)
+    tracer.load_scene(sc)
+    tracer.build_bvh(1, 1, 1)
+    W, H, D = 32, 32, 4
+    arr = tracer._batch_descs([dict(camera=sc["camera"], W=W, H=H, spp=1, render_id=9)], D)
+    t, ms, fc = m.Tuning(), C.c_double(0.0), C.c_int32(0)
+
+    def call(reps=1):
+        return m.lib().sdd_autotune(tracer.h, 1, arr, reps, None, C.byref(t), C.byref(ms), C.byref(fc))
+
+    arr[0].flags |= m.TRACE_NRC
+    assert call() == -6  # SDD_ERR_UNSUPPORTED
+    arr[0].flags &= ~m.TRACE_NRC
+    hl = tracer.new_log(W, H, 1, D)
+    arr[0].hit_log = hl.data_ptr()
+    assert call() == -1  # SDD_ERR_INVALID_ARG
+    arr[0].hit_log = None
+    assert call(reps=0) == -1
+    assert call() == 0  # and a valid search still runs
+    with pytest.raises(m.SddError):
+        tracer.resolve_image(9, W, H)  # its samples were discarded
+    tracer.set_tuning()

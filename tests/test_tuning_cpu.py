@@ -66,3 +66,21 @@ def test_store_rejects_bad_input(tmp_path):
     with pytest.raises(m.SddError):
         m.tune_cache_store(tmp_path / "no_such_dir" / "t.txt", "k", ms=1.0)
     assert not f.exists()
+
+
+def test_null_context_and_arguments():
+    """The context entry points refuse a null context or null outputs without a device."""
+    import ctypes as C
+    INVALID = -1  # SDD_ERR_INVALID_ARG
+    L = m.lib()
+    t = m.Tuning()
+    assert L.sdd_set_tuning(None, C.byref(t)) == INVALID
+    assert L.sdd_get_tuning(None, C.byref(t)) == INVALID
+    buf = C.create_string_buffer(64)
+    assert L.sdd_tune_key(None, 1, None, buf, 64) == INVALID
+    ms, fc = C.c_double(0.0), C.c_int32(0)
+    assert L.sdd_autotune(None, 1, None, 1, None, C.byref(t), C.byref(ms), C.byref(fc)) == INVALID
+    found = C.c_int32(0)
+    assert L.sdd_tune_cache_lookup(None, b"k", C.byref(t), None, C.byref(found)) == INVALID
+    assert L.sdd_tune_cache_store(b"/tmp/x", b"k", None, 1.0) == INVALID
+    assert L.sdd_validate_tuning(None, None, 0) == INVALID
