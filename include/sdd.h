@@ -267,8 +267,8 @@ sdd_status sdd_trace_batch(sdd_ctx *ctx, int32_t n, const sdd_trace_desc *descs)
  *                subdomain queue; 0 = as many as the memory budget holds
  *                (SDD_MEM_BUDGET_GB if set, else half the device's memory,
  *                at most 3/4 of what is free plus what the context's batch
- *                holds, at least 4 GiB), else a multiple of 256 in
- *                [256, 2^24]; a call with more paths runs several passes
+ *                holds, at least 4 GiB), else a multiple of 512 in
+ *                [512, 2^24]; a call with more paths runs several passes
  *   trace_grid   traversal workgroups per sweep launch; 0 = all that stay
  *                resident on the device, else a multiple of 8 (one share per
  *                XCD) up to that resident maximum

@@ -215,7 +215,7 @@ const char* tuning_problem(const sdd_tuning* t) {
     if (!t) return "null tuning";
     if (t->batch_paths != 0 &&
         (t->batch_paths < kShadeBlock || t->batch_paths > kMaxBatch || t->batch_paths % kShadeBlock != 0))
-        return "batch_paths must be 0 or a multiple of 256 in [256, 2^24]";
+        return "batch_paths must be 0 or a multiple of 512 in [512, 2^24]";
     if (t->trace_grid < 0 || t->trace_grid % kXcd != 0) return "trace_grid must be 0 or a positive multiple of 8";
     if (t->dir_bins != 0 && t->dir_bins != 1 && t->dir_bins != kExtBins) return "dir_bins must be 0, 1 or 4";
     return nullptr;

@@ -64,7 +64,7 @@ constexpr int kChunk = 64;        // rays per scheduling chunk (one wave)
 constexpr int kXcd = 8;           // XCDs of an MI355X; workgroup i runs on XCD i % 8
 constexpr int kMaxGlass = 4;      // pane crossings recorded per shadow segment
 constexpr int kMaxCells = 512;
-constexpr int kShadeBlock = 256;
+constexpr int kShadeBlock = 512;
 
 constexpr int kMaxBatch = 1 << 24;  // paths per batch (32-bit path arithmetic in the kernels)
 

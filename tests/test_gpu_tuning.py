@@ -31,7 +31,7 @@ def _render(tracer, sc, W, H, spp, D, graph=False, frames=1):
     return out
 
 
-SETTINGS = [dict(batch_paths=4096), dict(batch_paths=1280), dict(trace_grid=8), dict(trace_grid=24),
+SETTINGS = [dict(batch_paths=4096), dict(batch_paths=1536), dict(trace_grid=8), dict(trace_grid=24),
             dict(dir_bins=1), dict(batch_paths=2048, trace_grid=16, dir_bins=1), dict(dir_bins=4)]
 
 
@@ -55,7 +55,7 @@ def test_settings_leave_images_bit_identical(tracer, grid):
         img = _render(tracer, sc, W, H, spp, D)
         st = tracer.stats()
         if "batch_paths" in t:
-            padded = -(-W * H * spp // 256) * 256
+            padded = -(-W * H * spp // 512) * 512
             assert st["batches"] == -(-padded // t["batch_paths"])
             assert st["paths_per_batch"] == t["batch_paths"]
         for u, v in zip(base, img):

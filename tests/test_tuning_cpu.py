@@ -6,7 +6,7 @@ import pytest
 import paper_1912_06474_amd as m
 
 
-@pytest.mark.parametrize("t", [dict(), dict(batch_paths=256), dict(batch_paths=1 << 24), dict(trace_grid=8),
+@pytest.mark.parametrize("t", [dict(), dict(batch_paths=512), dict(batch_paths=1 << 24), dict(trace_grid=8),
                                dict(trace_grid=4096), dict(dir_bins=1), dict(dir_bins=4),
                                dict(batch_paths=1 << 20, trace_grid=512, dir_bins=1)])
 def test_valid_tunings(t):
@@ -14,9 +14,9 @@ def test_valid_tunings(t):
     assert ok and msg == ""
 
 
-@pytest.mark.parametrize("t,word", [(dict(batch_paths=255), "batch_paths"), (dict(batch_paths=300), "batch_paths"),
-                                    (dict(batch_paths=(1 << 24) + 256), "batch_paths"),
-                                    (dict(batch_paths=-256), "batch_paths"), (dict(trace_grid=-8), "trace_grid"),
+@pytest.mark.parametrize("t,word", [(dict(batch_paths=511), "batch_paths"), (dict(batch_paths=768), "batch_paths"),
+                                    (dict(batch_paths=(1 << 24) + 512), "batch_paths"),
+                                    (dict(batch_paths=-512), "batch_paths"), (dict(trace_grid=-8), "trace_grid"),
                                     (dict(trace_grid=12), "trace_grid"), (dict(dir_bins=2), "dir_bins"),
                                     (dict(dir_bins=8), "dir_bins"), (dict(dir_bins=-1), "dir_bins")])
 def test_malformed_tunings(t, word):
@@ -45,7 +45,7 @@ def test_results_file_roundtrip(tmp_path):
 def test_damaged_lines_are_skipped(tmp_path):
     f = tmp_path / "tune.txt"
     f.write_text("k\t4096 64 1 1.0\n"        # good
-                 "k\t100 64 1 0.5\n"         # batch not a multiple of 256
+                 "k\t100 64 1 0.5\n"         # batch not a multiple of 512
                  "k\t4096 12 1 0.5\n"        # grid not a multiple of 8
                  "k\t4096 64 3 0.5\n"        # bins not 0, 1, 4
                  "k\tgarbage\n"
