@@ -845,9 +845,10 @@ __device__ __forceinline__ float4 f4scale(float4 a, float s) { return make_float
 
 template <bool COATED>
 __global__ __launch_bounds__(256) void k_spectral(SpectralParams P) {
-    // records replayed per block: the coated pane code is too large to
-    // unroll four times, so coated scenes go one vertex at a time
-    constexpr int kVBlock = COATED ? 1 : 4;
+    // records replayed per block: two (90 VGPRs, 5 waves per SIMD) hide the
+    // loads' latency better than four (128 VGPRs, 4 waves); the coated pane
+    // code is too large to unroll, so coated scenes go one vertex at a time
+    constexpr int kVBlock = COATED ? 1 : 2;
     __shared__ float4 s_pane[kLdsPane];
     const int n_pane = P.n_glass * P.nlp;
     const bool pane_lds = n_pane <= kLdsPane;
