@@ -833,7 +833,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_route(RouteParams P) {
 //   emission:  beta Le                       (emitters, diffuse emitters)
 //   shadow ray: beta rho Le_light g T_panes  (after the Lambert factor rho)
 // Glass vertices multiply beta by R/P_R or T/(1-P_R) (Eq. 1, Sec. 6 slab).
-// Vertices are replayed in predicated blocks of 4 so that all their records
+// Vertices are replayed in predicated blocks of 2 so that all their records
 // and table values are loaded before the (sequential) arithmetic (one at a
 // time in scenes with coated panes, whose glass code is too large to unroll).
 
