@@ -583,14 +583,17 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
     float te = 0.0f, ts = 0.0f, r_sh = 0.0f;
     int prim = -1;
     if (valid) {
+        // the hit and the FP64 ray are loaded with the flags, before the
+        // branches that need them, so their latencies overlap
         uint32_t fl = P.flags[pid];
+        const float2 h = P.hit[pid];
+        const D4 ro = P.ray_o[pid], rd = P.ray_d[pid];
         if (fl & kAlive) {
             const uint32_t q = (uint32_t)(P.pb + lpid);
             const uint32_t qs = fdiv(q, P.fwh);
             const int s0 = P.s0p ? *P.s0p : P.s0;
             const int s = s0 + P.sb + (int)qs;
             const int p = (int)(q - qs * (uint32_t)P.WH);
-            const float2 h = P.hit[pid];
             prim = __float_as_int(h.y);
             if (P.hit_log) P.hit_log[((long long)p * P.spp_call + (s - s0)) * P.max_depth + P.depth - 1] = prim;
             const bool last_depth = P.depth == P.max_depth;
@@ -599,7 +602,6 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
             if (prim < 0) {
                 fl = 0;  // no sky dome: a miss carries nothing
             } else {
-                const D4 ro = P.ray_o[pid], rd = P.ray_d[pid];
                 const d3 o{ro.x, ro.y, ro.z}, d{rd.x, rd.y, rd.z};
                 const float4 pi = P.prim_info[prim];
                 const int word = __float_as_int(pi.w);
