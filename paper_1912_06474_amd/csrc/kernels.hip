@@ -313,10 +313,11 @@ __device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const 
                 leaf = link;
                 link = pop();
             }
-            // leave for the leaf loop once at most a third of the lanes here
-            // have no parked leaf (measured faster than waiting for all)
+            // leave for the leaf loop once at least half of the lanes here
+            // have parked a leaf (with 4-wide nodes, faster than waiting for
+            // two thirds or three quarters of them, and the same as a third)
             const unsigned long long here = __ballot(true), bare = __ballot(leaf == 0);
-            if (3 * __popcll(bare) <= __popcll(here)) break;
+            if (2 * __popcll(bare) <= __popcll(here)) break;
         }
         if (leaf == 0 && link < 0 && link != kDone) {
             leaf = link;
