@@ -167,6 +167,135 @@ def mlp_forward_bf16(params, X):
     return bf16_round(h) @ bf16_round(params["wo"]) + params["bo"]
 
 
+# ---------------------------------------------------------------------------
+# error bound of the network evaluated with BF16 operands
+# ---------------------------------------------------------------------------
+U_BF16 = 2.0 ** -8    # unit roundoff of bfloat16 (8 significand bits): |bf(x) - x| <= u |x|
+U_FP32 = 2.0 ** -24   # unit roundoff of float32
+
+
+def gamma(m, u=U_FP32):
+    """Higham's gamma_m = m u / (1 - m u): bound on the relative error of a sum
+    of m + 1 terms accumulated with m roundings of unit roundoff u."""
+    return m * u / (1.0 - m * u)
+
+
+def encode_error_bound(x, aabb_lo, aabb_hi, tables, n_sh_abs=4e-6, n_blob_abs=4e-6):
+    """Bound on |X_fp32 - X| for the network input as an FP32 kernel encodes it.
+
+    * position: xn = (x - lo) * (1 / (hi - lo)) in FP32 carries at most three
+      roundings (|d xn| <= 3 * 2^-24 <= 2^-22 after clamping to [0, 1]); the
+      lattice coordinate p = xn N then moves by at most N 2^-21.  The
+      trilinear interpolant is continuous across cells and its derivative
+      along an axis is a difference of two bilinear interpolants, at most
+      2 max|t_l| in magnitude, so a level's features move by at most
+      3 * N 2^-21 * 2 max|t_l|, plus the FP32 sum of 8 weighted corners,
+      gamma_11 max|t_l|;
+    * harmonics and one-blob bins: FP32 evaluation of bounded polynomials and
+      of exp(-d^2 / 2) (derivative at most 0.61), a few ulp of terms below 3:
+      n_sh_abs and n_blob_abs absolute.
+    """
+    n = len(np.asarray(x))
+    E = np.zeros((n, N_IN))
+    F = tables.shape[2]
+    for l in range(L_LEVELS):
+        N = level_resolution(l)
+        tmax = float(np.max(np.abs(tables[l])))
+        E[:, l * F:(l + 1) * F] = 3.0 * N * 2.0 ** -21 * 2.0 * tmax + gamma(11) * tmax
+    E[:, L_LEVELS * F:L_LEVELS * F + N_SH] = n_sh_abs
+    E[:, L_LEVELS * F + N_SH:] = n_blob_abs
+    return E
+
+
+def mlp_bf16_error_bound(params, X, EX, u=U_BF16, lam=6.0):
+    """FP64 output y of the network and a bound B on |y_hat - y| for an
+    evaluation y_hat with BF16 operands in every layer (inputs, activations,
+    weights, the output layer's included), FP32 accumulation and FP32 biases,
+    from an FP32 input X_hat with |X_hat - X| <= EX.
+
+    Error model (probabilistic rounding error analysis, Higham and Mary, SIAM
+    J. Sci. Comput. 2019): every BF16 rounding is bf(v) = v (1 + d), |d| <= u,
+    the d independent with mean zero.  To first order the output error is
+    linear in them,
+      dy = sum over layers k, inputs m:  (dy/da_{k-1,m}) a_{k-1,m} phi_{k,m}
+         + sum over weights (i, m):      (dy/dz_{k,i}) W_k,im a_{k-1,m} theta_{k,im},
+    phi the rounding of layer k's input operand, theta of its weight (layer 5 =
+    the output layer, dy/dz = 1), the sensitivities dy/dz, dy/da signed
+    (backpropagation of 1 through the exact ReLU masks).  By Hoeffding's
+    inequality |dy| <= lam u sqrt(V) with probability at least
+    1 - 2 exp(-lam^2 / 2) (3e-8 for lam = 6), V the sum of the squared
+    coefficients: the layer sums of squares sum_m (dy/da_m a_m)^2 and
+    sum_i (dy/dz_i)^2 sum_m (W_im a_m)^2.  Added in the worst case:
+      * products' second-order term theta phi: u^2 sum |dy/dz| |W| |a|;
+      * FP32 accumulation: gamma_66 (layer 0 in two partial sums) or gamma_65
+        of sum |dy/dz| ((1 + u)^2 |W| |a| + |b|);
+      * the input's encoding error: sum_m |dy/dX_m| EX_m;
+      * ReLU kinks: a unit whose |z| lies within its own error bound e (the
+        same model, carried to the unit through the signed maps between
+        layers) may take the other branch; its activation then differs from
+        the linear model's by |z + dz| <= e - |z|, which moves the output by
+        at most |dy/da| (e - |z|).
+    Returns (y, B, n_kink_units [n], u sqrt(V) [n]); under the model the error
+    has standard deviation at most u sqrt(V / 3) (a rounding error uniform on
+    [-u, u] has variance u^2 / 3)."""
+    X = np.asarray(X, np.float64)
+    n = len(X)
+    Ws = [np.asarray(w, np.float64) for w in params["W"]] + [np.asarray(params["wo"], np.float64)[None, :]]
+    bs = [np.asarray(b, np.float64) for b in params["b"]] + [np.array([float(params["bo"])])]
+    nl = N_LAYERS + 1
+    a, z = [X], []
+    for k in range(nl):
+        zk = a[-1] @ Ws[k].T + bs[k]
+        z.append(zk)
+        a.append(np.maximum(0.0, zk) if k < N_LAYERS else zk)
+    y = z[-1][:, 0]
+    masks = [(zk > 0.0).astype(np.float64) for zk in z[:N_LAYERS]] + [np.ones((n, 1))]
+    # sensitivities: g[k] = dy/dz_k, da[k] = dy/d(input of layer k)
+    g = [None] * nl
+    da = [None] * nl
+    g[nl - 1] = np.ones((n, 1))
+    for k in range(nl - 1, -1, -1):
+        da[k] = g[k] @ Ws[k]
+        if k > 0:
+            g[k - 1] = da[k] * masks[k - 1]
+    # squared coefficients of the roundings, per layer: q[k][i] = sum_m (W_im a_m)^2
+    q = [(a[k] ** 2) @ (Ws[k] ** 2).T for k in range(nl)]
+    V = np.zeros(n)
+    worst = np.zeros(n)
+    for k in range(nl):
+        V += np.sum((da[k] * a[k]) ** 2, axis=1) + np.sum(g[k] ** 2 * q[k], axis=1)
+        S = np.abs(a[k]) @ np.abs(Ws[k]).T
+        m = 66 if k == 0 else 65
+        worst += np.sum(np.abs(g[k]) * (u * u * S + gamma(m) * ((1.0 + u) ** 2 * S + np.abs(bs[k]))), axis=1)
+    EXa = np.abs(np.asarray(EX, np.float64) * np.ones_like(X))
+    worst += np.sum(np.abs(da[0]) * EXa, axis=1)
+    B = lam * u * np.sqrt(V) + worst
+    # per-unit bounds of the hidden layers, through the signed maps P[j] (layer j -> current)
+    nk = np.zeros(n, np.int64)
+    P = []
+    Vu = []
+    for k in range(N_LAYERS):
+        if k > 0:
+            P = [np.matmul(Ws[k][None], masks[k - 1][:, :, None] * Pj) for Pj in P]
+        P.append(np.broadcast_to(np.eye(N_HID), (n, N_HID, N_HID)))
+        var = np.zeros((n, N_HID))
+        wst = np.zeros((n, N_HID))
+        for j, Pj in enumerate(P):
+            PW = np.matmul(Pj, np.broadcast_to(Ws[j], (n,) + Ws[j].shape))
+            var += np.einsum("nim,nm->ni", PW ** 2, a[j] ** 2) + np.einsum("nij,nj->ni", Pj ** 2, q[j])
+            S = np.abs(a[j]) @ np.abs(Ws[j]).T
+            loc = u * u * S + gamma(66 if j == 0 else 65) * ((1.0 + u) ** 2 * S + np.abs(bs[j]))
+            if j == 0:
+                loc = loc + EXa @ np.abs(Ws[0]).T
+            wst += np.einsum("nij,nj->ni", np.abs(Pj), loc)
+        e = lam * u * np.sqrt(var) + wst
+        over = e - np.abs(z[k])          # how far the error bound reaches past the kink
+        near = over > 0.0
+        B = B + np.sum(np.where(near, np.abs(da[k + 1]) * over, 0.0), axis=1)
+        nk += near.sum(axis=1)
+    return y, B, nk, u * np.sqrt(V)
+
+
 def rel_l2_loss(y, t, eps=0.01):
     """Mean of (y - t)^2 / (sg(y)^2 + eps) and its gradient with respect to y."""
     den = y * y + eps

@@ -585,6 +585,51 @@ def point_light_plane(n_lambda: int = 16, seed: int = 0, pos=(2.0, 1.5, 1.5)):
     return sc
 
 
+PANE_A_CENTRE = (1.0, 1.5, 2.7)
+PANE_A_TILT_DEG = 35.0
+PANE_B_Z = 3.35
+WALL_LIGHT_POS = (1.5, 1.5, 3.6)
+
+
+def point_light_panes(n_lambda: int = 16, seed: int = 0, coating_state=None):
+    """A diffuse wall x = 0 lit by a point light (Eq. 3) that it sees only
+    through two 4 mm panes, and a camera that sees the wall but no pane.
+
+    * wall: x = 0, y in [-1, 4], z in [-1, 3.5], 5 x 5 quads, reflectance
+      rho(lambda), facing +x;
+    * pane A: 2 x 2 m, centred at PANE_A_CENTRE, tilted PANE_A_TILT_DEG about
+      the y axis (geometric normal -(sin a, 0, cos a), facing down), so a
+      shadow ray meets it at a cosine unlike its cosine at the wall;
+    * pane B: horizontal, z = PANE_B_Z, x and y in [0.5, 2.5], geometric
+      normal +z (facing up);
+    * point light at WALL_LIGHT_POS, above both panes;
+    * camera: eye (3, 1.5, 1.25) looking along -x at the wall, 30 degrees,
+      whose rays stay below z = 2.05 on their way to the wall.
+
+    Every shadow segment from the visible wall to the light crosses pane A,
+    then pane B, and nothing else.  With ``coating_state`` both panes carry
+    the electrochromic coating on the face their geometric normal points out of.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lam, w = lambda_grid(n_lambda)
+    mats = _Materials(len(lam))
+    wall = mats.add(DIFFUSE, rho=gaussian_reflectance(rng, lam))
+    pane = _glass_material(mats, lam, coating_state=coating_state)
+    point = mats.add(EMITTER, le=planck_shape(lam, scale=5.0))  # the point light's intensity I(lambda)
+    mesh = _Mesh()
+    _rect(mesh, (0, -1, -1), (0, 5, 0), (0, 0, 4.5), 5, 5, wall)
+    a = math.radians(PANE_A_TILT_DEG)
+    ca = np.asarray(PANE_A_CENTRE)
+    du = np.array([0.0, 2.0, 0.0])
+    dv = np.array([2.0 * math.cos(a), 0.0, -2.0 * math.sin(a)])
+    _rect(mesh, ca - 0.5 * du - 0.5 * dv, du, dv, 1, 1, pane)   # geometric normal du x dv: -(sin a, 0, cos a)
+    _rect(mesh, (0.5, 0.5, PANE_B_Z), (2, 0, 0), (0, 2, 0), 1, 1, pane)  # normal +z
+    cam = dict(eye=(3.0, 1.5, 1.25), target=(0.0, 1.5, 1.25), fov_deg=30.0, ortho=False, ortho_half_h=1.0)
+    return _finish(mesh, mats, lam, w, light_type=LIGHT_POINT, light_mat=point, name="point_light_panes",
+                   seed=seed, light_p0=WALL_LIGHT_POS, light_e1=(0.0, 0.0, 0.0), light_e2=(0.0, 0.0, 0.0),
+                   camera=cam)
+
+
 def area_light_plane(n_lambda: int = 16, seed: int = 0):
     """Floor plane under a 1 x 0.8 m parallelogram emitter at z = 1.2 facing -z."""
     rng = np.random.Generator(np.random.PCG64(seed))

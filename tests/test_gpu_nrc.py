@@ -14,20 +14,18 @@ coordinates exact in FP32) the FP32 path must agree within 1e-5.  Gradients
 whose ReLU decisions are clear: a row with a hidden pre-activation within
 1e-5 of the magnitude of its summed terms could take the other branch in FP32
 (a different but equally valid derivative), so such rows (a few per mille)
-are left out of the batch on both sides.  The BF16 path is compared with the reference that rounds the same
-operands to BF16: a row agrees to FP32 accumulation error unless one of its
-~400 rounding decisions falls the other way because the kernel's operand is
-an FP32 value and the reference's an FP64 one (odds ~1e-7 / 2^-8 per
-decision); such a row moves by about one BF16 ulp (2^-8) of one operand's
-contribution.  The odds are largest for the fine hash levels: the lattice
-coordinate x N (N up to 2048) carries the FP32 rounding of the normalised
-position amplified N times (~1e-4), so on general positions a good fraction
-of rows carries a flip: half the rows agree within 1e-4 and every row within
-2e-2.  On a power-of-two box with dyadic positions the lattice coordinates are
-exact in FP32 and flips become rare: on a network whose hidden layers are
-permutations (their sums are exact, so only the 64 input features are
-decisions in doubt) at least 98% of rows agree within 1e-5, which pins the
-operand layout exactly."""
+are left out of the batch on both sides.
+
+The BF16 path is judged by the FP64 forward and a bound derived from the
+unit roundoff u = 2^-8 and the layer sums (oracle.nrc.mlp_bf16_error_bound):
+to first order the output error is a sum of independent roundings of every
+operand, each at most u times its term, carried to the output by the
+network's signed sensitivities; with probability at least 1 - 3e-8 per row it
+stays within 6 u sqrt(sum of the squared terms), to which the FP32
+accumulation, the second-order products, the FP32 input encoding and the ReLU
+decisions within their units' own bounds are added in the worst case.  Every
+row must lie within it.  The BF16-operand emulation (oracle.nrc.
+mlp_forward_bf16) is printed as a diagnostic only."""
 import numpy as np
 import pytest
 
@@ -121,6 +119,22 @@ def _bf16_ok(y, yb):
     return float(np.mean(e <= 1e-4)), float(e.max())
 
 
+def _bf16_judge(y, params, tables, x, w, lam, lo=LO, hi=HI, tag=""):
+    """Every row within the derived bound of the FP64 forward; the BF16-operand
+    emulation is a diagnostic."""
+    p, t = _f64(params, tables)
+    X = ora.encode(x, w, lam, lo, hi, t)
+    yo, B, nk, _ = ora.mlp_bf16_error_bound(p, X, ora.encode_error_bound(x, lo, hi, t))
+    err = np.abs(np.asarray(y, np.float64) - yo)
+    frac, err_b = _bf16_ok(y, ora.mlp_forward_bf16(p, X))
+    scale = np.abs(yo) + np.sqrt(np.mean(yo ** 2))
+    print(f"[nrc] bf16 {tag} n={len(yo)}: max err/bound {float(np.max(err / B)):.3f}, median bound "
+          f"{float(np.median(B / scale)):.3e} of |y| + rms; (diagnostic: {frac:.4f} of rows within 1e-4 of the "
+          f"BF16-operand emulation, max {err_b:.3e}; kink units per row <= {int(nk.max())})", flush=True)
+    bad = np.flatnonzero(err > B)
+    assert len(bad) == 0, [(int(i), float(err[i]), float(B[i])) for i in bad[:8]]
+
+
 @pytest.mark.parametrize("n", [1, 8, 257, 3001])
 def test_fp32_forward_matches_oracle(tracer, n):
     params, tables = _net(1, 14)  # levels 0-1 indexed directly, 2-15 hashed
@@ -147,21 +161,19 @@ def test_fp32_forward_exact_lattice(tracer, n):
 
 
 @pytest.mark.parametrize("n", [5, 64, 1000, 4097])
-def test_bf16_forward_matches_bf16_oracle(tracer, n):
+def test_bf16_forward_within_derived_bound(tracer, n):
     params, tables = _net(2, 14)
     tracer.nrc_init(params, tables, LO, HI)
     x, w, lam = _rows(n, 12)
     y = tracer.nrc_infer(x, w, lam, "bf16").cpu().numpy()
-    frac, err_b = _bf16_ok(y, _oracle_y(params, tables, x, w, lam, bf16=True))
-    err_f = _close(y, _oracle_y(params, tables, x, w, lam))
-    print(f"[nrc] bf16 forward n={n}: vs BF16-operand reference: {frac:.4f} of rows within 1e-4, max {err_b:.3e}; "
-          f"vs FP64 max {err_f:.3e}", flush=True)
-    assert frac >= 0.5 and err_b <= 2e-2
-    assert err_f <= 5e-2
+    _bf16_judge(y, params, tables, x, w, lam, tag="general rows")
 
 
 @pytest.mark.parametrize("n", [64, 3001])
-def test_bf16_layout_exact_on_permutation_layers(tracer, n):
+def test_bf16_layout_on_permutation_layers(tracer, n):
+    """Hidden layers that permute their inputs (exact in BF16): the output then
+    depends on which slot each of the 64 input features reaches, so a layout
+    slip leaves the bound on most rows."""
     rng = np.random.default_rng(21)
     params, tables = _net(8, 14)
     params["W"] = [(rng.integers(-8, 9, (64, 64)) / 16.0).astype(np.float32)] + \
@@ -170,12 +182,7 @@ def test_bf16_layout_exact_on_permutation_layers(tracer, n):
     tracer.nrc_init(params, tables, *BOX2)
     x, w, lam = _dyadic_rows(n, 22)
     y = tracer.nrc_infer(x, w, lam, "bf16").cpu().numpy()
-    p, tb = _f64(params, tables)
-    yb = ora.mlp_forward_bf16(p, ora.encode(x, w, lam, BOX2[0], BOX2[1], tb))
-    e = _rel(y, yb)
-    frac = float(np.mean(e <= 1e-5))
-    print(f"[nrc] bf16 permutation layers n={n}: {frac:.4f} of rows within 1e-5, max {e.max():.3e}", flush=True)
-    assert frac >= 0.98 and e.max() <= 2e-2
+    _bf16_judge(y, params, tables, x, w, lam, *BOX2, tag="permutation layers")
 
 
 def test_forward_full_table_sampled(tracer):
@@ -189,12 +196,10 @@ def test_forward_full_table_sampled(tracer):
     idx = np.random.default_rng(14).choice(len(lam), 2000, replace=False)
     idx[:8] = np.arange(8)
     yo = _oracle_y(params, tables, x[idx], w[idx], lam[idx])
-    yb = _oracle_y(params, tables, x[idx], w[idx], lam[idx], bf16=True)
     e32 = _close(y32[idx], yo)
-    frac, e16 = _bf16_ok(y16[idx], yb)
-    print(f"[nrc] 2^20 rows, T=2^19: fp32 max {e32:.3e}; bf16 {frac:.4f} within 1e-4, max {e16:.3e}", flush=True)
+    print(f"[nrc] 2^20 rows, T=2^19: fp32 max {e32:.3e}", flush=True)
     assert e32 <= 3e-4
-    assert frac >= 0.5 and e16 <= 2e-2
+    _bf16_judge(y16[idx], params, tables, x[idx], w[idx], lam[idx], tag="2^20 rows, T=2^19, sampled")
     assert np.all(np.isfinite(y32)) and np.all(np.isfinite(y16))
 
 

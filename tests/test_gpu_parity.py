@@ -169,6 +169,19 @@ def test_fixture_parity(tracer, which):
     assert_parity(g, o, excluded_max=1)
 
 
+@pytest.mark.parametrize("coating", [None, 0.7])
+def test_point_light_through_panes_parity(tracer, coating):
+    """Light samples through two panes (one tilted), plain and coated: the
+    oracle's result here is pinned to Eq. 3 times the panes' transmittances."""
+    sc = sg.point_light_panes(16, seed=3, coating_state=coating)
+    W = H = 32
+    spp, D = 2, 3
+    g = gpu_render(tracer, sc, W, H, spp, D, grid=(2, 2, 2))
+    o = ora.render(sc, W, H, spp, D, logs=True)
+    assert (g["shadow_log"][:, :, 0] == 1).all()
+    assert_parity(g, o, excluded_max=1)
+
+
 def test_sample_split_and_batching_are_bitwise_identical(tracer):
     sc = sg.tiny_room()
     W = H = 32

@@ -191,3 +191,81 @@ def test_bf16_forward_is_exact_on_bf16_operands():
     for k in range(2, 5):
         h = np.maximum(0.0, 0.0 * h + params["b"][k])
     assert np.allclose(nrc.mlp_forward_bf16(params, X), h @ params["wo"] + params["bo"], rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the BF16 error bound the GPU network is judged by (FP64 forward +- bound)
+# ---------------------------------------------------------------------------
+LO3, HI3 = (0.0, 0.0, 0.0), (4.0, 3.0, 2.5)
+
+
+def _test_net(seed, log2=12, table_scale=0.5):
+    params, tables = sg.nrc_params(seed, table_size=1 << log2)
+    rng = np.random.default_rng(seed + 1000)
+    tables = rng.uniform(-table_scale, table_scale, tables.shape)
+    p = {"W": [np.asarray(w, np.float64) for w in params["W"]],
+         "b": [rng.uniform(-0.1, 0.1, 64) for _ in range(5)],
+         "wo": np.asarray(params["wo"], np.float64), "bo": 0.05}
+    return p, tables
+
+
+def _torch_bf16_forward(p, X):
+    """An evaluation independent of this module: torch rounds every operand to
+    bfloat16 and multiplies in float32 (its own accumulation order)."""
+    import torch
+
+    def bf(a):
+        return torch.tensor(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float32)
+
+    h = torch.tensor(np.asarray(X, np.float32))
+    for k in range(5):
+        h = torch.relu(bf(h) @ bf(p["W"][k]).T + torch.tensor(np.asarray(p["b"][k], np.float32)))
+    return (bf(h) @ bf(p["wo"]) + np.float32(p["bo"])).double().numpy()
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_bf16_bound_holds_and_is_informative(seed):
+    p, tables = _test_net(seed)
+    x, w, lam, _ = sg.nrc_rows(2000, seed)
+    X = nrc.encode(x, w, lam, LO3, HI3, tables)
+    X32 = X.astype(np.float32).astype(np.float64)          # the kernel's input is FP32
+    y, B, nk, s = nrc.mlp_bf16_error_bound(p, X, np.abs(X32 - X))
+    scale = np.abs(y) + np.sqrt(np.mean(y ** 2))
+    for name, yb in (("torch", _torch_bf16_forward(p, X32)), ("emulation", nrc.mlp_forward_bf16(p, X32))):
+        err = np.abs(yb - y)
+        assert np.all(err <= B), (name, float(np.max(err / B)))
+        # the error model's scale: uniform roundings of +-u give a standard
+        # deviation of at most u sqrt(V / 3); a wrong u (2x) moves this ratio out
+        r = float(np.sqrt(np.mean((err / (s / np.sqrt(3.0))) ** 2)))
+        assert 0.4 <= r <= 1.2, (name, r)
+        # and the bound is not inflated: the worst row reaches a tenth of it
+        assert float(np.max(err / B)) >= 0.05, name
+    assert float(np.median(B / scale)) <= 0.25
+    assert nk.max() < 64                                   # few ReLU decisions are in doubt
+
+
+def test_bf16_bound_catches_a_wrong_operand():
+    """A layout slip (one input feature fed to the wrong slot) breaks the bound."""
+    p, tables = _test_net(4)
+    x, w, lam, _ = sg.nrc_rows(500, 4)
+    X = nrc.encode(x, w, lam, LO3, HI3, tables)
+    y, B, _, _ = nrc.mlp_bf16_error_bound(p, X, np.zeros_like(X))
+    Xs = X.copy()
+    Xs[:, [3, 40]] = Xs[:, [40, 3]]                         # one pair of slots exchanged
+    assert np.mean(np.abs(_torch_bf16_forward(p, Xs) - y) > B) > 0.1
+    Xs = X.copy()
+    Xs[:, 32:48] = np.roll(Xs[:, 32:48], 4, axis=1)         # a lane group's slots rotated
+    assert np.mean(np.abs(_torch_bf16_forward(p, Xs) - y) > B) > 0.5
+
+
+def test_bf16_bound_encoding_term():
+    """The encoding allowance covers FP32 lattice coordinates of general
+    positions: features recomputed from positions rounded to FP32 relative
+    steps stay within it."""
+    p, tables = _test_net(5)
+    x, w, lam, _ = sg.nrc_rows(400, 5)
+    X = nrc.encode(x, w, lam, LO3, HI3, tables)
+    EX = nrc.encode_error_bound(x, LO3, HI3, tables)
+    xp = np.asarray(x, np.float64) * (1.0 + 3.0 * 2.0 ** -24)
+    Xp = nrc.encode(xp, w, lam, LO3, HI3, tables)
+    assert np.all(np.abs(Xp - X)[:, :32] <= EX[:, :32])
