@@ -205,7 +205,9 @@ typedef struct sdd_stats {
     int32_t n_cells;
     int64_t device_bytes;      /* device memory owned by the context */
     int64_t paths_per_batch;   /* paths per pipeline pass of the last trace call */
-    int32_t overflow;          /* nonzero: a shadow segment crossed more panes than supported */
+    int32_t overflow;          /* bits raised since sdd_reset_stats: 1 a shadow segment crossed
+                                  more glass panes than are tracked (4), 2 a subdomain queue count
+                                  exceeded its capacity (not expected: counts are bounded) */
     int32_t pad_;
     double ms_nrc_query;       /* cache-network launches of SDD_TRACE_NRC renders (SDD_TRACE_TIME_KERNELS;
                                   with BF16 queries the matrix-core kernel alone, its operand gathers
@@ -245,10 +247,16 @@ sdd_status sdd_validate_scene(const sdd_scene_desc *scene, char *msg, int msg_le
  * than SDD_MAX_CELLS cells, or leaf_max / sah_bins out of range. */
 sdd_status sdd_build_bvh(sdd_ctx *ctx, const sdd_bvh_desc *desc);
 
-/* Trace (asynchronously) and accumulate; see sdd_trace_desc.  SDD_ERR_STATE
- * without a BVH; SDD_ERR_INVALID_ARG for W, H, spp, max_depth out of range,
- * a render_id < 0, a changed W/H for an existing render, or a degenerate
- * camera (forward direction parallel to +z or eye == target). */
+/* Trace (asynchronously) and accumulate; see sdd_trace_desc.  This is the
+ * paper's rendering step: inverse ray tracing with a primary ray per pixel, a
+ * shadow ray toward the light at every diffuse vertex and a reflected or
+ * transmitted secondary ray, up to a bounce cap (Sec. 4; Eq. 2 estimated by
+ * Monte-Carlo paths, Eq. 3 for the light sample), glass panes through their
+ * Fresnel terms of n + i k (Eq. 1, Sec. 6), and every ray traced subdomain by
+ * subdomain with its state handed across the interfaces (Sec. 5).
+ * SDD_ERR_STATE without a BVH; SDD_ERR_INVALID_ARG for W, H, spp, max_depth
+ * out of range, a render_id < 0, a changed W/H for an existing render, or a
+ * degenerate camera (forward direction parallel to +z or eye == target). */
 sdd_status sdd_trace_spectral(sdd_ctx *ctx, const sdd_trace_desc *desc);
 
 /* Several renders in one pass of the pipeline (n in 1..SDD_MAX_RENDERS, all
@@ -330,13 +338,16 @@ sdd_status sdd_tune_key(sdd_ctx *ctx, int32_t n, const sdd_trace_desc *descs, ch
 sdd_status sdd_tune_cache_lookup(const char *path, const char *key, sdd_tuning *out, double *ms, int32_t *found);
 sdd_status sdd_tune_cache_store(const char *path, const char *key, const sdd_tuning *t, double ms);
 
-/* Per-pixel mean radiance of render_id over all samples traced so far, in
- * FP64: spectral_out [H][W][n_lambda] and xyz_out [H][W][3] (XYZ =
- * sum_l lambda_w[l] cmf[l][:] L[l]).  Either may be NULL.  Pointers are
- * device pointers if out_is_device, else host pointers.  Synchronises the
- * stream.  SDD_ERR_STATE for an unknown render or one with no samples;
- * SDD_ERR_OVERFLOW if a shadow segment crossed more glass panes than the
- * library tracks (the image is then not trustworthy). */
+/* Gathering of the results (Sec. 5): per-pixel mean radiance of render_id
+ * over all samples traced so far, in FP64: spectral_out [H][W][n_lambda] and
+ * xyz_out [H][W][3] (XYZ = sum_l lambda_w[l] cmf[l][:] L[l]).  Either may be
+ * NULL.  Pointers are device pointers if out_is_device, else host pointers;
+ * the caller owns them.  Synchronises the stream.  SDD_ERR_STATE for an
+ * unknown render or one with no samples; SDD_ERR_OVERFLOW (the outputs are
+ * written but not trustworthy) if a call that traced this render saw a shadow
+ * segment cross more glass panes than the library tracks, or a queue count
+ * above its capacity; sdd_last_error names which.  Other renders of the
+ * context are not affected. */
 sdd_status sdd_resolve_image(sdd_ctx *ctx, int32_t render_id, double *spectral_out, double *xyz_out,
                              int32_t out_is_device);
 

@@ -42,6 +42,7 @@ namespace {
 struct Render {
     int W = 0, H = 0;
     float* acc = nullptr;  // [nl][W*H] FP32
+    int* ovf = nullptr;    // overflow bits (kOverflow*) of every call that traced this render
     long long spp_done = 0;
 };
 
@@ -120,7 +121,8 @@ struct sdd_ctx {
     long long counts_len = 0;
     long long batch_bytes = 0;  // device bytes of the path batch (ensure_batch)
     long long call_budget = 0;  // memory budget of the current call (set before any capture)
-    int* d_overflow = nullptr;
+    int* d_overflow = nullptr;   // overflow bits of the current trace call (cleared at its start)
+    int* d_ovf_stats = nullptr;  // overflow bits since sdd_reset_stats
     int* d_ktot = nullptr;  // routing key totals [2][kMaxCells * kExtBins]
     int* d_gstack = nullptr;  // traversal stack spill: (kStack - kLdsStack) ints per trace thread
     unsigned long long* d_stats = nullptr;
@@ -384,7 +386,10 @@ void free_nrc(sdd_ctx* c) {
 
 void free_renders(sdd_ctx* c) {
     ++c->gen;
-    for (auto& kv : c->renders) dfree(c, kv.second.acc);
+    for (auto& kv : c->renders) {
+        dfree(c, kv.second.acc);
+        dfree(c, kv.second.ovf);
+    }
     c->renders.clear();
 }
 
@@ -685,13 +690,15 @@ sdd_status sdd_create(int hip_device, void* hip_stream, sdd_ctx** out) {
     // sets the grid for its subdomain count, never above this
     c->trace_grid_max = trace_grid_for(c, 1);
     c->trace_grid = c->trace_grid_max;
-    if (dalloc(c, &c->d_overflow, 1) != SDD_OK || dalloc(c, &c->d_stats, kStatCount) != SDD_OK ||
+    if (dalloc(c, &c->d_overflow, 1) != SDD_OK || dalloc(c, &c->d_ovf_stats, 1) != SDD_OK ||
+        dalloc(c, &c->d_stats, kStatCount) != SDD_OK ||
         dalloc(c, &c->d_ktot, 2 * (size_t)kMaxCells * kExtBins) != SDD_OK ||
         dalloc(c, &c->d_gstack, (size_t)c->trace_grid_max * kTraceBlock * (kStack - kLdsStack)) != SDD_OK) {
         sdd_destroy(c);
         return SDD_ERR_OOM;
     }
     if (hipMemsetAsync(c->d_overflow, 0, sizeof(int), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_ovf_stats, 0, sizeof(int), c->stream) != hipSuccess ||
         hipMemsetAsync(c->d_stats, 0, sizeof(unsigned long long) * kStatCount, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         sdd_destroy(c);
@@ -717,6 +724,7 @@ void sdd_destroy(sdd_ctx* c) {
     free_scene(c);
     free_nrc(c);
     dfree(c, c->d_overflow);
+    dfree(c, c->d_ovf_stats);
     dfree(c, c->d_ktot);
     dfree(c, c->d_gstack);
     dfree(c, c->d_stats);
@@ -1379,6 +1387,10 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
         if ((st = nrc_ensure_render(c, nb, std::max<long long>(1, n_slots), D)) != SDD_OK) return st;
         np = NrcPaths{1, stride, c->nrc_cx, c->nrc_cn, c->nrc_tx, c->nrc_tn};
     }
+    {  // this call's overflow bits start clear; they are folded into its renders at the end
+        Timer tm(c, timing, 3);
+        HIP_TRY(c, launch_fill_i32(c->d_overflow, 1, 0, c->stream));
+    }
     for (const Job& j : jobs) {
         if (j.t->hit_log) {
             Timer tm(c, timing, 3);
@@ -1612,6 +1624,14 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
         }
         ++c->batches;
     }
+    {
+        std::vector<int*> dst;
+        dst.reserve(jobs.size() + 1);
+        dst.push_back(c->d_ovf_stats);
+        for (const Job& j : jobs) dst.push_back(j.rd->ovf);
+        Timer tm(c, timing, 3);
+        HIP_TRY(c, launch_fold_flags(c->d_overflow, dst.data(), (int)dst.size(), c->stream));
+    }
     for (Job& j : jobs) j.rd->spp_done += j.t->spp;
     if (nrc) return nrc_train_after_call(c, n_slots * (D - 1), timing);
     return SDD_OK;
@@ -1630,7 +1650,12 @@ sdd_status render_for(sdd_ctx* c, const sdd_trace_desc* t, Render*& out) {
         ++c->gen;
         sdd_status st = dalloc(c, &rd.acc, n);
         if (st != SDD_OK) return st;
+        if ((st = dalloc(c, &rd.ovf, 1)) != SDD_OK) {
+            dfree(c, rd.acc);
+            return st;
+        }
         HIP_TRY(c, hipMemsetAsync(rd.acc, 0, sizeof(float) * n, c->stream));
+        HIP_TRY(c, launch_fill_i32(rd.ovf, 1, 0, c->stream));
         it = c->renders.emplace(t->render_id, rd).first;
     }
     out = &it->second;
@@ -2072,8 +2097,11 @@ sdd_status sdd_resolve_image(sdd_ctx* c, int32_t render_id, double* spectral_out
     dfree(c, tmp_x);
     if (e != hipSuccess) return hip_fail(c, e, "resolve");
     int ovf = 0;
-    HIP_TRY(c, hipMemcpy(&ovf, c->d_overflow, sizeof(int), hipMemcpyDeviceToHost));
-    if (ovf) return fail(c, SDD_ERR_OVERFLOW, "a shadow segment crossed more glass panes than tracked");
+    HIP_TRY(c, hipMemcpy(&ovf, rd.ovf, sizeof(int), hipMemcpyDeviceToHost));
+    if (ovf & kOverflowPanes)
+        return fail(c, SDD_ERR_OVERFLOW, "a shadow segment crossed more than " + std::to_string(kMaxGlass) +
+                                              " glass panes (only the first are tracked)");
+    if (ovf & kOverflowQueue) return fail(c, SDD_ERR_OVERFLOW, "a subdomain queue count exceeded its capacity");
     return SDD_OK;
 }
 
@@ -2085,6 +2113,7 @@ sdd_status sdd_reset_render(sdd_ctx* c, int32_t render_id) {
     DeviceGuard g(c->device);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     dfree(c, it->second.acc);
+    dfree(c, it->second.ovf);
     c->renders.erase(it);
     return SDD_OK;
 }
@@ -2097,7 +2126,7 @@ sdd_status sdd_get_stats(sdd_ctx* c, sdd_stats* out) {
     unsigned long long s[kStatCount];
     HIP_TRY(c, hipMemcpy(s, c->d_stats, sizeof(s), hipMemcpyDeviceToHost));
     int ovf = 0;
-    HIP_TRY(c, hipMemcpy(&ovf, c->d_overflow, sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(&ovf, c->d_ovf_stats, sizeof(int), hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof(*out));
     out->ext_rays = (int64_t)s[kStatExtRays] + c->cam_rays;
     out->shadow_rays = (int64_t)s[kStatShadowRays];
@@ -2134,6 +2163,7 @@ sdd_status sdd_reset_stats(sdd_ctx* c) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     harvest_events(c);
     HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, sizeof(unsigned long long) * kStatCount, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_ovf_stats, 0, sizeof(int), c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->batches = 0;
     c->cam_rays = 0;

@@ -18,6 +18,8 @@ hipError_t launch_nrc_rows(const NrcRowParams& p, hipStream_t st);
 hipError_t launch_resolve(int WH, int nl, int nlp, double inv_spp, const float* acc, const double* w,
                           const double* cmf, double* spectral, double* xyz, hipStream_t st);
 hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
+// dst[i] |= *src, i < n (stream-ordered; a kernel, so graph capture records no memset)
+hipError_t launch_fold_flags(const int* src, int* const* dst, int n, hipStream_t st);
 hipError_t launch_pane(int n, const float4* pc, const float* c, float2* out, hipStream_t st);
 // q[i] = (glass index, wavelength index, signed cosine bits, 0)
 hipError_t launch_glass(int n, const GlassTable& tab, const int4* q, float2* out, hipStream_t st);

@@ -349,7 +349,7 @@ __device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const 
                             if (n_glass < kMaxGlass)
                                 sh_glass[(size_t)pid * kMaxGlass + n_glass] = make_float2(-dot3(r.d, ng), c.w);
                             else
-                                atomicExch(overflow, 1);
+                                atomicOr(overflow, kOverflowPanes);
                             ++n_glass;
                         }
                     }
@@ -468,7 +468,7 @@ void k_trace(TraceParams P) {
         for (int e = c0; e < c1; ++e) {
             const int kind = e & 1;
             const int n = P.active[kind] ? P.q[kind].cnt_in[(e >> 1) * kCntStride] : 0;
-            if (n > P.cap) atomicExch(P.overflow, 2);  // never expected: counters are bounded by cap
+            if (n > P.cap) atomicOr(P.overflow, kOverflowQueue);  // never expected: counters are bounded by cap
             local += (n + kChunk - 1) / kChunk;
         }
         int incl = local;
@@ -1073,6 +1073,11 @@ __global__ void k_fill_i32(int* p, long long n, int v) {
     if (i < n) p[i] = v;
 }
 
+__global__ void k_fold_flags(FlagFold f) {
+    const int i = threadIdx.x;
+    if (i < f.n) atomicOr(f.dst[i], *f.src);
+}
+
 __global__ void k_pane(int n, const float4* pc, const float* c, float2* out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1192,6 +1197,17 @@ hipError_t launch_resolve(int WH, int nl, int nlp, double inv_spp, const float* 
 hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_flags(const int* src, int* const* dst, int n, hipStream_t st) {
+    for (int i0 = 0; i0 < n; i0 += kFoldMax) {
+        FlagFold f{};
+        f.src = src;
+        f.n = n - i0 < kFoldMax ? n - i0 : kFoldMax;
+        for (int i = 0; i < f.n; ++i) f.dst[i] = dst[i0 + i];
+        hipLaunchKernelGGL(k_fold_flags, dim3(1), dim3(64), 0, st, f);
+    }
     return hipGetLastError();
 }
 

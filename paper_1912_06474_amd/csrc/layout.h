@@ -63,6 +63,10 @@ constexpr int kTraceWaves = 8;    // waves per SIMD the trace kernel is compiled
 constexpr int kChunk = 64;        // rays per scheduling chunk (one wave)
 constexpr int kXcd = 8;           // XCDs of an MI355X; workgroup i runs on XCD i % 8
 constexpr int kMaxGlass = 4;      // pane crossings recorded per shadow segment
+// bits of the overflow flag the trace kernel raises (atomic OR)
+constexpr int kOverflowPanes = 1;  // a shadow segment crossed more than kMaxGlass panes
+constexpr int kOverflowQueue = 2;  // a subdomain queue count exceeded its capacity
+constexpr int kFoldMax = 32;       // destinations per flag-fold launch
 constexpr int kMaxCells = 512;
 constexpr int kShadeBlock = 512;
 
@@ -263,6 +267,13 @@ struct RouteParams {
 };
 
 // the glass tables of a scene, as the debug entry point sees them
+// dst[i] |= *src for i < n: a call's overflow flag folded into its renders' flags
+struct FlagFold {
+    const int* src;
+    int* dst[kFoldMax];
+    int n;
+};
+
 struct GlassTable {
     const float4* pane;
     const float4* coat;

@@ -591,7 +591,7 @@ PANE_B_Z = 3.35
 WALL_LIGHT_POS = (1.5, 1.5, 3.6)
 
 
-def point_light_panes(n_lambda: int = 16, seed: int = 0, coating_state=None):
+def point_light_panes(n_lambda: int = 16, seed: int = 0, coating_state=None, extra_panes: int = 0):
     """A diffuse wall x = 0 lit by a point light (Eq. 3) that it sees only
     through two 4 mm panes, and a camera that sees the wall but no pane.
 
@@ -608,7 +608,9 @@ def point_light_panes(n_lambda: int = 16, seed: int = 0, coating_state=None):
 
     Every shadow segment from the visible wall to the light crosses pane A,
     then pane B, and nothing else.  With ``coating_state`` both panes carry
-    the electrochromic coating on the face their geometric normal points out of.
+    the electrochromic coating on the face their geometric normal points out
+    of.  ``extra_panes`` stacks that many more horizontal panes 5 cm apart
+    above pane B (each shadow segment then crosses 2 + extra_panes panes).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     lam, w = lambda_grid(n_lambda)
@@ -624,6 +626,8 @@ def point_light_panes(n_lambda: int = 16, seed: int = 0, coating_state=None):
     dv = np.array([2.0 * math.cos(a), 0.0, -2.0 * math.sin(a)])
     _rect(mesh, ca - 0.5 * du - 0.5 * dv, du, dv, 1, 1, pane)   # geometric normal du x dv: -(sin a, 0, cos a)
     _rect(mesh, (0.5, 0.5, PANE_B_Z), (2, 0, 0), (0, 2, 0), 1, 1, pane)  # normal +z
+    for i in range(extra_panes):
+        _rect(mesh, (0.5, 0.5, PANE_B_Z + 0.05 * (i + 1)), (2, 0, 0), (0, 2, 0), 1, 1, pane)
     cam = dict(eye=(3.0, 1.5, 1.25), target=(0.0, 1.5, 1.25), fov_deg=30.0, ortho=False, ortho_half_h=1.0)
     return _finish(mesh, mats, lam, w, light_type=LIGHT_POINT, light_mat=point, name="point_light_panes",
                    seed=seed, light_p0=WALL_LIGHT_POS, light_e1=(0.0, 0.0, 0.0), light_e2=(0.0, 0.0, 0.0),

@@ -259,3 +259,38 @@ def test_error_paths(sdd):
         t.resolve_image(42, 8, 8)
     assert e.value.status == -2
     t.close()
+
+
+def test_overflow_flag_is_per_render_and_names_its_cause(sdd):
+    """A shadow segment through five panes (more than the four tracked) marks
+    the renders of that call only: another render of the same context, and a
+    render after a new scene, resolve cleanly; the statistics keep the bit
+    until they are reset."""
+    t = sdd.Tracer()
+    sc = sg.point_light_panes(16, seed=3, extra_panes=3)   # every wall point's shadow segment crosses 5 panes
+    t.load_scene(sc)
+    t.build_bvh(2, 2, 1)
+    W = H = 16
+    print("[overflow] 5-pane render, D=1", flush=True)
+    t.trace_spectral(sc["camera"], W, H, 1, 1, render_id=5)
+    with pytest.raises(sdd.SddError, match="more than 4 glass panes") as e:
+        t.resolve_image(5, W, H)
+    assert e.value.status == -5
+    assert t.stats()["overflow"] == 1
+    # looking down onto the pane stack with one vertex per path: no shadow rays
+    top = dict(eye=(1.5, 1.5, 4.5), target=(1.5, 1.6, 0.0), fov_deg=20.0)
+    t.trace_spectral(top, W, H, 1, 1, render_id=6)
+    s6, _ = t.resolve_image(6, W, H)
+    assert np.isfinite(s6.cpu().numpy()).all()
+    with pytest.raises(sdd.SddError, match="more than 4 glass panes"):
+        t.resolve_image(5, W, H)                            # still marked
+    t.reset_stats()
+    assert t.stats()["overflow"] == 0
+    # a new scene: its renders start clean
+    t.load_scene(sg.point_light_panes(16, seed=3))
+    t.build_bvh(2, 2, 1)
+    t.trace_spectral(sc["camera"], W, H, 1, 1, render_id=5)
+    s5, _ = t.resolve_image(5, W, H)
+    assert (s5.cpu().numpy() > 0).any()
+    assert t.stats()["overflow"] == 0
+    t.close()
