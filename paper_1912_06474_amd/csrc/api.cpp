@@ -1146,35 +1146,44 @@ namespace {
 
 sdd_status nrc_reserve(sdd_ctx* c, long long n);
 
-// operand staging of BF16 cache queries for n paths
-sdd_status nrc_ensure_ops(sdd_ctx* c, int n) {
-    const long long need = nrc_query_ops_paths(n);
-    if (need <= c->nrc_ocap) return SDD_OK;
-    dfree(c, c->nrc_hop);
-    dfree(c, c->nrc_sop);
-    dfree(c, c->nrc_okeys);
-    dfree(c, c->nrc_ovals);
-    dfree(c, c->nrc_otemp);
-    c->nrc_ocap = 0;
-    c->nrc_otemp_bytes = 0;
+// Operand staging of BF16 cache queries of n paths, and the sort's temporary
+// storage for a sort of n or of n_other paths (0: none).  The sort's need is
+// not monotonic in its size (a small sort takes another algorithm than a
+// large one), so every size a caller will sort is asked for separately.
+sdd_status nrc_ensure_ops(sdd_ctx* c, int n, int n_other = 0) {
+    const long long need = nrc_query_ops_paths(std::max(n, n_other));
+    size_t tb = 1;
+    for (int m : {n, n_other})
+        if (m > 0) tb = std::max({tb, nrc_order_temp_bytes(m), nrc_order_temp_bytes((int)nrc_query_ops_paths(m))});
     sdd_status st;
-    const size_t tb = std::max<size_t>(1, nrc_order_temp_bytes((int)need));
-    if ((st = dalloc(c, &c->nrc_hop, (size_t)(4 * need))) != SDD_OK ||
-        (st = dalloc(c, &c->nrc_sop, (size_t)(4 * need))) != SDD_OK ||
-        (st = dalloc(c, &c->nrc_okeys, (size_t)(2 * need))) != SDD_OK ||
-        (st = dalloc(c, &c->nrc_ovals, (size_t)(2 * need))) != SDD_OK ||
-        (st = dalloc(c, &c->nrc_otemp, tb)) != SDD_OK)
-        return st;
-    c->nrc_otemp_bytes = tb;
-    c->nrc_ocap = need;
+    if (need > c->nrc_ocap) {
+        dfree(c, c->nrc_hop);
+        dfree(c, c->nrc_sop);
+        dfree(c, c->nrc_okeys);
+        dfree(c, c->nrc_ovals);
+        c->nrc_ocap = 0;
+        if ((st = dalloc(c, &c->nrc_hop, (size_t)(4 * need))) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_sop, (size_t)(4 * need))) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_okeys, (size_t)(2 * need))) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_ovals, (size_t)(2 * need))) != SDD_OK)
+            return st;
+        c->nrc_ocap = need;
+    }
+    if (tb > c->nrc_otemp_bytes) {
+        dfree(c, c->nrc_otemp);
+        c->nrc_otemp_bytes = 0;
+        if ((st = dalloc(c, &c->nrc_otemp, tb)) != SDD_OK) return st;
+        c->nrc_otemp_bytes = tb;
+    }
     return SDD_OK;
 }
 
 // the gather order scratch of the cache queries (valid after nrc_ensure_ops)
 NrcOrder nrc_order(sdd_ctx* c) { return NrcOrder{c->nrc_okeys, c->nrc_ovals, c->nrc_otemp, c->nrc_otemp_bytes}; }
 
-// render buffers of the radiance cache: n batch paths, slots training paths of depth D
-sdd_status nrc_ensure_render(sdd_ctx* c, long long n, long long slots, int D) {
+// render buffers of the radiance cache: n batch paths (n_last in the call's
+// last batch), slots training paths of depth D
+sdd_status nrc_ensure_render(sdd_ctx* c, long long n, long long n_last, long long slots, int D) {
     sdd_status st;
     if (n > c->nrc_pcap) {
         dfree(c, c->nrc_cx);
@@ -1211,7 +1220,7 @@ sdd_status nrc_ensure_render(sdd_ctx* c, long long n, long long slots, int D) {
         c->nrc_dcap = D;
     }
     if (!c->nrc_count && (st = dalloc(c, &c->nrc_count, 1)) != SDD_OK) return st;
-    if ((st = nrc_ensure_ops(c, (int)n)) != SDD_OK) return st;
+    if ((st = nrc_ensure_ops(c, (int)n, (int)n_last)) != SDD_OK) return st;
     const long long bn = c->nrc_train_batch;
     if (bn > c->nrc_bcap) {
         dfree(c, c->nrc_bx);
@@ -1384,7 +1393,8 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
         const unsigned long long sw = (unsigned long long)(uint32_t)j.t->sample_offset * (unsigned long long)j.WH;
         r_nrc = (long long)((stride - sw % stride) % stride);
         n_slots = j.total > r_nrc ? (j.total - 1 - r_nrc) / stride + 1 : 0;
-        if ((st = nrc_ensure_render(c, nb, std::max<long long>(1, n_slots), D)) != SDD_OK) return st;
+        const long long n_last = total_pad - (total_pad - 1) / nb * nb;  // paths of the call's last batch
+        if ((st = nrc_ensure_render(c, nb, n_last, std::max<long long>(1, n_slots), D)) != SDD_OK) return st;
         np = NrcPaths{1, stride, c->nrc_cx, c->nrc_cn, c->nrc_tx, c->nrc_tn};
     }
     {  // this call's overflow bits start clear; they are folded into its renders at the end

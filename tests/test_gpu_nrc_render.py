@@ -96,6 +96,28 @@ def test_query_equals_infer(tracer, precision):
     assert np.array_equal(q[:, :nl], y)
 
 
+def test_bf16_query_after_a_larger_query(tracer):
+    """Queries of decreasing size on one context: the gather sort's temporary
+    storage is not monotonic in the sort's size (small sorts take another
+    algorithm), so each size must be sized for itself; every query still
+    equals the row forward bit for bit."""
+    sc = sg.tiny_room(0, 16)
+    tracer.load_scene(sc)
+    params, tables = sg.nrc_params(3, table_size=1 << 14)
+    tables = np.random.default_rng(4).uniform(-0.5, 0.5, tables.shape).astype(np.float32)
+    tracer.nrc_init(params, tables, LO, HI)
+    lam = np.asarray(sc["lambda_nm"], np.float32)
+    nl = len(lam)
+    for n in (65536, 1000, 63, 5000):
+        print(f"[nrc_render] bf16 query n={n}", flush=True)
+        x, w, _, _ = sg.nrc_rows(n, 50 + n, LO, HI)
+        q = tracer.nrc_query(x, w, "bf16").cpu().numpy()
+        k = min(n, 2000)
+        y = tracer.nrc_infer(np.repeat(x[:k], nl, axis=0), np.repeat(w[:k], nl, axis=0), np.tile(lam, k),
+                             "bf16").cpu().numpy().reshape(k, nl)
+        assert np.array_equal(q[:k, :nl], y)
+
+
 def _gpu_nrc_render(tracer, sc, W, H, spp, D, grid, train_paths, precision="fp32", seed=0, steps=0,
                     sample_offset=0):
     tracer.load_scene(sc)
@@ -176,19 +198,23 @@ def test_bf16_queries_and_training_in_the_render(tracer):
     assert not np.array_equal(t1, tables)  # the tables moved
 
 
-def test_cache_render_across_batches(tracer):
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_cache_render_across_batches(tracer, precision):
     """Small memory budgets split the call into many batches: the training
     slots of each batch segment are found from the call's path numbering, so
-    image and rows equal the one-batch render bit for bit."""
+    image and rows equal the one-batch render bit for bit.  With BF16 queries
+    the last, smaller batch sorts its gathers with its own sort's storage."""
     import os
     sc = sg.tiny_room(0, 16)
     W, H, spp, D = 64, 48, 3, 5
-    one, rows1, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), 700, sample_offset=5)
+    one, rows1, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), 700, sample_offset=5,
+                                       precision=precision)
     old = os.environ.get("SDD_MEM_BUDGET_GB")
     os.environ["SDD_MEM_BUDGET_GB"] = "0.002"
     try:
         tracer.reset_stats()
-        many, rows2, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), 700, sample_offset=5)
+        many, rows2, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), 700, sample_offset=5,
+                                            precision=precision)
         batches = tracer.stats()["batches"]
     finally:
         if old is None:
