@@ -469,6 +469,20 @@ sdd_status sdd_nrc_train_step(sdd_ctx *ctx, int32_t n, const float *x, const flo
  * or cache. */
 sdd_status sdd_nrc_query(sdd_ctx *ctx, int32_t n, const float *x4, const float *n4, float *out, int32_t precision);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the BF16
+ * query of sdd_nrc_query (precision 1), same arguments and the same result,
+ * bit for bit, with no allocation of any kind.  Its scratch (operand staging,
+ * the sort of the points by the Morton code of their position, the sort's
+ * temporary storage) is one static device array of 12 MiB per GPU, kept
+ * until the process ends.  Every call on a GPU shares that array, so calls
+ * that overlap on one GPU (two streams, two contexts, two threads) race; the
+ * caller orders them.  Nothing in it needs clearing between calls.
+ * SDD_ERR_INVALID_ARG for n above SDD_NRC_NOALLOC_MAX_PATHS; otherwise as
+ * sdd_nrc_query. */
+#define SDD_NRC_NOALLOC_MAX_PATHS 65536
+sdd_status sdd_nrc_query_noalloc(sdd_ctx *ctx, int32_t n, const float *x4, const float *n4, float *out);
+
 /* The last cache render's training rows (compacted, in path order): rows
  * host float [max_rows][8] = (x, y, z, lambda_nm, n_x, n_y, n_z, target);
  * n_rows gets the row count, n_steps the Adam steps taken, loss the last

@@ -31,7 +31,7 @@ EXPORTS = ("sdd_create", "sdd_destroy", "sdd_last_error", "sdd_load_scene", "sdd
            "sdd_trace_spectral", "sdd_resolve_image", "sdd_reset_render", "sdd_get_stats", "sdd_reset_stats",
            "sdd_debug_philox", "sdd_debug_pane", "sdd_debug_trace_rays", "sdd_debug_glass", "sdd_trace_batch",
            "sdd_nrc_param_count", "sdd_nrc_init", "sdd_nrc_infer", "sdd_nrc_train_step", "sdd_nrc_get_params",
-           "sdd_nrc_last_rows", "sdd_nrc_query")
+           "sdd_nrc_last_rows", "sdd_nrc_query", "sdd_nrc_query_noalloc")
 NRC_LEVELS, NRC_FEAT, NRC_HID, NRC_LAYERS = 16, 2, 64, 5
 
 
@@ -139,6 +139,7 @@ def lib():
         L.sdd_nrc_train_step.argtypes = [vp, i32, vp, vp, vp, vp, i32, C.POINTER(C.c_float)]
         L.sdd_nrc_get_params.argtypes = [vp, i32, vp]
         L.sdd_nrc_query.argtypes = [vp, i32, vp, vp, vp, i32]
+        L.sdd_nrc_query_noalloc.argtypes = [vp, i32, vp, vp, vp]
         L.sdd_nrc_last_rows.argtypes = [vp, i32, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_float)]
         tp = C.POINTER(Tuning)
@@ -481,6 +482,22 @@ class Tracer:
         out = torch.zeros((n, nlp), dtype=torch.float32, device=self.device)
         self._check(lib().sdd_nrc_query(self.h, n, x4.data_ptr(), n4.data_ptr(), out.data_ptr(),
                                         {"fp32": 0, "bf16": 1}[precision]))
+        return out
+
+    def nrc_query_noalloc(self, x, nrm):
+        """sdd_nrc_query_noalloc: the BF16 query with its scratch in the library's static array (no allocation
+        inside the library; this wrapper allocates the operand and output tensors)."""
+        torch = self.torch
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device).reshape(-1, 3)
+        nrm = torch.as_tensor(nrm, dtype=torch.float32, device=self.device).reshape(-1, 3)
+        n = x.shape[0]
+        x4 = torch.zeros((n, 4), dtype=torch.float32, device=self.device)
+        n4 = torch.zeros((n, 4), dtype=torch.float32, device=self.device)
+        x4[:, :3] = x
+        n4[:, :3] = nrm
+        nlp = (self.n_lambda + 3) // 4 * 4
+        out = torch.zeros((n, nlp), dtype=torch.float32, device=self.device)
+        self._check(lib().sdd_nrc_query_noalloc(self.h, n, x4.data_ptr(), n4.data_ptr(), out.data_ptr()))
         return out
 
     def nrc_last_rows(self, max_rows=None):

@@ -121,6 +121,7 @@ struct sdd_ctx {
     long long counts_len = 0;
     long long batch_bytes = 0;  // device bytes of the path batch (ensure_batch)
     long long call_budget = 0;  // memory budget of the current call (set before any capture)
+    void* noalloc_scratch = nullptr;  // device address of this device's allocation-free query scratch
     int* d_overflow = nullptr;   // overflow bits of the current trace call (cleared at its start)
     int* d_ovf_stats = nullptr;  // overflow bits since sdd_reset_stats
     int* d_ktot = nullptr;  // routing key totals [2][kMaxCells * kExtBins]
@@ -690,6 +691,11 @@ sdd_status sdd_create(int hip_device, void* hip_stream, sdd_ctx** out) {
     // sets the grid for its subdomain count, never above this
     c->trace_grid_max = trace_grid_for(c, 1);
     c->trace_grid = c->trace_grid_max;
+    // the allocation-free query's scratch: its device address, resolved once per device
+    if (nrc_noalloc_scratch(hip_device, &c->noalloc_scratch) != hipSuccess) {
+        delete c;
+        return SDD_ERR_HIP;
+    }
     if (dalloc(c, &c->d_overflow, 1) != SDD_OK || dalloc(c, &c->d_ovf_stats, 1) != SDD_OK ||
         dalloc(c, &c->d_stats, kStatCount) != SDD_OK ||
         dalloc(c, &c->d_ktot, 2 * (size_t)kMaxCells * kExtBins) != SDD_OK ||
@@ -2523,6 +2529,29 @@ sdd_status sdd_nrc_query(sdd_ctx* c, int32_t n, const float* x4, const float* n4
                                           precision, c->nrc_hop, c->nrc_sop, precision == 1 ? &ord : nullptr,
                                           c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "nrc query");
+    return SDD_OK;
+}
+
+sdd_status sdd_nrc_query_noalloc(sdd_ctx* c, int32_t n, const float* x4, const float* n4, float* out) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_query_noalloc before sdd_nrc_init");
+    if (!c->has_scene) return fail(c, SDD_ERR_STATE, "sdd_nrc_query_noalloc before sdd_load_scene (wavelengths)");
+    if (n < 0 || (n > 0 && (!x4 || !n4 || !out))) return fail(c, SDD_ERR_INVALID_ARG, "bad arguments");
+    if (n > SDD_NRC_NOALLOC_MAX_PATHS)
+        return fail(c, SDD_ERR_INVALID_ARG, "n = " + std::to_string(n) + " exceeds the allocation-free query's limit of " +
+                                                std::to_string(SDD_NRC_NOALLOC_MAX_PATHS) + " points");
+    if (n == 0) return SDD_OK;
+    DeviceGuard g(c->device);
+    uint4* hop = nullptr;
+    uint2* sop = nullptr;
+    NrcOrder ord{};
+    if (!nrc_query_scratch_layout(c->noalloc_scratch, kNoAllocScratchBytes, n, &hop, &sop, &ord))
+        return fail(c, SDD_ERR_INVALID_ARG, "the query's scratch does not fit the static array");
+    const hipError_t e = nrc_launch_query(c->nrc, n, reinterpret_cast<const float4*>(x4),
+                                          reinterpret_cast<const float4*>(n4), c->d_lam, c->nl, c->nlp, out, 0, 1, hop,
+                                          sop, &ord, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "nrc query (allocation-free)");
     return SDD_OK;
 }
 

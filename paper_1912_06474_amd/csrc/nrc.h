@@ -105,6 +105,18 @@ hipError_t nrc_launch_query_operands(const NrcNet& net, int n, const float4* cx,
                                      uint2* sop, const NrcOrder* ord, hipStream_t st);
 hipError_t nrc_launch_query_mfma(const NrcNet& net, int n, const uint4* hop, const uint2* sop, const float* lam,
                                  int nl, int nlp, float* lhat, int tiled, hipStream_t st);
+// Allocation-free BF16 query: its scratch (operand staging, sort keys and
+// values, the sort's temporary storage) lives in one file-scope device array
+// of kNoAllocScratchBytes per GPU, held until the process ends.
+constexpr size_t kNoAllocScratchBytes = 12u << 20;
+constexpr int kNoAllocMaxPaths = 1 << 16;
+// device address of that array on `device` (must be the current device);
+// resolved once per device and cached
+hipError_t nrc_noalloc_scratch(int device, void** out);
+// carve the scratch of an n-path BF16 query out of [base, base + cap), every
+// part 256-byte aligned; false if it does not fit
+bool nrc_query_scratch_layout(void* base, size_t cap, int n, uint4** hop, uint2** sop, NrcOrder* ord);
+
 // stable compaction of the training rows (pairs of float4) whose flag is set;
 // with temp == nullptr only sets *temp_bytes
 hipError_t nrc_select_rows(const float4* rows, const int* ok, int n, float4* out, int* d_count, void* temp,

@@ -18,6 +18,8 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <mutex>
+
 #include <cmath>
 
 #include "nrc.h"
@@ -925,6 +927,65 @@ hipError_t nrc_launch_query_mfma(const NrcNet& net, int n, const uint4* hop, con
     hipLaunchKernelGGL(k_query_mfma, dim3(nblocks(n, rows_per_block)), dim3(kMfmaBlock), 0, st, net, n, hop, sop,
                        lam, nl, nlp, lhat, tiled);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free query
+// ---------------------------------------------------------------------------
+// Host code never passes this array's name to a kernel or copy: in host code
+// it is a stand-in, not a device address.  nrc_noalloc_scratch resolves the
+// address once per device, with that device current, and the caller passes
+// that address on.  Every call on a GPU shares its array: calls that overlap
+// on one GPU race.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t nrc_noalloc_scratch(int device, void** out) {
+    if (!out || device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+bool nrc_query_scratch_layout(void* base, size_t cap, int n, uint4** hop, uint2** sop, NrcOrder* ord) {
+    if (!base || n <= 0) return false;
+    const size_t need = (size_t)nrc_query_ops_paths(n);
+    // the sort runs on n keys; its need is not monotonic in the size, so ask for n itself
+    const size_t tb = nrc_order_temp_bytes(n);
+    if (tb == 0) return false;
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    size_t off = 0;
+    char* b = static_cast<char*>(base);
+    const size_t o_hop = off;
+    off = up(off + 4 * need * sizeof(uint4));
+    const size_t o_sop = off;
+    off = up(off + 4 * need * sizeof(uint2));
+    const size_t o_keys = off;
+    off = up(off + 2 * need * sizeof(uint32_t));
+    const size_t o_vals = off;
+    off = up(off + 2 * need * sizeof(int));
+    const size_t o_temp = off;
+    off = up(off + tb);
+    if (off > cap) return false;
+    *hop = reinterpret_cast<uint4*>(b + o_hop);
+    *sop = reinterpret_cast<uint2*>(b + o_sop);
+    ord->keys = reinterpret_cast<uint32_t*>(b + o_keys);
+    ord->vals = reinterpret_cast<int*>(b + o_vals);
+    ord->temp = b + o_temp;
+    ord->temp_bytes = tb;
+    return true;
 }
 
 hipError_t nrc_select_rows(const float4* rows, const int* ok, int n, float4* out, int* d_count, void* temp,
