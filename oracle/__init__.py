@@ -70,6 +70,8 @@ def _declare(L):
                                  C.c_void_p, C.c_void_p, C.c_void_p]
     L.ora_shadow_rays.argtypes = [C.POINTER(Scene), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p]
+    L.ora_probe_paths.argtypes = [C.POINTER(Scene), C.c_void_p, C.POINTER(Args), C.c_int, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]
     L.ora_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     L.ora_u01.restype = C.c_double
     L.ora_u01.argtypes = [C.c_uint32]
@@ -202,6 +204,26 @@ def render(scene, W, H, spp, max_depth, *, camera=None, seed=0, render_id=0, sam
     res["n_ext_rays"] = int(o.n_ext_rays)
     res["n_shadow_rays"] = int(o.n_shadow_rays)
     return res
+
+
+PROBE_STRIDE = 18
+
+
+def probe_paths(scene, W, H, max_depth, pix, samples, *, camera=None, seed=0, render_id=0, use_bvh=True,
+                oscene=None):
+    """Replay path samples (pix[i], samples[i]) and return [n, D, 18] per-depth
+    state (see ora_probe_paths in oracle.h): ray, glass draw and P_R, light sample."""
+    osc = oscene or OracleScene(scene)
+    cam = camera or scene["camera"]
+    a = make_args(cam, W, H, 1, max_depth, seed, render_id, 0, use_bvh)
+    pix = np.ascontiguousarray(pix, np.int32)
+    samples = np.ascontiguousarray(samples, np.int32)
+    out = np.zeros((len(pix), max_depth, PROBE_STRIDE))
+    rc = lib().ora_probe_paths(C.byref(osc.c), osc.accel if use_bvh else None, C.byref(a), len(pix), _ptr(pix),
+                               _ptr(samples), _ptr(out))
+    if rc != 0:
+        raise RuntimeError("ora_probe_paths failed")
+    return out
 
 
 def trace_rays(scene, o, d, exclude=None, use_bvh=True, oscene=None):

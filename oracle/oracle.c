@@ -549,9 +549,14 @@ static int any_nonzero(const float *v, int n) {
  * the radiance the path then carries back into the vertex along its
  * continuation, (L_end[l] - L_d[l]) / beta_d[l], with L_d and beta_d the
  * estimate and throughput right after the vertex's light sample. */
+/* probe (NULL: none): per depth d, ORA_PROBE_STRIDE doubles at (d - 1) * stride:
+ * the ray that finds vertex d (origin, direction, excluded prim), the glass
+ * branch draw and P_R if vertex d is a pane that draws one, and the light
+ * sample of a diffuse vertex d (shadow origin, unit direction, length, cos at
+ * the vertex, cos at the light); NaN where a quantity does not arise. */
 static void trace_path(const ora_scene *sc, const ora_accel *acc, const ora_args *ar, int px, int py,
                        uint32_t s, double *L, int32_t *hlog, int32_t *slog, double *fhit,
-                       double *beta, double *tmp_T, int64_t *n_ext, int64_t *n_sh, double *rows) {
+                       double *beta, double *tmp_T, int64_t *n_ext, int64_t *n_sh, double *rows, double *probe) {
     const int nl = sc->n_lambda, D = ar->max_depth;
     const uint32_t p = (uint32_t)(py * ar->W + px);
     const int train = ar->nrc && ((uint64_t)s * (uint64_t)ar->W * (uint64_t)ar->H + p) % ar->nrc_stride == 0;
@@ -583,8 +588,15 @@ static void trace_path(const ora_scene *sc, const ora_accel *acc, const ora_args
         }
     }
 
+    if (probe) for (int k = 0; k < D * ORA_PROBE_STRIDE; ++k) probe[k] = NAN;
     for (int d = 1; d <= D; ++d) {
         double t;
+        double *pr = probe ? probe + (size_t)(d - 1) * ORA_PROBE_STRIDE : NULL;
+        if (pr) {
+            pr[0] = o.x; pr[1] = o.y; pr[2] = o.z;
+            pr[3] = dir.x; pr[4] = dir.y; pr[5] = dir.z;
+            pr[6] = (double)exclude;
+        }
         int prim = closest_hit(sc, acc, o, dir, exclude, &t);
         ++*n_ext;
         if (hlog) hlog[d - 1] = prim;
@@ -620,6 +632,11 @@ static void trace_path(const ora_scene *sc, const ora_accel *acc, const ora_args
                 v3 om = scl(w, 1.0 / r);
                 double cx = dot(n, om);
                 double cy = lt == ORA_LIGHT_PARALLELOGRAM ? -dot(nL, om) : 1.0;
+                if (pr) {
+                    pr[9] = xo.x; pr[10] = xo.y; pr[11] = xo.z;
+                    pr[12] = om.x; pr[13] = om.y; pr[14] = om.z;
+                    pr[15] = r; pr[16] = cx; pr[17] = cy;
+                }
                 if (cx > 0.0 && cy > 0.0) {
                     int vis = shadow_T(sc, acc, xo, om, r, prim, tmp_T);
                     ++*n_sh;
@@ -675,6 +692,7 @@ static void trace_path(const ora_scene *sc, const ora_accel *acc, const ora_args
             double PR = sumR / (sumR + sumT);
             if (d == D) break;
             rng_u(ar->seed, ar->render_id, p, s, (uint32_t)d, 0, ub);
+            if (pr) { pr[7] = ub[2]; pr[8] = PR; }
             if (ub[2] < PR) {
                 for (int l = 0; l < nl; ++l) beta[l] *= tmp_T[l] / PR;
                 dir = sub(dir, scl(ng, 2.0 * dot(dir, ng)));
@@ -729,7 +747,7 @@ int ora_render(const ora_scene *sc, const ora_accel *acc, const ora_args *ar, or
                 double *fh = out->first_hit ? out->first_hit + slot * 3 : NULL;
                 double *rw = out->nrc_rows ? out->nrc_rows + slot * (size_t)(D - 1) * 9 : NULL;
                 trace_path(sc, a, ar, px, py, (uint32_t)(ar->sample_offset + j), L, hl, sl, fh, beta, tmpT,
-                           &n_ext, &n_sh, rw);
+                           &n_ext, &n_sh, rw, NULL);
                 if (out->path_L) memcpy(out->path_L + slot * nl, L, sizeof(double) * (size_t)nl);
                 for (int l = 0; l < nl; ++l) acc_l[l] += L[l];
             }
@@ -748,4 +766,28 @@ int ora_render(const ora_scene *sc, const ora_accel *acc, const ora_args *ar, or
     out->n_ext_rays = n_ext;
     out->n_shadow_rays = n_sh;
     return 0;
+}
+
+int ora_probe_paths(const ora_scene *sc, const ora_accel *acc, const ora_args *ar, int n, const int32_t *pix,
+                    const int32_t *samp, double *out) {
+    if (!sc || !ar || !out || n < 0 || ar->max_depth <= 0 || sc->n_lambda <= 0) return -1;
+    const ora_accel *a = ar->use_bvh ? acc : NULL;
+    const int nl = sc->n_lambda, D = ar->max_depth;
+    int rc = 0;
+#pragma omp parallel
+    {
+        double *L = (double *)malloc(sizeof(double) * (size_t)nl);
+        double *beta = (double *)malloc(sizeof(double) * (size_t)nl);
+        double *tmpT = (double *)malloc(sizeof(double) * (size_t)nl);
+        int64_t ne = 0, ns = 0;
+#pragma omp for schedule(dynamic, 4)
+        for (int i = 0; i < n; ++i) {
+            const int p = pix[i];
+            if (p < 0 || p >= ar->W * ar->H) { rc = -1; continue; }
+            trace_path(sc, a, ar, p % ar->W, p / ar->W, (uint32_t)samp[i], L, NULL, NULL, NULL, beta, tmpT, &ne,
+                       &ns, NULL, out + (size_t)i * D * ORA_PROBE_STRIDE);
+        }
+        free(L); free(beta); free(tmpT);
+    }
+    return rc;
 }

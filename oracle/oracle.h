@@ -122,6 +122,19 @@ int ora_trace_rays(const ora_scene *sc, const ora_accel *acc, int n, const doubl
 int ora_shadow_rays(const ora_scene *sc, const ora_accel *acc, int n, const double *o,
                     const double *d, const double *r, const int32_t *exclude, double *out);
 
+/* Replay of n path samples (pixel pix[i], sample index samp[i]; args->spp
+ * and sample_offset unused) exposing, per depth d = 1..D, ORA_PROBE_STRIDE
+ * doubles at out[(i * D + d - 1) * stride]: [0..2] origin and [3..5] unit
+ * direction of the ray that finds vertex d, [6] its excluded prim; [7] the
+ * glass-branch draw u and [8] P_R if vertex d is a pane that draws one; for a
+ * diffuse vertex d with a light: [9..11] shadow-ray origin, [12..14] its unit
+ * direction, [15] its length, [16] cos at the vertex, [17] cos at the light.
+ * NaN where a quantity does not arise.  Test infrastructure: the parity tests
+ * take the margins of the decisions where a GPU path left the oracle's. */
+#define ORA_PROBE_STRIDE 18
+int ora_probe_paths(const ora_scene *sc, const ora_accel *acc, const ora_args *args, int n, const int32_t *pix,
+                    const int32_t *samp, double *out);
+
 void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double ora_u01(uint32_t x);
 

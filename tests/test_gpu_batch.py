@@ -15,7 +15,7 @@ import pytest
 
 import oracle as ora
 import scenegen as sg
-from parity import assert_parity
+from parity import ParityCtx, assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -108,7 +108,7 @@ def test_photochromic_state_parity(tracer):
         so = dict(sc)
         so["tri_mat"] = np.where(sc["tri_mat"] == base, states[k], sc["tri_mat"]).astype(np.int32)
         o = ora.render(so, W, H, spp, D, logs=True, seed=9)
-        assert_parity(g, o, excluded_max=1)
+        assert_parity(g, o, ParityCtx(so, W, H, spp, D, seed=9))
         if k == 7:
             # the darkest state transmits less through the pane than the clearest
             assert g["spectral"].sum() < prev
@@ -151,4 +151,5 @@ def test_photochromic_batch_full_size(tracer):
         s, x = res[r["render_id"]]
         g = dict(spectral=s[pix], xyz=x[pix], hit_log=r["hit_log"].cpu().numpy()[pix],
                  shadow_log=r["shadow_log"].cpu().numpy()[pix])
-        assert_parity(g, o)
+        assert_parity(g, o, ParityCtx(so, r["W"], r["H"], r["spp"], D, camera=r["camera"],
+                                      render_id=r["render_id"], pix=pix))

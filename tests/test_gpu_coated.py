@@ -7,7 +7,7 @@ import pytest
 
 import oracle as ora
 import scenegen as sg
-from parity import assert_parity, rel_err
+from parity import ParityCtx, assert_parity, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -85,14 +85,14 @@ def test_coated_lone_pane_parity(tracer):
     sc = sg.lone_pane(n_lambda=41, coating_state=0.8)
     g = gpu_render(tracer, sc, 32, 32, 8, 2, (2, 2, 1))
     o = ora.render(sc, 32, 32, 8, 2, logs=True)
-    assert_parity(g, o, excluded_max=1)
+    assert_parity(g, o, ParityCtx(sc, 32, 32, 8, 2))
 
 
 def test_coated_tiny_room_parity(tracer):
     sc = sg.tiny_room(coating_state=0.6)
     g = gpu_render(tracer, sc, 64, 64, 2, 6, (2, 2, 1), seed=3)
     o = ora.render(sc, 64, 64, 2, 6, logs=True, seed=3)
-    assert_parity(g, o, excluded_max=2)
+    assert_parity(g, o, ParityCtx(sc, 64, 64, 2, 6, seed=3))
 
 
 def test_electrochromic_room_full_frame_sampled(tracer):
@@ -107,5 +107,5 @@ def test_electrochromic_room_full_frame_sampled(tracer):
     rng = np.random.default_rng(11)
     pix = np.sort(rng.choice(W * H, 4096, replace=False)).astype(np.int32)
     o = ora.render(sc, W, H, spp, D, pix=pix, logs=True)
-    assert_parity({k: v[pix] for k, v in g.items()}, o)
+    assert_parity({k: v[pix] for k, v in g.items()}, o, ParityCtx(sc, W, H, spp, D, pix=pix))
     assert np.isfinite(g["spectral"]).all() and (g["spectral"] >= 0).all()

@@ -9,7 +9,7 @@ import pytest
 
 import oracle as ora
 import scenegen as sg
-from parity import assert_parity, hit_agreement
+from parity import ParityCtx, assert_parity, hit_agreement
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +62,7 @@ def test_device_bvh_render_parity(tracer):
     tracer.reset_render(0)
     g = dict(spectral=s.cpu().numpy(), xyz=x.cpu().numpy(), hit_log=hl.cpu().numpy(), shadow_log=sl.cpu().numpy())
     o = ora.render(sc, W, H, 2, 5, logs=True, seed=2)
-    assert_parity(g, o, excluded_max=2)
+    assert_parity(g, o, ParityCtx(sc, W, H, 2, 5, seed=2))
 
 
 @pytest.mark.parametrize("which", ["furnished_room", "electrochromic_room"])

@@ -21,7 +21,7 @@ import pytest
 
 import oracle as ora
 import scenegen as sg
-from parity import assert_parity
+from parity import ParityCtx, assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -155,7 +155,7 @@ def test_cache_render_matches_oracle(tracer, case):
     stride = -(-(W * H * spp) // case["train_paths"])
     o = ora.render(sc, W, H, spp, D, logs=True, seed=0, sample_offset=case["sample_offset"],
                    nrc=dict(stride=stride, c=COEF, lo=LO, hi=HI))
-    assert_parity(g, o)
+    assert_parity(g, o, ParityCtx(sc, W, H, spp, D, sample_offset=case["sample_offset"]))
     orows = _oracle_rows(o, W, H, spp)
     print(f"[nrc_render] stride {stride}: {len(rows)} training rows (oracle {len(orows)})", flush=True)
     assert len(rows) == len(orows) and len(rows) > 0
@@ -235,7 +235,7 @@ def test_cache_render_coated_panes_match_oracle(tracer):
     g, rows, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), 600)
     stride = -(-(W * H * spp) // 600)
     o = ora.render(sc, W, H, spp, D, logs=True, seed=0, nrc=dict(stride=stride, c=COEF, lo=LO, hi=HI))
-    assert_parity(g, o)
+    assert_parity(g, o, ParityCtx(sc, W, H, spp, D))
     orows = _oracle_rows(o, W, H, spp)
     assert len(rows) == len(orows) and len(rows) > 0
     t, to = rows[:, 7].astype(np.float64), orows[:, 8]
@@ -261,4 +261,4 @@ def test_cache_render_shallow_depths(tracer, D):
     else:
         stride = -(-(W * H * spp) // 300)
         o = ora.render(sc, W, H, spp, D, logs=True, seed=0, nrc=dict(stride=stride, c=COEF, lo=LO, hi=HI))
-        assert_parity(g, o)
+        assert_parity(g, o, ParityCtx(sc, W, H, spp, D))

@@ -6,7 +6,7 @@ import pytest
 
 import oracle as ora
 import scenegen as sg
-from parity import HIT_AGREE_MIN, REL_TOL, assert_parity, hit_agreement, rel_err
+from parity import HIT_AGREE_MIN, REL_TOL, ParityCtx, assert_parity, hit_agreement, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -121,14 +121,14 @@ def test_tiny_room_parity(tracer):
     sc = sg.tiny_room()
     g = gpu_render(tracer, sc, 64, 64, 1, 4, grid=(2, 2, 1))
     o = ora.render(sc, 64, 64, 1, 4, logs=True)
-    assert_parity(g, o, excluded_max=2)
+    assert_parity(g, o, ParityCtx(sc, 64, 64, 1, 4))
 
 
 def test_tiny_room_parity_more_samples(tracer):
     sc = sg.tiny_room()
     g = gpu_render(tracer, sc, 48, 40, 4, 6, grid=(2, 2, 1), seed=5)
     o = ora.render(sc, 48, 40, 4, 6, logs=True, seed=5)
-    assert_parity(g, o, excluded_max=3)
+    assert_parity(g, o, ParityCtx(sc, 48, 40, 4, 6, seed=5))
 
 
 def test_decomposition_invariance(tracer):
@@ -166,7 +166,7 @@ def test_fixture_parity(tracer, which):
     spp, D = 4, 2
     g = gpu_render(tracer, sc, W, H, spp, D, grid=(2, 2, 1))
     o = ora.render(sc, W, H, spp, D, logs=True)
-    assert_parity(g, o, excluded_max=1)
+    assert_parity(g, o, ParityCtx(sc, W, H, spp, D))
 
 
 @pytest.mark.parametrize("coating", [None, 0.7])
@@ -179,7 +179,7 @@ def test_point_light_through_panes_parity(tracer, coating):
     g = gpu_render(tracer, sc, W, H, spp, D, grid=(2, 2, 2))
     o = ora.render(sc, W, H, spp, D, logs=True)
     assert (g["shadow_log"][:, :, 0] == 1).all()
-    assert_parity(g, o, excluded_max=1)
+    assert_parity(g, o, ParityCtx(sc, W, H, spp, D))
 
 
 def test_sample_split_and_batching_are_bitwise_identical(tracer):
@@ -232,7 +232,7 @@ def test_edge_shapes(tracer):
     for (W, H, spp, D) in [(1, 1, 1, 1), (3, 1, 2, 1), (1, 7, 1, 3), (65, 33, 1, 2)]:
         g = gpu_render(tracer, sc, W, H, spp, D, grid=(2, 2, 1))
         o = ora.render(sc, W, H, spp, D, logs=True)
-        assert_parity(g, o, excluded_max=1)
+        assert_parity(g, o, ParityCtx(sc, W, H, spp, D))
 
 
 def test_error_paths(sdd):

@@ -15,7 +15,7 @@ import pytest
 
 import oracle as ora
 import scenegen as sg
-from parity import assert_parity, rel_err
+from parity import ParityCtx, assert_parity, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -59,7 +59,7 @@ def test_room_scale_sampled_pixels_parity(frame):
     rng = np.random.default_rng(7)
     pix = np.sort(rng.choice(W * H, 8192, replace=False)).astype(np.int32)
     o = ora.render(sc, W, H, SPP, D, pix=pix, logs=True)
-    assert_parity(_sub(g, pix), o)
+    assert_parity(_sub(g, pix), o, ParityCtx(sc, W, H, SPP, D, pix=pix))
 
 
 def test_room_scale_window_crop_parity(frame):
@@ -72,7 +72,7 @@ def test_room_scale_window_crop_parity(frame):
         np.asarray(sc["mat_type"])[np.asarray(sc["tri_mat"])] == sg.GLASS)).sum())
     print(f"[room_scale] crop: {n_glass} pane hits", flush=True)
     assert n_glass > 0
-    assert_parity(_sub(g, pix), o)
+    assert_parity(_sub(g, pix), o, ParityCtx(sc, W, H, SPP, D, pix=pix))
 
 
 def test_room_scale_log_structure_and_ray_counts(frame):
