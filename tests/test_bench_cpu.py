@@ -52,3 +52,38 @@ def test_committed_traffic_summaries_parse(workload):
     for k in ("fetch_kib_per_dispatch", "write_kib_per_dispatch", "fetch_scale", "write_scale"):
         assert float(kv[k]) > 0
     assert len(kv["source_sha256"]) == 64
+
+
+def test_relmse_fit_and_frames_to_target():
+    n = [(k, 0.1 * k, 0.004 + 40.0 / k) for k in range(100, 401, 10)]
+    a, b = bench.relmse_fit(n, floor=True)
+    assert abs(a - 0.004) < 1e-12 and abs(b - 40.0) < 1e-9
+    a0, b0 = bench.relmse_fit([(k, 0.0, 40.0 / k) for k in range(1, 50)], floor=False)
+    assert a0 == 0.0 and abs(b0 - 40.0) < 1e-9
+    assert abs(bench.frames_to(0.01, 0.004, 40.0) - 40.0 / 0.006) < 1e-9
+    assert bench.frames_to(0.01, 0.01, 40.0) is None and bench.frames_to(0.01, 0.02, 40.0) is None
+
+
+def test_error_split_recovers_bias_and_variance():
+    """Synthetic images: truth T, reference halves with noise s_r, a test image
+    whose halves carry noise s_i and a known bias; the split recovers the
+    weighted squared bias and variance within its own standard error."""
+    import torch
+    g = torch.Generator().manual_seed(3)
+    P, L = 200_000, 4
+    T = 0.5 + torch.rand(P, L, generator=g, dtype=torch.float64)
+    bias = 0.05 * T
+    s_r, s_i = 0.3, 0.2
+    R1 = T + s_r * torch.randn(P, L, generator=g, dtype=torch.float64)
+    R2 = T + s_r * torch.randn(P, L, generator=g, dtype=torch.float64)
+    R, varR = 0.5 * (R1 + R2), 0.25 * (R1 - R2) ** 2
+    Ia = T + bias + s_i * torch.randn(P, L, generator=g, dtype=torch.float64)
+    Ib = T + bias + s_i * torch.randn(P, L, generator=g, dtype=torch.float64)
+    w = 1.0 / T ** 2
+    b2, se, var_w = bench.error_split(Ia, Ib, R, varR, w)
+    want = float((bias ** 2 * w).mean())
+    assert abs(b2 - want) <= 4 * se, (b2, want, se)
+    assert abs(var_w - float((s_i ** 2 / 2 * w).mean())) <= 0.02 * var_w
+    # an unbiased image: the split's bias is zero within its error
+    b0, se0, _ = bench.error_split(Ia - bias, Ib - bias, R, varR, w)
+    assert abs(b0) <= 4 * se0
