@@ -61,7 +61,7 @@ WORKLOADS = {
     # 4 spp per frame, 41 wavelengths, paths end in the cache after vertex 2
     "nrc_room": dict(scene=("nrc_room", dict(seed=3, n_lambda=41)), W=1920, H=1080, spp=4, D=8, grid=(4, 4, 2),
                      nrc=dict(ref_frames=64, train_paths=1 << 16, train_steps=4, train_batch=1 << 14,
-                              train_warmup=20)),
+                              train_warmup=100)),
 }
 
 # Multiply-adds of one cache query launch, two flops each, as the network is
