@@ -167,7 +167,17 @@ typedef struct sdd_bvh_desc {
  *   glass_from, glass_to: material substitution for this render (photochromic
  *     states): pane triangles of GLASS_SLAB material glass_from are traced as
  *     GLASS_SLAB material glass_to.  Inactive when equal (e.g. both 0).
- * W * H * spp must be below 2^31.
+ *   crop_x0, crop_y0, crop_w, crop_h: a window of the W x H frame (all 0: the
+ *     whole frame).  Only its pixels are traced; each keeps the camera ray and
+ *     the random numbers of its place p in the frame, so a window's pixels
+ *     equal the same pixels of a whole-frame render.  The render's
+ *     accumulator, the logs and sdd_resolve_image then cover the window
+ *     ([crop_h][crop_w] pixels, row-major), and the render's paths (and the
+ *     radiance cache's training paths, SDD_TRACE_NRC) are numbered over the
+ *     window's pixels: sample s of window pixel i is path s * crop_w * crop_h + i.
+ *     SDD_ERR_INVALID_ARG unless 0 <= crop_x0, crop_x0 + crop_w <= W, and
+ *     likewise for y, with crop_w, crop_h both 0 or both > 0.
+ * (window pixels) * spp must be below 2^31.
  */
 typedef struct sdd_trace_desc {
     double eye[3], target[3];
@@ -183,6 +193,7 @@ typedef struct sdd_trace_desc {
     int32_t *hit_log;
     int32_t *shadow_log;
     int32_t glass_from, glass_to;
+    int32_t crop_x0, crop_y0, crop_w, crop_h;
 } sdd_trace_desc;
 
 /* Counters (sdd_get_stats); synchronises the context stream. */

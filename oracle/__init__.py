@@ -46,7 +46,7 @@ class Args(C.Structure):
         ("ortho", C.c_int), ("ortho_half_h", C.c_double),
         ("W", C.c_int), ("H", C.c_int), ("spp", C.c_int), ("sample_offset", C.c_int), ("max_depth", C.c_int),
         ("seed", C.c_uint32), ("render_id", C.c_uint32), ("use_bvh", C.c_int), ("n_threads", C.c_int),
-        ("n_pix", C.c_int), ("pix", C.c_void_p),
+        ("n_pix", C.c_int), ("pix", C.c_void_p), ("window", C.c_int),
         ("nrc", C.c_int), ("nrc_stride", C.c_uint32), ("nrc_c", C.c_double * 7), ("nrc_lo", C.c_double * 3),
         ("nrc_hi", C.c_double * 3),
     ]
@@ -164,10 +164,13 @@ def make_args(camera, W, H, spp, max_depth, seed=0, render_id=0, sample_offset=0
 
 def render(scene, W, H, spp, max_depth, *, camera=None, seed=0, render_id=0, sample_offset=0,
            use_bvh=True, n_threads=0, pix=None, logs=False, path_L=False, first_hit=False,
-           oscene=None, nrc=None):
+           oscene=None, nrc=None, crop=None):
     """Render with the oracle.  Returns a dict of numpy arrays.
 
     ``pix``: optional list of pixel indices p = py*W + px (outputs follow it).
+    ``crop``: optional window (x0, y0, w, h) of the frame: its pixels in row-major
+    order, with the render's paths numbered over the window (as a window
+    render numbers them); excludes ``pix``.
     ``nrc``: optional dict(stride, c (7 coefficients), lo, hi) selecting the
     radiance-cache estimator with the closed-form cache c0 + c[1:4].xn + c[4:7].n;
     the result then also holds ``nrc_rows`` [n_out][spp][D-1][9].
@@ -176,6 +179,11 @@ def render(scene, W, H, spp, max_depth, *, camera=None, seed=0, render_id=0, sam
     cam = camera or scene["camera"]
     a = make_args(cam, W, H, spp, max_depth, seed, render_id, sample_offset, use_bvh, n_threads)
     pix_arr = None
+    if crop is not None:
+        x0, y0, cw, ch = (int(v) for v in crop)
+        ys, xs = np.meshgrid(np.arange(y0, y0 + ch), np.arange(x0, x0 + cw), indexing="ij")
+        pix = (ys * W + xs).ravel()
+        a.window = 1
     if pix is not None:
         pix_arr = np.ascontiguousarray(pix, dtype=np.int32)
         a.n_pix, a.pix = len(pix_arr), _ptr(pix_arr)

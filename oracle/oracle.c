@@ -555,11 +555,12 @@ static int any_nonzero(const float *v, int n) {
  * sample of a diffuse vertex d (shadow origin, unit direction, length, cos at
  * the vertex, cos at the light); NaN where a quantity does not arise. */
 static void trace_path(const ora_scene *sc, const ora_accel *acc, const ora_args *ar, int px, int py,
-                       uint32_t s, double *L, int32_t *hlog, int32_t *slog, double *fhit,
+                       uint32_t s, uint64_t q, double *L, int32_t *hlog, int32_t *slog, double *fhit,
                        double *beta, double *tmp_T, int64_t *n_ext, int64_t *n_sh, double *rows, double *probe) {
     const int nl = sc->n_lambda, D = ar->max_depth;
     const uint32_t p = (uint32_t)(py * ar->W + px);
-    const int train = ar->nrc && ((uint64_t)s * (uint64_t)ar->W * (uint64_t)ar->H + p) % ar->nrc_stride == 0;
+    /* q: the path's number in the render (frame or window numbering) */
+    const int train = ar->nrc && q % ar->nrc_stride == 0;
     /* per training row: estimate and throughput at its wavelength when recorded */
     double row_L[64], row_b[64];
     int row_l[64];
@@ -746,8 +747,10 @@ int ora_render(const ora_scene *sc, const ora_accel *acc, const ora_args *ar, or
                 if (sl) for (int d = 0; d < D; ++d) sl[d] = -2;
                 double *fh = out->first_hit ? out->first_hit + slot * 3 : NULL;
                 double *rw = out->nrc_rows ? out->nrc_rows + slot * (size_t)(D - 1) * 9 : NULL;
-                trace_path(sc, a, ar, px, py, (uint32_t)(ar->sample_offset + j), L, hl, sl, fh, beta, tmpT,
-                           &n_ext, &n_sh, rw, NULL);
+                const uint32_t s = (uint32_t)(ar->sample_offset + j);
+                const uint64_t q = ar->window ? (uint64_t)s * (uint64_t)n_out + (uint64_t)i
+                                              : (uint64_t)s * (uint64_t)ar->W * (uint64_t)ar->H + (uint64_t)p;
+                trace_path(sc, a, ar, px, py, s, q, L, hl, sl, fh, beta, tmpT, &n_ext, &n_sh, rw, NULL);
                 if (out->path_L) memcpy(out->path_L + slot * nl, L, sizeof(double) * (size_t)nl);
                 for (int l = 0; l < nl; ++l) acc_l[l] += L[l];
             }
@@ -784,7 +787,8 @@ int ora_probe_paths(const ora_scene *sc, const ora_accel *acc, const ora_args *a
         for (int i = 0; i < n; ++i) {
             const int p = pix[i];
             if (p < 0 || p >= ar->W * ar->H) { rc = -1; continue; }
-            trace_path(sc, a, ar, p % ar->W, p / ar->W, (uint32_t)samp[i], L, NULL, NULL, NULL, beta, tmpT, &ne,
+            const uint64_t q = (uint64_t)(uint32_t)samp[i] * (uint64_t)ar->W * (uint64_t)ar->H + (uint64_t)p;
+            trace_path(sc, a, ar, p % ar->W, p / ar->W, (uint32_t)samp[i], q, L, NULL, NULL, NULL, beta, tmpT, &ne,
                        &ns, NULL, out + (size_t)i * D * ORA_PROBE_STRIDE);
         }
         free(L); free(beta); free(tmpT);

@@ -80,11 +80,15 @@ typedef struct ora_args {
     int n_threads;           /* <= 0: OpenMP default */
     int n_pix;               /* > 0: render only the listed pixels */
     const int32_t *pix;      /* [n_pix] pixel indices p = py*W + px */
+    int window;              /* 1: pix lists a window of the frame in row-major order and the render's
+                                paths are numbered over it (sample s of listed pixel i is path
+                                s * n_pix + i); 0: paths are numbered over the frame, s * W * H + p */
     /* radiance-cache estimator (nrc != 0) with a closed-form cache
      * L(x, n) = c[0] + c[1..3] . xn + c[4..6] . n, xn = clip((x - lo) / (hi - lo), 0, 1):
-     * training paths ((s W H + p) % nrc_stride == 0) are traced as without
-     * it; any other path ends at its first diffuse vertex of depth >= 2 after
-     * that vertex's light sample, adding beta * L(x, n). */
+     * training paths (path number % nrc_stride == 0, the path numbered as
+     * `window` says) are traced as without it; any other path ends at its first
+     * diffuse vertex of depth >= 2 after that vertex's light sample, adding
+     * beta * L(x, n). */
     int nrc;
     uint32_t nrc_stride;
     double nrc_c[7];

@@ -66,6 +66,7 @@ class TraceDesc(C.Structure):
         ("W", C.c_int32), ("H", C.c_int32), ("spp", C.c_int32), ("sample_offset", C.c_int32),
         ("max_depth", C.c_int32), ("seed", C.c_uint32), ("render_id", C.c_int32), ("flags", C.c_uint32),
         ("hit_log", C.c_void_p), ("shadow_log", C.c_void_p), ("glass_from", C.c_int32), ("glass_to", C.c_int32),
+        ("crop_x0", C.c_int32), ("crop_y0", C.c_int32), ("crop_w", C.c_int32), ("crop_h", C.c_int32),
     ]
 
 
@@ -275,7 +276,7 @@ class Tracer:
         self._check(lib().sdd_build_bvh(self.h, C.byref(BvhDesc(nx, ny, nz, leaf_max, sah_bins, int(bool(device))))))
 
     def _desc(self, camera, W, H, spp, max_depth, seed=0, render_id=0, sample_offset=0, time_kernels=False,
-              count_work=False, hit_log=None, shadow_log=None, glass_swap=None, nrc=False, graph=False):
+              count_work=False, hit_log=None, shadow_log=None, glass_swap=None, nrc=False, graph=False, crop=None):
         d = TraceDesc()
         d.eye[:] = [float(x) for x in camera["eye"]]
         d.target[:] = [float(x) for x in camera["target"]]
@@ -295,7 +296,10 @@ class Tracer:
         if graph:
             fl |= TRACE_GRAPH
         d.flags = fl
-        n_slots = int(W) * int(H) * int(spp) * int(max_depth)
+        if crop is not None:
+            d.crop_x0, d.crop_y0, d.crop_w, d.crop_h = (int(v) for v in crop)
+        npix = int(W) * int(H) if crop is None else int(crop[2]) * int(crop[3])
+        n_slots = npix * int(spp) * int(max_depth)
         for name, t in (("hit_log", hit_log), ("shadow_log", shadow_log)):
             if t is not None:
                 if not (t.is_cuda and t.dtype == self.torch.int32 and t.is_contiguous() and t.numel() == n_slots):
@@ -306,13 +310,15 @@ class Tracer:
 
     def trace_spectral(self, camera, W, H, spp, max_depth, *, seed=0, render_id=0, sample_offset=0,
                        time_kernels=False, count_work=False, hit_log=None, shadow_log=None, glass_swap=None,
-                       nrc=False, graph=False):
+                       nrc=False, graph=False, crop=None):
         """Trace spp samples of every pixel; glass_swap = (from_material, to_material) substitutes a
         glass material for this render (photochromic state); nrc=True uses the radiance cache
         (paths end in the cache, training paths train it after the call); graph=True captures the
-        call's launches in a HIP graph replayed by later calls that differ only in sample_offset."""
+        call's launches in a HIP graph replayed by later calls that differ only in sample_offset; crop =
+        (x0, y0, w, h) traces only that window of the W x H frame (logs and resolve_image then cover the
+        window: pass w, h there)."""
         d = self._desc(camera, W, H, spp, max_depth, seed, render_id, sample_offset, time_kernels, count_work,
-                       hit_log, shadow_log, glass_swap, nrc, graph)
+                       hit_log, shadow_log, glass_swap, nrc, graph, crop)
         self._check(lib().sdd_trace_spectral(self.h, C.byref(d)))
 
     def trace_batch(self, renders, max_depth, *, seed=0, time_kernels=False, count_work=False, graph=False):

@@ -40,7 +40,8 @@ using namespace sdd;
 namespace {
 
 struct Render {
-    int W = 0, H = 0;
+    int W = 0, H = 0;      // accumulator size: the render's window
+    int fW = 0, fH = 0, x0 = 0, y0 = 0;  // its frame and the window's place in it
     float* acc = nullptr;  // [nl][W*H] FP32
     int* ovf = nullptr;    // overflow bits (kOverflow*) of every call that traced this render
     long long spp_done = 0;
@@ -1300,21 +1301,33 @@ sdd_status nrc_train_after_call(sdd_ctx* c, long long n_rows, bool timing) {
 struct Job {
     const sdd_trace_desc* t = nullptr;
     Render* rd = nullptr;
-    int WH = 0;
-    long long total = 0;  // W * H * spp paths
+    int WH = 0;            // pixels of the render's window
+    PixWindow win{};
+    long long total = 0;  // WH * spp paths
     long long start = 0;  // first index in the call's path space (multiple of kShadeBlock)
     double f[3], r[3], u[3];
     bool ortho = false;
     int glass_from = -1, glass_to = -1;  // compact glass indices of the substitution
 };
 
+// pixels a render traces: its window, or the whole frame
+long long window_pixels(const sdd_trace_desc* t) {
+    return t->crop_w != 0 ? (long long)t->crop_w * t->crop_h : (long long)t->W * t->H;
+}
+
 // argument checks and camera basis of one render (no device work)
 sdd_status check_desc(sdd_ctx* c, const sdd_trace_desc* t, Job& j) {
     if (!t) return fail(c, SDD_ERR_INVALID_ARG, "null trace desc");
     if (t->W <= 0 || t->H <= 0 || t->spp <= 0) return fail(c, SDD_ERR_INVALID_ARG, "W, H and spp must be > 0");
     if ((long long)t->W * t->H > (1LL << 28)) return fail(c, SDD_ERR_INVALID_ARG, "image too large");
-    if ((long long)t->W * t->H * t->spp >= (1LL << 31))
-        return fail(c, SDD_ERR_INVALID_ARG, "W * H * spp must be < 2^31 per call");
+    const bool crop = t->crop_w != 0 || t->crop_h != 0;
+    if (crop && (t->crop_w <= 0 || t->crop_h <= 0 || t->crop_x0 < 0 || t->crop_y0 < 0 ||
+                 (long long)t->crop_x0 + t->crop_w > t->W || (long long)t->crop_y0 + t->crop_h > t->H))
+        return fail(c, SDD_ERR_INVALID_ARG, "crop window outside the frame");
+    if (!crop && (t->crop_x0 != 0 || t->crop_y0 != 0))
+        return fail(c, SDD_ERR_INVALID_ARG, "crop origin without a crop size");
+    if (window_pixels(t) * t->spp >= (1LL << 31))
+        return fail(c, SDD_ERR_INVALID_ARG, "window pixels * spp must be < 2^31 per call");
     if (t->max_depth < 1 || t->max_depth > SDD_MAX_DEPTH) return fail(c, SDD_ERR_INVALID_ARG, "max_depth out of range");
     if (t->render_id < 0) return fail(c, SDD_ERR_INVALID_ARG, "render_id must be >= 0");
     if (t->sample_offset < 0) return fail(c, SDD_ERR_INVALID_ARG, "sample_offset must be >= 0");
@@ -1343,7 +1356,8 @@ sdd_status check_desc(sdd_ctx* c, const sdd_trace_desc* t, Job& j) {
         j.glass_to = c->glass_of[b];
     }
     j.t = t;
-    j.WH = t->W * t->H;
+    j.WH = (int)window_pixels(t);
+    j.win = crop ? PixWindow{t->W, t->crop_x0, t->crop_y0, t->crop_w} : PixWindow{t->W, 0, 0, 0};
     j.total = (long long)j.WH * t->spp;
     return SDD_OK;
 }
@@ -1448,6 +1462,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
             cp.W = t->W;
             cp.H = t->H;
             cp.WH = sg.j->WH;
+            cp.win = sg.j->win;
             cp.s0 = t->sample_offset;
             cp.s0p = s0_dev ? s0_dev + (sg.j - jobs.data()) : nullptr;
             cp.key = make_uint2(t->seed, (uint32_t)t->render_id);
@@ -1525,6 +1540,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
                 sp.fwh = make_fastdiv((uint32_t)sg.j->WH);
                 sp.W = t->W;
                 sp.WH = sg.j->WH;
+                sp.win = sg.j->win;
                 sp.s0 = t->sample_offset;
                 sp.s0p = s0_dev ? s0_dev + (sg.j - jobs.data()) : nullptr;
                 sp.spp_call = t->spp;
@@ -1610,6 +1626,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
                     rp.pid_off = sg.pid_off;
                     rp.N_all = N;
                     rp.WH = sg.j->WH;
+                    rp.win = sg.j->win;
                     rp.s0 = t->sample_offset;
                     rp.key = make_uint2(t->seed, (uint32_t)t->render_id);
                     rp.max_depth = D;
@@ -1656,13 +1673,21 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
 // the accumulator of render_id (created on first use)
 sdd_status render_for(sdd_ctx* c, const sdd_trace_desc* t, Render*& out) {
     auto it = c->renders.find(t->render_id);
-    if (it != c->renders.end() && (it->second.W != t->W || it->second.H != t->H))
-        return fail(c, SDD_ERR_INVALID_ARG, "render_id reused with a different W, H");
+    const bool crop = t->crop_w != 0;
+    const int ww = crop ? t->crop_w : t->W, wh = crop ? t->crop_h : t->H;
+    const int x0 = crop ? t->crop_x0 : 0, y0 = crop ? t->crop_y0 : 0;
+    if (it != c->renders.end() && (it->second.fW != t->W || it->second.fH != t->H || it->second.W != ww ||
+                                   it->second.H != wh || it->second.x0 != x0 || it->second.y0 != y0))
+        return fail(c, SDD_ERR_INVALID_ARG, "render_id reused with a different W, H or window");
     if (it == c->renders.end()) {
         Render rd;
-        rd.W = t->W;
-        rd.H = t->H;
-        const size_t n = (size_t)c->nlp * t->W * t->H;
+        rd.W = ww;
+        rd.H = wh;
+        rd.fW = t->W;
+        rd.fH = t->H;
+        rd.x0 = x0;
+        rd.y0 = y0;
+        const size_t n = (size_t)c->nlp * ww * wh;
         ++c->gen;
         sdd_status st = dalloc(c, &rd.acc, n);
         if (st != SDD_OK) return st;
@@ -1848,7 +1873,7 @@ std::string tune_key(const sdd_ctx* c, int n, const sdd_trace_desc* d) {
     long long paths = 0;
     uint32_t fl = 0;
     for (int i = 0; i < n; ++i) {
-        paths += (long long)d[i].W * d[i].H * d[i].spp;
+        paths += window_pixels(&d[i]) * d[i].spp;
         fl |= d[i].flags & (SDD_TRACE_COUNT_WORK | SDD_TRACE_GRAPH);
     }
     std::ostringstream k;
@@ -1948,7 +1973,7 @@ sdd_status search_tuning(sdd_ctx* c, int n, const sdd_trace_desc* descs, int rep
     {
         std::vector<Job> jobs((size_t)n);
         for (int i = 0; i < n; ++i) jobs[i].t = &descs[i];
-        for (int i = 0; i < n; ++i) jobs[i].total = (long long)descs[i].W * descs[i].H * descs[i].spp;
+        for (int i = 0; i < n; ++i) jobs[i].total = window_pixels(&descs[i]) * descs[i].spp;
         const long long keep = c->tune_batch;
         c->tune_batch = 0;
         c->call_budget = mem_budget_bytes(c);

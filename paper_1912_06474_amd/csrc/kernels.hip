@@ -115,9 +115,10 @@ __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
         const uint32_t q = (uint32_t)(P.pb + lpid);
         const uint32_t qs = fdiv(q, P.fwh);
         const int s = (P.s0p ? *P.s0p : P.s0) + P.sb + (int)qs;
-        const int p = (int)(q - qs * (uint32_t)P.WH);
-        const int py = (int)(p / (unsigned)P.W), px = p - py * P.W;
-        const uint4 r = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, 0u, 0u), P.key);
+        const int p = (int)(q - qs * (uint32_t)P.WH);  // window pixel (path numbering, training rule)
+        const int pf = frame_pixel(P.win, p);            // frame pixel (camera ray, random numbers)
+        const int py = (int)(pf / (unsigned)P.W), px = pf - py * P.W;
+        const uint4 r = philox4x32_10(make_uint4((uint32_t)pf, (uint32_t)s, 0u, 0u), P.key);
         // the ray in FP64 (path state); traversal gets its FP32 rounding
         const double x = (double)px + (double)u01(r.x), y = (double)py + (double)u01(r.y);
         const double sx = 2.0 * x / (double)P.W - 1.0, sy = 1.0 - 2.0 * y / (double)P.H;
@@ -595,6 +596,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
             const int s0 = P.s0p ? *P.s0p : P.s0;
             const int s = s0 + P.sb + (int)qs;
             const int p = (int)(q - qs * (uint32_t)P.WH);
+            const int pf = frame_pixel(P.win, p);
             prim = __float_as_int(h.y);
             if (P.hit_log) P.hit_log[((long long)p * P.spp_call + (s - s0)) * P.max_depth + P.depth - 1] = prim;
             const bool last_depth = P.depth == P.max_depth;
@@ -626,7 +628,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                     rec.x = ((fl & kCountE) && cos_o > 0.0) ? (kVEmit | kVLast | (m << kVIdShift)) : kVNone;
                     fl = 0;
                 } else if (typ == kDiffuse) {
-                    const uint4 ub = philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, (uint32_t)P.depth, 0u), P.key);
+                    const uint4 ub = philox4x32_10(make_uint4((uint32_t)pf, (uint32_t)s, (uint32_t)P.depth, 0u), P.key);
                     xo64 = x + n * (double)kOffset;
                     xo = narrow(xo64);
                     float gfac = 0.0f;
@@ -676,7 +678,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                         fl = 0;
                     } else {
                         const uint4 uc =
-                            philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, (uint32_t)P.depth, 1u), P.key);
+                            philox4x32_10(make_uint4((uint32_t)pf, (uint32_t)s, (uint32_t)P.depth, 1u), P.key);
                         dn64 = cosine_dir64(n, (double)u01(uc.x), (double)u01(uc.y));
                         enq_e = true;
                     }
@@ -697,7 +699,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                     } else {
                         const float PR = sumR / (sumR + sumT);
                         const uint4 ub =
-                            philox4x32_10(make_uint4((uint32_t)p, (uint32_t)s, (uint32_t)P.depth, 0u), P.key);
+                            philox4x32_10(make_uint4((uint32_t)pf, (uint32_t)s, (uint32_t)P.depth, 0u), P.key);
                         const bool refl = u01(ub.z) < PR;
                         rec = make_int4((refl ? kVGlassR : kVGlassT) | (m << kVIdShift), __float_as_int(c),
                                         __float_as_int(PR), 0);
@@ -974,7 +976,7 @@ __global__ __launch_bounds__(256) void k_nrc_rows(NrcRowParams P) {
     const long long j = P.j0 + i;
     const long long qc = P.r + j * (long long)P.stride;
     const int pid = P.pid_off + (int)(qc - P.q0);
-    const int s = P.s0 + (int)(qc / P.WH), p = (int)(qc % P.WH);
+    const int s = P.s0 + (int)(qc / P.WH), p = frame_pixel(P.win, (int)(qc % P.WH));
     const int D = P.max_depth;
     bool live = true;
     for (int v = 0; v < D; ++v) {

@@ -85,6 +85,21 @@ inline FastDiv make_fastdiv(uint32_t d) {
 }
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) { return (__umulhi(n, f.m) + n) >> f.l; }
 
+// A render traces the pixels of a window of its frame: the paths, the
+// accumulator and the logs are numbered over the window's pixels, while the
+// camera ray and the random numbers belong to the pixel's place in the frame.
+struct PixWindow {
+    int fw;      // frame width
+    int x0, y0;  // window origin in the frame
+    int cw;      // window width; 0: the window is the whole frame
+};
+// frame pixel index of window pixel pl
+__host__ __device__ inline int frame_pixel(const PixWindow& w, int pl) {
+    if (w.cw == 0) return pl;
+    const int ly = pl / w.cw;
+    return (w.y0 + ly) * w.fw + w.x0 + (pl - ly * w.cw);
+}
+
 // FP64 vector of the per-path ray state (32 B, w unused)
 struct alignas(32) D4 {
     double x, y, z, w;
@@ -186,8 +201,9 @@ struct ShadeParams {
     int pid_off;           // its first path in the batch (a multiple of kShadeBlock)
     int glass_from, glass_to;  // compact glass index substituted for this render (-1: none)
     int pb, sb;            // pixel and sample of the batch's first path
-    FastDiv fwh;           // division by W * H
-    int W, WH;
+    FastDiv fwh;           // division by WH
+    int W, WH;             // frame width; pixels of the render's window
+    PixWindow win;
     int s0;                // first sample index of this call
     const int* s0p;        // if set, read the first sample index here (graph replays)
     int spp_call;
@@ -228,7 +244,8 @@ struct CamParams {
     int pid_off;           // its first path in the batch (a multiple of kShadeBlock)
     int pb, sb;
     FastDiv fwh;
-    int W, H, WH;
+    int W, H, WH;          // frame size (camera); pixels of the render's window
+    PixWindow win;
     int s0;
     const int* s0p;        // if set, read the first sample index here (graph replays)
     uint2 key;
@@ -324,7 +341,8 @@ struct NrcRowParams {
     long long q0;          // call path index of the segment's first path
     int pid_off;           // batch position of that path
     int N_all;
-    int WH, s0;
+    int WH, s0;            // pixels of the render's window
+    PixWindow win;
     uint2 key;
     int max_depth, nl, nlp, n_glass, n_mats;
     int glass_from, glass_to;

@@ -1,7 +1,9 @@
 """GPU parity of coated (electrochromic) panes: the device characteristic-matrix
 evaluation against the FP64 oracle, fixture and room renders, and the
-4M-triangle, 81-wavelength electrochromic room on 8 x 4 x 4 subdomains at its
-full 3840 x 2160 frame (sampled pixels)."""
+4M-triangle, 81-wavelength electrochromic room on 8 x 4 x 4 subdomains: its
+full 3840 x 2160 frame at 1 spp (sampled pixels), and a 256 x 144 window of
+that frame at the workload's 64 spp, plain and with the radiance cache,
+against the oracle element by element."""
 import numpy as np
 import pytest
 
@@ -95,17 +97,98 @@ def test_coated_tiny_room_parity(tracer):
     assert_parity(g, o, ParityCtx(sc, 64, 64, 2, 6, seed=3))
 
 
-def test_electrochromic_room_full_frame_sampled(tracer):
+@pytest.fixture(scope="module")
+def c4():
+    """The large electrochromic workload's scene and the oracle's view of it
+    (its BVH is built once for every test here)."""
+    sc = sg.electrochromic_room()
+    print(f"[electrochromic] {len(sc['tris'])} tris, {len(sc['lambda_nm'])} lambda", flush=True)
+    return sc, ora.OracleScene(sc)
+
+
+C4_FRAME = (3840, 2160)
+C4_CROP = (1376, 912, 256, 144)   # a window of the frame whose paths reach the panes
+C4_GRID = (8, 4, 4)
+
+
+def _crop_pixels(crop, W):
+    x0, y0, cw, ch = crop
+    ys, xs = np.meshgrid(np.arange(y0, y0 + ch), np.arange(x0, x0 + cw), indexing="ij")
+    return (ys * W + xs).ravel().astype(np.int32)
+
+
+def test_electrochromic_room_full_frame_sampled(tracer, c4):
     # the large workload's geometry, wavelengths, grid and frame; 1 spp keeps
     # the logs of every pixel within memory
-    sc = sg.electrochromic_room()
-    W, H, spp, D = 3840, 2160, 1, 8
-    print(f"[electrochromic] {len(sc['tris'])} tris, {len(sc['lambda_nm'])} lambda", flush=True)
-    g = gpu_render(tracer, sc, W, H, spp, D, (8, 4, 4))
+    sc, osc = c4
+    (W, H), spp, D = C4_FRAME, 1, 8
+    g = gpu_render(tracer, sc, W, H, spp, D, C4_GRID)
     st = tracer.stats()
     assert st["overflow"] == 0
     rng = np.random.default_rng(11)
     pix = np.sort(rng.choice(W * H, 4096, replace=False)).astype(np.int32)
-    o = ora.render(sc, W, H, spp, D, pix=pix, logs=True)
-    assert_parity({k: v[pix] for k, v in g.items()}, o, ParityCtx(sc, W, H, spp, D, pix=pix))
+    o = ora.render(sc, W, H, spp, D, pix=pix, logs=True, oscene=osc)
+    assert (o["spectral"].max(1) > 0).mean() > 0.03            # the sky reaches part of the frame
+    assert_parity({k: v[pix] for k, v in g.items()}, o, ParityCtx(sc, W, H, spp, D, pix=pix, oscene=osc))
     assert np.isfinite(g["spectral"]).all() and (g["spectral"] >= 0).all()
+
+
+def _crop_render(tracer, sc, spp, D, nrc=False):
+    (W, H), (x0, y0, cw, ch) = C4_FRAME, C4_CROP
+    hl = tracer.new_log(cw, ch, spp, D)
+    sl = tracer.new_log(cw, ch, spp, D)
+    print(f"[electrochromic] crop {C4_CROP} of {W}x{H}, {spp} spp, D={D}, cache={nrc}", flush=True)
+    tracer.trace_spectral(sc["camera"], W, H, spp, D, render_id=0, hit_log=hl, shadow_log=sl, crop=C4_CROP,
+                          nrc=nrc)
+    s, x = tracer.resolve_image(0, cw, ch)
+    out = dict(spectral=s.cpu().numpy(), xyz=x.cpu().numpy(), hit_log=hl.cpu().numpy(), shadow_log=sl.cpu().numpy())
+    tracer.reset_render(0)
+    return out
+
+
+def test_electrochromic_crop_64spp_plain(tracer, c4):
+    """The 256 x 144 window of the 3840 x 2160 frame at the workload's 64 spp,
+    81 wavelengths, 4M triangles, 8 x 4 x 4 subdomains, against the oracle
+    element by element."""
+    sc, osc = c4
+    (W, H), spp, D = C4_FRAME, 64, 8
+    tracer.load_scene(sc)
+    tracer.build_bvh(*C4_GRID)
+    g = _crop_render(tracer, sc, spp, D)
+    assert tracer.stats()["overflow"] == 0
+    o = ora.render(sc, W, H, spp, D, crop=C4_CROP, logs=True, oscene=osc)
+    glass = np.flatnonzero(np.asarray(sc["mat_type"])[np.asarray(sc["tri_mat"])] == sg.GLASS)
+    n_glass = int(np.isin(o["hit_log"], glass).sum())
+    lit = float((o["spectral"].max(1) > 0).mean())
+    print(f"[electrochromic] crop: {n_glass} pane hits, {lit:.3f} of pixels lit", flush=True)
+    assert n_glass > 0 and lit > 0.2
+    assert_parity(g, o, ParityCtx(sc, W, H, spp, D, pix=_crop_pixels(C4_CROP, W), oscene=osc))
+
+
+def test_electrochromic_crop_64spp_cache(tracer, c4):
+    """The same window rendered with the radiance cache (a network built to
+    evaluate a closed-form cache, so the oracle's estimator sees the same
+    cache): logs, radiance and training rows against the oracle."""
+    from test_gpu_nrc_render import COEF, HI, LO, _oracle_rows, affine_net
+    sc, osc = c4
+    (W, H), spp, D = C4_FRAME, 64, 8
+    cw, ch = C4_CROP[2], C4_CROP[3]
+    train_paths = 1 << 14
+    tracer.load_scene(sc)
+    tracer.build_bvh(*C4_GRID)
+    params, tables = affine_net(COEF)
+    tracer.nrc_init(params, tables, LO, HI, train_paths=train_paths, train_steps=0, precision="fp32")
+    g = _crop_render(tracer, sc, spp, D, nrc=True)
+    rows, _, _ = tracer.nrc_last_rows()
+    stride = -(-(cw * ch * spp) // train_paths)
+    o = ora.render(sc, W, H, spp, D, crop=C4_CROP, logs=True, oscene=osc,
+                   nrc=dict(stride=stride, c=COEF, lo=LO, hi=HI))
+    assert_parity(g, o, ParityCtx(sc, W, H, spp, D, pix=_crop_pixels(C4_CROP, W), oscene=osc))
+    orows = _oracle_rows(o, cw, ch, spp)
+    print(f"[electrochromic] cache crop: stride {stride}, {len(rows)} training rows (oracle {len(orows)})",
+          flush=True)
+    assert len(rows) == len(orows) and len(rows) > 0
+    assert np.array_equal(rows[:, 3], orows[:, 4].astype(np.float32))
+    assert np.abs(rows[:, 0:3] - orows[:, 1:4]).max() <= 1e-5
+    t, to = rows[:, 7].astype(np.float64), orows[:, 8]
+    assert (np.abs(t - to) / (np.abs(to) + 1e-6)).max() <= 1e-4

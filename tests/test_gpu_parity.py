@@ -294,3 +294,32 @@ def test_overflow_flag_is_per_render_and_names_its_cause(sdd):
     assert (s5.cpu().numpy() > 0).any()
     assert t.stats()["overflow"] == 0
     t.close()
+
+
+def test_window_render_equals_the_frame_render(tracer):
+    """A window of the frame (sdd_trace_desc crop) traces its pixels exactly as
+    the whole-frame render does: same camera rays and random numbers, so the
+    same logs and the same radiance bit for bit; and it matches the oracle's
+    window render."""
+    sc = sg.tiny_room()
+    W, H, spp, D = 64, 48, 2, 4
+    crop = (9, 17, 23, 13)
+    full = gpu_render(tracer, sc, W, H, spp, D, grid=(2, 2, 1))
+    tracer.reset_render(0)          # the window render takes the same render id (the same Philox key)
+    hl = tracer.new_log(crop[2], crop[3], spp, D)
+    sl = tracer.new_log(crop[2], crop[3], spp, D)
+    tracer.trace_spectral(sc["camera"], W, H, spp, D, render_id=0, hit_log=hl, shadow_log=sl, crop=crop)
+    s, x = tracer.resolve_image(0, crop[2], crop[3])
+    tracer.reset_render(0)
+    ys, xs = np.meshgrid(np.arange(crop[1], crop[1] + crop[3]), np.arange(crop[0], crop[0] + crop[2]), indexing="ij")
+    pix = (ys * W + xs).ravel()
+    assert np.array_equal(s.cpu().numpy(), full["spectral"][pix])
+    assert np.array_equal(hl.cpu().numpy(), full["hit_log"][pix])
+    assert np.array_equal(sl.cpu().numpy(), full["shadow_log"][pix])
+    o = ora.render(sc, W, H, spp, D, crop=crop, logs=True)
+    g = dict(spectral=s.cpu().numpy(), xyz=x.cpu().numpy(), hit_log=hl.cpu().numpy(), shadow_log=sl.cpu().numpy())
+    assert_parity(g, o, ParityCtx(sc, W, H, spp, D, pix=pix))
+    import paper_1912_06474_amd as m
+    for bad in ((60, 0, 5, 5), (0, 0, 0, 5), (-1, 0, 4, 4)):
+        with pytest.raises(m.SddError, match="INVALID_ARG"):
+            tracer.trace_spectral(sc["camera"], W, H, 1, D, render_id=4, crop=bad)

@@ -299,3 +299,29 @@ def test_every_path_training_is_the_plain_render(room):
     assert np.array_equal(o["path_L"], plain[D_ROOM]["path_L"])
     assert np.array_equal(o["spectral"], plain[D_ROOM]["spectral"])
     assert np.array_equal(o["hit_log"], plain[D_ROOM]["hit_log"])
+
+
+def test_window_render_traces_the_frame_pixels():
+    """A window render (crop) traces each of its pixels as the frame does (same
+    camera ray and random numbers); with the cache its training paths are
+    numbered over the window: sample s of window pixel i is path s * n + i."""
+    sc = sg.tiny_room(0, 16)
+    W, H, spp, D = 32, 24, 3, 4
+    crop = (5, 7, 11, 6)
+    ys, xs = np.meshgrid(np.arange(7, 13), np.arange(5, 16), indexing="ij")
+    pix = (ys * W + xs).ravel()
+    a = ora.render(sc, W, H, spp, D, crop=crop, logs=True, path_L=True)
+    b = ora.render(sc, W, H, spp, D, pix=pix, logs=True, path_L=True)
+    assert np.array_equal(a["path_L"], b["path_L"]) and np.array_equal(a["hit_log"], b["hit_log"])
+    n = len(pix)
+    stride = 7
+    c = ora.render(sc, W, H, spp, D, crop=crop, path_L=True, logs=True, nrc=_nrc(stride, 0.0))
+    s, i = np.meshgrid(np.arange(spp), np.arange(n))
+    train = (s * n + i) % stride == 0                     # [pixel, sample]
+    # training paths are the plain ones; the others end at their cache vertex (zero cache here)
+    assert np.array_equal(c["path_L"][train], a["path_L"][train])
+    mt = sc["mat_type"][sc["tri_mat"]]
+    cut = [(p, q) for p in range(n) for q in range(spp)
+           if not train[p, q] and _first_cache_depth(a["hit_log"][p, q], mt) and
+           _first_cache_depth(a["hit_log"][p, q], mt) < D]
+    assert cut and all((c["hit_log"][p, q, _first_cache_depth(a["hit_log"][p, q], mt):] == -2).all() for p, q in cut)
