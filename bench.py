@@ -505,7 +505,10 @@ def plain_line(args, workload, wl, scene, tr, build_s, cpu_s):
         res["work"] = {"node_visits_per_cell_visit": sw["node_visits"] / max(1, visits),
                        "tri_tests_per_cell_visit": sw["tri_tests"] / max(1, visits),
                        "cell_visits_per_ray": visits / max(1, sw["ext_rays"] + sw["shadow_rays"]),
-                       "scene_bytes_per_frame": 64 * sw["node_visits"] + 48 * sw["tri_tests"]}
+                       "scene_bytes_per_frame": 64 * sw["node_visits"] + 48 * sw["tri_tests"],
+                       # lanes busy per wave step of the traversal's node loop and triangle loop
+                       "node_loop_lane_utilisation": sw["node_visits"] / max(1, 64 * sw["wave_node_steps"]),
+                       "tri_loop_lane_utilisation": sw["tri_tests"] / max(1, 64 * sw["wave_tri_steps"])}
     if args.graph:
         import paper_1912_06474_amd as sdd
         gt = sdd.Tracer(stream=torch.cuda.Stream())  # graph capture needs a stream other than the null stream

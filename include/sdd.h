@@ -227,6 +227,10 @@ typedef struct sdd_stats {
     int64_t nrc_query_rows;    /* (path, wavelength) cache queries */
     int64_t nrc_query_launches;
     int64_t nrc_train_rows;    /* rows of the Adam steps */
+    int64_t wave_node_steps;   /* node steps of traversal waves, counted once per wave however many
+                                  of its lanes took one (SDD_TRACE_COUNT_WORK): node_visits /
+                                  (64 wave_node_steps) is the node loop's lane utilisation */
+    int64_t wave_tri_steps;    /* triangle-test steps of traversal waves, likewise (SDD_TRACE_COUNT_WORK) */
 } sdd_stats;
 
 /* Create a context on HIP device hip_device.  hip_stream is the hipStream_t

@@ -97,6 +97,7 @@ class Stats(C.Structure):
         ("device_bytes", C.c_int64), ("paths_per_batch", C.c_int64), ("overflow", C.c_int32), ("pad_", C.c_int32),
         ("ms_nrc_query", C.c_double), ("ms_nrc_train", C.c_double), ("nrc_query_rows", C.c_int64),
         ("nrc_query_launches", C.c_int64), ("nrc_train_rows", C.c_int64),
+        ("wave_node_steps", C.c_int64), ("wave_tri_steps", C.c_int64),
     ]
 
     def as_dict(self):

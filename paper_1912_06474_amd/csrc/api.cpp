@@ -2175,6 +2175,8 @@ sdd_status sdd_get_stats(sdd_ctx* c, sdd_stats* out) {
     out->shadow_cell_visits = (int64_t)s[kStatShadowVisits];
     out->node_visits = (int64_t)s[kStatNodes];
     out->tri_tests = (int64_t)s[kStatTris];
+    out->wave_node_steps = (int64_t)s[kStatNodeSteps];
+    out->wave_tri_steps = (int64_t)s[kStatTriSteps];
     out->batches = c->batches;
     out->launches_trace = c->launches_trace;
     out->ms_trace_ext = c->ms[0];

@@ -271,6 +271,10 @@ __device__ __forceinline__ d3 cosine_dir64(d3 n, double u0, double u1) {
 // wave-level helpers (64-wide)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+// 1 on the lowest active lane of the wave, 0 elsewhere (wave-level counting)
+__device__ __forceinline__ int first_active_lane() {
+    return (int)(lane_id() == (int)__builtin_ctzll(__builtin_amdgcn_read_exec()));
+}
 
 __device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
 

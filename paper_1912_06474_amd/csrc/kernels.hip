@@ -224,32 +224,86 @@ __device__ __forceinline__ int opaque(int v) {
     asm volatile("" : "+v"(v));
     return v;
 }
-__device__ __forceinline__ uint4 opaque(uint4 v) {
-    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
-    return v;
+// the same for the four child records of a node read from LDS: the four
+// reads are issued back to back and waited for once
+__device__ __forceinline__ void opaque4(uint4* c) {
+    asm volatile("" : "+v"(c[0].x), "+v"(c[0].y), "+v"(c[0].z), "+v"(c[0].w), "+v"(c[1].x), "+v"(c[1].y),
+                 "+v"(c[1].z), "+v"(c[1].w), "+v"(c[2].x), "+v"(c[2].y), "+v"(c[2].z), "+v"(c[2].w), "+v"(c[3].x),
+                 "+v"(c[3].y), "+v"(c[3].z), "+v"(c[3].w));
 }
 
-// Traversal of one cell's BVH with the node steps and the triangle tests in
-// separate loops.  A lane that reaches a leaf parks it and goes on down the
-// tree until most lanes of the wave still taking node steps have a parked
-// leaf; then the parked leaves are tested together.  The wave thus runs node
-// steps and triangle tests each with most of its lanes busy, instead of both
-// with part of them.
+// One work item (up to kPool chunks of one cell's queue of one ray kind) on
+// one wave, with lane refill.  Each lane traverses the cell's BVH for its ray
+// over (t_enter, t_exit] in rounds: node steps until at least half of the
+// lanes still taking them have parked a leaf, then the parked leaves.  Once a
+// quarter of the lanes have finished their rays (or all of them have), the
+// finished lanes store their results, hand the rays that go on to the
+// neighbouring cell's queue, and take the item's next rays; the LDS copy of
+// the cell's top nodes serves the whole item.  A ray's traversal does not
+// depend on which lane or round it runs in.
 //  - closest hit: thi = t_exit, best = -1 on entry; the hit does not depend on
 //    the visiting order (equal t goes to the lower primitive index);
 //  - shadow: thi = min(t_exit, t_max); a diffuse triangle in (tlo, thi] blocks
 //    the segment, a pane crossing is recorded in sh_glass (the order of the
 //    records changes only the rounding of the product of the pane factors).
 template <bool SHADOW, bool COUNT>
-__device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const uint4* top,
-                                         const float4* __restrict__ tris,
-                                         const float4* __restrict__ prim_info, int root, const RayTrav& r,
-                                         float tlo, float t_exit, float t_max, int exclude, float& thi, int& best,
-                                         bool& blocked, int& n_glass, int pid, const int* __restrict__ sh_state,
-                                         float2* __restrict__ sh_glass, int* overflow, int* stk, int* gstk,
-                                         int gstride, int& n_nodes, int& n_tris) {
+__device__ __forceinline__ void trace_item(const TraceParams& P, const QueueSet& Q, int cell, long long first,
+                                           int count, const uint4* top, int* stk, int* gstk, int gstride,
+                                           int& n_nodes, int& n_tris, int& n_node_steps, int& n_tri_steps) {
     constexpr int kDone = -2147483647 - 1;  // INT_MIN: no leaf encodes as it (~INT_MAX triangles)
-    int sp = 0;
+    const GridParams& g = P.grid;
+    const int ix = cell % g.nx, iy = (cell / g.nx) % g.ny, iz = cell / (g.nx * g.ny);
+    const float px0 = g.planes[ix], px1 = g.planes[ix + 1];
+    const float py0 = g.planes[g.off_y + iy], py1 = g.planes[g.off_y + iy + 1];
+    const float pz0 = g.planes[g.off_z + iz], pz1 = g.planes[g.off_z + iz + 1];
+    const int root = P.cell_root[cell];
+    const float4 qbase = P.cell_q[2 * cell], qstep = P.cell_q[2 * cell + 1];
+
+    // the lane's ray: its queue record, its traversal state
+    float4 qa = make_float4(0, 0, 0, 0), qb = make_float4(0, 0, 0, 0);
+    int2 qc = make_int2(0, 0);
+    RayTrav r;
+    float t_exit = 0.0f, thi = 0.0f;
+    int axis = 0, best = -1, n_glass = -1;
+    bool blocked = false, live = false;
+    int link = kDone, leaf = 0, sp = 0;
+    int cursor = 0;  // rays of the item handed out so far (the same on every lane)
+
+    auto fetch = [&](bool want) {
+        const unsigned long long m = __ballot(want);
+        const int i = cursor + rank_below(m);
+        cursor += popc64(m);
+        if (want && i < count) {
+            const long long q = (long long)cell * P.cap + first + i;
+            qa = Q.qa_in[q];
+            qb = Q.qb_in[q];
+            qc = Q.qc_in[q];
+            const f3 o = xyz(qa), d = xyz(qb);
+            // exit of this cell: nearest far plane, ties x < y < z
+            const float tx = d.x > 0.0f ? (px1 - o.x) / d.x : (d.x < 0.0f ? (px0 - o.x) / d.x : INFINITY);
+            const float ty = d.y > 0.0f ? (py1 - o.y) / d.y : (d.y < 0.0f ? (py0 - o.y) / d.y : INFINITY);
+            const float tz = d.z > 0.0f ? (pz1 - o.z) / d.z : (d.z < 0.0f ? (pz0 - o.z) / d.z : INFINITY);
+            axis = 0;
+            t_exit = tx;
+            if (ty < t_exit) {
+                t_exit = ty;
+                axis = 1;
+            }
+            if (tz < t_exit) {
+                t_exit = tz;
+                axis = 2;
+            }
+            r = make_trav(o, d, qbase, qstep);
+            thi = SHADOW ? fminf(t_exit, __int_as_float(qc.y)) : t_exit;
+            best = -1;
+            blocked = false;
+            n_glass = -1;
+            sp = 0;
+            leaf = 0;
+            link = (!SHADOW || thi > qa.w) ? root : kDone;
+            live = true;
+        }
+    };
     auto pop = [&]() -> int {
         // entries beyond kStack were never stored (the builders' depth cap keeps
         // the stack below it)
@@ -260,198 +314,173 @@ __device__ __forceinline__ void traverse(const uint4* __restrict__ nodes, const 
         else v = gstk[(sp - kLdsStack) * gstride];
         return v;
     };
-    int link = root;  // next node (>= 0) or leaf (< 0), kDone when the stack is empty
-    int leaf = 0;     // parked leaf (< 0), 0 for none
-    while (link != kDone) {
-        while (link >= 0) {
-            // the cell's first kTopNodes nodes (breadth-first: its top levels) come from LDS
-            const int rel = link - root;
-            uint4 ch[kBvhWidth];
-            if (rel < kTopNodes) {
+
+    fetch(true);
+    while (__ballot(live)) {
+        if (live) {
+            const float tlo = qa.w;
+            // node steps
+            while (link >= 0) {
+                // the cell's first kTopNodes nodes (breadth-first: its top levels) come from LDS
+                const int rel = link - root;
+                uint4 ch[kBvhWidth];
+                if (rel < kTopNodes) {
 #pragma unroll
-                for (int i = 0; i < kBvhWidth; ++i) ch[i] = opaque(top[kBvhWidth * rel + i]);
-            } else {
+                    for (int i = 0; i < kBvhWidth; ++i) ch[i] = top[kBvhWidth * rel + i];
+                    opaque4(ch);
+                } else {
 #pragma unroll
-                for (int i = 0; i < kBvhWidth; ++i) ch[i] = nodes[kBvhWidth * (size_t)link + i];
-            }
-            if (COUNT) ++n_nodes;
-            float t[kBvhWidth];
-            int l[kBvhWidth];
-#pragma unroll
-            for (int i = 0; i < kBvhWidth; ++i) {
-                l[i] = (int)ch[i].w;
-                const float te = box_enter(r, ch[i], tlo, thi);  // tested unconditionally: no branch per child
-                t[i] = l[i] == kEmptyLink ? INFINITY : te;
-            }
-            // nearest first: sorting network on (t, link), as min / max and selects
-            static_assert(kBvhWidth == 4, "the sorting network is written for 4 children");
-            auto order = [&](int i, int j) {
-                const bool sw = t[j] < t[i];
-                const float lo = sw ? t[j] : t[i], hi = sw ? t[i] : t[j];
-                const int li = sw ? l[j] : l[i], lj = sw ? l[i] : l[j];
-                t[i] = lo;
-                t[j] = hi;
-                l[i] = li;
-                l[j] = lj;
-            };
-            order(0, 1);
-            order(2, 3);
-            order(0, 2);
-            order(1, 3);
-            order(1, 2);
-            // the farther hit children wait on the stack, farthest deepest; the
-            // nearest is next (short stack in LDS, deeper entries in HBM)
-#pragma unroll
-            for (int i = kBvhWidth - 1; i >= 1; --i)
-                if (t[i] != INFINITY) {
-                    // typed address spaces keep these two stores apart (no flat store)
-                    if (sp < kLdsStack) ((lds_int*)stk)[sp * kTraceBlock] = l[i];
-                    else if (sp < kStack) ((global_int*)gstk)[(sp - kLdsStack) * gstride] = l[i];
-                    ++sp;
+                    for (int i = 0; i < kBvhWidth; ++i) ch[i] = P.nodes[kBvhWidth * (size_t)link + i];
                 }
-            link = t[0] != INFINITY ? l[0] : pop();
-            if (link < 0 && link != kDone && leaf == 0) {
+                if (COUNT) {
+                    ++n_nodes;
+                    n_node_steps += first_active_lane();
+                }
+                float t[kBvhWidth];
+                int l[kBvhWidth];
+#pragma unroll
+                for (int i = 0; i < kBvhWidth; ++i) {
+                    l[i] = (int)ch[i].w;
+                    const float te = box_enter(r, ch[i], tlo, thi);  // tested unconditionally: no branch per child
+                    t[i] = l[i] == kEmptyLink ? INFINITY : te;
+                }
+                // nearest first: sorting network on (t, link), as min / max and selects
+                static_assert(kBvhWidth == 4, "the sorting network is written for 4 children");
+                auto order = [&](int i, int j) {
+                    const bool sw = t[j] < t[i];
+                    const float lo = sw ? t[j] : t[i], hi = sw ? t[i] : t[j];
+                    const int li = sw ? l[j] : l[i], lj = sw ? l[i] : l[j];
+                    t[i] = lo;
+                    t[j] = hi;
+                    l[i] = li;
+                    l[j] = lj;
+                };
+                order(0, 1);
+                order(2, 3);
+                order(0, 2);
+                order(1, 3);
+                order(1, 2);
+                // the farther hit children wait on the stack, farthest deepest; the
+                // nearest is next (short stack in LDS, deeper entries in HBM)
+#pragma unroll
+                for (int i = kBvhWidth - 1; i >= 1; --i)
+                    if (t[i] != INFINITY) {
+                        // typed address spaces keep these two stores apart (no flat store)
+                        if (sp < kLdsStack) ((lds_int*)stk)[sp * kTraceBlock] = l[i];
+                        else if (sp < kStack) ((global_int*)gstk)[(sp - kLdsStack) * gstride] = l[i];
+                        ++sp;
+                    }
+                link = t[0] != INFINITY ? l[0] : pop();
+                if (link < 0 && link != kDone && leaf == 0) {
+                    leaf = link;
+                    link = pop();
+                }
+                // leave for the leaf loop once at least half of the lanes here
+                // have parked a leaf
+                const unsigned long long here = __ballot(true), bare = __ballot(leaf == 0);
+                if (2 * __popcll(bare) <= __popcll(here)) break;
+            }
+            if (leaf == 0 && link < 0 && link != kDone) {
                 leaf = link;
                 link = pop();
             }
-            // leave for the leaf loop once at least half of the lanes here
-            // have parked a leaf (with 4-wide nodes, faster than waiting for
-            // two thirds or three quarters of them, and the same as a third)
-            const unsigned long long here = __ballot(true), bare = __ballot(leaf == 0);
-            if (2 * __popcll(bare) <= __popcll(here)) break;
-        }
-        if (leaf == 0 && link < 0 && link != kDone) {
-            leaf = link;
-            link = pop();
-        }
-        while (leaf < 0) {
-            int ti = ~leaf;
-            for (;;) {
-                const float4 a = tris[3 * (size_t)ti], b = tris[3 * (size_t)ti + 1], c = tris[3 * (size_t)ti + 2];
-                const int prim = __float_as_int(a.w);
-                const int meta = __float_as_int(b.w);
-                const int typ = meta & 3;
-                if (prim != exclude && !(SHADOW && typ == kEmitter)) {
-                    if (COUNT) ++n_tris;
-                    float t;
-                    if (tri_test(r, a, b, c, t)) {
-                        if (!SHADOW) {
-                            if (t > tlo && (t < thi || (t == thi && (best < 0 || prim < best)))) {
-                                thi = t;
-                                best = prim;
+            // triangle tests of the parked leaves (and of leaves met right after them)
+            while (leaf < 0) {
+                int ti = ~leaf;
+                for (;;) {
+                    const float4 a = P.tris[3 * (size_t)ti], b = P.tris[3 * (size_t)ti + 1],
+                                 c = P.tris[3 * (size_t)ti + 2];
+                    const int prim = __float_as_int(a.w);
+                    const int meta = __float_as_int(b.w);
+                    const int typ = meta & 3;
+                    if (prim != qc.x && !(SHADOW && typ == kEmitter)) {
+                        if (COUNT) {
+                            ++n_tris;
+                            n_tri_steps += first_active_lane();
+                        }
+                        float tt;
+                        if (tri_test(r, a, b, c, tt)) {
+                            if (!SHADOW) {
+                                if (tt > tlo && (tt < thi || (tt == thi && (best < 0 || prim < best)))) {
+                                    thi = tt;
+                                    best = prim;
+                                }
+                            } else if (tt > tlo && tt <= t_exit && tt < __int_as_float(qc.y)) {
+                                if (typ == kDiffuse) {
+                                    blocked = true;
+                                    link = kDone;
+                                    break;
+                                }
+                                const int pid = __float_as_int(qb.w);
+                                const f3 ng = xyz(P.prim_info[prim]);
+                                if (n_glass < 0) n_glass = P.sh_state[pid] >> 4;
+                                if (n_glass < kMaxGlass)
+                                    P.sh_glass[(size_t)pid * kMaxGlass + n_glass] = make_float2(-dot3(r.d, ng), c.w);
+                                else
+                                    atomicOr(P.overflow, kOverflowPanes);
+                                ++n_glass;
                             }
-                        } else if (t > tlo && t <= t_exit && t < t_max) {
-                            if (typ == kDiffuse) {
-                                blocked = true;
-                                return;
-                            }
-                            const f3 ng = xyz(prim_info[prim]);
-                            if (n_glass < 0) n_glass = sh_state[pid] >> 4;
-                            if (n_glass < kMaxGlass)
-                                sh_glass[(size_t)pid * kMaxGlass + n_glass] = make_float2(-dot3(r.d, ng), c.w);
-                            else
-                                atomicOr(overflow, kOverflowPanes);
-                            ++n_glass;
                         }
                     }
+                    if (meta & kLastInLeaf) break;
+                    ++ti;
                 }
-                if (meta & kLastInLeaf) break;
-                ++ti;
-            }
-            leaf = 0;
-            if (link < 0 && link != kDone) {
-                leaf = link;
-                link = pop();
+                leaf = 0;
+                if (link < 0 && link != kDone) {
+                    leaf = link;
+                    link = pop();
+                }
             }
         }
-    }
-}
-
-// One chunk (up to 64 rays of one cell's queue, one wave): traverse the
-// cell's BVH over (t_enter, t_exit] and hand the rays that go on to the
-// neighbouring cell's queue.  Reached by all lanes of the wave together.
-template <bool SHADOW, bool COUNT>
-__device__ __forceinline__ void process_chunk(const TraceParams& P, const QueueSet& Q, int cell, int idx, bool active,
-                                              const uint4* top, int* stk, int* gstk, int gstride, int& n_nodes,
-                                              int& n_tris) {
-    const GridParams& g = P.grid;
-    const int ix = cell % g.nx, iy = (cell / g.nx) % g.ny, iz = cell / (g.nx * g.ny);
-    const float px0 = g.planes[ix], px1 = g.planes[ix + 1];
-    const float py0 = g.planes[g.off_y + iy], py1 = g.planes[g.off_y + iy + 1];
-    const float pz0 = g.planes[g.off_z + iz], pz1 = g.planes[g.off_z + iz + 1];
-    const int root = P.cell_root[cell];
-
-    bool cont = false;
-    int next = 0;
-    float4 qa = make_float4(0, 0, 0, 0), qb = make_float4(0, 0, 0, 0);
-    int2 qc = make_int2(0, 0);
-    if (active) {
-        const long long q = (long long)cell * P.cap + idx;
-        qa = Q.qa_in[q];
-        qb = Q.qb_in[q];
-        qc = Q.qc_in[q];
-        const f3 o = xyz(qa), d = xyz(qb);
-        const int pid = __float_as_int(qb.w);
-        const float t_enter = qa.w;
-        const float t_max = __int_as_float(qc.y);
-        // exit of this cell: nearest far plane, ties x < y < z
-        const float tx = d.x > 0.0f ? (px1 - o.x) / d.x : (d.x < 0.0f ? (px0 - o.x) / d.x : INFINITY);
-        const float ty = d.y > 0.0f ? (py1 - o.y) / d.y : (d.y < 0.0f ? (py0 - o.y) / d.y : INFINITY);
-        const float tz = d.z > 0.0f ? (pz1 - o.z) / d.z : (d.z < 0.0f ? (pz0 - o.z) / d.z : INFINITY);
-        int axis = 0;
-        float t_exit = tx;
-        if (ty < t_exit) {
-            t_exit = ty;
-            axis = 1;
-        }
-        if (tz < t_exit) {
-            t_exit = tz;
-            axis = 2;
-        }
-        const RayTrav r = make_trav(o, d, P.cell_q[2 * cell], P.cell_q[2 * cell + 1]);
-        float thi = SHADOW ? fminf(t_exit, t_max) : t_exit;
-        int best = -1;
-        bool blocked = false;
-        int n_glass = -1;  // pane crossings so far (-1: not loaded yet)
-        if (!SHADOW || thi > t_enter)
-            traverse<SHADOW, COUNT>(P.nodes, top, P.tris, P.prim_info, root, r, t_enter, t_exit, t_max, qc.x, thi, best,
-                                    blocked, n_glass, pid, P.sh_state, P.sh_glass, P.overflow, stk, gstk, gstride,
-                                    n_nodes, n_tris);
-        bool leave;
-        if (!SHADOW) {
-            if (best >= 0) P.hit[pid] = make_float2(thi, __int_as_float(best));
-            leave = best < 0;
-        } else {
-            if (blocked) P.sh_state[pid] = kShBlocked;
-            else if (n_glass >= 0) P.sh_state[pid] = kShVisible | (n_glass << 4);
-            leave = !blocked && t_exit < t_max;
-        }
-        if (leave) {
-            int nx = ix, ny = iy, nz = iz;
-            if (axis == 0) nx += d.x > 0.0f ? 1 : -1;
-            else if (axis == 1) ny += d.y > 0.0f ? 1 : -1;
-            else nz += d.z > 0.0f ? 1 : -1;
-            if (nx >= 0 && nx < g.nx && ny >= 0 && ny < g.ny && nz >= 0 && nz < g.nz) {
-                cont = true;
-                next = nx + g.nx * (ny + g.ny * nz);
-                qa.w = t_exit;  // carried bit-exactly into the neighbour
+        // finished rays: results, hand-off and refill, once a quarter of the
+        // lanes are done or no lane is still traversing
+        const bool done = live && link == kDone;
+        const int n_done = popc64(__ballot(done)), n_live = popc64(__ballot(live));
+        if (n_done == 0 || (4 * n_done < kChunk && n_done < n_live)) continue;
+        bool cont = false;
+        int next = 0;
+        if (done) {
+            const int pid = __float_as_int(qb.w);
+            bool leave;
+            if (!SHADOW) {
+                if (best >= 0) P.hit[pid] = make_float2(thi, __int_as_float(best));
+                leave = best < 0;
+            } else {
+                if (blocked) P.sh_state[pid] = kShBlocked;
+                else if (n_glass >= 0) P.sh_state[pid] = kShVisible | (n_glass << 4);
+                leave = !blocked && t_exit < __int_as_float(qc.y);
             }
+            if (leave) {
+                int nx = ix, ny = iy, nz = iz;
+                if (axis == 0) nx += qb.x > 0.0f ? 1 : -1;
+                else if (axis == 1) ny += qb.y > 0.0f ? 1 : -1;
+                else nz += qb.z > 0.0f ? 1 : -1;
+                if (nx >= 0 && nx < g.nx && ny >= 0 && ny < g.ny && nz >= 0 && nz < g.nz) {
+                    cont = true;
+                    next = nx + g.nx * (ny + g.ny * nz);
+                    qa.w = t_exit;  // carried bit-exactly into the neighbour
+                }
+            }
+            live = false;
         }
-    }
-    const int slot = wave_append(cont, next, Q.cnt_out, kCntStride);
-    if (cont && slot < P.cap) {
-        const long long q = (long long)next * P.cap + slot;
-        Q.qa_out[q] = qa;
-        Q.qb_out[q] = qb;
-        Q.qc_out[q] = qc;
+        const int slot = wave_append(cont, next, Q.cnt_out, kCntStride);
+        if (cont && slot < P.cap) {
+            const long long q = (long long)next * P.cap + slot;
+            Q.qa_out[q] = qa;
+            Q.qb_out[q] = qb;
+            Q.qc_out[q] = qc;
+        }
+        if (cursor < count) fetch(done);
     }
 }
 
 // One sweep over all subdomain queues of both ray kinds (closest-hit rays of
 // one depth and shadow rays of the previous one are independent, so they
-// share the sweep).  Work is split into 64-ray chunks ordered by (cell, kind);
-// the chunk range is cut into kXcd contiguous parts, part x served by the
-// workgroups of XCD x (consecutive cells share that XCD's L2).
+// share the sweep).  Work is split into items of up to kItem rays ordered by
+// (cell, kind); the item range is cut into kXcd contiguous parts, part x
+// served by the workgroups of XCD x (consecutive cells share that XCD's L2).
+// A wave works through one item at a time (trace_item: lanes refilled from
+// the item as their rays finish).
 template <bool COUNT>
 __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(kTraceWaves, kTraceWaves)))
 void k_trace(TraceParams P) {
@@ -461,7 +490,7 @@ void k_trace(TraceParams P) {
     const int G = P.n_cells;
     const int E = 2 * G;  // entry e = 2 * cell + kind
     if (threadIdx.x < 64) {
-        // exclusive prefix of the per-entry chunk counts (wave 0, lane-blocked scan)
+        // exclusive prefix of the per-entry item counts (wave 0, lane-blocked scan)
         const int ln = threadIdx.x;
         const int per = (E + 63) / 64;
         const int c0 = ln * per, c1 = min(c0 + per, E);
@@ -470,7 +499,7 @@ void k_trace(TraceParams P) {
             const int kind = e & 1;
             const int n = P.active[kind] ? P.q[kind].cnt_in[(e >> 1) * kCntStride] : 0;
             if (n > P.cap) atomicOr(P.overflow, kOverflowQueue);  // never expected: counters are bounded by cap
-            local += (n + kChunk - 1) / kChunk;
+            local += (n + kItem - 1) / kItem;
         }
         int incl = local;
 #pragma unroll
@@ -483,7 +512,7 @@ void k_trace(TraceParams P) {
             s_pref[e] = run;
             const int kind = e & 1;
             const int n = P.active[kind] ? P.q[kind].cnt_in[(e >> 1) * kCntStride] : 0;
-            run += (n + kChunk - 1) / kChunk;
+            run += (n + kItem - 1) / kItem;
         }
         if (ln == 63) s_pref[E] = incl;
     }
@@ -502,11 +531,11 @@ void k_trace(TraceParams P) {
     const int gstride = gridDim.x * kTraceBlock;  // entries of one level are contiguous over the grid
     int* gstk = P.gstack + blockIdx.x * kTraceBlock + threadIdx.x;
     const int xcd = blockIdx.x % kXcd;
-    int n_nodes = 0, n_tris = 0;
+    int n_nodes = 0, n_tris = 0, n_node_steps = 0, n_tri_steps = 0;
     uint4* top = s_top + (threadIdx.x / 64) * kBvhWidth * kTopNodes;  // this wave's copy of a cell's top nodes
     int top_cell = -1;
 
-    // static XCD-aware striding: the waves of XCD x walk part x of the chunk
+    // static XCD-aware striding: the waves of XCD x walk part x of the item
     // list round-robin (no atomics, so empty and near-empty sweeps cost only
     // the prologue)
     constexpr int kWavesPerBlock = kTraceBlock / 64;
@@ -514,11 +543,11 @@ void k_trace(TraceParams P) {
     const int nwx = (gridDim.x / kXcd) * kWavesPerBlock;
     const int lo = (int)((long long)total * xcd / kXcd);
     const int hi = (int)((long long)total * (xcd + 1) / kXcd);
-    for (int chunk = lo + lw; chunk < hi; chunk += nwx) {
+    for (int item = lo + lw; item < hi; item += nwx) {
         int a = 0, b = E;
         while (b - a > 1) {
             const int m = (a + b) >> 1;
-            if (s_pref[m] <= chunk) a = m;
+            if (s_pref[m] <= item) a = m;
             else b = m;
         }
         const int e = __builtin_amdgcn_readfirstlane(a);
@@ -534,20 +563,24 @@ void k_trace(TraceParams P) {
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
-        const int idx = (chunk - s_pref[e]) * kChunk + lane;
-        const bool active = idx < min((long long)P.q[kind].cnt_in[cell * kCntStride], P.cap);
+        const long long first = (long long)(item - s_pref[e]) * kItem;
+        const int count = (int)min((long long)kItem,
+                                   min((long long)P.q[kind].cnt_in[cell * kCntStride], P.cap) - first);
         if (kind == 0)
-            process_chunk<false, COUNT>(P, P.q[0], cell, idx, active, top, stk, gstk, gstride, n_nodes,
-                                        n_tris);
+            trace_item<false, COUNT>(P, P.q[0], cell, first, count, top, stk, gstk, gstride, n_nodes, n_tris,
+                                     n_node_steps, n_tri_steps);
         else
-            process_chunk<true, COUNT>(P, P.q[1], cell, idx, active, top, stk, gstk, gstride, n_nodes,
-                                       n_tris);
+            trace_item<true, COUNT>(P, P.q[1], cell, first, count, top, stk, gstk, gstride, n_nodes, n_tris,
+                                    n_node_steps, n_tri_steps);
     }
     if (COUNT) {
         const int nn = wave_sum(n_nodes), nt = wave_sum(n_tris);
+        const int ns = wave_sum(n_node_steps), nts = wave_sum(n_tri_steps);
         if (lane == 0) {
             atomicAdd(&P.stats[kStatNodes], (unsigned long long)nn);
             atomicAdd(&P.stats[kStatTris], (unsigned long long)nt);
+            atomicAdd(&P.stats[kStatNodeSteps], (unsigned long long)ns);
+            atomicAdd(&P.stats[kStatTriSteps], (unsigned long long)nts);
         }
     }
 }

@@ -61,6 +61,8 @@ constexpr int kCntStride = 32;
 constexpr int kTopNodes = 32;     // breadth-first top nodes (128 records) of the current cell kept in LDS per wave
 constexpr int kTraceWaves = 8;    // waves per SIMD the trace kernel is compiled for (registers <= 64)
 constexpr int kChunk = 64;        // rays per scheduling chunk (one wave)
+constexpr int kPool = 2;          // chunks per work item (one wave refills its lanes from them)
+constexpr int kItem = kChunk * kPool;
 constexpr int kXcd = 8;           // XCDs of an MI355X; workgroup i runs on XCD i % 8
 constexpr int kMaxGlass = 4;      // pane crossings recorded per shadow segment
 // bits of the overflow flag the trace kernel raises (atomic OR)
@@ -128,6 +130,8 @@ enum Stat : int {
     kStatShadowVisits,
     kStatNodes,
     kStatTris,
+    kStatNodeSteps,  // wave-level steps (counted by the first active lane)
+    kStatTriSteps,
     kStatCount
 };
 

@@ -220,6 +220,29 @@ def test_run_to_run_bitwise(tracer):
         assert np.array_equal(a[k], b[k])
 
 
+def test_work_counters_leave_the_render_unchanged(tracer):
+    """Counting traversal work changes only the counters; every lane-level
+    count lies between its wave-level step count and 64 times it.  A frame
+    several times the wave count makes lanes refill from their work items."""
+    sc = sg.tiny_room()
+    W, H, spp, D = 96, 64, 4, 4
+    a = gpu_render(tracer, sc, W, H, spp, D, grid=(2, 2, 1))
+    tracer.reset_render(0)  # the same render again (its random numbers are keyed by the render id)
+    hl = tracer.new_log(W, H, spp, D)
+    sl = tracer.new_log(W, H, spp, D)
+    tracer.reset_stats()
+    tracer.trace_spectral(sc["camera"], W, H, spp, D, render_id=0, hit_log=hl, shadow_log=sl, count_work=True)
+    s, x = tracer.resolve_image(0, W, H)
+    st = tracer.stats()
+    tracer.reset_render(0)
+    assert np.array_equal(a["spectral"], s.cpu().numpy()) and np.array_equal(a["xyz"], x.cpu().numpy())
+    assert np.array_equal(a["hit_log"], hl.cpu().numpy()) and np.array_equal(a["shadow_log"], sl.cpu().numpy())
+    for lanes, steps in (("node_visits", "wave_node_steps"), ("tri_tests", "wave_tri_steps")):
+        assert 0 < st[steps] <= st[lanes] <= 64 * st[steps], (lanes, st[lanes], st[steps])
+    print(f"[count] node loop {st['node_visits'] / (64 * st['wave_node_steps']):.3f}, "
+          f"leaf loop {st['tri_tests'] / (64 * st['wave_tri_steps']):.3f} of lanes busy", flush=True)
+
+
 def test_xyz_is_weighted_cmf_sum(tracer):
     sc = sg.tiny_room()
     g = gpu_render(tracer, sc, 16, 16, 1, 3, grid=(2, 2, 1))
