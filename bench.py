@@ -262,6 +262,8 @@ def nrc_comparison(args, tr, scene, wl):
     if args.nrc_train_batch is not None:
         cfg["train_batch"] = args.nrc_train_batch
     cfg["lr"] = args.nrc_lr if args.nrc_lr is not None else 1e-2
+    if args.nrc_warmup is not None:
+        cfg["train_warmup"] = args.nrc_warmup
     nl = len(scene["lambda_nm"])
     cam = scene["camera"]
     frames = args.frames_per_step * max(args.steps, 2)
@@ -483,7 +485,9 @@ def plain_line(args, workload, wl, scene, tr, build_s, cpu_s):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": dt / args.steps * 1e3,
-        "dtype": "f32 traversal and per-lambda transport, f64 path state and resolve",
+        "dtype": ("f32 traversal, path state and per-lambda transport, f64 resolve (FP32-path-state measurement "
+                  "build)" if os.environ.get("SDD_PATH_STATE") == "f32"
+                  else "f32 traversal and per-lambda transport, f64 path state and resolve"),
         "config": {"workload": f"{workload}: {len(scene['tris'])} tris, {frame_desc}, {nl} lambda, depth {D}, "
                                f"grid {'x'.join(map(str, wl['grid']))}",
                    "paths_per_step": paths_per_step, "rays_per_step": rays / args.steps,
@@ -578,9 +582,14 @@ def main():
     ap.add_argument("--nrc-train-steps", type=int, default=None, help="nrc_room: Adam steps per frame (default 4)")
     ap.add_argument("--nrc-train-batch", type=int, default=None, help="nrc_room: rows per Adam step (default 2^14)")
     ap.add_argument("--nrc-lr", type=float, default=None, help="nrc_room: Adam learning rate (default 1e-2)")
+    ap.add_argument("--nrc-warmup", type=int, default=None,
+                    help="nrc_room: cache training frames before accumulation (default 100; their time counts)")
     ap.add_argument("--autotune", nargs="?", const="", default=None, metavar="FILE",
                     help="search the launch settings on the step's own call before the warmup (results file "
                          "FILE is read first and written after a search)")
+    ap.add_argument("--path-state", choices=["f64", "f32"], default="f64",
+                    help="f32: load the FP32-path-state measurement build (libsdd_f32state.so) to time what FP64 "
+                         "path state costs; the library itself keeps FP64 path state")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -592,6 +601,8 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.path_state == "f32":
+        os.environ["SDD_PATH_STATE"] = "f32"  # read when the package is first imported
 
     cpu_s = 0.0 if args.no_cpu_baseline else args.cpu_seconds
     wl, scene, tr, build_s = load(args.workload, args)

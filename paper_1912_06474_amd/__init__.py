@@ -20,7 +20,10 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsdd.so")
+# SDD_PATH_STATE=f32 selects the FP32-path-state measurement build (the same
+# kernels with the per-path ray state and shading geometry in FP32), which
+# exists to state what FP64 path state buys in accuracy and costs in time
+LIB_PATH = os.path.join(HERE, "libsdd_f32state.so" if os.environ.get("SDD_PATH_STATE") == "f32" else "libsdd.so")
 
 SDD_OK = 0
 STATUS = {0: "SDD_OK", -1: "SDD_ERR_INVALID_ARG", -2: "SDD_ERR_STATE", -3: "SDD_ERR_OOM", -4: "SDD_ERR_HIP",

@@ -20,15 +20,29 @@ HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-Wall", "-Wno-unused-result"]
 
 
+# The FP32-path-state measurement build: the same sources with the per-path
+# ray state and shading geometry in FP32 (it states what FP64 state buys in
+# accuracy and costs in time); loaded only when SDD_PATH_STATE=f32.
+VARIANTS = {"": [], "_f32state": ["-DSDD_PATH_STATE_F32"]}
+
+
 def build(verbose: bool = False, jobs: int = 3) -> str:
-    objdir = os.path.join(HERE, "_build")
+    """Build libsdd.so and the measurement build; returns the library's path."""
+    for suffix, defs in VARIANTS.items():
+        _build_one(suffix, defs, verbose)
+    return LIB
+
+
+def _build_one(suffix: str, defs: list, verbose: bool) -> str:
+    objdir = os.path.join(HERE, "_build" + suffix)
+    lib = os.path.join(HERE, "libsdd" + suffix + ".so")
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmd = ["hipcc", *HIPFLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
+        cmd = ["hipcc", *HIPFLAGS, *defs, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
@@ -43,12 +57,12 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
             failed = True
     if failed:
         raise RuntimeError("HIP compilation failed")
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", lib + ".tmp"]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":

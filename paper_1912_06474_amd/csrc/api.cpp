@@ -175,6 +175,9 @@ struct sdd_ctx {
     int* nrc_ovals = nullptr;       // path indices [2][paths], and the sort's scratch
     char* nrc_otemp = nullptr;
     size_t nrc_otemp_bytes = 0;
+    int* nrc_flags = nullptr;  // a render query's paths with a cache vertex: flags, rows (paths + 1 each),
+    int* nrc_rank = nullptr;   // and the path of each row
+    int* nrc_cp = nullptr;
     long long nrc_ocap = 0;
 
     // graph replay of repeated trace calls (SDD_TRACE_GRAPH)
@@ -371,6 +374,9 @@ void free_nrc(sdd_ctx* c) {
     dfree(c, c->nrc_hop);
     dfree(c, c->nrc_sop);
     dfree(c, c->nrc_okeys);
+    dfree(c, c->nrc_flags);
+    dfree(c, c->nrc_rank);
+    dfree(c, c->nrc_cp);
     dfree(c, c->nrc_ovals);
     dfree(c, c->nrc_otemp);
     c->nrc_ocap = 0;
@@ -528,7 +534,7 @@ long long mem_budget_bytes(const sdd_ctx* c) {
 }
 
 long long bytes_per_path(const sdd_ctx* c, int max_depth) {
-    return 4LL * c->G * (16 + 16 + 8) + 2 * (16 + 16 + 8 + 4) + 32 + 32 + 8 + 4 +
+    return 4LL * c->G * (16 + 16 + 8) + 2 * (16 + 16 + 8 + 4) + 2 * (long long)sizeof(D4) + 8 + 4 +
            (long long)max_depth * (16 + 4 + 8 * kMaxGlass);
 }
 
@@ -1161,18 +1167,26 @@ sdd_status nrc_ensure_ops(sdd_ctx* c, int n, int n_other = 0) {
     const long long need = nrc_query_ops_paths(std::max(n, n_other));
     size_t tb = 1;
     for (int m : {n, n_other})
-        if (m > 0) tb = std::max({tb, nrc_order_temp_bytes(m), nrc_order_temp_bytes((int)nrc_query_ops_paths(m))});
+        if (m > 0)
+            tb = std::max({tb, nrc_order_temp_bytes(m), nrc_order_temp_bytes((int)nrc_query_ops_paths(m)),
+                           nrc_scan_temp_bytes(m + 1)});
     sdd_status st;
     if (need > c->nrc_ocap) {
         dfree(c, c->nrc_hop);
         dfree(c, c->nrc_sop);
         dfree(c, c->nrc_okeys);
         dfree(c, c->nrc_ovals);
+        dfree(c, c->nrc_flags);
+        dfree(c, c->nrc_rank);
+        dfree(c, c->nrc_cp);
         c->nrc_ocap = 0;
         if ((st = dalloc(c, &c->nrc_hop, (size_t)(4 * need))) != SDD_OK ||
             (st = dalloc(c, &c->nrc_sop, (size_t)(4 * need))) != SDD_OK ||
             (st = dalloc(c, &c->nrc_okeys, (size_t)(2 * need))) != SDD_OK ||
-            (st = dalloc(c, &c->nrc_ovals, (size_t)(2 * need))) != SDD_OK)
+            (st = dalloc(c, &c->nrc_ovals, (size_t)(2 * need))) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_flags, (size_t)(need + 1))) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_rank, (size_t)(need + 1))) != SDD_OK ||
+            (st = dalloc(c, &c->nrc_cp, (size_t)need)) != SDD_OK)
             return st;
         c->nrc_ocap = need;
     }
@@ -1557,22 +1571,24 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
         st = run_sweeps(c, -1, ph_sh(D), cap, count, timing, D, N);
         if (st != SDD_OK) return st;
         if (nrc) {  // cache values at the batch's cache vertices, every wavelength
-            c->nrc_query_rows += (long long)N * c->nl;
             ++c->nrc_query_launches;
             if (c->nrc_precision == 0) {
+                c->nrc_query_rows += (long long)N * c->nl;  // every path slot
                 Timer tm(c, timing, 4);
                 HIP_TRY(c, nrc_launch_query(c->nrc, N, c->nrc_cx, c->nrc_cn, c->d_lam, c->nl, c->nlp, c->nrc_lhat, 1,
                                             0, c->nrc_hop, c->nrc_sop, nullptr, c->stream));
             } else {
+                // only the paths that own a cache vertex (the kernel counts their rows)
                 {
                     Timer tm(c, timing, 3);
                     const NrcOrder ord = nrc_order(c);
-                    HIP_TRY(c, nrc_launch_query_operands(c->nrc, N, c->nrc_cx, c->nrc_cn, c->nrc_hop, c->nrc_sop,
-                                                         &ord, c->stream));
+                    HIP_TRY(c, nrc_launch_cache_operands(c->nrc, N, c->nrc_cx, c->nrc_cn, c->nrc_hop, c->nrc_sop,
+                                                         &ord, c->nrc_flags, c->nrc_rank, c->nrc_cp, c->stream));
                 }
                 Timer tm(c, timing, 4);  // the matrix-core kernel alone
                 HIP_TRY(c, nrc_launch_query_mfma(c->nrc, N, c->nrc_hop, c->nrc_sop, c->d_lam, c->nl, c->nlp,
-                                                 c->nrc_lhat, 1, c->stream));
+                                                 c->nrc_lhat, 1, c->stream, c->nrc_rank + N, c->nrc_cp,
+                                                 c->d_stats + kStatNrcRows));
             }
         }
         for (const Seg& sg : segs) {
@@ -2185,7 +2201,7 @@ sdd_status sdd_get_stats(sdd_ctx* c, sdd_stats* out) {
     out->ms_other = c->ms[3];
     out->ms_nrc_query = c->ms[4];
     out->ms_nrc_train = c->ms[5];
-    out->nrc_query_rows = c->nrc_query_rows;
+    out->nrc_query_rows = c->nrc_query_rows + (int64_t)s[kStatNrcRows];
     out->nrc_query_launches = c->nrc_query_launches;
     out->nrc_train_rows = c->nrc_train_rows;
     out->n_refs = c->has_bvh ? c->gb.n_refs : 0;

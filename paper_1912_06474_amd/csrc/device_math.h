@@ -42,6 +42,25 @@ __device__ __forceinline__ d3 wide(f3 a) { return d3{a.x, a.y, a.z}; }
 __device__ __forceinline__ d3 wide(float4 a) { return d3{a.x, a.y, a.z}; }
 __device__ __forceinline__ f3 narrow(d3 a) { return f3{(float)a.x, (float)a.y, (float)a.z}; }
 
+// Precision of the per-path ray state and of the shading geometry built on it
+// (camera ray, hit point on the triangle's plane, normal, light sample and
+// NEE geometry, bounce directions): FP64 in the library.  Compiled with
+// SDD_PATH_STATE_F32 (a measurement build, libsdd_f32state.so) they are FP32,
+// state storage included, so that build states what FP32 state costs in
+// accuracy against the FP64 oracle and what FP64 state costs in time.
+#ifdef SDD_PATH_STATE_F32
+using preal = float;
+using pv3 = f3;
+__device__ __forceinline__ pv3 state3(f3 a) { return a; }
+__device__ __forceinline__ pv3 state3(float4 a) { return f3{a.x, a.y, a.z}; }
+__device__ __forceinline__ f3 narrow(f3 a) { return a; }
+#else
+using preal = double;
+using pv3 = d3;
+__device__ __forceinline__ pv3 state3(f3 a) { return wide(a); }
+__device__ __forceinline__ pv3 state3(float4 a) { return wide(a); }
+#endif
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32
 // multiplies with the published multipliers and Weyl key increments.
@@ -266,6 +285,12 @@ __device__ __forceinline__ d3 cosine_dir64(d3 n, double u0, double u1) {
     const double lz = sqrt(1.0 - u0);
     return b1 * (r * cp) + b2 * (r * sp) + n * lz;
 }
+
+#ifdef SDD_PATH_STATE_F32
+__device__ __forceinline__ pv3 cosine_dir_state(pv3 n, preal u0, preal u1) { return cosine_dir(n, u0, u1); }
+#else
+__device__ __forceinline__ pv3 cosine_dir_state(pv3 n, preal u0, preal u1) { return cosine_dir64(n, u0, u1); }
+#endif
 
 // ---------------------------------------------------------------------------
 // wave-level helpers (64-wide)

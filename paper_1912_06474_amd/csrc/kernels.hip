@@ -119,22 +119,24 @@ __global__ __launch_bounds__(kShadeBlock) void k_camgen(CamParams P) {
         const int pf = frame_pixel(P.win, p);            // frame pixel (camera ray, random numbers)
         const int py = (int)(pf / (unsigned)P.W), px = pf - py * P.W;
         const uint4 r = philox4x32_10(make_uint4((uint32_t)pf, (uint32_t)s, 0u, 0u), P.key);
-        // the ray in FP64 (path state); traversal gets its FP32 rounding
-        const double x = (double)px + (double)u01(r.x), y = (double)py + (double)u01(r.y);
-        const double sx = 2.0 * x / (double)P.W - 1.0, sy = 1.0 - 2.0 * y / (double)P.H;
-        const d3 eye{P.eye[0], P.eye[1], P.eye[2]}, fw{P.fwd[0], P.fwd[1], P.fwd[2]};
-        const d3 rt{P.right[0], P.right[1], P.right[2]}, up{P.up[0], P.up[1], P.up[2]};
-        d3 o64 = eye, d64 = fw;
+        // the ray in the path state's precision (FP64); traversal gets its FP32 rounding
+        const preal x = (preal)px + (preal)u01(r.x), y = (preal)py + (preal)u01(r.y);
+        const preal sx = (preal)2 * x / (preal)P.W - (preal)1, sy = (preal)1 - (preal)2 * y / (preal)P.H;
+        const pv3 eye{(preal)P.eye[0], (preal)P.eye[1], (preal)P.eye[2]};
+        const pv3 fw{(preal)P.fwd[0], (preal)P.fwd[1], (preal)P.fwd[2]};
+        const pv3 rt{(preal)P.right[0], (preal)P.right[1], (preal)P.right[2]};
+        const pv3 up{(preal)P.up[0], (preal)P.up[1], (preal)P.up[2]};
+        pv3 o64 = eye, d64 = fw;
         if (P.ortho) {
-            o64 = eye + rt * (sx * P.ortho_half_h * P.aspect) + up * (sy * P.ortho_half_h);
+            o64 = eye + rt * (sx * (preal)P.ortho_half_h * (preal)P.aspect) + up * (sy * (preal)P.ortho_half_h);
         } else {
-            const d3 v = fw + rt * (sx * P.tan_half * P.aspect) + up * (sy * P.tan_half);
-            d64 = v * (1.0 / sqrt(dot3(v, v)));
+            const pv3 v = fw + rt * (sx * (preal)P.tan_half * (preal)P.aspect) + up * (sy * (preal)P.tan_half);
+            d64 = v * ((preal)1 / sqrt(dot3(v, v)));
         }
         o = narrow(o64);
         d = narrow(d64);
-        P.ray_o[pid] = D4{o64.x, o64.y, o64.z, 0.0};
-        P.ray_d[pid] = D4{d64.x, d64.y, d64.z, 0.0};
+        P.ray_o[pid] = D4{o64.x, o64.y, o64.z, 0};
+        P.ray_d[pid] = D4{d64.x, d64.y, d64.z, 0};
         P.hit[pid] = make_float2(INFINITY, __int_as_float(-1));
         uint32_t fl = kAlive | kCountE;
         if (P.nrc.on && ((uint64_t)(uint32_t)s * (uint64_t)P.WH + (uint64_t)p) % P.nrc.stride == 0) fl |= kTrain;
@@ -476,8 +478,9 @@ __device__ __forceinline__ void trace_item(const TraceParams& P, const QueueSet&
 
 // One sweep over all subdomain queues of both ray kinds (closest-hit rays of
 // one depth and shadow rays of the previous one are independent, so they
-// share the sweep).  Work is split into items of up to kItem rays ordered by
-// (cell, kind); the item range is cut into kXcd contiguous parts, part x
+// share the sweep).  Work is split into items ordered by (cell, kind): up to
+// kItem rays in a sweep with kPool chunks per wave of the grid, one chunk in a
+// smaller one.  The item range is cut into kXcd contiguous parts, part x
 // served by the workgroups of XCD x (consecutive cells share that XCD's L2).
 // A wave works through one item at a time (trace_item: lanes refilled from
 // the item as their rays finish).
@@ -489,17 +492,32 @@ void k_trace(TraceParams P) {
     __shared__ uint4 s_top[(kTraceBlock / 64) * kBvhWidth * kTopNodes];
     const int G = P.n_cells;
     const int E = 2 * G;  // entry e = 2 * cell + kind
+    constexpr int kWavesPerBlock = kTraceBlock / 64;
+    __shared__ int s_item;  // rays per work item in this sweep
     if (threadIdx.x < 64) {
         // exclusive prefix of the per-entry item counts (wave 0, lane-blocked scan)
         const int ln = threadIdx.x;
         const int per = (E + 63) / 64;
         const int c0 = ln * per, c1 = min(c0 + per, E);
+        // items of kPool chunks only when the sweep has kPool chunks per wave of
+        // the grid; a smaller sweep keeps one chunk per wave so that all its
+        // chunks run at once (every block takes the same decision)
+        int chunks = 0;
+        for (int e = c0; e < c1; ++e) {
+            const int kind = e & 1;
+            const int n = P.active[kind] ? P.q[kind].cnt_in[(e >> 1) * kCntStride] : 0;
+            chunks += (min((long long)n, P.cap) + kChunk - 1) / kChunk;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) chunks += __shfl_xor(chunks, o);
+        const int item = chunks >= kPool * (int)gridDim.x * kWavesPerBlock ? kItem : kChunk;
+        if (ln == 0) s_item = item;
         int local = 0;
         for (int e = c0; e < c1; ++e) {
             const int kind = e & 1;
             const int n = P.active[kind] ? P.q[kind].cnt_in[(e >> 1) * kCntStride] : 0;
             if (n > P.cap) atomicOr(P.overflow, kOverflowQueue);  // never expected: counters are bounded by cap
-            local += (n + kItem - 1) / kItem;
+            local += (n + item - 1) / item;
         }
         int incl = local;
 #pragma unroll
@@ -512,13 +530,14 @@ void k_trace(TraceParams P) {
             s_pref[e] = run;
             const int kind = e & 1;
             const int n = P.active[kind] ? P.q[kind].cnt_in[(e >> 1) * kCntStride] : 0;
-            run += (n + kItem - 1) / kItem;
+            run += (n + item - 1) / item;
         }
         if (ln == 63) s_pref[E] = incl;
     }
     __syncthreads();
     const int total = s_pref[E];
     if (total == 0) return;
+    const int item_rays = s_item;
     if (blockIdx.x == 0 && threadIdx.x < 2 && P.active[threadIdx.x]) {
         // every queued ray is traversed exactly once in this sweep
         unsigned long long n = 0;
@@ -538,7 +557,6 @@ void k_trace(TraceParams P) {
     // static XCD-aware striding: the waves of XCD x walk part x of the item
     // list round-robin (no atomics, so empty and near-empty sweeps cost only
     // the prologue)
-    constexpr int kWavesPerBlock = kTraceBlock / 64;
     const int lw = (blockIdx.x / kXcd) * kWavesPerBlock + (int)(threadIdx.x / 64);
     const int nwx = (gridDim.x / kXcd) * kWavesPerBlock;
     const int lo = (int)((long long)total * xcd / kXcd);
@@ -563,8 +581,8 @@ void k_trace(TraceParams P) {
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
-        const long long first = (long long)(item - s_pref[e]) * kItem;
-        const int count = (int)min((long long)kItem,
+        const long long first = (long long)(item - s_pref[e]) * item_rays;
+        const int count = (int)min((long long)item_rays,
                                    min((long long)P.q[kind].cnt_in[cell * kCntStride], P.cap) - first);
         if (kind == 0)
             trace_item<false, COUNT>(P, P.q[0], cell, first, count, top, stk, gstk, gstride, n_nodes, n_tris,
@@ -638,7 +656,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
             if (prim < 0) {
                 fl = 0;  // no sky dome: a miss carries nothing
             } else {
-                const d3 o{ro.x, ro.y, ro.z}, d{rd.x, rd.y, rd.z};
+                const pv3 o{ro.x, ro.y, ro.z}, d{rd.x, rd.y, rd.z};
                 const float4 pi = P.prim_info[prim];
                 const int word = __float_as_int(pi.w);
                 const int typ = (word >> kMatTypeShift) & 3;
@@ -646,41 +664,44 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                 int m = word & kMatIdMask;
                 if (typ == kGlass && m == P.glass_from) m = P.glass_to;
                 const int emits = (word & kMatEmits) ? kVEmits : 0;
-                // geometry in FP64 from the triangle's vertices: N = (v1 - v0) x (v2 - v0),
-                // the hit point on its plane x = o + t d with t = N.(v0 - o) / N.d (the
-                // FP32 traversal t only chose the triangle), the side the ray came from
-                const d3 v0 = wide(P.prim_v[3 * (size_t)prim]);
-                const d3 N = cross3(wide(P.prim_v[3 * (size_t)prim + 1]) - v0, wide(P.prim_v[3 * (size_t)prim + 2]) - v0);
-                const double nn = dot3(N, N), nd = dot3(N, d);
-                const d3 ng = nn > 0.0 ? N * (1.0 / sqrt(nn)) : wide(xyz(pi));
-                const double cos_o = -dot3(ng, d);
-                const d3 n = cos_o > 0.0 ? ng : ng * -1.0;
-                const d3 x = nd != 0.0 ? o + d * (dot3(N, v0 - o) / nd) : o + d * (double)h.x;
-                d3 xo64 = x, dn64 = d;
+                // geometry in the path state's precision (FP64) from the triangle's
+                // vertices: N = (v1 - v0) x (v2 - v0), the hit point on its plane
+                // x = o + t d with t = N.(v0 - o) / N.d (the FP32 traversal t only
+                // chose the triangle), the side the ray came from
+                const pv3 v0 = state3(P.prim_v[3 * (size_t)prim]);
+                const pv3 N =
+                    cross3(state3(P.prim_v[3 * (size_t)prim + 1]) - v0, state3(P.prim_v[3 * (size_t)prim + 2]) - v0);
+                const preal nn = dot3(N, N), nd = dot3(N, d);
+                const pv3 ng = nn > (preal)0 ? N * ((preal)1 / sqrt(nn)) : state3(xyz(pi));
+                const preal cos_o = -dot3(ng, d);
+                const pv3 n = cos_o > (preal)0 ? ng : ng * (preal)-1;
+                const pv3 x = nd != (preal)0 ? o + d * (dot3(N, v0 - o) / nd) : o + d * (preal)h.x;
+                pv3 xo64 = x, dn64 = d;
                 if (typ == kEmitter) {
-                    rec.x = ((fl & kCountE) && cos_o > 0.0) ? (kVEmit | kVLast | (m << kVIdShift)) : kVNone;
+                    rec.x = ((fl & kCountE) && cos_o > (preal)0) ? (kVEmit | kVLast | (m << kVIdShift)) : kVNone;
                     fl = 0;
                 } else if (typ == kDiffuse) {
                     const uint4 ub = philox4x32_10(make_uint4((uint32_t)pf, (uint32_t)s, (uint32_t)P.depth, 0u), P.key);
-                    xo64 = x + n * (double)kOffset;
+                    xo64 = x + n * (preal)kOffset;
                     xo = narrow(xo64);
                     float gfac = 0.0f;
                     if (P.light_type != 0) {
                         // light sample and geometry term
-                        d3 y{P.lp0[0], P.lp0[1], P.lp0[2]};
+                        pv3 y{(preal)P.lp0[0], (preal)P.lp0[1], (preal)P.lp0[2]};
                         if (P.light_type == 1)
-                            y = y + d3{P.le1[0], P.le1[1], P.le1[2]} * (double)u01(ub.x) +
-                                d3{P.le2[0], P.le2[1], P.le2[2]} * (double)u01(ub.y);
-                        const d3 w = y - xo64;
-                        const double r2 = dot3(w, w);
-                        const double r = sqrt(r2);
-                        const d3 om = w * (1.0 / r);
-                        const double cx = dot3(n, om);
-                        const double cy = P.light_type == 1 ? -dot3(d3{P.nL[0], P.nL[1], P.nL[2]}, om) : 1.0;
-                        if (cx > 0.0 && cy > 0.0) {
+                            y = y + pv3{(preal)P.le1[0], (preal)P.le1[1], (preal)P.le1[2]} * (preal)u01(ub.x) +
+                                pv3{(preal)P.le2[0], (preal)P.le2[1], (preal)P.le2[2]} * (preal)u01(ub.y);
+                        const pv3 w = y - xo64;
+                        const preal r2 = dot3(w, w);
+                        const preal r = sqrt(r2);
+                        const pv3 om = w * ((preal)1 / r);
+                        const preal cx = dot3(n, om);
+                        const preal cy =
+                            P.light_type == 1 ? -dot3(pv3{(preal)P.nL[0], (preal)P.nL[1], (preal)P.nL[2]}, om) : (preal)1;
+                        if (cx > (preal)0 && cy > (preal)0) {
                             // (rho/pi) Le cos_x cos_y / r^2 * A (area light); (rho/pi) I cos_x / r^2 (Eq. 3)
-                            gfac = (float)((P.light_type == 1 ? cx * cy / r2 * P.light_area : cx / r2) *
-                                           (1.0 / 3.14159265358979323846));
+                            gfac = (float)((P.light_type == 1 ? cx * cy / r2 * (preal)P.light_area : cx / r2) *
+                                           (preal)(1.0 / 3.14159265358979323846));
                             sh = kShVisible;
                             ws = narrow(om);
                             r_sh = (float)r;
@@ -712,13 +733,13 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                     } else {
                         const uint4 uc =
                             philox4x32_10(make_uint4((uint32_t)pf, (uint32_t)s, (uint32_t)P.depth, 1u), P.key);
-                        dn64 = cosine_dir64(n, (double)u01(uc.x), (double)u01(uc.y));
+                        dn64 = cosine_dir_state(n, (preal)u01(uc.x), (preal)u01(uc.y));
                         enq_e = true;
                     }
                 } else {  // glass pane
                     // signed cosine: > 0 when the ray meets the normal-side (coated) face
                     const float cabs = (float)fabs(dot3(d, ng));
-                    const float c = cos_o > 0.0 ? cabs : -cabs;
+                    const float c = cos_o > (preal)0 ? cabs : -cabs;
                     float sumR = 0.0f, sumT = 0.0f;
                     for (int l = 0; l < P.nl; ++l) {
                         float Rl, Tl;
@@ -737,18 +758,18 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                         rec = make_int4((refl ? kVGlassR : kVGlassT) | (m << kVIdShift), __float_as_int(c),
                                         __float_as_int(PR), 0);
                         if (refl) {
-                            dn64 = d - ng * (2.0 * dot3(d, ng));
+                            dn64 = d - ng * ((preal)2 * dot3(d, ng));
                             fl |= kCountE;
-                            xo64 = x + n * (double)kOffset;
+                            xo64 = x + n * (preal)kOffset;
                         } else {
-                            xo64 = x - n * (double)kOffset;
+                            xo64 = x - n * (preal)kOffset;
                         }
                         enq_e = true;
                     }
                 }
                 if (enq_e) {
-                    P.ray_o[pid] = D4{xo64.x, xo64.y, xo64.z, 0.0};
-                    P.ray_d[pid] = D4{dn64.x, dn64.y, dn64.z, 0.0};
+                    P.ray_o[pid] = D4{xo64.x, xo64.y, xo64.z, 0};
+                    P.ray_d[pid] = D4{dn64.x, dn64.y, dn64.z, 0};
                     xo = narrow(xo64);
                     dn = narrow(dn64);
                 }

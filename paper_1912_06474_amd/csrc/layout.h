@@ -102,10 +102,17 @@ __host__ __device__ inline int frame_pixel(const PixWindow& w, int pl) {
     return (w.y0 + ly) * w.fw + w.x0 + (pl - ly * w.cw);
 }
 
-// FP64 vector of the per-path ray state (32 B, w unused)
+// vector of the per-path ray state (w unused): FP64, 32 B (FP32, 16 B, in the
+// SDD_PATH_STATE_F32 measurement build)
+#ifdef SDD_PATH_STATE_F32
+struct alignas(16) D4 {
+    float x, y, z, w;
+};
+#else
 struct alignas(32) D4 {
     double x, y, z, w;
 };
+#endif
 
 enum : int { kDiffuse = 0, kGlass = 1, kEmitter = 2 };
 enum : uint32_t { kAlive = 1u, kCountE = 2u, kTrain = 4u };
@@ -132,6 +139,7 @@ enum Stat : int {
     kStatTris,
     kStatNodeSteps,  // wave-level steps (counted by the first active lane)
     kStatTriSteps,
+    kStatNrcRows,    // (path, wavelength) rows of BF16 render queries (cache vertices only)
     kStatCount
 };
 

@@ -103,8 +103,25 @@ hipError_t nrc_launch_query(const NrcNet& net, int n, const float4* cx, const fl
 // path order if ord is null), then the matrix-core network
 hipError_t nrc_launch_query_operands(const NrcNet& net, int n, const float4* cx, const float4* cn, uint4* hop,
                                      uint2* sop, const NrcOrder* ord, hipStream_t st);
+// n_dev (device, nullable): the number of rows to evaluate, read by the kernel
+// (at most n); cp (nullable): row r is the cache vertex of path cp[r], whose
+// values go to lhat[nrc_lhat_index(cp[r], l)]; rows_stat (nullable) gains
+// rows * nl
 hipError_t nrc_launch_query_mfma(const NrcNet& net, int n, const uint4* hop, const uint2* sop, const float* lam,
-                                 int nl, int nlp, float* lhat, int tiled, hipStream_t st);
+                                 int nl, int nlp, float* lhat, int tiled, hipStream_t st, const int* n_dev = nullptr,
+                                 const int* cp = nullptr, unsigned long long* rows_stat = nullptr);
+// Operands of a render's cache query, only for the paths that own a cache
+// vertex (cx[p].w == 1) among its n paths.  flags and rank (n + 1 ints each)
+// number those paths in path order: rank[p] is path p's row, rank[n] the
+// number of rows; cp[row] = p.  The gathers run in the Morton order of ord
+// (31-bit keys: paths without a cache vertex sort last), the operands go to
+// the path's row, so rows keep path order and the query's stores stay runs of
+// neighbouring paths.  ord->temp must hold nrc_order_temp_bytes(n) and
+// nrc_scan_temp_bytes(n + 1) bytes.
+hipError_t nrc_launch_cache_operands(const NrcNet& net, int n, const float4* cx, const float4* cn, uint4* hop,
+                                     uint2* sop, const NrcOrder* ord, int* flags, int* rank, int* cp,
+                                     hipStream_t st);
+size_t nrc_scan_temp_bytes(int n);
 // Allocation-free BF16 query: its scratch (operand staging, sort keys and
 // values, the sort's temporary storage) lives in one file-scope device array
 // of kNoAllocScratchBytes per GPU, held until the process ends.

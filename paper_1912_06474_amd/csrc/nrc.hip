@@ -668,18 +668,14 @@ __global__ __launch_bounds__(kMfmaBlock) void k_infer_mfma(NrcNet net, int n, co
 // the path's 16-column tile reads them: hop[(tile * 4 + g) * 16 + c],
 // sop[(tile * 4 + g) * 16 + c].  A plain gather kernel at full occupancy; the
 // matrix kernel then needs no parking space and no gathers.
-__global__ __launch_bounds__(256) void k_query_operands(NrcNet net, int n, const float4* cx, const float4* cn,
-                                                        uint4* hop, uint2* sop, const int* order) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int p = order ? order[i] : i;  // a permutation of 0 .. n-1
-    const float4 x4 = cx[p], n4 = cn[p];
+__device__ __forceinline__ void query_operands(const NrcNet& net, float4 x4, float4 n4, int row, uint4* hop,
+                                               uint2* sop) {
     const float xp[3] = {x4.x, x4.y, x4.z};
     float xn[3];
     normalise(net, xp, xn);
     float sh[kNrcSh];
     sh_features(net.shK, n4.x, n4.y, n4.z, sh);
-    const size_t slot = (size_t)(p >> 4) * 64 + (p & 15);
+    const size_t slot = (size_t)(row >> 4) * 64 + (row & 15);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         uint32_t w[4];
@@ -696,6 +692,27 @@ __global__ __launch_bounds__(256) void k_query_operands(NrcNet net, int n, const
     }
 }
 
+__global__ __launch_bounds__(256) void k_query_operands(NrcNet net, int n, const float4* cx, const float4* cn,
+                                                        uint4* hop, uint2* sop, const int* order) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int p = order ? order[i] : i;  // a permutation of 0 .. n-1
+    query_operands(net, cx[p], cn[p], p, hop, sop);
+}
+
+// a render's query: gathers in Morton order, operands to the path's row
+__global__ __launch_bounds__(256) void k_cache_operands(NrcNet net, int n, const float4* cx, const float4* cn,
+                                                        uint4* hop, uint2* sop, const int* order, const int* flags,
+                                                        const int* rank, int* cp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int p = order[i];
+    if (!flags[p]) return;  // no cache vertex (these sort last)
+    const int r = rank[p];
+    cp[r] = p;
+    query_operands(net, cx[p], cn[p], r, hop, sop);
+}
+
 // 30-bit Morton code of the normalised cache vertex (10 bits per axis)
 __device__ __forceinline__ uint32_t spread3(uint32_t x) {
     x &= 0x3ffu;
@@ -706,10 +723,7 @@ __device__ __forceinline__ uint32_t spread3(uint32_t x) {
     return x;
 }
 
-__global__ __launch_bounds__(256) void k_query_keys(NrcNet net, int n, const float4* cx, uint32_t* keys, int* vals) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const float4 x4 = cx[p];
+__device__ __forceinline__ uint32_t morton_key(const NrcNet& net, float4 x4) {
     const float xp[3] = {x4.x, x4.y, x4.z};
     float xn[3];
     normalise(net, xp, xn);
@@ -719,8 +733,31 @@ __global__ __launch_bounds__(256) void k_query_keys(NrcNet net, int n, const flo
         const float q = fminf(fmaxf(xn[a] * 1024.0f, 0.0f), 1023.0f);  // NaN -> 0
         m |= spread3((uint32_t)q) << a;
     }
-    keys[p] = m;
+    return m;
+}
+
+__global__ __launch_bounds__(256) void k_query_keys(NrcNet net, int n, const float4* cx, uint32_t* keys, int* vals) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    keys[p] = morton_key(net, cx[p]);
     vals[p] = p;
+}
+
+// keys of a render's query: paths without a cache vertex get bit 30 (last in
+// a 31-bit sort); flags[p] marks the others, flags[n] = 0 closes the scan
+__global__ __launch_bounds__(256) void k_cache_keys(NrcNet net, int n, const float4* cx, uint32_t* keys, int* vals,
+                                                    int* flags) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > n) return;
+    if (p == n) {
+        flags[n] = 0;
+        return;
+    }
+    const float4 x4 = cx[p];
+    const bool has = x4.w == 1.0f;
+    keys[p] = has ? morton_key(net, x4) : (1u << 30);
+    vals[p] = p;
+    flags[p] = has;
 }
 
 // Cache values of n paths at every wavelength: lhat[path][l], from the
@@ -730,13 +767,25 @@ __global__ __launch_bounds__(256) void k_query_keys(NrcNet net, int n, const flo
 // the weights, so three blocks fit a CU.  Same products and summation order
 // as k_infer_mfma.
 __global__ __launch_bounds__(kMfmaBlock) __attribute__((amdgpu_waves_per_eu(3)))
-void k_query_mfma(NrcNet net, int n, const uint4* hop, const uint2* sop,
-                                                          const float* lam, int nl, int nlp, float* lhat, int tiled) {
+void k_query_mfma(NrcNet net, int n, const uint4* hop, const uint2* sop, const float* lam, int nl, int nlp,
+                  float* lhat, int tiled, const int* n_dev, const int* cp, unsigned long long* rows_stat) {
+    if (n_dev) n = min(n, *n_dev);
+    if (rows_stat && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(rows_stat, (unsigned long long)n * nl);
+    const long long first_row = (long long)blockIdx.x * kMfmaBlock / 64 * kMfmaRowsPerWave;
+    if (first_row >= n) return;  // whole block idle (before the staging barrier)
     __shared__ MfmaLds L;
     mfma_stage(net, L);
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
     const long long base = ((long long)blockIdx.x * (kMfmaBlock / 64) + wv) * kMfmaRowsPerWave;
     if (base >= n) return;  // whole wave idle (no barrier follows)
+    // where each tile's column c goes: lhat[dst[nt] + l * lstep] (no store for dst < 0)
+    long long dst[4];
+    const int lstep = tiled ? 16 : 1;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const long long row = base + nt * 16 + c;
+        dst[nt] = row < n ? (long long)nrc_lhat_index(cp ? (long long)cp[row] : row, 0, nlp, tiled) : -1;
+    }
     bf16x8 hq[4];           // step-0 operand per tile
     uint2 shq[4];           // harmonics per tile
 #pragma unroll
@@ -777,10 +826,8 @@ void k_query_mfma(NrcNet net, int n, const uint4* hop, const uint2* sop,
         float out[4];
         mfma_rest(L, lane, g, z0, bo, out);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const long long row = base + nt * 16 + c;
-            if (g == 0 && row < n) lhat[nrc_lhat_index(row, l, nlp, tiled)] = out[nt];
-        }
+        for (int nt = 0; nt < 4; ++nt)
+            if (g == 0 && dst[nt] >= 0) lhat[dst[nt] + (long long)l * lstep] = out[nt];
     }
 }
 
@@ -892,12 +939,46 @@ hipError_t nrc_launch_query(const NrcNet& net, int n, const float4* cx, const fl
     return nrc_launch_query_mfma(net, n, hop, sop, lam, nl, nlp, lhat, tiled, st);
 }
 
+// sort keys are 31 bits: 30 of Morton code, and bit 30 for paths without a
+// cache vertex (render queries)
+constexpr int kOrderBits = 31;
+
 size_t nrc_order_temp_bytes(int n) {
     size_t bytes = 0;
     hipcub::DoubleBuffer<uint32_t> kb(nullptr, nullptr);
     hipcub::DoubleBuffer<int> vb(nullptr, nullptr);
-    if (hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kb, vb, n, 0, 30) != hipSuccess) return 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kb, vb, n, 0, kOrderBits) != hipSuccess) return 0;
     return bytes;
+}
+
+size_t nrc_scan_temp_bytes(int n) {
+    size_t bytes = 0;
+    if (hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, (const int*)nullptr, (int*)nullptr, n) != hipSuccess)
+        return 0;
+    return bytes;
+}
+
+hipError_t nrc_launch_cache_operands(const NrcNet& net, int n, const float4* cx, const float4* cn, uint4* hop,
+                                     uint2* sop, const NrcOrder* ord, int* flags, int* rank, int* cp,
+                                     hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (!ord || nrc_order_temp_bytes(n) > ord->temp_bytes || nrc_scan_temp_bytes(n + 1) > ord->temp_bytes)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cache_keys, dim3(nblocks((long long)n + 1, 256)), dim3(256), 0, st, net, n, cx, ord->keys,
+                       ord->vals, flags);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t bytes = ord->temp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(ord->temp, bytes, (const int*)flags, rank, n + 1, st);
+    if (e != hipSuccess) return e;
+    hipcub::DoubleBuffer<uint32_t> kb(ord->keys, ord->keys + n);
+    hipcub::DoubleBuffer<int> vb(ord->vals, ord->vals + n);
+    bytes = ord->temp_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(ord->temp, bytes, kb, vb, n, 0, kOrderBits, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cache_operands, dim3(nblocks(n, 256)), dim3(256), 0, st, net, n, cx, cn, hop, sop,
+                       (const int*)vb.Current(), (const int*)flags, (const int*)rank, cp);
+    return hipGetLastError();
 }
 
 hipError_t nrc_launch_query_operands(const NrcNet& net, int n, const float4* cx, const float4* cn, uint4* hop,
@@ -912,7 +993,7 @@ hipError_t nrc_launch_query_operands(const NrcNet& net, int n, const float4* cx,
         hipcub::DoubleBuffer<uint32_t> kb(ord->keys, ord->keys + n);
         hipcub::DoubleBuffer<int> vb(ord->vals, ord->vals + n);
         size_t bytes = ord->temp_bytes;
-        e = hipcub::DeviceRadixSort::SortPairs(ord->temp, bytes, kb, vb, n, 0, 30, st);
+        e = hipcub::DeviceRadixSort::SortPairs(ord->temp, bytes, kb, vb, n, 0, kOrderBits, st);
         if (e != hipSuccess) return e;
         order = vb.Current();  // the buffer the last pass wrote (chosen on the host)
     }
@@ -921,11 +1002,12 @@ hipError_t nrc_launch_query_operands(const NrcNet& net, int n, const float4* cx,
 }
 
 hipError_t nrc_launch_query_mfma(const NrcNet& net, int n, const uint4* hop, const uint2* sop, const float* lam,
-                                 int nl, int nlp, float* lhat, int tiled, hipStream_t st) {
+                                 int nl, int nlp, float* lhat, int tiled, hipStream_t st, const int* n_dev,
+                                 const int* cp, unsigned long long* rows_stat) {
     if (n <= 0 || nl <= 0) return hipSuccess;
     const int rows_per_block = (kMfmaBlock / 64) * kMfmaRowsPerWave;
     hipLaunchKernelGGL(k_query_mfma, dim3(nblocks(n, rows_per_block)), dim3(kMfmaBlock), 0, st, net, n, hop, sop,
-                       lam, nl, nlp, lhat, tiled);
+                       lam, nl, nlp, lhat, tiled, n_dev, cp, rows_stat);
     return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ import pytest
 
 import oracle as ora
 import scenegen as sg
+from oracle import nrc as onrc
 from parity import ParityCtx, assert_parity
 
 pytestmark = pytest.mark.gpu
@@ -119,10 +120,10 @@ def test_bf16_query_after_a_larger_query(tracer):
 
 
 def _gpu_nrc_render(tracer, sc, W, H, spp, D, grid, train_paths, precision="fp32", seed=0, steps=0,
-                    sample_offset=0):
+                    sample_offset=0, net=None):
     tracer.load_scene(sc)
     tracer.build_bvh(*grid)
-    params, tables = affine_net(COEF)
+    params, tables = net if net is not None else affine_net(COEF)
     tracer.nrc_init(params, tables, LO, HI, train_paths=train_paths, train_steps=steps, precision=precision)
     hl = tracer.new_log(W, H, spp, D)
     sl = tracer.new_log(W, H, spp, D)
@@ -196,6 +197,58 @@ def test_bf16_queries_and_training_in_the_render(tracer):
     assert diff <= 0.1
     assert steps == 3 and np.isfinite(loss) and len(rows) > 0
     assert not np.array_equal(t1, tables)  # the tables moved
+
+
+def test_bf16_render_queries_only_cache_vertices(tracer):
+    """The BF16 render query evaluates exactly the paths that own a cache
+    vertex -- a path other than a training path, at its first diffuse vertex
+    of depth >= 2, read off the hit log -- and each value reaches its own
+    path: against the FP32 render every pixel moves by no more than BF16
+    operands move the network, while the cache itself differs by up to 1.2
+    between cache vertices (a value sent to another path shows)."""
+    sc = sg.tiny_room(0, 16)
+    W, H, spp, D = 64, 48, 3, 5
+    train = 700
+    coef = (1.0, 0.5, -0.4, 0.3, 0.0, 0.0, 0.0)
+    net = affine_net(coef, offset=1.0)  # hidden unit in [0.6, 1.8]: BF16 ulp 2^-7
+    nl = len(sc["lambda_nm"])
+    g32, _, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), train, net=net)
+    tracer.reset_stats()
+    g16, _, _, _ = _gpu_nrc_render(tracer, sc, W, H, spp, D, (2, 2, 1), train, precision="bf16", net=net)
+    st = tracer.stats()
+    assert np.array_equal(g16["hit_log"], g32["hit_log"])
+    hl = g16["hit_log"]  # [pixel][sample][depth]
+    stride = -(-(W * H * spp) // train)
+    q = np.arange(spp)[None, :] * (W * H) + np.arange(W * H)[:, None]
+    ttype = np.asarray(sc["mat_type"])[np.asarray(sc["tri_mat"])]
+    diffuse = (hl >= 0) & (ttype[np.maximum(hl, 0)] == sg.DIFFUSE)
+    has_cache = (q % stride != 0) & diffuse[:, :, 1:].any(axis=2)
+    print(f"[nrc_render] {int(has_cache.sum())} of {W * H * spp} paths own a cache vertex; "
+          f"{st['nrc_query_rows'] // nl} queried", flush=True)
+    assert st["nrc_query_rows"] == int(has_cache.sum()) * nl
+    assert 0 < has_cache.sum() < W * H * spp
+    # How far BF16 operands move this network from its FP64 value over the
+    # room (positions, normals, wavelengths): the tolerance is 4x the largest
+    # such move, far below the spread of the cache itself.  A pixel is a mean
+    # of path values whose cache terms carry a throughput <= 1, so it moves by
+    # no more than one cache value does.  (The BF16 forward's own accuracy is
+    # judged against its derived bound in the network tests.)
+    params, tables = net
+    p64 = {"W": [np.asarray(w, np.float64) for w in params["W"]],
+           "b": [np.asarray(b, np.float64) for b in params["b"]],
+           "wo": np.asarray(params["wo"], np.float64), "bo": float(params["bo"])}
+    t64 = np.asarray(tables, np.float64)
+    x, w, lam, _ = sg.nrc_rows(20000, 5, LO, HI)
+    X = onrc.encode(x, w, lam, LO, HI, t64)
+    yo, _ = onrc.mlp_forward(p64, X)
+    yb = onrc.mlp_forward_bf16(p64, X.astype(np.float32).astype(np.float64))
+    tol = 4.0 * float(np.abs(yb - yo).max())
+    spread = float(yo.max() - yo.min())
+    diff = float(np.abs(g16["spectral"] - g32["spectral"]).max())
+    print(f"[nrc_render] bf16 vs fp32 render: max |dL| {diff:.3e}, bound {tol:.3e}, cache spread {spread:.3f}",
+          flush=True)
+    assert spread > 20 * tol
+    assert diff <= tol
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
