@@ -60,7 +60,7 @@ WORKLOADS = {
     # radiance cache vs plain at equal image quality: 1M triangles, 1920 x 1080,
     # 4 spp per frame, 41 wavelengths, paths end in the cache after vertex 2
     "nrc_room": dict(scene=("nrc_room", dict(seed=3, n_lambda=41)), W=1920, H=1080, spp=4, D=8, grid=(4, 4, 2),
-                     nrc=dict(ref_frames=64, train_paths=1 << 16, train_steps=4, train_batch=1 << 14,
+                     nrc=dict(ref_frames=64, train_paths=1 << 16, train_steps=8, train_batch=1 << 14,
                               train_warmup=100)),
 }
 
@@ -579,7 +579,7 @@ def main():
                          "as many; default 64)")
     ap.add_argument("--frames-per-step", type=int, default=FRAMES_PER_STEP,
                     help="nrc_room: frames of each method per step (default %(default)s)")
-    ap.add_argument("--nrc-train-steps", type=int, default=None, help="nrc_room: Adam steps per frame (default 4)")
+    ap.add_argument("--nrc-train-steps", type=int, default=None, help="nrc_room: Adam steps per frame (default 8)")
     ap.add_argument("--nrc-train-batch", type=int, default=None, help="nrc_room: rows per Adam step (default 2^14)")
     ap.add_argument("--nrc-lr", type=float, default=None, help="nrc_room: Adam learning rate (default 1e-2)")
     ap.add_argument("--nrc-warmup", type=int, default=None,

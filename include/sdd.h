@@ -472,8 +472,14 @@ sdd_status sdd_nrc_train_step(sdd_ctx *ctx, int32_t n, const float *x, const flo
  * word 0 mod n_lambda): target the radiance the path carries back into the
  * vertex along its continuation, at l, the same terms the estimator adds.
  * After the call, S = train_steps Adam steps run on the call's rows: step k
- * on rows (k + i S) m, i < train_batch, m = max(1, rows / (S train_batch)).  Gradient sums use atomics, so trained caches
- * differ between runs by rounding.
+ * on rows (k + i S) m, i < train_batch, m = max(1, rows / (S train_batch)).
+ * The rows are compacted and counted on the context's stream before the call
+ * returns; the steps then run on a stream of the context's own (default
+ * priority), ordered after the rows by an event, so they overlap the next
+ * call's tracing.  The next cache render waits for them on the device before
+ * its cache query; every sdd_nrc_* call, sdd_get_stats and sdd_reset_stats
+ * wait for them on the host first.  Gradient sums use atomics, so trained
+ * caches differ between runs by rounding.
  */
 
 /* Cache values of n surface points at every wavelength of the loaded scene,

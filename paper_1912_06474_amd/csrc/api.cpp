@@ -168,6 +168,12 @@ struct sdd_ctx {
     long long nrc_last_rows = 0;
     int nrc_last_steps = 0;
     float nrc_last_loss = 0.0f;
+    // the Adam steps after a cache render run on a stream of their own and
+    // overlap the next call's tracing: nrc_pending until ev_trained is waited for
+    hipStream_t nrc_stream = nullptr;
+    hipEvent_t nrc_ev_rows = nullptr, nrc_ev_trained = nullptr;
+    bool nrc_pending = false;
+    float* nrc_h_loss = nullptr;  // pinned: the last step's loss
     float* d_lam = nullptr;  // scene wavelengths (nm), FP32
     uint4* nrc_hop = nullptr;  // staged matrix operands of cache queries
     uint2* nrc_sop = nullptr;
@@ -341,6 +347,8 @@ void free_batch(sdd_ctx* c) {
     c->batch_bytes = 0;
 }
 
+hipError_t nrc_wait_host(sdd_ctx* c);
+
 void free_nrc_batch(sdd_ctx* c) {
     dfree(c, c->nrc_acts);
     dfree(c, c->nrc_dz);
@@ -370,6 +378,14 @@ void free_nrc_render(sdd_ctx* c) {
 }
 
 void free_nrc(sdd_ctx* c) {
+    (void)nrc_wait_host(c);
+    if (c->nrc_stream) (void)hipStreamDestroy(c->nrc_stream);
+    if (c->nrc_ev_rows) (void)hipEventDestroy(c->nrc_ev_rows);
+    if (c->nrc_ev_trained) (void)hipEventDestroy(c->nrc_ev_trained);
+    if (c->nrc_h_loss) (void)hipHostFree(c->nrc_h_loss);
+    c->nrc_stream = nullptr;
+    c->nrc_ev_rows = c->nrc_ev_trained = nullptr;
+    c->nrc_h_loss = nullptr;
     free_nrc_render(c);
     dfree(c, c->nrc_hop);
     dfree(c, c->nrc_sop);
@@ -499,20 +515,38 @@ void harvest_events(sdd_ctx* c) {
 struct Timer {
     sdd_ctx* c;
     bool on;
+    hipStream_t st;
     TimedLaunch t{};
-    Timer(sdd_ctx* ctx, bool enabled, int cls) : c(ctx), on(enabled) {
+    Timer(sdd_ctx* ctx, bool enabled, int cls, hipStream_t stream = nullptr)
+        : c(ctx), on(enabled), st(stream ? stream : ctx->stream) {
         if (!on) return;
         t.cls = cls;
         t.a = take_event(c);
         t.b = take_event(c);
-        if (t.a) (void)hipEventRecord(t.a, c->stream);
+        if (t.a) (void)hipEventRecord(t.a, st);
     }
     ~Timer() {
         if (!on) return;
-        if (t.b) (void)hipEventRecord(t.b, c->stream);
+        if (t.b) (void)hipEventRecord(t.b, st);
         c->timed.push_back(t);
     }
 };
+
+// The cache's Adam steps after a render (nrc_train_after_call) may still run
+// on c->nrc_stream.  nrc_wait_gpu orders the context stream after them (the
+// next render's cache query); nrc_wait_host waits for them on the host (every
+// API call that reads, changes or frees the cache, and statistics).
+void nrc_wait_gpu(sdd_ctx* c) {
+    if (c->nrc_pending) (void)hipStreamWaitEvent(c->stream, c->nrc_ev_trained, 0);
+}
+
+hipError_t nrc_wait_host(sdd_ctx* c) {
+    if (!c->nrc_pending) return hipSuccess;
+    const hipError_t e = hipEventSynchronize(c->nrc_ev_trained);
+    c->nrc_pending = false;
+    if (c->nrc_h_loss) c->nrc_last_loss = *c->nrc_h_loss;
+    return e;
+}
 
 // Device memory the path batch (queues, path state, history) may take:
 // SDD_MEM_BUDGET_GB if set, else half the device's memory, at most three
@@ -1206,6 +1240,8 @@ NrcOrder nrc_order(sdd_ctx* c) { return NrcOrder{c->nrc_okeys, c->nrc_ovals, c->
 // last batch), slots training paths of depth D
 sdd_status nrc_ensure_render(sdd_ctx* c, long long n, long long n_last, long long slots, int D) {
     sdd_status st;
+    if (n > c->nrc_pcap || slots > c->nrc_scap || D > c->nrc_dcap || c->nrc_train_batch > c->nrc_bcap)
+        HIP_TRY(c, nrc_wait_host(c));  // buffers the pending Adam steps may still read
     if (n > c->nrc_pcap) {
         dfree(c, c->nrc_cx);
         dfree(c, c->nrc_cn);
@@ -1260,8 +1296,12 @@ sdd_status nrc_ensure_render(sdd_ctx* c, long long n, long long n_last, long lon
 
 // After a cache render: compact the training rows the call produced and take
 // up to train_steps Adam steps (S), step k on rows (k + i S) m, i < train_batch,
-// with m = max(1, rows / (S train_batch)): spread over the whole image.
+// with m = max(1, rows / (S train_batch)): spread over the whole image.  The
+// rows are compacted and counted on the context stream; the steps then run
+// on c->nrc_stream, after an event on the context stream, so they overlap
+// the next call's tracing (its cache query waits for them: nrc_wait_gpu).
 sdd_status nrc_train_after_call(sdd_ctx* c, long long n_rows, bool timing) {
+    HIP_TRY(c, nrc_wait_host(c));
     c->nrc_last_rows = 0;
     c->nrc_last_steps = 0;
     c->nrc_last_loss = 0.0f;
@@ -1281,33 +1321,38 @@ sdd_status nrc_train_after_call(sdd_ctx* c, long long n_rows, bool timing) {
     if (S <= 0) return SDD_OK;
     sdd_status st = nrc_reserve(c, c->nrc_train_batch);
     if (st != SDD_OK) return st;
+    if (!c->nrc_stream) {  // the training stream, at the default priority
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->nrc_stream, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->nrc_ev_rows, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->nrc_ev_trained, hipEventDisableTiming));
+        HIP_TRY(c, hipHostMalloc((void**)&c->nrc_h_loss, sizeof(float), hipHostMallocDefault));
+        *c->nrc_h_loss = 0.0f;
+    }
+    hipStream_t ts = c->nrc_stream;
+    HIP_TRY(c, hipEventRecord(c->nrc_ev_rows, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(ts, c->nrc_ev_rows, 0));
     // more rows than S steps take: every m-th row (spread over the whole image)
     const long long used = (long long)S * c->nrc_train_batch;
     const int m = count > used ? (int)(count / used) : 1;
-    double loss_sum = 0.0;
     for (int k = 0; k < S; ++k) {
         const int nk = (int)std::min<long long>(c->nrc_train_batch, ((long long)count / m - k + S - 1) / S);
         c->nrc_train_rows += nk;
-        Timer tm(c, timing, 5);
-        HIP_TRY(c, nrc_launch_unpack(c->nrc_crows, k, S, m, nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt,
-                                     c->stream));
+        Timer tm(c, timing, 5, ts);
+        HIP_TRY(c, nrc_launch_unpack(c->nrc_crows, k, S, m, nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt, ts));
         NrcBatch b{nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt, c->nrc_acts, c->nrc_dz, c->nrc_y, c->nrc_dy,
                    c->nrc_loss};
-        HIP_TRY(c, nrc_launch_zero(c->nrc.g, c->nrc.n_all, c->stream));
-        HIP_TRY(c, nrc_launch_zero(c->nrc_loss, 1, c->stream));
-        HIP_TRY(c, nrc_launch_grad(c->nrc, b, c->stream));
-        HIP_TRY(c, nrc_launch_adam(c->nrc, c->nrc_t + 1, c->nrc_lr, c->nrc_b1, c->nrc_b2, c->nrc_eps, c->stream));
-        HIP_TRY(c, nrc_launch_pack(c->nrc, c->stream));
+        HIP_TRY(c, nrc_launch_zero(c->nrc.g, c->nrc.n_all, ts));
+        HIP_TRY(c, nrc_launch_zero(c->nrc_loss, 1, ts));
+        HIP_TRY(c, nrc_launch_grad(c->nrc, b, ts));
+        HIP_TRY(c, nrc_launch_adam(c->nrc, c->nrc_t + 1, c->nrc_lr, c->nrc_b1, c->nrc_b2, c->nrc_eps, ts));
+        HIP_TRY(c, nrc_launch_pack(c->nrc, ts));
         ++c->nrc_t;
-        if (k == S - 1) {  // the last step's loss (one read-back per call)
-            float l = 0.0f;
-            HIP_TRY(c, hipMemcpyAsync(&l, c->nrc_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
-            HIP_TRY(c, hipStreamSynchronize(c->stream));
-            loss_sum = l;
-        }
     }
+    // the last step's loss, read when asked for (nrc_wait_host)
+    HIP_TRY(c, hipMemcpyAsync(c->nrc_h_loss, c->nrc_loss, sizeof(float), hipMemcpyDeviceToHost, ts));
+    HIP_TRY(c, hipEventRecord(c->nrc_ev_trained, ts));
+    c->nrc_pending = true;
     c->nrc_last_steps = S;
-    c->nrc_last_loss = (float)loss_sum;
     return SDD_OK;
 }
 
@@ -1571,6 +1616,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
         st = run_sweeps(c, -1, ph_sh(D), cap, count, timing, D, N);
         if (st != SDD_OK) return st;
         if (nrc) {  // cache values at the batch's cache vertices, every wavelength
+            nrc_wait_gpu(c);  // the previous call's Adam steps (on the training stream)
             ++c->nrc_query_launches;
             if (c->nrc_precision == 0) {
                 c->nrc_query_rows += (long long)N * c->nl;  // every path slot
@@ -2179,6 +2225,7 @@ sdd_status sdd_get_stats(sdd_ctx* c, sdd_stats* out) {
     if (!c || !out) return SDD_ERR_INVALID_ARG;
     DeviceGuard g(c->device);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, nrc_wait_host(c));
     harvest_events(c);
     unsigned long long s[kStatCount];
     HIP_TRY(c, hipMemcpy(s, c->d_stats, sizeof(s), hipMemcpyDeviceToHost));
@@ -2220,6 +2267,7 @@ sdd_status sdd_reset_stats(sdd_ctx* c) {
     if (!c) return SDD_ERR_INVALID_ARG;
     DeviceGuard g(c->device);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, nrc_wait_host(c));
     harvest_events(c);
     HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, sizeof(unsigned long long) * kStatCount, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d_ovf_stats, 0, sizeof(int), c->stream));
@@ -2418,6 +2466,7 @@ void sh_constants(float* K) {
 
 sdd_status nrc_reserve(sdd_ctx* c, long long n) {
     if (n <= c->nrc_cap) return SDD_OK;
+    HIP_TRY(c, nrc_wait_host(c));
     free_nrc_batch(c);
     sdd_status st;
     if ((st = dalloc(c, &c->nrc_acts, (size_t)(kNrcLayers + 1) * kNrcHid * n)) != SDD_OK ||
@@ -2516,6 +2565,7 @@ sdd_status sdd_nrc_infer(sdd_ctx* c, int32_t n, const float* x, const float* w, 
     if (!c) return SDD_ERR_INVALID_ARG;
     c->err.clear();
     if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_infer before sdd_nrc_init");
+    HIP_TRY(c, nrc_wait_host(c));  // the Adam steps of the last cache render
     if (n < 0 || (n > 0 && (!x || !w || !lam || !y))) return fail(c, SDD_ERR_INVALID_ARG, "bad rows");
     if (precision != 0 && precision != 1) return fail(c, SDD_ERR_INVALID_ARG, "precision must be 0 or 1");
     if (n == 0) return SDD_OK;
@@ -2531,6 +2581,7 @@ sdd_status sdd_nrc_train_step(sdd_ctx* c, int32_t n, const float* x, const float
     if (!c) return SDD_ERR_INVALID_ARG;
     c->err.clear();
     if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_train_step before sdd_nrc_init");
+    HIP_TRY(c, nrc_wait_host(c));  // the Adam steps of the last cache render
     if (n < 1 || n > kNrcMaxRows) return fail(c, SDD_ERR_INVALID_ARG, "n out of range");
     if (!x || !w || !lam || !t) return fail(c, SDD_ERR_INVALID_ARG, "null rows");
     DeviceGuard g(c->device);
@@ -2557,6 +2608,7 @@ sdd_status sdd_nrc_query(sdd_ctx* c, int32_t n, const float* x4, const float* n4
     if (!c) return SDD_ERR_INVALID_ARG;
     c->err.clear();
     if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_query before sdd_nrc_init");
+    HIP_TRY(c, nrc_wait_host(c));  // the Adam steps of the last cache render
     if (!c->has_scene) return fail(c, SDD_ERR_STATE, "sdd_nrc_query before sdd_load_scene (wavelengths)");
     if (n < 0 || (n > 0 && (!x4 || !n4 || !out))) return fail(c, SDD_ERR_INVALID_ARG, "bad arguments");
     if (precision != 0 && precision != 1) return fail(c, SDD_ERR_INVALID_ARG, "precision must be 0 or 1");
@@ -2579,6 +2631,7 @@ sdd_status sdd_nrc_query_noalloc(sdd_ctx* c, int32_t n, const float* x4, const f
     if (!c) return SDD_ERR_INVALID_ARG;
     c->err.clear();
     if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_query_noalloc before sdd_nrc_init");
+    HIP_TRY(c, nrc_wait_host(c));  // the Adam steps of the last cache render
     if (!c->has_scene) return fail(c, SDD_ERR_STATE, "sdd_nrc_query_noalloc before sdd_load_scene (wavelengths)");
     if (n < 0 || (n > 0 && (!x4 || !n4 || !out))) return fail(c, SDD_ERR_INVALID_ARG, "bad arguments");
     if (n > SDD_NRC_NOALLOC_MAX_PATHS)
@@ -2603,6 +2656,7 @@ sdd_status sdd_nrc_last_rows(sdd_ctx* c, int32_t max_rows, float* rows, int32_t*
     if (!c) return SDD_ERR_INVALID_ARG;
     c->err.clear();
     if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_last_rows before sdd_nrc_init");
+    HIP_TRY(c, nrc_wait_host(c));  // the Adam steps of the last cache render
     if (max_rows < 0 || (max_rows > 0 && !rows)) return fail(c, SDD_ERR_INVALID_ARG, "bad arguments");
     DeviceGuard g(c->device);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -2622,6 +2676,7 @@ sdd_status sdd_nrc_get_params(sdd_ctx* c, int32_t which, float* out) {
     if (!c) return SDD_ERR_INVALID_ARG;
     c->err.clear();
     if (!c->has_nrc) return fail(c, SDD_ERR_STATE, "sdd_nrc_get_params before sdd_nrc_init");
+    HIP_TRY(c, nrc_wait_host(c));  // the Adam steps of the last cache render
     if (which < 0 || which > 3 || !out) return fail(c, SDD_ERR_INVALID_ARG, "bad arguments");
     DeviceGuard g(c->device);
     const float* src = which == 0 ? c->nrc.p : which == 1 ? c->nrc.g : which == 2 ? c->nrc.m : c->nrc.v;
