@@ -161,6 +161,40 @@ def cpu_baseline(scene, wl, target_s=15.0):
                       f"{nl} wavelengths, FP64, {rays} rays in {dt:.2f} s"}
 
 
+def cpu_oracle_cases():
+    """The FP64 oracle on the comparison cases it is held against: the tiny
+    parity room's whole frame, and the 4M-triangle electrochromic frame at its
+    64 spp on the 64 x 36 centre of the 256 x 144 window the GPU is compared
+    on (the whole window, 16 times the pixels, takes about two minutes on 8
+    cores; its time is extrapolated).  Scene generation and the oracle's BVH
+    are not timed."""
+    import oracle
+    import scenegen
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    cases = []
+    for name, make, W, H, spp, D, crop in (
+            ("tiny_room whole frame", lambda: scenegen.tiny_room(), 64, 64, 1, 4, None),
+            ("electrochromic_room 64x36 centre of the 256x144 window", lambda: scenegen.electrochromic_room(), 3840,
+             2160, 64, 8, (1472, 966, 64, 36))):
+        sc = make()
+        osc = oracle.OracleScene(sc)
+        _ = osc.accel
+        t0 = time.perf_counter()
+        r = oracle.render(sc, W, H, spp, D, crop=crop, oscene=osc, n_threads=threads)
+        dt = time.perf_counter() - t0
+        rays = r["n_ext_rays"] + r["n_shadow_rays"]
+        nl = len(sc["lambda_nm"])
+        px = crop[2] * crop[3] if crop else W * H
+        log(f"[cpu_baseline] {name}: {dt:.2f} s")
+        c = {"case": f"{name}: {len(sc['tris'])} tris, {px} px x {spp} spp, depth {D}, {nl} lambda",
+             "seconds": dt, "rays": rays, "rays_lambda_per_s": rays * nl / dt, "cores": threads}
+        if crop:
+            c["seconds_whole_256x144_window_est"] = dt * (256 * 144) / px
+        cases.append(c)
+    return cases
+
+
 def relmse_fit(hist, floor=True):
     """Least-squares fit of rel-MSE(n) ~ a + b / n over frames n (a = 0 if not floor)."""
     import numpy as np
@@ -264,6 +298,8 @@ def nrc_comparison(args, tr, scene, wl):
     cfg["lr"] = args.nrc_lr if args.nrc_lr is not None else 1e-2
     if args.nrc_warmup is not None:
         cfg["train_warmup"] = args.nrc_warmup
+    if args.nrc_table_fp16 is not None:
+        cfg["table_fp16"] = bool(args.nrc_table_fp16)
     nl = len(scene["lambda_nm"])
     cam = scene["camera"]
     frames = args.frames_per_step * max(args.steps, 2)
@@ -276,7 +312,8 @@ def nrc_comparison(args, tr, scene, wl):
     def init_cache():
         params, tables = scenegen.nrc_params(0)
         tr.nrc_init(params, tables, ROOM_LO, ROOM_HI, lr=cfg["lr"], train_paths=cfg["train_paths"],
-                    train_steps=cfg["train_steps"], train_batch=cfg["train_batch"], precision="bf16")
+                    train_steps=cfg["train_steps"], train_batch=cfg["train_batch"], precision="bf16",
+                    table_fp16=cfg.get("table_fp16", False))
 
     t0 = time.perf_counter()
     refs = []
@@ -401,7 +438,8 @@ def nrc_comparison(args, tr, scene, wl):
                       "ms_query_mfma_per_frame": stn["ms_nrc_query"] / (frames + cfg["train_warmup"]),
                       "ms_train_per_frame": stn["ms_nrc_train"] / (frames + cfg["train_warmup"])},
             "speedup_to_1pct": (t1_plain / t1_nrc) if (t1_nrc and t1_plain) else None,
-            "cache_settings": {k: cfg[k] for k in ("train_paths", "train_steps", "train_batch", "lr")},
+            "cache_settings": {k: cfg.get(k) for k in ("train_paths", "train_steps", "train_batch", "lr",
+                                                       "table_fp16")},
         },
         "roofline": rt if dominant == "trace" else rq,
         "roofline_query": rq,
@@ -582,6 +620,8 @@ def main():
     ap.add_argument("--nrc-train-steps", type=int, default=None, help="nrc_room: Adam steps per frame (default 8)")
     ap.add_argument("--nrc-train-batch", type=int, default=None, help="nrc_room: rows per Adam step (default 2^14)")
     ap.add_argument("--nrc-lr", type=float, default=None, help="nrc_room: Adam learning rate (default 1e-2)")
+    ap.add_argument("--nrc-table-fp16", type=int, choices=[0, 1], default=None,
+                    help="nrc_room: 1 = BF16 queries gather from an FP16 copy of the hash tables")
     ap.add_argument("--nrc-warmup", type=int, default=None,
                     help="nrc_room: cache training frames before accumulation (default 100; their time counts)")
     ap.add_argument("--autotune", nargs="?", const="", default=None, metavar="FILE",
@@ -618,6 +658,7 @@ def main():
         res["build_bvh_s"] = build_s
         if cpu_s > 0:
             res["cpu_baseline"] = cpu_baseline(scene, wl, cpu_s)
+            res["cpu_oracle_cases"] = cpu_oracle_cases()
         tr.close()
         del scene
         if not args.no_plain_line:

@@ -431,6 +431,9 @@ typedef struct sdd_nrc_desc {
     int32_t train_steps;           /* Adam steps after each call (>= 0) */
     int32_t train_batch;           /* rows per step, 1..2^22 */
     int32_t precision;             /* cache queries: 0 FP32, 1 BF16 matrix cores */
+    int32_t table_fp16;            /* 1: BF16 queries and BF16 rows gather the hash features from an FP16
+                                      copy of the tables (round to nearest, refreshed after every Adam
+                                      step); the FP32 tables stay the training copy.  0: FP32 tables */
 } sdd_nrc_desc;
 
 /* Parameter count for a table size; -1 if table_log2 is out of range. */

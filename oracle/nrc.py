@@ -180,7 +180,7 @@ def gamma(m, u=U_FP32):
     return m * u / (1.0 - m * u)
 
 
-def encode_error_bound(x, aabb_lo, aabb_hi, tables, n_sh_abs=4e-6, n_blob_abs=4e-6):
+def encode_error_bound(x, aabb_lo, aabb_hi, tables, n_sh_abs=4e-6, n_blob_abs=4e-6, table_u=0.0):
     """Bound on |X_fp32 - X| for the network input as an FP32 kernel encodes it.
 
     * position: xn = (x - lo) * (1 / (hi - lo)) in FP32 carries at most three
@@ -193,7 +193,11 @@ def encode_error_bound(x, aabb_lo, aabb_hi, tables, n_sh_abs=4e-6, n_blob_abs=4e
       gamma_11 max|t_l|;
     * harmonics and one-blob bins: FP32 evaluation of bounded polynomials and
       of exp(-d^2 / 2) (derivative at most 0.61), a few ulp of terms below 3:
-      n_sh_abs and n_blob_abs absolute.
+      n_sh_abs and n_blob_abs absolute;
+    * table_u > 0: the kernel reads the table entries rounded to a format of
+      unit roundoff table_u (FP16: 2^-11); each corner value moves by at most
+      table_u |t|, so the interpolant (weights summing to 1) by at most
+      table_u max|t_l|.
     """
     n = len(np.asarray(x))
     E = np.zeros((n, N_IN))
@@ -201,7 +205,7 @@ def encode_error_bound(x, aabb_lo, aabb_hi, tables, n_sh_abs=4e-6, n_blob_abs=4e
     for l in range(L_LEVELS):
         N = level_resolution(l)
         tmax = float(np.max(np.abs(tables[l])))
-        E[:, l * F:(l + 1) * F] = 3.0 * N * 2.0 ** -21 * 2.0 * tmax + gamma(11) * tmax
+        E[:, l * F:(l + 1) * F] = 3.0 * N * 2.0 ** -21 * 2.0 * tmax + gamma(11) * tmax + table_u * tmax
     E[:, L_LEVELS * F:L_LEVELS * F + N_SH] = n_sh_abs
     E[:, L_LEVELS * F + N_SH:] = n_blob_abs
     return E

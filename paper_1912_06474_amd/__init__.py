@@ -78,7 +78,7 @@ class NrcDesc(C.Structure):
                 ("lambda_lo", C.c_float), ("lambda_hi", C.c_float), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float), ("params", C.c_void_p),
                 ("train_paths", C.c_int32), ("train_steps", C.c_int32), ("train_batch", C.c_int32),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("table_fp16", C.c_int32)]
 
 
 class Tuning(C.Structure):
@@ -434,9 +434,11 @@ class Tracer:
 
     # ---- learned radiance cache -------------------------------------------------
     def nrc_init(self, params, tables, aabb_lo, aabb_hi, lambda_range=(380.0, 780.0), lr=1e-2, betas=(0.9, 0.99),
-                 eps=1e-8, train_paths=1 << 16, train_steps=4, train_batch=1 << 14, precision="bf16"):
+                 eps=1e-8, train_paths=1 << 16, train_steps=4, train_batch=1 << 14, precision="bf16",
+                 table_fp16=False):
         """Create the cache from a parameter dict (W [5][64][64], b [5][64], wo [64], bo) and hash
-        tables [16][T][2] (T a power of two); the last four settings apply to renders with nrc=True."""
+        tables [16][T][2] (T a power of two); train_* and precision apply to renders with nrc=True;
+        table_fp16: BF16 queries gather from an FP16 copy of the tables."""
         T = int(np.asarray(tables).shape[1])
         log2 = T.bit_length() - 1
         if T != 1 << log2:
@@ -452,6 +454,7 @@ class Tracer:
         d.params = flat.ctypes.data
         d.train_paths, d.train_steps, d.train_batch = int(train_paths), int(train_steps), int(train_batch)
         d.precision = {"fp32": 0, "bf16": 1}[precision]
+        d.table_fp16 = int(bool(table_fp16))
         self._check(lib().sdd_nrc_init(self.h, C.byref(d)))
 
     def _rows(self, *arrays):

@@ -174,6 +174,7 @@ struct sdd_ctx {
     hipEvent_t nrc_ev_rows = nullptr, nrc_ev_trained = nullptr;
     bool nrc_pending = false;
     float* nrc_h_loss = nullptr;  // pinned: the last step's loss
+    uint32_t* nrc_t16 = nullptr;  // FP16 copy of the tables for BF16 queries (sdd_nrc_desc.table_fp16)
     float* d_lam = nullptr;  // scene wavelengths (nm), FP32
     uint4* nrc_hop = nullptr;  // staged matrix operands of cache queries
     uint2* nrc_sop = nullptr;
@@ -386,6 +387,7 @@ void free_nrc(sdd_ctx* c) {
     c->nrc_stream = nullptr;
     c->nrc_ev_rows = c->nrc_ev_trained = nullptr;
     c->nrc_h_loss = nullptr;
+    dfree(c, c->nrc_t16);
     free_nrc_render(c);
     dfree(c, c->nrc_hop);
     dfree(c, c->nrc_sop);
@@ -538,6 +540,14 @@ struct Timer {
 // API call that reads, changes or frees the cache, and statistics).
 void nrc_wait_gpu(sdd_ctx* c) {
     if (c->nrc_pending) (void)hipStreamWaitEvent(c->stream, c->nrc_ev_trained, 0);
+}
+
+// the network as BF16 queries and BF16 rows evaluate it: with the FP16 copy
+// of the tables when the cache keeps one (training reads c->nrc, FP32 tables)
+NrcNet qnet(const sdd_ctx* c) {
+    NrcNet n = c->nrc;
+    n.t16 = c->nrc_t16;
+    return n;
 }
 
 hipError_t nrc_wait_host(sdd_ctx* c) {
@@ -1348,6 +1358,7 @@ sdd_status nrc_train_after_call(sdd_ctx* c, long long n_rows, bool timing) {
         HIP_TRY(c, nrc_launch_pack(c->nrc, ts));
         ++c->nrc_t;
     }
+    if (c->nrc_t16) HIP_TRY(c, nrc_launch_tables_f16(c->nrc, c->nrc_t16, ts));
     // the last step's loss, read when asked for (nrc_wait_host)
     HIP_TRY(c, hipMemcpyAsync(c->nrc_h_loss, c->nrc_loss, sizeof(float), hipMemcpyDeviceToHost, ts));
     HIP_TRY(c, hipEventRecord(c->nrc_ev_trained, ts));
@@ -1628,7 +1639,7 @@ sdd_status trace_jobs(sdd_ctx* c, std::vector<Job>& jobs, const int* s0_dev = nu
                 {
                     Timer tm(c, timing, 3);
                     const NrcOrder ord = nrc_order(c);
-                    HIP_TRY(c, nrc_launch_cache_operands(c->nrc, N, c->nrc_cx, c->nrc_cn, c->nrc_hop, c->nrc_sop,
+                    HIP_TRY(c, nrc_launch_cache_operands(qnet(c), N, c->nrc_cx, c->nrc_cn, c->nrc_hop, c->nrc_sop,
                                                          &ord, c->nrc_flags, c->nrc_rank, c->nrc_cp, c->stream));
                 }
                 Timer tm(c, timing, 4);  // the matrix-core kernel alone
@@ -2504,8 +2515,9 @@ sdd_status sdd_nrc_init(sdd_ctx* c, const sdd_nrc_desc* d) {
         return fail(c, SDD_ERR_INVALID_ARG, "bad Adam hyper-parameters");
     if (!d->params) return fail(c, SDD_ERR_INVALID_ARG, "null parameters");
     if (d->train_paths < 1 || d->train_steps < 0 || d->train_batch < 1 || d->train_batch > kNrcMaxRows ||
-        (d->precision != 0 && d->precision != 1))
-        return fail(c, SDD_ERR_INVALID_ARG, "bad render settings (train_paths, train_steps, train_batch, precision)");
+        (d->precision != 0 && d->precision != 1) || (d->table_fp16 != 0 && d->table_fp16 != 1))
+        return fail(c, SDD_ERR_INVALID_ARG,
+                    "bad render settings (train_paths, train_steps, train_batch, precision, table_fp16)");
     const long long n_all = nrc_count(d->table_log2);
     for (long long i = 0; i < n_all; ++i)
         if (!std::isfinite(d->params[i])) return fail(c, SDD_ERR_INVALID_ARG, "non-finite parameter");
@@ -2534,7 +2546,8 @@ sdd_status sdd_nrc_init(sdd_ctx* c, const sdd_nrc_desc* d) {
     if ((st = upload(c, &net.p, d->params, (size_t)n_all)) != SDD_OK || (st = dalloc(c, &net.g, (size_t)n_all)) != SDD_OK ||
         (st = dalloc(c, &net.m, (size_t)n_all)) != SDD_OK || (st = dalloc(c, &net.v, (size_t)n_all)) != SDD_OK ||
         (st = dalloc(c, &net.wq, (size_t)kNrcFragsAll * 8)) != SDD_OK ||
-        (st = dalloc(c, &net.wf, (size_t)kNrcFrags32)) != SDD_OK || (st = dalloc(c, &c->nrc_loss, 1)) != SDD_OK) {
+        (st = dalloc(c, &net.wf, (size_t)kNrcFrags32)) != SDD_OK || (st = dalloc(c, &c->nrc_loss, 1)) != SDD_OK ||
+        (d->table_fp16 && (st = dalloc(c, &c->nrc_t16, (size_t)(net.n_tab / 2))) != SDD_OK)) {
         free_nrc(c);
         return st;
     }
@@ -2542,6 +2555,7 @@ sdd_status sdd_nrc_init(sdd_ctx* c, const sdd_nrc_desc* d) {
     if (e == hipSuccess) e = nrc_launch_zero(net.m, n_all, c->stream);
     if (e == hipSuccess) e = nrc_launch_zero(net.v, n_all, c->stream);
     if (e == hipSuccess) e = nrc_launch_pack(net, c->stream);
+    if (e == hipSuccess && c->nrc_t16) e = nrc_launch_tables_f16(net, c->nrc_t16, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         free_nrc(c);
@@ -2571,7 +2585,7 @@ sdd_status sdd_nrc_infer(sdd_ctx* c, int32_t n, const float* x, const float* w, 
     if (n == 0) return SDD_OK;
     DeviceGuard g(c->device);
     const hipError_t e = precision == 0 ? nrc_launch_infer(c->nrc, n, x, w, lam, y, c->stream)
-                                        : nrc_launch_infer_mfma(c->nrc, n, x, w, lam, y, c->stream);
+                                        : nrc_launch_infer_mfma(qnet(c), n, x, w, lam, y, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "nrc infer");
     return SDD_OK;
 }
@@ -2594,6 +2608,7 @@ sdd_status sdd_nrc_train_step(sdd_ctx* c, int32_t n, const float* x, const float
     if (e == hipSuccess && apply) {
         e = nrc_launch_adam(c->nrc, c->nrc_t + 1, c->nrc_lr, c->nrc_b1, c->nrc_b2, c->nrc_eps, c->stream);
         if (e == hipSuccess) e = nrc_launch_pack(c->nrc, c->stream);
+        if (e == hipSuccess && c->nrc_t16) e = nrc_launch_tables_f16(c->nrc, c->nrc_t16, c->stream);
         if (e == hipSuccess) ++c->nrc_t;
     }
     if (e == hipSuccess && loss) {
@@ -2619,7 +2634,7 @@ sdd_status sdd_nrc_query(sdd_ctx* c, int32_t n, const float* x4, const float* n4
         if (st != SDD_OK) return st;
     }
     const NrcOrder ord = nrc_order(c);
-    const hipError_t e = nrc_launch_query(c->nrc, n, reinterpret_cast<const float4*>(x4),
+    const hipError_t e = nrc_launch_query(precision == 1 ? qnet(c) : c->nrc, n, reinterpret_cast<const float4*>(x4),
                                           reinterpret_cast<const float4*>(n4), c->d_lam, c->nl, c->nlp, out, 0,
                                           precision, c->nrc_hop, c->nrc_sop, precision == 1 ? &ord : nullptr,
                                           c->stream);
@@ -2644,7 +2659,7 @@ sdd_status sdd_nrc_query_noalloc(sdd_ctx* c, int32_t n, const float* x4, const f
     NrcOrder ord{};
     if (!nrc_query_scratch_layout(c->noalloc_scratch, kNoAllocScratchBytes, n, &hop, &sop, &ord))
         return fail(c, SDD_ERR_INVALID_ARG, "the query's scratch does not fit the static array");
-    const hipError_t e = nrc_launch_query(c->nrc, n, reinterpret_cast<const float4*>(x4),
+    const hipError_t e = nrc_launch_query(qnet(c), n, reinterpret_cast<const float4*>(x4),
                                           reinterpret_cast<const float4*>(n4), c->d_lam, c->nl, c->nlp, out, 0, 1, hop,
                                           sop, &ord, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "nrc query (allocation-free)");

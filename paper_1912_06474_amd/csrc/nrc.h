@@ -34,6 +34,7 @@ struct NrcNet {
     float* v;          // Adam second moments
     uint16_t* wq;      // [kNrcFragsAll][8] BF16 weights, operand order (refreshed by nrc_launch_pack)
     float* wf;         // [2][5][4][16][64] FP32 hidden weights in training operand order: W, then W^T
+    const uint32_t* t16;  // FP16 pairs of the tables, one per entry (nullptr: gathers read the FP32 tables)
     long long n_tab;   // L * T * F
     long long n_all;   // all parameters
     int T;             // table entries per level (power of two)
@@ -148,5 +149,7 @@ hipError_t nrc_launch_grad(const NrcNet& net, const NrcBatch& b, hipStream_t st)
 // Adam step t (>= 1) over all parameters
 hipError_t nrc_launch_adam(const NrcNet& net, int t, float lr, float b1, float b2, float eps, hipStream_t st);
 hipError_t nrc_launch_zero(float* p, long long n, hipStream_t st);
+// FP16 copy of the tables (round to nearest even): t16[i] holds features 2i, 2i+1
+hipError_t nrc_launch_tables_f16(const NrcNet& net, uint32_t* t16, hipStream_t st);
 
 }  // namespace sdd

@@ -110,12 +110,20 @@ __device__ __forceinline__ float2 hash_level(const NrcNet& net, int l, int N, in
     float f[3];
     level_setup(N, xn, i0, f);
     const float2* tab = reinterpret_cast<const float2*>(net.p) + (size_t)l * net.T;
+    const uint32_t* tab16 = net.t16 ? net.t16 + (size_t)l * net.T : nullptr;
     float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const float w = corner_weight(f, c);
         const uint32_t s = corner_slot(N, dense, net.T, i0[0] + (c & 1), i0[1] + ((c >> 1) & 1), i0[2] + (c >> 2));
-        const float2 e = tab[s];
+        float2 e;
+        if (tab16) {
+            const uint32_t h = tab16[s];
+            e = make_float2((float)__builtin_bit_cast(_Float16, (uint16_t)(h & 0xffffu)),
+                            (float)__builtin_bit_cast(_Float16, (uint16_t)(h >> 16)));
+        } else {
+            e = tab[s];
+        }
         a0 += w * e.x;
         a1 += w * e.y;
     }
@@ -433,6 +441,14 @@ __global__ void k_adam(NrcNet net, float lr, float b1, float b2, float eps, floa
     net.m[i] = m;
     net.v[i] = v;
     net.p[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+__global__ void k_tables_f16(const float* p, long long n_pairs, uint32_t* t16) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pairs) return;
+    const float2 v = reinterpret_cast<const float2*>(p)[i];
+    const uint16_t lo = __builtin_bit_cast(uint16_t, (_Float16)v.x), hi = __builtin_bit_cast(uint16_t, (_Float16)v.y);
+    t16[i] = (uint32_t)lo | ((uint32_t)hi << 16);
 }
 
 __global__ void k_zero(float* p, long long n) {
@@ -1109,6 +1125,13 @@ hipError_t nrc_launch_adam(const NrcNet& net, int t, float lr, float b1, float b
     const float c1 = (float)(1.0 - std::pow((double)b1, (double)t));
     const float c2 = (float)(1.0 - std::pow((double)b2, (double)t));
     hipLaunchKernelGGL(k_adam, dim3(nblocks(net.n_all, 256)), dim3(256), 0, st, net, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t nrc_launch_tables_f16(const NrcNet& net, uint32_t* t16, hipStream_t st) {
+    const long long pairs = net.n_tab / 2;
+    if (pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tables_f16, dim3(nblocks(pairs, 256)), dim3(256), 0, st, (const float*)net.p, pairs, t16);
     return hipGetLastError();
 }
 

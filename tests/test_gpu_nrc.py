@@ -119,12 +119,13 @@ def _bf16_ok(y, yb):
     return float(np.mean(e <= 1e-4)), float(e.max())
 
 
-def _bf16_judge(y, params, tables, x, w, lam, lo=LO, hi=HI, tag=""):
+def _bf16_judge(y, params, tables, x, w, lam, lo=LO, hi=HI, tag="", table_u=0.0):
     """Every row within the derived bound of the FP64 forward; the BF16-operand
-    emulation is a diagnostic."""
+    emulation is a diagnostic.  table_u: unit roundoff of the tables the
+    kernel gathered from (FP16 copy: 2^-11)."""
     p, t = _f64(params, tables)
     X = ora.encode(x, w, lam, lo, hi, t)
-    yo, B, nk, _ = ora.mlp_bf16_error_bound(p, X, ora.encode_error_bound(x, lo, hi, t))
+    yo, B, nk, _ = ora.mlp_bf16_error_bound(p, X, ora.encode_error_bound(x, lo, hi, t, table_u=table_u))
     err = np.abs(np.asarray(y, np.float64) - yo)
     frac, err_b = _bf16_ok(y, ora.mlp_forward_bf16(p, X))
     scale = np.abs(yo) + np.sqrt(np.mean(yo ** 2))
@@ -167,6 +168,23 @@ def test_bf16_forward_within_derived_bound(tracer, n):
     x, w, lam = _rows(n, 12)
     y = tracer.nrc_infer(x, w, lam, "bf16").cpu().numpy()
     _bf16_judge(y, params, tables, x, w, lam, tag="general rows")
+
+
+@pytest.mark.parametrize("n", [64, 3001])
+def test_bf16_forward_fp16_tables_within_derived_bound(tracer, n):
+    """Hash features gathered from the FP16 copy of the tables: within the
+    bound that adds the tables' FP16 rounding to the encoding error."""
+    params, tables = _net(2, 14)
+    tracer.nrc_init(params, tables, LO, HI, table_fp16=True)
+    x, w, lam = _rows(n, 13)
+    y = tracer.nrc_infer(x, w, lam, "bf16").cpu().numpy()
+    _bf16_judge(y, params, tables, x, w, lam, tag="FP16 tables", table_u=2.0 ** -11)
+    # the copy follows the training copy: one Adam step, then both paths again
+    xt, wt, lt = _rows(512, 14)
+    tracer.nrc_train_step(xt, wt, lt, np.ones(512, np.float32))
+    p1, t1 = tracer.nrc_get("params")
+    y1 = tracer.nrc_infer(x, w, lam, "bf16").cpu().numpy()
+    _bf16_judge(y1, p1, t1, x, w, lam, tag="FP16 tables after a step", table_u=2.0 ** -11)
 
 
 @pytest.mark.parametrize("n", [64, 3001])

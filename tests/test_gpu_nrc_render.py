@@ -77,14 +77,15 @@ def test_affine_network_is_the_closed_form(tracer):
     assert err <= 2e-6
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_query_equals_infer(tracer, precision):
-    """The render's per-path, all-wavelength query equals the row forward bit for bit."""
+@pytest.mark.parametrize("precision,fp16", [("fp32", False), ("bf16", False), ("bf16", True)])
+def test_query_equals_infer(tracer, precision, fp16):
+    """The render's per-path, all-wavelength query equals the row forward bit
+    for bit (with FP16 tables both gather from the FP16 copy)."""
     sc = sg.tiny_room(0, 16)
     tracer.load_scene(sc)
     params, tables = sg.nrc_params(3, table_size=1 << 14)
     tables = np.random.default_rng(4).uniform(-0.5, 0.5, tables.shape).astype(np.float32)
-    tracer.nrc_init(params, tables, LO, HI)
+    tracer.nrc_init(params, tables, LO, HI, table_fp16=fp16)
     n = 1000
     x, w, _, _ = sg.nrc_rows(n, 5, LO, HI)
     q = tracer.nrc_query(x, w, precision).cpu().numpy()

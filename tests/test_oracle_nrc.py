@@ -269,3 +269,19 @@ def test_bf16_bound_encoding_term():
     xp = np.asarray(x, np.float64) * (1.0 + 3.0 * 2.0 ** -24)
     Xp = nrc.encode(xp, w, lam, LO3, HI3, tables)
     assert np.all(np.abs(Xp - X)[:, :32] <= EX[:, :32])
+
+
+def test_bf16_bound_fp16_table_term():
+    """The table term covers tables read in FP16: features encoded from the
+    FP16 rounding of the tables stay within table_u = 2^-11 of max |t| per
+    level, and that term is needed (without it the bound fails)."""
+    p, tables = _test_net(6)
+    x, w, lam, _ = sg.nrc_rows(2000, 6)
+    X = nrc.encode(x, w, lam, LO3, HI3, tables)
+    t16 = tables.astype(np.float16).astype(np.float64)
+    X16 = nrc.encode(x, w, lam, LO3, HI3, t16)
+    d = np.abs(X16 - X)[:, :32]
+    E16 = nrc.encode_error_bound(x, LO3, HI3, tables, table_u=2.0 ** -11)
+    E0 = nrc.encode_error_bound(x, LO3, HI3, tables)
+    assert np.all(d <= E16[:, :32] - E0[:, :32])   # the table term alone covers it
+    assert np.any(d > E0[:, :32])                  # and the FP32 terms do not
