@@ -483,6 +483,8 @@ def plain_line(args, workload, wl, scene, tr, build_s, cpu_s):
                 t.resolve_image(r["render_id"], r["W"], r["H"], spectral=True, xyz=True)
         step += 1
 
+    if args.defer_rays:
+        tr.set_deferral(args.defer_rays, args.defer_extra)
     tuned = None
     if args.autotune is not None:
         t0 = time.perf_counter()
@@ -534,6 +536,7 @@ def plain_line(args, workload, wl, scene, tr, build_s, cpu_s):
         "kernel_ms_per_step": {k: v / args.steps for k, v in kern_ms.items()},
         "build_bvh_s": build_s,
         "bvh": "device LBVH" if args.device_bvh else "host binned SAH",
+        "deferral": {"below_rays": args.defer_rays, "extra_sweeps": args.defer_extra} if args.defer_rays else None,
         "tuning": dict(tr.get_tuning(), paths_per_pass=st["paths_per_batch"],
                        autotuned=None if tuned is None else {"from_cache": tuned["from_cache"],
                                                              "search_ms_per_call": tuned["ms"]}),
@@ -627,6 +630,9 @@ def main():
     ap.add_argument("--autotune", nargs="?", const="", default=None, metavar="FILE",
                     help="search the launch settings on the step's own call before the warmup (results file "
                          "FILE is read first and written after a search)")
+    ap.add_argument("--defer-rays", type=int, default=0,
+                    help="plain workloads: queues with fewer rays wait a sweep (the paper's deferral rule; 0: off)")
+    ap.add_argument("--defer-extra", type=int, default=2, help="extra sweeps per depth for --defer-rays")
     ap.add_argument("--path-state", choices=["f64", "f32"], default="f64",
                     help="f32: load the FP32-path-state measurement build (libsdd_f32state.so) to time what FP64 "
                          "path state costs; the library itself keeps FP64 path state")

@@ -313,6 +313,21 @@ sdd_status sdd_validate_tuning(const sdd_tuning *t, char *msg, int msg_len);
  * maximum.  A captured SDD_TRACE_GRAPH sequence is recaptured. */
 sdd_status sdd_set_tuning(sdd_ctx *ctx, const sdd_tuning *t);
 
+/* Deferral of small subdomain queues, after the load-balancing rule of
+ * Sec. 5 (a processor leaves a subdomain with few rays left while other
+ * subdomains hold many, and comes back to it later).  On one device every
+ * subdomain stays resident, so the rule becomes: in a sweep, the queue of a
+ * subdomain holding fewer than below_rays rays of one kind waits for the
+ * next sweep (its rays are carried over unchanged) as long as even its
+ * worst-placed ray still drains within the depth's sweeps; extra_sweeps
+ * (0..4) sweeps per depth are added to the S = nx + ny + nz - 2 that drain
+ * every queue without deferral.  below_rays = 0 (the default) turns it off.
+ * Images, logs and counters are unchanged by it (a ray's traversal does not
+ * depend on when it runs).  Waits for the context's stream; a captured
+ * SDD_TRACE_GRAPH sequence is recaptured.  SDD_ERR_INVALID_ARG for
+ * below_rays < 0 or extra_sweeps outside 0..4. */
+sdd_status sdd_set_deferral(sdd_ctx *ctx, int32_t below_rays, int32_t extra_sweeps);
+
 /* Settings in force: batch_paths as requested (0 = from the budget; the
  * paths per pass of the last call are in sdd_stats.paths_per_batch), trace_grid and
  * dir_bins as launched (0 before sdd_build_bvh). */

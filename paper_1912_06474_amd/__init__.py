@@ -34,7 +34,7 @@ EXPORTS = ("sdd_create", "sdd_destroy", "sdd_last_error", "sdd_load_scene", "sdd
            "sdd_trace_spectral", "sdd_resolve_image", "sdd_reset_render", "sdd_get_stats", "sdd_reset_stats",
            "sdd_debug_philox", "sdd_debug_pane", "sdd_debug_trace_rays", "sdd_debug_glass", "sdd_trace_batch",
            "sdd_nrc_param_count", "sdd_nrc_init", "sdd_nrc_infer", "sdd_nrc_train_step", "sdd_nrc_get_params",
-           "sdd_nrc_last_rows", "sdd_nrc_query", "sdd_nrc_query_noalloc")
+           "sdd_nrc_last_rows", "sdd_nrc_query", "sdd_nrc_query_noalloc", "sdd_set_deferral")
 NRC_LEVELS, NRC_FEAT, NRC_HID, NRC_LAYERS = 16, 2, 64, 5
 
 
@@ -150,6 +150,7 @@ def lib():
         tp = C.POINTER(Tuning)
         L.sdd_validate_tuning.argtypes = [tp, C.c_char_p, C.c_int]
         L.sdd_set_tuning.argtypes = [vp, tp]
+        L.sdd_set_deferral.argtypes = [vp, i32, i32]
         L.sdd_get_tuning.argtypes = [vp, tp]
         L.sdd_autotune.argtypes = [vp, i32, C.POINTER(TraceDesc), i32, C.c_char_p, tp, C.POINTER(C.c_double),
                                    C.POINTER(C.c_int32)]
@@ -346,6 +347,11 @@ class Tracer:
     def set_tuning(self, batch_paths=0, trace_grid=0, dir_bins=0):
         """Launch settings for later calls (0 = the library's choice); images do not change."""
         self._check(lib().sdd_set_tuning(self.h, C.byref(Tuning(batch_paths, trace_grid, dir_bins))))
+
+    def set_deferral(self, below_rays, extra_sweeps=2):
+        """Small queues (fewer than below_rays rays) wait a sweep while their rays can still drain;
+        extra_sweeps sweeps per depth are added (0 turns deferral off)."""
+        self._check(lib().sdd_set_deferral(self.h, int(below_rays), int(extra_sweeps)))
 
     def get_tuning(self):
         t = Tuning()

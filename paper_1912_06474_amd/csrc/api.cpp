@@ -119,6 +119,7 @@ struct sdd_ctx {
     Stage stage[2] = {};
     int n_blocks = 0;
     int* d_counts = nullptr;
+    int defer_rays = 0, defer_extra = 0;  // sdd_set_deferral
     long long counts_len = 0;
     long long batch_bytes = 0;  // device bytes of the path batch (ensure_batch)
     long long call_budget = 0;  // memory budget of the current call (set before any capture)
@@ -583,7 +584,7 @@ long long bytes_per_path(const sdd_ctx* c, int max_depth) {
 }
 
 sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
-    const long long cnt_len = (long long)(2 * max_depth + 1) * (c->S + 1) * c->G * kCntStride;
+    const long long cnt_len = (long long)(2 * max_depth + 1) * (c->S + kMaxDeferExtra + 1) * c->G * kCntStride;
     if (n <= c->ncap && max_depth <= c->dcap) return SDD_OK;
     free_batch(c);
     const long long bytes0 = c->device_bytes;
@@ -629,8 +630,11 @@ sdd_status ensure_batch(sdd_ctx* c, long long n, int max_depth) {
 
 // counters of (phase, sweep); phase 2(d-1) holds the closest-hit rays of
 // depth d, phase 2(d-1)+1 the shadow rays of depth d
+// sweeps per depth: the S that drain every queue, plus a deferral schedule's extra sweeps
+inline int n_sweeps(const sdd_ctx* c) { return c->S + (c->defer_rays > 0 ? c->defer_extra : 0); }
+
 inline int* counts_at(sdd_ctx* c, int phase, int k) {
-    return c->d_counts + ((long long)phase * (c->S + 1) + k) * c->G * kCntStride;
+    return c->d_counts + ((long long)phase * (c->S + kMaxDeferExtra + 1) + k) * c->G * kCntStride;
 }
 inline int ph_ext(int d) { return 2 * (d - 1); }
 inline int ph_sh(int d) { return 2 * (d - 1) + 1; }
@@ -654,8 +658,12 @@ QueueSet queue_set(sdd_ctx* c, int in_buf, int out_buf, int phase, int k) {
 // sh_depth (path stride n_paths).
 sdd_status run_sweeps(sdd_ctx* c, int ext_phase, int sh_phase, long long cap, bool count, bool timing,
                       int sh_depth = 0, long long n_paths = 0) {
-    for (int k = 0; k < c->S; ++k) {
+    const int S = n_sweeps(c);
+    for (int k = 0; k < S; ++k) {
         TraceParams p{};
+        p.defer_below = c->defer_rays;
+        p.sweep = k;
+        p.n_sweeps = S;
         const bool even = k % 2 == 0;
         if (ext_phase >= 0) p.q[0] = queue_set(c, even ? 0 : 1, even ? 1 : 0, ext_phase, k);
         if (sh_phase >= 0) p.q[1] = queue_set(c, even ? 2 : 3, even ? 3 : 2, sh_phase, k);
@@ -2095,6 +2103,20 @@ sdd_status sdd_set_tuning(sdd_ctx* c, const sdd_tuning* t) {
     DeviceGuard g(c->device);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     set_tuning_fields(c, *t);
+    return SDD_OK;
+}
+
+sdd_status sdd_set_deferral(sdd_ctx* c, int32_t below_rays, int32_t extra_sweeps) {
+    if (!c) return SDD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (below_rays < 0 || extra_sweeps < 0 || extra_sweeps > kMaxDeferExtra)
+        return fail(c, SDD_ERR_INVALID_ARG,
+                    "below_rays must be >= 0 and extra_sweeps in 0.." + std::to_string(kMaxDeferExtra));
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->defer_rays = below_rays;
+    c->defer_extra = extra_sweeps;
+    ++c->gen;  // a captured launch sequence has another number of sweeps
     return SDD_OK;
 }
 

@@ -494,6 +494,16 @@ void k_trace(TraceParams P) {
     const int E = 2 * G;  // entry e = 2 * cell + kind
     constexpr int kWavesPerBlock = kTraceBlock / 64;
     __shared__ int s_item;  // rays per work item in this sweep
+    __shared__ uint32_t s_defer[(2 * kMaxCells + 31) / 32];  // entries that wait for the next sweep
+    auto deferred = [&](int e, int n) -> bool {
+        if (P.defer_below <= 0 || n <= 0 || n >= P.defer_below) return false;
+        const GridParams& g = P.grid;
+        const int cell = e >> 1, ix = cell % g.nx, iy = (cell / g.nx) % g.ny, iz = cell / (g.nx * g.ny);
+        const int R = max(ix, g.nx - 1 - ix) + max(iy, g.ny - 1 - iy) + max(iz, g.nz - 1 - iz);
+        return P.sweep + 1 + R <= P.n_sweeps - 1;
+    };
+    for (int i = threadIdx.x; i < (E + 31) / 32; i += blockDim.x) s_defer[i] = 0u;
+    __syncthreads();
     if (threadIdx.x < 64) {
         // exclusive prefix of the per-entry item counts (wave 0, lane-blocked scan)
         const int ln = threadIdx.x;
@@ -517,6 +527,7 @@ void k_trace(TraceParams P) {
             const int kind = e & 1;
             const int n = P.active[kind] ? P.q[kind].cnt_in[(e >> 1) * kCntStride] : 0;
             if (n > P.cap) atomicOr(P.overflow, kOverflowQueue);  // never expected: counters are bounded by cap
+            if (deferred(e, n)) atomicOr(&s_defer[e >> 5], 1u << (e & 31));
             local += (n + item - 1) / item;
         }
         int incl = local;
@@ -539,10 +550,13 @@ void k_trace(TraceParams P) {
     if (total == 0) return;
     const int item_rays = s_item;
     if (blockIdx.x == 0 && threadIdx.x < 2 && P.active[threadIdx.x]) {
-        // every queued ray is traversed exactly once in this sweep
+        // every queued ray is traversed exactly once in this sweep (a waiting queue in a later one)
         unsigned long long n = 0;
-        for (int c = 0; c < G; ++c)
-            n += (unsigned long long)min((long long)P.q[threadIdx.x].cnt_in[c * kCntStride], P.cap);
+        for (int c = 0; c < G; ++c) {
+            const int e = 2 * c + (int)threadIdx.x;
+            if (!((s_defer[e >> 5] >> (e & 31)) & 1u))
+                n += (unsigned long long)min((long long)P.q[threadIdx.x].cnt_in[c * kCntStride], P.cap);
+        }
         if (n) atomicAdd(&P.stats[threadIdx.x == 0 ? kStatExtVisits : kStatShadowVisits], n);
     }
     const int lane = lane_id();
@@ -570,6 +584,32 @@ void k_trace(TraceParams P) {
         }
         const int e = __builtin_amdgcn_readfirstlane(a);
         const int cell = e >> 1, kind = e & 1;
+        if ((s_defer[e >> 5] >> (e & 31)) & 1u) {
+            // the queue waits: its rays go unchanged to its own queue of the next sweep
+            const QueueSet& Q = P.q[kind];
+            const long long first = (long long)(item - s_pref[e]) * item_rays;
+            const int count = (int)min((long long)item_rays,
+                                       min((long long)Q.cnt_in[cell * kCntStride], P.cap) - first);
+            for (int b = 0; b < count; b += 64) {
+                const bool on = b + lane < count;
+                const long long q = (long long)cell * P.cap + first + b + lane;
+                float4 qa = make_float4(0, 0, 0, 0), qb = make_float4(0, 0, 0, 0);
+                int2 qc = make_int2(0, 0);
+                if (on) {
+                    qa = Q.qa_in[q];
+                    qb = Q.qb_in[q];
+                    qc = Q.qc_in[q];
+                }
+                const int slot = wave_append(on, cell, Q.cnt_out, kCntStride);
+                if (on && slot < P.cap) {
+                    const long long o = (long long)cell * P.cap + slot;
+                    Q.qa_out[o] = qa;
+                    Q.qb_out[o] = qb;
+                    Q.qc_out[o] = qc;
+                }
+            }
+            continue;
+        }
         if (cell != top_cell) {
             // the wave is done with the previous cell's copy (its traversals
             // have returned), so it can be overwritten; LDS operations of one

@@ -194,7 +194,14 @@ struct TraceParams {
     int* overflow;
     int* gstack;          // spill stack: (kStack - kLdsStack) entries per thread of the grid
     unsigned long long* stats;
+    // deferral (the paper's load-balancing rule, Sec. 5): in sweep `sweep` of
+    // n_sweeps, a queue with fewer than defer_below rays (0: never) waits for
+    // the next sweep when even its worst-placed ray still drains: sweep + 1 +
+    // R(cell) <= n_sweeps - 1, R the most cell boundaries a ray can still cross
+    int defer_below;
+    int sweep, n_sweeps;
 };
+constexpr int kMaxDeferExtra = 4;  // sweeps per depth a deferral schedule may add
 
 // Radiance-cache rendering.  Training paths ((s * WH + p) % stride == 0,
 // s the absolute sample index) are traced in full; every other path ends at

@@ -346,3 +346,34 @@ def test_window_render_equals_the_frame_render(tracer):
     for bad in ((60, 0, 5, 5), (0, 0, 0, 5), (-1, 0, 4, 4)):
         with pytest.raises(m.SddError, match="INVALID_ARG"):
             tracer.trace_spectral(sc["camera"], W, H, 1, D, render_id=4, crop=bad)
+
+
+@pytest.mark.parametrize("below,extra", [(64, 2), (100000, 4)])
+def test_deferral_leaves_the_render_unchanged(tracer, below, extra):
+    """Small queues waiting a sweep (the paper's load-balancing rule): the
+    same images, logs and per-kind visit counts, on a grid with many sweeps
+    (below = 100000 defers every queue whose rays can still drain)."""
+    import paper_1912_06474_amd as m
+    sc = sg.tiny_room()
+    W, H, spp, D, grid = 64, 48, 3, 5, (4, 4, 2)
+    tracer.reset_stats()
+    a = gpu_render(tracer, sc, W, H, spp, D, grid=grid)
+    sa = tracer.stats()
+    tracer.reset_render(0)
+    tracer.set_deferral(below, extra)
+    try:
+        tracer.reset_stats()
+        b = gpu_render(tracer, sc, W, H, spp, D, grid=grid)
+        sb = tracer.stats()
+        tracer.reset_render(0)
+    finally:
+        tracer.set_deferral(0, 0)
+    for k in ("spectral", "xyz", "hit_log", "shadow_log"):
+        assert np.array_equal(a[k], b[k]), k
+    for k in ("ext_rays", "shadow_rays", "ext_cell_visits", "shadow_cell_visits", "overflow"):
+        assert sa[k] == sb[k], (k, sa[k], sb[k])
+    assert sb["launches_trace"] == sa["launches_trace"] + extra * (sa["launches_trace"] // 8)
+    with pytest.raises(m.SddError, match="INVALID_ARG"):
+        tracer.set_deferral(-1, 2)
+    with pytest.raises(m.SddError, match="INVALID_ARG"):
+        tracer.set_deferral(64, 5)
