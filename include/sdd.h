@@ -530,7 +530,9 @@ sdd_status sdd_nrc_last_rows(sdd_ctx *ctx, int32_t max_rows, float *rows, int32_
                              float *loss);
 
 /* Copy a parameter-sized array to the host: which 0 parameters, 1 last
- * gradient, 2 Adam first moments, 3 second moments.  Synchronises. */
+ * gradient of sdd_nrc_train_step (the Adam steps after a cache render leave
+ * the gradients at zero), 2 Adam first moments, 3 second moments.
+ * Synchronises. */
 sdd_status sdd_nrc_get_params(sdd_ctx *ctx, int32_t which, float *out);
 
 #ifdef __cplusplus

@@ -176,6 +176,7 @@ struct sdd_ctx {
     bool nrc_pending = false;
     float* nrc_h_loss = nullptr;  // pinned: the last step's loss
     uint32_t* nrc_t16 = nullptr;  // FP16 copy of the tables for BF16 queries (sdd_nrc_desc.table_fp16)
+    bool nrc_g_dirty = false;     // gradients hold a step's sums (sdd_nrc_train_step leaves them readable)
     float* d_lam = nullptr;  // scene wavelengths (nm), FP32
     uint4* nrc_hop = nullptr;  // staged matrix operands of cache queries
     uint2* nrc_sop = nullptr;
@@ -1359,10 +1360,12 @@ sdd_status nrc_train_after_call(sdd_ctx* c, long long n_rows, bool timing) {
         HIP_TRY(c, nrc_launch_unpack(c->nrc_crows, k, S, m, nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt, ts));
         NrcBatch b{nk, c->nrc_bx, c->nrc_bw, c->nrc_blam, c->nrc_bt, c->nrc_acts, c->nrc_dz, c->nrc_y, c->nrc_dy,
                    c->nrc_loss};
-        HIP_TRY(c, nrc_launch_zero(c->nrc.g, c->nrc.n_all, ts));
+        if (c->nrc_g_dirty) HIP_TRY(c, nrc_launch_zero(c->nrc.g, c->nrc.n_all, ts));
         HIP_TRY(c, nrc_launch_zero(c->nrc_loss, 1, ts));
         HIP_TRY(c, nrc_launch_grad(c->nrc, b, ts));
-        HIP_TRY(c, nrc_launch_adam(c->nrc, c->nrc_t + 1, c->nrc_lr, c->nrc_b1, c->nrc_b2, c->nrc_eps, ts));
+        // Adam leaves the gradients at zero for the next step (no zeroing pass over the tables)
+        HIP_TRY(c, nrc_launch_adam(c->nrc, c->nrc_t + 1, c->nrc_lr, c->nrc_b1, c->nrc_b2, c->nrc_eps, ts, true));
+        c->nrc_g_dirty = false;
         HIP_TRY(c, nrc_launch_pack(c->nrc, ts));
         ++c->nrc_t;
     }
@@ -2592,6 +2595,7 @@ sdd_status sdd_nrc_init(sdd_ctx* c, const sdd_nrc_desc* d) {
     c->nrc_b2 = d->beta2;
     c->nrc_eps = d->eps;
     c->nrc_t = 0;
+    c->nrc_g_dirty = false;
     c->has_nrc = true;
     return SDD_OK;
 }
@@ -2624,9 +2628,10 @@ sdd_status sdd_nrc_train_step(sdd_ctx* c, int32_t n, const float* x, const float
     sdd_status st = nrc_reserve(c, n);
     if (st != SDD_OK) return st;
     NrcBatch b{n, x, w, lam, t, c->nrc_acts, c->nrc_dz, c->nrc_y, c->nrc_dy, c->nrc_loss};
-    hipError_t e = nrc_launch_zero(c->nrc.g, c->nrc.n_all, c->stream);
+    hipError_t e = c->nrc_g_dirty ? nrc_launch_zero(c->nrc.g, c->nrc.n_all, c->stream) : hipSuccess;
     if (e == hipSuccess) e = nrc_launch_zero(c->nrc_loss, 1, c->stream);
     if (e == hipSuccess) e = nrc_launch_grad(c->nrc, b, c->stream);
+    c->nrc_g_dirty = true;  // this step's gradients stay readable (sdd_nrc_get_params)
     if (e == hipSuccess && apply) {
         e = nrc_launch_adam(c->nrc, c->nrc_t + 1, c->nrc_lr, c->nrc_b1, c->nrc_b2, c->nrc_eps, c->stream);
         if (e == hipSuccess) e = nrc_launch_pack(c->nrc, c->stream);

@@ -146,8 +146,10 @@ hipError_t nrc_launch_unpack(const float4* rows, int k, int S, int m, int n, flo
 hipError_t nrc_launch_pack(const NrcNet& net, hipStream_t st);
 // forward, loss, backward, gradient reduction (gradients are accumulated in net.g)
 hipError_t nrc_launch_grad(const NrcNet& net, const NrcBatch& b, hipStream_t st);
-// Adam step t (>= 1) over all parameters
-hipError_t nrc_launch_adam(const NrcNet& net, int t, float lr, float b1, float b2, float eps, hipStream_t st);
+// Adam step t (>= 1) over all parameters; clear: leave the gradients at zero
+// for the next step's accumulation (else they stay readable)
+hipError_t nrc_launch_adam(const NrcNet& net, int t, float lr, float b1, float b2, float eps, hipStream_t st,
+                           bool clear = false);
 hipError_t nrc_launch_zero(float* p, long long n, hipStream_t st);
 // FP16 copy of the tables (round to nearest even): t16[i] holds features 2i, 2i+1
 hipError_t nrc_launch_tables_f16(const NrcNet& net, uint32_t* t16, hipStream_t st);

@@ -432,10 +432,11 @@ __global__ __launch_bounds__(256) void k_train_wgrad(NrcNet net, NrcBatch b, int
     }
 }
 
-__global__ void k_adam(NrcNet net, float lr, float b1, float b2, float eps, float c1, float c2) {
+__global__ void k_adam(NrcNet net, float lr, float b1, float b2, float eps, float c1, float c2, int clear) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= net.n_all) return;
     const float g = net.g[i];
+    if (clear) net.g[i] = 0.0f;  // ready for the next step's accumulation
     const float m = b1 * net.m[i] + (1.0f - b1) * g;
     const float v = b2 * net.v[i] + (1.0f - b2) * g * g;
     net.m[i] = m;
@@ -1121,10 +1122,12 @@ hipError_t nrc_launch_grad(const NrcNet& net, const NrcBatch& b, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t nrc_launch_adam(const NrcNet& net, int t, float lr, float b1, float b2, float eps, hipStream_t st) {
+hipError_t nrc_launch_adam(const NrcNet& net, int t, float lr, float b1, float b2, float eps, hipStream_t st,
+                           bool clear) {
     const float c1 = (float)(1.0 - std::pow((double)b1, (double)t));
     const float c2 = (float)(1.0 - std::pow((double)b2, (double)t));
-    hipLaunchKernelGGL(k_adam, dim3(nblocks(net.n_all, 256)), dim3(256), 0, st, net, lr, b1, b2, eps, c1, c2);
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(net.n_all, 256)), dim3(256), 0, st, net, lr, b1, b2, eps, c1, c2,
+                       clear ? 1 : 0);
     return hipGetLastError();
 }
 
