@@ -251,15 +251,25 @@ __device__ __forceinline__ void opaque4(uint4* c) {
 template <bool SHADOW, bool COUNT>
 __device__ __forceinline__ void trace_item(const TraceParams& P, const QueueSet& Q, int cell, long long first,
                                            int count, const uint4* top, int* stk, int* gstk, int gstride,
-                                           int& n_nodes, int& n_tris, int& n_node_steps, int& n_tri_steps) {
+                                           int& n_nodes, int& n_tris, int& n_node_steps, int& n_tri_steps,
+                                           float4* cc) {
     constexpr int kDone = -2147483647 - 1;  // INT_MIN: no leaf encodes as it (~INT_MAX triangles)
     const GridParams& g = P.grid;
-    const int ix = cell % g.nx, iy = (cell / g.nx) % g.ny, iz = cell / (g.nx * g.ny);
-    const float px0 = g.planes[ix], px1 = g.planes[ix + 1];
-    const float py0 = g.planes[g.off_y + iy], py1 = g.planes[g.off_y + iy + 1];
-    const float pz0 = g.planes[g.off_z + iz], pz1 = g.planes[g.off_z + iz + 1];
     const int root = P.cell_root[cell];
-    const float4 qbase = P.cell_q[2 * cell], qstep = P.cell_q[2 * cell + 1];
+    {
+        // the cell's exit planes and lattice, kept in the wave's LDS slot (read
+        // again at each refill rather than held in registers across rounds)
+        const int ix = cell % g.nx, iy = (cell / g.nx) % g.ny, iz = cell / (g.nx * g.ny);
+        const int lane = lane_id();
+        if (lane == 0) {
+            cc[0] = make_float4(g.planes[ix], g.planes[ix + 1], g.planes[g.off_y + iy], g.planes[g.off_y + iy + 1]);
+            cc[1] = make_float4(g.planes[g.off_z + iz], g.planes[g.off_z + iz + 1], 0.0f, 0.0f);
+            cc[2] = P.cell_q[2 * cell];
+            cc[3] = P.cell_q[2 * cell + 1];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
 
     // the lane's ray: its queue record, its traversal state
     float4 qa = make_float4(0, 0, 0, 0), qb = make_float4(0, 0, 0, 0);
@@ -281,10 +291,11 @@ __device__ __forceinline__ void trace_item(const TraceParams& P, const QueueSet&
             qb = Q.qb_in[q];
             qc = Q.qc_in[q];
             const f3 o = xyz(qa), d = xyz(qb);
+            const float4 pxy = cc[0], pz = cc[1];
             // exit of this cell: nearest far plane, ties x < y < z
-            const float tx = d.x > 0.0f ? (px1 - o.x) / d.x : (d.x < 0.0f ? (px0 - o.x) / d.x : INFINITY);
-            const float ty = d.y > 0.0f ? (py1 - o.y) / d.y : (d.y < 0.0f ? (py0 - o.y) / d.y : INFINITY);
-            const float tz = d.z > 0.0f ? (pz1 - o.z) / d.z : (d.z < 0.0f ? (pz0 - o.z) / d.z : INFINITY);
+            const float tx = d.x > 0.0f ? (pxy.y - o.x) / d.x : (d.x < 0.0f ? (pxy.x - o.x) / d.x : INFINITY);
+            const float ty = d.y > 0.0f ? (pxy.w - o.y) / d.y : (d.y < 0.0f ? (pxy.z - o.y) / d.y : INFINITY);
+            const float tz = d.z > 0.0f ? (pz.y - o.z) / d.z : (d.z < 0.0f ? (pz.x - o.z) / d.z : INFINITY);
             axis = 0;
             t_exit = tx;
             if (ty < t_exit) {
@@ -295,7 +306,7 @@ __device__ __forceinline__ void trace_item(const TraceParams& P, const QueueSet&
                 t_exit = tz;
                 axis = 2;
             }
-            r = make_trav(o, d, qbase, qstep);
+            r = make_trav(o, d, cc[2], cc[3]);
             thi = SHADOW ? fminf(t_exit, __int_as_float(qc.y)) : t_exit;
             best = -1;
             blocked = false;
@@ -453,7 +464,7 @@ __device__ __forceinline__ void trace_item(const TraceParams& P, const QueueSet&
                 leave = !blocked && t_exit < __int_as_float(qc.y);
             }
             if (leave) {
-                int nx = ix, ny = iy, nz = iz;
+                int nx = cell % g.nx, ny = (cell / g.nx) % g.ny, nz = cell / (g.nx * g.ny);
                 if (axis == 0) nx += qb.x > 0.0f ? 1 : -1;
                 else if (axis == 1) ny += qb.y > 0.0f ? 1 : -1;
                 else nz += qb.z > 0.0f ? 1 : -1;
@@ -490,6 +501,7 @@ void k_trace(TraceParams P) {
     extern __shared__ int s_pref[];  // 2 * n_cells + 1 entries (dynamic, so small grids keep occupancy)
     __shared__ int s_stack[kLdsStack * kTraceBlock];
     __shared__ uint4 s_top[(kTraceBlock / 64) * kBvhWidth * kTopNodes];
+    __shared__ float4 s_cell[(kTraceBlock / 64) * 4];  // per wave: the current item's cell constants
     const int G = P.n_cells;
     const int E = 2 * G;  // entry e = 2 * cell + kind
     constexpr int kWavesPerBlock = kTraceBlock / 64;
@@ -626,10 +638,10 @@ void k_trace(TraceParams P) {
                                    min((long long)P.q[kind].cnt_in[cell * kCntStride], P.cap) - first);
         if (kind == 0)
             trace_item<false, COUNT>(P, P.q[0], cell, first, count, top, stk, gstk, gstride, n_nodes, n_tris,
-                                     n_node_steps, n_tri_steps);
+                                     n_node_steps, n_tri_steps, s_cell + 4 * (threadIdx.x / 64));
         else
             trace_item<true, COUNT>(P, P.q[1], cell, first, count, top, stk, gstk, gstride, n_nodes, n_tris,
-                                    n_node_steps, n_tri_steps);
+                                    n_node_steps, n_tri_steps, s_cell + 4 * (threadIdx.x / 64));
     }
     if (COUNT) {
         const int nn = wave_sum(n_nodes), nt = wave_sum(n_tris);
