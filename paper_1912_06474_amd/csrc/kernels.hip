@@ -668,10 +668,53 @@ void k_trace(TraceParams P) {
 //    uniform area sample of the parallelogram), then a cosine-weighted bounce;
 //  - glass pane: reflect with probability P_R = mean R / (mean R + mean T) of
 //    the pane's Fresnel slab terms (Eq. 1, Sec. 6), else transmit straight on.
+// R and T summed over the wavelengths for the coated-pane hits of a wave,
+// shared out over all of its lanes (a hit's transfer matrices at every
+// wavelength would otherwise run on its lane alone while the others wait).
+// The (hit, wavelength) pairs go out 64 per round, hits in rank order; each
+// hit's lane then adds its pairs from the wave's LDS slots in wavelength
+// order, the order of a lone lane's loop, so the sums are the same.  Every
+// lane of the wave calls this.
+template <bool COATED>
+__device__ __forceinline__ void wave_pane_sums(bool need, int m, float c, const float4* pane, const ShadeParams& P,
+                                               int* owner, float2* rt, float& sumR, float& sumT) {
+    const unsigned long long own = __ballot(need);
+    if (own == 0) return;
+    const int lane = lane_id(), n_own = popc64(own), rank = rank_below(own);
+    if (need) owner[rank] = lane;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    const int nl = P.nl, total = n_own * nl;
+    for (int base = 0; base < total; base += 64) {
+        const int q = base + lane;
+        const int orank = min(q / nl, n_own - 1);
+        const int o = owner[orank];
+        const int mo = __shfl(m, o);
+        const float co = __shfl(c, o);
+        float R = 0.0f, T = 0.0f;
+        if (q < total) glass_RT<COATED>(pane, P.coat, P.coat_n, P.coat_layers, P.nlp, mo, q - orank * nl, co, R, T);
+        rt[lane] = make_float2(R, T);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (need) {
+            const int lo = max(rank * nl - base, 0), hi = min((rank + 1) * nl - base, 64);
+            for (int k = lo; k < hi; ++k) {
+                const float2 v = rt[k];
+                sumR += v.x;
+                sumT += v.y;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 template <bool COATED>
 __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
     __shared__ int s_wcnt[(kShadeBlock / 64) * kMaxCells];
     __shared__ float4 s_pane[kLdsPane];
+    __shared__ int s_gown[COATED ? kShadeBlock : 1];     // per wave: lanes of its coated-pane hits by rank
+    __shared__ float2 s_grt[COATED ? kShadeBlock : 1];   // per wave: R and T of one round of pairs
     const int n_pane = P.n_glass * P.nlp;
     const bool pane_lds = n_pane <= kLdsPane;
     if (pane_lds)
@@ -687,47 +730,82 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
     f3 xo{0, 0, 0}, dn{0, 0, 1}, ws{0, 0, 1};
     float te = 0.0f, ts = 0.0f, r_sh = 0.0f;
     int prim = -1;
+    // the hit and the FP64 ray are loaded with the flags, before the branches
+    // that need them, so their latencies overlap
+    uint32_t fl = 0;
+    float2 h = make_float2(0.0f, 0.0f);
+    D4 ro{}, rd{};
     if (valid) {
-        // the hit and the FP64 ray are loaded with the flags, before the
-        // branches that need them, so their latencies overlap
-        uint32_t fl = P.flags[pid];
-        const float2 h = P.hit[pid];
-        const D4 ro = P.ray_o[pid], rd = P.ray_d[pid];
-        if (fl & kAlive) {
+        fl = P.flags[pid];
+        h = P.hit[pid];
+        ro = P.ray_o[pid];
+        rd = P.ray_d[pid];
+    }
+    const bool alive = valid && (fl & kAlive);
+    if (alive) prim = __float_as_int(h.y);
+    const bool last_depth = P.depth == P.max_depth;
+    // the hit's material and geometry (the coated-pane sums below need them
+    // on every lane of the wave before the branches on the material)
+    const pv3 o{ro.x, ro.y, ro.z}, d{rd.x, rd.y, rd.z};
+    float4 pi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    int typ = -1, m = 0, emits = 0;
+    pv3 ng{0, 0, 1}, n{0, 0, 1}, x{0, 0, 0};
+    preal cos_o = 0;
+    if (alive && prim >= 0) {
+        pi = P.prim_info[prim];
+        const int word = __float_as_int(pi.w);
+        typ = (word >> kMatTypeShift) & 3;
+        // material, or compact glass index for glass (with this render's substitution)
+        m = word & kMatIdMask;
+        if (typ == kGlass && m == P.glass_from) m = P.glass_to;
+        emits = (word & kMatEmits) ? kVEmits : 0;
+        // geometry in the path state's precision (FP64) from the triangle's
+        // vertices: N = (v1 - v0) x (v2 - v0), the hit point on its plane
+        // x = o + t d with t = N.(v0 - o) / N.d (the FP32 traversal t only
+        // chose the triangle), the side the ray came from
+        const pv3 v0 = state3(P.prim_v[3 * (size_t)prim]);
+        const pv3 N =
+            cross3(state3(P.prim_v[3 * (size_t)prim + 1]) - v0, state3(P.prim_v[3 * (size_t)prim + 2]) - v0);
+        const preal nn = dot3(N, N), nd = dot3(N, d);
+        ng = nn > (preal)0 ? N * ((preal)1 / sqrt(nn)) : state3(xyz(pi));
+        cos_o = -dot3(ng, d);
+        n = cos_o > (preal)0 ? ng : ng * (preal)-1;
+        x = nd != (preal)0 ? o + d * (dot3(N, v0 - o) / nd) : o + d * (preal)h.x;
+    }
+    // a pane hit: signed cosine, > 0 when the ray meets the normal-side (coated) face
+    const bool pane_hit = alive && prim >= 0 && typ == kGlass;
+    float pane_c = 0.0f;
+    if (pane_hit) {
+        const float cabs = (float)fabs(dot3(d, ng));
+        pane_c = cos_o > (preal)0 ? cabs : -cabs;
+    }
+    float sumR = 0.0f, sumT = 0.0f;  // over the wavelengths, for a pane hit before the last depth
+    if (COATED) {
+        const int w = threadIdx.x / 64;
+        wave_pane_sums<COATED>(pane_hit && !last_depth, m, pane_c, pane, P, s_gown + 64 * w, s_grt + 64 * w, sumR,
+                               sumT);
+    } else if (pane_hit && !last_depth) {
+        for (int l = 0; l < P.nl; ++l) {
+            float Rl, Tl;
+            glass_RT<COATED>(pane, P.coat, P.coat_n, P.coat_layers, P.nlp, m, l, pane_c, Rl, Tl);
+            sumR += Rl;
+            sumT += Tl;
+        }
+    }
+    if (alive) {
+        {
             const uint32_t q = (uint32_t)(P.pb + lpid);
             const uint32_t qs = fdiv(q, P.fwh);
             const int s0 = P.s0p ? *P.s0p : P.s0;
             const int s = s0 + P.sb + (int)qs;
             const int p = (int)(q - qs * (uint32_t)P.WH);
             const int pf = frame_pixel(P.win, p);
-            prim = __float_as_int(h.y);
             if (P.hit_log) P.hit_log[((long long)p * P.spp_call + (s - s0)) * P.max_depth + P.depth - 1] = prim;
-            const bool last_depth = P.depth == P.max_depth;
             int4 rec = make_int4(kVNone, 0, 0, 0);
             int sh = kShNone;
             if (prim < 0) {
                 fl = 0;  // no sky dome: a miss carries nothing
             } else {
-                const pv3 o{ro.x, ro.y, ro.z}, d{rd.x, rd.y, rd.z};
-                const float4 pi = P.prim_info[prim];
-                const int word = __float_as_int(pi.w);
-                const int typ = (word >> kMatTypeShift) & 3;
-                // material, or compact glass index for glass (with this render's substitution)
-                int m = word & kMatIdMask;
-                if (typ == kGlass && m == P.glass_from) m = P.glass_to;
-                const int emits = (word & kMatEmits) ? kVEmits : 0;
-                // geometry in the path state's precision (FP64) from the triangle's
-                // vertices: N = (v1 - v0) x (v2 - v0), the hit point on its plane
-                // x = o + t d with t = N.(v0 - o) / N.d (the FP32 traversal t only
-                // chose the triangle), the side the ray came from
-                const pv3 v0 = state3(P.prim_v[3 * (size_t)prim]);
-                const pv3 N =
-                    cross3(state3(P.prim_v[3 * (size_t)prim + 1]) - v0, state3(P.prim_v[3 * (size_t)prim + 2]) - v0);
-                const preal nn = dot3(N, N), nd = dot3(N, d);
-                const pv3 ng = nn > (preal)0 ? N * ((preal)1 / sqrt(nn)) : state3(xyz(pi));
-                const preal cos_o = -dot3(ng, d);
-                const pv3 n = cos_o > (preal)0 ? ng : ng * (preal)-1;
-                const pv3 x = nd != (preal)0 ? o + d * (dot3(N, v0 - o) / nd) : o + d * (preal)h.x;
                 pv3 xo64 = x, dn64 = d;
                 if (typ == kEmitter) {
                     rec.x = ((fl & kCountE) && cos_o > (preal)0) ? (kVEmit | kVLast | (m << kVIdShift)) : kVNone;
@@ -788,17 +866,8 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
                         dn64 = cosine_dir_state(n, (preal)u01(uc.x), (preal)u01(uc.y));
                         enq_e = true;
                     }
-                } else {  // glass pane
-                    // signed cosine: > 0 when the ray meets the normal-side (coated) face
-                    const float cabs = (float)fabs(dot3(d, ng));
-                    const float c = cos_o > (preal)0 ? cabs : -cabs;
-                    float sumR = 0.0f, sumT = 0.0f;
-                    for (int l = 0; l < P.nl; ++l) {
-                        float Rl, Tl;
-                        glass_RT<COATED>(pane, P.coat, P.coat_n, P.coat_layers, P.nlp, m, l, c, Rl, Tl);
-                        sumR += Rl;
-                        sumT += Tl;
-                    }
+                } else {  // glass pane: R and T summed over the wavelengths above
+                    const float c = pane_c;
                     if (!(sumR + sumT > 0.0f) || last_depth) {
                         rec.x = kVGlassT | kVLast | (m << kVIdShift);
                         fl = 0;
