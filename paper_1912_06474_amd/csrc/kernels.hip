@@ -668,9 +668,10 @@ void k_trace(TraceParams P) {
 //    uniform area sample of the parallelogram), then a cosine-weighted bounce;
 //  - glass pane: reflect with probability P_R = mean R / (mean R + mean T) of
 //    the pane's Fresnel slab terms (Eq. 1, Sec. 6), else transmit straight on.
-// R and T summed over the wavelengths for the coated-pane hits of a wave,
-// shared out over all of its lanes (a hit's transfer matrices at every
-// wavelength would otherwise run on its lane alone while the others wait).
+// R and T summed over the wavelengths for the pane hits of a wave, shared out
+// over all of its lanes (a hit's slab terms, or a coated pane's transfer
+// matrices, at every wavelength would otherwise run on its lane alone while
+// the others wait).
 // The (hit, wavelength) pairs go out 64 per round, hits in rank order; each
 // hit's lane then adds its pairs from the wave's LDS slots in wavelength
 // order, the order of a lone lane's loop, so the sums are the same.  Every
@@ -713,8 +714,8 @@ template <bool COATED>
 __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
     __shared__ int s_wcnt[(kShadeBlock / 64) * kMaxCells];
     __shared__ float4 s_pane[kLdsPane];
-    __shared__ int s_gown[COATED ? kShadeBlock : 1];     // per wave: lanes of its coated-pane hits by rank
-    __shared__ float2 s_grt[COATED ? kShadeBlock : 1];   // per wave: R and T of one round of pairs
+    __shared__ int s_gown[kShadeBlock];     // per wave: lanes of its pane hits by rank
+    __shared__ float2 s_grt[kShadeBlock];   // per wave: R and T of one round of pairs
     const int n_pane = P.n_glass * P.nlp;
     const bool pane_lds = n_pane <= kLdsPane;
     if (pane_lds)
@@ -744,8 +745,8 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
     const bool alive = valid && (fl & kAlive);
     if (alive) prim = __float_as_int(h.y);
     const bool last_depth = P.depth == P.max_depth;
-    // the hit's material and geometry (the coated-pane sums below need them
-    // on every lane of the wave before the branches on the material)
+    // the hit's material and geometry (the pane sums below need them on
+    // every lane of the wave before the branches on the material)
     const pv3 o{ro.x, ro.y, ro.z}, d{rd.x, rd.y, rd.z};
     float4 pi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     int typ = -1, m = 0, emits = 0;
@@ -780,18 +781,8 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
         pane_c = cos_o > (preal)0 ? cabs : -cabs;
     }
     float sumR = 0.0f, sumT = 0.0f;  // over the wavelengths, for a pane hit before the last depth
-    if (COATED) {
-        const int w = threadIdx.x / 64;
-        wave_pane_sums<COATED>(pane_hit && !last_depth, m, pane_c, pane, P, s_gown + 64 * w, s_grt + 64 * w, sumR,
-                               sumT);
-    } else if (pane_hit && !last_depth) {
-        for (int l = 0; l < P.nl; ++l) {
-            float Rl, Tl;
-            glass_RT<COATED>(pane, P.coat, P.coat_n, P.coat_layers, P.nlp, m, l, pane_c, Rl, Tl);
-            sumR += Rl;
-            sumT += Tl;
-        }
-    }
+    const int wv = threadIdx.x / 64;
+    wave_pane_sums<COATED>(pane_hit && !last_depth, m, pane_c, pane, P, s_gown + 64 * wv, s_grt + 64 * wv, sumR, sumT);
     if (alive) {
         {
             const uint32_t q = (uint32_t)(P.pb + lpid);
