@@ -310,25 +310,29 @@ __device__ __forceinline__ int rank_below(uint64_t m) {
 
 // Multi-split append: every lane with `active` gets a unique slot in the
 // segment `key` of a segmented queue whose per-segment fill counters are
-// counts[key * stride].  One atomic per distinct key in the wave (ballot +
-// mbcnt).  Must be reached by all lanes of the wave together.
+// counts[key * stride].  The active lanes are grouped by key (ballot per
+// distinct key); each group's lowest lane takes the group's slots with one
+// atomic, and the leaders' atomics go out as one instruction, so the wave
+// waits on memory once.  A lane's slot is its leader's base plus its rank in
+// the group.  Must be reached by all lanes of the wave together.
 __device__ __forceinline__ int wave_append(bool active, int key, int* counts, int stride) {
-    int slot = -1;
+    int leader = 0, rank = 0, n_key = 0;
     uint64_t pending = __ballot(active);
     while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int lk = __builtin_amdgcn_readlane(key, leader);
+        const int l = __ffsll((unsigned long long)pending) - 1;
+        const int lk = __builtin_amdgcn_readlane(key, l);
         const uint64_t m = __ballot(active && key == lk);
-        int base = 0;
-        if (lane_id() == leader) base = atomicAdd(&counts[(size_t)lk * stride], popc64(m));
-        base = __builtin_amdgcn_readlane(base, leader);
         if (active && key == lk) {
-            slot = base + rank_below(m);
-            active = false;
+            leader = l;
+            rank = rank_below(m);
         }
+        if (lane_id() == l) n_key = popc64(m);
         pending &= ~m;
     }
-    return slot;
+    int base = 0;
+    if (active && lane_id() == leader) base = atomicAdd(&counts[(size_t)key * stride], n_key);
+    base = __shfl(base, leader);
+    return active ? base + rank : -1;
 }
 
 // Stable workgroup multi-split rank: every thread with `active` gets its
