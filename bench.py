@@ -34,11 +34,15 @@ COPY_FLOATS = 1 << 28          # plain device copy of 1 GiB, for scaling FETCH_S
 
 # HBM bytes of the dominant kernel measured with rocprofv3 --pmc FETCH_SIZE /
 # WRITE_SIZE, valid only while that kernel's sources are unchanged
+# key: (counter summary, the kernel sources it holds for, the workload it was taken on)
 TRAFFIC = {
     "furnished_room": (os.path.join(ROOT, "profiles", "k_trace_traffic_furnished_room_512x512_16spp.txt"),
-                       ["kernels.hip", "layout.h", "device_math.h"]),
+                       ["kernels.hip", "layout.h", "device_math.h"], "furnished_room"),
     "nrc_room": (os.path.join(ROOT, "profiles", "k_query_mfma_traffic_nrc_room_1920x1080_4spp.txt"),
-                 ["nrc.hip", "nrc.h"]),
+                 ["nrc.hip", "nrc.h"], "nrc_room"),
+    # k_trace in the radiance-cache frames (the cache line's dominant kernel)
+    "nrc_room_trace": (os.path.join(ROOT, "profiles", "k_trace_traffic_nrc_room_1920x1080_4spp.txt"),
+                       ["kernels.hip", "layout.h", "device_math.h"], "nrc_room"),
 }
 
 
@@ -83,13 +87,13 @@ def source_hash(sources):
     return h.hexdigest()
 
 
-def measured_traffic(workload, grid):
-    """HBM bytes per launch of the workload's dominant kernel from the committed
-    counter summary, or None if it was taken on other kernel sources or another
-    workload."""
-    if workload not in TRAFFIC:
+def measured_traffic(key, grid):
+    """HBM bytes per launch of a kernel (TRAFFIC[key]) from the committed
+    counter summary, or None if it was taken on other kernel sources, another
+    workload or another grid."""
+    if key not in TRAFFIC:
         return None
-    path, sources = TRAFFIC[workload]
+    path, sources, workload = TRAFFIC[key]
     try:
         with open(path) as fh:
             kv = dict(l.strip().split("=", 1) for l in fh if "=" in l and not l.lstrip().startswith("#"))
@@ -315,6 +319,9 @@ def nrc_comparison(args, tr, scene, wl):
                     train_steps=cfg["train_steps"], train_batch=cfg["train_batch"], precision="bf16",
                     table_fp16=cfg.get("table_fp16", False))
 
+    if args.cache_only:
+        return cache_frames_only(args, tr, wl, cfg, nl, frames, trace, init_cache)
+
     t0 = time.perf_counter()
     refs = []
     for k in range(3):
@@ -410,7 +417,7 @@ def nrc_comparison(args, tr, scene, wl):
     dominant = max(kern, key=kern.get)
     traffic_q = measured_traffic("nrc_room", wl["grid"])
     rq = query_roofline(stn, nl, traffic_q)
-    rt = trace_roofline(stn, None)
+    rt = trace_roofline(stn, measured_traffic("nrc_room_trace", wl["grid"]))
     return {
         "metric": "spectral path samples/s (rays x lambda/s) at <=1% rel-MSE; radiance cache vs plain, one MI355X",
         "value": value,
@@ -445,6 +452,35 @@ def nrc_comparison(args, tr, scene, wl):
         "roofline_query": rq,
         "kernel_ms_per_cache_frame": {k: v / (frames + cfg["train_warmup"]) for k, v in kern.items()},
     }
+
+
+def cache_frames_only(args, tr, wl, cfg, nl, frames, trace, init_cache):
+    """The cache side of the comparison alone, for profiling: the cache's
+    training warm-up and its frames, as in the comparison, without the
+    references and the plain frames, so that a kernel trace or counter run of
+    this command covers exactly the launches the cache line's roofline
+    averages over."""
+    import torch
+
+    init_cache()
+    tr.reset_stats()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for f in range(cfg["train_warmup"]):
+        trace(3, 3_000_000 + f * wl["spp"], True)
+    tr.reset_render(3)
+    for f in range(frames):
+        trace(2, f * wl["spp"], True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    stn = tr.stats()
+    n = frames + cfg["train_warmup"]
+    return {"metric": "radiance-cache frames only (profiling run of the cache line's kernels)",
+            "frames": n, "ms_per_frame": dt / n * 1e3,
+            "roofline": trace_roofline(stn, measured_traffic("nrc_room_trace", wl["grid"])),
+            "roofline_query": query_roofline(stn, nl, measured_traffic("nrc_room", wl["grid"])),
+            "kernel_ms_per_cache_frame": {"trace": (stn["ms_trace_ext"] + stn["ms_trace_shadow"]) / n,
+                                          "nrc_query": stn["ms_nrc_query"] / n}}
 
 
 def plain_line(args, workload, wl, scene, tr, build_s, cpu_s):
@@ -636,6 +672,8 @@ def main():
     ap.add_argument("--path-state", choices=["f64", "f32"], default="f64",
                     help="f32: load the FP32-path-state measurement build (libsdd_f32state.so) to time what FP64 "
                          "path state costs; the library itself keeps FP64 path state")
+    ap.add_argument("--cache-only", action="store_true",
+                    help="nrc_room: only the cache's warm-up and frames (profiling the cache line's kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -657,6 +695,10 @@ def main():
     if "nrc" in wl:
         W, H, spp, D = wl["W"], wl["H"], wl["spp"], wl["D"]
         res = nrc_comparison(args, tr, scene, wl)
+        if args.cache_only:
+            tr.close()
+            print(json.dumps(res))
+            return
         res.update(common)
         res["config"] = {"workload": f"{args.workload}: {len(scene['tris'])} tris, {W}x{H}, {spp} spp per frame, "
                                      f"{len(scene['lambda_nm'])} lambda, depth {D}, cache after vertex 2, grid "

@@ -31,7 +31,7 @@ def _write(path, sha, workload="furnished_room", grid="4x4x2"):
 def test_traffic_is_gated_on_sources_workload_and_grid(tmp_path, monkeypatch):
     srcs = bench.TRAFFIC["furnished_room"][1]
     f = tmp_path / "t.txt"
-    monkeypatch.setitem(bench.TRAFFIC, "furnished_room", (str(f), srcs))
+    monkeypatch.setitem(bench.TRAFFIC, "furnished_room", (str(f), srcs, "furnished_room"))
     _write(f, bench.source_hash(srcs))
     assert bench.measured_traffic("furnished_room", (4, 4, 2)) == (100.0 * 2.0 + 50.0) * 1024.0
     assert bench.measured_traffic("furnished_room", (2, 2, 2)) is None  # another grid
@@ -44,9 +44,9 @@ def test_traffic_is_gated_on_sources_workload_and_grid(tmp_path, monkeypatch):
     assert bench.measured_traffic("no_such_workload", (1, 1, 1)) is None
 
 
-@pytest.mark.parametrize("workload", sorted(bench.TRAFFIC))
-def test_committed_traffic_summaries_parse(workload):
-    path, srcs = bench.TRAFFIC[workload]
+@pytest.mark.parametrize("key", sorted(bench.TRAFFIC))
+def test_committed_traffic_summaries_parse(key):
+    path, srcs, workload = bench.TRAFFIC[key]
     kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.lstrip().startswith("#"))
     assert kv["workload"] == workload
     for k in ("fetch_kib_per_dispatch", "write_kib_per_dispatch", "fetch_scale", "write_scale"):
