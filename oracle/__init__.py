@@ -2,7 +2,7 @@
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The product library never calls it:
-it exists to judge the HIP path (plain FP64 definitions, see ``oracle.h``).
+it exists to check the HIP path against (plain FP64 definitions, see ``oracle.h``).
 """
 from __future__ import annotations
 

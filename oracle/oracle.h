@@ -1,7 +1,7 @@
 /*
  * FP64 CPU oracle for spectral ray tracing of a lit room -- TEST INFRASTRUCTURE.
  *
- * This library exists only to judge the HIP path.  Only the test-suite, the
+ * This library exists only to check the HIP path against.  Only the test-suite, the
  * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
  * code, header, table or constant with the GPU library; both read the same
  * seeded scene arrays (scenegen/), which carry no rendering arithmetic.
