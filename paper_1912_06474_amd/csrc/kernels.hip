@@ -1200,18 +1200,24 @@ __global__ __launch_bounds__(256) void k_nrc_rows(NrcRowParams P) {
 }
 
 // FP64: mean over samples and XYZ = sum_l w_l cmf_l L_l
-// 64 pixels per block: their accumulator rows (contiguous) are staged in LDS
-// with coalesced loads, the spectral means are written as one contiguous run,
-// and one thread per pixel forms XYZ
+// 64 pixels per block: their accumulator rows (contiguous, nlp a multiple of
+// 4) are staged in LDS (dynamic, 64 nlp floats, so short spectra keep many
+// blocks per CU) with 16-byte loads, the spectral means are written as one
+// contiguous run, and one thread per (pixel, X/Y/Z) forms XYZ from the
+// products w_l cmf_l staged once per block
 constexpr int kResolvePix = 64;
 __global__ __launch_bounds__(256) void k_resolve(int WH, int nl, int nlp, double inv_spp, const float* __restrict__ acc,
                                                  const double* __restrict__ w, const double* __restrict__ cmf,
                                                  double* spectral, double* xyz) {
-    __shared__ float s_acc[kResolvePix * 128];
+    extern __shared__ float4 s_acc4[];  // kResolvePix * nlp / 4
+    __shared__ double s_wc[3 * 128];    // w_l cmf_l, l < nl <= 128
+    const float* s_acc = reinterpret_cast<const float*>(s_acc4);
     const int p0 = blockIdx.x * kResolvePix;
     const int np = min(kResolvePix, WH - p0);
-    const float* src = acc + (size_t)p0 * nlp;
-    for (int e = threadIdx.x; e < np * nlp; e += blockDim.x) s_acc[e] = src[e];
+    const float4* src = reinterpret_cast<const float4*>(acc + (size_t)p0 * nlp);
+    for (int e = threadIdx.x; e < np * nlp / 4; e += blockDim.x) s_acc4[e] = src[e];
+    if (xyz)
+        for (int e = threadIdx.x; e < 3 * nl; e += blockDim.x) s_wc[e] = w[e / 3] * cmf[e];
     __syncthreads();
     if (spectral) {
         double* dst = spectral + (size_t)p0 * nl;
@@ -1220,19 +1226,14 @@ __global__ __launch_bounds__(256) void k_resolve(int WH, int nl, int nlp, double
             dst[e] = (double)s_acc[pp * nlp + l] * inv_spp;
         }
     }
-    if (xyz && (int)threadIdx.x < np) {
-        const int pp = threadIdx.x;
-        double X = 0.0, Y = 0.0, Z = 0.0;
+    if (xyz && (int)threadIdx.x < 3 * np) {
+        const int pp = threadIdx.x / 3, k = threadIdx.x - 3 * pp;
+        double X = 0.0;
         for (int l = 0; l < nl; ++l) {
             const double v = (double)s_acc[pp * nlp + l] * inv_spp;
-            X += w[l] * cmf[3 * l] * v;
-            Y += w[l] * cmf[3 * l + 1] * v;
-            Z += w[l] * cmf[3 * l + 2] * v;
+            X += s_wc[3 * l + k] * v;
         }
-        const size_t p = (size_t)(p0 + pp);
-        xyz[3 * p] = X;
-        xyz[3 * p + 1] = Y;
-        xyz[3 * p + 2] = Z;
+        xyz[3 * (size_t)p0 + threadIdx.x] = X;  // pixel p0 + pp, component k
     }
 }
 
@@ -1356,9 +1357,9 @@ hipError_t launch_nrc_rows(const NrcRowParams& p, hipStream_t st) {
 
 hipError_t launch_resolve(int WH, int nl, int nlp, double inv_spp, const float* acc, const double* w,
                           const double* cmf, double* spectral, double* xyz, hipStream_t st) {
-    if (nlp > 128) return hipErrorInvalidValue;  // the LDS staging holds 128 wavelengths per pixel
-    hipLaunchKernelGGL(k_resolve, dim3(blocks_for(WH, kResolvePix)), dim3(256), 0, st, WH, nl, nlp, inv_spp, acc, w,
-                       cmf, spectral, xyz);
+    if (nlp > 128 || nlp % 4 != 0 || nl > nlp) return hipErrorInvalidValue;  // the LDS staging's shape
+    hipLaunchKernelGGL(k_resolve, dim3(blocks_for(WH, kResolvePix)), dim3(256), sizeof(float) * kResolvePix * nlp, st,
+                       WH, nl, nlp, inv_spp, acc, w, cmf, spectral, xyz);
     return hipGetLastError();
 }
 
