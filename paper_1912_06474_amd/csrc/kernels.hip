@@ -732,15 +732,26 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(ShadeParams P) {
     float te = 0.0f, ts = 0.0f, r_sh = 0.0f;
     int prim = -1;
     // the hit and the FP64 ray are loaded with the flags, before the branches
-    // that need them, so their latencies overlap
+    // that need them, so their latencies overlap; past depth 2 of a cache
+    // render most paths have ended in the cache, and those are read only
+    // when their flags say they live
     uint32_t fl = 0;
     float2 h = make_float2(0.0f, 0.0f);
     D4 ro{}, rd{};
     if (valid) {
-        fl = P.flags[pid];
-        h = P.hit[pid];
-        ro = P.ray_o[pid];
-        rd = P.ray_d[pid];
+        if (!(P.nrc.on && P.depth > 2)) {
+            fl = P.flags[pid];
+            h = P.hit[pid];
+            ro = P.ray_o[pid];
+            rd = P.ray_d[pid];
+        } else {
+            fl = P.flags[pid];
+            if (fl & kAlive) {
+                h = P.hit[pid];
+                ro = P.ray_o[pid];
+                rd = P.ray_d[pid];
+            }
+        }
     }
     const bool alive = valid && (fl & kAlive);
     if (alive) prim = __float_as_int(h.y);
