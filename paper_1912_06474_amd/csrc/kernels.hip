@@ -982,27 +982,80 @@ __global__ __launch_bounds__(256) void k_route_scan(RouteParams P) {
 // A key's runs from consecutive path blocks are adjacent in its queue, and
 // when one XCD writes them its L2 merges them into whole lines instead of
 // several XCDs writing back parts of the same lines.
+// The block's records of one kind are staged in LDS in key order (a key's
+// records by rank), so that consecutive threads write consecutive slots of a
+// key's run in its cell's queue: whole lines instead of scattered 40-byte
+// records.  Every record goes to the slot it would get on its own thread.
 __global__ __launch_bounds__(kShadeBlock) void k_route(RouteParams P) {
+    __shared__ int s_off[kShadeBlock];     // per key: exclusive prefix of the block's counts
+    __shared__ int s_key[kShadeBlock];     // per staged record: its key
+    __shared__ float4 s_qa[kShadeBlock], s_qb[kShadeBlock];
+    __shared__ int2 s_qc[kShadeBlock];
+    __shared__ int s_wsum[kShadeBlock / 64];
     const int per = gridDim.x / kXcd;  // the grid is a multiple of kXcd
     const int pb = (int)(blockIdx.x % kXcd) * per + (int)(blockIdx.x / kXcd);
-    if (pb >= P.n_blocks) return;
-    const int pid = pb * kShadeBlock + threadIdx.x;
-    if (pid >= P.N) return;
+    if (pb >= P.n_blocks) return;      // whole block: before any barrier
+    const int t = threadIdx.x;
+    const int pid = pb * kShadeBlock + t;
+    const bool valid = pid < P.N;
 #pragma unroll
     for (int kind = 0; kind < 2; ++kind) {
-        if (!P.active[kind]) continue;
+        if (!P.active[kind]) continue;  // uniform
         const Stage& S = P.st[kind];
-        const int tag = S.tag[pid];
-        if (tag < 0) continue;
-        const int key = tag & 0xFFFF, rank = tag >> 16, nbin = P.nbin[kind];
-        const int cell = key / nbin;
-        long long slot = (long long)S.hist[(long long)key * P.n_blocks + pb] + rank;
-        for (int k2 = cell * nbin; k2 < key; ++k2) slot += P.ktot[kind][k2];  // the cell's lower bins
-        if (slot < 0 || slot >= P.cap || cell >= P.n_cells) continue;  // never expected: defence only
-        const long long q = (long long)cell * P.cap + slot;
-        P.qa[kind][q] = S.qa[pid];
-        P.qb[kind][q] = S.qb[pid];
-        P.qc[kind][q] = S.qc[pid];
+        const int nbin = P.nbin[kind], n_keys = P.n_cells * nbin;
+        const int tag = valid ? S.tag[pid] : -1;
+        const int key = tag & 0xFFFF, rank = tag >> 16;
+        // the block's count per key (the key's highest rank + 1), then their prefix
+        s_off[t] = 0;
+        __syncthreads();
+        if (tag >= 0 && key < kShadeBlock) atomicMax(&s_off[key], rank + 1);
+        __syncthreads();
+        const int c = s_off[t];  // keys beyond n_keys stay 0
+        int incl = c;            // block-wide inclusive scan over the keys
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o);
+            if (lane_id() >= o) incl += v;
+        }
+        if (lane_id() == 63) s_wsum[t / 64] = incl;
+        __syncthreads();
+        int wbase = 0;
+        for (int w = 0; w < t / 64; ++w) wbase += s_wsum[w];
+        const int n_staged = [&] { int n = 0; for (int w = 0; w < kShadeBlock / 64; ++w) n += s_wsum[w]; return n; }();
+        __syncthreads();
+        s_off[t] = wbase + incl - c;
+        __syncthreads();
+        if (tag >= 0 && key < kShadeBlock && n_keys <= kShadeBlock) {
+            const int at = s_off[key] + rank;
+            s_key[at] = key;
+            s_qa[at] = S.qa[pid];
+            s_qb[at] = S.qb[pid];
+            s_qc[at] = S.qc[pid];
+        }
+        __syncthreads();
+        if (t < n_staged && n_keys <= kShadeBlock) {
+            const int k = s_key[t], cell = k / nbin;
+            long long slot = (long long)S.hist[(long long)k * P.n_blocks + pb] + (t - s_off[k]);
+            for (int k2 = cell * nbin; k2 < k; ++k2) slot += P.ktot[kind][k2];  // the cell's lower bins
+            if (slot >= 0 && slot < P.cap && cell < P.n_cells) {  // always: defence only
+                const long long q = (long long)cell * P.cap + slot;
+                P.qa[kind][q] = s_qa[t];
+                P.qb[kind][q] = s_qb[t];
+                P.qc[kind][q] = s_qc[t];
+            }
+        }
+        if (n_keys > kShadeBlock && tag >= 0) {  // more keys than staging slots (not with the library's grids)
+            const int cell = key / nbin;
+            long long slot = (long long)S.hist[(long long)key * P.n_blocks + pb] + rank;
+            for (int k2 = cell * nbin; k2 < key; ++k2) slot += P.ktot[kind][k2];
+            if (slot >= 0 && slot < P.cap && cell < P.n_cells) {
+                const long long q = (long long)cell * P.cap + slot;
+                P.qa[kind][q] = S.qa[pid];
+                P.qb[kind][q] = S.qb[pid];
+                P.qc[kind][q] = S.qc[pid];
+            }
+        }
+        __syncthreads();  // the staging is reused by the next kind
     }
 }
 
