@@ -188,12 +188,18 @@ __device__ __forceinline__ RayTrav make_trav(f3 o, f3 d, float4 qbase, float4 qs
 
 // slab test of one quantised child box against [tlo, thi]; returns the entry t
 // (or +inf on a miss)
-__device__ __forceinline__ float box_enter(const RayTrav& r, uint4 c, float tlo, float thi) {
-    const float ax = fmaf((float)(c.x & 0xffffu), r.sinv.x, r.boff.x), bx = fmaf((float)(c.x >> 16), r.sinv.x, r.boff.x);
-    const float ay = fmaf((float)(c.y & 0xffffu), r.sinv.y, r.boff.y), by = fmaf((float)(c.y >> 16), r.sinv.y, r.boff.y);
-    const float az = fmaf((float)(c.z & 0xffffu), r.sinv.z, r.boff.z), bz = fmaf((float)(c.z >> 16), r.sinv.z, r.boff.z);
-    const float tmin = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tlo));
-    const float tmax = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), thi));
+// sx, sy, sz: 16 where the ray runs down that axis (its far plane is the
+// low one), else 0; rotating the record's plane pair by it puts the near
+// plane in the low half, so no min / max sorts each axis's two t
+__device__ __forceinline__ float box_enter(const RayTrav& r, uint4 c, float tlo, float thi, uint32_t sx, uint32_t sy,
+                                           uint32_t sz) {
+    const uint32_t cx = __builtin_amdgcn_alignbit(c.x, c.x, sx), cy = __builtin_amdgcn_alignbit(c.y, c.y, sy),
+                   cz = __builtin_amdgcn_alignbit(c.z, c.z, sz);
+    const float nx = fmaf((float)(cx & 0xffffu), r.sinv.x, r.boff.x), fx = fmaf((float)(cx >> 16), r.sinv.x, r.boff.x);
+    const float ny = fmaf((float)(cy & 0xffffu), r.sinv.y, r.boff.y), fy = fmaf((float)(cy >> 16), r.sinv.y, r.boff.y);
+    const float nz = fmaf((float)(cz & 0xffffu), r.sinv.z, r.boff.z), fz = fmaf((float)(cz >> 16), r.sinv.z, r.boff.z);
+    const float tmin = fmaxf(fmaxf(nx, ny), fmaxf(nz, tlo));
+    const float tmax = fminf(fminf(fx, fy), fminf(fz, thi));
     return tmin <= tmax ? tmin : INFINITY;
 }
 
@@ -351,10 +357,12 @@ __device__ __forceinline__ void trace_item(const TraceParams& P, const QueueSet&
                 }
                 float t[kBvhWidth];
                 int l[kBvhWidth];
+                const uint32_t sx = (__float_as_uint(r.sinv.x) >> 27) & 16u, sy = (__float_as_uint(r.sinv.y) >> 27) & 16u,
+                               sz = (__float_as_uint(r.sinv.z) >> 27) & 16u;
 #pragma unroll
                 for (int i = 0; i < kBvhWidth; ++i) {
                     l[i] = (int)ch[i].w;
-                    const float te = box_enter(r, ch[i], tlo, thi);  // tested unconditionally: no branch per child
+                    const float te = box_enter(r, ch[i], tlo, thi, sx, sy, sz);  // tested unconditionally: no branch per child
                     t[i] = l[i] == kEmptyLink ? INFINITY : te;
                 }
                 // nearest first: sorting network on (t, link), as min / max and selects
